@@ -1,0 +1,375 @@
+"""Plain FP64 CPU oracle (ctypes wrapper around ``liboracle.so``).
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product package imports this
+module; it is used by the test suite, by the smoke check and by the
+CPU-baseline leg of the benchmark.  The C sources (``mds_oracle.c``) are plain
+loops in double precision built with ``-ffp-contract=off``; see that file for
+the passages of the paper each function follows.
+
+All arrays are numpy float64 / int32, column-major for dense matrices.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_SRC = os.path.join(_HERE, "mds_oracle.c")
+
+
+def build(force: bool = True) -> str:
+    """Compile liboracle.so with gcc (no BLAS, no contraction)."""
+    if force or not os.path.exists(_LIB_PATH):
+        cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
+               "-std=c11", "-Wall", "-o", _LIB_PATH + ".tmp", _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(_LIB_PATH + ".tmp", _LIB_PATH)
+    return _LIB_PATH
+
+
+_lib = None
+
+_dp = C.POINTER(C.c_double)
+_ip = C.POINTER(C.c_int32)
+
+
+class OrqProblem(C.Structure):
+    _fields_ = [("n_d", C.c_int32), ("n_s", C.c_int32), ("m", C.c_int32),
+                ("H", _dp), ("c", _dp), ("w", _dp), ("g", _dp), ("Jd", _dp),
+                ("rp", _ip), ("ci", _ip), ("v", _dp), ("b", _dp),
+                ("xl", _dp), ("xu", _dp)]
+
+
+class OrFactor(C.Structure):
+    _fields_ = [("N", C.c_int32), ("dw", C.c_double), ("dc", C.c_double),
+                ("L", _dp), ("dd", _dp), ("ds", _dp), ("ipiv", _ip), ("inv_d", _dp),
+                ("inertia", C.c_int32 * 3), ("info", C.c_int32), ("trials", C.c_int32)]
+
+
+class OrIpmOpts(C.Structure):
+    _fields_ = [("tol", C.c_double), ("mu0", C.c_double), ("max_iter", C.c_int32),
+                ("refine_steps", C.c_int32), ("dw_max", C.c_double)]
+
+
+class OrIpmTrace(C.Structure):
+    _fields_ = [("mu", C.c_double), ("E0", C.c_double), ("theta", C.c_double),
+                ("phi", C.c_double), ("alpha_pr", C.c_double), ("alpha_du", C.c_double),
+                ("dw", C.c_double), ("dc", C.c_double), ("inertia", C.c_int32 * 3),
+                ("trials", C.c_int32), ("backtracks", C.c_int32)]
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build(force=True)
+        L = C.CDLL(_LIB_PATH)
+        P = C.POINTER(OrqProblem)
+        F = C.POINTER(OrFactor)
+        L.or_condense.argtypes = [P, _dp, _dp, C.c_double, C.c_double, _dp, _dp]
+        L.or_rhs_condense.argtypes = [P, _dp, _dp, _dp, _dp]
+        L.or_backsub.argtypes = [P, _dp, _dp, _dp, _dp]
+        L.or_bk.argtypes = [C.c_int32, _dp, _ip, _dp, _dp, _ip]
+        L.or_bk.restype = C.c_int
+        L.or_inertia.argtypes = [C.c_int32, _ip, _dp, _dp, _ip]
+        L.or_ldl_solve.argtypes = [C.c_int32, _dp, _ip, _dp, _dp, _dp]
+        L.or_ldl_solve.restype = C.c_int
+        L.or_kkt_matvec.argtypes = [P, _dp, _dp, C.c_double, C.c_double, _dp, _dp, _dp,
+                                    _dp, _dp, _dp]
+        L.or_kkt_norm_inf.argtypes = [P, _dp, _dp, C.c_double, C.c_double]
+        L.or_kkt_norm_inf.restype = C.c_double
+        L.or_factor_new.argtypes = [P]
+        L.or_factor_new.restype = F
+        L.or_factor_free.argtypes = [F]
+        L.or_factor_once.argtypes = [P, _dp, _dp, C.c_double, C.c_double, F]
+        L.or_factor_inertia.argtypes = [P, _dp, _dp, C.c_double, _dp, C.c_double, F]
+        L.or_factor_inertia.restype = C.c_int
+        L.or_newton_solve.argtypes = [P, F, _dp, _dp, _dp, _dp, _dp, _dp]
+        L.or_newton_solve.restype = C.c_int
+        L.or_newton_refine.argtypes = [P, F, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp,
+                                       C.c_int32, C.c_double, _dp]
+        L.or_newton_refine.restype = C.c_int
+        L.or_sigma_rhs.argtypes = [P, _dp, _dp, _dp, _dp, C.c_double, _dp, _dp, _dp]
+        L.or_ftb.argtypes = [C.c_int64, _dp, _dp, C.c_double]
+        L.or_ftb.restype = C.c_double
+        L.or_opt_error.argtypes = [P, _dp, _dp, _dp, _dp, C.c_double, _dp]
+        L.or_opt_error.restype = C.c_double
+        for nm in ("or_objective", "or_theta"):
+            getattr(L, nm).argtypes = [P, _dp]
+            getattr(L, nm).restype = C.c_double
+        L.or_barrier.argtypes = [P, _dp, C.c_double]
+        L.or_barrier.restype = C.c_double
+        L.or_ipm.argtypes = [P, C.POINTER(OrIpmOpts), _dp, _dp, _dp, _dp, _ip,
+                             C.POINTER(OrIpmTrace)]
+        L.or_ipm.restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _d(a):
+    return a.ctypes.data_as(_dp)
+
+
+def _i(a):
+    return a.ctypes.data_as(_ip)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+class Problem:
+    """Holds contiguous copies of a problem dict and the C struct that views them."""
+
+    def __init__(self, p: dict):
+        self.n_d, self.n_s, self.m = int(p["n_d"]), int(p["n_s"]), int(p["m"])
+        self.H = _f64(np.asarray(p["H"]).reshape(-1, order="F"))
+        self.c = _f64(p["c"])
+        self.w = _f64(p["w"])
+        self.g = _f64(p["g"])
+        self.Jd = _f64(np.asarray(p["Jd"]).reshape(-1, order="F"))
+        self.rp = np.ascontiguousarray(p["rp"], dtype=np.int32)
+        self.ci = np.ascontiguousarray(p["ci"], dtype=np.int32)
+        self.v = _f64(p["v"])
+        self.b = _f64(p["b"])
+        self.xl = _f64(p["xl"])
+        self.xu = _f64(p["xu"])
+        self._keep = [np.zeros(1)]
+        self.s = OrqProblem(self.n_d, self.n_s, self.m, *[_d(self._nz(a)) for a in (
+            self.H, self.c, self.w, self.g, self.Jd)], _i(self._nzi(self.rp)),
+            _i(self._nzi(self.ci)), _d(self._nz(self.v)), _d(self._nz(self.b)),
+            _d(self._nz(self.xl)), _d(self._nz(self.xu)))
+
+    def _nz(self, a):
+        if a.size == 0:
+            a = np.zeros(1)
+            self._keep.append(a)
+        return a
+
+    def _nzi(self, a):
+        if a.size == 0:
+            a = np.zeros(1, dtype=np.int32)
+            self._keep.append(a)
+        return a
+
+    @property
+    def N(self):
+        return self.n_d + self.m
+
+    @property
+    def ptr(self):
+        return C.byref(self.s)
+
+
+def _buf(n, dtype=np.float64):
+    return np.zeros(max(int(n), 1), dtype=dtype)
+
+
+def condense(P: Problem, sigma_d, dsbase, dw=0.0, dc=0.0):
+    """Condensed matrix M (N x N, full symmetric) and inv_d = 1/(dsbase+dw)."""
+    N = P.N
+    M = _buf(N * N)
+    inv_d = _buf(P.n_s)
+    lib().or_condense(P.ptr, _d(_f64(sigma_d) if P.n_d else _buf(1)),
+                      _d(_f64(dsbase) if P.n_s else _buf(1)), dw, dc, _d(M), _d(inv_d))
+    return M[:N * N].reshape((N, N), order="F"), inv_d[:P.n_s]
+
+
+def rhs_condense(P: Problem, inv_d, r_s, r_y):
+    out = _buf(P.m)
+    lib().or_rhs_condense(P.ptr, _d(_f64(inv_d) if P.n_s else _buf(1)),
+                          _d(_f64(r_s) if P.n_s else _buf(1)),
+                          _d(_f64(r_y) if P.m else _buf(1)), _d(out))
+    return out[:P.m]
+
+
+def backsub(P: Problem, inv_d, r_s, dy):
+    out = _buf(P.n_s)
+    lib().or_backsub(P.ptr, _d(_f64(inv_d) if P.n_s else _buf(1)),
+                     _d(_f64(r_s) if P.n_s else _buf(1)), _d(_f64(dy) if P.m else _buf(1)),
+                     _d(out))
+    return out[:P.n_s]
+
+
+def bk(A):
+    """Bunch-Kaufman LDL' of symmetric A (lower triangle read).
+
+    Returns (L, dd, ds, ipiv, info, kind): L unit lower in standard form
+    (P'AP = L D L'), D's diagonal and sub-diagonal, LAPACK 1-based ipiv.
+    """
+    A = np.asarray(A, dtype=np.float64)
+    N = A.shape[0]
+    W = _buf(N * N)
+    W[:N * N] = A.reshape(-1, order="F")
+    ipiv = _buf(N, np.int32)
+    dd, ds = _buf(N), _buf(N)
+    kind = _buf(N, np.int32)
+    info = lib().or_bk(N, _d(W), _i(ipiv), _d(dd), _d(ds), _i(kind))
+    L = np.tril(W[:N * N].reshape((N, N), order="F"), -1) + np.eye(N)
+    return L, dd[:N], ds[:N], ipiv[:N], info, kind[:N]
+
+
+def inertia(ipiv, dd, ds):
+    N = len(ipiv)
+    out = np.zeros(3, dtype=np.int32)
+    lib().or_inertia(N, _i(np.ascontiguousarray(ipiv, dtype=np.int32) if N else _buf(1, np.int32)),
+                     _d(_f64(dd) if N else _buf(1)), _d(_f64(ds) if N else _buf(1)), _i(out))
+    return tuple(int(v) for v in out)
+
+
+def ldl_solve(L, ipiv, dd, ds, b):
+    N = len(ipiv)
+    x = _f64(np.array(b, dtype=np.float64, copy=True))
+    Lf = _f64(np.asarray(L).reshape(-1, order="F"))
+    st = lib().or_ldl_solve(N, _d(Lf), _i(np.ascontiguousarray(ipiv, dtype=np.int32)),
+                            _d(_f64(dd)), _d(_f64(ds)), _d(x))
+    return x, st
+
+
+def kkt_matvec(P: Problem, sigma_d, dsbase, dw, dc, dx_d, dx_s, dy):
+    o_d, o_s, o_y = _buf(P.n_d), _buf(P.n_s), _buf(P.m)
+    a = [_f64(v) if len(v) else _buf(1) for v in (sigma_d, dsbase, dx_d, dx_s, dy)]
+    lib().or_kkt_matvec(P.ptr, _d(a[0]), _d(a[1]), dw, dc, _d(a[2]), _d(a[3]), _d(a[4]),
+                        _d(o_d), _d(o_s), _d(o_y))
+    return o_d[:P.n_d], o_s[:P.n_s], o_y[:P.m]
+
+
+def kkt_norm_inf(P: Problem, sigma_d, dsbase, dw, dc):
+    a = [_f64(v) if len(v) else _buf(1) for v in (sigma_d, dsbase)]
+    return lib().or_kkt_norm_inf(P.ptr, _d(a[0]), _d(a[1]), dw, dc)
+
+
+class Factor:
+    """A factored, regularised Newton system owned by the oracle."""
+
+    def __init__(self, P: Problem):
+        self.P = P
+        self.p = lib().or_factor_new(P.ptr)
+
+    def __del__(self):
+        try:
+            lib().or_factor_free(self.p)
+        except Exception:
+            pass
+
+    @property
+    def s(self):
+        return self.p.contents
+
+    def once(self, sigma_d, dsbase, dw=0.0, dc=0.0):
+        self._sd, self._db = _f64(sigma_d) if len(sigma_d) else _buf(1), \
+            _f64(dsbase) if len(dsbase) else _buf(1)
+        lib().or_factor_once(self.P.ptr, _d(self._sd), _d(self._db), dw, dc, self.p)
+        return self
+
+    def correct(self, sigma_d, dsbase, mu, dw_last=0.0, dw_max=1e20):
+        """Inertia-correction loop.  Returns (status, dw_last_new)."""
+        self._sd, self._db = _f64(sigma_d) if len(sigma_d) else _buf(1), \
+            _f64(dsbase) if len(dsbase) else _buf(1)
+        dl = np.array([dw_last], dtype=np.float64)
+        st = lib().or_factor_inertia(self.P.ptr, _d(self._sd), _d(self._db), mu, _d(dl),
+                                     dw_max, self.p)
+        return st, float(dl[0])
+
+    @property
+    def inertia(self):
+        return tuple(int(v) for v in self.s.inertia)
+
+    @property
+    def ipiv(self):
+        N = self.s.N
+        return np.ctypeslib.as_array(self.s.ipiv, shape=(max(N, 1),))[:N].copy()
+
+    @property
+    def dd(self):
+        N = self.s.N
+        return np.ctypeslib.as_array(self.s.dd, shape=(max(N, 1),))[:N].copy()
+
+    @property
+    def ds(self):
+        N = self.s.N
+        return np.ctypeslib.as_array(self.s.ds, shape=(max(N, 1),))[:N].copy()
+
+    @property
+    def L(self):
+        N = self.s.N
+        a = np.ctypeslib.as_array(self.s.L, shape=(max(N * N, 1),))[:N * N].copy()
+        return np.tril(a.reshape((N, N), order="F"), -1) + np.eye(N)
+
+    def solve(self, r_d, r_s, r_y):
+        P = self.P
+        o = [_buf(P.n_d), _buf(P.n_s), _buf(P.m)]
+        a = [_f64(v) if len(v) else _buf(1) for v in (r_d, r_s, r_y)]
+        st = lib().or_newton_solve(P.ptr, self.p, _d(a[0]), _d(a[1]), _d(a[2]),
+                                   _d(o[0]), _d(o[1]), _d(o[2]))
+        return o[0][:P.n_d], o[1][:P.n_s], o[2][:P.m], st
+
+    def refine(self, r_d, r_s, r_y, max_steps=5, eta_tol=1e-14):
+        P = self.P
+        o = [_buf(P.n_d), _buf(P.n_s), _buf(P.m)]
+        a = [_f64(v) if len(v) else _buf(1) for v in (r_d, r_s, r_y)]
+        eta = np.zeros(1)
+        steps = lib().or_newton_refine(P.ptr, self.p, _d(self._sd), _d(self._db), _d(a[0]),
+                                       _d(a[1]), _d(a[2]), _d(o[0]), _d(o[1]), _d(o[2]),
+                                       max_steps, eta_tol, _d(eta))
+        return o[0][:P.n_d], o[1][:P.n_s], o[2][:P.m], steps, float(eta[0])
+
+
+def sigma_rhs(P: Problem, x, y, zl, zu, mu):
+    n = P.n_d + P.n_s
+    sig, rx, ry = _buf(n), _buf(n), _buf(P.m)
+    a = [_f64(v) if len(v) else _buf(1) for v in (x, y, zl, zu)]
+    lib().or_sigma_rhs(P.ptr, _d(a[0]), _d(a[1]), _d(a[2]), _d(a[3]), mu, _d(sig), _d(rx),
+                       _d(ry))
+    return sig[:n], rx[:n], ry[:P.m]
+
+
+def ftb(v, dv, tau):
+    v, dv = _f64(v), _f64(dv)
+    return lib().or_ftb(len(v), _d(v if len(v) else _buf(1)), _d(dv if len(dv) else _buf(1)),
+                        tau)
+
+
+def opt_error(P: Problem, x, y, zl, zu, mu):
+    parts = np.zeros(6)
+    a = [_f64(v) if len(v) else _buf(1) for v in (x, y, zl, zu)]
+    e = lib().or_opt_error(P.ptr, _d(a[0]), _d(a[1]), _d(a[2]), _d(a[3]), mu, _d(parts))
+    return e, parts
+
+
+def objective(P: Problem, x):
+    return lib().or_objective(P.ptr, _d(_f64(x)))
+
+
+def barrier(P: Problem, x, mu):
+    return lib().or_barrier(P.ptr, _d(_f64(x)), mu)
+
+
+def theta(P: Problem, x):
+    return lib().or_theta(P.ptr, _d(_f64(x)))
+
+
+IPM_STATUS = {4: "converged", 5: "ls_fail", 6: "maxiter", 2: "inertia_fail", 7: "nonfinite"}
+
+
+def ipm(P: Problem, tol=1e-8, mu0=0.1, max_iter=200, refine_steps=2, dw_max=1e20):
+    """Whole filter line-search IPM.  Returns dict with x, y, zl, zu, status, iters, trace."""
+    n = P.n_d + P.n_s
+    x, zl, zu, y = _buf(n), _buf(n), _buf(n), _buf(P.m)
+    it = np.zeros(1, dtype=np.int32)
+    opts = OrIpmOpts(tol, mu0, max_iter, refine_steps, dw_max)
+    tr = (OrIpmTrace * (max_iter + 1))()
+    st = lib().or_ipm(P.ptr, C.byref(opts), _d(x), _d(y), _d(zl), _d(zu), _i(it), tr)
+    iters = int(it[0])
+    rows = []
+    for k in range(min(iters + 1, max_iter)):
+        t = tr[k]
+        rows.append(dict(mu=t.mu, E0=t.E0, theta=t.theta, phi=t.phi, alpha_pr=t.alpha_pr,
+                         alpha_du=t.alpha_du, dw=t.dw, dc=t.dc, inertia=tuple(t.inertia),
+                         trials=t.trials, backtracks=t.backtracks))
+    return dict(x=x[:n], y=y[:P.m], zl=zl[:n], zu=zu[:n], status=IPM_STATUS.get(st, st),
+                code=st, iters=iters, trace=rows)

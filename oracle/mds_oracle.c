@@ -1,0 +1,767 @@
+/*
+ * Plain FP64 CPU oracle for the mixed dense-sparse interior-point Newton step.
+ * TEST INFRASTRUCTURE ONLY (see mds_oracle.h).  Build: gcc -O2 -ffp-contract=off.
+ *
+ * The paper (Peles et al., HiOp on accelerators) fixes the method:
+ *  - Sec. 2, eqs. (obj)-(bounds): the MDS problem; assumptions A1/A2;
+ *  - Sec. 2.1, eq. (linsys4x4): the Newton/KKT system, the inertia requirement
+ *    (n,0,m) and its enforcement by diagonal shifts;
+ *  - Sec. 2.2, eq. (compressed): Gauss elimination of the sparse block;
+ *  - Sec. 2.3: kernel classes K1-K4, Bunch-Kaufman LDL' and Haynsworth
+ *    inertia additivity.
+ * Where the paper defers to Waechter & Biegler (the filter line-search IPM and
+ * its inertia-correction algorithm) the constants are theirs.
+ */
+#include "mds_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define IDX(i, j, ld) ((size_t)(j) * (size_t)(ld) + (size_t)(i))
+
+/* ======================================================================== */
+/* Condensation: Sec. 2.2, eq. (compressed) with no inequality block.        */
+/* ======================================================================== */
+
+void or_condense(const orq_problem *P, const double *sigma_d, const double *dsbase,
+                 double dw, double dc, double *M, double *inv_d) {
+  const int nd = P->n_d, ns = P->n_s, m = P->m, N = nd + m;
+  for (int k = 0; k < ns; ++k) inv_d[k] = 1.0 / (dsbase[k] + dw);
+  /* (1,1) block: H + Sigma_d + dw I  (Q_{x_d} with its shift) */
+  for (int j = 0; j < nd; ++j)
+    for (int i = 0; i < nd; ++i) {
+      double h = (i >= j) ? P->H[IDX(i, j, nd)] : P->H[IDX(j, i, nd)];
+      if (i == j) h = (h + sigma_d[i]) + dw;
+      M[IDX(i, j, N)] = h;
+    }
+  /* (2,1) and (1,2) blocks: the dense Jacobian J_d and its transpose */
+  for (int j = 0; j < nd; ++j)
+    for (int i = 0; i < m; ++i) {
+      M[IDX(nd + i, j, N)] = P->Jd[IDX(i, j, m)];
+      M[IDX(j, nd + i, N)] = P->Jd[IDX(i, j, m)];
+    }
+  /* (2,2) block: -J_s D_s^{-1} J_s' - dc I.  Entry (i,j), i >= j, sums over the
+   * shared columns k of rows i and j in ascending k. */
+  for (int j = 0; j < m; ++j)
+    for (int i = j; i < m; ++i) {
+      double acc = 0.0;
+      int a = P->rp[i], ae = P->rp[i + 1], b = P->rp[j], be = P->rp[j + 1];
+      while (a < ae && b < be) {
+        int ka = P->ci[a], kb = P->ci[b];
+        if (ka < kb) ++a;
+        else if (kb < ka) ++b;
+        else {
+          acc = acc - (P->v[a] * inv_d[ka]) * P->v[b];
+          ++a; ++b;
+        }
+      }
+      if (i == j) acc = acc - dc;
+      M[IDX(nd + i, nd + j, N)] = acc;
+      M[IDX(nd + j, nd + i, N)] = acc;
+    }
+}
+
+void or_rhs_condense(const orq_problem *P, const double *inv_d, const double *r_s,
+                     const double *r_y, double *rhat) {
+  for (int i = 0; i < P->m; ++i) {
+    double t = r_y[i];
+    for (int a = P->rp[i]; a < P->rp[i + 1]; ++a) {
+      int k = P->ci[a];
+      t = t - P->v[a] * (inv_d[k] * r_s[k]);
+    }
+    rhat[i] = t;
+  }
+}
+
+void or_backsub(const orq_problem *P, const double *inv_d, const double *r_s,
+                const double *dy, double *dx_s) {
+  /* t = r_s - J_s' dy, accumulated row by row in ascending row order */
+  double *t = (double *)malloc(sizeof(double) * (size_t)(P->n_s > 0 ? P->n_s : 1));
+  for (int k = 0; k < P->n_s; ++k) t[k] = r_s[k];
+  for (int i = 0; i < P->m; ++i)
+    for (int a = P->rp[i]; a < P->rp[i + 1]; ++a) t[P->ci[a]] = t[P->ci[a]] - P->v[a] * dy[i];
+  for (int k = 0; k < P->n_s; ++k) dx_s[k] = inv_d[k] * t[k];
+  free(t);
+}
+
+/* ======================================================================== */
+/* Bunch-Kaufman diagonal pivoting, lower triangle, left to right (Sec. 2.3). */
+/* ======================================================================== */
+
+static void swap_d(double *a, double *b) {
+  double t = *a; *a = *b; *b = t;
+}
+
+int or_bk(int32_t N, double *A, int32_t *ipiv, double *dd, double *ds, int32_t *kind) {
+  const double alpha = (1.0 + sqrt(17.0)) / 8.0;
+  int info = 0;
+  double *w0 = (double *)malloc(sizeof(double) * (size_t)(N > 0 ? N : 1));
+  double *w1 = (double *)malloc(sizeof(double) * (size_t)(N > 0 ? N : 1));
+  double *l0 = (double *)malloc(sizeof(double) * (size_t)(N > 0 ? N : 1));
+  double *l1 = (double *)malloc(sizeof(double) * (size_t)(N > 0 ? N : 1));
+  for (int i = 0; i < N; ++i) { dd[i] = 0.0; ds[i] = 0.0; }
+  int k = 0;
+  while (k < N) {
+    double absakk = fabs(A[IDX(k, k, N)]);
+    /* column maximum below the diagonal; the first index wins ties */
+    int imax = k;
+    double colmax = 0.0;
+    for (int i = k + 1; i < N; ++i) {
+      double t = fabs(A[IDX(i, k, N)]);
+      if (t > colmax) { colmax = t; imax = i; }
+    }
+    if (fmax(absakk, colmax) == 0.0 || isnan(absakk)) {
+      /* zero column: record a zero 1x1 pivot and move on without elimination */
+      if (info == 0) info = k + 1;
+      ipiv[k] = k + 1;
+      dd[k] = A[IDX(k, k, N)];
+      if (kind) kind[k] = 0;
+      k += 1;
+      continue;
+    }
+    int kp = k, kstep = 1, br = 1;
+    if (absakk >= alpha * colmax) {
+      kp = k; br = 1;
+    } else {
+      /* largest off-diagonal magnitude in row/column imax of the active part */
+      double rowmax = 0.0;
+      for (int j = k; j < imax; ++j) rowmax = fmax(rowmax, fabs(A[IDX(imax, j, N)]));
+      for (int i = imax + 1; i < N; ++i) rowmax = fmax(rowmax, fabs(A[IDX(i, imax, N)]));
+      if (absakk >= alpha * colmax * (colmax / rowmax)) {
+        kp = k; br = 2;
+      } else if (fabs(A[IDX(imax, imax, N)]) >= alpha * rowmax) {
+        kp = imax; br = 3;
+      } else {
+        kp = imax; kstep = 2; br = 4;
+      }
+    }
+    if (kind) { kind[k] = br; if (kstep == 2) kind[k + 1] = br; }
+    /* symmetric interchange of indices p = k+kstep-1 and q = kp (lower storage) */
+    int p = k + kstep - 1, q = kp;
+    if (q != p) {
+      for (int j = 0; j < p; ++j) swap_d(&A[IDX(p, j, N)], &A[IDX(q, j, N)]);
+      for (int j = p + 1; j < q; ++j) swap_d(&A[IDX(j, p, N)], &A[IDX(q, j, N)]);
+      swap_d(&A[IDX(p, p, N)], &A[IDX(q, q, N)]);
+      for (int i = q + 1; i < N; ++i) swap_d(&A[IDX(i, p, N)], &A[IDX(i, q, N)]);
+    }
+    if (kstep == 1) {
+      double d = A[IDX(k, k, N)];
+      dd[k] = d;
+      ipiv[k] = kp + 1;
+      for (int i = k + 1; i < N; ++i) { w0[i] = A[IDX(i, k, N)]; l0[i] = w0[i] / d; }
+      /* rank-1 update of the trailing lower triangle: A -= l w' */
+      for (int j = k + 1; j < N; ++j)
+        for (int i = j; i < N; ++i) A[IDX(i, j, N)] = A[IDX(i, j, N)] - l0[i] * w0[j];
+      for (int i = k + 1; i < N; ++i) A[IDX(i, k, N)] = l0[i];
+      k += 1;
+    } else {
+      double a = A[IDX(k, k, N)], b = A[IDX(k + 1, k, N)], c = A[IDX(k + 1, k + 1, N)];
+      double det = a * c - b * b;
+      dd[k] = a; dd[k + 1] = c; ds[k] = b;
+      ipiv[k] = -(kp + 1);
+      ipiv[k + 1] = -(kp + 1);
+      /* L rows = [w0 w1] * inv([[a b];[b c]]) by Cramer's rule */
+      for (int i = k + 2; i < N; ++i) {
+        double x = A[IDX(i, k, N)], y = A[IDX(i, k + 1, N)];
+        w0[i] = x; w1[i] = y;
+        l0[i] = (x * c - y * b) / det;
+        l1[i] = (y * a - x * b) / det;
+      }
+      /* rank-2 update: A -= [l0 l1] [w0 w1]' */
+      for (int j = k + 2; j < N; ++j)
+        for (int i = j; i < N; ++i)
+          A[IDX(i, j, N)] = A[IDX(i, j, N)] - (l0[i] * w0[j] + l1[i] * w1[j]);
+      for (int i = k + 2; i < N; ++i) { A[IDX(i, k, N)] = l0[i]; A[IDX(i, k + 1, N)] = l1[i]; }
+      A[IDX(k + 1, k, N)] = 0.0; /* belongs to D, not to L */
+      k += 2;
+    }
+  }
+  free(w0); free(w1); free(l0); free(l1);
+  return info;
+}
+
+/* Inertia from the block-diagonal D (Sec. 2.3 and Sylvester's law of inertia):
+ * a 1x1 pivot counts by its sign; every 2x2 block that Bunch-Kaufman selects
+ * has a negative determinant (|a c| < alpha^2 b^2 < b^2) and so counts (1,0,1). */
+void or_inertia(int32_t N, const int32_t *ipiv, const double *dd, const double *ds,
+                int32_t out[3]) {
+  (void)ds;
+  out[0] = out[1] = out[2] = 0;
+  for (int k = 0; k < N;) {
+    if (ipiv[k] > 0) {
+      if (dd[k] > 0.0) out[0]++;
+      else if (dd[k] < 0.0) out[2]++;
+      else out[1]++;
+      k += 1;
+    } else {
+      out[0]++; out[2]++;
+      k += 2;
+    }
+  }
+}
+
+int or_ldl_solve(int32_t N, const double *L, const int32_t *ipiv, const double *dd,
+                 const double *ds, double *b) {
+  int status = 0;
+  /* b <- P' b : interchanges in pivot order */
+  for (int k = 0; k < N;) {
+    if (ipiv[k] > 0) {
+      int kp = ipiv[k] - 1;
+      if (kp != k) swap_d(&b[k], &b[kp]);
+      k += 1;
+    } else {
+      int kp = -ipiv[k] - 1;
+      if (kp != k + 1) swap_d(&b[k + 1], &b[kp]);
+      k += 2;
+    }
+  }
+  /* L y = b (unit lower) */
+  for (int j = 0; j < N; ++j)
+    for (int i = j + 1; i < N; ++i) b[i] = b[i] - L[IDX(i, j, N)] * b[j];
+  /* D z = y */
+  for (int k = 0; k < N;) {
+    if (ipiv[k] > 0) {
+      if (dd[k] == 0.0) status = 1;
+      b[k] = b[k] / dd[k];
+      k += 1;
+    } else {
+      double a = dd[k], c = dd[k + 1], s = ds[k];
+      double det = a * c - s * s;
+      double y0 = b[k], y1 = b[k + 1];
+      b[k] = (c * y0 - s * y1) / det;
+      b[k + 1] = (a * y1 - s * y0) / det;
+      k += 2;
+    }
+  }
+  /* L' x = z */
+  for (int j = N - 1; j >= 0; --j) {
+    double t = b[j];
+    for (int i = j + 1; i < N; ++i) t = t - L[IDX(i, j, N)] * b[i];
+    b[j] = t;
+  }
+  /* x <- P x : interchanges in reverse pivot order */
+  int *start = (int *)malloc(sizeof(int) * (size_t)(N > 0 ? N : 1));
+  int np = 0;
+  for (int k = 0; k < N;) { start[np++] = k; k += (ipiv[k] > 0) ? 1 : 2; }
+  for (int t = np - 1; t >= 0; --t) {
+    int k = start[t];
+    if (ipiv[k] > 0) {
+      int kp = ipiv[k] - 1;
+      if (kp != k) swap_d(&b[k], &b[kp]);
+    } else {
+      int kp = -ipiv[k] - 1;
+      if (kp != k + 1) swap_d(&b[k + 1], &b[kp]);
+    }
+  }
+  free(start);
+  return status;
+}
+
+/* ======================================================================== */
+/* Full KKT operator of eq. (linsys4x4) restricted to equality constraints. */
+/* ======================================================================== */
+
+void or_kkt_matvec(const orq_problem *P, const double *sigma_d, const double *dsbase,
+                   double dw, double dc, const double *dx_d, const double *dx_s,
+                   const double *dy, double *o_d, double *o_s, double *o_y) {
+  const int nd = P->n_d, ns = P->n_s, m = P->m;
+  for (int i = 0; i < nd; ++i) {
+    double t = 0.0;
+    for (int j = 0; j < nd; ++j) {
+      double h = (i >= j) ? P->H[IDX(i, j, nd)] : P->H[IDX(j, i, nd)];
+      t = t + h * dx_d[j];
+    }
+    t = t + (sigma_d[i] + dw) * dx_d[i];
+    for (int r = 0; r < m; ++r) t = t + P->Jd[IDX(r, i, m)] * dy[r];
+    o_d[i] = t;
+  }
+  for (int k = 0; k < ns; ++k) o_s[k] = (dsbase[k] + dw) * dx_s[k];
+  for (int r = 0; r < m; ++r)
+    for (int a = P->rp[r]; a < P->rp[r + 1]; ++a) o_s[P->ci[a]] = o_s[P->ci[a]] + P->v[a] * dy[r];
+  for (int r = 0; r < m; ++r) {
+    double t = 0.0;
+    for (int j = 0; j < nd; ++j) t = t + P->Jd[IDX(r, j, m)] * dx_d[j];
+    for (int a = P->rp[r]; a < P->rp[r + 1]; ++a) t = t + P->v[a] * dx_s[P->ci[a]];
+    t = t - dc * dy[r];
+    o_y[r] = t;
+  }
+}
+
+double or_kkt_norm_inf(const orq_problem *P, const double *sigma_d, const double *dsbase,
+                       double dw, double dc) {
+  const int nd = P->n_d, ns = P->n_s, m = P->m;
+  double best = 0.0;
+  for (int i = 0; i < nd; ++i) {
+    double t = 0.0;
+    for (int j = 0; j < nd; ++j) {
+      double h = (i >= j) ? P->H[IDX(i, j, nd)] : P->H[IDX(j, i, nd)];
+      if (i == j) h = h + sigma_d[i] + dw;
+      t += fabs(h);
+    }
+    for (int r = 0; r < m; ++r) t += fabs(P->Jd[IDX(r, i, m)]);
+    best = fmax(best, t);
+  }
+  double *col = (double *)calloc((size_t)(ns > 0 ? ns : 1), sizeof(double));
+  for (int r = 0; r < m; ++r)
+    for (int a = P->rp[r]; a < P->rp[r + 1]; ++a) col[P->ci[a]] += fabs(P->v[a]);
+  for (int k = 0; k < ns; ++k) best = fmax(best, fabs(dsbase[k] + dw) + col[k]);
+  free(col);
+  for (int r = 0; r < m; ++r) {
+    double t = fabs(dc);
+    for (int j = 0; j < nd; ++j) t += fabs(P->Jd[IDX(r, j, m)]);
+    for (int a = P->rp[r]; a < P->rp[r + 1]; ++a) t += fabs(P->v[a]);
+    best = fmax(best, t);
+  }
+  return best;
+}
+
+/* ======================================================================== */
+/* Factor objects, the inertia-correction loop, solve and refinement.       */
+/* ======================================================================== */
+
+or_factor *or_factor_new(const orq_problem *P) {
+  or_factor *F = (or_factor *)calloc(1, sizeof(or_factor));
+  int N = P->n_d + P->m;
+  F->N = N;
+  size_t nn = (size_t)N * (size_t)N;
+  F->L = (double *)malloc(sizeof(double) * (nn > 0 ? nn : 1));
+  F->dd = (double *)malloc(sizeof(double) * (size_t)(N > 0 ? N : 1));
+  F->ds = (double *)malloc(sizeof(double) * (size_t)(N > 0 ? N : 1));
+  F->ipiv = (int32_t *)malloc(sizeof(int32_t) * (size_t)(N > 0 ? N : 1));
+  F->inv_d = (double *)malloc(sizeof(double) * (size_t)(P->n_s > 0 ? P->n_s : 1));
+  return F;
+}
+
+void or_factor_free(or_factor *F) {
+  if (!F) return;
+  free(F->L); free(F->dd); free(F->ds); free(F->ipiv); free(F->inv_d); free(F);
+}
+
+void or_factor_once(const orq_problem *P, const double *sigma_d, const double *dsbase,
+                    double dw, double dc, or_factor *F) {
+  F->dw = dw;
+  F->dc = dc;
+  or_condense(P, sigma_d, dsbase, dw, dc, F->L, F->inv_d);
+  F->info = or_bk(F->N, F->L, F->ipiv, F->dd, F->ds, NULL);
+  or_inertia(F->N, F->ipiv, F->dd, F->ds, F->inertia);
+}
+
+static int inertia_ok(const orq_problem *P, const or_factor *F) {
+  return F->inertia[0] == P->n_d && F->inertia[1] == 0 && F->inertia[2] == P->m;
+}
+
+int or_factor_inertia(const orq_problem *P, const double *sigma_d, const double *dsbase,
+                      double mu, double *dw_last, double dw_max, or_factor *F) {
+  /* Waechter & Biegler (2006), Algorithm IC, with their constants. */
+  const double dw_min = 1e-20, dw0 = 1e-4, kw_minus = 1.0 / 3.0, kw_plus = 8.0,
+               kw_plus_bar = 100.0, dc_bar = 1e-8, kappa_c = 0.25;
+  F->trials = 1;
+  or_factor_once(P, sigma_d, dsbase, 0.0, 0.0, F);
+  if (inertia_ok(P, F)) return 0;
+  double dc = (F->inertia[1] > 0) ? dc_bar * pow(mu, kappa_c) : 0.0;
+  double dw = (*dw_last == 0.0) ? dw0 : fmax(dw_min, kw_minus * *dw_last);
+  for (;;) {
+    F->trials++;
+    or_factor_once(P, sigma_d, dsbase, dw, dc, F);
+    if (inertia_ok(P, F)) { *dw_last = dw; return 0; }
+    dw = (*dw_last == 0.0) ? kw_plus_bar * dw : kw_plus * dw;
+    if (dw > dw_max) return 2;
+  }
+}
+
+int or_newton_solve(const orq_problem *P, const or_factor *F, const double *r_d,
+                    const double *r_s, const double *r_y, double *dx_d, double *dx_s,
+                    double *dy) {
+  const int nd = P->n_d, m = P->m, N = nd + m;
+  double *z = (double *)malloc(sizeof(double) * (size_t)(N > 0 ? N : 1));
+  for (int i = 0; i < nd; ++i) z[i] = r_d[i];
+  or_rhs_condense(P, F->inv_d, r_s, r_y, z + nd);
+  int st = or_ldl_solve(N, F->L, F->ipiv, F->dd, F->ds, z);
+  for (int i = 0; i < nd; ++i) dx_d[i] = z[i];
+  for (int i = 0; i < m; ++i) dy[i] = z[nd + i];
+  or_backsub(P, F->inv_d, r_s, dy, dx_s);
+  free(z);
+  return st;
+}
+
+static double amax(int64_t n, const double *v) {
+  double t = 0.0;
+  for (int64_t i = 0; i < n; ++i) t = fmax(t, fabs(v[i]));
+  return t;
+}
+
+int or_newton_refine(const orq_problem *P, const or_factor *F, const double *sigma_d,
+                     const double *dsbase, const double *r_d, const double *r_s,
+                     const double *r_y, double *dx_d, double *dx_s, double *dy,
+                     int32_t max_steps, double eta_tol, double *eta_out) {
+  const int nd = P->n_d, ns = P->n_s, m = P->m;
+  size_t nt = (size_t)nd + (size_t)ns + (size_t)m;
+  double *buf = (double *)malloc(sizeof(double) * (nt * 4 + 1));
+  double *res = buf, *cor = buf + nt, *prev = buf + 2 * nt, *kx = buf + 3 * nt;
+  or_newton_solve(P, F, r_d, r_s, r_y, dx_d, dx_s, dy);
+  double nK = or_kkt_norm_inf(P, sigma_d, dsbase, F->dw, F->dc);
+  double nr = fmax(amax(nd, r_d), fmax(amax(ns, r_s), amax(m, r_y)));
+  double eta_prev = INFINITY;
+  int steps = 0;
+  double eta = 0.0;
+  for (;;) {
+    or_kkt_matvec(P, sigma_d, dsbase, F->dw, F->dc, dx_d, dx_s, dy, kx, kx + nd, kx + nd + ns);
+    for (int i = 0; i < nd; ++i) res[i] = r_d[i] - kx[i];
+    for (int i = 0; i < ns; ++i) res[nd + i] = r_s[i] - kx[nd + i];
+    for (int i = 0; i < m; ++i) res[nd + ns + i] = r_y[i] - kx[nd + ns + i];
+    double nx = fmax(amax(nd, dx_d), fmax(amax(ns, dx_s), amax(m, dy)));
+    double den = nK * nx + nr;
+    eta = (den > 0.0) ? amax((int64_t)nt, res) / den : 0.0;
+    if (steps > 0 && !(eta < eta_prev)) {
+      /* no decrease: keep the previous iterate */
+      memcpy(dx_d, prev, sizeof(double) * (size_t)nd);
+      memcpy(dx_s, prev + nd, sizeof(double) * (size_t)ns);
+      memcpy(dy, prev + nd + ns, sizeof(double) * (size_t)m);
+      eta = eta_prev;
+      break;
+    }
+    if (eta <= eta_tol || steps >= max_steps) break;
+    memcpy(prev, dx_d, sizeof(double) * (size_t)nd);
+    memcpy(prev + nd, dx_s, sizeof(double) * (size_t)ns);
+    memcpy(prev + nd + ns, dy, sizeof(double) * (size_t)m);
+    eta_prev = eta;
+    or_newton_solve(P, F, res, res + nd, res + nd + ns, cor, cor + nd, cor + nd + ns);
+    for (int i = 0; i < nd; ++i) dx_d[i] = dx_d[i] + cor[i];
+    for (int i = 0; i < ns; ++i) dx_s[i] = dx_s[i] + cor[nd + i];
+    for (int i = 0; i < m; ++i) dy[i] = dy[i] + cor[nd + ns + i];
+    steps++;
+  }
+  if (eta_out) *eta_out = eta;
+  free(buf);
+  return steps;
+}
+
+/* ======================================================================== */
+/* IPM vector quantities (K1/K2).                                           */
+/* ======================================================================== */
+
+static void grad_f(const orq_problem *P, const double *x, double *gf) {
+  const int nd = P->n_d, ns = P->n_s;
+  for (int i = 0; i < nd; ++i) {
+    double t = 0.0;
+    for (int j = 0; j < nd; ++j) {
+      double h = (i >= j) ? P->H[IDX(i, j, nd)] : P->H[IDX(j, i, nd)];
+      t = t + h * x[j];
+    }
+    gf[i] = t + P->c[i];
+  }
+  for (int k = 0; k < ns; ++k) gf[nd + k] = P->w[k] * x[nd + k] + P->g[k];
+}
+
+/* c(x) = J x - b */
+static void constr(const orq_problem *P, const double *x, double *cx) {
+  const int nd = P->n_d, m = P->m;
+  for (int r = 0; r < m; ++r) {
+    double t = 0.0;
+    for (int j = 0; j < nd; ++j) t = t + P->Jd[IDX(r, j, m)] * x[j];
+    for (int a = P->rp[r]; a < P->rp[r + 1]; ++a) t = t + P->v[a] * x[nd + P->ci[a]];
+    cx[r] = t - P->b[r];
+  }
+}
+
+/* out = J' y */
+static void jac_t(const orq_problem *P, const double *y, double *out) {
+  const int nd = P->n_d, ns = P->n_s, m = P->m;
+  for (int j = 0; j < nd; ++j) {
+    double t = 0.0;
+    for (int r = 0; r < m; ++r) t = t + P->Jd[IDX(r, j, m)] * y[r];
+    out[j] = t;
+  }
+  for (int k = 0; k < ns; ++k) out[nd + k] = 0.0;
+  for (int r = 0; r < m; ++r)
+    for (int a = P->rp[r]; a < P->rp[r + 1]; ++a) out[nd + P->ci[a]] = out[nd + P->ci[a]] + P->v[a] * y[r];
+}
+
+void or_sigma_rhs(const orq_problem *P, const double *x, const double *y, const double *zl,
+                  const double *zu, double mu, double *sigma, double *r_x, double *r_y) {
+  const int n = P->n_d + P->n_s, m = P->m;
+  double *gf = (double *)malloc(sizeof(double) * (size_t)n);
+  double *jy = (double *)malloc(sizeof(double) * (size_t)n);
+  grad_f(P, x, gf);
+  jac_t(P, y, jy);
+  for (int i = 0; i < n; ++i) {
+    double s = 0.0, gb = gf[i] + jy[i];
+    if (isfinite(P->xl[i])) {
+      double sl = x[i] - P->xl[i];
+      s = s + zl[i] / sl;
+      gb = gb - mu / sl;
+    }
+    if (isfinite(P->xu[i])) {
+      double su = P->xu[i] - x[i];
+      s = s + zu[i] / su;
+      gb = gb + mu / su;
+    }
+    sigma[i] = s;
+    r_x[i] = -gb;
+  }
+  double *cx = (double *)malloc(sizeof(double) * (size_t)(m > 0 ? m : 1));
+  constr(P, x, cx);
+  for (int r = 0; r < m; ++r) r_y[r] = -cx[r];
+  free(cx); free(gf); free(jy);
+}
+
+double or_ftb(int64_t n, const double *v, const double *dv, double tau) {
+  double a = 1.0;
+  for (int64_t i = 0; i < n; ++i)
+    if (dv[i] < 0.0) a = fmin(a, -tau * v[i] / dv[i]);
+  return a;
+}
+
+double or_opt_error(const orq_problem *P, const double *x, const double *y,
+                    const double *zl, const double *zu, double mu, double parts[6]) {
+  const int n = P->n_d + P->n_s, m = P->m;
+  const double s_max = 100.0;
+  double *gf = (double *)malloc(sizeof(double) * (size_t)n);
+  double *jy = (double *)malloc(sizeof(double) * (size_t)n);
+  double *cx = (double *)malloc(sizeof(double) * (size_t)(m > 0 ? m : 1));
+  grad_f(P, x, gf);
+  jac_t(P, y, jy);
+  constr(P, x, cx);
+  double dual = 0.0, cl = 0.0, cu = 0.0, z1 = 0.0, y1 = 0.0;
+  int nz = 0;
+  for (int i = 0; i < n; ++i) {
+    double r = gf[i] + jy[i];
+    if (isfinite(P->xl[i])) {
+      r = r - zl[i];
+      cl = fmax(cl, fabs((x[i] - P->xl[i]) * zl[i] - mu));
+      z1 += fabs(zl[i]);
+      nz++;
+    }
+    if (isfinite(P->xu[i])) {
+      r = r + zu[i];
+      cu = fmax(cu, fabs((P->xu[i] - x[i]) * zu[i] - mu));
+      z1 += fabs(zu[i]);
+      nz++;
+    }
+    dual = fmax(dual, fabs(r));
+  }
+  double prim = 0.0;
+  for (int r = 0; r < m; ++r) { prim = fmax(prim, fabs(cx[r])); y1 += fabs(y[r]); }
+  double sd = (m + nz > 0) ? fmax(s_max, (y1 + z1) / (double)(m + nz)) / s_max : 1.0;
+  double sc = (nz > 0) ? fmax(s_max, z1 / (double)nz) / s_max : 1.0;
+  if (parts) {
+    parts[0] = dual; parts[1] = prim; parts[2] = cl; parts[3] = cu; parts[4] = sd; parts[5] = sc;
+  }
+  free(gf); free(jy); free(cx);
+  return fmax(fmax(dual / sd, prim), fmax(cl, cu) / sc);
+}
+
+double or_objective(const orq_problem *P, const double *x) {
+  const int nd = P->n_d, ns = P->n_s;
+  double f = 0.0;
+  for (int i = 0; i < nd; ++i) {
+    double t = 0.0;
+    for (int j = 0; j < nd; ++j) {
+      double h = (i >= j) ? P->H[IDX(i, j, nd)] : P->H[IDX(j, i, nd)];
+      t = t + h * x[j];
+    }
+    f = f + x[i] * (0.5 * t + P->c[i]);
+  }
+  for (int k = 0; k < ns; ++k) {
+    double xs = x[nd + k];
+    f = f + xs * (0.5 * P->w[k] * xs + P->g[k]);
+  }
+  return f;
+}
+
+double or_barrier(const orq_problem *P, const double *x, double mu) {
+  const int n = P->n_d + P->n_s;
+  double lg = 0.0;
+  for (int i = 0; i < n; ++i) {
+    if (isfinite(P->xl[i])) lg = lg + log(x[i] - P->xl[i]);
+    if (isfinite(P->xu[i])) lg = lg + log(P->xu[i] - x[i]);
+  }
+  return or_objective(P, x) - mu * lg;
+}
+
+double or_theta(const orq_problem *P, const double *x) {
+  double *cx = (double *)malloc(sizeof(double) * (size_t)(P->m > 0 ? P->m : 1));
+  constr(P, x, cx);
+  double t = 0.0;
+  for (int r = 0; r < P->m; ++r) t += fabs(cx[r]);
+  free(cx);
+  return t;
+}
+
+/* ======================================================================== */
+/* Filter line-search IPM (Sec. 2.1).                                        */
+/* ======================================================================== */
+
+typedef struct { double th, ph; } fentry;
+
+int or_ipm(const orq_problem *P, const or_ipm_opts *o, double *x, double *y, double *zl,
+           double *zu, int32_t *iters, or_ipm_trace *trace) {
+  const int nd = P->n_d, ns = P->n_s, m = P->m, n = nd + ns;
+  /* Waechter & Biegler (2006) defaults */
+  const double tau_min = 0.99, kappa_eps = 10.0, kappa_mu = 0.2, theta_mu = 1.5;
+  const double kappa_sigma = 1e10, gamma_theta = 1e-5, gamma_phi = 1e-8, delta = 1.0;
+  const double s_theta = 1.1, s_phi = 2.3, eta_phi = 1e-8, gamma_alpha = 0.05;
+  const double kappa1 = 1e-2, kappa2 = 1e-2;
+  int status = 6;
+
+  /* start point: x = 0 pushed into the interior of its bounds */
+  for (int i = 0; i < n; ++i) {
+    double l = P->xl[i], u = P->xu[i], xi = 0.0;
+    int hl = isfinite(l), hu = isfinite(u);
+    if (hl && hu) {
+      double pl = fmin(kappa1 * fmax(1.0, fabs(l)), kappa2 * (u - l));
+      double pu = fmin(kappa1 * fmax(1.0, fabs(u)), kappa2 * (u - l));
+      xi = fmin(fmax(xi, l + pl), u - pu);
+    } else if (hl) {
+      xi = fmax(xi, l + kappa1 * fmax(1.0, fabs(l)));
+    } else if (hu) {
+      xi = fmin(xi, u - kappa1 * fmax(1.0, fabs(u)));
+    }
+    x[i] = xi;
+    zl[i] = hl ? 1.0 : 0.0;
+    zu[i] = hu ? 1.0 : 0.0;
+  }
+  for (int r = 0; r < m; ++r) y[r] = 0.0;
+  double mu = o->mu0, tau = fmax(tau_min, 1.0 - mu), dw_last = 0.0;
+  double th0 = or_theta(P, x);
+  double theta_max = 1e4 * fmax(1.0, th0), theta_min = 1e-4 * fmax(1.0, th0);
+  fentry *filt = (fentry *)malloc(sizeof(fentry) * (size_t)(o->max_iter + 1));
+  int nf = 0;
+
+  double *sig = (double *)malloc(sizeof(double) * (size_t)n);
+  double *rx = (double *)malloc(sizeof(double) * (size_t)n);
+  double *ry = (double *)malloc(sizeof(double) * (size_t)(m > 0 ? m : 1));
+  double *dsb = (double *)malloc(sizeof(double) * (size_t)(ns > 0 ? ns : 1));
+  double *dx = (double *)malloc(sizeof(double) * (size_t)n);
+  double *dy = (double *)malloc(sizeof(double) * (size_t)(m > 0 ? m : 1));
+  double *dzl = (double *)malloc(sizeof(double) * (size_t)n);
+  double *dzu = (double *)malloc(sizeof(double) * (size_t)n);
+  double *xt = (double *)malloc(sizeof(double) * (size_t)n);
+  double *gf = (double *)malloc(sizeof(double) * (size_t)n);
+  or_factor *F = or_factor_new(P);
+
+  int it = 0;
+  for (it = 0; it < o->max_iter; ++it) {
+    double E0 = or_opt_error(P, x, y, zl, zu, 0.0, NULL);
+    if (!isfinite(E0)) { status = 7; break; }
+    if (trace) { memset(&trace[it], 0, sizeof(or_ipm_trace)); trace[it].E0 = E0; }
+    if (E0 <= o->tol) { status = 4; break; }
+    /* barrier update while the barrier subproblem is solved to kappa_eps*mu */
+    while (or_opt_error(P, x, y, zl, zu, mu, NULL) <= kappa_eps * mu) {
+      double mnew = fmax(o->tol / 10.0, fmin(kappa_mu * mu, pow(mu, theta_mu)));
+      if (!(mnew < mu)) break;
+      mu = mnew;
+      tau = fmax(tau_min, 1.0 - mu);
+      nf = 0;
+    }
+    /* Newton system */
+    or_sigma_rhs(P, x, y, zl, zu, mu, sig, rx, ry);
+    for (int k = 0; k < ns; ++k) dsb[k] = P->w[k] + sig[nd + k];
+    int fst = or_factor_inertia(P, sig, dsb, mu, &dw_last, o->dw_max, F);
+    if (trace) {
+      trace[it].mu = mu; trace[it].dw = F->dw; trace[it].dc = F->dc; trace[it].trials = F->trials;
+      memcpy(trace[it].inertia, F->inertia, sizeof(F->inertia));
+    }
+    if (fst != 0) { status = 2; break; }
+    double eta = 0.0;
+    or_newton_refine(P, F, sig, dsb, rx, rx + nd, ry, dx, dx + nd, dy, o->refine_steps, 1e-14, &eta);
+    /* dual directions from the linearised complementarity */
+    for (int i = 0; i < n; ++i) {
+      dzl[i] = 0.0; dzu[i] = 0.0;
+      if (isfinite(P->xl[i])) {
+        double sl = x[i] - P->xl[i];
+        dzl[i] = mu / sl - zl[i] - (zl[i] / sl) * dx[i];
+      }
+      if (isfinite(P->xu[i])) {
+        double su = P->xu[i] - x[i];
+        dzu[i] = mu / su - zu[i] + (zu[i] / su) * dx[i];
+      }
+    }
+    /* fraction to the boundary for slacks and bound multipliers */
+    double a_pr = 1.0, a_du = 1.0;
+    for (int i = 0; i < n; ++i) {
+      if (isfinite(P->xl[i])) {
+        double sl = x[i] - P->xl[i];
+        if (dx[i] < 0.0) a_pr = fmin(a_pr, -tau * sl / dx[i]);
+        if (dzl[i] < 0.0) a_du = fmin(a_du, -tau * zl[i] / dzl[i]);
+      }
+      if (isfinite(P->xu[i])) {
+        double su = P->xu[i] - x[i];
+        if (-dx[i] < 0.0) a_pr = fmin(a_pr, -tau * su / (-dx[i]));
+        if (dzu[i] < 0.0) a_du = fmin(a_du, -tau * zu[i] / dzu[i]);
+      }
+    }
+    /* backtracking filter line search */
+    double th = or_theta(P, x), ph = or_barrier(P, x, mu);
+    grad_f(P, x, gf);
+    double gphi = 0.0;
+    for (int i = 0; i < n; ++i) {
+      double gi = gf[i];
+      if (isfinite(P->xl[i])) gi = gi - mu / (x[i] - P->xl[i]);
+      if (isfinite(P->xu[i])) gi = gi + mu / (P->xu[i] - x[i]);
+      gphi = gphi + gi * dx[i];
+    }
+    double amin;
+    if (gphi < 0.0) {
+      amin = fmin(gamma_theta, gamma_phi * th / (-gphi));
+      if (th <= theta_min) amin = fmin(amin, delta * pow(th, s_theta) / pow(-gphi, s_phi));
+      amin = gamma_alpha * amin;
+    } else {
+      amin = gamma_alpha * gamma_theta;
+    }
+    double alpha = a_pr;
+    int accepted = 0, augment = 1, nbt = 0;
+    double tht = 0.0, pht = 0.0;
+    for (;;) {
+      for (int i = 0; i < n; ++i) xt[i] = x[i] + alpha * dx[i];
+      tht = or_theta(P, xt);
+      pht = or_barrier(P, xt, mu);
+      int ok = isfinite(tht) && isfinite(pht);
+      int infilt = !ok || tht >= theta_max;
+      for (int f = 0; f < nf && !infilt; ++f)
+        if (tht >= filt[f].th && pht >= filt[f].ph) infilt = 1;
+      if (!infilt) {
+        int sw = gphi < 0.0 && alpha * pow(-gphi, s_phi) > delta * pow(th, s_theta);
+        int armijo = pht <= ph + eta_phi * alpha * gphi;
+        if (th <= theta_min && sw) {
+          if (armijo) accepted = 1;
+        } else if (tht <= (1.0 - gamma_theta) * th || pht <= ph - gamma_phi * th) {
+          accepted = 1;
+        }
+        if (accepted) augment = !(sw && armijo);
+      }
+      if (accepted) break;
+      alpha = 0.5 * alpha;
+      nbt++;
+      if (alpha < amin) break;
+    }
+    if (trace) {
+      trace[it].theta = th; trace[it].phi = ph; trace[it].alpha_pr = alpha;
+      trace[it].alpha_du = a_du; trace[it].backtracks = nbt;
+    }
+    if (!accepted) { status = 5; break; }
+    if (augment) {
+      filt[nf].th = (1.0 - gamma_theta) * th;
+      filt[nf].ph = ph - gamma_phi * th;
+      nf++;
+    }
+    for (int i = 0; i < n; ++i) x[i] = xt[i];
+    for (int r = 0; r < m; ++r) y[r] = y[r] + alpha * dy[r];
+    for (int i = 0; i < n; ++i) {
+      if (isfinite(P->xl[i])) {
+        double z = zl[i] + a_du * dzl[i], sl = x[i] - P->xl[i];
+        zl[i] = fmax(fmin(z, kappa_sigma * mu / sl), mu / (kappa_sigma * sl));
+      }
+      if (isfinite(P->xu[i])) {
+        double z = zu[i] + a_du * dzu[i], su = P->xu[i] - x[i];
+        zu[i] = fmax(fmin(z, kappa_sigma * mu / su), mu / (kappa_sigma * su));
+      }
+    }
+  }
+  *iters = it;
+  or_factor_free(F);
+  free(filt); free(sig); free(rx); free(ry); free(dsb); free(dx); free(dy);
+  free(dzl); free(dzu); free(xt); free(gf);
+  return status;
+}

@@ -1,0 +1,157 @@
+/*
+ * Plain FP64 CPU oracle for the mixed dense-sparse (MDS) interior-point
+ * Newton step.  TEST INFRASTRUCTURE ONLY: the product library never links,
+ * loads or calls anything declared here; only the test suite, the smoke check
+ * and the CPU-baseline leg of the benchmark do.
+ *
+ * Everything is written as slow, obviously correct loops in double precision,
+ * compiled without floating-point contraction (-ffp-contract=off) so that each
+ * expression rounds exactly as written.  Each function names the passage of
+ * the paper (Peles et al., "Porting the Nonlinear Optimization Library HiOp to
+ * Accelerator-Based Hardware Architectures") or the textbook method it follows.
+ *
+ * Storage conventions: dense matrices are column-major (element (i,j) of an
+ * r-row matrix at [i + j*r]); the sparse Jacobian block J_s is CSR with
+ * strictly increasing column indices inside each row.
+ */
+#ifndef MDS_ORACLE_H
+#define MDS_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Quadratic MDS test problem (the objective/constraint class of Sec. 2, with
+ * constant Hessian blocks):  min 0.5 x_d'H x_d + c'x_d + sum(0.5 w x_s^2 + g x_s)
+ * s.t. J_d x_d + J_s x_s = b,  xl <= x <= xu  (x = [x_d; x_s], bounds may be
+ * +-INFINITY). */
+typedef struct {
+  int32_t n_d, n_s, m;
+  const double *H;      /* n_d x n_d, symmetric                     */
+  const double *c;      /* n_d                                       */
+  const double *w;      /* n_s, >= 0 (assumption A2)                 */
+  const double *g;      /* n_s                                       */
+  const double *Jd;     /* m x n_d                                   */
+  const int32_t *rp;    /* m+1 CSR row pointers of J_s               */
+  const int32_t *ci;    /* nnz column indices                        */
+  const double *v;      /* nnz values                                */
+  const double *b;      /* m                                         */
+  const double *xl;     /* n                                         */
+  const double *xu;     /* n                                         */
+} orq_problem;
+
+/* ---- condensation (Sec. 2.2, eq. (compressed), 2x2-block form) ---------- */
+/* M (N x N, N = n_d + m, full symmetric, column-major) and inv_d = 1/(dsbase+dw). */
+void or_condense(const orq_problem *P, const double *sigma_d, const double *dsbase,
+                 double dw, double dc, double *M, double *inv_d);
+/* rhat = r_y - J_s (inv_d .* r_s) */
+void or_rhs_condense(const orq_problem *P, const double *inv_d, const double *r_s,
+                     const double *r_y, double *rhat);
+/* dx_s = inv_d .* (r_s - J_s' dy) */
+void or_backsub(const orq_problem *P, const double *inv_d, const double *r_s,
+                const double *dy, double *dx_s);
+
+/* ---- Bunch-Kaufman LDL' (Sec. 2.3; Bunch & Kaufman 1977) --------------- */
+/* A: N x N column-major, lower triangle read.  On exit the strictly lower
+ * triangle holds unit-lower L with P'AP = L D L' (all interchanges applied to
+ * every column: "standard form"); dd/ds hold D's diagonal / sub-diagonal;
+ * ipiv is LAPACK's 1-based lower encoding.  Returns info (0, or 1-based index
+ * of the first exactly-zero 1x1 pivot).  If kind != NULL, kind[k] records the
+ * branch taken at pivot step k (0 zero column, 1 plain 1x1, 2 1x1 after the
+ * second test, 3 1x1 with swap, 4 2x2). */
+int or_bk(int32_t N, double *A, int32_t *ipiv, double *dd, double *ds, int32_t *kind);
+/* inertia (npos, nzero, nneg) from D */
+void or_inertia(int32_t N, const int32_t *ipiv, const double *dd, const double *ds,
+                int32_t out[3]);
+/* b <- (P L D L' P')^{-1} b.  Returns 0, or 1 if D has a zero 1x1 pivot. */
+int or_ldl_solve(int32_t N, const double *L, const int32_t *ipiv, const double *dd,
+                 const double *ds, double *b);
+
+/* ---- full (uncondensed) KKT operator (eq. (linsys4x4), 2x2-block form) --- */
+/* out = K * [dx_d; dx_s; dy] with
+ * K = [[H+diag(sigma_d)+dw I, 0, Jd'], [0, diag(dsbase)+dw I, Js'], [Jd, Js, -dc I]] */
+void or_kkt_matvec(const orq_problem *P, const double *sigma_d, const double *dsbase,
+                   double dw, double dc, const double *dx_d, const double *dx_s,
+                   const double *dy, double *o_d, double *o_s, double *o_y);
+double or_kkt_norm_inf(const orq_problem *P, const double *sigma_d, const double *dsbase,
+                       double dw, double dc);
+
+/* ---- a factored Newton system with its regularisation -------------------- */
+typedef struct {
+  int32_t N;
+  double dw, dc;
+  double *L;        /* N*N */
+  double *dd, *ds;  /* N each */
+  int32_t *ipiv;    /* N */
+  double *inv_d;    /* n_s */
+  int32_t inertia[3];
+  int32_t info;
+  int32_t trials;   /* factorizations done by the last correction loop */
+} or_factor;
+
+or_factor *or_factor_new(const orq_problem *P);
+void or_factor_free(or_factor *F);
+/* Condense + factor once with the given shifts. */
+void or_factor_once(const orq_problem *P, const double *sigma_d, const double *dsbase,
+                    double dw, double dc, or_factor *F);
+/* Inertia-correction loop (Sec. 2.1; Algorithm IC of Waechter & Biegler 2006).
+ * *dw_last is read and updated.  Returns 0 when In(M) = (n_d, 0, m), 2 when the
+ * shift exceeds dw_max. */
+int or_factor_inertia(const orq_problem *P, const double *sigma_d, const double *dsbase,
+                      double mu, double *dw_last, double dw_max, or_factor *F);
+/* Solve the factored Newton system for one right-hand side (condense the rhs,
+ * LDL' solve, back-substitute).  Returns 0 or 1 (zero pivot). */
+int or_newton_solve(const orq_problem *P, const or_factor *F, const double *r_d,
+                    const double *r_s, const double *r_y, double *dx_d, double *dx_s,
+                    double *dy);
+/* Solve + classic FP64 iterative refinement on the full KKT residual.
+ * eta_out: normwise backward error at exit; returns steps taken. */
+int or_newton_refine(const orq_problem *P, const or_factor *F, const double *sigma_d,
+                     const double *dsbase, const double *r_d, const double *r_s,
+                     const double *r_y, double *dx_d, double *dx_s, double *dy,
+                     int32_t max_steps, double eta_tol, double *eta_out);
+
+/* ---- IPM vector quantities (Sec. 2.1, kernels K1/K2) --------------------- */
+/* Sigma = zl/(x-l) + zu/(u-x); r = -(grad f + J'y - mu/(x-l) + mu/(u-x)); r_y = -(Jx-b).
+ * Infinite bounds contribute nothing.  sigma (n), r_x (n), r_y (m). */
+void or_sigma_rhs(const orq_problem *P, const double *x, const double *y, const double *zl,
+                  const double *zu, double mu, double *sigma, double *r_x, double *r_y);
+/* Largest alpha in (0,1] with v + alpha dv >= (1-tau) v for all entries with dv < 0. */
+double or_ftb(int64_t n, const double *v, const double *dv, double tau);
+/* Scaled optimality error E_mu (components returned in parts[4]: dual inf,
+ * primal inf, lower compl., upper compl.; scaling in parts[4..5]). */
+double or_opt_error(const orq_problem *P, const double *x, const double *y,
+                    const double *zl, const double *zu, double mu, double parts[6]);
+/* objective f, barrier function phi_mu, constraint violation theta = ||Jx-b||_1 */
+double or_objective(const orq_problem *P, const double *x);
+double or_barrier(const orq_problem *P, const double *x, double mu);
+double or_theta(const orq_problem *P, const double *x);
+
+/* ---- filter line-search IPM (Sec. 2.1; Waechter & Biegler 2006) ---------- */
+typedef struct {
+  double tol;          /* stop when E_0 <= tol              (1e-8) */
+  double mu0;          /* initial barrier parameter         (0.1)  */
+  int32_t max_iter;    /* (200) */
+  int32_t refine_steps;/* IR steps per Newton solve         (2)    */
+  double dw_max;       /* (1e20) */
+} or_ipm_opts;
+
+typedef struct {       /* one row per iteration */
+  double mu, E0, theta, phi, alpha_pr, alpha_du, dw, dc;
+  int32_t inertia[3];
+  int32_t trials, backtracks;
+} or_ipm_trace;
+
+/* x (n), y (m), zl, zu (n) are outputs (start point computed inside).
+ * Returns 4 converged, 5 line-search failure, 6 max iterations, 2 inertia
+ * failure, 7 non-finite values.  *iters: iterations done.  trace may be NULL
+ * or hold max_iter rows. */
+int or_ipm(const orq_problem *P, const or_ipm_opts *o, double *x, double *y, double *zl,
+           double *zu, int32_t *iters, or_ipm_trace *trace);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

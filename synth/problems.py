@@ -1,0 +1,133 @@
+"""Seeded synthetic mixed dense-sparse problems.
+
+This module holds the input recipe only: random draws and the assembly of the
+problem data (H, c, w, g, J_d, J_s, b, bounds).  It contains none of the
+interior-point arithmetic; both the CPU oracle and the GPU library are fed
+from it.
+
+Recipe (the paper's workloads, the HiOp mini app and Kron-reduced ACOPF
+grids, are not available; these draws stand in for them):
+
+* objective 0.5 x_d'H x_d + c'x_d + sum_i (0.5 w_i x_s,i^2 + g_i x_s,i);
+  H = Q Q'/n_d + S with Q, c ~ N(0,1); S = U diag(lam) U' with lam ~ U[-1,1]
+  and U Haar-orthogonal (QR of a Gaussian with the sign of diag(R) fixed);
+  w ~ U[0.1, 10]; g ~ N(0,1);
+* equality constraints J_d x_d + J_s x_s = b: J_s has r distinct columns per
+  row drawn uniformly without replacement (sorted), N(0,1) values; J_d is
+  N(0,1)/sqrt(n_d); b = J_s x0_s + J_d x0_d with x0 ~ U[-0.5, 0.5];
+* bounds [-1, 1] on every variable.
+
+Draw order inside one ``SeedSequence([cfg, p])`` stream:
+x0_d, x0_s, Q, lam, G (for U), c, w, g, J_s pattern, J_s values, J_d.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+# named workloads: (n_d, n_s, m, nnz per row of J_s)
+CONFIGS = {
+    0: dict(n_d=64, n_s=2000, m=128, r=4),        # whole FP64 IPM, N = 192
+    1: dict(n_d=1024, n_s=200000, m=3072, r=6),   # OPF-scale step, N = 4096
+    2: dict(n_d=4096, n_s=1000000, m=12288, r=8), # large condensed system, N = 16384
+}
+
+
+def _rng(cfg: int, p: int) -> np.random.Generator:
+    return np.random.default_rng(np.random.SeedSequence([int(cfg), int(p)]))
+
+
+def _haar(rng, n):
+    G = rng.standard_normal((n, n))
+    Qm, R = np.linalg.qr(G)
+    d = np.sign(np.diag(R))
+    d[d == 0] = 1.0
+    return Qm * d[None, :]
+
+
+def _pattern(rng, m, n_s, r):
+    """r distinct sorted column indices per row (rejection of repeated rows)."""
+    r = min(r, n_s)
+    if m == 0 or r == 0:
+        return np.zeros((m, 0), dtype=np.int64)
+    cols = rng.integers(0, n_s, size=(m, r))
+    cols.sort(axis=1)
+    for i in range(m):
+        row = cols[i]
+        while r > 1 and np.any(row[1:] == row[:-1]):
+            row = np.sort(rng.integers(0, n_s, size=r))
+        cols[i] = row
+    return cols
+
+
+def make_problem(n_d: int, n_s: int, m: int, r: int, cfg: int = 0, p: int = 0,
+                 h_scale: str = "n_d", s_scale: float = 1.0) -> dict:
+    """One seeded problem.  h_scale='n_d' divides Q Q' by n_d (and J_d by
+    sqrt(n_d)); '64' uses the literal constant 64 for both.  s_scale widens the
+    eigenvalue range of S to U[-s_scale, s_scale] (a more nonconvex variant
+    used to exercise the inertia correction)."""
+    rng = _rng(cfg, p)
+    x0_d = rng.uniform(-0.5, 0.5, n_d)
+    x0_s = rng.uniform(-0.5, 0.5, n_s)
+    Q = rng.standard_normal((n_d, n_d))
+    lam = rng.uniform(-1.0, 1.0, n_d) * s_scale
+    U = _haar(rng, n_d) if n_d > 0 else np.zeros((0, 0))
+    c = rng.standard_normal(n_d)
+    w = rng.uniform(0.1, 10.0, n_s)
+    g = rng.standard_normal(n_s)
+    cols = _pattern(rng, m, n_s, r)
+    rr = cols.shape[1]
+    vals = rng.standard_normal(m * rr)
+    scale = float(max(n_d, 1)) if h_scale == "n_d" else 64.0
+    Jd = rng.standard_normal((m, n_d)) / np.sqrt(scale)
+    S = (U * lam[None, :]) @ U.T if n_d > 0 else np.zeros((0, 0))
+    S = 0.5 * (S + S.T)
+    H = Q @ Q.T / scale + S
+    H = 0.5 * (H + H.T)
+    rp = (np.arange(m + 1) * rr).astype(np.int32)
+    ci = cols.reshape(-1).astype(np.int32)
+    # b = J_s x0_s + J_d x0_d, evaluated once here and stored
+    bs = np.zeros(m)
+    if m and rr:
+        bs = (vals.reshape(m, rr) * x0_s[cols]).sum(axis=1)
+    b = bs + (Jd @ x0_d if n_d else 0.0)
+    n = n_d + n_s
+    return dict(n_d=n_d, n_s=n_s, m=m, r=rr, H=np.asfortranarray(H), c=c, w=w, g=g,
+                Jd=np.asfortranarray(Jd), rp=rp, ci=ci, v=vals, b=np.asarray(b, dtype=np.float64),
+                xl=-np.ones(n), xu=np.ones(n), x0=np.concatenate([x0_d, x0_s]))
+
+
+def config_problem(cfg: int, p: int = 0, **kw) -> dict:
+    c = CONFIGS[cfg]
+    return make_problem(c["n_d"], c["n_s"], c["m"], c["r"], cfg=cfg, p=p, **kw)
+
+
+def batch_sizes(p: int, cfg: int = 3):
+    """Sizes of batched scenario problem p: N = 4*U{64..512}, n_d = N/4,
+    m = 3N/4, n_s = 50N, 4 nonzeros per row of J_s."""
+    rng = np.random.default_rng(np.random.SeedSequence([cfg, p, 1]))
+    N = 4 * int(rng.integers(64, 513))
+    return dict(n_d=N // 4, n_s=50 * N, m=3 * N // 4, r=4, N=N)
+
+
+def kkt_state(prob: dict, seed: int, log_range=(-8.0, 8.0)) -> dict:
+    """A Newton system at a synthetic late-barrier state: Sigma_d and
+    D_s = w + Sigma_s drawn log-uniform over 10^log_range, right-hand sides
+    N(0,1)."""
+    rng = np.random.default_rng(np.random.SeedSequence([99, seed]))
+    lo, hi = log_range
+    sigma_d = 10.0 ** rng.uniform(lo, hi, prob["n_d"])
+    dsbase = 10.0 ** rng.uniform(lo, hi, prob["n_s"])
+    return dict(sigma_d=sigma_d, dsbase=dsbase,
+                r_d=rng.standard_normal(prob["n_d"]),
+                r_s=rng.standard_normal(prob["n_s"]),
+                r_y=rng.standard_normal(prob["m"]))
+
+
+def interior_iterate(prob: dict, seed: int) -> dict:
+    """A random strictly interior primal-dual point (x in (-0.9, 0.9),
+    y ~ N(0,1), bound multipliers log-uniform in [1e-3, 10]) and mu."""
+    rng = np.random.default_rng(np.random.SeedSequence([77, seed]))
+    n = prob["n_d"] + prob["n_s"]
+    return dict(x=rng.uniform(-0.9, 0.9, n), y=rng.standard_normal(prob["m"]),
+                zl=10.0 ** rng.uniform(-3, 1, n), zu=10.0 ** rng.uniform(-3, 1, n),
+                mu=float(10.0 ** rng.uniform(-6, -1)))
