@@ -1,0 +1,272 @@
+/*
+ * mdsipm — MI355X (gfx950) library for the Newton-step hot path of the
+ * mixed dense-sparse (MDS) interior-point method of Peles et al., "Porting the
+ * Nonlinear Optimization Library HiOp to Accelerator-Based Hardware
+ * Architectures".
+ *
+ * Problem class (Sec. 2, eqs. (obj)-(bounds), equality constraints only):
+ *     min  0.5 x_d'H x_d + c'x_d + sum_i (0.5 w_i x_s,i^2 + g_i x_s,i)
+ *     s.t. J_d x_d + J_s x_s = b,   xl <= x <= xu,   x = [x_d; x_s].
+ * Assumption A1 (no cross Hessian) and A2 (diagonal, nonnegative Hessian of
+ * the sparse block: w >= 0) hold by construction of this class.
+ *
+ * Newton system (Sec. 2.1, eq. (linsys4x4) without the inequality block):
+ *     [[H + Sigma_d + dw I, 0,               J_d'],   [dx_d]   [r_d]
+ *      [0,                  D_s,             J_s'],   [dx_s] = [r_s]
+ *      [J_d,                J_s,            -dc I]]   [dy  ]   [r_y]
+ * with D_s = w + Sigma_s + dw (diagonal, positive).  Eliminating dx_s
+ * (Sec. 2.2, eq. (compressed)) leaves the dense symmetric indefinite
+ *     M = [[H + Sigma_d + dw I, J_d'], [J_d, -J_s D_s^{-1} J_s' - dc I]]
+ * of size N = n_d + m, factored by Bunch-Kaufman LDL' (Sec. 2.3); its inertia
+ * plus In(D_s) = (n_s,0,0) is the inertia of the full system (Haynsworth).
+ *
+ * Conventions
+ *  - All array pointers are DEVICE pointers (hipMalloc'd or framework-owned
+ *    device memory) unless the parameter name ends in _host.  The caller owns
+ *    every array, including the workspace; the library owns only the handle.
+ *  - Dense matrices are column-major.  J_s is CSR with strictly increasing
+ *    column indices in each row (validated).
+ *  - Calls are asynchronous on the handle's stream unless documented as
+ *    synchronizing (those that return host results synchronize that stream
+ *    only).  One handle per host thread.
+ *  - Return value: 0 = success; < 0 = usage or system error (outputs
+ *    untouched, message in mds_last_error); > 0 = numerical outcome (outputs
+ *    valid).  No C++ exception crosses this interface.
+ *  - Zero sizes are legal: n_s = 0 (no Schur term), m = 0 (M = H + Sigma_d +
+ *    dw I), n_d = 0 (M = -J_s D_s^{-1} J_s' - dc I).
+ */
+#ifndef MDSIPM_H
+#define MDSIPM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mds_handle mds_handle;
+
+enum {
+  MDS_OK = 0,
+  /* usage / system errors (< 0) */
+  MDS_EINVAL = -1,          /* bad argument value                          */
+  MDS_ENULL = -2,           /* required pointer is NULL                    */
+  MDS_EDIMS = -3,           /* negative or inconsistent dimensions         */
+  MDS_EWORKSPACE = -4,      /* workspace too small or misaligned           */
+  MDS_ESTATE = -5,          /* call order violated (e.g. solve before factor) */
+  MDS_EHIP = -6,            /* HIP runtime error                           */
+  MDS_ENONFINITE_INPUT = -7,/* NaN/Inf in problem data                     */
+  MDS_EDS_NONPOS = -8,      /* w < 0, xl >= xu, or D_s <= 0                */
+  MDS_EPATTERN = -9,        /* CSR pattern invalid (unsorted, out of range) */
+  /* numerical outcomes (> 0) */
+  MDS_ZERO_PIVOT = 1,       /* D has an exactly zero 1x1 pivot             */
+  MDS_INERTIA_FAIL = 2,     /* correction shift exceeded dw_max            */
+  MDS_REFINE_NOCONV = 3,    /* refinement stopped above its tolerance      */
+  MDS_IPM_CONVERGED = 4,
+  MDS_IPM_LS_FAIL = 5,      /* line search step below alpha_min            */
+  MDS_IPM_MAXITER = 6,
+  MDS_IPM_NONFINITE = 7
+};
+
+typedef struct {
+  int32_t n_d, n_s, m; /* N = n_d + m is the condensed size */
+  int64_t nnz_s;       /* nonzeros of J_s */
+} mds_dims;
+
+typedef struct {
+  int32_t nb;          /* panel width of the blocked factorization (0: default) */
+  int32_t reserved[7];
+} mds_options;
+
+/* Problem data, all device pointers, caller-owned, must stay valid and
+ * unmodified while the handle uses them (until the next mds_set_problem or
+ * mds_destroy). */
+typedef struct {
+  const double *H;        /* n_d x n_d, symmetric (both triangles read)     */
+  const double *c;        /* n_d                                             */
+  const double *w;        /* n_s, >= 0                                       */
+  const double *g;        /* n_s                                             */
+  const double *J_d;      /* m x n_d                                         */
+  const int32_t *Js_rowptr; /* m+1                                           */
+  const int32_t *Js_col;  /* nnz_s                                           */
+  const double *Js_val;   /* nnz_s                                           */
+  const double *b;        /* m                                               */
+  const double *xl, *xu;  /* n = n_d + n_s; +-INFINITY allowed, xl < xu      */
+} mds_problem;
+
+typedef struct {
+  int32_t npos, nzero, nneg; /* inertia of M                               */
+  int32_t n2x2;              /* number of 2x2 pivot blocks                  */
+  int32_t info;              /* 0, or 1-based index of the first zero pivot */
+} mds_inertia;
+
+/* Inertia-correction state (Sec. 2.1; Algorithm IC of Waechter & Biegler).
+ * delta_w_last is read and written; the other fields are outputs. */
+typedef struct {
+  double delta_w_last;
+  double delta_w, delta_c;  /* shifts of the accepted factorization          */
+  double delta_w_max;       /* cap; 0 selects 1e20                           */
+  int32_t trials;           /* factorizations performed                      */
+  int32_t pad;
+} mds_reg;
+
+typedef struct {
+  double eta;               /* normwise backward error on the full system    */
+  double rel_residual;      /* ||r - K d||_inf / ||r||_inf                   */
+  int32_t steps;            /* refinement corrections applied                */
+  int32_t pad;
+} mds_refine_info;
+
+/* IPM iterate.  x, y, zl, zu are device arrays (n, m, n, n); the scalars are
+ * host values that mds_ipm_init sets and mds_ipm_step updates. */
+typedef struct {
+  double *x, *y, *zl, *zu;
+  double mu, tau;
+  int32_t iter;
+  int32_t pad;
+} mds_iterate;
+
+typedef struct {
+  double tol;          /* stop when E_0 <= tol (1e-8)                        */
+  double mu0;          /* initial barrier parameter (0.1)                    */
+  int32_t max_iter;    /* (200)                                              */
+  int32_t refine_steps;/* refinement steps per Newton solve (2)              */
+  double dw_max;       /* correction cap (1e20)                              */
+} mds_ipm_opts;
+
+typedef struct {       /* one IPM iteration (host) */
+  double mu, E0, theta, phi, alpha_pr, alpha_du, delta_w, delta_c, eta;
+  int32_t inertia[3];
+  int32_t trials;      /* factorizations (inertia-correction trials)          */
+  int32_t solves;      /* LDL' solves (1 + refinement corrections)            */
+  int32_t backtracks, status;
+} mds_step_info;
+
+/* Per-kernel-class device time, accumulated while timing is enabled
+ * (hipEvents recorded around each launch on the handle's stream). */
+enum { MDS_T_CONDENSE = 0, MDS_T_PANEL = 1, MDS_T_TRAILING = 2, MDS_T_SOLVE = 3,
+       MDS_T_CLASSES = 4 };
+typedef struct {
+  double ms[MDS_T_CLASSES];     /* summed kernel time per class            */
+  int64_t launches[MDS_T_CLASSES];
+} mds_timings;
+
+/* ---- lifetime ----------------------------------------------------------- */
+
+/* Bytes of device workspace for these dimensions (256-byte aligned start
+ * required).  Dominated by the N x N matrix (8 N^2 bytes). */
+size_t mds_workspace_bytes(const mds_dims *dims, const mds_options *opts);
+
+/* Create a handle bound to the current HIP device, the given stream (a
+ * hipStream_t; NULL = default stream) and a caller-owned device workspace of
+ * at least mds_workspace_bytes() bytes.  opts may be NULL. */
+int mds_create(mds_handle **out, const mds_dims *dims, const mds_options *opts,
+               void *stream, void *workspace, size_t workspace_bytes);
+void mds_destroy(mds_handle *h);
+
+/* Attach problem data; validates it (finite values, w >= 0, xl < xu, sorted
+ * in-range CSR) and builds the column-compressed copy of J_s in the
+ * workspace.  Synchronizes the stream. */
+int mds_set_problem(mds_handle *h, const mds_problem *p);
+
+/* ---- Newton-step hot path ------------------------------------------------ */
+
+/* Assemble M (Sec. 2.2, eq. (compressed); kernel class K3) and
+ * D_s^{-1} = 1/(dsbase + delta_w) into the workspace.  sigma_d (n_d) and
+ * dsbase = w + Sigma_s (n_s, > 0) are device arrays that must remain valid
+ * until the next mds_condense (the correction loop re-condenses with them).
+ * The (2,2) block is accumulated over the shared columns of each row pair in
+ * ascending column order, so M is bitwise reproducible.  Async. */
+int mds_condense(mds_handle *h, const double *sigma_d, const double *dsbase,
+                 double delta_w, double delta_c);
+
+/* Bunch-Kaufman LDL' of the condensed M with its inertia (Sec. 2.3, kernel
+ * class K4).  reg == NULL: factor M as last condensed.  reg != NULL: run the
+ * inertia-correction loop (Sec. 2.1): factor with zero shifts, then re-condense
+ * and refactor with growing delta_w (and delta_c = 1e-8 mu^(1/4) if M is
+ * singular) until In(M) = (n_d, 0, m).  Synchronizes the stream.
+ * Returns 0, MDS_ZERO_PIVOT (reg == NULL and an exact zero pivot) or
+ * MDS_INERTIA_FAIL. */
+int mds_factor_inertia(mds_handle *h, mds_reg *reg, double mu, mds_inertia *out_host);
+
+/* Solve the factored Newton system for one right-hand side: condense the rhs
+ * (r_hat = r_y - J_s D_s^{-1} r_s), LDL' solve for [dx_d; dy], back-substitute
+ * dx_s = D_s^{-1} (r_s - J_s' dy).  Inputs and outputs are device arrays and
+ * must not alias.  Async. */
+int mds_solve(mds_handle *h, const double *r_d, const double *r_s, const double *r_y,
+              double *dx_d, double *dx_s, double *dy);
+
+/* mds_solve followed by FP64 iterative refinement on the residual of the full
+ * (uncondensed) system, evaluated matrix-free.  Stops when the normwise
+ * backward error eta <= eta_tol, when it stops decreasing (the best iterate
+ * is kept) or after max_steps corrections.  Synchronizes the stream. */
+int mds_refine(mds_handle *h, const double *r_d, const double *r_s, const double *r_y,
+               double *dx_d, double *dx_s, double *dy, int32_t max_steps, double eta_tol,
+               mds_refine_info *info_host);
+
+/* ---- IPM vector kernels (Sec. 2.1, kernel classes K1/K2) ------------------ */
+
+/* sigma = zl/(x-xl) + zu/(xu-x); r_x = -(grad f + J'y - mu/(x-xl) + mu/(xu-x));
+ * r_y = -(J x - b).  Infinite bounds contribute nothing.  Async. */
+int mds_sigma_rhs(mds_handle *h, const double *x, const double *y, const double *zl,
+                  const double *zu, double mu, double *sigma, double *r_x, double *r_y);
+
+/* Fraction to the boundary: largest alpha in (0,1] with
+ * v + alpha dv >= (1 - tau) v wherever dv < 0.  Synchronizes. */
+int mds_ftb(mds_handle *h, int64_t n, const double *v, const double *dv, double tau,
+            double *alpha_host);
+
+/* Scaled optimality error E_mu; parts_host (may be NULL) receives
+ * {dual inf, primal inf, lower compl, upper compl, s_d, s_c}.  Synchronizes. */
+int mds_opt_error(mds_handle *h, const double *x, const double *y, const double *zl,
+                  const double *zu, double mu, double *E_host, double *parts_host);
+
+/* Objective f, barrier function phi_mu and theta = ||J x - b||_1.  Synchronizes. */
+int mds_merit(mds_handle *h, const double *x, double mu, double *f_host, double *phi_host,
+              double *theta_host);
+
+/* ---- filter line-search IPM (Sec. 2.1) ------------------------------------ */
+
+/* Set the start point (x = 0 pushed inside its bounds, y = 0, z = 1 on finite
+ * bounds) and reset the filter and correction state.  opts may be NULL. */
+int mds_ipm_init(mds_handle *h, mds_iterate *it, const mds_ipm_opts *opts);
+
+/* One IPM iteration: convergence test, barrier update, Newton step with
+ * inertia correction and refinement, fraction to the boundary, filter
+ * backtracking line search, update with the bound-multiplier safeguard.
+ * Returns 0 (step taken), MDS_IPM_CONVERGED (no step taken), or a failure
+ * code.  Synchronizes. */
+int mds_ipm_step(mds_handle *h, mds_iterate *it, mds_step_info *info_host);
+
+/* mds_ipm_init followed by mds_ipm_step until it returns nonzero.  trace_host
+ * (may be NULL) receives one row per call of mds_ipm_step, at most trace_cap
+ * rows; *iters_host the number of steps taken.  Returns the final status
+ * (MDS_IPM_CONVERGED on success).  Synchronizes. */
+int mds_ipm_solve(mds_handle *h, mds_iterate *it, const mds_ipm_opts *opts,
+                  mds_step_info *trace_host, int32_t trace_cap, int32_t *iters_host);
+
+/* ---- diagnostics ----------------------------------------------------------- */
+
+/* Copy the assembled M (before factorization) to host (N*N doubles). */
+int mds_get_matrix(mds_handle *h, double *M_host);
+/* Copy the factor to host in standard form: P'MP = L D L' with L unit lower
+ * (N*N column-major, strictly lower part), D diagonal/sub-diagonal (N each)
+ * and LAPACK-style 1-based ipiv (lower).  Any pointer may be NULL. */
+int mds_get_factor(mds_handle *h, double *L_host, double *dd_host, double *ds_host,
+                   int32_t *ipiv_host);
+/* Copy D^{-1}_s (n_s) to host. */
+int mds_get_inv_ds(mds_handle *h, double *inv_d_host);
+
+/* Enable (1) or disable (0) per-launch timing; enabling clears the totals. */
+int mds_set_timing(mds_handle *h, int enable);
+/* Synchronize the stream and return the accumulated totals. */
+int mds_get_timings(mds_handle *h, mds_timings *out_host);
+
+const char *mds_status_string(int status);
+const char *mds_last_error(const mds_handle *h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

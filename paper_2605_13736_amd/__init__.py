@@ -1,0 +1,389 @@
+"""Python binding of libmdsipm (the gfx950 HIP library declared in include/mdsipm.h).
+
+Argument marshalling only: every numerical step runs in the library's HIP
+kernels.  PyTorch provides device memory and the stream.  Importing this
+package does not need a GPU; creating a :class:`Solver` does, and it raises
+if the built library or a ROCm device is missing (there is no CPU fallback).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmdsipm.so")
+
+# status codes (include/mdsipm.h)
+MDS_OK = 0
+MDS_ZERO_PIVOT = 1
+MDS_INERTIA_FAIL = 2
+MDS_REFINE_NOCONV = 3
+MDS_IPM_CONVERGED = 4
+MDS_IPM_LS_FAIL = 5
+MDS_IPM_MAXITER = 6
+MDS_IPM_NONFINITE = 7
+STATUS_NAMES = {4: "converged", 5: "ls_fail", 6: "maxiter", 2: "inertia_fail", 7: "nonfinite"}
+
+_vp = C.c_void_p
+_dp = C.POINTER(C.c_double)
+_ip = C.POINTER(C.c_int32)
+
+
+class Dims(C.Structure):
+    _fields_ = [("n_d", C.c_int32), ("n_s", C.c_int32), ("m", C.c_int32), ("nnz_s", C.c_int64)]
+
+
+class Options(C.Structure):
+    _fields_ = [("nb", C.c_int32), ("reserved", C.c_int32 * 7)]
+
+
+class Problem(C.Structure):
+    _fields_ = [("H", _vp), ("c", _vp), ("w", _vp), ("g", _vp), ("J_d", _vp),
+                ("Js_rowptr", _vp), ("Js_col", _vp), ("Js_val", _vp), ("b", _vp),
+                ("xl", _vp), ("xu", _vp)]
+
+
+class Inertia(C.Structure):
+    _fields_ = [("npos", C.c_int32), ("nzero", C.c_int32), ("nneg", C.c_int32),
+                ("n2x2", C.c_int32), ("info", C.c_int32)]
+
+
+class Reg(C.Structure):
+    _fields_ = [("delta_w_last", C.c_double), ("delta_w", C.c_double), ("delta_c", C.c_double),
+                ("delta_w_max", C.c_double), ("trials", C.c_int32), ("pad", C.c_int32)]
+
+
+class RefineInfo(C.Structure):
+    _fields_ = [("eta", C.c_double), ("rel_residual", C.c_double), ("steps", C.c_int32),
+                ("pad", C.c_int32)]
+
+
+class Iterate(C.Structure):
+    _fields_ = [("x", _vp), ("y", _vp), ("zl", _vp), ("zu", _vp), ("mu", C.c_double),
+                ("tau", C.c_double), ("iter", C.c_int32), ("pad", C.c_int32)]
+
+
+class IpmOpts(C.Structure):
+    _fields_ = [("tol", C.c_double), ("mu0", C.c_double), ("max_iter", C.c_int32),
+                ("refine_steps", C.c_int32), ("dw_max", C.c_double)]
+
+
+class StepInfo(C.Structure):
+    _fields_ = [("mu", C.c_double), ("E0", C.c_double), ("theta", C.c_double),
+                ("phi", C.c_double), ("alpha_pr", C.c_double), ("alpha_du", C.c_double),
+                ("delta_w", C.c_double), ("delta_c", C.c_double), ("eta", C.c_double),
+                ("inertia", C.c_int32 * 3), ("trials", C.c_int32), ("solves", C.c_int32),
+                ("backtracks", C.c_int32), ("status", C.c_int32)]
+
+
+T_CLASSES = ("condense", "panel", "trailing", "solve")
+
+
+class Timings(C.Structure):
+    _fields_ = [("ms", C.c_double * 4), ("launches", C.c_int64 * 4)]
+
+
+# exported functions: name -> (restype, argtypes)
+SIGNATURES = {
+    "mds_workspace_bytes": (C.c_size_t, [C.POINTER(Dims), C.POINTER(Options)]),
+    "mds_create": (C.c_int, [C.POINTER(_vp), C.POINTER(Dims), C.POINTER(Options), _vp, _vp,
+                             C.c_size_t]),
+    "mds_destroy": (None, [_vp]),
+    "mds_set_problem": (C.c_int, [_vp, C.POINTER(Problem)]),
+    "mds_condense": (C.c_int, [_vp, _vp, _vp, C.c_double, C.c_double]),
+    "mds_factor_inertia": (C.c_int, [_vp, C.POINTER(Reg), C.c_double, C.POINTER(Inertia)]),
+    "mds_solve": (C.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "mds_refine": (C.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, C.c_int32, C.c_double,
+                             C.POINTER(RefineInfo)]),
+    "mds_sigma_rhs": (C.c_int, [_vp, _vp, _vp, _vp, _vp, C.c_double, _vp, _vp, _vp]),
+    "mds_ftb": (C.c_int, [_vp, C.c_int64, _vp, _vp, C.c_double, _dp]),
+    "mds_opt_error": (C.c_int, [_vp, _vp, _vp, _vp, _vp, C.c_double, _dp, _dp]),
+    "mds_merit": (C.c_int, [_vp, _vp, C.c_double, _dp, _dp, _dp]),
+    "mds_ipm_init": (C.c_int, [_vp, C.POINTER(Iterate), C.POINTER(IpmOpts)]),
+    "mds_ipm_step": (C.c_int, [_vp, C.POINTER(Iterate), C.POINTER(StepInfo)]),
+    "mds_ipm_solve": (C.c_int, [_vp, C.POINTER(Iterate), C.POINTER(IpmOpts),
+                                C.POINTER(StepInfo), C.c_int32, _ip]),
+    "mds_get_matrix": (C.c_int, [_vp, _dp]),
+    "mds_get_factor": (C.c_int, [_vp, _dp, _dp, _dp, _ip]),
+    "mds_get_inv_ds": (C.c_int, [_vp, _dp]),
+    "mds_set_timing": (C.c_int, [_vp, C.c_int]),
+    "mds_get_timings": (C.c_int, [_vp, C.POINTER(Timings)]),
+    "mds_status_string": (C.c_char_p, [C.c_int]),
+    "mds_last_error": (C.c_char_p, [_vp]),
+}
+
+_lib = None
+
+
+def lib():
+    """Load libmdsipm.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python paper_2605_13736_amd/build.py`")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+class MdsError(RuntimeError):
+    pass
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None and t.numel() > 0 else C.c_void_p(
+        t.data_ptr() if t is not None else 0)
+
+
+class Solver:
+    """One library handle bound to a device, a stream and a workspace tensor."""
+
+    def __init__(self, n_d: int, n_s: int, m: int, nnz_s: int, nb: int = 0,
+                 device: str = "cuda:0", stream=None):
+        torch = _torch()
+        if not torch.cuda.is_available():
+            raise MdsError("no ROCm GPU visible: the mdsipm library has no CPU path")
+        self.torch = torch
+        self.device = torch.device(device)
+        self.dims = Dims(n_d, n_s, m, nnz_s)
+        self.opts = Options(nb)
+        self.n_d, self.n_s, self.m = n_d, n_s, m
+        self.N, self.n = n_d + m, n_d + n_s
+        L = lib()
+        nbytes = L.mds_workspace_bytes(C.byref(self.dims), C.byref(self.opts))
+        if nbytes == 0:
+            raise MdsError("invalid dimensions")
+        with torch.cuda.device(self.device):
+            self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+            self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+            base = self.ws.data_ptr()
+            aligned = (base + 255) & ~255
+            h = C.c_void_p()
+            st = L.mds_create(C.byref(h), C.byref(self.dims), C.byref(self.opts),
+                              C.c_void_p(self.stream.cuda_stream), C.c_void_p(aligned), nbytes)
+        if st != 0:
+            raise MdsError(f"mds_create: {L.mds_status_string(st).decode()}")
+        self.h = h
+        self._keep = {}
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().mds_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- helpers --------------------------------------------------------
+    def _check(self, st, what, ok=(0,)):
+        if st < 0:
+            msg = lib().mds_last_error(self.h).decode()
+            raise MdsError(f"{what}: {lib().mds_status_string(st).decode()} ({msg})")
+        return st
+
+    def dev(self, a, dtype=None):
+        torch = self.torch
+        if isinstance(a, torch.Tensor):
+            return a.to(self.device).contiguous()
+        arr = np.asarray(a)
+        if dtype is None:
+            dtype = torch.int32 if arr.dtype.kind in "iu" else torch.float64
+        return torch.as_tensor(np.ascontiguousarray(arr)).to(device=self.device,
+                                                            dtype=dtype).contiguous()
+
+    def empty(self, n):
+        return self.torch.empty(max(int(n), 0), dtype=self.torch.float64, device=self.device)
+
+    # ---- problem --------------------------------------------------------
+    def set_problem(self, prob: dict):
+        torch = self.torch
+        nd, m = self.n_d, self.m
+        T = dict(
+            H=self.dev(np.asarray(prob["H"], dtype=np.float64).reshape(-1, order="F")),
+            c=self.dev(np.asarray(prob["c"], dtype=np.float64)),
+            w=self.dev(np.asarray(prob["w"], dtype=np.float64)),
+            g=self.dev(np.asarray(prob["g"], dtype=np.float64)),
+            J_d=self.dev(np.asarray(prob["Jd"], dtype=np.float64).reshape(-1, order="F")),
+            Js_rowptr=self.dev(np.asarray(prob["rp"], dtype=np.int32), torch.int32),
+            Js_col=self.dev(np.asarray(prob["ci"], dtype=np.int32), torch.int32),
+            Js_val=self.dev(np.asarray(prob["v"], dtype=np.float64)),
+            b=self.dev(np.asarray(prob["b"], dtype=np.float64)),
+            xl=self.dev(np.asarray(prob["xl"], dtype=np.float64)),
+            xu=self.dev(np.asarray(prob["xu"], dtype=np.float64)),
+        )
+        assert T["H"].numel() == nd * nd and T["J_d"].numel() == m * nd
+        self.P = T
+        self.cp = Problem(*[_ptr(T[k]) for k, _ in Problem._fields_])
+        st = lib().mds_set_problem(self.h, C.byref(self.cp))
+        self._check(st, "mds_set_problem")
+        return st
+
+    # ---- Newton-step hot path -------------------------------------------
+    def condense(self, sigma_d, dsbase, delta_w=0.0, delta_c=0.0):
+        sd, db = self.dev(sigma_d), self.dev(dsbase)
+        self._keep["sigma_d"], self._keep["dsbase"] = sd, db
+        st = lib().mds_condense(self.h, _ptr(sd), _ptr(db), float(delta_w), float(delta_c))
+        return self._check(st, "mds_condense")
+
+    def factor_inertia(self, mu=0.0, reg=None):
+        """reg None: factor as condensed.  reg dict (delta_w_last, delta_w_max):
+        run the inertia-correction loop.  Returns (status, inertia, reg)."""
+        inn = Inertia()
+        if reg is None:
+            st = lib().mds_factor_inertia(self.h, None, float(mu), C.byref(inn))
+            self._check(st, "mds_factor_inertia")
+            return st, _inertia_dict(inn), None
+        r = Reg(reg.get("delta_w_last", 0.0), 0.0, 0.0, reg.get("delta_w_max", 0.0), 0, 0)
+        st = lib().mds_factor_inertia(self.h, C.byref(r), float(mu), C.byref(inn))
+        self._check(st, "mds_factor_inertia")
+        return st, _inertia_dict(inn), dict(delta_w_last=r.delta_w_last, delta_w=r.delta_w,
+                                            delta_c=r.delta_c, trials=r.trials)
+
+    def solve(self, r_d, r_s, r_y):
+        a = [self.dev(v) for v in (r_d, r_s, r_y)]
+        o = [self.empty(self.n_d), self.empty(self.n_s), self.empty(self.m)]
+        st = lib().mds_solve(self.h, *[_ptr(t) for t in a], *[_ptr(t) for t in o])
+        self._check(st, "mds_solve")
+        return o
+
+    def refine(self, r_d, r_s, r_y, max_steps=5, eta_tol=1e-14):
+        a = [self.dev(v) for v in (r_d, r_s, r_y)]
+        o = [self.empty(self.n_d), self.empty(self.n_s), self.empty(self.m)]
+        info = RefineInfo()
+        st = lib().mds_refine(self.h, *[_ptr(t) for t in a], *[_ptr(t) for t in o],
+                              int(max_steps), float(eta_tol), C.byref(info))
+        self._check(st, "mds_refine")
+        return o, dict(status=st, eta=info.eta, rel_residual=info.rel_residual,
+                       steps=info.steps)
+
+    # ---- vector kernels -------------------------------------------------
+    def sigma_rhs(self, x, y, zl, zu, mu):
+        a = [self.dev(v) for v in (x, y, zl, zu)]
+        sig, rx, ry = self.empty(self.n), self.empty(self.n), self.empty(self.m)
+        st = lib().mds_sigma_rhs(self.h, *[_ptr(t) for t in a], float(mu), _ptr(sig), _ptr(rx),
+                                 _ptr(ry))
+        self._check(st, "mds_sigma_rhs")
+        return sig, rx, ry
+
+    def ftb(self, v, dv, tau):
+        v, dv = self.dev(v), self.dev(dv)
+        out = C.c_double()
+        st = lib().mds_ftb(self.h, v.numel(), _ptr(v), _ptr(dv), float(tau), C.byref(out))
+        self._check(st, "mds_ftb")
+        return out.value
+
+    def opt_error(self, x, y, zl, zu, mu):
+        a = [self.dev(v) for v in (x, y, zl, zu)]
+        E = C.c_double()
+        parts = (C.c_double * 6)()
+        st = lib().mds_opt_error(self.h, *[_ptr(t) for t in a], float(mu), C.byref(E), parts)
+        self._check(st, "mds_opt_error")
+        return E.value, list(parts)
+
+    def merit(self, x, mu):
+        x = self.dev(x)
+        f, phi, th = C.c_double(), C.c_double(), C.c_double()
+        st = lib().mds_merit(self.h, _ptr(x), float(mu), C.byref(f), C.byref(phi), C.byref(th))
+        self._check(st, "mds_merit")
+        return f.value, phi.value, th.value
+
+    # ---- IPM ------------------------------------------------------------
+    def new_iterate(self):
+        it = dict(x=self.empty(self.n), y=self.empty(self.m), zl=self.empty(self.n),
+                  zu=self.empty(self.n))
+        it["c"] = Iterate(_ptr(it["x"]), _ptr(it["y"]), _ptr(it["zl"]), _ptr(it["zu"]),
+                          0.0, 0.0, 0, 0)
+        return it
+
+    def ipm_init(self, it, tol=1e-8, mu0=0.1, max_iter=200, refine_steps=2, dw_max=1e20):
+        self._opts = IpmOpts(tol, mu0, max_iter, refine_steps, dw_max)
+        st = lib().mds_ipm_init(self.h, C.byref(it["c"]), C.byref(self._opts))
+        return self._check(st, "mds_ipm_init")
+
+    def ipm_step(self, it):
+        info = StepInfo()
+        st = lib().mds_ipm_step(self.h, C.byref(it["c"]), C.byref(info))
+        self._check(st, "mds_ipm_step")
+        return st, _step_dict(info)
+
+    def ipm_solve(self, it=None, tol=1e-8, mu0=0.1, max_iter=200, refine_steps=2, dw_max=1e20):
+        it = it if it is not None else self.new_iterate()
+        opts = IpmOpts(tol, mu0, max_iter, refine_steps, dw_max)
+        cap = max_iter + 2
+        tr = (StepInfo * cap)()
+        iters = C.c_int32()
+        st = lib().mds_ipm_solve(self.h, C.byref(it["c"]), C.byref(opts), tr, cap,
+                                 C.byref(iters))
+        self._check(st, "mds_ipm_solve")
+        n = min(iters.value + 1, cap)
+        return dict(status=STATUS_NAMES.get(st, st), code=st, iters=iters.value,
+                    trace=[_step_dict(tr[k]) for k in range(n)], x=it["x"], y=it["y"],
+                    zl=it["zl"], zu=it["zu"], mu=it["c"].mu)
+
+    # ---- timing ---------------------------------------------------------
+    def set_timing(self, enable: bool):
+        self._check(lib().mds_set_timing(self.h, int(bool(enable))), "mds_set_timing")
+
+    def get_timings(self):
+        t = Timings()
+        self._check(lib().mds_get_timings(self.h, C.byref(t)), "mds_get_timings")
+        return {name: dict(ms=t.ms[i], launches=int(t.launches[i]))
+                for i, name in enumerate(T_CLASSES)}
+
+    # ---- diagnostics ----------------------------------------------------
+    def get_matrix(self):
+        N = self.N
+        out = np.empty(max(N * N, 1))
+        st = lib().mds_get_matrix(self.h, out.ctypes.data_as(_dp))
+        self._check(st, "mds_get_matrix")
+        return out[:N * N].reshape((N, N), order="F")
+
+    def get_factor(self):
+        N = self.N
+        L = np.empty(max(N * N, 1))
+        dd, ds = np.empty(max(N, 1)), np.empty(max(N, 1))
+        ipiv = np.empty(max(N, 1), dtype=np.int32)
+        st = lib().mds_get_factor(self.h, L.ctypes.data_as(_dp), dd.ctypes.data_as(_dp),
+                                  ds.ctypes.data_as(_dp), ipiv.ctypes.data_as(_ip))
+        self._check(st, "mds_get_factor")
+        Lm = L[:N * N].reshape((N, N), order="F") + np.eye(N)
+        return Lm, dd[:N], ds[:N], ipiv[:N]
+
+    def get_inv_ds(self):
+        out = np.empty(max(self.n_s, 1))
+        st = lib().mds_get_inv_ds(self.h, out.ctypes.data_as(_dp))
+        self._check(st, "mds_get_inv_ds")
+        return out[:self.n_s]
+
+
+def _inertia_dict(i):
+    return dict(npos=i.npos, nzero=i.nzero, nneg=i.nneg, n2x2=i.n2x2, info=i.info)
+
+
+def _step_dict(s):
+    return dict(mu=s.mu, E0=s.E0, theta=s.theta, phi=s.phi, alpha_pr=s.alpha_pr,
+                alpha_du=s.alpha_du, dw=s.delta_w, dc=s.delta_c, eta=s.eta,
+                inertia=tuple(s.inertia), trials=s.trials, solves=s.solves,
+                backtracks=s.backtracks, status=s.status)
+
+
+def solver_for(prob: dict, nb: int = 0, device: str = "cuda:0") -> Solver:
+    """Create a Solver sized for a problem dict and attach the problem."""
+    s = Solver(prob["n_d"], prob["n_s"], prob["m"], len(prob["v"]), nb=nb, device=device)
+    s.set_problem(prob)
+    return s

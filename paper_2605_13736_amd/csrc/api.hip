@@ -1,0 +1,920 @@
+// C-ABI of the mdsipm library: handle and workspace management, validation,
+// the inertia-correction loop, refinement and the host control of the filter
+// line-search IPM.  Every numerical step on vectors and matrices runs in the
+// HIP kernels; the host only sequences launches and takes scalar decisions.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstring>
+#include <new>
+
+#include "internal.hpp"
+#include "ipm.hpp"
+
+using namespace mds;
+
+namespace {
+
+int set_err(mds_handle *h, int code, const char *fmt, ...) {
+  if (h) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(h->err, sizeof(h->err), fmt, ap);
+    va_end(ap);
+  }
+  return code;
+}
+
+#define HIPCHK(expr)                                                                       \
+  do {                                                                                     \
+    hipError_t e_ = (expr);                                                                \
+    if (e_ != hipSuccess) return set_err(h, MDS_EHIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+#define TRY(expr)             \
+  do {                        \
+    int r_ = (expr);          \
+    if (r_ < 0) return r_;    \
+  } while (0)
+
+// ---- per-launch timing ---------------------------------------------------
+int ev_take(mds_handle *h) {
+  const size_t used = 2 * h->ev_marks.size();
+  while (h->ev_pool.size() < used + 2) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return -1;
+    h->ev_pool.push_back(e);
+  }
+  return (int)used;
+}
+
+struct TimedLaunch {
+  mds_handle *h;
+  int cls, idx;
+  TimedLaunch(mds_handle *h_, int c) : h(h_), cls(c), idx(-1) {
+    if (!h->timing) return;
+    idx = ev_take(h);
+    if (idx >= 0) (void)hipEventRecord(h->ev_pool[idx], h->stream);
+  }
+  ~TimedLaunch() {
+    if (idx < 0) return;
+    (void)hipEventRecord(h->ev_pool[idx + 1], h->stream);
+    h->ev_marks.push_back({cls, {idx, idx + 1}});
+  }
+};
+
+int resolve_timings(mds_handle *h) {
+  if (h->ev_marks.empty()) return MDS_OK;
+  if (hipStreamSynchronize(h->stream) != hipSuccess) return MDS_EHIP;
+  for (auto &mk : h->ev_marks) {
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, h->ev_pool[mk.second.first], h->ev_pool[mk.second.second]) ==
+        hipSuccess) {
+      h->t_ms[mk.first] += ms;
+      h->t_n[mk.first] += 1;
+    }
+  }
+  h->ev_marks.clear();
+  return MDS_OK;
+}
+
+// Workspace slots, in carving order.
+enum Slot {
+  S_M, S_W, S_DD, S_DS, S_IPIV, S_BLK, S_PK0, S_FST, S_INVD, S_CPTR, S_CROW, S_CVAL, S_CFILL,
+  S_FLAGS, S_RED, S_SCAL, S_Z, S_SIG, S_RX, S_RY, S_DSB, S_DX, S_DY, S_DZL, S_DZU, S_XT, S_RES,
+  S_COR, S_PREV, S_KX, S_TN, S_TM, S_TN2, S_KNH, S_KNJD, S_KNY, S_KNJS, S_COUNT
+};
+
+struct Layout {
+  size_t off[S_COUNT];
+  size_t total;
+};
+
+int default_nb(int N) { return (N >= 64) ? 16 : 8; }
+
+Layout make_layout(const mds_dims &d, int nb) {
+  const size_t nd = d.n_d, ns = d.n_s, m = d.m, N = nd + m, n = nd + ns;
+  const size_t nnz = (size_t)d.nnz_s;
+  const size_t maxp = N / (size_t)nb + 2;
+  size_t bytes[S_COUNT] = {};
+  bytes[S_M] = 8 * N * N;
+  bytes[S_W] = 8 * N * (size_t)(nb + 2);
+  bytes[S_DD] = bytes[S_DS] = 8 * N;
+  bytes[S_IPIV] = bytes[S_BLK] = 4 * N;
+  bytes[S_PK0] = 4 * (maxp + 2);
+  bytes[S_FST] = sizeof(FacState);
+  bytes[S_INVD] = 8 * ns;
+  bytes[S_CPTR] = 4 * (ns + 1);
+  bytes[S_CROW] = 4 * nnz;
+  bytes[S_CVAL] = 8 * nnz;
+  bytes[S_CFILL] = 4 * ns;
+  bytes[S_FLAGS] = 4 * 16;
+  bytes[S_RED] = 8 * (size_t)kRedBlocks * 8;
+  bytes[S_SCAL] = 8 * 64;
+  bytes[S_Z] = 8 * N;
+  bytes[S_SIG] = bytes[S_RX] = 8 * n;
+  bytes[S_RY] = 8 * m;
+  bytes[S_DSB] = 8 * ns;
+  bytes[S_DX] = bytes[S_DZL] = bytes[S_DZU] = bytes[S_XT] = 8 * n;
+  bytes[S_DY] = 8 * m;
+  bytes[S_RES] = bytes[S_COR] = bytes[S_PREV] = bytes[S_KX] = 8 * (n + m);
+  bytes[S_TN] = bytes[S_TN2] = 8 * n;
+  bytes[S_TM] = 8 * m;
+  bytes[S_KNH] = bytes[S_KNJD] = 8 * nd;
+  bytes[S_KNY] = 8 * m;
+  bytes[S_KNJS] = 8 * ns;
+  Layout L{};
+  size_t o = 0;
+  for (int s = 0; s < S_COUNT; ++s) {
+    L.off[s] = o;
+    o += (bytes[s] + 255) & ~(size_t)255;
+    if (bytes[s] == 0) o += 256;  // distinct valid addresses for empty arrays
+  }
+  L.total = o;
+  return L;
+}
+
+bool dims_ok(const mds_dims *d) {
+  return d && d->n_d >= 0 && d->n_s >= 0 && d->m >= 0 && d->nnz_s >= 0 &&
+         (int64_t)d->n_d + d->m <= 65536 && (int64_t)d->n_d + d->n_s < ((int64_t)1 << 30) &&
+         d->nnz_s < ((int64_t)1 << 30);
+}
+
+int nb_of(const mds_dims &d, const mds_options *o) {
+  int nb = (o && o->nb > 0) ? o->nb : default_nb(d.n_d + d.m);
+  return std::min(std::max(nb, 2), kMaxNb);
+}
+
+inline hipStream_t S(mds_handle *h) { return h->stream; }
+inline int ND(mds_handle *h) { return h->dims.n_d; }
+inline int NS(mds_handle *h) { return h->dims.n_s; }
+inline int MM(mds_handle *h) { return h->dims.m; }
+
+// ---- internal building blocks -------------------------------------------------
+
+int condense_impl(mds_handle *h, double dw, double dc) {
+  {
+    TimedLaunch t(h, MDS_T_CONDENSE);
+    launch_inv_d(S(h), NS(h), h->dsbase, dw, h->w.inv_d);
+    launch_condense_dense(S(h), ND(h), MM(h), h->P.H, h->P.J_d, h->sigma_d, dw, h->w.M);
+    launch_condense_schur(S(h), ND(h), MM(h), h->N, h->P.Js_rowptr, h->P.Js_col, h->P.Js_val,
+                          h->w.csc_ptr, h->w.csc_row, h->w.csc_val, h->w.inv_d, dc, h->w.M);
+  }
+  HIPCHK(hipGetLastError());
+  h->dw = dw;
+  h->dc = dc;
+  h->have_M = true;
+  h->have_factor = false;
+  return MDS_OK;
+}
+
+// Blocked Bunch-Kaufman of the current M; reads back the inertia.
+int factor_impl(mds_handle *h, mds_inertia *out) {
+  const int N = h->N;
+  launch_fac_reset(S(h), h->w.fst, h->w.panel_k0);
+  const int slots = (N + h->nb - 1) / h->nb;
+  for (int b = 0; b < slots; ++b) {
+    {
+      TimedLaunch t(h, MDS_T_PANEL);
+      launch_bk_panel(S(h), N, h->nb, h->alpha_bk, h->w.M, h->w.W, h->w.dd, h->w.ds, h->w.ipiv,
+                      h->w.blk, h->w.fst, h->w.panel_k0);
+    }
+    if ((long)N - (long)(b + 1) * h->nb > 0) {
+      TimedLaunch t(h, MDS_T_TRAILING);
+      launch_bk_trailing(S(h), N, h->nb, b, h->w.W, h->w.M, h->w.fst, h->w.panel_k0);
+    }
+  }
+  HIPCHK(hipGetLastError());
+  FacState st{};
+  HIPCHK(hipMemcpyAsync(&st, h->w.fst, sizeof(st), hipMemcpyDeviceToHost, S(h)));
+  HIPCHK(hipStreamSynchronize(S(h)));
+  if (st.k != N) return set_err(h, MDS_EHIP, "factorization stopped at %d of %d", st.k, N);
+  out->npos = st.npos;
+  out->nzero = st.nzero;
+  out->nneg = st.nneg;
+  out->n2x2 = st.n2x2;
+  out->info = st.info;
+  h->have_factor = true;
+  h->have_M = false;
+  return MDS_OK;
+}
+
+bool inertia_ok(mds_handle *h, const mds_inertia &in) {
+  return in.npos == ND(h) && in.nzero == 0 && in.nneg == MM(h);
+}
+
+// Inertia correction (Waechter & Biegler, Algorithm IC).
+int correct_impl(mds_handle *h, mds_reg *reg, double mu, mds_inertia *out) {
+  const double dw_min = 1e-20, dw0 = 1e-4, kw_minus = 1.0 / 3.0, kw_plus = 8.0,
+               kw_plus_bar = 100.0, dc_bar = 1e-8, kappa_c = 0.25;
+  const double dw_max = (reg->delta_w_max > 0.0) ? reg->delta_w_max : 1e20;
+  const double dw_last = reg->delta_w_last;
+  reg->trials = 1;
+  TRY(condense_impl(h, 0.0, 0.0));
+  TRY(factor_impl(h, out));
+  if (inertia_ok(h, *out)) {
+    reg->delta_w = 0.0;
+    reg->delta_c = 0.0;
+    return MDS_OK;
+  }
+  const double dc = (out->nzero > 0) ? dc_bar * std::pow(mu, kappa_c) : 0.0;
+  double dw = (dw_last == 0.0) ? dw0 : std::max(dw_min, kw_minus * dw_last);
+  for (;;) {
+    reg->trials++;
+    TRY(condense_impl(h, dw, dc));
+    TRY(factor_impl(h, out));
+    if (inertia_ok(h, *out)) {
+      reg->delta_w_last = dw;
+      reg->delta_w = dw;
+      reg->delta_c = dc;
+      return MDS_OK;
+    }
+    dw = (dw_last == 0.0) ? kw_plus_bar * dw : kw_plus * dw;
+    if (dw > dw_max) {
+      reg->delta_w = h->dw;
+      reg->delta_c = h->dc;
+      return MDS_INERTIA_FAIL;
+    }
+  }
+}
+
+int solve_impl(mds_handle *h, const double *r_d, const double *r_s, const double *r_y,
+               double *dx_d, double *dx_s, double *dy) {
+  const int nd = ND(h), ns = NS(h), m = MM(h), N = h->N;
+  if (nd > 0) HIPCHK(hipMemcpyAsync(h->w.z, r_d, 8 * (size_t)nd, hipMemcpyDeviceToDevice, S(h)));
+  launch_rhs_condense(S(h), m, h->P.Js_rowptr, h->P.Js_col, h->P.Js_val, h->w.inv_d, r_s, r_y,
+                      h->w.z + nd);
+  {
+    TimedLaunch t(h, MDS_T_SOLVE);
+    launch_ldl_solve(S(h), N, h->w.M, h->w.dd, h->w.ds, h->w.ipiv, h->w.blk, h->w.panel_k0,
+                     h->w.fst, h->w.z);
+  }
+  h->nsolves++;
+  if (nd > 0) HIPCHK(hipMemcpyAsync(dx_d, h->w.z, 8 * (size_t)nd, hipMemcpyDeviceToDevice, S(h)));
+  if (m > 0) HIPCHK(hipMemcpyAsync(dy, h->w.z + nd, 8 * (size_t)m, hipMemcpyDeviceToDevice, S(h)));
+  launch_backsub(S(h), ns, h->w.csc_ptr, h->w.csc_row, h->w.csc_val, h->w.inv_d, r_s, dy, dx_s);
+  HIPCHK(hipGetLastError());
+  return MDS_OK;
+}
+
+// [od; os; oy] = K [dxd; dxs; dy] for the regularised full Newton system
+void kkt_matvec(mds_handle *h, const double *dxd, const double *dxs, const double *dy,
+                double *od, double *os, double *oy) {
+  const int nd = ND(h), ns = NS(h), m = MM(h);
+  const mds_problem &P = h->P;
+  if (nd > 0) {
+    launch_gemv_n(S(h), nd, nd, P.H, nd, dxd, 0.0, od);
+    if (m > 0) launch_gemv_t(S(h), m, nd, P.J_d, m, dy, 1.0, od);
+  }
+  launch_spmv_csc(S(h), ns, h->w.csc_ptr, h->w.csc_row, h->w.csc_val, dy, 0.0, os);
+  if (m > 0) {
+    if (nd > 0) {
+      launch_gemv_n(S(h), m, nd, P.J_d, m, dxd, 0.0, oy);
+      launch_spmv_csr(S(h), m, P.Js_rowptr, P.Js_col, P.Js_val, dxs, 1.0, oy);
+    } else {
+      launch_spmv_csr(S(h), m, P.Js_rowptr, P.Js_col, P.Js_val, dxs, 0.0, oy);
+    }
+  }
+  kkt_finish(S(h), nd, ns, m, h->sigma_d, h->dsbase, h->dw, h->dc, dxd, dxs, dy, od, os, oy);
+}
+
+int read_scal(mds_handle *h, double *dst, int count) {
+  HIPCHK(hipMemcpyAsync(dst, h->w.scal, 8 * (size_t)count, hipMemcpyDeviceToHost, S(h)));
+  HIPCHK(hipStreamSynchronize(S(h)));
+  return MDS_OK;
+}
+
+int amax3(mds_handle *h, int64_t na, const double *a, int64_t nb, const double *b, int64_t nc,
+          const double *c, double out[3]) {
+  ipm_red_amax3(S(h), na, a, nb, b, nc, c, h->w.red, h->w.scal);
+  HIPCHK(hipGetLastError());
+  double s[8];
+  TRY(read_scal(h, s, 8));
+  out[0] = s[0];
+  out[1] = s[1];
+  out[2] = s[2];
+  return MDS_OK;
+}
+
+int refine_impl(mds_handle *h, const double *r_d, const double *r_s, const double *r_y,
+                double *dx_d, double *dx_s, double *dy, int max_steps, double eta_tol,
+                mds_refine_info *info) {
+  const int nd = ND(h), ns = NS(h), m = MM(h);
+  const size_t nt = (size_t)nd + ns + m;
+  double *res = h->w.res, *cor = h->w.cor, *prev = h->w.prev, *kx = h->w.kx;
+  TRY(solve_impl(h, r_d, r_s, r_y, dx_d, dx_s, dy));
+  kkt_norm_parts(S(h), nd, ns, m, h->P.H, h->sigma_d, h->dw, h->P.J_d, h->P.Js_rowptr,
+                 h->P.Js_val, h->w.csc_ptr, h->w.csc_val, h->dsbase, h->dc, h->w.kn_h,
+                 h->w.kn_jd, h->w.kn_y, h->w.kn_js, h->w.red, h->w.scal);
+  HIPCHK(hipGetLastError());
+  double s8[8];
+  TRY(read_scal(h, s8, 8));
+  const double nK = std::max(s8[0], std::max(s8[1], s8[2]));
+  double a3[3];
+  TRY(amax3(h, nd, r_d, ns, r_s, m, r_y, a3));
+  const double nr = std::max(a3[0], std::max(a3[1], a3[2]));
+  double eta_prev = INFINITY, eta = 0.0, rres = 0.0;
+  int steps = 0;
+  for (;;) {
+    kkt_matvec(h, dx_d, dx_s, dy, kx, kx + nd, kx + nd + ns);
+    vec_sub(S(h), nd, r_d, kx, res);
+    vec_sub(S(h), ns, r_s, kx + nd, res + nd);
+    vec_sub(S(h), m, r_y, kx + nd + ns, res + nd + ns);
+    double rr[3], xx[3];
+    TRY(amax3(h, nd, res, ns, res + nd, m, res + nd + ns, rr));
+    TRY(amax3(h, nd, dx_d, ns, dx_s, m, dy, xx));
+    const double nres = std::max(rr[0], std::max(rr[1], rr[2]));
+    const double nx = std::max(xx[0], std::max(xx[1], xx[2]));
+    const double den = nK * nx + nr;
+    eta = (den > 0.0) ? nres / den : 0.0;
+    rres = (nr > 0.0) ? nres / nr : 0.0;
+    if (steps > 0 && !(eta < eta_prev)) {
+      // no decrease: keep the previous iterate
+      vec_copy(S(h), nd, prev, dx_d);
+      vec_copy(S(h), ns, prev + nd, dx_s);
+      vec_copy(S(h), m, prev + nd + ns, dy);
+      eta = eta_prev;
+      break;
+    }
+    if (eta <= eta_tol || steps >= max_steps) break;
+    vec_copy(S(h), nd, dx_d, prev);
+    vec_copy(S(h), ns, dx_s, prev + nd);
+    vec_copy(S(h), m, dy, prev + nd + ns);
+    eta_prev = eta;
+    TRY(solve_impl(h, res, res + nd, res + nd + ns, cor, cor + nd, cor + nd + ns));
+    vec_add_inplace(S(h), nd, cor, dx_d);
+    vec_add_inplace(S(h), ns, cor + nd, dx_s);
+    vec_add_inplace(S(h), m, cor + nd + ns, dy);
+    steps++;
+  }
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(S(h)));
+  (void)nt;
+  if (info) {
+    info->eta = eta;
+    info->rel_residual = rres;
+    info->steps = steps;
+  }
+  return (eta <= eta_tol) ? MDS_OK : MDS_REFINE_NOCONV;
+}
+
+// gf = grad f(x) -> tn; jty = J'y -> tn2; cx = J x - b -> tm (and r_y = -cx if ry)
+void eval_grad_constr(mds_handle *h, const double *x, const double *y, double *ry) {
+  const int nd = ND(h), ns = NS(h), m = MM(h);
+  const mds_problem &P = h->P;
+  double *gf = h->w.tn, *jty = h->w.tn2, *cx = h->w.tm;
+  launch_gemv_n(S(h), nd, nd, P.H, nd, x, 0.0, gf);
+  ipm_grad_finish(S(h), nd, ns, P.c, P.w, P.g, x, gf);
+  if (y) {
+    if (nd > 0) {
+      if (m > 0) launch_gemv_t(S(h), m, nd, P.J_d, m, y, 0.0, jty);
+      else hipMemsetAsync(jty, 0, 8 * (size_t)nd, S(h));
+    }
+    launch_spmv_csc(S(h), ns, h->w.csc_ptr, h->w.csc_row, h->w.csc_val, y, 0.0, jty + nd);
+  }
+  if (m > 0) {
+    if (nd > 0) {
+      launch_gemv_n(S(h), m, nd, P.J_d, m, x, 0.0, cx);
+      launch_spmv_csr(S(h), m, P.Js_rowptr, P.Js_col, P.Js_val, x + nd, 1.0, cx);
+    } else {
+      launch_spmv_csr(S(h), m, P.Js_rowptr, P.Js_col, P.Js_val, x + nd, 0.0, cx);
+    }
+    ipm_constr_finish(S(h), m, P.b, cx, ry);
+  }
+}
+
+int opt_error_impl(mds_handle *h, const double *x, const double *y, const double *zl,
+                   const double *zu, double mu, double *E, double *parts) {
+  const int n = h->n, m = MM(h);
+  const double s_max = 100.0;
+  eval_grad_constr(h, x, y, nullptr);
+  ipm_red_opt(S(h), n, m, x, y, zl, zu, h->P.xl, h->P.xu, h->w.tn, h->w.tn2, h->w.tm, mu,
+              h->w.red, h->w.scal);
+  HIPCHK(hipGetLastError());
+  double s[8];
+  TRY(read_scal(h, s, 8));
+  const double dual = s[0], prim = s[1], cl = s[2], cu = s[3], y1 = s[4], z1 = s[5];
+  const double nz = s[6];
+  const double sd = (m + nz > 0) ? std::max(s_max, (y1 + z1) / ((double)m + nz)) / s_max : 1.0;
+  const double sc = (nz > 0) ? std::max(s_max, z1 / nz) / s_max : 1.0;
+  *E = std::max(std::max(dual / sd, prim), std::max(cl, cu) / sc);
+  if (parts) {
+    parts[0] = dual;
+    parts[1] = prim;
+    parts[2] = cl;
+    parts[3] = cu;
+    parts[4] = sd;
+    parts[5] = sc;
+  }
+  return MDS_OK;
+}
+
+int merit_impl(mds_handle *h, const double *x, double mu, double *f, double *phi, double *theta) {
+  const int nd = ND(h), ns = NS(h), m = MM(h);
+  const mds_problem &P = h->P;
+  double *hx = h->w.tn, *cx = h->w.tm;
+  launch_gemv_n(S(h), nd, nd, P.H, nd, x, 0.0, hx);
+  if (m > 0) {
+    if (nd > 0) {
+      launch_gemv_n(S(h), m, nd, P.J_d, m, x, 0.0, cx);
+      launch_spmv_csr(S(h), m, P.Js_rowptr, P.Js_col, P.Js_val, x + nd, 1.0, cx);
+    } else {
+      launch_spmv_csr(S(h), m, P.Js_rowptr, P.Js_col, P.Js_val, x + nd, 0.0, cx);
+    }
+    ipm_constr_finish(S(h), m, P.b, cx, nullptr);
+  }
+  ipm_red_merit(S(h), nd, ns, m, x, hx, P.c, P.w, P.g, P.xl, P.xu, cx, h->w.red, h->w.scal);
+  HIPCHK(hipGetLastError());
+  double s[8];
+  TRY(read_scal(h, s, 8));
+  if (f) *f = s[4];
+  if (phi) *phi = s[4] - mu * s[5];
+  if (theta) *theta = s[6];
+  return MDS_OK;
+}
+
+int check_ready(mds_handle *h) {
+  if (!h) return MDS_ENULL;
+  if (!h->have_problem) return set_err(h, MDS_ESTATE, "no problem attached");
+  return MDS_OK;
+}
+
+}  // namespace
+
+// =============================================================================
+// exported functions
+// =============================================================================
+
+extern "C" {
+
+size_t mds_workspace_bytes(const mds_dims *dims, const mds_options *opts) {
+  if (!dims_ok(dims)) return 0;
+  return make_layout(*dims, nb_of(*dims, opts)).total;
+}
+
+int mds_create(mds_handle **out, const mds_dims *dims, const mds_options *opts, void *stream,
+               void *workspace, size_t workspace_bytes) {
+  if (!out || !dims) return MDS_ENULL;
+  *out = nullptr;
+  if (!dims_ok(dims)) return MDS_EDIMS;
+  const int nb = nb_of(*dims, opts);
+  const Layout L = make_layout(*dims, nb);
+  if (!workspace) return MDS_ENULL;
+  if (workspace_bytes < L.total || ((uintptr_t)workspace & 255) != 0) return MDS_EWORKSPACE;
+  mds_handle *h = new (std::nothrow) mds_handle();
+  if (!h) return MDS_EINVAL;
+  h->stream = (hipStream_t)stream;
+  if (hipGetDevice(&h->device) != hipSuccess) {
+    delete h;
+    return MDS_EHIP;
+  }
+  h->dims = *dims;
+  h->N = dims->n_d + dims->m;
+  h->n = dims->n_d + dims->n_s;
+  h->nb = nb;
+  h->max_panels = h->N / nb + 2;
+  h->ws_bytes = workspace_bytes;
+  h->alpha_bk = (1.0 + std::sqrt(17.0)) / 8.0;
+  char *base = (char *)workspace;
+  auto D = [&](int s) { return (double *)(base + L.off[s]); };
+  auto I = [&](int s) { return (int32_t *)(base + L.off[s]); };
+  Work &w = h->w;
+  w.M = D(S_M);
+  w.W = D(S_W);
+  w.dd = D(S_DD);
+  w.ds = D(S_DS);
+  w.ipiv = I(S_IPIV);
+  w.blk = I(S_BLK);
+  w.panel_k0 = I(S_PK0);
+  w.fst = (FacState *)(base + L.off[S_FST]);
+  w.inv_d = D(S_INVD);
+  w.csc_ptr = I(S_CPTR);
+  w.csc_row = I(S_CROW);
+  w.csc_val = D(S_CVAL);
+  w.csc_fill = I(S_CFILL);
+  w.flags = I(S_FLAGS);
+  w.red = D(S_RED);
+  w.scal = D(S_SCAL);
+  w.z = D(S_Z);
+  w.sig = D(S_SIG);
+  w.rx = D(S_RX);
+  w.ry = D(S_RY);
+  w.dsb = D(S_DSB);
+  w.dx = D(S_DX);
+  w.dy = D(S_DY);
+  w.dzl = D(S_DZL);
+  w.dzu = D(S_DZU);
+  w.xt = D(S_XT);
+  w.res = D(S_RES);
+  w.cor = D(S_COR);
+  w.prev = D(S_PREV);
+  w.kx = D(S_KX);
+  w.tn = D(S_TN);
+  w.tm = D(S_TM);
+  w.tn2 = D(S_TN2);
+  w.kn_h = D(S_KNH);
+  w.kn_jd = D(S_KNJD);
+  w.kn_y = D(S_KNY);
+  w.kn_js = D(S_KNJS);
+  *out = h;
+  return MDS_OK;
+}
+
+void mds_destroy(mds_handle *h) {
+  if (!h) return;
+  for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
+  delete h;
+}
+
+int mds_set_problem(mds_handle *h, const mds_problem *p) {
+  if (!h || !p) return MDS_ENULL;
+  const mds_dims &d = h->dims;
+  const int64_t nd = d.n_d, ns = d.n_s, m = d.m;
+  if ((nd > 0 && (!p->H || !p->c)) || (ns > 0 && (!p->w || !p->g)) ||
+      (m > 0 && nd > 0 && !p->J_d) || (m > 0 && !p->b) || !p->Js_rowptr ||
+      (d.nnz_s > 0 && (!p->Js_col || !p->Js_val)) || (nd + ns > 0 && (!p->xl || !p->xu)))
+    return set_err(h, MDS_ENULL, "problem array missing");
+  h->have_problem = false;
+  h->have_M = h->have_factor = false;
+  h->ipm_ready = false;
+  HIPCHK(hipMemsetAsync(h->w.flags, 0, 64, S(h)));
+  launch_validate(S(h), d, *p, h->w.flags);
+  HIPCHK(hipGetLastError());
+  int32_t f[16];
+  HIPCHK(hipMemcpyAsync(f, h->w.flags, 64, hipMemcpyDeviceToHost, S(h)));
+  HIPCHK(hipStreamSynchronize(S(h)));
+  if (f[3]) return set_err(h, MDS_EPATTERN, "J_s CSR pattern invalid (row pointers, range or order)");
+  if (f[0]) return set_err(h, MDS_ENONFINITE_INPUT, "non-finite value in problem data");
+  if (f[1]) return set_err(h, MDS_EDS_NONPOS, "w has a negative entry");
+  if (f[2]) return set_err(h, MDS_EDS_NONPOS, "bounds violate xl < xu");
+  if (f[4]) return set_err(h, MDS_EINVAL, "H is not exactly symmetric");
+  h->P = *p;
+  launch_csc_build(S(h), (int)m, (int)ns, d.nnz_s, p->Js_rowptr, p->Js_col, p->Js_val,
+                   h->w.csc_ptr, h->w.csc_row, h->w.csc_val, h->w.csc_fill);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(S(h)));
+  h->have_problem = true;
+  return MDS_OK;
+}
+
+int mds_condense(mds_handle *h, const double *sigma_d, const double *dsbase, double delta_w,
+                 double delta_c) {
+  TRY(check_ready(h));
+  if ((ND(h) > 0 && !sigma_d) || (NS(h) > 0 && !dsbase))
+    return set_err(h, MDS_ENULL, "sigma_d / dsbase missing");
+  if (!std::isfinite(delta_w) || !std::isfinite(delta_c) || delta_w < 0.0 || delta_c < 0.0)
+    return set_err(h, MDS_EINVAL, "shifts must be finite and nonnegative");
+  h->sigma_d = sigma_d;
+  h->dsbase = dsbase;
+  return condense_impl(h, delta_w, delta_c);
+}
+
+int mds_factor_inertia(mds_handle *h, mds_reg *reg, double mu, mds_inertia *out_host) {
+  TRY(check_ready(h));
+  if (!out_host) return set_err(h, MDS_ENULL, "out_host is NULL");
+  if (!reg) {
+    if (!h->have_M) return set_err(h, MDS_ESTATE, "mds_condense must precede factorization");
+    TRY(factor_impl(h, out_host));
+    return out_host->info ? MDS_ZERO_PIVOT : MDS_OK;
+  }
+  if (!h->sigma_d && ND(h) > 0) return set_err(h, MDS_ESTATE, "mds_condense must precede factorization");
+  if (!(mu >= 0.0)) return set_err(h, MDS_EINVAL, "mu must be nonnegative");
+  return correct_impl(h, reg, mu, out_host);
+}
+
+int mds_solve(mds_handle *h, const double *r_d, const double *r_s, const double *r_y,
+              double *dx_d, double *dx_s, double *dy) {
+  TRY(check_ready(h));
+  if (!h->have_factor) return set_err(h, MDS_ESTATE, "no factorization");
+  if ((ND(h) > 0 && (!r_d || !dx_d)) || (NS(h) > 0 && (!r_s || !dx_s)) ||
+      (MM(h) > 0 && (!r_y || !dy)))
+    return set_err(h, MDS_ENULL, "vector missing");
+  return solve_impl(h, r_d, r_s, r_y, dx_d, dx_s, dy);
+}
+
+int mds_refine(mds_handle *h, const double *r_d, const double *r_s, const double *r_y,
+               double *dx_d, double *dx_s, double *dy, int32_t max_steps, double eta_tol,
+               mds_refine_info *info_host) {
+  TRY(check_ready(h));
+  if (!h->have_factor) return set_err(h, MDS_ESTATE, "no factorization");
+  if ((ND(h) > 0 && (!r_d || !dx_d)) || (NS(h) > 0 && (!r_s || !dx_s)) ||
+      (MM(h) > 0 && (!r_y || !dy)))
+    return set_err(h, MDS_ENULL, "vector missing");
+  if (max_steps < 0) return set_err(h, MDS_EINVAL, "max_steps < 0");
+  return refine_impl(h, r_d, r_s, r_y, dx_d, dx_s, dy, max_steps, eta_tol, info_host);
+}
+
+int mds_sigma_rhs(mds_handle *h, const double *x, const double *y, const double *zl,
+                  const double *zu, double mu, double *sigma, double *r_x, double *r_y) {
+  TRY(check_ready(h));
+  if ((h->n > 0 && (!x || !zl || !zu || !sigma || !r_x)) || (MM(h) > 0 && (!y || !r_y)))
+    return set_err(h, MDS_ENULL, "vector missing");
+  eval_grad_constr(h, x, y, r_y);
+  ipm_sigma_rhs(S(h), h->n, x, zl, zu, h->P.xl, h->P.xu, h->w.tn, h->w.tn2, mu, sigma, r_x);
+  HIPCHK(hipGetLastError());
+  return MDS_OK;
+}
+
+int mds_ftb(mds_handle *h, int64_t n, const double *v, const double *dv, double tau,
+            double *alpha_host) {
+  if (!h || !alpha_host) return MDS_ENULL;
+  if (n < 0) return set_err(h, MDS_EDIMS, "n < 0");
+  if (n > 0 && (!v || !dv)) return set_err(h, MDS_ENULL, "vector missing");
+  if (n == 0) {
+    *alpha_host = 1.0;
+    return MDS_OK;
+  }
+  ipm_red_ftb1(S(h), n, v, dv, tau, h->w.red, h->w.scal);
+  HIPCHK(hipGetLastError());
+  double s[8];
+  TRY(read_scal(h, s, 8));
+  *alpha_host = -s[0];
+  return MDS_OK;
+}
+
+int mds_opt_error(mds_handle *h, const double *x, const double *y, const double *zl,
+                  const double *zu, double mu, double *E_host, double *parts_host) {
+  TRY(check_ready(h));
+  if (!E_host) return set_err(h, MDS_ENULL, "E_host is NULL");
+  return opt_error_impl(h, x, y, zl, zu, mu, E_host, parts_host);
+}
+
+int mds_merit(mds_handle *h, const double *x, double mu, double *f_host, double *phi_host,
+              double *theta_host) {
+  TRY(check_ready(h));
+  return merit_impl(h, x, mu, f_host, phi_host, theta_host);
+}
+
+int mds_ipm_init(mds_handle *h, mds_iterate *it, const mds_ipm_opts *opts) {
+  TRY(check_ready(h));
+  if (!it || (h->n > 0 && (!it->x || !it->zl || !it->zu)) || (MM(h) > 0 && !it->y))
+    return set_err(h, MDS_ENULL, "iterate missing");
+  mds_ipm_opts o{1e-8, 0.1, 200, 2, 1e20};
+  if (opts) o = *opts;
+  h->ipm = o;
+  ipm_init_point(S(h), h->n, MM(h), h->P.xl, h->P.xu, it->x, it->y, it->zl, it->zu);
+  HIPCHK(hipGetLastError());
+  it->mu = o.mu0;
+  it->tau = std::max(0.99, 1.0 - it->mu);
+  it->iter = 0;
+  h->dw_last = 0.0;
+  h->filter.clear();
+  double th0 = 0.0;
+  TRY(merit_impl(h, it->x, it->mu, nullptr, nullptr, &th0));
+  h->theta_max = 1e4 * std::max(1.0, th0);
+  h->theta_min = 1e-4 * std::max(1.0, th0);
+  h->ipm_ready = true;
+  return MDS_OK;
+}
+
+int mds_ipm_step(mds_handle *h, mds_iterate *it, mds_step_info *info) {
+  TRY(check_ready(h));
+  if (!h->ipm_ready) return set_err(h, MDS_ESTATE, "mds_ipm_init must precede mds_ipm_step");
+  if (!it) return set_err(h, MDS_ENULL, "iterate missing");
+  // Waechter & Biegler (2006) defaults
+  const double tau_min = 0.99, kappa_eps = 10.0, kappa_mu = 0.2, theta_mu = 1.5;
+  const double gamma_theta = 1e-5, gamma_phi = 1e-8, delta = 1.0, s_theta = 1.1, s_phi = 2.3;
+  const double eta_phi = 1e-8, gamma_alpha = 0.05;
+  const int nd = ND(h), ns = NS(h), m = MM(h), n = h->n;
+  const mds_problem &P = h->P;
+  mds_step_info loc{};
+  mds_step_info &I = info ? *info : loc;
+  memset(&I, 0, sizeof(I));
+  double *x = it->x, *y = it->y, *zl = it->zl, *zu = it->zu;
+  double mu = it->mu, tau = it->tau;
+
+  I.mu = mu;
+  if (it->iter >= h->ipm.max_iter) return I.status = MDS_IPM_MAXITER;
+  double E0 = 0.0;
+  TRY(opt_error_impl(h, x, y, zl, zu, 0.0, &E0, nullptr));
+  I.E0 = E0;
+  if (!std::isfinite(E0)) return I.status = MDS_IPM_NONFINITE;
+  if (E0 <= h->ipm.tol) return I.status = MDS_IPM_CONVERGED;
+  // barrier update while the barrier subproblem is solved to kappa_eps * mu
+  for (;;) {
+    double Emu = 0.0;
+    TRY(opt_error_impl(h, x, y, zl, zu, mu, &Emu, nullptr));
+    if (!(Emu <= kappa_eps * mu)) break;
+    const double mnew = std::max(h->ipm.tol / 10.0, std::min(kappa_mu * mu, std::pow(mu, theta_mu)));
+    if (!(mnew < mu)) break;
+    mu = mnew;
+    tau = std::max(tau_min, 1.0 - mu);
+    h->filter.clear();
+  }
+  I.mu = mu;
+  // Newton system with inertia correction and refinement
+  double *sig = h->w.sig, *rx = h->w.rx, *ry = h->w.ry, *dsb = h->w.dsb;
+  double *dx = h->w.dx, *dy = h->w.dy, *dzl = h->w.dzl, *dzu = h->w.dzu, *xt = h->w.xt;
+  TRY(mds_sigma_rhs(h, x, y, zl, zu, mu, sig, rx, ry));
+  ipm_dsbase(S(h), nd, ns, P.w, sig, dsb);
+  h->sigma_d = sig;
+  h->dsbase = dsb;
+  mds_reg reg{};
+  reg.delta_w_last = h->dw_last;
+  reg.delta_w_max = h->ipm.dw_max;
+  mds_inertia in{};
+  int fst = correct_impl(h, &reg, mu, &in);
+  if (fst < 0) return fst;
+  h->dw_last = reg.delta_w_last;
+  I.delta_w = reg.delta_w;
+  I.delta_c = reg.delta_c;
+  I.inertia[0] = in.npos;
+  I.inertia[1] = in.nzero;
+  I.inertia[2] = in.nneg;
+  I.trials = reg.trials;
+  if (fst == MDS_INERTIA_FAIL) return I.status = MDS_INERTIA_FAIL;
+  mds_refine_info ri{};
+  int rst = refine_impl(h, rx, rx + nd, ry, dx, dx + nd, dy, h->ipm.refine_steps, 1e-14, &ri);
+  if (rst < 0) return rst;
+  I.eta = ri.eta;
+  I.solves = 1 + ri.steps;
+  ipm_dz(S(h), n, x, zl, zu, P.xl, P.xu, dx, mu, dzl, dzu);
+  ipm_red_ftb(S(h), n, x, P.xl, P.xu, dx, zl, zu, dzl, dzu, tau, h->w.red, h->w.scal);
+  HIPCHK(hipGetLastError());
+  double s8[8];
+  TRY(read_scal(h, s8, 8));
+  const double a_pr = -s8[0], a_du = -s8[1];
+  // grad(phi_mu)' dx at x (needs grad f: recompute, refinement used the scratch)
+  eval_grad_constr(h, x, nullptr, nullptr);
+  ipm_red_gphi(S(h), n, h->w.tn, x, P.xl, P.xu, dx, mu, h->w.red, h->w.scal);
+  HIPCHK(hipGetLastError());
+  TRY(read_scal(h, s8, 8));
+  const double gphi = s8[4];
+  double th = 0.0, ph = 0.0;
+  TRY(merit_impl(h, x, mu, nullptr, &ph, &th));
+  double amin;
+  if (gphi < 0.0) {
+    amin = std::min(gamma_theta, gamma_phi * th / (-gphi));
+    if (th <= h->theta_min) amin = std::min(amin, delta * std::pow(th, s_theta) / std::pow(-gphi, s_phi));
+    amin = gamma_alpha * amin;
+  } else {
+    amin = gamma_alpha * gamma_theta;
+  }
+  double alpha = a_pr;
+  bool accepted = false, augment = true;
+  int nbt = 0;
+  for (;;) {
+    ipm_axpy_to(S(h), n, x, dx, alpha, xt);
+    double tht = 0.0, pht = 0.0;
+    TRY(merit_impl(h, xt, mu, nullptr, &pht, &tht));
+    const bool ok = std::isfinite(tht) && std::isfinite(pht);
+    bool infilt = !ok || tht >= h->theta_max;
+    for (size_t f = 0; f < h->filter.size() && !infilt; ++f)
+      if (tht >= h->filter[f].first && pht >= h->filter[f].second) infilt = true;
+    if (!infilt) {
+      const bool sw = gphi < 0.0 && alpha * std::pow(-gphi, s_phi) > delta * std::pow(th, s_theta);
+      const bool armijo = pht <= ph + eta_phi * alpha * gphi;
+      if (th <= h->theta_min && sw) {
+        if (armijo) accepted = true;
+      } else if (tht <= (1.0 - gamma_theta) * th || pht <= ph - gamma_phi * th) {
+        accepted = true;
+      }
+      if (accepted) augment = !(sw && armijo);
+    }
+    if (accepted) break;
+    alpha = 0.5 * alpha;
+    nbt++;
+    if (alpha < amin) break;
+  }
+  I.theta = th;
+  I.phi = ph;
+  I.alpha_pr = alpha;
+  I.alpha_du = a_du;
+  I.backtracks = nbt;
+  if (!accepted) {
+    it->mu = mu;
+    it->tau = tau;
+    return I.status = MDS_IPM_LS_FAIL;
+  }
+  if (augment) h->filter.emplace_back((1.0 - gamma_theta) * th, ph - gamma_phi * th);
+  ipm_accept(S(h), n, m, xt, x, y, dy, zl, zu, dzl, dzu, P.xl, P.xu, alpha, a_du, mu);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(S(h)));
+  it->mu = mu;
+  it->tau = tau;
+  it->iter++;
+  I.status = MDS_OK;
+  return MDS_OK;
+}
+
+int mds_ipm_solve(mds_handle *h, mds_iterate *it, const mds_ipm_opts *opts,
+                  mds_step_info *trace_host, int32_t trace_cap, int32_t *iters_host) {
+  TRY(mds_ipm_init(h, it, opts));
+  int st = MDS_OK;
+  int rows = 0;
+  for (;;) {
+    mds_step_info info{};
+    st = mds_ipm_step(h, it, &info);
+    if (trace_host && rows < trace_cap) trace_host[rows] = info;
+    rows++;
+    if (st != MDS_OK) break;
+  }
+  if (iters_host) *iters_host = it->iter;
+  return st;
+}
+
+int mds_get_matrix(mds_handle *h, double *M_host) {
+  if (!h || !M_host) return MDS_ENULL;
+  const size_t N = h->N;
+  HIPCHK(hipMemcpyAsync(M_host, h->w.M, 8 * N * N, hipMemcpyDeviceToHost, S(h)));
+  HIPCHK(hipStreamSynchronize(S(h)));
+  return MDS_OK;
+}
+
+int mds_get_factor(mds_handle *h, double *L_host, double *dd_host, double *ds_host,
+                   int32_t *ipiv_host) {
+  if (!h) return MDS_ENULL;
+  if (!h->have_factor) return set_err(h, MDS_ESTATE, "no factorization");
+  const int N = h->N;
+  std::vector<int32_t> ipiv(N), blk(N), pk0(h->max_panels + 2);
+  FacState st{};
+  HIPCHK(hipMemcpyAsync(ipiv.data(), h->w.ipiv, 4 * (size_t)N, hipMemcpyDeviceToHost, S(h)));
+  HIPCHK(hipMemcpyAsync(blk.data(), h->w.blk, 4 * (size_t)N, hipMemcpyDeviceToHost, S(h)));
+  HIPCHK(hipMemcpyAsync(&st, h->w.fst, sizeof(st), hipMemcpyDeviceToHost, S(h)));
+  HIPCHK(hipMemcpyAsync(pk0.data(), h->w.panel_k0, 4 * pk0.size(), hipMemcpyDeviceToHost, S(h)));
+  if (dd_host) HIPCHK(hipMemcpyAsync(dd_host, h->w.dd, 8 * (size_t)N, hipMemcpyDeviceToHost, S(h)));
+  if (ds_host) HIPCHK(hipMemcpyAsync(ds_host, h->w.ds, 8 * (size_t)N, hipMemcpyDeviceToHost, S(h)));
+  if (L_host) HIPCHK(hipMemcpyAsync(L_host, h->w.M, 8 * (size_t)N * N, hipMemcpyDeviceToHost, S(h)));
+  HIPCHK(hipStreamSynchronize(S(h)));
+  if (ipiv_host) memcpy(ipiv_host, ipiv.data(), 4 * (size_t)N);
+  if (!L_host) return MDS_OK;
+  // keep the strictly lower part only
+  for (int c = 0; c < N; ++c)
+    for (int i = 0; i <= c; ++i) L_host[(size_t)i + (size_t)c * N] = 0.0;
+  // standard form: every interchange of a later panel permutes the rows of all
+  // columns of the earlier panels
+  for (int b = 0; b < st.npanel; ++b) {
+    const int k0 = pk0[b], k1 = pk0[b + 1];
+    for (int k = k0; k < k1;) {
+      int p, q;
+      if (blk[k] == 1) {
+        p = k;
+        q = ipiv[k] - 1;
+        k += 1;
+      } else {
+        p = k + 1;
+        q = -ipiv[k] - 1;
+        k += 2;
+      }
+      if (p == q) continue;
+      for (int c = 0; c < k0; ++c)
+        std::swap(L_host[(size_t)p + (size_t)c * N], L_host[(size_t)q + (size_t)c * N]);
+    }
+  }
+  return MDS_OK;
+}
+
+int mds_get_inv_ds(mds_handle *h, double *inv_d_host) {
+  if (!h || !inv_d_host) return MDS_ENULL;
+  HIPCHK(hipMemcpyAsync(inv_d_host, h->w.inv_d, 8 * (size_t)NS(h), hipMemcpyDeviceToHost, S(h)));
+  HIPCHK(hipStreamSynchronize(S(h)));
+  return MDS_OK;
+}
+
+int mds_set_timing(mds_handle *h, int enable) {
+  if (!h) return MDS_ENULL;
+  if (resolve_timings(h) != MDS_OK) return set_err(h, MDS_EHIP, "event synchronization failed");
+  h->timing = enable != 0;
+  for (int c = 0; c < MDS_T_CLASSES; ++c) {
+    h->t_ms[c] = 0.0;
+    h->t_n[c] = 0;
+  }
+  return MDS_OK;
+}
+
+int mds_get_timings(mds_handle *h, mds_timings *out) {
+  if (!h || !out) return MDS_ENULL;
+  if (resolve_timings(h) != MDS_OK) return set_err(h, MDS_EHIP, "event synchronization failed");
+  for (int c = 0; c < MDS_T_CLASSES; ++c) {
+    out->ms[c] = h->t_ms[c];
+    out->launches[c] = h->t_n[c];
+  }
+  return MDS_OK;
+}
+
+const char *mds_status_string(int s) {
+  switch (s) {
+    case MDS_OK: return "ok";
+    case MDS_EINVAL: return "invalid argument";
+    case MDS_ENULL: return "null pointer";
+    case MDS_EDIMS: return "invalid dimensions";
+    case MDS_EWORKSPACE: return "workspace too small or misaligned";
+    case MDS_ESTATE: return "call order violated";
+    case MDS_EHIP: return "HIP runtime error";
+    case MDS_ENONFINITE_INPUT: return "non-finite input";
+    case MDS_EDS_NONPOS: return "nonpositive diagonal or invalid bounds";
+    case MDS_EPATTERN: return "invalid sparsity pattern";
+    case MDS_ZERO_PIVOT: return "zero pivot";
+    case MDS_INERTIA_FAIL: return "inertia correction failed";
+    case MDS_REFINE_NOCONV: return "refinement did not reach its tolerance";
+    case MDS_IPM_CONVERGED: return "converged";
+    case MDS_IPM_LS_FAIL: return "line search failed";
+    case MDS_IPM_MAXITER: return "iteration limit";
+    case MDS_IPM_NONFINITE: return "non-finite iterate";
+    default: return "unknown status";
+  }
+}
+
+const char *mds_last_error(const mds_handle *h) { return h ? h->err : "null handle"; }
+
+}  // extern "C"

@@ -1,0 +1,128 @@
+// Internal declarations of the mdsipm library (gfx950 only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <utility>
+#include <vector>
+
+#include "mdsipm.h"
+
+namespace mds {
+
+constexpr int kPanelThreads = 1024;  // one workgroup factors a panel
+constexpr int kMaxNb = 64;           // largest supported panel width
+constexpr int kRedBlocks = 1024;     // partial-reduction slots
+
+// Device-side factorization progress, written by the panel kernel.
+struct FacState {
+  int32_t k;       // first unfactored index (start of the next panel)
+  int32_t npanel;  // panels completed
+  int32_t info;    // 1-based index of the first exact zero pivot, or 0
+  int32_t npos, nzero, nneg, n2x2;
+  int32_t pad;
+};
+
+// Pointers into the caller's workspace.
+struct Work {
+  double *M;          // N x N, full symmetric, column-major; L after factoring
+  double *W;          // N x (nb + 2) panel workspace (updated columns)
+  double *dd, *ds;    // D diagonal / sub-diagonal (N)
+  int32_t *ipiv;      // LAPACK-style pivots (N)
+  int32_t *blk;       // 1: 1x1 pivot, 2: first of a 2x2, 3: second of a 2x2
+  int32_t *panel_k0;  // panel start indices (max_panels + 1)
+  FacState *fst;
+  double *inv_d;      // D_s^{-1} (n_s)
+  int32_t *csc_ptr;   // n_s + 1
+  int32_t *csc_row;   // nnz
+  double *csc_val;    // nnz
+  int32_t *csc_fill;  // n_s scratch
+  int32_t *flags;     // validation flags (16)
+  double *red;        // reduction partials (kRedBlocks * 8)
+  double *scal;       // device scalars (64)
+  double *z;          // N: condensed rhs / solution
+  // Newton / IPM vectors
+  double *sig, *rx, *ry, *dsb;       // n, n, m, n_s
+  double *dx, *dy, *dzl, *dzu, *xt;  // n, m, n, n, n
+  double *res, *cor, *prev, *kx;     // n + m each (refinement)
+  double *tn, *tm, *tn2;             // scratch n, m, n
+  double *kn_h, *kn_jd, *kn_y, *kn_js;  // ||K||_inf row-sum scratch: n_d, n_d, m, n_s
+};
+
+}  // namespace mds
+
+struct mds_handle {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  mds_dims dims{};
+  int N = 0, n = 0, nb = 16, max_panels = 0;
+  mds::Work w{};
+  size_t ws_bytes = 0;
+  mds_problem P{};
+  bool have_problem = false, have_M = false, have_factor = false;
+  const double *sigma_d = nullptr, *dsbase = nullptr;  // last condense inputs
+  double dw = 0.0, dc = 0.0;                           // shifts of current M / factor
+  double alpha_bk = 0.0;                               // (1 + sqrt(17)) / 8
+  // IPM state
+  mds_ipm_opts ipm{};
+  double theta_max = 0.0, theta_min = 0.0, dw_last = 0.0;
+  std::vector<std::pair<double, double>> filter;
+  bool ipm_ready = false;
+  // per-launch timing (hipEvent pairs, resolved in mds_get_timings)
+  bool timing = false;
+  int64_t nsolves = 0;  // LDL' solves performed (statistics)
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<std::pair<int, std::pair<int, int>>> ev_marks;  // class, (start, stop)
+  double t_ms[MDS_T_CLASSES] = {0, 0, 0, 0};
+  int64_t t_n[MDS_T_CLASSES] = {0, 0, 0, 0};
+  char err[512] = {0};
+};
+
+// ---- kernel launch wrappers (defined in the .hip files) --------------------
+namespace mds {
+
+// condense.hip
+void launch_inv_d(hipStream_t s, int ns, const double *dsbase, double dw, double *inv_d);
+void launch_condense_dense(hipStream_t s, int nd, int m, const double *H, const double *Jd,
+                           const double *sigma_d, double dw, double *M);
+void launch_condense_schur(hipStream_t s, int nd, int m, int N, const int32_t *rp,
+                           const int32_t *ci, const double *v, const int32_t *cptr,
+                           const int32_t *crow, const double *cval, const double *inv_d,
+                           double dc, double *M);
+void launch_rhs_condense(hipStream_t s, int m, const int32_t *rp, const int32_t *ci,
+                         const double *v, const double *inv_d, const double *r_s,
+                         const double *r_y, double *out);
+void launch_backsub(hipStream_t s, int ns, const int32_t *cptr, const int32_t *crow,
+                    const double *cval, const double *inv_d, const double *r_s,
+                    const double *dy, double *dx_s);
+void launch_csc_build(hipStream_t s, int m, int ns, int64_t nnz, const int32_t *rp,
+                      const int32_t *ci, const double *v, int32_t *cptr, int32_t *crow,
+                      double *cval, int32_t *fill);
+void launch_validate(hipStream_t s, const mds_dims &d, const mds_problem &p, int32_t *flags);
+
+// bk.hip
+void launch_fac_reset(hipStream_t s, FacState *st, int32_t *panel_k0);
+void launch_bk_panel(hipStream_t s, int N, int nb, double alpha, double *M, double *W,
+                     double *dd, double *ds, int32_t *ipiv, int32_t *blk, FacState *st,
+                     int32_t *panel_k0);
+void launch_bk_trailing(hipStream_t s, int N, int nb, int slot, const double *W, double *M,
+                        const FacState *st, const int32_t *panel_k0);
+
+// solve.hip
+void launch_ldl_solve(hipStream_t s, int N, const double *M, const double *dd,
+                      const double *ds, const int32_t *ipiv, const int32_t *blk,
+                      const int32_t *panel_k0, const FacState *st, double *z);
+
+// vec.hip
+void launch_gemv_n(hipStream_t s, int rows, int cols, const double *A, int lda,
+                   const double *x, double beta, double *y);
+void launch_gemv_t(hipStream_t s, int rows, int cols, const double *A, int lda,
+                   const double *x, double beta, double *y);
+void launch_spmv_csr(hipStream_t s, int rows, const int32_t *rp, const int32_t *ci,
+                     const double *v, const double *x, double beta, double *y);
+void launch_spmv_csc(hipStream_t s, int cols, const int32_t *cptr, const int32_t *crow,
+                     const double *cval, const double *x, double beta, double *y);
+
+}  // namespace mds

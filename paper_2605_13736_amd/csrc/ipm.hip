@@ -1,0 +1,554 @@
+// Element-wise and reduction kernels of the filter line-search IPM
+// (Sec. 2.1; kernel class K1).  Infinite bounds contribute nothing: their
+// slacks, barrier terms and multipliers are skipped.
+//
+// Reductions write one 8-slot record per workgroup (slots 0-3 maxima, 4-7
+// sums) into `red`; k_red_final combines the records in block order.  The
+// grid size depends only on the vector length, so every sum is evaluated in
+// the same order on every run.
+#include "internal.hpp"
+#include "ipm.hpp"
+#include "vec.hpp"
+
+namespace mds {
+namespace {
+
+constexpr int RB = 256;
+
+inline unsigned grid1(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+__global__ void k_init_point(int n, int m, const double *__restrict__ xl,
+                             const double *__restrict__ xu, double *__restrict__ x,
+                             double *__restrict__ y, double *__restrict__ zl,
+                             double *__restrict__ zu) {
+  const double kappa1 = 1e-2, kappa2 = 1e-2;
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    const double l = xl[i], u = xu[i];
+    const bool hl = isfinite(l), hu = isfinite(u);
+    double xi = 0.0;
+    if (hl && hu) {
+      const double pl = fmin(kappa1 * fmax(1.0, fabs(l)), kappa2 * (u - l));
+      const double pu = fmin(kappa1 * fmax(1.0, fabs(u)), kappa2 * (u - l));
+      xi = fmin(fmax(xi, l + pl), u - pu);
+    } else if (hl) {
+      xi = fmax(xi, l + kappa1 * fmax(1.0, fabs(l)));
+    } else if (hu) {
+      xi = fmin(xi, u - kappa1 * fmax(1.0, fabs(u)));
+    }
+    x[i] = xi;
+    zl[i] = hl ? 1.0 : 0.0;
+    zu[i] = hu ? 1.0 : 0.0;
+  }
+  if (i < m) y[i] = 0.0;
+}
+
+// gf[0:nd] holds H x_d on entry; gradient of f completed in place.
+__global__ void k_grad_finish(int nd, int ns, const double *__restrict__ c,
+                              const double *__restrict__ w, const double *__restrict__ g,
+                              const double *__restrict__ x, double *__restrict__ gf) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nd) gf[i] = gf[i] + c[i];
+  else if (i < nd + ns) gf[i] = w[i - nd] * x[i] + g[i - nd];
+}
+
+__global__ void k_sigma_rhs(int n, const double *__restrict__ x, const double *__restrict__ zl,
+                            const double *__restrict__ zu, const double *__restrict__ xl,
+                            const double *__restrict__ xu, const double *__restrict__ gf,
+                            const double *__restrict__ jty, double mu,
+                            double *__restrict__ sigma, double *__restrict__ rx) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double s = 0.0, gb = gf[i] + jty[i];
+  const double l = xl[i], u = xu[i];
+  if (isfinite(l)) {
+    const double sl = x[i] - l;
+    s = s + zl[i] / sl;
+    gb = gb - mu / sl;
+  }
+  if (isfinite(u)) {
+    const double su = u - x[i];
+    s = s + zu[i] / su;
+    gb = gb + mu / su;
+  }
+  sigma[i] = s;
+  rx[i] = -gb;
+}
+
+// cx holds J x on entry; becomes J x - b, and r_y = -(J x - b).
+__global__ void k_constr_finish(int m, const double *__restrict__ b, double *__restrict__ cx,
+                                double *__restrict__ ry) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  const double t = cx[i] - b[i];
+  cx[i] = t;
+  if (ry) ry[i] = -t;
+}
+
+__global__ void k_dsbase(int nd, int ns, const double *__restrict__ w,
+                         const double *__restrict__ sig, double *__restrict__ dsb) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < ns) dsb[k] = w[k] + sig[nd + k];
+}
+
+__global__ void k_dz(int n, const double *__restrict__ x, const double *__restrict__ zl,
+                     const double *__restrict__ zu, const double *__restrict__ xl,
+                     const double *__restrict__ xu, const double *__restrict__ dx, double mu,
+                     double *__restrict__ dzl, double *__restrict__ dzu) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double a = 0.0, b = 0.0;
+  if (isfinite(xl[i])) {
+    const double sl = x[i] - xl[i];
+    a = mu / sl - zl[i] - (zl[i] / sl) * dx[i];
+  }
+  if (isfinite(xu[i])) {
+    const double su = xu[i] - x[i];
+    b = mu / su - zu[i] + (zu[i] / su) * dx[i];
+  }
+  dzl[i] = a;
+  dzu[i] = b;
+}
+
+// slot 0: max dual infeasibility, 1: max |J x - b|, 2/3: max complementarity
+// (lower/upper), 4: sum |y|, 5: sum of bound multipliers, 6: finite bounds
+__global__ __launch_bounds__(RB) void k_red_opt(int n, int m, const double *__restrict__ x,
+                                                const double *__restrict__ y,
+                                                const double *__restrict__ zl,
+                                                const double *__restrict__ zu,
+                                                const double *__restrict__ xl,
+                                                const double *__restrict__ xu,
+                                                const double *__restrict__ gf,
+                                                const double *__restrict__ jty,
+                                                const double *__restrict__ cx, double mu,
+                                                double *__restrict__ red) {
+  double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  const int64_t stride = (int64_t)gridDim.x * RB;
+  const int64_t len = (n > m) ? n : m;
+  for (int64_t e = (int64_t)blockIdx.x * RB + threadIdx.x; e < len; e += stride) {
+    if (e < n) {
+      double r = gf[e] + jty[e];
+      if (isfinite(xl[e])) {
+        r = r - zl[e];
+        v[2] = fmax(v[2], fabs((x[e] - xl[e]) * zl[e] - mu));
+        v[5] += fabs(zl[e]);
+        v[6] += 1.0;
+      }
+      if (isfinite(xu[e])) {
+        r = r + zu[e];
+        v[3] = fmax(v[3], fabs((xu[e] - x[e]) * zu[e] - mu));
+        v[5] += fabs(zu[e]);
+        v[6] += 1.0;
+      }
+      v[0] = fmax(v[0], fabs(r));
+    }
+    if (e < m) {
+      v[1] = fmax(v[1], fabs(cx[e]));
+      v[4] += fabs(y[e]);
+    }
+  }
+  block_reduce8(v, red + (size_t)blockIdx.x * 8);
+}
+
+// slot 4: f(x), 5: sum of log-slacks, 6: theta = ||J x - b||_1.
+// hx holds H x_d, cx holds J x - b.
+__global__ __launch_bounds__(RB) void k_red_merit(int nd, int ns, int m,
+                                                  const double *__restrict__ x,
+                                                  const double *__restrict__ hx,
+                                                  const double *__restrict__ c,
+                                                  const double *__restrict__ w,
+                                                  const double *__restrict__ g,
+                                                  const double *__restrict__ xl,
+                                                  const double *__restrict__ xu,
+                                                  const double *__restrict__ cx,
+                                                  double *__restrict__ red) {
+  double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  const int n = nd + ns;
+  const int64_t stride = (int64_t)gridDim.x * RB;
+  const int64_t len = (n > m) ? n : m;
+  for (int64_t e = (int64_t)blockIdx.x * RB + threadIdx.x; e < len; e += stride) {
+    if (e < nd) {
+      v[4] += x[e] * (0.5 * hx[e] + c[e]);
+    } else if (e < n) {
+      const double xs = x[e];
+      v[4] += xs * (0.5 * w[e - nd] * xs + g[e - nd]);
+    }
+    if (e < n) {
+      if (isfinite(xl[e])) v[5] += log(x[e] - xl[e]);
+      if (isfinite(xu[e])) v[5] += log(xu[e] - x[e]);
+    }
+    if (e < m) v[6] += fabs(cx[e]);
+  }
+  block_reduce8(v, red + (size_t)blockIdx.x * 8);
+}
+
+// slot 4: grad(phi_mu)' dx
+__global__ __launch_bounds__(RB) void k_red_gphi(int n, const double *__restrict__ gf,
+                                                 const double *__restrict__ x,
+                                                 const double *__restrict__ xl,
+                                                 const double *__restrict__ xu,
+                                                 const double *__restrict__ dx, double mu,
+                                                 double *__restrict__ red) {
+  double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  const int64_t stride = (int64_t)gridDim.x * RB;
+  for (int64_t e = (int64_t)blockIdx.x * RB + threadIdx.x; e < n; e += stride) {
+    double gi = gf[e];
+    if (isfinite(xl[e])) gi = gi - mu / (x[e] - xl[e]);
+    if (isfinite(xu[e])) gi = gi + mu / (xu[e] - x[e]);
+    v[4] += gi * dx[e];
+  }
+  block_reduce8(v, red + (size_t)blockIdx.x * 8);
+}
+
+// Fraction to the boundary: slot 0 = max of -(step limit) over primal slacks,
+// slot 1 = same over bound multipliers (so alpha = min(1, -slot)).
+__global__ __launch_bounds__(RB) void k_red_ftb(int n, const double *__restrict__ x,
+                                                const double *__restrict__ xl,
+                                                const double *__restrict__ xu,
+                                                const double *__restrict__ dx,
+                                                const double *__restrict__ zl,
+                                                const double *__restrict__ zu,
+                                                const double *__restrict__ dzl,
+                                                const double *__restrict__ dzu, double tau,
+                                                double *__restrict__ red) {
+  double v[8] = {-1.0, -1.0, 0, 0, 0, 0, 0, 0};
+  const int64_t stride = (int64_t)gridDim.x * RB;
+  for (int64_t e = (int64_t)blockIdx.x * RB + threadIdx.x; e < n; e += stride) {
+    if (isfinite(xl[e])) {
+      const double sl = x[e] - xl[e];
+      if (dx[e] < 0.0) v[0] = fmax(v[0], -(-tau * sl / dx[e]));
+      if (dzl[e] < 0.0) v[1] = fmax(v[1], -(-tau * zl[e] / dzl[e]));
+    }
+    if (isfinite(xu[e])) {
+      const double su = xu[e] - x[e];
+      if (-dx[e] < 0.0) v[0] = fmax(v[0], -(-tau * su / (-dx[e])));
+      if (dzu[e] < 0.0) v[1] = fmax(v[1], -(-tau * zu[e] / dzu[e]));
+    }
+  }
+  block_reduce8(v, red + (size_t)blockIdx.x * 8);
+}
+
+// generic fraction to the boundary of one vector
+__global__ __launch_bounds__(RB) void k_red_ftb1(int64_t n, const double *__restrict__ v0,
+                                                 const double *__restrict__ dv, double tau,
+                                                 double *__restrict__ red) {
+  double v[8] = {-1.0, 0, 0, 0, 0, 0, 0, 0};
+  const int64_t stride = (int64_t)gridDim.x * RB;
+  for (int64_t e = (int64_t)blockIdx.x * RB + threadIdx.x; e < n; e += stride)
+    if (dv[e] < 0.0) v[0] = fmax(v[0], -(-tau * v0[e] / dv[e]));
+  block_reduce8(v, red + (size_t)blockIdx.x * 8);
+}
+
+__global__ void k_red_final(int nb, const double *__restrict__ red, double *__restrict__ out) {
+  const int s = threadIdx.x;
+  if (s >= 8) return;
+  double t = red[s];
+  for (int b = 1; b < nb; ++b) t = (s < 4) ? fmax(t, red[(size_t)b * 8 + s]) : t + red[(size_t)b * 8 + s];
+  out[s] = t;
+}
+
+__global__ void k_axpy_to(int n, const double *__restrict__ x, const double *__restrict__ dx,
+                          double a, double *__restrict__ out) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = x[i] + a * dx[i];
+}
+
+__global__ void k_accept(int n, int m, const double *__restrict__ xt, double *__restrict__ x,
+                         double *__restrict__ y, const double *__restrict__ dy,
+                         double *__restrict__ zl, double *__restrict__ zu,
+                         const double *__restrict__ dzl, const double *__restrict__ dzu,
+                         const double *__restrict__ xl, const double *__restrict__ xu,
+                         double alpha, double alpha_z, double mu) {
+  const double kappa_sigma = 1e10;
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    const double xi = xt[i];
+    x[i] = xi;
+    if (isfinite(xl[i])) {
+      const double z = zl[i] + alpha_z * dzl[i], sl = xi - xl[i];
+      zl[i] = fmax(fmin(z, kappa_sigma * mu / sl), mu / (kappa_sigma * sl));
+    }
+    if (isfinite(xu[i])) {
+      const double z = zu[i] + alpha_z * dzu[i], su = xu[i] - xi;
+      zu[i] = fmax(fmin(z, kappa_sigma * mu / su), mu / (kappa_sigma * su));
+    }
+  }
+  if (i < m) y[i] = y[i] + alpha * dy[i];
+}
+
+__global__ void k_copy_scaled(int64_t n, const double *__restrict__ src, double *__restrict__ dst) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src[i];
+}
+
+// res = r - K d for the full regularised Newton system; kd holds K d.
+__global__ void k_sub(int64_t n, const double *__restrict__ a, const double *__restrict__ b,
+                      double *__restrict__ out) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = a[i] - b[i];
+}
+
+__global__ void k_add_inplace(int64_t n, const double *__restrict__ a, double *__restrict__ out) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = out[i] + a[i];
+}
+
+// K d, second block row (x_s): (dsbase + dw) dx_s + J_s' dy, with J_s' dy in o_s.
+__global__ void k_kkt_s(int ns, const double *__restrict__ dsb, double dw,
+                        const double *__restrict__ dxs, double *__restrict__ o_s) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < ns) o_s[k] = fma(dsb[k] + dw, dxs[k], o_s[k]);
+}
+
+// first block row (x_d): o_d = H dx_d + (sigma_d + dw) dx_d + J_d' dy (o_d holds
+// H dx_d + J_d' dy on entry)
+__global__ void k_kkt_d(int nd, const double *__restrict__ sig, double dw,
+                        const double *__restrict__ dxd, double *__restrict__ o_d) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nd) o_d[i] = fma(sig[i] + dw, dxd[i], o_d[i]);
+}
+
+// third block row (y): o_y = J dx - dc dy (o_y holds J dx on entry)
+__global__ void k_kkt_y(int m, double dc, const double *__restrict__ dy, double *__restrict__ o_y) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < m) o_y[i] = fma(-dc, dy[i], o_y[i]);
+}
+
+// slot 0: max |a|, slot 1: max |b|, slot 2: max |c|  (infinity norms)
+__global__ __launch_bounds__(RB) void k_red_amax3(int64_t na, const double *__restrict__ a,
+                                                  int64_t nb, const double *__restrict__ b,
+                                                  int64_t nc, const double *__restrict__ c,
+                                                  double *__restrict__ red) {
+  double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  const int64_t stride = (int64_t)gridDim.x * RB;
+  int64_t len = na > nb ? na : nb;
+  len = len > nc ? len : nc;
+  for (int64_t e = (int64_t)blockIdx.x * RB + threadIdx.x; e < len; e += stride) {
+    if (e < na) v[0] = fmax(v[0], fabs(a[e]));
+    if (e < nb) v[1] = fmax(v[1], fabs(b[e]));
+    if (e < nc) v[2] = fmax(v[2], fabs(c[e]));
+  }
+  block_reduce8(v, red + (size_t)blockIdx.x * 8);
+}
+
+// ||K||_inf row sums (the operator norm used in the backward error):
+// slot 0 over the x_d rows, slot 1 over the x_s rows, slot 2 over the y rows.
+// colsum holds, per x_s column, sum_i |J_s(i,k)|; rowabs_d / rowabs_y the
+// absolute row sums of the dense parts (computed by k_absrows).
+__global__ __launch_bounds__(RB) void k_red_knorm(int nd, int ns, int m,
+                                                  const double *__restrict__ hrow,
+                                                  const double *__restrict__ sig, double dw,
+                                                  const double *__restrict__ jdcol,
+                                                  const double *__restrict__ dsb,
+                                                  const double *__restrict__ jscol,
+                                                  const double *__restrict__ yrow, double dc,
+                                                  double *__restrict__ red) {
+  double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  const int64_t stride = (int64_t)gridDim.x * RB;
+  int64_t len = nd > ns ? nd : ns;
+  len = len > m ? len : m;
+  for (int64_t e = (int64_t)blockIdx.x * RB + threadIdx.x; e < len; e += stride) {
+    if (e < nd) v[0] = fmax(v[0], hrow[e] + jdcol[e]);
+    if (e < ns) v[1] = fmax(v[1], fabs(dsb[e] + dw) + jscol[e]);
+    if (e < m) v[2] = fmax(v[2], yrow[e] + fabs(dc));
+  }
+  (void)sig;
+  block_reduce8(v, red + (size_t)blockIdx.x * 8);
+}
+
+// absolute row sums: x_d rows of [H + diag(sig + dw)], |J_d| column sums
+// (x_d rows of J_d'), and y rows |J_d| + |J_s|; J_s column sums for x_s rows.
+__global__ void k_abs_hrow(int nd, const double *__restrict__ H, const double *__restrict__ sig,
+                           double dw, double *__restrict__ out) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nd) return;
+  double t = 0.0;
+  for (int j = 0; j < nd; ++j) {
+    double h = H[(size_t)i + (size_t)j * nd];
+    if (i == j) h = h + sig[i] + dw;
+    t += fabs(h);
+  }
+  out[i] = t;
+}
+
+__global__ void k_abs_jdcol(int m, int nd, const double *__restrict__ Jd,
+                            double *__restrict__ out) {
+  const int lane = threadIdx.x & 63;
+  const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (j >= nd) return;
+  double s = 0.0;
+  for (int i = lane; i < m; i += 64) s += fabs(Jd[(size_t)i + (size_t)j * m]);
+  s = wave_sum(s);
+  if (lane == 0) out[j] = s;
+}
+
+__global__ void k_abs_yrow(int m, int nd, const double *__restrict__ Jd,
+                           const int32_t *__restrict__ rp, const double *__restrict__ v,
+                           double *__restrict__ out) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  double t = 0.0;
+  for (int j = 0; j < nd; ++j) t += fabs(Jd[(size_t)i + (size_t)j * m]);
+  for (int a = rp[i]; a < rp[i + 1]; ++a) t += fabs(v[a]);
+  out[i] = t;
+}
+
+__global__ void k_abs_jscol(int ns, const int32_t *__restrict__ cptr,
+                            const double *__restrict__ cval, double *__restrict__ out) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= ns) return;
+  double t = 0.0;
+  for (int e = cptr[k]; e < cptr[k + 1]; ++e) t += fabs(cval[e]);
+  out[k] = t;
+}
+
+inline unsigned red_grid(int64_t len) {
+  int64_t g = (len + RB - 1) / RB;
+  if (g < 1) g = 1;
+  if (g > kRedBlocks) g = kRedBlocks;
+  return (unsigned)g;
+}
+
+}  // namespace
+
+void ipm_init_point(hipStream_t s, int n, int m, const double *xl, const double *xu, double *x,
+                    double *y, double *zl, double *zu) {
+  const int len = n > m ? n : m;
+  if (len <= 0) return;
+  k_init_point<<<grid1(len, 256), 256, 0, s>>>(n, m, xl, xu, x, y, zl, zu);
+}
+
+void ipm_grad_finish(hipStream_t s, int nd, int ns, const double *c, const double *w,
+                     const double *g, const double *x, double *gf) {
+  if (nd + ns <= 0) return;
+  k_grad_finish<<<grid1(nd + ns, 256), 256, 0, s>>>(nd, ns, c, w, g, x, gf);
+}
+
+void ipm_sigma_rhs(hipStream_t s, int n, const double *x, const double *zl, const double *zu,
+                   const double *xl, const double *xu, const double *gf, const double *jty,
+                   double mu, double *sigma, double *rx) {
+  if (n <= 0) return;
+  k_sigma_rhs<<<grid1(n, 256), 256, 0, s>>>(n, x, zl, zu, xl, xu, gf, jty, mu, sigma, rx);
+}
+
+void ipm_constr_finish(hipStream_t s, int m, const double *b, double *cx, double *ry) {
+  if (m <= 0) return;
+  k_constr_finish<<<grid1(m, 256), 256, 0, s>>>(m, b, cx, ry);
+}
+
+void ipm_dsbase(hipStream_t s, int nd, int ns, const double *w, const double *sig, double *dsb) {
+  if (ns <= 0) return;
+  k_dsbase<<<grid1(ns, 256), 256, 0, s>>>(nd, ns, w, sig, dsb);
+}
+
+void ipm_dz(hipStream_t s, int n, const double *x, const double *zl, const double *zu,
+            const double *xl, const double *xu, const double *dx, double mu, double *dzl,
+            double *dzu) {
+  if (n <= 0) return;
+  k_dz<<<grid1(n, 256), 256, 0, s>>>(n, x, zl, zu, xl, xu, dx, mu, dzl, dzu);
+}
+
+void ipm_red_opt(hipStream_t s, int n, int m, const double *x, const double *y, const double *zl,
+                 const double *zu, const double *xl, const double *xu, const double *gf,
+                 const double *jty, const double *cx, double mu, double *red, double *out) {
+  const unsigned g = red_grid(n > m ? n : m);
+  k_red_opt<<<g, RB, 0, s>>>(n, m, x, y, zl, zu, xl, xu, gf, jty, cx, mu, red);
+  k_red_final<<<1, 64, 0, s>>>((int)g, red, out);
+}
+
+void ipm_red_merit(hipStream_t s, int nd, int ns, int m, const double *x, const double *hx,
+                   const double *c, const double *w, const double *g, const double *xl,
+                   const double *xu, const double *cx, double *red, double *out) {
+  const int n = nd + ns;
+  const unsigned gr = red_grid(n > m ? n : m);
+  k_red_merit<<<gr, RB, 0, s>>>(nd, ns, m, x, hx, c, w, g, xl, xu, cx, red);
+  k_red_final<<<1, 64, 0, s>>>((int)gr, red, out);
+}
+
+void ipm_red_gphi(hipStream_t s, int n, const double *gf, const double *x, const double *xl,
+                  const double *xu, const double *dx, double mu, double *red, double *out) {
+  const unsigned g = red_grid(n);
+  k_red_gphi<<<g, RB, 0, s>>>(n, gf, x, xl, xu, dx, mu, red);
+  k_red_final<<<1, 64, 0, s>>>((int)g, red, out);
+}
+
+void ipm_red_ftb(hipStream_t s, int n, const double *x, const double *xl, const double *xu,
+                 const double *dx, const double *zl, const double *zu, const double *dzl,
+                 const double *dzu, double tau, double *red, double *out) {
+  const unsigned g = red_grid(n);
+  k_red_ftb<<<g, RB, 0, s>>>(n, x, xl, xu, dx, zl, zu, dzl, dzu, tau, red);
+  k_red_final<<<1, 64, 0, s>>>((int)g, red, out);
+}
+
+void ipm_red_ftb1(hipStream_t s, int64_t n, const double *v, const double *dv, double tau,
+                  double *red, double *out) {
+  const unsigned g = red_grid(n);
+  k_red_ftb1<<<g, RB, 0, s>>>(n, v, dv, tau, red);
+  k_red_final<<<1, 64, 0, s>>>((int)g, red, out);
+}
+
+void ipm_red_amax3(hipStream_t s, int64_t na, const double *a, int64_t nb, const double *b,
+                   int64_t nc, const double *c, double *red, double *out) {
+  int64_t len = na > nb ? na : nb;
+  len = len > nc ? len : nc;
+  const unsigned g = red_grid(len);
+  k_red_amax3<<<g, RB, 0, s>>>(na, a, nb, b, nc, c, red);
+  k_red_final<<<1, 64, 0, s>>>((int)g, red, out);
+}
+
+void ipm_axpy_to(hipStream_t s, int n, const double *x, const double *dx, double a, double *out) {
+  if (n <= 0) return;
+  k_axpy_to<<<grid1(n, 256), 256, 0, s>>>(n, x, dx, a, out);
+}
+
+void ipm_accept(hipStream_t s, int n, int m, const double *xt, double *x, double *y,
+                const double *dy, double *zl, double *zu, const double *dzl, const double *dzu,
+                const double *xl, const double *xu, double alpha, double alpha_z, double mu) {
+  const int len = n > m ? n : m;
+  if (len <= 0) return;
+  k_accept<<<grid1(len, 256), 256, 0, s>>>(n, m, xt, x, y, dy, zl, zu, dzl, dzu, xl, xu, alpha,
+                                           alpha_z, mu);
+}
+
+void vec_copy(hipStream_t s, int64_t n, const double *src, double *dst) {
+  if (n <= 0) return;
+  k_copy_scaled<<<grid1(n, 256), 256, 0, s>>>(n, src, dst);
+}
+
+void vec_sub(hipStream_t s, int64_t n, const double *a, const double *b, double *out) {
+  if (n <= 0) return;
+  k_sub<<<grid1(n, 256), 256, 0, s>>>(n, a, b, out);
+}
+
+void vec_add_inplace(hipStream_t s, int64_t n, const double *a, double *out) {
+  if (n <= 0) return;
+  k_add_inplace<<<grid1(n, 256), 256, 0, s>>>(n, a, out);
+}
+
+void kkt_finish(hipStream_t s, int nd, int ns, int m, const double *sig, const double *dsb,
+                double dw, double dc, const double *dxd, const double *dxs, const double *dy,
+                double *od, double *os, double *oy) {
+  if (nd > 0) k_kkt_d<<<grid1(nd, 256), 256, 0, s>>>(nd, sig, dw, dxd, od);
+  if (ns > 0) k_kkt_s<<<grid1(ns, 256), 256, 0, s>>>(ns, dsb, dw, dxs, os);
+  if (m > 0) k_kkt_y<<<grid1(m, 256), 256, 0, s>>>(m, dc, dy, oy);
+}
+
+void kkt_norm_parts(hipStream_t s, int nd, int ns, int m, const double *H, const double *sig,
+                    double dw, const double *Jd, const int32_t *rp, const double *v,
+                    const int32_t *cptr, const double *cval, const double *dsb, double dc,
+                    double *hrow, double *jdcol, double *yrow, double *jscol, double *red,
+                    double *out) {
+  if (nd > 0) {
+    k_abs_hrow<<<grid1(nd, 256), 256, 0, s>>>(nd, H, sig, dw, hrow);
+    k_abs_jdcol<<<grid1(nd, 4), 256, 0, s>>>(m, nd, Jd, jdcol);
+  }
+  if (m > 0) k_abs_yrow<<<grid1(m, 256), 256, 0, s>>>(m, nd, Jd, rp, v, yrow);
+  if (ns > 0) k_abs_jscol<<<grid1(ns, 256), 256, 0, s>>>(ns, cptr, cval, jscol);
+  int64_t len = nd > ns ? nd : ns;
+  len = len > m ? len : m;
+  const unsigned g = red_grid(len);
+  k_red_knorm<<<g, RB, 0, s>>>(nd, ns, m, hrow, sig, dw, jdcol, dsb, jscol, yrow, dc, red);
+  k_red_final<<<1, 64, 0, s>>>((int)g, red, out);
+}
+
+}  // namespace mds

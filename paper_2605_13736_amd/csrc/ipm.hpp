@@ -1,0 +1,53 @@
+// Launchers of the IPM vector kernels (ipm.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace mds {
+
+void ipm_init_point(hipStream_t s, int n, int m, const double *xl, const double *xu, double *x,
+                    double *y, double *zl, double *zu);
+void ipm_grad_finish(hipStream_t s, int nd, int ns, const double *c, const double *w,
+                     const double *g, const double *x, double *gf);
+void ipm_sigma_rhs(hipStream_t s, int n, const double *x, const double *zl, const double *zu,
+                   const double *xl, const double *xu, const double *gf, const double *jty,
+                   double mu, double *sigma, double *rx);
+void ipm_constr_finish(hipStream_t s, int m, const double *b, double *cx, double *ry);
+void ipm_dsbase(hipStream_t s, int nd, int ns, const double *w, const double *sig, double *dsb);
+void ipm_dz(hipStream_t s, int n, const double *x, const double *zl, const double *zu,
+            const double *xl, const double *xu, const double *dx, double mu, double *dzl,
+            double *dzu);
+void ipm_red_opt(hipStream_t s, int n, int m, const double *x, const double *y, const double *zl,
+                 const double *zu, const double *xl, const double *xu, const double *gf,
+                 const double *jty, const double *cx, double mu, double *red, double *out);
+void ipm_red_merit(hipStream_t s, int nd, int ns, int m, const double *x, const double *hx,
+                   const double *c, const double *w, const double *g, const double *xl,
+                   const double *xu, const double *cx, double *red, double *out);
+void ipm_red_gphi(hipStream_t s, int n, const double *gf, const double *x, const double *xl,
+                  const double *xu, const double *dx, double mu, double *red, double *out);
+void ipm_red_ftb(hipStream_t s, int n, const double *x, const double *xl, const double *xu,
+                 const double *dx, const double *zl, const double *zu, const double *dzl,
+                 const double *dzu, double tau, double *red, double *out);
+void ipm_red_ftb1(hipStream_t s, int64_t n, const double *v, const double *dv, double tau,
+                  double *red, double *out);
+void ipm_red_amax3(hipStream_t s, int64_t na, const double *a, int64_t nb, const double *b,
+                   int64_t nc, const double *c, double *red, double *out);
+void ipm_axpy_to(hipStream_t s, int n, const double *x, const double *dx, double a, double *out);
+void ipm_accept(hipStream_t s, int n, int m, const double *xt, double *x, double *y,
+                const double *dy, double *zl, double *zu, const double *dzl, const double *dzu,
+                const double *xl, const double *xu, double alpha, double alpha_z, double mu);
+void vec_copy(hipStream_t s, int64_t n, const double *src, double *dst);
+void vec_sub(hipStream_t s, int64_t n, const double *a, const double *b, double *out);
+void vec_add_inplace(hipStream_t s, int64_t n, const double *a, double *out);
+void kkt_finish(hipStream_t s, int nd, int ns, int m, const double *sig, const double *dsb,
+                double dw, double dc, const double *dxd, const double *dxs, const double *dy,
+                double *od, double *os, double *oy);
+void kkt_norm_parts(hipStream_t s, int nd, int ns, int m, const double *H, const double *sig,
+                    double dw, const double *Jd, const int32_t *rp, const double *v,
+                    const int32_t *cptr, const double *cval, const double *dsb, double dc,
+                    double *hrow, double *jdcol, double *yrow, double *jscol, double *red,
+                    double *out);
+
+}  // namespace mds

@@ -1,0 +1,77 @@
+"""The C-ABI library loads and exports every function include/mdsipm.h declares
+(no GPU needed: no compute call is made), and the argument checks that run
+before any device work behave as documented."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+import paper_2605_13736_amd as mds
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mdsipm.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mds_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_declares_the_hot_path_calls():
+    names = declared_functions()
+    for required in ("mds_condense", "mds_factor_inertia", "mds_solve", "mds_refine",
+                     "mds_ipm_step", "mds_create", "mds_set_problem"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    L = mds.lib()
+    for name in declared_functions():
+        assert hasattr(L, name), name
+
+
+def test_binding_covers_every_declared_symbol():
+    assert set(declared_functions()) == set(mds.SIGNATURES)
+
+
+def test_workspace_bytes_and_invalid_dims():
+    L = mds.lib()
+    d = mds.Dims(64, 2000, 128, 512)
+    nb = L.mds_workspace_bytes(C.byref(d), None)
+    assert nb >= 8 * 192 * 192
+    assert L.mds_workspace_bytes(C.byref(mds.Dims(-1, 3, 3, 0)), None) == 0
+    # zero sizes are legal
+    assert L.mds_workspace_bytes(C.byref(mds.Dims(0, 0, 0, 0)), None) > 0
+
+
+def test_create_rejects_bad_arguments_before_device_work():
+    L = mds.lib()
+    h = C.c_void_p()
+    d = mds.Dims(4, 5, 3, 6)
+    assert L.mds_create(None, C.byref(d), None, None, None, 0) == -2        # ENULL
+    assert L.mds_create(C.byref(h), C.byref(mds.Dims(-1, 0, 0, 0)), None, None, None, 0) == -3
+    assert L.mds_create(C.byref(h), C.byref(d), None, None, None, 1 << 20) == -2
+    need = L.mds_workspace_bytes(C.byref(d), None)
+    buf = C.create_string_buffer(need + 512)
+    addr = (C.addressof(buf) + 255) & ~255
+    # too small / misaligned
+    assert L.mds_create(C.byref(h), C.byref(d), None, None, C.c_void_p(addr), need - 1) == -4
+    assert L.mds_create(C.byref(h), C.byref(d), None, None, C.c_void_p(addr + 8), need) == -4
+
+
+def test_status_strings():
+    L = mds.lib()
+    assert L.mds_status_string(0) == b"ok"
+    assert L.mds_status_string(4) == b"converged"
+    assert L.mds_status_string(-9) == b"invalid sparsity pattern"
+    assert L.mds_last_error(None) == b"null handle"
+
+
+def test_no_cpu_fallback_without_gpu():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("GPU present")
+    with pytest.raises(mds.MdsError):
+        mds.Solver(4, 5, 3, 6)
