@@ -76,7 +76,9 @@ typedef struct {
 
 typedef struct {
   int32_t nb;          /* panel width of the blocked factorization (0: default) */
-  int32_t reserved[7];
+  int32_t panel;       /* 0: automatic (register-resident panel when N <= 4096),
+                          1: panel kept in device memory                       */
+  int32_t reserved[6];
 } mds_options;
 
 /* Problem data, all device pointers, caller-owned, must stay valid and

@@ -36,7 +36,7 @@ class Dims(C.Structure):
 
 
 class Options(C.Structure):
-    _fields_ = [("nb", C.c_int32), ("reserved", C.c_int32 * 7)]
+    _fields_ = [("nb", C.c_int32), ("panel", C.c_int32), ("reserved", C.c_int32 * 6)]
 
 
 class Problem(C.Structure):
@@ -151,14 +151,14 @@ class Solver:
     """One library handle bound to a device, a stream and a workspace tensor."""
 
     def __init__(self, n_d: int, n_s: int, m: int, nnz_s: int, nb: int = 0,
-                 device: str = "cuda:0", stream=None):
+                 device: str = "cuda:0", stream=None, panel: str = "auto"):
         torch = _torch()
         if not torch.cuda.is_available():
             raise MdsError("no ROCm GPU visible: the mdsipm library has no CPU path")
         self.torch = torch
         self.device = torch.device(device)
         self.dims = Dims(n_d, n_s, m, nnz_s)
-        self.opts = Options(nb)
+        self.opts = Options(nb, 1 if panel == "mem" else 0)
         self.n_d, self.n_s, self.m = n_d, n_s, m
         self.N, self.n = n_d + m, n_d + n_s
         L = lib()
@@ -382,8 +382,9 @@ def _step_dict(s):
                 backtracks=s.backtracks, status=s.status)
 
 
-def solver_for(prob: dict, nb: int = 0, device: str = "cuda:0") -> Solver:
+def solver_for(prob: dict, nb: int = 0, device: str = "cuda:0", panel: str = "auto") -> Solver:
     """Create a Solver sized for a problem dict and attach the problem."""
-    s = Solver(prob["n_d"], prob["n_s"], prob["m"], len(prob["v"]), nb=nb, device=device)
+    s = Solver(prob["n_d"], prob["n_s"], prob["m"], len(prob["v"]), nb=nb, device=device,
+               panel=panel)
     s.set_problem(prob)
     return s

@@ -95,7 +95,7 @@ int default_nb(int N) { return (N >= 64) ? 16 : 8; }
 Layout make_layout(const mds_dims &d, int nb) {
   const size_t nd = d.n_d, ns = d.n_s, m = d.m, N = nd + m, n = nd + ns;
   const size_t nnz = (size_t)d.nnz_s;
-  const size_t maxp = N / (size_t)nb + 2;
+  const size_t maxp = N / (size_t)std::max(nb - 1, 1) + 2;
   size_t bytes[S_COUNT] = {};
   bytes[S_M] = 8 * N * N;
   bytes[S_W] = 8 * N * (size_t)(nb + 2);
@@ -140,10 +140,31 @@ bool dims_ok(const mds_dims *d) {
          d->nnz_s < ((int64_t)1 << 30);
 }
 
-int nb_of(const mds_dims &d, const mds_options *o) {
-  int nb = (o && o->nb > 0) ? o->nb : default_nb(d.n_d + d.m);
-  return std::min(std::max(nb, 2), kMaxNb);
+// Panel choice: the register-resident kernel for N <= 4096 (panel width up
+// to its register tile), else the kernel that keeps the panel in memory.
+struct PanelChoice {
+  bool reg;
+  int nb, adv;
+};
+
+PanelChoice panel_of(const mds_dims &d, const mds_options *o) {
+  const int N = d.n_d + d.m;
+  const bool force_mem = o && o->panel == 1;
+  const int rnb = bk_reg_nb(N);
+  PanelChoice c{};
+  if (rnb > 0 && !force_mem) {
+    int nb = (o && o->nb > 0) ? o->nb : rnb;
+    nb = std::min(std::max(nb, 2), rnb);
+    c = {true, nb, std::max(nb - 1, 1)};
+  } else {
+    int nb = (o && o->nb > 0) ? o->nb : default_nb(N);
+    nb = std::min(std::max(nb, 2), kMaxNb);
+    c = {false, nb, nb};
+  }
+  return c;
 }
+
+int nb_of(const mds_dims &d, const mds_options *o) { return panel_of(d, o).nb; }
 
 inline hipStream_t S(mds_handle *h) { return h->stream; }
 inline int ND(mds_handle *h) { return h->dims.n_d; }
@@ -172,16 +193,20 @@ int condense_impl(mds_handle *h, double dw, double dc) {
 int factor_impl(mds_handle *h, mds_inertia *out) {
   const int N = h->N;
   launch_fac_reset(S(h), h->w.fst, h->w.panel_k0);
-  const int slots = (N + h->nb - 1) / h->nb;
+  const int slots = (N + h->adv - 1) / h->adv;
   for (int b = 0; b < slots; ++b) {
     {
       TimedLaunch t(h, MDS_T_PANEL);
-      launch_bk_panel(S(h), N, h->nb, h->alpha_bk, h->w.M, h->w.W, h->w.dd, h->w.ds, h->w.ipiv,
-                      h->w.blk, h->w.fst, h->w.panel_k0);
+      if (h->panel_reg)
+        launch_bk_panel_reg(S(h), N, h->nb, h->alpha_bk, h->w.M, h->w.W, h->w.dd, h->w.ds,
+                            h->w.ipiv, h->w.blk, h->w.fst, h->w.panel_k0);
+      else
+        launch_bk_panel(S(h), N, h->nb, h->alpha_bk, h->w.M, h->w.W, h->w.dd, h->w.ds,
+                        h->w.ipiv, h->w.blk, h->w.fst, h->w.panel_k0);
     }
-    if ((long)N - (long)(b + 1) * h->nb > 0) {
+    if ((long)N - (long)(b + 1) * h->adv > 0) {
       TimedLaunch t(h, MDS_T_TRAILING);
-      launch_bk_trailing(S(h), N, h->nb, b, h->w.W, h->w.M, h->w.fst, h->w.panel_k0);
+      launch_bk_trailing(S(h), N, h->nb, h->adv, b, h->w.W, h->w.M, h->w.fst, h->w.panel_k0);
     }
   }
   HIPCHK(hipGetLastError());
@@ -471,8 +496,11 @@ int mds_create(mds_handle **out, const mds_dims *dims, const mds_options *opts, 
   h->dims = *dims;
   h->N = dims->n_d + dims->m;
   h->n = dims->n_d + dims->n_s;
+  const PanelChoice pc = panel_of(*dims, opts);
   h->nb = nb;
-  h->max_panels = h->N / nb + 2;
+  h->panel_reg = pc.reg;
+  h->adv = pc.adv;
+  h->max_panels = h->N / pc.adv + 2;
   h->ws_bytes = workspace_bytes;
   h->alpha_bk = (1.0 + std::sqrt(17.0)) / 8.0;
   char *base = (char *)workspace;

@@ -263,6 +263,7 @@ __global__ __launch_bounds__(NT) void k_bk_panel(int N, int nb, double alpha,
           x = W[(size_t)i + (size_t)j * ld];
         }
         M[(size_t)i + (size_t)k * ld] = (kind == 0) ? 0.0 : x / d;
+        if (kind == 0) W[(size_t)i + (size_t)j * ld] = 0.0;  // eliminates nothing
       }
       if (tid == 0) {
         if (kind == 3) {
@@ -396,11 +397,11 @@ void launch_bk_panel(hipStream_t s, int N, int nb, double alpha, double *M, doub
   k_bk_panel<<<1, NT, 0, s>>>(N, nb, alpha, M, W, dd, ds, ipiv, blk, st, panel_k0);
 }
 
-void launch_bk_trailing(hipStream_t s, int N, int nb, int slot, const double *W, double *M,
-                        const FacState *st, const int32_t *panel_k0) {
-  // every panel before this slot has at least nb columns, so the trailing
-  // matrix after slot `slot` has at most N - (slot+1)*nb rows
-  const long rem = (long)N - (long)(slot + 1) * nb;
+void launch_bk_trailing(hipStream_t s, int N, int nb, int adv, int slot, const double *W,
+                        double *M, const FacState *st, const int32_t *panel_k0) {
+  // every panel before this slot has at least adv columns, so the trailing
+  // matrix after slot `slot` has at most N - (slot+1)*adv rows
+  const long rem = (long)N - (long)(slot + 1) * adv;
   if (rem <= 0) return;
   const long nt = (rem + TT - 1) / TT;
   const long tiles = nt * (nt + 1) / 2;

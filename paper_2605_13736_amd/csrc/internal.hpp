@@ -58,6 +58,8 @@ struct mds_handle {
   hipStream_t stream = nullptr;
   mds_dims dims{};
   int N = 0, n = 0, nb = 16, max_panels = 0;
+  bool panel_reg = false;  // register-resident panel kernel
+  int adv = 16;            // least number of columns a panel factors
   mds::Work w{};
   size_t ws_bytes = 0;
   mds_problem P{};
@@ -107,8 +109,15 @@ void launch_fac_reset(hipStream_t s, FacState *st, int32_t *panel_k0);
 void launch_bk_panel(hipStream_t s, int N, int nb, double alpha, double *M, double *W,
                      double *dd, double *ds, int32_t *ipiv, int32_t *blk, FacState *st,
                      int32_t *panel_k0);
-void launch_bk_trailing(hipStream_t s, int N, int nb, int slot, const double *W, double *M,
-                        const FacState *st, const int32_t *panel_k0);
+void launch_bk_trailing(hipStream_t s, int N, int nb, int adv, int slot, const double *W,
+                        double *M, const FacState *st, const int32_t *panel_k0);
+
+// bk_reg.hip: register-resident panel for N <= 4096
+int bk_reg_rows(int N);
+int bk_reg_nb(int N);
+void launch_bk_panel_reg(hipStream_t s, int N, int nb, double alpha, double *M, double *W,
+                         double *dd, double *ds, int32_t *ipiv, int32_t *blk, FacState *st,
+                         int32_t *panel_k0);
 
 // solve.hip
 void launch_ldl_solve(hipStream_t s, int N, const double *M, const double *dd,

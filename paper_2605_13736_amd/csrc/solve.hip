@@ -27,6 +27,8 @@ __device__ inline double wave_sum(double v) {
   return v;
 }
 
+constexpr int kStage = 34;  // diagonal blocks up to this width are staged in LDS
+
 template <bool kLds>
 __global__ __launch_bounds__(NT) void k_ldl_solve(int N, const double *__restrict__ M,
                                                   const double *__restrict__ dd,
@@ -39,6 +41,7 @@ __global__ __launch_bounds__(NT) void k_ldl_solve(int N, const double *__restric
   extern __shared__ double s_dyn[];
   __shared__ double s_zc[kMaxNb + 2];
   __shared__ double s_part[kMaxNb + 2][NW];
+  __shared__ double s_L[kStage][kStage + 1];  // diagonal block of the panel, [row][col]
   __shared__ int s_piv[kMaxNb + 2], s_blk[kMaxNb + 2];
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const size_t ld = (size_t)N;
@@ -52,38 +55,61 @@ __global__ __launch_bounds__(NT) void k_ldl_solve(int N, const double *__restric
   // ---- forward --------------------------------------------------------------
   for (int b = 0; b < np; ++b) {
     const int k0 = panel_k0[b], k1 = panel_k0[b + 1], w = k1 - k0;
+    const bool staged = (w <= kStage);
     if (tid < w) {
       s_piv[tid] = ipiv[k0 + tid];
       s_blk[tid] = blk[k0 + tid];
     }
+    if (staged)
+      for (int e = tid; e < w * w; e += NT) {
+        const int r = e % w, c = e / w;
+        s_L[r][c] = (r > c) ? M[(size_t)(k0 + r) + (size_t)(k0 + c) * ld] : 0.0;
+      }
     __syncthreads();
-    if (tid == 0) {
-      for (int t = 0; t < w;) {
-        const int k = k0 + t;
-        if (s_blk[t] == 1) {
-          const int kp = s_piv[t] - 1;
-          if (kp != k) {
-            double x = z[k];
-            z[k] = z[kp];
-            z[kp] = x;
+    if (wid == 0) {
+      if (lane == 0) {
+        for (int t = 0; t < w;) {
+          const int k = k0 + t;
+          if (s_blk[t] == 1) {
+            const int kp = s_piv[t] - 1;
+            if (kp != k) {
+              const double x = z[k], y = z[kp];
+              z[k] = y;
+              z[kp] = x;
+            }
+            t += 1;
+          } else {
+            const int kp = -s_piv[t] - 1;
+            if (kp != k + 1) {
+              const double x = z[k + 1], y = z[kp];
+              z[k + 1] = y;
+              z[kp] = x;
+            }
+            t += 2;
           }
-          t += 1;
-        } else {
-          const int kp = -s_piv[t] - 1;
-          if (kp != k + 1) {
-            double x = z[k + 1];
-            z[k + 1] = z[kp];
-            z[kp] = x;
-          }
-          t += 2;
         }
       }
-      for (int c = 0; c < w; ++c) {
-        const double zc = z[k0 + c];
-        for (int i = c + 1; i < w; ++i)
-          z[k0 + i] = fma(-M[(size_t)(k0 + i) + (size_t)(k0 + c) * ld], zc, z[k0 + i]);
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      if (staged) {
+        // unit-lower triangle of the panel: lane t owns z[k0 + t]
+        double zt = (lane < w) ? z[k0 + lane] : 0.0;
+        for (int c = 0; c < w; ++c) {
+          const double zc = __shfl(zt, c);
+          if (lane > c && lane < w) zt = fma(-s_L[lane][c], zc, zt);
+        }
+        if (lane < w) {
+          z[k0 + lane] = zt;
+          s_zc[lane] = zt;
+        }
+      } else if (lane == 0) {
+        for (int c = 0; c < w; ++c) {
+          const double zc = z[k0 + c];
+          for (int i = c + 1; i < w; ++i)
+            z[k0 + i] = fma(-M[(size_t)(k0 + i) + (size_t)(k0 + c) * ld], zc, z[k0 + i]);
+        }
+        for (int c = 0; c < w; ++c) s_zc[c] = z[k0 + c];
       }
-      for (int c = 0; c < w; ++c) s_zc[c] = z[k0 + c];
     }
     __syncthreads();
     for (int i = k1 + tid; i < N; i += NT) {
@@ -112,6 +138,7 @@ __global__ __launch_bounds__(NT) void k_ldl_solve(int N, const double *__restric
   // ---- backward -------------------------------------------------------------
   for (int b = np - 1; b >= 0; --b) {
     const int k0 = panel_k0[b], k1 = panel_k0[b + 1], w = k1 - k0;
+    const bool staged = (w <= kStage);
     for (int t = 0; t < w; ++t) {
       double a = 0.0;
       for (int i = k1 + tid; i < N; i += NT) a = fma(M[(size_t)i + (size_t)(k0 + t) * ld], z[i], a);
@@ -122,41 +149,67 @@ __global__ __launch_bounds__(NT) void k_ldl_solve(int N, const double *__restric
       s_piv[tid] = ipiv[k0 + tid];
       s_blk[tid] = blk[k0 + tid];
     }
+    if (staged)
+      for (int e = tid; e < w * w; e += NT) {
+        const int r = e % w, c = e / w;
+        s_L[r][c] = (r > c) ? M[(size_t)(k0 + r) + (size_t)(k0 + c) * ld] : 0.0;
+      }
     __syncthreads();
-    if (tid == 0) {
-      for (int t = 0; t < w; ++t) {
-        double sdot = 0.0;
-        for (int q = 0; q < NW; ++q) sdot += s_part[t][q];
-        z[k0 + t] -= sdot;
+    if (wid == 0) {
+      if (staged) {
+        // z[k0:k1] -= dots, then the unit-upper triangle L11' backwards:
+        // lane t owns z[k0 + t]
+        double zt = 0.0;
+        if (lane < w) {
+          double sdot = 0.0;
+          for (int q = 0; q < NW; ++q) sdot += s_part[lane][q];
+          zt = z[k0 + lane] - sdot;
+        }
+        for (int c = w - 1; c >= 0; --c) {
+          // finalize x_c, then remove its contribution from the rows above
+          const double xc = __shfl(zt, c);
+          if (lane < c) zt = fma(-s_L[c][lane], xc, zt);
+        }
+        if (lane < w) z[k0 + lane] = zt;
+      } else if (lane == 0) {
+        for (int t = 0; t < w; ++t) {
+          double sdot = 0.0;
+          for (int q = 0; q < NW; ++q) sdot += s_part[t][q];
+          z[k0 + t] -= sdot;
+        }
+        for (int c = w - 1; c >= 0; --c) {
+          double a = z[k0 + c];
+          for (int i = c + 1; i < w; ++i)
+            a = fma(-M[(size_t)(k0 + i) + (size_t)(k0 + c) * ld], z[k0 + i], a);
+          z[k0 + c] = a;
+        }
       }
-      for (int c = w - 1; c >= 0; --c) {
-        double a = z[k0 + c];
-        for (int i = c + 1; i < w; ++i)
-          a = fma(-M[(size_t)(k0 + i) + (size_t)(k0 + c) * ld], z[k0 + i], a);
-        z[k0 + c] = a;
-      }
-      // undo this panel's interchanges in reverse order
-      int starts[kMaxNb + 2];
-      int ns = 0;
-      for (int t = 0; t < w;) {
-        starts[ns++] = t;
-        t += (s_blk[t] == 1) ? 1 : 2;
-      }
-      for (int e = ns - 1; e >= 0; --e) {
-        const int t = starts[e], k = k0 + t;
-        if (s_blk[t] == 1) {
-          const int kp = s_piv[t] - 1;
-          if (kp != k) {
-            double x = z[k];
-            z[k] = z[kp];
-            z[kp] = x;
-          }
-        } else {
-          const int kp = -s_piv[t] - 1;
-          if (kp != k + 1) {
-            double x = z[k + 1];
-            z[k + 1] = z[kp];
-            z[kp] = x;
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      if (lane == 0) {
+        // undo this panel's interchanges in reverse order
+        int starts[kMaxNb + 2];
+        int ns = 0;
+        for (int t = 0; t < w;) {
+          starts[ns++] = t;
+          t += (s_blk[t] == 1) ? 1 : 2;
+        }
+        for (int e = ns - 1; e >= 0; --e) {
+          const int t = starts[e], k = k0 + t;
+          if (s_blk[t] == 1) {
+            const int kp = s_piv[t] - 1;
+            if (kp != k) {
+              const double x = z[k], y = z[kp];
+              z[k] = y;
+              z[kp] = x;
+            }
+          } else {
+            const int kp = -s_piv[t] - 1;
+            if (kp != k + 1) {
+              const double x = z[k + 1], y = z[kp];
+              z[k + 1] = y;
+              z[kp] = x;
+            }
           }
         }
       }
