@@ -37,29 +37,25 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def panel_bytes_per_launch(N, nb, launches_per_factor):
+def panel_bytes_per_launch(N, launches_per_factor):
     """Algorithmic HBM bytes of one panel launch, averaged over a factorization:
-    each panel of width w reads its w columns of M once, writes L and W once,
-    and reads one pivot-candidate column per pivot (rows below k0):
-    about 4 * (N - k0) * w * 8 bytes; averaged over k0 this is 4 * (N/2) * nb * 8."""
-    total = 0.0
-    k0 = 0
-    while k0 < N:
-        w = min(nb, N - k0)
-        total += 4.0 * (N - k0) * w * 8.0
-        k0 += w
-    return total / max(launches_per_factor, 1)
+    a panel of width w starting at k0 reads its w columns (rows >= k0) once,
+    reads one pivot-candidate column per pivot, and writes L and W once:
+    4 * (N - k0) * w * 8 bytes.  Summed over the factorization this is
+    4 * 8 * N (N + 1) / 2 whatever the widths; divided by the launches."""
+    return 4.0 * 8.0 * N * (N + 1) / 2.0 / max(launches_per_factor, 1)
 
 
-def trailing_bytes_per_launch(N, nb):
-    """Algorithmic bytes of one trailing update: read and write the lower
-    trailing triangle, write its mirror, read the L and W panels."""
+def trailing_bytes_per_launch(N, w):
+    """Algorithmic bytes of one trailing update (panels of width w): read and
+    write the lower trailing triangle, write its mirror, read the L and W
+    panels."""
     total, cnt, k0 = 0.0, 0, 0
-    while k0 + nb < N:
-        n = N - (k0 + nb)
-        total += (n * (n + 1) / 2) * 8.0 * 3 + 2.0 * n * nb * 8.0
+    while k0 + w < N:
+        n = N - (k0 + w)
+        total += (n * (n + 1) / 2) * 8.0 * 3 + 2.0 * n * w * 8.0
         cnt += 1
-        k0 += nb
+        k0 += w
     return total / max(cnt, 1)
 
 
@@ -92,7 +88,19 @@ def main():
     ap.add_argument("--nb", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ipm-solves", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="only run a plain 256 MiB device copy (calibrates HBM counters)")
     args = ap.parse_args()
+    if args.calib_copy:
+        import torch
+        x = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"calib_copy_bytes_read": x.numel() * 8,
+                          "calib_copy_bytes_written": x.numel() * 8, "launches": 3}))
+        return
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
               "(the multi-GPU sharding is a design only)", file=sys.stderr)
@@ -109,7 +117,8 @@ def main():
     N = cfg["n_d"] + cfg["m"]
     log(f"workload N={N} n_s={cfg['n_s']} nnz={len(prob['v'])}")
     S = mds.solver_for(prob, nb=args.nb)
-    nb = S.opts.nb if S.opts.nb > 0 else (16 if N >= 64 else 8)
+    info0 = S.info()
+    nb = info0["nb"]
     it = S.new_iterate()
     S.ipm_init(it)
 
@@ -145,11 +154,11 @@ def main():
     nlaunch = max(tim[dom]["launches"], 1)
     avg_s = tim[dom]["ms"] / 1e3 / nlaunch
     if dom == "panel":
-        per_launch = panel_bytes_per_launch(N, nb, tim["panel"]["launches"] / max(facs, 1))
+        per_launch = panel_bytes_per_launch(N, tim["panel"]["launches"] / max(facs, 1))
         roof = dict(bound="hbm", achieved=per_launch / avg_s / 1e9, peak=HBM_PEAK_GBS,
                     unit="GB/s")
     elif dom == "trailing":
-        per_launch = trailing_bytes_per_launch(N, nb)
+        per_launch = trailing_bytes_per_launch(N, N / max(tim["panel"]["launches"] / max(facs, 1), 1))
         roof = dict(bound="hbm", achieved=per_launch / avg_s / 1e9, peak=HBM_PEAK_GBS,
                     unit="GB/s")
     elif dom == "solve":
@@ -163,7 +172,8 @@ def main():
                     unit="GB/s")
     roof["frac"] = roof["achieved"] / roof["peak"]
     roof["traffic"] = None
-    roof["kernel"] = {"panel": "k_bk_panel", "trailing": "k_bk_trailing",
+    roof["kernel"] = {"panel": "k_bk_panel_reg" if info0["panel"] == "reg" else "k_bk_panel",
+                      "trailing": "k_bk_trailing",
                       "solve": "k_ldl_solve", "condense": "k_condense_dense"}[dom]
     roof["avg_launch_us"] = avg_s * 1e6
     roof["bytes_per_launch"] = per_launch
@@ -177,7 +187,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"FP64 IPM Newton steps, n_d=1024 n_s=200000 m=3072 (N={N}), "
                                "J_s 6 nnz/row, seeded synthetic", "N": N, "nb": nb,
-                   "precision": "fp64"},
+                   "panel": info0["panel"], "precision": "fp64"},
         "roofline": roof,
         "factor": {"ms_per_factorization": fac_ms, "tflops": factor_tfs,
                    "frac_fp64_mfma_peak": factor_tfs / FP64_MFMA_PEAK_TFS,

@@ -260,6 +260,16 @@ int mds_get_factor(mds_handle *h, double *L_host, double *dd_host, double *ds_ho
 /* Copy D^{-1}_s (n_s) to host. */
 int mds_get_inv_ds(mds_handle *h, double *inv_d_host);
 
+/* Configuration chosen at mds_create (host). */
+typedef struct {
+  int32_t nb;           /* panel width limit                                  */
+  int32_t min_width;    /* fewest columns a panel factors (except the last)   */
+  int32_t panel;        /* 0: register-resident panel, 1: panel in memory    */
+  int32_t pad;
+  int64_t workspace_bytes;
+} mds_info;
+int mds_get_info(const mds_handle *h, mds_info *out_host);
+
 /* Enable (1) or disable (0) per-launch timing; enabling clears the totals. */
 int mds_set_timing(mds_handle *h, int enable);
 /* Synchronize the stream and return the accumulated totals. */

@@ -81,6 +81,11 @@ class StepInfo(C.Structure):
 T_CLASSES = ("condense", "panel", "trailing", "solve")
 
 
+class Info(C.Structure):
+    _fields_ = [("nb", C.c_int32), ("min_width", C.c_int32), ("panel", C.c_int32),
+                ("pad", C.c_int32), ("workspace_bytes", C.c_int64)]
+
+
 class Timings(C.Structure):
     _fields_ = [("ms", C.c_double * 4), ("launches", C.c_int64 * 4)]
 
@@ -108,6 +113,7 @@ SIGNATURES = {
     "mds_get_matrix": (C.c_int, [_vp, _dp]),
     "mds_get_factor": (C.c_int, [_vp, _dp, _dp, _dp, _ip]),
     "mds_get_inv_ds": (C.c_int, [_vp, _dp]),
+    "mds_get_info": (C.c_int, [_vp, C.POINTER(Info)]),
     "mds_set_timing": (C.c_int, [_vp, C.c_int]),
     "mds_get_timings": (C.c_int, [_vp, C.POINTER(Timings)]),
     "mds_status_string": (C.c_char_p, [C.c_int]),
@@ -334,6 +340,12 @@ class Solver:
         return dict(status=STATUS_NAMES.get(st, st), code=st, iters=iters.value,
                     trace=[_step_dict(tr[k]) for k in range(n)], x=it["x"], y=it["y"],
                     zl=it["zl"], zu=it["zu"], mu=it["c"].mu)
+
+    def info(self):
+        i = Info()
+        self._check(lib().mds_get_info(self.h, C.byref(i)), "mds_get_info")
+        return dict(nb=i.nb, min_width=i.min_width, panel="reg" if i.panel == 0 else "mem",
+                    workspace_bytes=i.workspace_bytes)
 
     # ---- timing ---------------------------------------------------------
     def set_timing(self, enable: bool):

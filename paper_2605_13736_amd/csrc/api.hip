@@ -80,7 +80,7 @@ int resolve_timings(mds_handle *h) {
 
 // Workspace slots, in carving order.
 enum Slot {
-  S_M, S_W, S_DD, S_DS, S_IPIV, S_BLK, S_PK0, S_FST, S_INVD, S_CPTR, S_CROW, S_CVAL, S_CFILL,
+  S_M, S_M2, S_SRC, S_W, S_DD, S_DS, S_IPIV, S_BLK, S_PK0, S_FST, S_INVD, S_CPTR, S_CROW, S_CVAL, S_CFILL,
   S_FLAGS, S_RED, S_SCAL, S_Z, S_SIG, S_RX, S_RY, S_DSB, S_DX, S_DY, S_DZL, S_DZU, S_XT, S_RES,
   S_COR, S_PREV, S_KX, S_TN, S_TM, S_TN2, S_KNH, S_KNJD, S_KNY, S_KNJS, S_COUNT
 };
@@ -92,12 +92,14 @@ struct Layout {
 
 int default_nb(int N) { return (N >= 64) ? 16 : 8; }
 
-Layout make_layout(const mds_dims &d, int nb) {
+Layout make_layout(const mds_dims &d, int nb, bool pingpong) {
   const size_t nd = d.n_d, ns = d.n_s, m = d.m, N = nd + m, n = nd + ns;
   const size_t nnz = (size_t)d.nnz_s;
   const size_t maxp = N / (size_t)std::max(nb - 1, 1) + 2;
   size_t bytes[S_COUNT] = {};
   bytes[S_M] = 8 * N * N;
+  bytes[S_M2] = pingpong ? 8 * N * N : 0;
+  bytes[S_SRC] = 4 * N;
   bytes[S_W] = 8 * N * (size_t)(nb + 2);
   bytes[S_DD] = bytes[S_DS] = 8 * N;
   bytes[S_IPIV] = bytes[S_BLK] = 4 * N;
@@ -195,18 +197,24 @@ int factor_impl(mds_handle *h, mds_inertia *out) {
   launch_fac_reset(S(h), h->w.fst, h->w.panel_k0);
   const int slots = (N + h->adv - 1) / h->adv;
   for (int b = 0; b < slots; ++b) {
+    // register panel: slot b reads buffer b%2 and writes its L and the
+    // updated trailing matrix into the other buffer
+    double *X = h->w.M, *Y = h->w.M;
+    if (h->panel_reg && (b & 1)) X = h->w.M2;
+    if (h->panel_reg && !(b & 1)) Y = h->w.M2;
     {
       TimedLaunch t(h, MDS_T_PANEL);
       if (h->panel_reg)
-        launch_bk_panel_reg(S(h), N, h->nb, h->alpha_bk, h->w.M, h->w.W, h->w.dd, h->w.ds,
-                            h->w.ipiv, h->w.blk, h->w.fst, h->w.panel_k0);
+        launch_bk_panel_reg(S(h), N, h->nb, h->alpha_bk, X, Y, h->w.src, h->w.W, h->w.dd,
+                            h->w.ds, h->w.ipiv, h->w.blk, h->w.fst, h->w.panel_k0);
       else
         launch_bk_panel(S(h), N, h->nb, h->alpha_bk, h->w.M, h->w.W, h->w.dd, h->w.ds,
                         h->w.ipiv, h->w.blk, h->w.fst, h->w.panel_k0);
     }
     if ((long)N - (long)(b + 1) * h->adv > 0) {
       TimedLaunch t(h, MDS_T_TRAILING);
-      launch_bk_trailing(S(h), N, h->nb, h->adv, b, h->w.W, h->w.M, h->w.fst, h->w.panel_k0);
+      launch_bk_trailing(S(h), N, h->nb, h->adv, b, h->w.W, X, Y, Y,
+                         h->panel_reg ? h->w.src : nullptr, h->w.fst, h->w.panel_k0);
     }
   }
   HIPCHK(hipGetLastError());
@@ -271,8 +279,8 @@ int solve_impl(mds_handle *h, const double *r_d, const double *r_s, const double
                       h->w.z + nd);
   {
     TimedLaunch t(h, MDS_T_SOLVE);
-    launch_ldl_solve(S(h), N, h->w.M, h->w.dd, h->w.ds, h->w.ipiv, h->w.blk, h->w.panel_k0,
-                     h->w.fst, h->w.z);
+    launch_ldl_solve(S(h), N, h->w.M, h->w.M2, h->panel_reg ? 1 : 0, h->w.dd, h->w.ds,
+                     h->w.ipiv, h->w.blk, h->w.panel_k0, h->w.fst, h->w.z);
   }
   h->nsolves++;
   if (nd > 0) HIPCHK(hipMemcpyAsync(dx_d, h->w.z, 8 * (size_t)nd, hipMemcpyDeviceToDevice, S(h)));
@@ -474,7 +482,8 @@ extern "C" {
 
 size_t mds_workspace_bytes(const mds_dims *dims, const mds_options *opts) {
   if (!dims_ok(dims)) return 0;
-  return make_layout(*dims, nb_of(*dims, opts)).total;
+  const PanelChoice pc = panel_of(*dims, opts);
+  return make_layout(*dims, pc.nb, pc.reg).total;
 }
 
 int mds_create(mds_handle **out, const mds_dims *dims, const mds_options *opts, void *stream,
@@ -483,7 +492,7 @@ int mds_create(mds_handle **out, const mds_dims *dims, const mds_options *opts, 
   *out = nullptr;
   if (!dims_ok(dims)) return MDS_EDIMS;
   const int nb = nb_of(*dims, opts);
-  const Layout L = make_layout(*dims, nb);
+  const Layout L = make_layout(*dims, nb, panel_of(*dims, opts).reg);
   if (!workspace) return MDS_ENULL;
   if (workspace_bytes < L.total || ((uintptr_t)workspace & 255) != 0) return MDS_EWORKSPACE;
   mds_handle *h = new (std::nothrow) mds_handle();
@@ -508,6 +517,8 @@ int mds_create(mds_handle **out, const mds_dims *dims, const mds_options *opts, 
   auto I = [&](int s) { return (int32_t *)(base + L.off[s]); };
   Work &w = h->w;
   w.M = D(S_M);
+  w.M2 = D(S_M2);
+  w.src = I(S_SRC);
   w.W = D(S_W);
   w.dd = D(S_DD);
   w.ds = D(S_DS);
@@ -862,10 +873,22 @@ int mds_get_factor(mds_handle *h, double *L_host, double *dd_host, double *ds_ho
   HIPCHK(hipMemcpyAsync(pk0.data(), h->w.panel_k0, 4 * pk0.size(), hipMemcpyDeviceToHost, S(h)));
   if (dd_host) HIPCHK(hipMemcpyAsync(dd_host, h->w.dd, 8 * (size_t)N, hipMemcpyDeviceToHost, S(h)));
   if (ds_host) HIPCHK(hipMemcpyAsync(ds_host, h->w.ds, 8 * (size_t)N, hipMemcpyDeviceToHost, S(h)));
-  if (L_host) HIPCHK(hipMemcpyAsync(L_host, h->w.M, 8 * (size_t)N * N, hipMemcpyDeviceToHost, S(h)));
+  std::vector<double> L2;
+  if (L_host) {
+    HIPCHK(hipMemcpyAsync(L_host, h->w.M, 8 * (size_t)N * N, hipMemcpyDeviceToHost, S(h)));
+    if (h->panel_reg) {
+      L2.resize((size_t)N * N);
+      HIPCHK(hipMemcpyAsync(L2.data(), h->w.M2, 8 * (size_t)N * N, hipMemcpyDeviceToHost, S(h)));
+    }
+  }
   HIPCHK(hipStreamSynchronize(S(h)));
   if (ipiv_host) memcpy(ipiv_host, ipiv.data(), 4 * (size_t)N);
   if (!L_host) return MDS_OK;
+  // register panel: even panels wrote their multipliers to the second buffer
+  if (h->panel_reg)
+    for (int b = 0; b < st.npanel; b += 2)
+      for (int c = pk0[b]; c < pk0[b + 1]; ++c)
+        memcpy(&L_host[(size_t)c * N], &L2[(size_t)c * N], 8 * (size_t)N);
   // keep the strictly lower part only
   for (int c = 0; c < N; ++c)
     for (int i = 0; i <= c; ++i) L_host[(size_t)i + (size_t)c * N] = 0.0;
@@ -896,6 +919,16 @@ int mds_get_inv_ds(mds_handle *h, double *inv_d_host) {
   if (!h || !inv_d_host) return MDS_ENULL;
   HIPCHK(hipMemcpyAsync(inv_d_host, h->w.inv_d, 8 * (size_t)NS(h), hipMemcpyDeviceToHost, S(h)));
   HIPCHK(hipStreamSynchronize(S(h)));
+  return MDS_OK;
+}
+
+int mds_get_info(const mds_handle *h, mds_info *out) {
+  if (!h || !out) return MDS_ENULL;
+  out->nb = h->nb;
+  out->min_width = h->adv;
+  out->panel = h->panel_reg ? 0 : 1;
+  out->pad = 0;
+  out->workspace_bytes = (int64_t)h->ws_bytes;
   return MDS_OK;
 }
 

@@ -27,7 +27,9 @@
 //
 // Trailing update: M22 -= L21 W21' over the lower tiles of the trailing
 // matrix with FP64 MFMA (v_mfma_f64_16x16x4), each result mirrored into the
-// upper triangle.
+// upper triangle.  With the register-resident panel (bk_reg.hip) the update
+// also applies the panel's interchanges: it reads the un-updated entry
+// through the panel's index map from one buffer and writes the other.
 #include <climits>
 
 #include "internal.hpp"
@@ -309,8 +311,12 @@ __global__ __launch_bounds__(NT) void k_bk_panel(int N, int nb, double alpha,
 // register r of lane l holds D[l/16 + 4r][l%16].
 constexpr int TT = 64;
 
+// X: matrix the panel read (entry (x, c) at X[src(x) + src(c) N]); Y: output
+// buffer (may equal X when src is null); Lsrc: buffer holding the panel's L.
 __global__ __launch_bounds__(256) void k_bk_trailing(int N, int nb, const double *__restrict__ W,
-                                                     double *__restrict__ M,
+                                                     const double *X, double *Y,
+                                                     const double *Lsrc,
+                                                     const int32_t *__restrict__ src,
                                                      const FacState *__restrict__ st,
                                                      const int32_t *__restrict__ panel_k0,
                                                      int slot) {
@@ -351,7 +357,7 @@ __global__ __launch_bounds__(256) void k_bk_trailing(int N, int nb, const double
 #pragma unroll
     for (int b = 0; b < 2; ++b) {
       const int i = wi + b * 16 + l16;
-      bv[b] = (t < jw && i < N) ? M[(size_t)i + (size_t)(k0 + t) * ld] : 0.0;
+      bv[b] = (t < jw && i < N) ? Lsrc[(size_t)i + (size_t)(k0 + t) * ld] : 0.0;
     }
 #pragma unroll
     for (int a = 0; a < 2; ++a)
@@ -370,9 +376,9 @@ __global__ __launch_bounds__(256) void k_bk_trailing(int N, int nb, const double
         const int c = wc + a * 16 + l4 + 4 * r;
         const int i = wi + b * 16 + l16;
         if (c < N && i < N && (!diag || i >= c)) {
-          const size_t pos = (size_t)i + (size_t)c * ld;
-          const double v = M[pos] - acc[a][b][r];
-          M[pos] = v;
+          const int si = src ? src[i] : i, sc = src ? src[c] : c;
+          const double v = X[(size_t)si + (size_t)sc * ld] - acc[a][b][r];
+          Y[(size_t)i + (size_t)c * ld] = v;
           s_t[c - c0][i - i0] = v;
         }
       }
@@ -381,7 +387,7 @@ __global__ __launch_bounds__(256) void k_bk_trailing(int N, int nb, const double
   for (int e = tid; e < TT * TT; e += 256) {
     const int cl = e & (TT - 1), il = e >> 6;
     const int c = c0 + cl, i = i0 + il;
-    if (c < N && i < N && i > c && (!diag || il >= cl)) M[(size_t)c + (size_t)i * ld] = s_t[cl][il];
+    if (c < N && i < N && i > c && (!diag || il >= cl)) Y[(size_t)c + (size_t)i * ld] = s_t[cl][il];
   }
 }
 
@@ -398,14 +404,15 @@ void launch_bk_panel(hipStream_t s, int N, int nb, double alpha, double *M, doub
 }
 
 void launch_bk_trailing(hipStream_t s, int N, int nb, int adv, int slot, const double *W,
-                        double *M, const FacState *st, const int32_t *panel_k0) {
+                        const double *X, double *Y, const double *Lsrc, const int32_t *src,
+                        const FacState *st, const int32_t *panel_k0) {
   // every panel before this slot has at least adv columns, so the trailing
   // matrix after slot `slot` has at most N - (slot+1)*adv rows
   const long rem = (long)N - (long)(slot + 1) * adv;
   if (rem <= 0) return;
   const long nt = (rem + TT - 1) / TT;
   const long tiles = nt * (nt + 1) / 2;
-  k_bk_trailing<<<(unsigned)tiles, 256, 0, s>>>(N, nb, W, M, st, panel_k0, slot);
+  k_bk_trailing<<<(unsigned)tiles, 256, 0, s>>>(N, nb, W, X, Y, Lsrc, src, st, panel_k0, slot);
 }
 
 }  // namespace mds

@@ -88,7 +88,9 @@ __device__ inline void w_row_global(const double (&L)[NB], const double *sD0, co
 
 template <int T, int R, int NB>
 __global__ __launch_bounds__(T) void k_bk_panel_reg(int N, int nb, double alpha,
-                                                    double *__restrict__ M,
+                                                    const double *__restrict__ X,
+                                                    double *__restrict__ Lout,
+                                                    int32_t *__restrict__ src_out,
                                                     double *__restrict__ W,
                                                     double *__restrict__ dd,
                                                     double *__restrict__ ds,
@@ -129,26 +131,36 @@ __global__ __launch_bounds__(T) void k_bk_panel_reg(int N, int nb, double alpha,
   __shared__ double s_wic[R * T];
   // updated pivot column w_k for the owned rows (LDS)
   __shared__ double s_wkc[R * T];
+  // logical -> physical index map of the active part: the logical entry (x, c)
+  // of the matrix is X[src(x) + src(c) * N].  Interchanges only update the map.
+  __shared__ int s_map[T * R];
   double Lr[R][NB];
   double pre1[R], pre2[R];
+  int srcr[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
 #pragma unroll
     for (int t = 0; t < NB; ++t) Lr[r][t] = 0.0;
     const int i = k0 + tid + T * r;
-    s_acur[r * T + tid] = (i < N) ? M[i + k0 * ld] : 0.0;
+    srcr[r] = i;
+    s_map[r * T + tid] = i;
+    s_acur[r * T + tid] = (i < N) ? X[i + k0 * ld] : 0.0;
     pre1[r] = pre2[r] = 0.0;
   }
+  __syncthreads();
 
   int k = k0, j = 0;
   int c_pos = 0, c_zero = 0, c_neg = 0, c_2x2 = 0, first_zero = 0;
 
   while (j < nb - 1 && k < N) {
     // ---- prefetch the un-updated candidate next column k+1 ------------------
+    {
+      const int sc1 = (k + 1 < N) ? s_map[k + 1 - k0] : 0;
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const int i = k0 + tid + T * r;
-      pre1[r] = (i > k && i < N) ? M[i + (k + 1) * ld] : 0.0;
+      for (int r = 0; r < R; ++r) {
+        const int i = k0 + tid + T * r;
+        pre1[r] = (i > k && i < N) ? X[srcr[r] + sc1 * ld] : 0.0;
+      }
     }
     // ---- updated column k and its largest off-diagonal magnitude -----------
     double bv = -1.0;
@@ -202,6 +214,12 @@ __global__ __launch_bounds__(T) void k_bk_panel_reg(int N, int nb, double alpha,
       imax = k;
     }
     const double akk = s_akk, absakk = fabs(akk);
+    // physical indices of the rows that may move this step (read before any
+    // thread updates the map)
+    const int src_k = s_map[k - k0];
+    const int src_k1 = (k + 1 < N) ? s_map[k + 1 - k0] : 0;
+    const int src_k2 = (k + 2 < N) ? s_map[k + 2 - k0] : 0;
+    const int src_i = s_map[imax - k0];
 
     // ---- Bunch-Kaufman decision ----------------------------------------------
     int kind;  // 0 zero, 1 1x1, 2 1x1 (second test), 3 1x1 swap, 4 2x2
@@ -223,7 +241,7 @@ __global__ __launch_bounds__(T) void k_bk_panel_reg(int N, int nb, double alpha,
           s_x[3] = s_wkc[r * T + tid];
         }
         if (i == k + 2) s_x[7] = pre1[r];
-        s_wic[r * T + tid] = (i >= k && i < N) ? M[i + imax * ld] : 0.0;
+        s_wic[r * T + tid] = (i >= k && i < N) ? X[srcr[r] + src_i * ld] : 0.0;
       }
       __syncthreads();
       double rv = 0.0;
@@ -261,13 +279,12 @@ __global__ __launch_bounds__(T) void k_bk_panel_reg(int N, int nb, double alpha,
         kind = 4;
         q = imax;
         kstep = 2;
-        // next column is k+2: load its un-updated values now.  Entries this
-        // step's interchange overwrites are replaced by the patch below, so
-        // racing with those writes is harmless.
+        // next column is k+2: load its un-updated values now (the patch below
+        // replaces the entries this step's interchange changes)
 #pragma unroll
         for (int r = 0; r < R; ++r) {
           const int i = k0 + tid + T * r;
-          pre2[r] = (i > k + 1 && i < N) ? M[i + (k + 2) * ld] : 0.0;
+          pre2[r] = (i > k + 1 && i < N) ? X[srcr[r] + src_k2 * ld] : 0.0;
         }
       }
     }
@@ -303,6 +320,8 @@ row_barrier();
 #pragma unroll
           for (int t = 0; t < NB; ++t)
             if (t < j) Lr[r][t] = s_Li[t];
+          srcr[r] = src_i;
+          s_map[k - k0] = src_i;
         } else {
           const double c = (i == q) ? s_x[1] : s_wic[r * T + tid];
           if (i == q) {
@@ -310,11 +329,8 @@ row_barrier();
 #pragma unroll
             for (int t = 0; t < NB; ++t)
               if (t < j) Lr[r][t] = s_Lk[t];
-            M[q + q * ld] = s_x[5];
-          } else {
-            const double a0 = s_acur[r * T + tid];
-            M[i + q * ld] = a0;
-            M[q + i * ld] = a0;
+            srcr[r] = src_k;
+            s_map[q - k0] = src_k;
           }
           const double l = c / aii;
 #pragma unroll
@@ -328,6 +344,8 @@ row_barrier();
 #pragma unroll
             for (int t = 0; t < NB; ++t)
               if (t < j) Lr[r][t] = s_Li[t];
+            srcr[r] = src_i;
+            s_map[k + 1 - k0] = src_i;
           }
         } else if (i >= k + 2) {
           const bool isq = sw && (i == q);
@@ -338,11 +356,8 @@ row_barrier();
 #pragma unroll
             for (int t = 0; t < NB; ++t)
               if (t < j) Lr[r][t] = s_Lk1[t];
-            M[q + q * ld] = s_x[4];
-          } else if (sw) {
-            const double a0 = pre1[r];
-            M[i + q * ld] = a0;
-            M[q + i * ld] = a0;
+            srcr[r] = src_k1;
+            s_map[q - k0] = src_k1;
           }
           const double l0 = (x0 * Dc - y0 * Db) / det;
           const double l1 = (y0 * Da - x0 * Db) / det;
@@ -419,8 +434,11 @@ row_barrier();
     if (i >= N) continue;
 #pragma unroll
     for (int t = 0; t < NB; ++t)
-      if (t < jend && i > k0 + t) M[i + (k0 + t) * ld] = Lr[r][t];
-    if (i >= kend) w_row_global<NB>(Lr[r], s_D0, s_D1, s_B, jend, W + i, ld);
+      if (t < jend && i > k0 + t) Lout[i + (k0 + t) * ld] = Lr[r][t];
+    if (i >= kend) {
+      w_row_global<NB>(Lr[r], s_D0, s_D1, s_B, jend, W + i, ld);
+      src_out[i] = srcr[r];
+    }
   }
   if (tid == 0) {
     const int b = st->npanel;
@@ -456,12 +474,12 @@ int bk_reg_nb(int N) {
   }
 }
 
-void launch_bk_panel_reg(hipStream_t s, int N, int nb, double alpha, double *M, double *W,
-                         double *dd, double *ds, int32_t *ipiv, int32_t *blk, FacState *st,
-                         int32_t *panel_k0) {
-#define MDS_PANEL_REG(R_, NB_)                                                            \
-  k_bk_panel_reg<TMAX, R_, NB_><<<1, TMAX, 0, s>>>(N, nb, alpha, M, W, dd, ds, ipiv, blk, st, \
-                                                   panel_k0)
+void launch_bk_panel_reg(hipStream_t s, int N, int nb, double alpha, const double *X,
+                         double *Lout, int32_t *src_out, double *W, double *dd, double *ds,
+                         int32_t *ipiv, int32_t *blk, FacState *st, int32_t *panel_k0) {
+#define MDS_PANEL_REG(R_, NB_)                                                         \
+  k_bk_panel_reg<TMAX, R_, NB_><<<1, TMAX, 0, s>>>(N, nb, alpha, X, Lout, src_out, W, dd, ds, \
+                                                   ipiv, blk, st, panel_k0)
   switch (bk_reg_rows(N)) {
     case 1: MDS_PANEL_REG(1, 32); break;
     case 2: MDS_PANEL_REG(2, 32); break;

@@ -28,6 +28,8 @@ struct FacState {
 // Pointers into the caller's workspace.
 struct Work {
   double *M;          // N x N, full symmetric, column-major; L after factoring
+  double *M2;         // second N x N buffer (register panel: ping-pong + L of even panels)
+  int32_t *src;       // N: logical -> physical index map of the last panel
   double *W;          // N x (nb + 2) panel workspace (updated columns)
   double *dd, *ds;    // D diagonal / sub-diagonal (N)
   int32_t *ipiv;      // LAPACK-style pivots (N)
@@ -77,8 +79,8 @@ struct mds_handle {
   int64_t nsolves = 0;  // LDL' solves performed (statistics)
   std::vector<hipEvent_t> ev_pool;
   std::vector<std::pair<int, std::pair<int, int>>> ev_marks;  // class, (start, stop)
-  double t_ms[MDS_T_CLASSES] = {0, 0, 0, 0};
-  int64_t t_n[MDS_T_CLASSES] = {0, 0, 0, 0};
+  double t_ms[MDS_T_CLASSES] = {};
+  int64_t t_n[MDS_T_CLASSES] = {};
   char err[512] = {0};
 };
 
@@ -110,19 +112,22 @@ void launch_bk_panel(hipStream_t s, int N, int nb, double alpha, double *M, doub
                      double *dd, double *ds, int32_t *ipiv, int32_t *blk, FacState *st,
                      int32_t *panel_k0);
 void launch_bk_trailing(hipStream_t s, int N, int nb, int adv, int slot, const double *W,
-                        double *M, const FacState *st, const int32_t *panel_k0);
+                        const double *X, double *Y, const double *Lsrc, const int32_t *src,
+                        const FacState *st, const int32_t *panel_k0);
 
 // bk_reg.hip: register-resident panel for N <= 4096
 int bk_reg_rows(int N);
 int bk_reg_nb(int N);
-void launch_bk_panel_reg(hipStream_t s, int N, int nb, double alpha, double *M, double *W,
-                         double *dd, double *ds, int32_t *ipiv, int32_t *blk, FacState *st,
-                         int32_t *panel_k0);
+void launch_bk_panel_reg(hipStream_t s, int N, int nb, double alpha, const double *X,
+                         double *Lout, int32_t *src_out, double *W, double *dd, double *ds,
+                         int32_t *ipiv, int32_t *blk, FacState *st, int32_t *panel_k0);
 
 // solve.hip
-void launch_ldl_solve(hipStream_t s, int N, const double *M, const double *dd,
-                      const double *ds, const int32_t *ipiv, const int32_t *blk,
-                      const int32_t *panel_k0, const FacState *st, double *z);
+// L of panel b lives in M1 when pingpong and b is even, else in M0
+void launch_ldl_solve(hipStream_t s, int N, const double *M0, const double *M1, int pingpong,
+                      const double *dd, const double *ds, const int32_t *ipiv,
+                      const int32_t *blk, const int32_t *panel_k0, const FacState *st,
+                      double *z);
 
 // vec.hip
 void launch_gemv_n(hipStream_t s, int rows, int cols, const double *A, int lda,

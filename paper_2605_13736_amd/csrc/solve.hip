@@ -30,7 +30,8 @@ __device__ inline double wave_sum(double v) {
 constexpr int kStage = 34;  // diagonal blocks up to this width are staged in LDS
 
 template <bool kLds>
-__global__ __launch_bounds__(NT) void k_ldl_solve(int N, const double *__restrict__ M,
+__global__ __launch_bounds__(NT) void k_ldl_solve(int N, const double *__restrict__ M0,
+                                                  const double *__restrict__ M1, int pingpong,
                                                   const double *__restrict__ dd,
                                                   const double *__restrict__ ds,
                                                   const int32_t *__restrict__ ipiv,
@@ -55,6 +56,7 @@ __global__ __launch_bounds__(NT) void k_ldl_solve(int N, const double *__restric
   // ---- forward --------------------------------------------------------------
   for (int b = 0; b < np; ++b) {
     const int k0 = panel_k0[b], k1 = panel_k0[b + 1], w = k1 - k0;
+    const double *__restrict__ M = (pingpong && (b & 1) == 0) ? M1 : M0;
     const bool staged = (w <= kStage);
     if (tid < w) {
       s_piv[tid] = ipiv[k0 + tid];
@@ -138,6 +140,7 @@ __global__ __launch_bounds__(NT) void k_ldl_solve(int N, const double *__restric
   // ---- backward -------------------------------------------------------------
   for (int b = np - 1; b >= 0; --b) {
     const int k0 = panel_k0[b], k1 = panel_k0[b + 1], w = k1 - k0;
+    const double *__restrict__ M = (pingpong && (b & 1) == 0) ? M1 : M0;
     const bool staged = (w <= kStage);
     for (int t = 0; t < w; ++t) {
       double a = 0.0;
@@ -223,15 +226,17 @@ __global__ __launch_bounds__(NT) void k_ldl_solve(int N, const double *__restric
 
 }  // namespace
 
-void launch_ldl_solve(hipStream_t s, int N, const double *M, const double *dd,
-                      const double *ds, const int32_t *ipiv, const int32_t *blk,
-                      const int32_t *panel_k0, const FacState *st, double *z) {
+void launch_ldl_solve(hipStream_t s, int N, const double *M0, const double *M1, int pingpong,
+                      const double *dd, const double *ds, const int32_t *ipiv,
+                      const int32_t *blk, const int32_t *panel_k0, const FacState *st,
+                      double *z) {
   if (N <= 0) return;
   if (N <= kLdsMaxN) {
-    k_ldl_solve<true><<<1, NT, sizeof(double) * (size_t)N, s>>>(N, M, dd, ds, ipiv, blk,
-                                                                  panel_k0, st, z);
+    k_ldl_solve<true><<<1, NT, sizeof(double) * (size_t)N, s>>>(N, M0, M1, pingpong, dd, ds,
+                                                                  ipiv, blk, panel_k0, st, z);
   } else {
-    k_ldl_solve<false><<<1, NT, 0, s>>>(N, M, dd, ds, ipiv, blk, panel_k0, st, z);
+    k_ldl_solve<false><<<1, NT, 0, s>>>(N, M0, M1, pingpong, dd, ds, ipiv, blk, panel_k0, st,
+                                        z);
   }
 }
 
