@@ -70,7 +70,7 @@ enum {
 };
 
 typedef struct {
-  int32_t n_d, n_s, m; /* N = n_d + m is the condensed size */
+  int32_t n_d, n_s, m; /* N = n_d + m is the condensed size, N <= 20480 */
   int64_t nnz_s;       /* nonzeros of J_s */
 } mds_dims;
 
@@ -146,9 +146,11 @@ typedef struct {       /* one IPM iteration (host) */
 } mds_step_info;
 
 /* Per-kernel-class device time, accumulated while timing is enabled
- * (hipEvents recorded around each launch on the handle's stream). */
+ * (hipEvents recorded around each launch on the handle's stream).  PERMUTE is
+ * the conversion of a new factor to standard form before its first solve;
+ * SOLVE is one triangular-solve sequence (permute, L, D, L', permute). */
 enum { MDS_T_CONDENSE = 0, MDS_T_PANEL = 1, MDS_T_TRAILING = 2, MDS_T_SOLVE = 3,
-       MDS_T_CLASSES = 4 };
+       MDS_T_PERMUTE = 4, MDS_T_CLASSES = 5 };
 typedef struct {
   double ms[MDS_T_CLASSES];     /* summed kernel time per class            */
   int64_t launches[MDS_T_CLASSES];
@@ -194,8 +196,10 @@ int mds_factor_inertia(mds_handle *h, mds_reg *reg, double mu, mds_inertia *out_
 
 /* Solve the factored Newton system for one right-hand side: condense the rhs
  * (r_hat = r_y - J_s D_s^{-1} r_s), LDL' solve for [dx_d; dy], back-substitute
- * dx_s = D_s^{-1} (r_s - J_s' dy).  Inputs and outputs are device arrays and
- * must not alias.  Async. */
+ * dx_s = D_s^{-1} (r_s - J_s' dy).  The first solve after a factorization
+ * first brings the factor to standard form in place.  Inputs and outputs are
+ * device arrays and must not alias.  Async; a failure of the solve kernels'
+ * bounded dependency waits is reported (MDS_EHIP) by the next mds_refine. */
 int mds_solve(mds_handle *h, const double *r_d, const double *r_s, const double *r_y,
               double *dx_d, double *dx_s, double *dy);
 

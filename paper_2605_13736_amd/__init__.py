@@ -78,7 +78,7 @@ class StepInfo(C.Structure):
                 ("backtracks", C.c_int32), ("status", C.c_int32)]
 
 
-T_CLASSES = ("condense", "panel", "trailing", "solve")
+T_CLASSES = ("condense", "panel", "trailing", "solve", "permute")
 
 
 class Info(C.Structure):
@@ -87,7 +87,7 @@ class Info(C.Structure):
 
 
 class Timings(C.Structure):
-    _fields_ = [("ms", C.c_double * 4), ("launches", C.c_int64 * 4)]
+    _fields_ = [("ms", C.c_double * len(T_CLASSES)), ("launches", C.c_int64 * len(T_CLASSES))]
 
 
 # exported functions: name -> (restype, argtypes)

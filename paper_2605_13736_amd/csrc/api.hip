@@ -81,7 +81,7 @@ int resolve_timings(mds_handle *h) {
 // Workspace slots, in carving order.
 enum Slot {
   S_M, S_M2, S_SRC, S_W, S_DD, S_DS, S_IPIV, S_BLK, S_PK0, S_FST, S_INVD, S_CPTR, S_CROW, S_CVAL, S_CFILL,
-  S_FLAGS, S_RED, S_SCAL, S_Z, S_SIG, S_RX, S_RY, S_DSB, S_DX, S_DY, S_DZL, S_DZU, S_XT, S_RES,
+  S_FLAGS, S_RED, S_SCAL, S_Z, S_Z2, S_HMAP, S_PERM, S_COLP, S_TRSV, S_SIG, S_RX, S_RY, S_DSB, S_DX, S_DY, S_DZL, S_DZU, S_XT, S_RES,
   S_COR, S_PREV, S_KX, S_TN, S_TM, S_TN2, S_KNH, S_KNJD, S_KNY, S_KNJS, S_COUNT
 };
 
@@ -113,7 +113,10 @@ Layout make_layout(const mds_dims &d, int nb, bool pingpong) {
   bytes[S_FLAGS] = 4 * 16;
   bytes[S_RED] = 8 * (size_t)kRedBlocks * 8;
   bytes[S_SCAL] = 8 * 64;
-  bytes[S_Z] = 8 * N;
+  bytes[S_Z] = bytes[S_Z2] = 8 * N;
+  bytes[S_HMAP] = 4 * maxp * N;
+  bytes[S_PERM] = bytes[S_COLP] = 4 * N;
+  bytes[S_TRSV] = 4 * (4 + 2 * (size_t)std_solve_blocks((int)N));
   bytes[S_SIG] = bytes[S_RX] = 8 * n;
   bytes[S_RY] = 8 * m;
   bytes[S_DSB] = 8 * ns;
@@ -138,7 +141,7 @@ Layout make_layout(const mds_dims &d, int nb, bool pingpong) {
 
 bool dims_ok(const mds_dims *d) {
   return d && d->n_d >= 0 && d->n_s >= 0 && d->m >= 0 && d->nnz_s >= 0 &&
-         (int64_t)d->n_d + d->m <= 65536 && (int64_t)d->n_d + d->n_s < ((int64_t)1 << 30) &&
+         (int64_t)d->n_d + d->m <= std_max_n() && (int64_t)d->n_d + d->n_s < ((int64_t)1 << 30) &&
          d->nnz_s < ((int64_t)1 << 30);
 }
 
@@ -229,6 +232,25 @@ int factor_impl(mds_handle *h, mds_inertia *out) {
   out->info = st.info;
   h->have_factor = true;
   h->have_M = false;
+  h->std_ready = false;
+  return MDS_OK;
+}
+
+// Standard form of the current factor, in place in M (once per factorization).
+void ensure_std(mds_handle *h) {
+  if (h->std_ready) return;
+  TimedLaunch t(h, MDS_T_PERMUTE);
+  launch_std_form(S(h), h->N, h->w.M, h->w.M2, h->panel_reg ? 1 : 0, h->w.ipiv, h->w.blk,
+                  h->w.panel_k0, h->w.fst, h->w.hmap, h->w.perm, h->w.colpanel, h->w.M);
+  h->std_ready = true;
+}
+
+// Error word of the triangular solves (a bounded wait that expired).
+int solve_status(mds_handle *h) {
+  int32_t e = 0;
+  HIPCHK(hipMemcpyAsync(&e, h->w.trsv + 1, 4, hipMemcpyDeviceToHost, S(h)));
+  HIPCHK(hipStreamSynchronize(S(h)));
+  if (e) return set_err(h, MDS_EHIP, "triangular solve: dependency wait timed out");
   return MDS_OK;
 }
 
@@ -277,10 +299,11 @@ int solve_impl(mds_handle *h, const double *r_d, const double *r_s, const double
   if (nd > 0) HIPCHK(hipMemcpyAsync(h->w.z, r_d, 8 * (size_t)nd, hipMemcpyDeviceToDevice, S(h)));
   launch_rhs_condense(S(h), m, h->P.Js_rowptr, h->P.Js_col, h->P.Js_val, h->w.inv_d, r_s, r_y,
                       h->w.z + nd);
+  ensure_std(h);
   {
     TimedLaunch t(h, MDS_T_SOLVE);
-    launch_ldl_solve(S(h), N, h->w.M, h->w.M2, h->panel_reg ? 1 : 0, h->w.dd, h->w.ds,
-                     h->w.ipiv, h->w.blk, h->w.panel_k0, h->w.fst, h->w.z);
+    launch_std_solve(S(h), N, h->w.M, h->w.dd, h->w.ds, h->w.blk, h->w.perm, h->w.z, h->w.z2,
+                     h->w.z, h->w.trsv);
   }
   h->nsolves++;
   if (nd > 0) HIPCHK(hipMemcpyAsync(dx_d, h->w.z, 8 * (size_t)nd, hipMemcpyDeviceToDevice, S(h)));
@@ -382,6 +405,7 @@ int refine_impl(mds_handle *h, const double *r_d, const double *r_s, const doubl
   }
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(S(h)));
+  TRY(solve_status(h));
   (void)nt;
   if (info) {
     info->eta = eta;
@@ -535,6 +559,11 @@ int mds_create(mds_handle **out, const mds_dims *dims, const mds_options *opts, 
   w.red = D(S_RED);
   w.scal = D(S_SCAL);
   w.z = D(S_Z);
+  w.z2 = D(S_Z2);
+  w.hmap = I(S_HMAP);
+  w.perm = I(S_PERM);
+  w.colpanel = I(S_COLP);
+  w.trsv = I(S_TRSV);
   w.sig = D(S_SIG);
   w.rx = D(S_RX);
   w.ry = D(S_RY);
@@ -555,6 +584,13 @@ int mds_create(mds_handle **out, const mds_dims *dims, const mds_options *opts, 
   w.kn_jd = D(S_KNJD);
   w.kn_y = D(S_KNY);
   w.kn_js = D(S_KNJS);
+  if (std_prepare() != hipSuccess ||
+      hipMemsetAsync(w.trsv, 0, 4 * (4 + 2 * (size_t)std_solve_blocks(h->N)), h->stream) !=
+          hipSuccess ||
+      hipStreamSynchronize(h->stream) != hipSuccess) {
+    delete h;
+    return MDS_EHIP;
+  }
   *out = h;
   return MDS_OK;
 }
@@ -865,53 +901,16 @@ int mds_get_factor(mds_handle *h, double *L_host, double *dd_host, double *ds_ho
   if (!h) return MDS_ENULL;
   if (!h->have_factor) return set_err(h, MDS_ESTATE, "no factorization");
   const int N = h->N;
-  std::vector<int32_t> ipiv(N), blk(N), pk0(h->max_panels + 2);
-  FacState st{};
-  HIPCHK(hipMemcpyAsync(ipiv.data(), h->w.ipiv, 4 * (size_t)N, hipMemcpyDeviceToHost, S(h)));
-  HIPCHK(hipMemcpyAsync(blk.data(), h->w.blk, 4 * (size_t)N, hipMemcpyDeviceToHost, S(h)));
-  HIPCHK(hipMemcpyAsync(&st, h->w.fst, sizeof(st), hipMemcpyDeviceToHost, S(h)));
-  HIPCHK(hipMemcpyAsync(pk0.data(), h->w.panel_k0, 4 * pk0.size(), hipMemcpyDeviceToHost, S(h)));
+  ensure_std(h);
+  if (ipiv_host) HIPCHK(hipMemcpyAsync(ipiv_host, h->w.ipiv, 4 * (size_t)N, hipMemcpyDeviceToHost, S(h)));
   if (dd_host) HIPCHK(hipMemcpyAsync(dd_host, h->w.dd, 8 * (size_t)N, hipMemcpyDeviceToHost, S(h)));
   if (ds_host) HIPCHK(hipMemcpyAsync(ds_host, h->w.ds, 8 * (size_t)N, hipMemcpyDeviceToHost, S(h)));
-  std::vector<double> L2;
-  if (L_host) {
+  if (L_host)
     HIPCHK(hipMemcpyAsync(L_host, h->w.M, 8 * (size_t)N * N, hipMemcpyDeviceToHost, S(h)));
-    if (h->panel_reg) {
-      L2.resize((size_t)N * N);
-      HIPCHK(hipMemcpyAsync(L2.data(), h->w.M2, 8 * (size_t)N * N, hipMemcpyDeviceToHost, S(h)));
-    }
-  }
   HIPCHK(hipStreamSynchronize(S(h)));
-  if (ipiv_host) memcpy(ipiv_host, ipiv.data(), 4 * (size_t)N);
-  if (!L_host) return MDS_OK;
-  // register panel: even panels wrote their multipliers to the second buffer
-  if (h->panel_reg)
-    for (int b = 0; b < st.npanel; b += 2)
-      for (int c = pk0[b]; c < pk0[b + 1]; ++c)
-        memcpy(&L_host[(size_t)c * N], &L2[(size_t)c * N], 8 * (size_t)N);
-  // keep the strictly lower part only
-  for (int c = 0; c < N; ++c)
-    for (int i = 0; i <= c; ++i) L_host[(size_t)i + (size_t)c * N] = 0.0;
-  // standard form: every interchange of a later panel permutes the rows of all
-  // columns of the earlier panels
-  for (int b = 0; b < st.npanel; ++b) {
-    const int k0 = pk0[b], k1 = pk0[b + 1];
-    for (int k = k0; k < k1;) {
-      int p, q;
-      if (blk[k] == 1) {
-        p = k;
-        q = ipiv[k] - 1;
-        k += 1;
-      } else {
-        p = k + 1;
-        q = -ipiv[k] - 1;
-        k += 2;
-      }
-      if (p == q) continue;
-      for (int c = 0; c < k0; ++c)
-        std::swap(L_host[(size_t)p + (size_t)c * N], L_host[(size_t)q + (size_t)c * N]);
-    }
-  }
+  if (L_host)  // keep the strictly lower part only
+    for (int c = 0; c < N; ++c)
+      for (int i = 0; i <= c; ++i) L_host[(size_t)i + (size_t)c * N] = 0.0;
   return MDS_OK;
 }
 

@@ -45,6 +45,11 @@ struct Work {
   double *red;        // reduction partials (kRedBlocks * 8)
   double *scal;       // device scalars (64)
   double *z;          // N: condensed rhs / solution
+  double *z2;         // N: permuted solve vector
+  int32_t *hmap;      // max_panels x N: row map of each panel's frame to the final order
+  int32_t *perm;      // N: final row permutation of the factorization
+  int32_t *colpanel;  // N: panel of each column
+  int32_t *trsv;      // solve epoch, error word, pad, per-block flags (2 x blocks)
   // Newton / IPM vectors
   double *sig, *rx, *ry, *dsb;       // n, n, m, n_s
   double *dx, *dy, *dzl, *dzu, *xt;  // n, m, n, n, n
@@ -66,6 +71,7 @@ struct mds_handle {
   size_t ws_bytes = 0;
   mds_problem P{};
   bool have_problem = false, have_M = false, have_factor = false;
+  bool std_ready = false;  // factor converted to standard form (in M)
   const double *sigma_d = nullptr, *dsbase = nullptr;  // last condense inputs
   double dw = 0.0, dc = 0.0;                           // shifts of current M / factor
   double alpha_bk = 0.0;                               // (1 + sqrt(17)) / 8
@@ -122,12 +128,21 @@ void launch_bk_panel_reg(hipStream_t s, int N, int nb, double alpha, const doubl
                          double *Lout, int32_t *src_out, double *W, double *dd, double *ds,
                          int32_t *ipiv, int32_t *blk, FacState *st, int32_t *panel_k0);
 
-// solve.hip
-// L of panel b lives in M1 when pingpong and b is even, else in M0
-void launch_ldl_solve(hipStream_t s, int N, const double *M0, const double *M1, int pingpong,
-                      const double *dd, const double *ds, const int32_t *ipiv,
-                      const int32_t *blk, const int32_t *panel_k0, const FacState *st,
-                      double *z);
+// solve_std.hip: standard form of the factor (L of panel b lives in M1 when
+// pingpong and b is even, else in M0; the result may be M0 itself) and the
+// multi-workgroup solve
+int std_max_n();
+int std_solve_blocks(int N);
+hipError_t std_prepare();
+void launch_std_form(hipStream_t s, int N, const double *M0, const double *M1, int pingpong,
+                     const int32_t *ipiv, const int32_t *blk, const int32_t *panel_k0,
+                     const FacState *st, int32_t *hmap, int32_t *perm, int32_t *colpanel,
+                     double *Lstd);
+// out = M^{-1} v through P, L, D; z is scratch (N); trsv: epoch, error word,
+// pad, 2 * std_solve_blocks(N) flags
+void launch_std_solve(hipStream_t s, int N, const double *Lstd, const double *dd,
+                      const double *ds, const int32_t *blk, const int32_t *perm, const double *v,
+                      double *z, double *out, int32_t *trsv);
 
 // vec.hip
 void launch_gemv_n(hipStream_t s, int rows, int cols, const double *A, int lda,
