@@ -74,11 +74,21 @@ typedef struct {
   int64_t nnz_s;       /* nonzeros of J_s */
 } mds_dims;
 
+/* Precision of the trailing updates of the factorization.  MDS_FP64: every
+ * step in FP64.  MDS_FP32 / MDS_BF16: the trailing matrix is stored in FP32
+ * and its rank-w updates run on FP32 MFMA, or on BF16 MFMA with FP32
+ * accumulation; pivot search, L, the 1x1/2x2 D blocks and the solves stay
+ * FP64, and mds_refine runs GMRES-based iterative refinement in FP64 on the
+ * full Newton system, preconditioned by the low-precision factorization.
+ * The mixed modes need the register-resident panel (N <= 4096). */
+enum { MDS_FP64 = 0, MDS_FP32 = 1, MDS_BF16 = 2 };
+
 typedef struct {
   int32_t nb;          /* panel width of the blocked factorization (0: default) */
   int32_t panel;       /* 0: automatic (register-resident panel when N <= 4096),
                           1: panel kept in device memory                       */
-  int32_t reserved[6];
+  int32_t precision;   /* MDS_FP64 (default), MDS_FP32 or MDS_BF16             */
+  int32_t reserved[5];
 } mds_options;
 
 /* Problem data, all device pointers, caller-owned, must stay valid and
@@ -204,9 +214,13 @@ int mds_solve(mds_handle *h, const double *r_d, const double *r_s, const double 
               double *dx_d, double *dx_s, double *dy);
 
 /* mds_solve followed by FP64 iterative refinement on the residual of the full
- * (uncondensed) system, evaluated matrix-free.  Stops when the normwise
- * backward error eta <= eta_tol, when it stops decreasing (the best iterate
- * is kept) or after max_steps corrections.  Synchronizes the stream. */
+ * (uncondensed) system, evaluated matrix-free.  FP64 factorization: classic
+ * refinement, which stops when the normwise backward error eta <= eta_tol,
+ * when it stops decreasing (the best iterate is kept) or after max_steps
+ * corrections.  Mixed-precision factorization: restarted GMRES(20) in FP64
+ * with the low-precision LDL' solve as right preconditioner, until
+ * eta <= eta_tol or max_steps GMRES iterations; info->steps counts GMRES
+ * iterations.  Synchronizes the stream. */
 int mds_refine(mds_handle *h, const double *r_d, const double *r_s, const double *r_y,
                double *dx_d, double *dx_s, double *dy, int32_t max_steps, double eta_tol,
                mds_refine_info *info_host);
@@ -269,7 +283,7 @@ typedef struct {
   int32_t nb;           /* panel width limit                                  */
   int32_t min_width;    /* fewest columns a panel factors (except the last)   */
   int32_t panel;        /* 0: register-resident panel, 1: panel in memory    */
-  int32_t pad;
+  int32_t precision;    /* MDS_FP64, MDS_FP32 or MDS_BF16                     */
   int64_t workspace_bytes;
 } mds_info;
 int mds_get_info(const mds_handle *h, mds_info *out_host);

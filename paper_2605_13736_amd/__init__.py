@@ -36,7 +36,11 @@ class Dims(C.Structure):
 
 
 class Options(C.Structure):
-    _fields_ = [("nb", C.c_int32), ("panel", C.c_int32), ("reserved", C.c_int32 * 6)]
+    _fields_ = [("nb", C.c_int32), ("panel", C.c_int32), ("precision", C.c_int32),
+                ("reserved", C.c_int32 * 5)]
+
+
+PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2}
 
 
 class Problem(C.Structure):
@@ -83,7 +87,7 @@ T_CLASSES = ("condense", "panel", "trailing", "solve", "permute")
 
 class Info(C.Structure):
     _fields_ = [("nb", C.c_int32), ("min_width", C.c_int32), ("panel", C.c_int32),
-                ("pad", C.c_int32), ("workspace_bytes", C.c_int64)]
+                ("precision", C.c_int32), ("workspace_bytes", C.c_int64)]
 
 
 class Timings(C.Structure):
@@ -157,14 +161,18 @@ class Solver:
     """One library handle bound to a device, a stream and a workspace tensor."""
 
     def __init__(self, n_d: int, n_s: int, m: int, nnz_s: int, nb: int = 0,
-                 device: str = "cuda:0", stream=None, panel: str = "auto"):
+                 device: str = "cuda:0", stream=None, panel: str = "auto",
+                 precision: str = "fp64"):
         torch = _torch()
         if not torch.cuda.is_available():
             raise MdsError("no ROCm GPU visible: the mdsipm library has no CPU path")
         self.torch = torch
         self.device = torch.device(device)
         self.dims = Dims(n_d, n_s, m, nnz_s)
-        self.opts = Options(nb, 1 if panel == "mem" else 0)
+        if precision not in PRECISIONS:
+            raise MdsError(f"precision must be one of {sorted(PRECISIONS)}")
+        self.precision = precision
+        self.opts = Options(nb, 1 if panel == "mem" else 0, PRECISIONS[precision])
         self.n_d, self.n_s, self.m = n_d, n_s, m
         self.N, self.n = n_d + m, n_d + n_s
         L = lib()
@@ -344,8 +352,9 @@ class Solver:
     def info(self):
         i = Info()
         self._check(lib().mds_get_info(self.h, C.byref(i)), "mds_get_info")
+        prec = {v: k for k, v in PRECISIONS.items()}[i.precision]
         return dict(nb=i.nb, min_width=i.min_width, panel="reg" if i.panel == 0 else "mem",
-                    workspace_bytes=i.workspace_bytes)
+                    precision=prec, workspace_bytes=i.workspace_bytes)
 
     # ---- timing ---------------------------------------------------------
     def set_timing(self, enable: bool):
@@ -394,9 +403,10 @@ def _step_dict(s):
                 backtracks=s.backtracks, status=s.status)
 
 
-def solver_for(prob: dict, nb: int = 0, device: str = "cuda:0", panel: str = "auto") -> Solver:
+def solver_for(prob: dict, nb: int = 0, device: str = "cuda:0", panel: str = "auto",
+               precision: str = "fp64") -> Solver:
     """Create a Solver sized for a problem dict and attach the problem."""
     s = Solver(prob["n_d"], prob["n_s"], prob["m"], len(prob["v"]), nb=nb, device=device,
-               panel=panel)
+               panel=panel, precision=precision)
     s.set_problem(prob)
     return s

@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstring>
 #include <new>
+#include <vector>
 
 #include "internal.hpp"
 #include "ipm.hpp"
@@ -82,7 +83,8 @@ int resolve_timings(mds_handle *h) {
 enum Slot {
   S_M, S_M2, S_SRC, S_W, S_DD, S_DS, S_IPIV, S_BLK, S_PK0, S_FST, S_INVD, S_CPTR, S_CROW, S_CVAL, S_CFILL,
   S_FLAGS, S_RED, S_SCAL, S_Z, S_Z2, S_HMAP, S_PERM, S_COLP, S_TRSV, S_SIG, S_RX, S_RY, S_DSB, S_DX, S_DY, S_DZL, S_DZU, S_XT, S_RES,
-  S_COR, S_PREV, S_KX, S_TN, S_TM, S_TN2, S_KNH, S_KNJD, S_KNY, S_KNJS, S_COUNT
+  S_COR, S_PREV, S_KX, S_TN, S_TM, S_TN2, S_KNH, S_KNJD, S_KNY, S_KNJS, S_X32A, S_X32B, S_GV,
+  S_GZ, S_GRHS, S_GX, S_GW, S_GPART, S_GCOEF, S_COUNT
 };
 
 struct Layout {
@@ -92,13 +94,21 @@ struct Layout {
 
 int default_nb(int N) { return (N >= 64) ? 16 : 8; }
 
-Layout make_layout(const mds_dims &d, int nb, bool pingpong) {
+Layout make_layout(const mds_dims &d, int nb, bool pingpong, int precision) {
   const size_t nd = d.n_d, ns = d.n_s, m = d.m, N = nd + m, n = nd + ns;
   const size_t nnz = (size_t)d.nnz_s;
   const size_t maxp = N / (size_t)std::max(nb - 1, 1) + 2;
   size_t bytes[S_COUNT] = {};
   bytes[S_M] = 8 * N * N;
-  bytes[S_M2] = pingpong ? 8 * N * N : 0;
+  const bool mixed = precision != MDS_FP64;
+  bytes[S_M2] = (pingpong && !mixed) ? 8 * N * N : 0;
+  bytes[S_X32A] = bytes[S_X32B] = mixed ? 4 * N * N : 0;
+  const size_t nK = n + m, R = (size_t)kGmresRestart;
+  bytes[S_GV] = mixed ? 8 * nK * (R + 1) : 0;
+  bytes[S_GZ] = mixed ? 8 * nK * R : 0;
+  bytes[S_GRHS] = bytes[S_GX] = bytes[S_GW] = mixed ? 8 * nK : 0;
+  bytes[S_GPART] = 8 * (size_t)kDotBlocks * (R + 2);
+  bytes[S_GCOEF] = 8 * (R + 2);
   bytes[S_SRC] = 4 * N;
   bytes[S_W] = 8 * N * (size_t)(nb + 2);
   bytes[S_DD] = bytes[S_DS] = 8 * N;
@@ -157,6 +167,9 @@ PanelChoice panel_of(const mds_dims &d, const mds_options *o) {
   const bool force_mem = o && o->panel == 1;
   const int rnb = bk_reg_nb(N);
   PanelChoice c{};
+  const int prec = o ? o->precision : MDS_FP64;
+  if (prec != MDS_FP64 && prec != MDS_FP32 && prec != MDS_BF16) return c;  // nb = 0: invalid
+  if (prec != MDS_FP64 && (rnb == 0 || force_mem)) return c;
   if (rnb > 0 && !force_mem) {
     int nb = (o && o->nb > 0) ? o->nb : rnb;
     nb = std::min(std::max(nb, 2), rnb);
@@ -199,7 +212,29 @@ int factor_impl(mds_handle *h, mds_inertia *out) {
   const int N = h->N;
   launch_fac_reset(S(h), h->w.fst, h->w.panel_k0);
   const int slots = (N + h->adv - 1) / h->adv;
-  for (int b = 0; b < slots; ++b) {
+  if (h->precision != MDS_FP64) {
+    // mixed precision: the trailing matrix lives in the FP32 ping-pong
+    // buffers; L (FP64) goes to M, which then holds the whole factor
+    {
+      TimedLaunch t(h, MDS_T_CONDENSE);
+      launch_to_f32(S(h), (int64_t)N * N, h->w.M, h->w.X32[0]);
+    }
+    for (int b = 0; b < slots; ++b) {
+      const float *X = h->w.X32[b & 1];
+      float *Y = h->w.X32[(b + 1) & 1];
+      {
+        TimedLaunch t(h, MDS_T_PANEL);
+        launch_bk_panel_reg(S(h), N, h->nb, h->alpha_bk, X, h->w.M, h->w.src, h->w.W, h->w.dd,
+                            h->w.ds, h->w.ipiv, h->w.blk, h->w.fst, h->w.panel_k0);
+      }
+      if ((long)N - (long)(b + 1) * h->adv > 0) {
+        TimedLaunch t(h, MDS_T_TRAILING);
+        launch_trailing_lp(S(h), h->precision, N, h->nb, h->adv, b, h->w.W, X, Y, h->w.M,
+                           h->w.src, h->w.fst, h->w.panel_k0);
+      }
+    }
+  }
+  for (int b = 0; b < (h->precision == MDS_FP64 ? slots : 0); ++b) {
     // register panel: slot b reads buffer b%2 and writes its L and the
     // updated trailing matrix into the other buffer
     double *X = h->w.M, *Y = h->w.M;
@@ -240,7 +275,8 @@ int factor_impl(mds_handle *h, mds_inertia *out) {
 void ensure_std(mds_handle *h) {
   if (h->std_ready) return;
   TimedLaunch t(h, MDS_T_PERMUTE);
-  launch_std_form(S(h), h->N, h->w.M, h->w.M2, h->panel_reg ? 1 : 0, h->w.ipiv, h->w.blk,
+  const int pingpong = (h->panel_reg && h->precision == MDS_FP64) ? 1 : 0;
+  launch_std_form(S(h), h->N, h->w.M, h->w.M2, pingpong, h->w.ipiv, h->w.blk,
                   h->w.panel_k0, h->w.fst, h->w.hmap, h->w.perm, h->w.colpanel, h->w.M);
   h->std_ready = true;
 }
@@ -352,9 +388,146 @@ int amax3(mds_handle *h, int64_t na, const double *a, int64_t nb, const double *
   return MDS_OK;
 }
 
+// ---- GMRES-based refinement (mixed precision) ---------------------------------
+// Deterministic products of the columns V[:, 0..ncol) with w: the host adds
+// the per-block partials in block order.
+int krylov_dots(mds_handle *h, int64_t n, int ncol, const double *V, int64_t ldv,
+                const double *w, double *out) {
+  launch_dots(S(h), n, ncol, V, ldv, w, h->w.gpart);
+  HIPCHK(hipGetLastError());
+  double part[kDotBlocks * (kGmresRestart + 2)];
+  HIPCHK(hipMemcpyAsync(part, h->w.gpart, 8 * (size_t)ncol * kDotBlocks, hipMemcpyDeviceToHost,
+                        S(h)));
+  HIPCHK(hipStreamSynchronize(S(h)));
+  for (int c = 0; c < ncol; ++c) {
+    double t = 0.0;
+    for (int b = 0; b < kDotBlocks; ++b) t += part[c * kDotBlocks + b];
+    out[c] = t;
+  }
+  return MDS_OK;
+}
+
+int set_coef(mds_handle *h, const double *c, int n) {
+  HIPCHK(hipMemcpyAsync(h->w.gcoef, c, 8 * (size_t)n, hipMemcpyHostToDevice, S(h)));
+  HIPCHK(hipStreamSynchronize(S(h)));
+  return MDS_OK;
+}
+
+// Restarted GMRES(kGmresRestart) in FP64 on the full Newton system K x = r,
+// right-preconditioned by the (low-precision) condensed LDL' solve P^{-1}:
+// x = x0 + Z y with Z = P^{-1} V, classical Gram-Schmidt applied twice, Givens
+// rotations on the host.  x0 = P^{-1} r.  Stops when the normwise backward
+// error eta <= eta_tol or after max_iters GMRES iterations.
+int gmres_refine(mds_handle *h, const double *r_d, const double *r_s, const double *r_y,
+                 double *dx_d, double *dx_s, double *dy, int max_iters, double eta_tol,
+                 mds_refine_info *info) {
+  const int nd = ND(h), ns = NS(h), m = MM(h);
+  const int64_t nK = (int64_t)nd + ns + m;
+  const int R = kGmresRestart;
+  double *r = h->w.grhs, *x = h->w.gx, *w = h->w.gw, *V = h->w.gV, *Z = h->w.gZ;
+  vec_copy(S(h), nd, r_d, r);
+  vec_copy(S(h), ns, r_s, r + nd);
+  vec_copy(S(h), m, r_y, r + nd + ns);
+  TRY(solve_impl(h, r, r + nd, r + nd + ns, x, x + nd, x + nd + ns));
+  kkt_norm_parts(S(h), nd, ns, m, h->P.H, h->sigma_d, h->dw, h->P.J_d, h->P.Js_rowptr,
+                 h->P.Js_val, h->w.csc_ptr, h->w.csc_val, h->dsbase, h->dc, h->w.kn_h,
+                 h->w.kn_jd, h->w.kn_y, h->w.kn_js, h->w.red, h->w.scal);
+  HIPCHK(hipGetLastError());
+  double s8[8];
+  TRY(read_scal(h, s8, 8));
+  const double nKn = std::max(s8[0], std::max(s8[1], s8[2]));
+  double a3[3];
+  TRY(amax3(h, nd, r, ns, r + nd, m, r + nd + ns, a3));
+  const double nr = std::max(a3[0], std::max(a3[1], a3[2]));
+  double eta = 0.0, nres = 0.0, den = 0.0;
+  // w = r - K x and the backward error of x
+  auto evaluate = [&]() -> int {
+    kkt_matvec(h, x, x + nd, x + nd + ns, w, w + nd, w + nd + ns);
+    vec_sub(S(h), nK, r, w, w);
+    double rr[3], xx[3];
+    TRY(amax3(h, nd, w, ns, w + nd, m, w + nd + ns, rr));
+    TRY(amax3(h, nd, x, ns, x + nd, m, x + nd + ns, xx));
+    nres = std::max(rr[0], std::max(rr[1], rr[2]));
+    const double nx = std::max(xx[0], std::max(xx[1], xx[2]));
+    den = nKn * nx + nr;
+    eta = (den > 0.0) ? nres / den : 0.0;
+    return MDS_OK;
+  };
+  TRY(evaluate());
+  int iters = 0;
+  std::vector<double> H((size_t)(R + 1) * R), cs(R), sn(R), g(R + 1), y(R);
+  double h1[kGmresRestart + 2], h2[kGmresRestart + 2];
+  while (eta > eta_tol && iters < max_iters) {
+    double beta2 = 0.0;
+    TRY(krylov_dots(h, nK, 1, w, nK, w, &beta2));
+    const double beta = std::sqrt(beta2);
+    if (!(beta > 0.0)) break;
+    launch_scale(S(h), nK, 1.0 / beta, w, V);
+    std::fill(g.begin(), g.end(), 0.0);
+    g[0] = beta;
+    int jdone = 0;
+    for (int j = 0; j < R && iters < max_iters; ++j) {
+      double *vj = V + (int64_t)j * nK, *zj = Z + (int64_t)j * nK;
+      TRY(solve_impl(h, vj, vj + nd, vj + nd + ns, zj, zj + nd, zj + nd + ns));
+      kkt_matvec(h, zj, zj + nd, zj + nd + ns, w, w + nd, w + nd + ns);
+      TRY(krylov_dots(h, nK, j + 1, V, nK, w, h1));
+      TRY(set_coef(h, h1, j + 1));
+      launch_sub_cols(S(h), nK, j + 1, V, nK, h->w.gcoef, w);
+      TRY(krylov_dots(h, nK, j + 1, V, nK, w, h2));
+      TRY(set_coef(h, h2, j + 1));
+      launch_sub_cols(S(h), nK, j + 1, V, nK, h->w.gcoef, w);
+      double hn2 = 0.0;
+      TRY(krylov_dots(h, nK, 1, w, nK, w, &hn2));
+      const double hn = std::sqrt(hn2);
+      double *Hj = &H[(size_t)j * (R + 1)];  // column j
+      for (int i = 0; i <= j; ++i) Hj[i] = h1[i] + h2[i];
+      Hj[j + 1] = hn;
+      if (hn > 0.0) launch_scale(S(h), nK, 1.0 / hn, w, V + (int64_t)(j + 1) * nK);
+      for (int i = 0; i < j; ++i) {
+        const double t0 = cs[i] * Hj[i] + sn[i] * Hj[i + 1];
+        Hj[i + 1] = -sn[i] * Hj[i] + cs[i] * Hj[i + 1];
+        Hj[i] = t0;
+      }
+      const double rho = std::hypot(Hj[j], Hj[j + 1]);
+      cs[j] = (rho > 0.0) ? Hj[j] / rho : 1.0;
+      sn[j] = (rho > 0.0) ? Hj[j + 1] / rho : 0.0;
+      Hj[j] = rho;
+      Hj[j + 1] = 0.0;
+      g[j + 1] = -sn[j] * g[j];
+      g[j] = cs[j] * g[j];
+      ++iters;
+      jdone = j + 1;
+      if (!(hn > 0.0) || std::fabs(g[j + 1]) <= eta_tol * den) break;
+    }
+    if (jdone == 0) break;
+    for (int i = jdone - 1; i >= 0; --i) {
+      double t = g[i];
+      for (int c = i + 1; c < jdone; ++c) t -= H[(size_t)c * (R + 1) + i] * y[c];
+      y[i] = t / H[(size_t)i * (R + 1) + i];
+    }
+    TRY(set_coef(h, y.data(), jdone));
+    launch_add_cols(S(h), nK, jdone, Z, nK, h->w.gcoef, x);
+    TRY(evaluate());
+  }
+  vec_copy(S(h), nd, x, dx_d);
+  vec_copy(S(h), ns, x + nd, dx_s);
+  vec_copy(S(h), m, x + nd + ns, dy);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(S(h)));
+  TRY(solve_status(h));
+  if (info) {
+    info->eta = eta;
+    info->rel_residual = (nr > 0.0) ? nres / nr : 0.0;
+    info->steps = iters;
+  }
+  return (eta <= eta_tol) ? MDS_OK : MDS_REFINE_NOCONV;
+}
+
 int refine_impl(mds_handle *h, const double *r_d, const double *r_s, const double *r_y,
                 double *dx_d, double *dx_s, double *dy, int max_steps, double eta_tol,
                 mds_refine_info *info) {
+  if (h->precision != MDS_FP64)
+    return gmres_refine(h, r_d, r_s, r_y, dx_d, dx_s, dy, max_steps, eta_tol, info);
   const int nd = ND(h), ns = NS(h), m = MM(h);
   const size_t nt = (size_t)nd + ns + m;
   double *res = h->w.res, *cor = h->w.cor, *prev = h->w.prev, *kx = h->w.kx;
@@ -507,7 +680,8 @@ extern "C" {
 size_t mds_workspace_bytes(const mds_dims *dims, const mds_options *opts) {
   if (!dims_ok(dims)) return 0;
   const PanelChoice pc = panel_of(*dims, opts);
-  return make_layout(*dims, pc.nb, pc.reg).total;
+  if (pc.nb == 0) return 0;
+  return make_layout(*dims, pc.nb, pc.reg, opts ? opts->precision : MDS_FP64).total;
 }
 
 int mds_create(mds_handle **out, const mds_dims *dims, const mds_options *opts, void *stream,
@@ -516,7 +690,9 @@ int mds_create(mds_handle **out, const mds_dims *dims, const mds_options *opts, 
   *out = nullptr;
   if (!dims_ok(dims)) return MDS_EDIMS;
   const int nb = nb_of(*dims, opts);
-  const Layout L = make_layout(*dims, nb, panel_of(*dims, opts).reg);
+  if (nb == 0) return MDS_EINVAL;
+  const int prec = opts ? opts->precision : MDS_FP64;
+  const Layout L = make_layout(*dims, nb, panel_of(*dims, opts).reg, prec);
   if (!workspace) return MDS_ENULL;
   if (workspace_bytes < L.total || ((uintptr_t)workspace & 255) != 0) return MDS_EWORKSPACE;
   mds_handle *h = new (std::nothrow) mds_handle();
@@ -532,6 +708,7 @@ int mds_create(mds_handle **out, const mds_dims *dims, const mds_options *opts, 
   const PanelChoice pc = panel_of(*dims, opts);
   h->nb = nb;
   h->panel_reg = pc.reg;
+  h->precision = prec;
   h->adv = pc.adv;
   h->max_panels = h->N / pc.adv + 2;
   h->ws_bytes = workspace_bytes;
@@ -542,6 +719,15 @@ int mds_create(mds_handle **out, const mds_dims *dims, const mds_options *opts, 
   Work &w = h->w;
   w.M = D(S_M);
   w.M2 = D(S_M2);
+  w.X32[0] = (float *)(base + L.off[S_X32A]);
+  w.X32[1] = (float *)(base + L.off[S_X32B]);
+  w.gV = D(S_GV);
+  w.gZ = D(S_GZ);
+  w.grhs = D(S_GRHS);
+  w.gx = D(S_GX);
+  w.gw = D(S_GW);
+  w.gpart = D(S_GPART);
+  w.gcoef = D(S_GCOEF);
   w.src = I(S_SRC);
   w.W = D(S_W);
   w.dd = D(S_DD);
@@ -799,7 +985,10 @@ int mds_ipm_step(mds_handle *h, mds_iterate *it, mds_step_info *info) {
   I.trials = reg.trials;
   if (fst == MDS_INERTIA_FAIL) return I.status = MDS_INERTIA_FAIL;
   mds_refine_info ri{};
-  int rst = refine_impl(h, rx, rx + nd, ry, dx, dx + nd, dy, h->ipm.refine_steps, 1e-14, &ri);
+  // mixed precision: the refinement budget counts GMRES iterations
+  const int rsteps = (h->precision == MDS_FP64) ? h->ipm.refine_steps
+                                                : std::max(h->ipm.refine_steps, 60);
+  int rst = refine_impl(h, rx, rx + nd, ry, dx, dx + nd, dy, rsteps, 1e-14, &ri);
   if (rst < 0) return rst;
   I.eta = ri.eta;
   I.solves = 1 + ri.steps;
@@ -926,7 +1115,7 @@ int mds_get_info(const mds_handle *h, mds_info *out) {
   out->nb = h->nb;
   out->min_width = h->adv;
   out->panel = h->panel_reg ? 0 : 1;
-  out->pad = 0;
+  out->precision = h->precision;
   out->workspace_bytes = (int64_t)h->ws_bytes;
   return MDS_OK;
 }

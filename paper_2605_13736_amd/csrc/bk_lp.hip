@@ -1,0 +1,158 @@
+// Mixed-precision trailing update of the blocked Bunch-Kaufman factorization:
+// the trailing matrix is stored in FP32 and the rank-w product L21 W21' runs
+// on FP32 MFMA (v_mfma_f32_16x16x4f32) or on BF16 MFMA with FP32 accumulation
+// (v_mfma_f32_16x16x16bf16_1k).  The panel (pivot search, D blocks, L and W)
+// stays FP64: L and W are rounded to the product's input type here.  As in
+// the FP64 update, the un-updated entry is read through the panel's index
+// map from one buffer and the result (lower tile and its mirror) is written
+// to the other.
+#include "internal.hpp"
+
+namespace mds {
+namespace {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef short s4 __attribute__((ext_vector_type(4)));
+
+constexpr int TT = 64;
+
+// round-to-nearest-even FP32 -> BF16 (finite inputs)
+__device__ inline short to_bf16(float x) {
+  const uint32_t u = __float_as_uint(x);
+  return (short)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+
+// MODE 1: FP32 products; MODE 2: BF16 products.  256 threads per 64 x 64
+// lower tile; wave w computes the 32 x 32 quarter (c rows wc.., i columns wi..)
+// of D[c][i] = sum_t W[c, t] L[i, t] as 2 x 2 MFMA blocks of 16 x 16.
+template <int MODE>
+__global__ __launch_bounds__(256) void k_trailing_lp(int N, int nb, const double *__restrict__ W,
+                                                     const float *X, float *Y,
+                                                     const double *__restrict__ Lsrc,
+                                                     const int32_t *__restrict__ src,
+                                                     const FacState *__restrict__ st,
+                                                     const int32_t *__restrict__ panel_k0,
+                                                     int slot) {
+  __shared__ float s_t[TT][TT + 1];
+  if (slot >= st->npanel) return;
+  const int k0 = panel_k0[slot], kend = panel_k0[slot + 1];
+  if (kend >= N || kend <= k0 || kend - k0 > nb + 1) return;
+  const int jw = kend - k0;
+  const int nt = (N - kend + TT - 1) / TT;
+  const int x = blockIdx.x;
+  int ti = (int)((sqrt(8.0 * (double)x + 1.0) - 1.0) * 0.5);
+  while ((ti + 1) * (ti + 2) / 2 <= x) ++ti;
+  while (ti * (ti + 1) / 2 > x) --ti;
+  const int tj = x - ti * (ti + 1) / 2;
+  if (ti >= nt) return;
+  const int i0 = kend + ti * TT, c0 = kend + tj * TT;
+  const size_t ld = (size_t)N;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int wc = c0 + (wv & 1) * 32, wi = i0 + (wv >> 1) * 32;
+  const int l16 = lane & 15, l4 = lane >> 4;
+
+  f4 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = f4{0.f, 0.f, 0.f, 0.f};
+
+  if (MODE == 1) {
+    for (int t0 = 0; t0 < jw; t0 += 4) {
+      const int t = t0 + l4;
+      float av[2], bv[2];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        const int c = wc + a * 16 + l16;
+        av[a] = (t < jw && c < N) ? (float)W[(size_t)c + (size_t)t * ld] : 0.f;
+      }
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        const int i = wi + b * 16 + l16;
+        bv[b] = (t < jw && i < N) ? (float)Lsrc[(size_t)i + (size_t)(k0 + t) * ld] : 0.f;
+      }
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a], bv[b], acc[a][b], 0, 0, 0);
+    }
+  } else {
+    for (int t0 = 0; t0 < jw; t0 += 16) {
+      s4 av[2], bv[2];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int t = t0 + 4 * l4 + e;
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+          const int c = wc + a * 16 + l16;
+          av[a][e] = to_bf16((t < jw && c < N) ? (float)W[(size_t)c + (size_t)t * ld] : 0.f);
+        }
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          const int i = wi + b * 16 + l16;
+          bv[b][e] = to_bf16((t < jw && i < N) ? (float)Lsrc[(size_t)i + (size_t)(k0 + t) * ld] : 0.f);
+        }
+      }
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av[a], bv[b], acc[a][b], 0, 0, 0);
+    }
+  }
+
+  const bool diag = (ti == tj);
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        // 16 x 16 FP32-accumulating MFMA result: lane l, register r holds
+        // row 4 (l / 16) + r, column l % 16
+        const int c = wc + a * 16 + 4 * l4 + r;
+        const int i = wi + b * 16 + l16;
+        if (c < N && i < N && (!diag || i >= c)) {
+          const int si = src ? src[i] : i, sc = src ? src[c] : c;
+          const float v = X[(size_t)si + (size_t)sc * ld] - acc[a][b][r];
+          Y[(size_t)i + (size_t)c * ld] = v;
+          s_t[c - c0][i - i0] = v;
+        }
+      }
+  __syncthreads();
+  for (int e = tid; e < TT * TT; e += 256) {
+    const int cl = e & (TT - 1), il = e >> 6;
+    const int c = c0 + cl, i = i0 + il;
+    if (c < N && i < N && i > c && (!diag || il >= cl)) Y[(size_t)c + (size_t)i * ld] = s_t[cl][il];
+  }
+}
+
+__global__ void k_to_f32(int64_t n, const double *__restrict__ a, float *__restrict__ b) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t e = i; e < n; e += stride) b[e] = (float)a[e];
+}
+
+}  // namespace
+
+void launch_trailing_lp(hipStream_t s, int mode, int N, int nb, int adv, int slot,
+                        const double *W, const float *X, float *Y, const double *Lsrc,
+                        const int32_t *src, const FacState *st, const int32_t *panel_k0) {
+  const long rem = (long)N - (long)(slot + 1) * adv;
+  if (rem <= 0) return;
+  const long nt = (rem + TT - 1) / TT;
+  const long tiles = nt * (nt + 1) / 2;
+  if (mode == 2)
+    k_trailing_lp<2><<<(unsigned)tiles, 256, 0, s>>>(N, nb, W, X, Y, Lsrc, src, st, panel_k0, slot);
+  else
+    k_trailing_lp<1><<<(unsigned)tiles, 256, 0, s>>>(N, nb, W, X, Y, Lsrc, src, st, panel_k0, slot);
+}
+
+void launch_to_f32(hipStream_t s, int64_t n, const double *a, float *b) {
+  if (n <= 0) return;
+  const int64_t blocks = std::min<int64_t>((n + 255) / 256, 8192);
+  k_to_f32<<<(unsigned)blocks, 256, 0, s>>>(n, a, b);
+}
+
+}  // namespace mds

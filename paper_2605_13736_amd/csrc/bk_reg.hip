@@ -1,17 +1,23 @@
 // Register-resident Bunch-Kaufman panel (Sec. 2.3): same decisions and the
 // same output layout as the panel in bk.hip, for N <= 4096.
 //
-// One workgroup of 512 threads (two waves per SIMD); thread t owns the fixed
-// rows k0 + t + 512 r (r < R) of the panel for its whole duration and keeps
-// their multipliers L[i, k0:k0+nb] in registers (R * nb <= 64 doubles), so the updated column
+// One workgroup of 512 threads (two waves per SIMD).  Thread t owns the
+// physical rows rho = k0 + t + 512 r (r < R) of the buffer X for the whole
+// panel and keeps their multipliers L[rho, k0:k0+nb] in registers
+// (R * nb <= 64 doubles).  An interchange p <-> q only changes which logical
+// position a physical row holds (pos[r], and the logical -> physical map
+// s_map used to address columns); multipliers stay with their physical row,
+// which is exactly the row interchange of the panel's L.  The updated column
 //   w = A0[:, c] - L_panel W_panel[c, :]'
-// costs no memory traffic for L.  W rows are formed on demand as L D.  The
-// un-updated values of the next candidate column k+1 are prefetched at the
-// start of every pivot step (column k+2 as soon as a 2x2 pivot is chosen) and
-// patched for the interchange the step makes, so the only global-memory round trip on the critical path is the
-// column of a pivot candidate imax.  When an interchange p <-> q moves row
-// contents between threads, the rows involved (k, k+1, imax) are published
-// in LDS before the reduction barriers that precede the decision.
+// therefore costs no memory traffic for L, and the un-updated values of the
+// next pivot column are the prefetched values of one of the columns k, k+1
+// or k+2 (whichever the interchange puts at the next position).
+//
+// Every VALU instruction of a pivot step costs a wave several cycles, so the
+// step is written for a small instruction count: register indices are
+// static, columns not yet factored are skipped by wave-uniform branches, and
+// the W row (L D) of a pivot candidate is formed lane-parallel by the wave
+// that owns the row.
 //
 // The panel stops once j >= nb - 1 (width nb - 1, or nb after a final 2x2),
 // so that a 2x2 pivot always fits the register tile.
@@ -31,64 +37,39 @@ __device__ inline void amax_combine(double &v, int &i, double v2, int i2) {
   }
 }
 
-// W[i, t] = sum_s L[i, s] D[s, t] over the pivot block holding column t.
-// Columns t < jlim use the panel's D from LDS; column jlim (and jlim+1) use
-// the current step's D passed in registers (kind_cur: 1 = 1x1 d0, 2 = 2x2).
-// Compiler-level memory barrier: keeps the LDS reads of a rarely taken row
-// move inside its branch (hoisting them would pin NB doubles in registers).
-__device__ inline void row_barrier() { __asm__ __volatile__("" ::: "memory"); }
+// Keeps a wave-uniform branch a branch: a block holding it cannot be
+// if-converted into selects that would execute its instructions always.
+__device__ inline void keep_branch() { __asm__ __volatile__(""); }
 
+// Orders this wave's earlier LDS writes before its later LDS reads.
+__device__ inline void lds_wave_sync() { __asm__ __volatile__("s_waitcnt lgkmcnt(0)" ::: "memory"); }
+
+// Lane t < NB of the calling wave: W[t] of the L row in Lrow, from the stored
+// coefficients (cA diagonal, cB / cC off-diagonal of a 2x2 for its first /
+// second column; zero for columns not yet stored) plus, for the step that
+// just factored columns jc (and jc + 1 if two), its D from registers.
 template <int NB>
-__device__ inline void w_row(const double (&L)[NB], const double *sD0, const double *sD1,
-                             const int *sB, int jlim, int kind_cur, double d0, double d1,
-                             double dsub, double *out) {
-#pragma unroll
-  for (int t = 0; t < NB; ++t) {
-    double v = 0.0;
-    if (t < jlim) {
-      const int b = sB[t];
-      if (b == 1) {
-        v = L[t] * sD0[t];
-      } else if (b == 2) {
-        if (t + 1 < NB) v = L[t] * sD0[t] + L[t + 1] * sD1[t];
-      } else if (b == 3) {
-        if (t >= 1) v = L[t - 1] * sD1[t - 1] + L[t] * sD0[t];
-      }
-    } else if (t == jlim) {
-      if (kind_cur == 1) {
-        v = L[t] * d0;
-      } else if (kind_cur == 2) {
-        if (t + 1 < NB) v = L[t] * d0 + L[t + 1] * dsub;
-      }
-    } else if (t == jlim + 1 && kind_cur == 2) {
-      if (t >= 1) v = L[t - 1] * dsub + L[t] * d1;
-    }
-    out[t] = v;
+__device__ inline double w_lane(const double *Lrow, const double *cA, const double *cB,
+                                const double *cC, int t, int jc, bool cur, bool two, double d0,
+                                double d1, double db) {
+  const double lt = Lrow[t];
+  const double ln = (t + 1 < NB) ? Lrow[t + 1] : 0.0;
+  const double lp = (t >= 1) ? Lrow[t - 1] : 0.0;
+  double v = lt * cA[t];
+  v = v + ln * cB[t];
+  v = v + lp * cC[t];
+  if (cur) {
+    if (t == jc) v = v + (two ? (lt * d0 + ln * db) : lt * d0);
+    if (two && t == jc + 1) v = v + (lt * d1 + lp * db);
   }
+  return v;
 }
 
-// W[i, t] for t < jend into global memory (stride ld)
-template <int NB>
-__device__ inline void w_row_global(const double (&L)[NB], const double *sD0, const double *sD1,
-                                    const int *sB, int jend, double *out, int ld) {
-#pragma unroll
-  for (int t = 0; t < NB; ++t) {
-    if (t >= jend) continue;
-    const int b = sB[t];
-    double v = 0.0;
-    if (b == 1) v = L[t] * sD0[t];
-    else if (b == 2) {
-      if (t + 1 < NB) v = L[t] * sD0[t] + L[t + 1] * sD1[t];
-    } else if (b == 3) {
-      if (t >= 1) v = L[t - 1] * sD1[t - 1] + L[t] * sD0[t];
-    }
-    out[t * ld] = v;
-  }
-}
-
-template <int T, int R, int NB>
+// X holds the trailing matrix in FP64 or (mixed precision) FP32; every
+// value is widened to FP64 on load and all panel arithmetic is FP64.
+template <int T, int R, int NB, typename TX>
 __global__ __launch_bounds__(T) void k_bk_panel_reg(int N, int nb, double alpha,
-                                                    const double *__restrict__ X,
+                                                    const TX *__restrict__ X,
                                                     double *__restrict__ Lout,
                                                     int32_t *__restrict__ src_out,
                                                     double *__restrict__ W,
@@ -98,100 +79,96 @@ __global__ __launch_bounds__(T) void k_bk_panel_reg(int N, int nb, double alpha,
                                                     int32_t *__restrict__ blk, FacState *st,
                                                     int32_t *__restrict__ panel_k0) {
   constexpr int NWV = T / 64;
-  __shared__ double s_wk[NB], s_wi[NB];            // W rows of pivot k and candidate imax
-  __shared__ double s_Lk[NB], s_Lk1[NB], s_Li[NB];  // L rows of k, k+1, imax
-  __shared__ double s_D0[NB], s_D1[NB];            // panel D: diagonal, sub-diagonal
-  __shared__ int s_B[NB];                          // 1: 1x1, 2/3: first/second of 2x2
+  static_assert(NB <= 64, "one lane per panel column");
+  __shared__ double s_wk[NB], s_wi[NB];            // W rows of the pivot k and of imax
+  __shared__ double s_cA[NB], s_cB[NB], s_cC[NB];  // W = L D coefficients per panel column
+  __shared__ double s_lrow[NB];                    // L row of imax / of the next pivot
   __shared__ double s_rv[NWV];
   __shared__ int s_ri[NWV];
-  __shared__ double s_akk, s_aii;
-  // s_x: [0] w_k[k+1], [1] w_i[k], [2] w_i[k+1], [3] w_k[imax], [4] A0[k+1,k+1],
-  //      [5] A0[k,k], [6] A0[k+1,k], [7] A0[k+2,k+1]
-  __shared__ double s_x[8];
+  __shared__ double s_akk, s_aii, s_wki;
   __shared__ int s_k0;
+  // per owned row: un-updated values of the current pivot column, its updated
+  // values, the updated candidate column
+  __shared__ double s_acur[R * T], s_wkc[R * T], s_wic[R * T];
+  // logical -> physical row of the active part (X is addressed physically)
+  __shared__ int s_map[R * T];
 
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   if (tid == 0) s_k0 = st->k;
-  for (int t = tid; t < NB; t += T) {
-    s_wk[t] = 0.0;
-    s_wi[t] = 0.0;
-    s_D0[t] = 0.0;
-    s_D1[t] = 0.0;
-    s_B[t] = 0;
+  if (tid < NB) {
+    s_wk[tid] = 0.0;
+    s_wi[tid] = 0.0;
+    s_cA[tid] = 0.0;
+    s_cB[tid] = 0.0;
+    s_cC[tid] = 0.0;
   }
   __syncthreads();
   const int k0 = s_k0;
   if (k0 >= N) return;
   const int ld = N;  // N <= 4096: every offset fits in 32 bits
 
-  // un-updated values of the current column for the owned rows live in LDS
-  // (s_acur[r * T + tid]) to leave the registers to L
-  __shared__ double s_acur[R * T];
-  // updated candidate column w_imax for the owned rows (LDS, for the same reason)
-  __shared__ double s_wic[R * T];
-  // updated pivot column w_k for the owned rows (LDS)
-  __shared__ double s_wkc[R * T];
-  // logical -> physical index map of the active part: the logical entry (x, c)
-  // of the matrix is X[src(x) + src(c) * N].  Interchanges only update the map.
-  __shared__ int s_map[T * R];
   double Lr[R][NB];
   double pre1[R], pre2[R];
-  int srcr[R];
+  int pos[R];  // logical position of the owned physical row (-1: past N)
 #pragma unroll
   for (int r = 0; r < R; ++r) {
 #pragma unroll
     for (int t = 0; t < NB; ++t) Lr[r][t] = 0.0;
-    const int i = k0 + tid + T * r;
-    srcr[r] = i;
-    s_map[r * T + tid] = i;
-    s_acur[r * T + tid] = (i < N) ? X[i + k0 * ld] : 0.0;
+    const int rho = k0 + tid + T * r;
+    pos[r] = (rho < N) ? rho : -1;
+    s_map[r * T + tid] = rho;
+    s_acur[r * T + tid] = (rho < N) ? (double)X[rho + k0 * ld] : 0.0;
     pre1[r] = pre2[r] = 0.0;
   }
   __syncthreads();
 
   int k = k0, j = 0;
   int c_pos = 0, c_zero = 0, c_neg = 0, c_2x2 = 0, first_zero = 0;
+  // D of the previous step; thread 0 stores its coefficients at the start of
+  // the next step (the W row of the next pivot takes them from registers)
+  int pj = -1;
+  bool p2 = false;
+  double pA0 = 0.0, pB0 = 0.0, pA1 = 0.0;
 
   while (j < nb - 1 && k < N) {
-    // ---- prefetch the un-updated candidate next column k+1 ------------------
+    if (tid == 0 && pj >= 0) {
+      s_cA[pj] = pA0;
+      s_cB[pj] = pB0;
+      if (p2) {
+        s_cA[pj + 1] = pA1;
+        s_cC[pj + 1] = pB0;
+      }
+    }
+    // ---- prefetch the un-updated column k+1 --------------------------------
     {
       const int sc1 = (k + 1 < N) ? s_map[k + 1 - k0] : 0;
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        const int i = k0 + tid + T * r;
-        pre1[r] = (i > k && i < N) ? X[srcr[r] + sc1 * ld] : 0.0;
+        const int rho = k0 + tid + T * r;
+        if (pos[r] >= k && k + 1 < N) pre1[r] = (double)X[rho + sc1 * ld];
       }
     }
     // ---- updated column k and its largest off-diagonal magnitude -----------
+    double a[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) a[r] = s_acur[r * T + tid];
+#pragma unroll
+    for (int t = 0; t < NB; ++t) {
+      if (t < j) {
+        keep_branch();
+        const double w = s_wk[t];
+#pragma unroll
+        for (int r = 0; r < R; ++r) a[r] = fma(-Lr[r][t], w, a[r]);
+      }
+    }
     double bv = -1.0;
     int bi = INT_MAX;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      const int i = k0 + tid + T * r;
-      if (i >= k && i < N) {
-        const double ac = s_acur[r * T + tid];
-        double a = ac;
-#pragma unroll
-        for (int t = 0; t < NB; ++t) a = fma(-Lr[r][t], s_wk[t], a);
-        s_wkc[r * T + tid] = a;
-        if (i == k) {
-          s_akk = a;
-          s_x[5] = ac;
-#pragma unroll
-          for (int t = 0; t < NB; ++t) s_Lk[t] = Lr[r][t];
-        } else {
-          if (i == k + 1) {
-            s_x[0] = a;
-            s_x[6] = ac;
-#pragma unroll
-            for (int t = 0; t < NB; ++t) s_Lk1[t] = Lr[r][t];
-          }
-          const double v = fabs(a);
-          if (v > bv) {
-            bv = v;
-            bi = i;
-          }
-        }
+      if (pos[r] >= k) {
+        s_wkc[r * T + tid] = a[r];
+        if (pos[r] == k) s_akk = a[r];
+        else amax_combine(bv, bi, fabs(a[r]), pos[r]);
       }
     }
 #pragma unroll
@@ -208,58 +185,65 @@ __global__ __launch_bounds__(T) void k_bk_panel_reg(int N, int nb, double alpha,
     double colmax = -1.0;
     int imax = INT_MAX;
 #pragma unroll
-    for (int q = 0; q < NWV; ++q) amax_combine(colmax, imax, s_rv[q], s_ri[q]);
+    for (int w = 0; w < NWV; ++w) amax_combine(colmax, imax, s_rv[w], s_ri[w]);
     if (colmax < 0.0) {
       colmax = 0.0;
       imax = k;
     }
     const double akk = s_akk, absakk = fabs(akk);
-    // physical indices of the rows that may move this step (read before any
-    // thread updates the map)
-    const int src_k = s_map[k - k0];
-    const int src_k1 = (k + 1 < N) ? s_map[k + 1 - k0] : 0;
-    const int src_k2 = (k + 2 < N) ? s_map[k + 2 - k0] : 0;
-    const int src_i = s_map[imax - k0];
 
     // ---- Bunch-Kaufman decision ----------------------------------------------
     int kind;  // 0 zero, 1 1x1, 2 1x1 (second test), 3 1x1 swap, 4 2x2
     int kstep = 1, q = k;
-    double aii = 0.0;
+    double aii = 0.0, wki = 0.0;
     if (fmax(absakk, colmax) == 0.0 || isnan(absakk)) {
       kind = 0;
     } else if (absakk >= alpha * colmax) {
       kind = 1;
     } else {
-      // candidate column imax: publish its row (W, L, w_k) and load A0[:, imax]
+      // candidate column imax (and column k+2, which follows a 2x2 pivot):
+      // un-updated values, and the W row of imax
+      const int src_i = s_map[imax - k0];
+      const int src_k2 = (k + 2 < N) ? s_map[k + 2 - k0] : 0;
+      double wic[R];
+      bool own = false;
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        const int i = k0 + tid + T * r;
-        if (i == imax) {
-          w_row<NB>(Lr[r], s_D0, s_D1, s_B, j, 0, 0.0, 0.0, 0.0, s_wi);
-#pragma unroll
-          for (int t = 0; t < NB; ++t) s_Li[t] = Lr[r][t];
-          s_x[3] = s_wkc[r * T + tid];
+        const int rho = k0 + tid + T * r;
+        wic[r] = 0.0;
+        if (pos[r] >= k) {
+          wic[r] = (double)X[rho + src_i * ld];
+          if (k + 2 < N) pre2[r] = (double)X[rho + src_k2 * ld];
         }
-        if (i == k + 2) s_x[7] = pre1[r];
-        s_wic[r * T + tid] = (i >= k && i < N) ? X[srcr[r] + src_i * ld] : 0.0;
+        if (pos[r] == imax) {
+          own = true;
+#pragma unroll
+          for (int t = 0; t < NB; ++t) s_lrow[t] = Lr[r][t];
+          s_wki = s_wkc[r * T + tid];
+        }
+      }
+      if (__ballot(own) != 0) {
+        lds_wave_sync();
+        if (lane < NB)
+          s_wi[lane] = w_lane<NB>(s_lrow, s_cA, s_cB, s_cC, lane, 0, false, false, 0.0, 0.0, 0.0);
       }
       __syncthreads();
+#pragma unroll
+      for (int t = 0; t < NB; ++t) {
+        if (t < j) {
+          keep_branch();
+          const double w = s_wi[t];
+#pragma unroll
+          for (int r = 0; r < R; ++r) wic[r] = fma(-Lr[r][t], w, wic[r]);
+        }
+      }
       double rv = 0.0;
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        const int i = k0 + tid + T * r;
-        if (i >= k && i < N) {
-          double a = s_wic[r * T + tid];
-#pragma unroll
-          for (int t = 0; t < NB; ++t) a = fma(-Lr[r][t], s_wi[t], a);
-          s_wic[r * T + tid] = a;
-          if (i == imax) s_aii = a;
-          else rv = fmax(rv, fabs(a));
-          if (i == k) s_x[1] = a;
-          if (i == k + 1) {
-            s_x[2] = a;
-            s_x[4] = pre1[r];
-          }
+        if (pos[r] >= k) {
+          s_wic[r * T + tid] = wic[r];
+          if (pos[r] == imax) s_aii = wic[r];
+          else rv = fmax(rv, fabs(wic[r]));
         }
       }
 #pragma unroll
@@ -268,8 +252,9 @@ __global__ __launch_bounds__(T) void k_bk_panel_reg(int N, int nb, double alpha,
       __syncthreads();
       double rowmax = 0.0;
 #pragma unroll
-      for (int qq = 0; qq < NWV; ++qq) rowmax = fmax(rowmax, s_rv[qq]);
+      for (int w = 0; w < NWV; ++w) rowmax = fmax(rowmax, s_rv[w]);
       aii = s_aii;
+      wki = s_wki;
       if (absakk >= alpha * colmax * (colmax / rowmax)) {
         kind = 2;
       } else if (fabs(aii) >= alpha * rowmax) {
@@ -279,13 +264,6 @@ __global__ __launch_bounds__(T) void k_bk_panel_reg(int N, int nb, double alpha,
         kind = 4;
         q = imax;
         kstep = 2;
-        // next column is k+2: load its un-updated values now (the patch below
-        // replaces the entries this step's interchange changes)
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-          const int i = k0 + tid + T * r;
-          pre2[r] = (i > k + 1 && i < N) ? X[srcr[r] + src_k2 * ld] : 0.0;
-        }
       }
     }
     const int p = k + kstep - 1;
@@ -297,92 +275,71 @@ __global__ __launch_bounds__(T) void k_bk_panel_reg(int N, int nb, double alpha,
     // a zero (or NaN) pivot eliminates nothing: its W column is zero
     const double Dw = (kind == 0) ? 0.0 : Da;
     if (kind == 4) {
-      Db = s_x[3];
+      Db = wki;
       Dc = aii;
       det = Da * Dc - Db * Db;
     }
 
-    // ---- multipliers, row moves, copy of index p into index q, next column --
+    // ---- multipliers, new positions, next column ------------------------------
+    double l0[R], l1[R];
+    bool act[R];
+    bool ownn = false;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      const int i = k0 + tid + T * r;
-      if (i < k || i >= N) continue;
-      if (kind <= 2) {
-        if (i > k) {
-          const double l = (kind == 0) ? 0.0 : s_wkc[r * T + tid] / akk;
-#pragma unroll
-          for (int t = 0; t < NB; ++t)
-            if (t == j) Lr[r][t] = l;
-        }
+      const int pr = pos[r];
+      l1[r] = 0.0;
+      if (kind == 4) {
+        act[r] = pr >= k + 1 && pr != q;
+        const double x0 = s_wkc[r * T + tid], y0 = s_wic[r * T + tid];
+        l0[r] = (x0 * Dc - y0 * Db) / det;
+        l1[r] = (y0 * Da - x0 * Db) / det;
       } else if (kind == 3) {
-        if (i == k) {
-row_barrier();
-#pragma unroll
-          for (int t = 0; t < NB; ++t)
-            if (t < j) Lr[r][t] = s_Li[t];
-          srcr[r] = src_i;
-          s_map[k - k0] = src_i;
-        } else {
-          const double c = (i == q) ? s_x[1] : s_wic[r * T + tid];
-          if (i == q) {
-row_barrier();
-#pragma unroll
-            for (int t = 0; t < NB; ++t)
-              if (t < j) Lr[r][t] = s_Lk[t];
-            srcr[r] = src_k;
-            s_map[q - k0] = src_k;
-          }
-          const double l = c / aii;
-#pragma unroll
-          for (int t = 0; t < NB; ++t)
-            if (t == j) Lr[r][t] = l;
-        }
-      } else {  // kind 4: 2x2 on (k, k+1) after k+1 <-> q
-        if (i == k + 1) {
-          if (sw) {
-row_barrier();
-#pragma unroll
-            for (int t = 0; t < NB; ++t)
-              if (t < j) Lr[r][t] = s_Li[t];
-            srcr[r] = src_i;
-            s_map[k + 1 - k0] = src_i;
-          }
-        } else if (i >= k + 2) {
-          const bool isq = sw && (i == q);
-          const double x0 = isq ? s_x[0] : s_wkc[r * T + tid];
-          const double y0 = isq ? s_x[2] : s_wic[r * T + tid];
-          if (isq) {
-row_barrier();
-#pragma unroll
-            for (int t = 0; t < NB; ++t)
-              if (t < j) Lr[r][t] = s_Lk1[t];
-            srcr[r] = src_k1;
-            s_map[q - k0] = src_k1;
-          }
-          const double l0 = (x0 * Dc - y0 * Db) / det;
-          const double l1 = (y0 * Da - x0 * Db) / det;
-#pragma unroll
-          for (int t = 0; t < NB; ++t) {
-            if (t == j) Lr[r][t] = l0;
-            if (t == j + 1) Lr[r][t] = l1;
-          }
-        }
+        act[r] = pr >= k && pr != q;
+        l0[r] = s_wic[r * T + tid] / aii;
+      } else {
+        act[r] = pr > k;
+        l0[r] = (kind == 0) ? 0.0 : s_wkc[r * T + tid] / akk;
       }
-      // un-updated values of the next column kn after this step's interchange
-      double an = (kstep == 1) ? pre1[r] : pre2[r];
+      int np = pr;
       if (sw) {
-        if (q == kn) {
-          if (i == q) an = (kind == 3) ? s_x[5] : s_x[4];
-          else an = (kind == 3) ? s_acur[r * T + tid] : pre1[r];
-        } else if (i == q) {
-          an = (kind == 3) ? s_x[6] : s_x[7];
-        }
+        if (pr == p) np = q;
+        else if (pr == q) np = p;
       }
+      pos[r] = np;
+      double an = pre1[r];
+      if (kind == 3 && q == k + 1) an = s_acur[r * T + tid];
+      if (kind == 4 && q != k + 2) an = pre2[r];
       s_acur[r * T + tid] = an;
     }
+#pragma unroll
+    for (int t = 0; t < NB; ++t) {
+      if (t == j) {
+        keep_branch();
+#pragma unroll
+        for (int r = 0; r < R; ++r) Lr[r][t] = act[r] ? l0[r] : Lr[r][t];
+      }
+      if (kind == 4 && t == j + 1) {
+        keep_branch();
+#pragma unroll
+        for (int r = 0; r < R; ++r) Lr[r][t] = act[r] ? l1[r] : Lr[r][t];
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      if (pos[r] == kn) {
+        ownn = true;
+#pragma unroll
+        for (int t = 0; t < NB; ++t) s_lrow[t] = Lr[r][t];
+      }
+    }
 
-    // ---- pivot records and the W row of the next pivot -----------------------
+    // ---- pivot records, map, and the W row of the next pivot -----------------
     if (tid == 0) {
+      if (sw) {
+        const int t0 = s_map[p - k0];
+        s_map[p - k0] = s_map[q - k0];
+        s_map[q - k0] = t0;
+      }
       if (kind == 4) {
         dd[k] = Da;
         dd[k + 1] = Dc;
@@ -392,11 +349,6 @@ row_barrier();
         ipiv[k + 1] = -(q + 1);
         blk[k] = 2;
         blk[k + 1] = 3;
-        s_D0[j] = Da;
-        s_D0[j + 1] = Dc;
-        s_D1[j] = Db;
-        s_B[j] = 2;
-        s_B[j + 1] = 3;
         c_pos++;
         c_neg++;
         c_2x2++;
@@ -405,8 +357,6 @@ row_barrier();
         ds[k] = 0.0;
         ipiv[k] = q + 1;
         blk[k] = 1;
-        s_D0[j] = Dw;
-        s_B[j] = 1;
         if (Da > 0.0) c_pos++;
         else if (Da < 0.0) c_neg++;
         else {
@@ -415,29 +365,52 @@ row_barrier();
         }
       }
     }
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const int i = k0 + tid + T * r;
-      if (i == kn && kn < N)
-        w_row<NB>(Lr[r], s_D0, s_D1, s_B, j, (kind == 4) ? 2 : 1, Dw, Dc, Db, s_wk);
+    if (__ballot(ownn) != 0 && kn < N) {
+      lds_wave_sync();
+      if (lane < NB)
+        s_wk[lane] = w_lane<NB>(s_lrow, s_cA, s_cB, s_cC, lane, j, true, kind == 4,
+                                (kind == 4) ? Da : Dw, Dc, Db);
     }
-    k = kn;
+    pj = j;
+    p2 = (kind == 4);
+    pA0 = (kind == 4) ? Da : Dw;
+    pB0 = Db;
+    pA1 = Dc;
     j += kstep;
+    k = kn;
     __syncthreads();
   }
 
   // ---- write the panel's multipliers and W = L D for the trailing rows ---------
   const int kend = k, jend = j;
+  if (tid == 0 && pj >= 0) {
+    s_cA[pj] = pA0;
+    s_cB[pj] = pB0;
+    if (p2) {
+      s_cA[pj + 1] = pA1;
+      s_cC[pj + 1] = pB0;
+    }
+  }
+  __syncthreads();
 #pragma unroll
   for (int r = 0; r < R; ++r) {
-    const int i = k0 + tid + T * r;
-    if (i >= N) continue;
+    const int pr = pos[r];
+    if (pr < 0) continue;
+    const int rho = k0 + tid + T * r;
 #pragma unroll
     for (int t = 0; t < NB; ++t)
-      if (t < jend && i > k0 + t) Lout[i + (k0 + t) * ld] = Lr[r][t];
-    if (i >= kend) {
-      w_row_global<NB>(Lr[r], s_D0, s_D1, s_B, jend, W + i, ld);
-      src_out[i] = srcr[r];
+      if (t < jend && pr > k0 + t) Lout[pr + (k0 + t) * ld] = Lr[r][t];
+    if (pr >= kend) {
+#pragma unroll
+      for (int t = 0; t < NB; ++t) {
+        if (t < jend) {
+          double v = Lr[r][t] * s_cA[t];
+          if (t + 1 < NB) v = v + Lr[r][t + 1 < NB ? t + 1 : t] * s_cB[t];
+          if (t >= 1) v = v + Lr[r][t >= 1 ? t - 1 : 0] * s_cC[t];
+          W[pr + t * ld] = v;
+        }
+      }
+      src_out[pr] = rho;
     }
   }
   if (tid == 0) {
@@ -455,8 +428,8 @@ row_barrier();
 
 }  // namespace
 
-// Panel variant for a matrix of order N: 1024 threads and R rows per thread
-// (R * 1024 >= N), with the register tile NB chosen so that R * NB = 32
+// Panel variant for a matrix of order N: 512 threads and R rows per thread
+// (R * 512 >= N), with the register tile NB chosen so that R * NB <= 64
 // doubles of L per thread.
 int bk_reg_rows(int N) {
   for (int r = 1; r <= 8; r *= 2)
@@ -474,12 +447,13 @@ int bk_reg_nb(int N) {
   }
 }
 
-void launch_bk_panel_reg(hipStream_t s, int N, int nb, double alpha, const double *X,
-                         double *Lout, int32_t *src_out, double *W, double *dd, double *ds,
-                         int32_t *ipiv, int32_t *blk, FacState *st, int32_t *panel_k0) {
-#define MDS_PANEL_REG(R_, NB_)                                                         \
-  k_bk_panel_reg<TMAX, R_, NB_><<<1, TMAX, 0, s>>>(N, nb, alpha, X, Lout, src_out, W, dd, ds, \
-                                                   ipiv, blk, st, panel_k0)
+template <typename TX>
+static void panel_reg(hipStream_t s, int N, int nb, double alpha, const TX *X, double *Lout,
+                      int32_t *src_out, double *W, double *dd, double *ds, int32_t *ipiv,
+                      int32_t *blk, FacState *st, int32_t *panel_k0) {
+#define MDS_PANEL_REG(R_, NB_)                                                                \
+  k_bk_panel_reg<TMAX, R_, NB_, TX><<<1, TMAX, 0, s>>>(N, nb, alpha, X, Lout, src_out, W, dd, \
+                                                       ds, ipiv, blk, st, panel_k0)
   switch (bk_reg_rows(N)) {
     case 1: MDS_PANEL_REG(1, 32); break;
     case 2: MDS_PANEL_REG(2, 32); break;
@@ -488,6 +462,18 @@ void launch_bk_panel_reg(hipStream_t s, int N, int nb, double alpha, const doubl
     default: break;
   }
 #undef MDS_PANEL_REG
+}
+
+void launch_bk_panel_reg(hipStream_t s, int N, int nb, double alpha, const double *X,
+                         double *Lout, int32_t *src_out, double *W, double *dd, double *ds,
+                         int32_t *ipiv, int32_t *blk, FacState *st, int32_t *panel_k0) {
+  panel_reg(s, N, nb, alpha, X, Lout, src_out, W, dd, ds, ipiv, blk, st, panel_k0);
+}
+
+void launch_bk_panel_reg(hipStream_t s, int N, int nb, double alpha, const float *X,
+                         double *Lout, int32_t *src_out, double *W, double *dd, double *ds,
+                         int32_t *ipiv, int32_t *blk, FacState *st, int32_t *panel_k0) {
+  panel_reg(s, N, nb, alpha, X, Lout, src_out, W, dd, ds, ipiv, blk, st, panel_k0);
 }
 
 }  // namespace mds

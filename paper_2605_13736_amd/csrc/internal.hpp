@@ -15,6 +15,8 @@ namespace mds {
 constexpr int kPanelThreads = 1024;  // one workgroup factors a panel
 constexpr int kMaxNb = 64;           // largest supported panel width
 constexpr int kRedBlocks = 1024;     // partial-reduction slots
+constexpr int kDotBlocks = 64;       // blocks per column of a Krylov dot product
+constexpr int kGmresRestart = 20;    // GMRES restart length of the mixed-precision refinement
 
 // Device-side factorization progress, written by the panel kernel.
 struct FacState {
@@ -29,6 +31,7 @@ struct FacState {
 struct Work {
   double *M;          // N x N, full symmetric, column-major; L after factoring
   double *M2;         // second N x N buffer (register panel: ping-pong + L of even panels)
+  float *X32[2];      // mixed precision: FP32 ping-pong buffers of the trailing matrix
   int32_t *src;       // N: logical -> physical index map of the last panel
   double *W;          // N x (nb + 2) panel workspace (updated columns)
   double *dd, *ds;    // D diagonal / sub-diagonal (N)
@@ -56,6 +59,9 @@ struct Work {
   double *res, *cor, *prev, *kx;     // n + m each (refinement)
   double *tn, *tm, *tn2;             // scratch n, m, n
   double *kn_h, *kn_jd, *kn_y, *kn_js;  // ||K||_inf row-sum scratch: n_d, n_d, m, n_s
+  // GMRES refinement (mixed precision): basis V (nK x (restart+1)), Z = P^{-1} V
+  // (nK x restart), rhs, iterate, residual / work vector, dot partials, coefficients
+  double *gV, *gZ, *grhs, *gx, *gw, *gpart, *gcoef;
 };
 
 }  // namespace mds
@@ -66,6 +72,7 @@ struct mds_handle {
   mds_dims dims{};
   int N = 0, n = 0, nb = 16, max_panels = 0;
   bool panel_reg = false;  // register-resident panel kernel
+  int precision = MDS_FP64;
   int adv = 16;            // least number of columns a panel factors
   mds::Work w{};
   size_t ws_bytes = 0;
@@ -121,12 +128,30 @@ void launch_bk_trailing(hipStream_t s, int N, int nb, int adv, int slot, const d
                         const double *X, double *Y, const double *Lsrc, const int32_t *src,
                         const FacState *st, const int32_t *panel_k0);
 
-// bk_reg.hip: register-resident panel for N <= 4096
+// bk_reg.hip: register-resident panel for N <= 4096 (X in FP64 or FP32)
 int bk_reg_rows(int N);
 int bk_reg_nb(int N);
 void launch_bk_panel_reg(hipStream_t s, int N, int nb, double alpha, const double *X,
                          double *Lout, int32_t *src_out, double *W, double *dd, double *ds,
                          int32_t *ipiv, int32_t *blk, FacState *st, int32_t *panel_k0);
+void launch_bk_panel_reg(hipStream_t s, int N, int nb, double alpha, const float *X,
+                         double *Lout, int32_t *src_out, double *W, double *dd, double *ds,
+                         int32_t *ipiv, int32_t *blk, FacState *st, int32_t *panel_k0);
+
+// bk_lp.hip: FP32-storage trailing update (mode MDS_FP32 or MDS_BF16 products)
+void launch_trailing_lp(hipStream_t s, int mode, int N, int nb, int adv, int slot,
+                        const double *W, const float *X, float *Y, const double *Lsrc,
+                        const int32_t *src, const FacState *st, const int32_t *panel_k0);
+void launch_to_f32(hipStream_t s, int64_t n, const double *a, float *b);
+
+// gmres.hip: Krylov products (partial[c * kDotBlocks + b]) and updates
+void launch_dots(hipStream_t s, int64_t n, int ncol, const double *V, int64_t ldv,
+                 const double *w, double *partial);
+void launch_sub_cols(hipStream_t s, int64_t n, int ncol, const double *V, int64_t ldv,
+                     const double *coef, double *w);
+void launch_add_cols(hipStream_t s, int64_t n, int ncol, const double *Z, int64_t ldz,
+                     const double *coef, double *x);
+void launch_scale(hipStream_t s, int64_t n, double alpha, const double *w, double *out);
 
 // solve_std.hip: standard form of the factor (L of panel b lives in M1 when
 // pingpong and b is even, else in M0; the result may be M0 itself) and the
