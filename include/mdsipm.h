@@ -296,6 +296,63 @@ int mds_get_timings(mds_handle *h, mds_timings *out_host);
 const char *mds_status_string(int status);
 const char *mds_last_error(const mds_handle *h);
 
+/* ---- batched Newton solves (many scenario problems of uneven size) -------- */
+
+/* One problem of a batch: the data of one regularised Newton system (Sec. 2.2,
+ * eq. (compressed)) and its right-hand side.  All pointers are device
+ * pointers, caller-owned, valid for the batch's lifetime; outputs are
+ * written by every mds_batch_run.  Layouts as in mds_problem.  Condensed size
+ * N = n_d + m must satisfy 1 <= N <= 2048. */
+typedef struct {
+  int32_t n_d, n_s, m, pad;
+  int64_t nnz_s;
+  const double *H, *J_d;                  /* n_d x n_d, m x n_d column-major   */
+  const int32_t *Js_rowptr, *Js_col;      /* CSR of J_s (m x n_s), sorted rows */
+  const double *Js_val;
+  const double *sigma_d, *dsbase;         /* Sigma_d (n_d), w + Sigma_s (n_s)  */
+  const double *r_d, *r_s, *r_y;          /* right-hand side                   */
+  double *dx_d, *dx_s, *dy;               /* solution                          */
+} mds_batch_problem;
+
+/* Per-problem outcome (host).  Times are wall-clock ticks (100 MHz) since
+ * the first workgroup of the launch started. */
+typedef struct {
+  int32_t npos, nzero, nneg, trials;      /* final inertia of M, factorizations */
+  double delta_w, delta_c;                /* shifts of the accepted factor      */
+  int64_t t_start, t_done;
+  int32_t status;                         /* 0 or MDS_INERTIA_FAIL              */
+  int32_t slot;                           /* workgroup that solved it           */
+} mds_batch_result;
+
+typedef struct {
+  int32_t nb;         /* panel width, 2..16 (0: 16)                              */
+  int32_t grid;       /* persistent workgroups = scratch slots (0: min(count, 256)) */
+  int32_t use_graph;  /* 0: plain launches; otherwise replay a captured hipGraph */
+  int32_t reserved[5];
+} mds_batch_opts;
+
+typedef struct mds_batch mds_batch;
+
+/* Bytes of device workspace for a batch (0: invalid sizes). */
+size_t mds_batch_workspace_bytes(const mds_batch_problem *probs_host, int32_t count,
+                                 const mds_batch_opts *opts);
+/* Build the batch: column-compressed copies of every J_s, the problem table
+ * (largest N first) and one scratch slot per persistent workgroup.
+ * Synchronizes the stream. */
+int mds_batch_create(mds_batch **out, const mds_batch_problem *probs_host, int32_t count,
+                     const mds_batch_opts *opts, void *stream, void *workspace,
+                     size_t workspace_bytes);
+/* Solve every problem: for each, condense, factor with the inertia
+ * correction loop (delta_c = 1e-8 mu^(1/4) on a singular M), solve and
+ * back-substitute, in one persistent kernel (hipGraph replay).  results_host
+ * (may be NULL) receives count entries.  Synchronizes. */
+int mds_batch_run(mds_batch *b, double mu, mds_batch_result *results_host);
+/* Time each candidate (panel width x grid) once and keep the fastest;
+ * chosen_host (may be NULL) receives it.  Runs the batch several times. */
+int mds_batch_autotune(mds_batch *b, double mu, mds_batch_opts *chosen_host);
+int mds_batch_get_config(const mds_batch *b, mds_batch_opts *out_host);
+void mds_batch_destroy(mds_batch *b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -90,6 +90,26 @@ class Info(C.Structure):
                 ("precision", C.c_int32), ("workspace_bytes", C.c_int64)]
 
 
+class BatchProblem(C.Structure):
+    _fields_ = [("n_d", C.c_int32), ("n_s", C.c_int32), ("m", C.c_int32), ("pad", C.c_int32),
+                ("nnz_s", C.c_int64), ("H", _vp), ("J_d", _vp), ("Js_rowptr", _vp),
+                ("Js_col", _vp), ("Js_val", _vp), ("sigma_d", _vp), ("dsbase", _vp),
+                ("r_d", _vp), ("r_s", _vp), ("r_y", _vp), ("dx_d", _vp), ("dx_s", _vp),
+                ("dy", _vp)]
+
+
+class BatchResult(C.Structure):
+    _fields_ = [("npos", C.c_int32), ("nzero", C.c_int32), ("nneg", C.c_int32),
+                ("trials", C.c_int32), ("delta_w", C.c_double), ("delta_c", C.c_double),
+                ("t_start", C.c_int64), ("t_done", C.c_int64), ("status", C.c_int32),
+                ("slot", C.c_int32)]
+
+
+class BatchOpts(C.Structure):
+    _fields_ = [("nb", C.c_int32), ("grid", C.c_int32), ("use_graph", C.c_int32),
+                ("reserved", C.c_int32 * 5)]
+
+
 class Timings(C.Structure):
     _fields_ = [("ms", C.c_double * len(T_CLASSES)), ("launches", C.c_int64 * len(T_CLASSES))]
 
@@ -120,6 +140,14 @@ SIGNATURES = {
     "mds_get_info": (C.c_int, [_vp, C.POINTER(Info)]),
     "mds_set_timing": (C.c_int, [_vp, C.c_int]),
     "mds_get_timings": (C.c_int, [_vp, C.POINTER(Timings)]),
+    "mds_batch_workspace_bytes": (C.c_size_t, [C.POINTER(BatchProblem), C.c_int32,
+                                               C.POINTER(BatchOpts)]),
+    "mds_batch_create": (C.c_int, [C.POINTER(_vp), C.POINTER(BatchProblem), C.c_int32,
+                                   C.POINTER(BatchOpts), _vp, _vp, C.c_size_t]),
+    "mds_batch_run": (C.c_int, [_vp, C.c_double, C.POINTER(BatchResult)]),
+    "mds_batch_autotune": (C.c_int, [_vp, C.c_double, C.POINTER(BatchOpts)]),
+    "mds_batch_get_config": (C.c_int, [_vp, C.POINTER(BatchOpts)]),
+    "mds_batch_destroy": (None, [_vp]),
     "mds_status_string": (C.c_char_p, [C.c_int]),
     "mds_last_error": (C.c_char_p, [_vp]),
 }
@@ -410,3 +438,97 @@ def solver_for(prob: dict, nb: int = 0, device: str = "cuda:0", panel: str = "au
                panel=panel, precision=precision)
     s.set_problem(prob)
     return s
+
+
+class Batch:
+    """Many independent Newton systems solved by one persistent kernel.
+
+    items: list of dicts with the problem arrays of a synthetic problem dict
+    (H, Jd, rp, ci, v, n_d, n_s, m) plus sigma_d, dsbase, r_d, r_s, r_y."""
+
+    def __init__(self, items, nb=0, grid=0, use_graph=True, device="cuda:0"):
+        torch = _torch()
+        if not torch.cuda.is_available():
+            raise MdsError("no ROCm GPU visible: the mdsipm library has no CPU path")
+        self.torch, self.device = torch, torch.device(device)
+        self.count = len(items)
+        self._keep = []
+        self.out = []
+        descs = (BatchProblem * self.count)()
+
+        def dev(a, dt=None):
+            arr = np.asarray(a)
+            if dt is None:
+                dt = torch.int32 if arr.dtype.kind in "iu" else torch.float64
+            t = torch.as_tensor(np.ascontiguousarray(arr)).to(device=self.device, dtype=dt)
+            self._keep.append(t)
+            return t
+
+        for p, it in enumerate(items):
+            nd, ns, m = int(it["n_d"]), int(it["n_s"]), int(it["m"])
+            H = dev(np.asarray(it["H"], dtype=np.float64).reshape(-1, order="F"))
+            Jd = dev(np.asarray(it["Jd"], dtype=np.float64).reshape(-1, order="F"))
+            rp = dev(np.asarray(it["rp"], dtype=np.int32), torch.int32)
+            ci = dev(np.asarray(it["ci"], dtype=np.int32), torch.int32)
+            v = dev(np.asarray(it["v"], dtype=np.float64))
+            ins = [dev(np.asarray(it[k], dtype=np.float64))
+                   for k in ("sigma_d", "dsbase", "r_d", "r_s", "r_y")]
+            o = [torch.empty(max(n, 0), dtype=torch.float64, device=self.device)
+                 for n in (nd, ns, m)]
+            self.out.append(o)
+            descs[p] = BatchProblem(nd, ns, m, 0, int(len(it["v"])), _ptr(H), _ptr(Jd), _ptr(rp),
+                                    _ptr(ci), _ptr(v), *[_ptr(t) for t in ins],
+                                    *[_ptr(t) for t in o])
+        self.descs = descs
+        self.opts = BatchOpts(int(nb), int(grid), 1 if use_graph else 0)
+        L = lib()
+        nbytes = L.mds_batch_workspace_bytes(descs, self.count, C.byref(self.opts))
+        if nbytes == 0:
+            raise MdsError("invalid batch sizes (each problem needs 1 <= n_d + m <= 2048)")
+        with torch.cuda.device(self.device):
+            self.stream = torch.cuda.current_stream(self.device)
+            self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+            aligned = (self.ws.data_ptr() + 255) & ~255
+            h = C.c_void_p()
+            st = L.mds_batch_create(C.byref(h), descs, self.count, C.byref(self.opts),
+                                    C.c_void_p(self.stream.cuda_stream), C.c_void_p(aligned),
+                                    nbytes)
+        if st != 0:
+            raise MdsError(f"mds_batch_create: {L.mds_status_string(st).decode()}")
+        self.h = h
+        self.workspace_bytes = nbytes
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().mds_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def run(self, mu=0.0):
+        res = (BatchResult * self.count)()
+        st = lib().mds_batch_run(self.h, float(mu), res)
+        if st != 0:
+            raise MdsError(f"mds_batch_run: {lib().mds_status_string(st).decode()}")
+        return [dict(inertia=(r.npos, r.nzero, r.nneg), trials=r.trials, delta_w=r.delta_w,
+                     delta_c=r.delta_c, t_start=r.t_start, t_done=r.t_done, status=r.status,
+                     slot=r.slot) for r in res]
+
+    def autotune(self, mu=0.0):
+        o = BatchOpts()
+        st = lib().mds_batch_autotune(self.h, float(mu), C.byref(o))
+        if st != 0:
+            raise MdsError(f"mds_batch_autotune: {lib().mds_status_string(st).decode()}")
+        return dict(nb=o.nb, grid=o.grid, use_graph=bool(o.use_graph))
+
+    def config(self):
+        o = BatchOpts()
+        lib().mds_batch_get_config(self.h, C.byref(o))
+        return dict(nb=o.nb, grid=o.grid, use_graph=bool(o.use_graph))
+
+    def solution(self, p):
+        return [t.detach().cpu().numpy() for t in self.out[p]]

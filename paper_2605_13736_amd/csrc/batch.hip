@@ -1,0 +1,750 @@
+// Batched condensed-KKT Newton solves (scenario problems of uneven size, the
+// motivation of Sec. 1): one persistent kernel in which every workgroup takes
+// problems from an atomic queue (largest first) and runs the whole Newton
+// system for each inside the workgroup:
+//   condense (same IEEE sequence as condense.hip, so M is bit-identical),
+//   blocked Bunch-Kaufman (panel::panel_reg_dev + per-wave trailing tiles on
+//   FP64 MFMA, ping-pong buffers), inertia correction (Algorithm IC),
+//   LDL' solve in the panels' own row frames, back-substitution of dx_s.
+// Each workgroup owns one slot of scratch buffers sized for the largest
+// problem.  The host captures the queue reset and the kernel in a hipGraph and
+// chooses the panel width and the grid by timing candidates (autotune).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "panel_reg.hpp"
+
+namespace mds {
+namespace {
+
+constexpr int BT = 512;   // threads per workgroup (the register panel's)
+constexpr int BR = 4;     // register rows per thread: N <= 2048
+constexpr int BNB = 16;   // register panel tile
+constexpr int BMAX_N = BT * BR;
+constexpr int TW = 32;    // per-wave trailing tile
+constexpr int NWAVE = BT / 64;
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+struct ProbDev {
+  int32_t nd, ns, m, nnz;
+  const double *H, *Jd;
+  const int32_t *rp, *ci;
+  const double *v;
+  const int32_t *cptr, *crow;
+  const double *cval;
+  const double *sigma_d, *dsbase, *r_d, *r_s, *r_y;
+  double *dx_d, *dx_s, *dy;
+};
+
+struct SlotDev {
+  double *buf[2], *W, *dd, *ds, *inv_d;
+  int32_t *src, *ipiv, *blk, *pk0;
+  FacState *st;
+};
+
+struct ResultDev {
+  int32_t npos, nzero, nneg, trials;
+  double delta_w, delta_c;
+  int64_t t_start, t_done;
+  int32_t status, pad;
+};
+
+// ---- condensation (bit-identical to k_condense_dense / k_condense_schur) ----
+__device__ __attribute__((noinline)) void condense_wg(const ProbDev &P, double *inv_d, double dw, double dc, double *M) {
+  const int tid = threadIdx.x, nd = P.nd, m = P.m, N = nd + m;
+  for (int k = tid; k < P.ns; k += BT) inv_d[k] = 1.0 / (P.dsbase[k] + dw);
+  for (int j = 0; j < N; ++j)
+  for (int i = tid; i < N; i += BT) {
+    double v;
+    if (i < nd && j < nd) {
+      v = P.H[(size_t)i + (size_t)j * nd];
+      if (i == j) v = (v + P.sigma_d[i]) + dw;
+    } else if (j < nd) {
+      v = P.Jd[(size_t)(i - nd) + (size_t)j * m];
+    } else if (i < nd) {
+      v = P.Jd[(size_t)(j - nd) + (size_t)i * m];
+    } else {
+      v = 0.0;
+    }
+    M[(size_t)i + (size_t)j * N] = v;
+  }
+  __syncthreads();
+  for (int r = tid; r < m; r += BT) {
+    const size_t col = (size_t)(nd + r) * N;
+    for (int a = P.rp[r]; a < P.rp[r + 1]; ++a) {
+      const int k = P.ci[a];
+      const double jrk = P.v[a], dk = inv_d[k];
+      for (int e = P.cptr[k]; e < P.cptr[k + 1]; ++e) {
+        const int i = P.crow[e];
+        if (i < r) continue;
+        const size_t pos = (size_t)(nd + i) + col;
+        double acc = M[pos];
+        acc = acc - (P.cval[e] * dk) * jrk;
+        M[pos] = acc;
+        if (i != r) M[(size_t)(nd + r) + (size_t)(nd + i) * N] = acc;
+      }
+    }
+    const size_t dpos = (size_t)(nd + r) + col;
+    M[dpos] = M[dpos] - dc;
+  }
+  __syncthreads();
+}
+
+// ---- trailing update: every wave takes 32 x 32 lower tiles on its own --------
+// D[c][i] = sum_t W[c, t] L[i, t]; Y(i, c) = X(src i, src c) - D[c][i] for the
+// lower tile, mirrored through the wave's LDS tile.
+__device__ __attribute__((noinline)) void trailing_wg(int N, int k0, int kend, const double *W, const double *X, double *Y,
+                            const int32_t *src, double (*s_t)[TW + 1]) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int l16 = lane & 15, l4 = lane >> 4;
+  const int jw = kend - k0, n = N - kend;
+  const int nt = (n + TW - 1) / TW;
+  const int ntiles = nt * (nt + 1) / 2;
+  const size_t ld = (size_t)N;
+  double(*t)[TW + 1] = s_t + wv * TW;
+  for (int x = wv; x < ntiles; x += NWAVE) {
+    int ti = (int)((sqrt(8.0 * (double)x + 1.0) - 1.0) * 0.5);
+    while ((ti + 1) * (ti + 2) / 2 <= x) ++ti;
+    while (ti * (ti + 1) / 2 > x) --ti;
+    const int tj = x - ti * (ti + 1) / 2;
+    const int i0 = kend + ti * TW, c0 = kend + tj * TW;
+    d4 acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int t0 = 0; t0 < jw; t0 += 4) {
+      const int tt = t0 + l4;
+      double av[2], bv[2];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        const int c = c0 + a * 16 + l16;
+        av[a] = (tt < jw && c < N) ? W[(size_t)c + (size_t)tt * ld] : 0.0;
+      }
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        const int i = i0 + b * 16 + l16;
+        bv[b] = (tt < jw && i < N) ? Y[(size_t)i + (size_t)(k0 + tt) * ld] : 0.0;
+      }
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+          acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+    }
+    const bool diag = (ti == tj);
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          // FP64 16 x 16 MFMA result: lane l, register r holds row l/16 + 4 r
+          const int c = c0 + a * 16 + l4 + 4 * r;
+          const int i = i0 + b * 16 + l16;
+          if (c < N && i < N && (!diag || i >= c)) {
+            const double v = X[(size_t)src[i] + (size_t)src[c] * ld] - acc[a][b][r];
+            Y[(size_t)i + (size_t)c * ld] = v;
+            t[c - c0][i - i0] = v;
+          }
+        }
+    __builtin_amdgcn_wave_barrier();
+    __asm__ __volatile__("s_waitcnt lgkmcnt(0)" ::: "memory");
+    for (int e = lane; e < TW * TW; e += 64) {
+      const int cl = e & (TW - 1), il = e / TW;
+      const int c = c0 + cl, i = i0 + il;
+      if (c < N && i < N && i > c && (!diag || il >= cl)) Y[(size_t)c + (size_t)i * ld] = t[cl][il];
+    }
+    __builtin_amdgcn_wave_barrier();
+    __asm__ __volatile__("s_waitcnt lgkmcnt(0)" ::: "memory");
+  }
+}
+
+// The phases are kept out of line so that each gets its own register
+// allocation (the panel needs most of the register file for L).
+__device__ __attribute__((noinline)) void panel_call(int N, int nb, double alpha, const double *X,
+                                                     double *Y, const SlotDev &S) {
+  panel::panel_reg_dev<BT, BR, BNB, double>(N, nb, alpha, X, Y, S.src, S.W, S.dd, S.ds, S.ipiv,
+                                            S.blk, S.st, S.pk0);
+}
+
+// ---- blocked factorization of the slot's buf[0] --------------------------------
+__device__ void factor_wg(int N, int nb, double alpha, const SlotDev &S,
+                          double (*s_t)[TW + 1]) {
+  const int tid = threadIdx.x;
+  if (tid == 0) {
+    FacState z{};
+    *S.st = z;
+    S.pk0[0] = 0;
+  }
+  __syncthreads();
+  for (int b = 0;; ++b) {
+    const int k0 = S.st->k;
+    if (k0 >= N) break;
+    const double *X = S.buf[b & 1];
+    double *Y = S.buf[(b + 1) & 1];
+    panel_call(N, nb, alpha, X, Y, S);
+    __syncthreads();
+    const int kend = S.st->k;
+    if (kend < N) trailing_wg(N, k0, kend, S.W, X, Y, S.src, s_t);
+    __syncthreads();
+  }
+}
+
+// ---- LDL' solve in the panels' row frames (z in LDS) ----------------------------
+__device__ __attribute__((noinline)) void solve_wg(int N, const SlotDev &S, double *z, double *s_part) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int np = S.st->npanel;
+  const size_t ld = (size_t)N;
+  // forward: P_b, then L_b
+  for (int b = 0; b < np; ++b) {
+    const int k0 = S.pk0[b], k1 = S.pk0[b + 1];
+    const double *Lb = S.buf[(b + 1) & 1];
+    if (tid == 0) {
+      for (int k = k0; k < k1;) {
+        int p, q;
+        if (S.blk[k] == 1) {
+          p = k;
+          q = S.ipiv[k] - 1;
+          k += 1;
+        } else {
+          p = k + 1;
+          q = -S.ipiv[k] - 1;
+          k += 2;
+        }
+        if (p != q) {
+          const double t = z[p];
+          z[p] = z[q];
+          z[q] = t;
+        }
+      }
+    }
+    __syncthreads();
+    const int w = k1 - k0;
+    if (wv == 0) {
+      double v = (lane < w) ? z[k0 + lane] : 0.0;
+      for (int c = 0; c + 1 < w; ++c) {
+        const double zc = __shfl(v, c);
+        if (lane > c && lane < w) v = fma(-Lb[(size_t)(k0 + lane) + (size_t)(k0 + c) * ld], zc, v);
+      }
+      if (lane < w) z[k0 + lane] = v;
+    }
+    __syncthreads();
+    for (int x = k1 + tid; x < N; x += BT) {
+      double v = z[x];
+      for (int c = k0; c < k1; ++c) v = fma(-Lb[(size_t)x + (size_t)c * ld], z[c], v);
+      z[x] = v;
+    }
+    __syncthreads();
+  }
+  // D
+  for (int k = tid; k < N; k += BT) {
+    const int bk = S.blk[k];
+    if (bk == 1) {
+      z[k] = z[k] / S.dd[k];
+    } else if (bk == 2) {
+      const double a = S.dd[k], c = S.dd[k + 1], s = S.ds[k];
+      const double det = a * c - s * s;
+      const double y0 = z[k], y1 = z[k + 1];
+      z[k] = (c * y0 - s * y1) / det;
+      z[k + 1] = (a * y1 - s * y0) / det;
+    }
+  }
+  __syncthreads();
+  // backward: L_b', then P_b'
+  for (int b = np - 1; b >= 0; --b) {
+    const int k0 = S.pk0[b], k1 = S.pk0[b + 1], w = k1 - k0;
+    const double *Lb = S.buf[(b + 1) & 1];
+    double acc[BNB + 1];
+#pragma unroll
+    for (int c = 0; c <= BNB; ++c) acc[c] = 0.0;
+    for (int x = k1 + tid; x < N; x += BT) {
+      const double zx = z[x];
+#pragma unroll
+      for (int c = 0; c <= BNB; ++c)
+        if (c < w) acc[c] = fma(Lb[(size_t)x + (size_t)(k0 + c) * ld], zx, acc[c]);
+    }
+#pragma unroll
+    for (int c = 0; c <= BNB; ++c) {
+      double v = acc[c];
+      for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+      if (lane == 0) s_part[wv * (BNB + 1) + c] = v;
+    }
+    __syncthreads();
+    if (wv == 0) {
+      double v = 0.0;
+      if (lane < w) {
+        double s = 0.0;
+        for (int q = 0; q < NWAVE; ++q) s += s_part[q * (BNB + 1) + lane];
+        v = z[k0 + lane] - s;
+      }
+      for (int c = w - 1; c > 0; --c) {
+        const double xc = __shfl(v, c);
+        if (lane < c) v = fma(-Lb[(size_t)(k0 + c) + (size_t)(k0 + lane) * ld], xc, v);
+      }
+      if (lane < w) z[k0 + lane] = v;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      int ks[BNB + 2], ne = 0;
+      for (int k = k0; k < k1;) {
+        ks[ne++] = k;
+        k += (S.blk[k] == 1) ? 1 : 2;
+      }
+      for (int e = ne - 1; e >= 0; --e) {
+        const int k = ks[e];
+        int p, q;
+        if (S.blk[k] == 1) {
+          p = k;
+          q = S.ipiv[k] - 1;
+        } else {
+          p = k + 1;
+          q = -S.ipiv[k] - 1;
+        }
+        if (p != q) {
+          const double t = z[p];
+          z[p] = z[q];
+          z[q] = t;
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void k_batch_reset(int32_t *queue, unsigned long long *t0) {
+  if (threadIdx.x == 0) {
+    queue[0] = 0;
+    t0[0] = ~0ull;
+  }
+}
+
+// The persistent kernel.  dc_sing = 1e-8 mu^(1/4), computed on the host.
+__global__ __launch_bounds__(BT) void k_batch(int count, const int32_t *__restrict__ order,
+                                              const ProbDev *__restrict__ probs,
+                                              const SlotDev *__restrict__ slots, int nb,
+                                              double alpha, const double *dc_sing_p,
+                                              int32_t *queue, unsigned long long *t0,
+                                              ResultDev *results) {
+  const double dc_sing = *dc_sing_p;
+  __shared__ double s_t[NWAVE * TW][TW + 1];
+  __shared__ double s_z[BMAX_N];
+  __shared__ double s_part[NWAVE * (BNB + 1)];
+  __shared__ int s_p;
+  const int tid = threadIdx.x;
+  const SlotDev S = slots[blockIdx.x];
+  if (tid == 0) atomicMin(t0, (unsigned long long)wall_clock64());
+  for (;;) {
+    if (tid == 0) s_p = atomicAdd(queue, 1);
+    __syncthreads();
+    const int p = s_p;
+    __syncthreads();
+    if (p >= count) break;
+    const int pid = order[p];
+    const ProbDev P = probs[pid];
+    const int N = P.nd + P.m;
+    const unsigned long long ts = wall_clock64();
+    // inertia correction (Waechter & Biegler, Algorithm IC) from delta_w_last = 0
+    const double dw0 = 1e-4, kw_plus_bar = 100.0, dw_max = 1e20;
+    int trials = 1, status = 0;
+    double dw = 0.0, dc = 0.0;
+    condense_wg(P, S.inv_d, 0.0, 0.0, S.buf[0]);
+    factor_wg(N, nb, alpha, S, s_t);
+    bool ok = S.st->npos == P.nd && S.st->nzero == 0 && S.st->nneg == P.m;
+    if (!ok) {
+      dc = (S.st->nzero > 0) ? dc_sing : 0.0;
+      dw = dw0;
+      for (;;) {
+        trials++;
+        condense_wg(P, S.inv_d, dw, dc, S.buf[0]);
+        factor_wg(N, nb, alpha, S, s_t);
+        ok = S.st->npos == P.nd && S.st->nzero == 0 && S.st->nneg == P.m;
+        if (ok) break;
+        dw = kw_plus_bar * dw;
+        if (dw > dw_max) {
+          status = MDS_INERTIA_FAIL;
+          break;
+        }
+      }
+    }
+    // condensed right-hand side, solve, back-substitution
+    for (int i = tid; i < N; i += BT) {
+      double t;
+      if (i < P.nd) {
+        t = P.r_d[i];
+      } else {
+        const int r = i - P.nd;
+        t = P.r_y[r];
+        for (int a = P.rp[r]; a < P.rp[r + 1]; ++a) {
+          const int k = P.ci[a];
+          t = t - P.v[a] * (S.inv_d[k] * P.r_s[k]);
+        }
+      }
+      s_z[i] = t;
+    }
+    __syncthreads();
+    solve_wg(N, S, s_z, s_part);
+    for (int i = tid; i < N; i += BT) {
+      if (i < P.nd) P.dx_d[i] = s_z[i];
+      else P.dy[i - P.nd] = s_z[i];
+    }
+    __syncthreads();
+    for (int k = tid; k < P.ns; k += BT) {
+      double t = P.r_s[k];
+      for (int e = P.cptr[k]; e < P.cptr[k + 1]; ++e) t = t - P.cval[e] * s_z[P.nd + P.crow[e]];
+      P.dx_s[k] = S.inv_d[k] * t;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      ResultDev r;
+      r.npos = S.st->npos;
+      r.nzero = S.st->nzero;
+      r.nneg = S.st->nneg;
+      r.trials = trials;
+      r.delta_w = dw;
+      r.delta_c = dc;
+      r.t_start = (int64_t)ts;
+      r.t_done = (int64_t)wall_clock64();
+      r.status = status;
+      r.pad = (int32_t)blockIdx.x;
+      results[pid] = r;
+    }
+  }
+}
+
+
+// ============================ host side ========================================
+
+}  // namespace
+
+struct mds_batch_impl {
+  hipStream_t stream = nullptr;
+  int count = 0, Nmax = 0, nsmax = 0, nslots = 0;
+  int nb = BNB, grid = 0;
+  bool use_graph = true;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  int g_nb = -1, g_grid = -1;
+  double alpha = 0.0;
+  ProbDev *d_probs = nullptr;
+  SlotDev *d_slots = nullptr;
+  int32_t *d_order = nullptr, *d_queue = nullptr;
+  unsigned long long *d_t0 = nullptr;
+  double *d_dc = nullptr;
+  ResultDev *d_results = nullptr;
+  std::vector<ResultDev> h_results;
+  char err[256] = {0};
+};
+
+namespace {
+
+size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+struct BatchLayout {
+  size_t probs, slots, order, ctl, results, csc_total, slot_bytes, total;
+  int Nmax, nsmax, nslots;
+  std::vector<size_t> csc_off;
+};
+
+bool batch_layout(const mds_batch_problem *ps, int count, const mds_batch_opts *o, BatchLayout &L) {
+  if (!ps || count <= 0) return false;
+  L.Nmax = 0;
+  L.nsmax = 0;
+  L.csc_off.resize(count);
+  size_t csc = 0;
+  for (int p = 0; p < count; ++p) {
+    const mds_batch_problem &q = ps[p];
+    if (q.n_d < 0 || q.n_s < 0 || q.m < 0 || q.nnz_s < 0) return false;
+    const int N = q.n_d + q.m;
+    if (N < 1 || N > BMAX_N || q.nnz_s >= (1LL << 30)) return false;
+    L.Nmax = std::max(L.Nmax, N);
+    L.nsmax = std::max(L.nsmax, q.n_s);
+    L.csc_off[p] = csc;
+    csc += al256(4 * ((size_t)q.n_s + 1)) + al256(4 * (size_t)q.nnz_s + 4) +
+           al256(8 * (size_t)q.nnz_s + 8) + al256(4 * (size_t)q.n_s + 4);
+  }
+  const int want = (o && o->grid > 0) ? o->grid : 256;
+  L.nslots = std::max(1, std::min(count, want));
+  const size_t N = (size_t)L.Nmax;
+  L.slot_bytes = 2 * al256(8 * N * N) + al256(8 * N * (kMaxNb + 2)) + 2 * al256(8 * N) +
+                 al256(8 * (size_t)std::max(L.nsmax, 1)) + 3 * al256(4 * N) + al256(4 * (N + 4)) +
+                 al256(sizeof(FacState));
+  L.probs = al256(sizeof(ProbDev) * count);
+  L.slots = al256(sizeof(SlotDev) * L.nslots);
+  L.order = al256(4 * (size_t)count);
+  L.ctl = 256;
+  L.results = al256(sizeof(ResultDev) * count);
+  L.csc_total = csc;
+  L.total = L.probs + L.slots + L.order + L.ctl + L.results + L.csc_total + L.slot_bytes * L.nslots;
+  return true;
+}
+
+int launch_batch(mds_batch_impl *b) {
+  k_batch_reset<<<1, 64, 0, b->stream>>>(b->d_queue, b->d_t0);
+  k_batch<<<(unsigned)b->grid, BT, 0, b->stream>>>(b->count, b->d_order, b->d_probs, b->d_slots,
+                                                    b->nb, b->alpha, b->d_dc, b->d_queue, b->d_t0,
+                                                    b->d_results);
+  return hipGetLastError() == hipSuccess ? MDS_OK : MDS_EHIP;
+}
+
+int run_once(mds_batch_impl *b) {
+  if (!b->use_graph) return launch_batch(b);
+  if (!b->gexec || b->g_nb != b->nb || b->g_grid != b->grid) {
+    if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->gexec = nullptr;
+    b->graph = nullptr;
+    if (hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+      return MDS_EHIP;
+    const int st = launch_batch(b);
+    hipGraph_t g = nullptr;
+    if (hipStreamEndCapture(b->stream, &g) != hipSuccess || st != MDS_OK) return MDS_EHIP;
+    b->graph = g;
+    if (hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0) != hipSuccess) return MDS_EHIP;
+    b->g_nb = b->nb;
+    b->g_grid = b->grid;
+  }
+  return hipGraphLaunch(b->gexec, b->stream) == hipSuccess ? MDS_OK : MDS_EHIP;
+}
+
+}  // namespace
+}  // namespace mds
+
+using namespace mds;
+
+struct mds_batch : mds_batch_impl {};
+
+extern "C" {
+
+size_t mds_batch_workspace_bytes(const mds_batch_problem *probs_host, int32_t count,
+                                 const mds_batch_opts *opts) {
+  BatchLayout L;
+  if (!batch_layout(probs_host, count, opts, L)) return 0;
+  return L.total;
+}
+
+int mds_batch_create(mds_batch **out, const mds_batch_problem *probs_host, int32_t count,
+                     const mds_batch_opts *opts, void *stream, void *workspace, size_t bytes) {
+  if (!out || !probs_host || !workspace) return MDS_ENULL;
+  *out = nullptr;
+  BatchLayout L;
+  if (!batch_layout(probs_host, count, opts, L)) return MDS_EDIMS;
+  if (bytes < L.total || ((uintptr_t)workspace & 255) != 0) return MDS_EWORKSPACE;
+  if (opts && (opts->nb < 0 || opts->nb == 1 || opts->nb > BNB)) return MDS_EINVAL;
+  for (int p = 0; p < count; ++p) {
+    const mds_batch_problem &q = probs_host[p];
+    if ((q.n_d > 0 && (!q.H || !q.sigma_d || !q.r_d || !q.dx_d)) ||
+        (q.m > 0 && q.n_d > 0 && !q.J_d) || !q.Js_rowptr ||
+        (q.nnz_s > 0 && (!q.Js_col || !q.Js_val)) ||
+        (q.n_s > 0 && (!q.dsbase || !q.r_s || !q.dx_s)) || (q.m > 0 && (!q.r_y || !q.dy)))
+      return MDS_ENULL;
+  }
+  mds_batch *b = new (std::nothrow) mds_batch();
+  if (!b) return MDS_EINVAL;
+  b->stream = (hipStream_t)stream;
+  b->count = count;
+  b->Nmax = L.Nmax;
+  b->nsmax = L.nsmax;
+  b->nslots = L.nslots;
+  b->grid = L.nslots;
+  b->nb = (opts && opts->nb > 0) ? opts->nb : BNB;
+  b->use_graph = !(opts && opts->use_graph == 0);
+  b->alpha = (1.0 + std::sqrt(17.0)) / 8.0;
+  char *base = (char *)workspace;
+  size_t o = 0;
+  b->d_probs = (ProbDev *)(base + o);
+  o += L.probs;
+  b->d_slots = (SlotDev *)(base + o);
+  o += L.slots;
+  b->d_order = (int32_t *)(base + o);
+  o += L.order;
+  b->d_queue = (int32_t *)(base + o);
+  b->d_t0 = (unsigned long long *)(base + o + 64);
+  b->d_dc = (double *)(base + o + 128);
+  o += L.ctl;
+  b->d_results = (ResultDev *)(base + o);
+  o += L.results;
+  char *csc_base = base + o;
+  o += L.csc_total;
+  std::vector<ProbDev> hp(count);
+  hipStream_t s = b->stream;
+  for (int p = 0; p < count; ++p) {
+    const mds_batch_problem &q = probs_host[p];
+    char *c = csc_base + L.csc_off[p];
+    int32_t *cptr = (int32_t *)c;
+    c += al256(4 * ((size_t)q.n_s + 1));
+    int32_t *crow = (int32_t *)c;
+    c += al256(4 * (size_t)q.nnz_s + 4);
+    double *cval = (double *)c;
+    c += al256(8 * (size_t)q.nnz_s + 8);
+    int32_t *fill = (int32_t *)c;
+    launch_csc_build(s, q.m, q.n_s, q.nnz_s, q.Js_rowptr, q.Js_col, q.Js_val, cptr, crow, cval,
+                     fill);
+    ProbDev d{};
+    d.nd = q.n_d;
+    d.ns = q.n_s;
+    d.m = q.m;
+    d.nnz = (int32_t)q.nnz_s;
+    d.H = q.H;
+    d.Jd = q.J_d;
+    d.rp = q.Js_rowptr;
+    d.ci = q.Js_col;
+    d.v = q.Js_val;
+    d.cptr = cptr;
+    d.crow = crow;
+    d.cval = cval;
+    d.sigma_d = q.sigma_d;
+    d.dsbase = q.dsbase;
+    d.r_d = q.r_d;
+    d.r_s = q.r_s;
+    d.r_y = q.r_y;
+    d.dx_d = q.dx_d;
+    d.dx_s = q.dx_s;
+    d.dy = q.dy;
+    hp[p] = d;
+  }
+  std::vector<SlotDev> hs(L.nslots);
+  const size_t N = (size_t)L.Nmax;
+  for (int k = 0; k < L.nslots; ++k) {
+    char *c = base + o + (size_t)k * L.slot_bytes;
+    SlotDev &S = hs[k];
+    S.buf[0] = (double *)c;
+    c += al256(8 * N * N);
+    S.buf[1] = (double *)c;
+    c += al256(8 * N * N);
+    S.W = (double *)c;
+    c += al256(8 * N * (kMaxNb + 2));
+    S.dd = (double *)c;
+    c += al256(8 * N);
+    S.ds = (double *)c;
+    c += al256(8 * N);
+    S.inv_d = (double *)c;
+    c += al256(8 * (size_t)std::max(L.nsmax, 1));
+    S.src = (int32_t *)c;
+    c += al256(4 * N);
+    S.ipiv = (int32_t *)c;
+    c += al256(4 * N);
+    S.blk = (int32_t *)c;
+    c += al256(4 * N);
+    S.pk0 = (int32_t *)c;
+    c += al256(4 * (N + 4));
+    S.st = (FacState *)c;
+  }
+  // largest problems first (LPT), ties by index
+  std::vector<int32_t> order(count);
+  for (int p = 0; p < count; ++p) order[p] = p;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int c) {
+    return probs_host[a].n_d + probs_host[a].m > probs_host[c].n_d + probs_host[c].m;
+  });
+  bool ok = hipMemcpyAsync(b->d_probs, hp.data(), sizeof(ProbDev) * count, hipMemcpyHostToDevice,
+                           s) == hipSuccess &&
+            hipMemcpyAsync(b->d_slots, hs.data(), sizeof(SlotDev) * L.nslots,
+                           hipMemcpyHostToDevice, s) == hipSuccess &&
+            hipMemcpyAsync(b->d_order, order.data(), 4 * (size_t)count, hipMemcpyHostToDevice,
+                           s) == hipSuccess &&
+            hipGetLastError() == hipSuccess && hipStreamSynchronize(s) == hipSuccess;
+  if (!ok) {
+    delete b;
+    return MDS_EHIP;
+  }
+  b->h_results.resize(count);
+  *out = b;
+  return MDS_OK;
+}
+
+int mds_batch_run(mds_batch *b, double mu, mds_batch_result *results_host) {
+  if (!b) return MDS_ENULL;
+  if (!(mu >= 0.0)) return MDS_EINVAL;
+  const double dc = 1e-8 * std::pow(mu, 0.25);
+  if (hipMemcpyAsync(b->d_dc, &dc, 8, hipMemcpyHostToDevice, b->stream) != hipSuccess)
+    return MDS_EHIP;
+  if (hipStreamSynchronize(b->stream) != hipSuccess) return MDS_EHIP;
+  int st = run_once(b);
+  if (st != MDS_OK) return st;
+  unsigned long long t0 = 0;
+  if (hipMemcpyAsync(b->h_results.data(), b->d_results, sizeof(ResultDev) * b->count,
+                     hipMemcpyDeviceToHost, b->stream) != hipSuccess ||
+      hipMemcpyAsync(&t0, b->d_t0, 8, hipMemcpyDeviceToHost, b->stream) != hipSuccess ||
+      hipStreamSynchronize(b->stream) != hipSuccess)
+    return MDS_EHIP;
+  if (results_host) {
+    for (int p = 0; p < b->count; ++p) {
+      const ResultDev &r = b->h_results[p];
+      mds_batch_result &o = results_host[p];
+      o.npos = r.npos;
+      o.nzero = r.nzero;
+      o.nneg = r.nneg;
+      o.trials = r.trials;
+      o.delta_w = r.delta_w;
+      o.delta_c = r.delta_c;
+      o.t_start = r.t_start - (int64_t)t0;
+      o.t_done = r.t_done - (int64_t)t0;
+      o.status = r.status;
+      o.slot = r.pad;
+    }
+  }
+  return MDS_OK;
+}
+
+int mds_batch_autotune(mds_batch *b, double mu, mds_batch_opts *chosen_host) {
+  if (!b) return MDS_ENULL;
+  const int nbs[3] = {8, 12, BNB};
+  int grids[3] = {std::min(b->nslots, 64), std::min(b->nslots, 128), b->nslots};
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return MDS_EHIP;
+  float best = 1e30f;
+  int bnb = b->nb, bgrid = b->grid;
+  for (int gi = 0; gi < 3; ++gi) {
+    if (gi > 0 && grids[gi] == grids[gi - 1]) continue;
+    for (int ni = 0; ni < 3; ++ni) {
+      b->nb = nbs[ni];
+      b->grid = grids[gi];
+      int st = mds_batch_run(b, mu, nullptr);  // warm (and builds the graph)
+      if (st != MDS_OK) return st;
+      (void)hipEventRecord(e0, b->stream);
+      st = run_once(b);
+      (void)hipEventRecord(e1, b->stream);
+      if (st != MDS_OK || hipEventSynchronize(e1) != hipSuccess) return MDS_EHIP;
+      float ms = 0.0f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      if (ms < best) {
+        best = ms;
+        bnb = b->nb;
+        bgrid = b->grid;
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  b->nb = bnb;
+  b->grid = bgrid;
+  if (chosen_host) {
+    memset(chosen_host, 0, sizeof(*chosen_host));
+    chosen_host->nb = bnb;
+    chosen_host->grid = bgrid;
+    chosen_host->use_graph = b->use_graph ? 1 : 0;
+  }
+  return MDS_OK;
+}
+
+int mds_batch_get_config(const mds_batch *b, mds_batch_opts *out_host) {
+  if (!b || !out_host) return MDS_ENULL;
+  memset(out_host, 0, sizeof(*out_host));
+  out_host->nb = b->nb;
+  out_host->grid = b->grid;
+  out_host->use_graph = b->use_graph ? 1 : 0;
+  return MDS_OK;
+}
+
+void mds_batch_destroy(mds_batch *b) {
+  if (!b) return;
+  if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  delete b;
+}
+
+}  // extern "C"

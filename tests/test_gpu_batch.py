@@ -1,0 +1,112 @@
+"""Batched persistent-kernel Newton solves against the oracle, problem by problem.
+
+Bars, per problem of a batch of uneven sizes (including zero-size blocks and a
+nonconvex problem whose inertia correction fires):
+* inertia of the accepted factorization, number of correction trials and
+  the shifts delta_w, delta_c identical to the oracle's correction loop;
+* solution within 1e-8 (relative, max-norm) of the oracle's solve;
+* hipGraph replays give bitwise identical solutions (each problem is solved
+  inside one workgroup, so the result does not depend on scheduling);
+* after autotuning, solutions still match the oracle.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2605_13736_amd as mds
+import synth
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [
+    # (n_d, n_s, m, r, s_scale)
+    (10, 40, 27, 3, 1.0),
+    (64, 2000, 128, 4, 1.0),
+    (100, 900, 200, 4, 1.0),
+    (0, 50, 40, 3, 1.0),
+    (33, 0, 20, 0, 1.0),
+    (45, 30, 0, 2, 1.0),
+    (150, 3000, 550, 6, 1.0),
+    (64, 3200, 192, 4, 1.0),
+    (64, 2000, 128, 4, 6.0),
+    (256, 12800, 768, 4, 1.0),
+]
+MU = 0.05
+
+
+def say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+
+
+def _items():
+    items = []
+    for idx, (nd, ns, m, r, sc) in enumerate(SHAPES):
+        prob = synth.make_problem(nd, ns, m, r, cfg=700 + idx, p=0, s_scale=sc)
+        st = synth.kkt_state(prob, idx, (-1.0, 1.0))
+        it = dict(prob)
+        it.update(sigma_d=st["sigma_d"], dsbase=st["dsbase"], r_d=st["r_d"], r_s=st["r_s"],
+                  r_y=st["r_y"])
+        items.append((prob, st, it))
+    return items
+
+
+@pytest.fixture(scope="module")
+def batch_and_ref():
+    items = _items()
+    say(f"batch of {len(items)} problems, N = {[p['n_d'] + p['m'] for p, _, _ in items]}")
+    B = mds.Batch([it for _, _, it in items])
+    refs = []
+    for prob, st, _ in items:
+        F = oracle.Factor(oracle.Problem(prob))
+        status, _ = F.correct(st["sigma_d"], st["dsbase"], MU)
+        od, os_, oy, _ = F.solve(st["r_d"], st["r_s"], st["r_y"])
+        refs.append(dict(status=status, inertia=F.inertia, trials=F.s.trials, dw=F.s.dw,
+                         dc=F.s.dc, x=np.concatenate([od, os_, oy])))
+    return B, refs
+
+
+def _check(B, res, refs):
+    for p, (r, ref) in enumerate(zip(res, refs)):
+        assert r["inertia"] == ref["inertia"], p
+        assert r["trials"] == ref["trials"], p
+        assert r["delta_w"] == ref["dw"] and r["delta_c"] == ref["dc"], p
+        x = np.concatenate(B.solution(p))
+        scale = max(np.abs(ref["x"]).max(), 1e-300)
+        assert np.abs(x - ref["x"]).max() <= 1e-8 * scale, p
+
+
+def test_batch_matches_oracle(batch_and_ref):
+    B, refs = batch_and_ref
+    res = B.run(MU)
+    _check(B, res, refs)
+    assert max(r["trials"] for r in res) > 1  # the nonconvex problem needs correction
+    assert all(r["t_done"] >= r["t_start"] >= 0 for r in res)
+
+
+def test_batch_graph_replays_are_identical(batch_and_ref):
+    B, refs = batch_and_ref
+    B.run(MU)
+    first = [np.concatenate(B.solution(p)).copy() for p in range(B.count)]
+    for rep in range(3):
+        _ = np.ones(1000).sum()  # eager host work between replays
+        B.run(MU)
+        for p in range(B.count):
+            assert np.array_equal(np.concatenate(B.solution(p)), first[p]), (rep, p)
+
+
+def test_batch_autotune_keeps_results(batch_and_ref):
+    B, refs = batch_and_ref
+    cfg = B.autotune(MU)
+    say(f"autotuned {cfg}")
+    assert 2 <= cfg["nb"] <= 16 and 1 <= cfg["grid"] <= B.count
+    _check(B, B.run(MU), refs)
+
+
+def test_batch_rejects_oversize():
+    prob = synth.make_problem(600, 100, 1500, 3, cfg=790, p=0)
+    st = synth.kkt_state(prob, 0, (-1.0, 1.0))
+    it = dict(prob)
+    it.update(sigma_d=st["sigma_d"], dsbase=st["dsbase"], r_d=st["r_d"], r_s=st["r_s"],
+              r_y=st["r_y"])
+    with pytest.raises(mds.MdsError):
+        mds.Batch([it])
