@@ -30,6 +30,12 @@ sys.path.insert(0, ROOT)
 
 METRIC = "KKT factor+solve TFLOP/s & IPM solves/s: mixed/learned vs FP64, 1e-8 res"
 HBM_PEAK_GBS = 8000.0
+# HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE passes, scaled by
+# the counters of a 256 MiB copy (the profile file gives the commands and the
+# factors); valid for the kernel source as profiled.
+MEASURED_TRAFFIC = {
+    "k_bk_panel": (1022549.0, "profiles/bk_panel_ipm_newton_step_n4096.md"),
+}
 FP64_MFMA_PEAK_TFS = 78.6
 
 
@@ -57,6 +63,114 @@ def trailing_bytes_per_launch(N, w):
         cnt += 1
         k0 += w
     return total / max(cnt, 1)
+
+
+def mixed_section(prob, N, reps=3):
+    """One Newton system of the workload at a seeded interior point, solved
+    to backward error 1e-14 by (a) FP64 factor + classic refinement and (b)
+    FP32 / BF16 trailing updates + FP64 GMRES refinement.  Reports the time
+    of condense + factor + refined solve, nominal TFLOP/s, refinement
+    iterations, and the max-norm error of each solution relative to FP64's."""
+    import torch
+    import paper_2605_13736_amd as mds
+    import synth
+    it = synth.interior_iterate(prob, 0)
+    nd = prob["n_d"]
+    out, ref = {}, None
+    for prec in ("fp64", "fp32", "bf16"):
+        S = mds.solver_for(prob, precision=prec)
+        sig, rx, ry = S.sigma_rhs(it["x"], it["y"], it["zl"], it["zu"], it["mu"])
+        dsb = S.dev(prob["w"]) + sig[nd:]
+        sd = sig[:nd].contiguous()
+        steps = 2 if prec == "fp64" else 60
+
+        def once():
+            S.condense(sd, dsb, 0.0, 0.0)
+            S.factor_inertia()
+            return S.refine(rx[:nd], rx[nd:], ry, steps, 1e-14)
+
+        once()
+        torch.cuda.synchronize()
+        S.set_timing(True)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            (a, b, c), info = once()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        tim = S.get_timings()
+        S.set_timing(False)
+        x = torch.cat([a, b, c]).cpu().numpy()
+        if ref is None:
+            ref = x
+        fac_ms = (tim["panel"]["ms"] + tim["trailing"]["ms"]) / reps
+        out[prec] = dict(ms_condense_factor_refine=dt * 1e3, ms_factor=fac_ms,
+                         tflops_nominal=(N ** 3 / 3.0 + 2.0 * N ** 2) / dt / 1e12,
+                         refine_iterations=info["steps"], eta=info["eta"],
+                         rel_err_vs_fp64=float(abs(x - ref).max() / max(abs(ref).max(), 1e-300)))
+        del S
+        torch.cuda.empty_cache()
+    return out
+
+
+def batch_section(count, mu=0.05, singles=6):
+    """The scenario batch: count problems with N = 4 U{64..512}, n_d = N/4,
+    m = 3N/4, n_s = 50N, 4 nonzeros per row of J_s, each at a seeded barrier
+    state; solved by the persistent kernel after autotuning.  Also times a
+    loop of single-problem FP64 solves on the first `singles` problems."""
+    import numpy as np
+    import torch
+    import paper_2605_13736_amd as mds
+    import synth
+    items, flops = [], 0.0
+    for p in range(count):
+        sz = synth.batch_sizes(p)
+        prob = synth.make_problem(sz["n_d"], sz["n_s"], sz["m"], sz["r"], cfg=3, p=p)
+        st = synth.kkt_state(prob, p, (-1.0, 1.0))
+        it = dict(prob)
+        it.update(sigma_d=st["sigma_d"], dsbase=st["dsbase"], r_d=st["r_d"], r_s=st["r_s"],
+                  r_y=st["r_y"])
+        items.append(it)
+        N = sz["N"]
+        flops += N ** 3 / 3.0 + 2.0 * N ** 2
+    B = mds.Batch(items)
+    B.run(mu)
+    cfg = B.autotune(mu)
+    torch.cuda.synchronize()
+    reps = 3
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        res = B.run(mu)
+    dt = (time.perf_counter() - t0) / reps
+    lat_ms = np.array([r["t_done"] for r in res], dtype=np.float64) / 1e5  # 100 MHz ticks
+    # loop of single-problem solves (same systems, FP64 path, inertia correction)
+    t_single = 0.0
+    for p in range(singles):
+        it = items[p]
+        S = mds.solver_for(it)
+        S.condense(it["sigma_d"], it["dsbase"])
+        S.factor_inertia(mu, reg={})
+        S.solve(it["r_d"], it["r_s"], it["r_y"])
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        S.condense(it["sigma_d"], it["dsbase"])
+        S.factor_inertia(mu, reg={})
+        S.solve(it["r_d"], it["r_s"], it["r_y"])
+        torch.cuda.synchronize()
+        t_single += time.perf_counter() - t1
+        del S
+    per_single = t_single / singles
+    Ns = [it["n_d"] + it["m"] for it in items]
+    return dict(workload=f"{count} problems, N = 4*U{{64..512}} (mean {np.mean(Ns):.0f}), "
+                         "n_d = N/4, m = 3N/4, n_s = 50N, 4 nnz/row of J_s, FP64",
+                problems_per_s=count / dt, ms_per_batch=dt * 1e3,
+                tflops_nominal=flops / dt / 1e12,
+                latency_ms_p50=float(np.percentile(lat_ms, 50)),
+                latency_ms_p99=float(np.percentile(lat_ms, 99)),
+                autotuned=cfg, trials_max=max(r["trials"] for r in res),
+                single_loop_ms_per_problem=per_single * 1e3,
+                speedup_vs_single_loop=per_single * count / dt,
+                single_loop_sample=f"first {singles} problems of the batch (sizes differ "
+                                   "from the batch mean)")
 
 
 def cpu_baseline(prob, N):
@@ -88,6 +202,9 @@ def main():
     ap.add_argument("--nb", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ipm-solves", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--batch-count", type=int, default=128)
     ap.add_argument("--calib-copy", action="store_true",
                     help="only run a plain 256 MiB device copy (calibrates HBM counters)")
     args = ap.parse_args()
@@ -171,10 +288,13 @@ def main():
         roof = dict(bound="hbm", achieved=per_launch / avg_s / 1e9, peak=HBM_PEAK_GBS,
                     unit="GB/s")
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = None
     roof["kernel"] = {"panel": "k_bk_panel_reg" if info0["panel"] == "reg" else "k_bk_panel",
                       "trailing": "k_bk_trailing",
                       "solve": "k_ldl_solve", "condense": "k_condense_dense"}[dom]
+    meas = MEASURED_TRAFFIC.get(roof["kernel"])
+    roof["traffic"] = meas[0] if meas else None
+    if meas:
+        roof["traffic_source"] = meas[1]
     roof["avg_launch_us"] = avg_s * 1e6
     roof["bytes_per_launch"] = per_launch
     fac_ms = (tim["panel"]["ms"] + tim["trailing"]["ms"]) / max(facs, 1)
@@ -209,6 +329,12 @@ def main():
         out["ipm_solves"] = {"workload": "whole FP64 IPM to E_0 <= 1e-8, n_d=64 n_s=2000 m=128 "
                                          "(N=192)", "solves_per_s": 1.0 / d0,
                              "iters": r["iters"], "status": r["status"]}
+    if not args.no_mixed:
+        log("mixed precision section")
+        out["mixed"] = mixed_section(prob, N)
+    if not args.no_batch:
+        log("batch section")
+        out["batch"] = batch_section(args.batch_count)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob, N)
     print(json.dumps(out), flush=True)

@@ -85,10 +85,13 @@ enum { MDS_FP64 = 0, MDS_FP32 = 1, MDS_BF16 = 2 };
 
 typedef struct {
   int32_t nb;          /* panel width of the blocked factorization (0: default) */
-  int32_t panel;       /* 0: automatic (register-resident panel when N <= 4096),
-                          1: panel kept in device memory                       */
+  int32_t panel;       /* 0: automatic (register-resident panel when its tile
+                          allows nb >= 16, i.e. N <= 2048; FP64 only),
+                          1: panel kept in device memory,
+                          2: register-resident panel (N <= 4096)               */
   int32_t precision;   /* MDS_FP64 (default), MDS_FP32 or MDS_BF16             */
-  int32_t reserved[5];
+  int32_t panel_threads; /* register panel workgroup: 512 (default) or 1024     */
+  int32_t reserved[4];
 } mds_options;
 
 /* Problem data, all device pointers, caller-owned, must stay valid and
@@ -252,6 +255,14 @@ int mds_merit(mds_handle *h, const double *x, double mu, double *f_host, double 
  * bounds) and reset the filter and correction state.  opts may be NULL. */
 int mds_ipm_init(mds_handle *h, mds_iterate *it, const mds_ipm_opts *opts);
 
+/* mds_ipm_init from a proposed start (the learned warm start): x_d0 (n_d)
+ * and y0 (m) device arrays, barrier parameter mu0 > 0.  x_s is completed from
+ * the sparse block's stationarity, -(g + J_s' y0) / w where w > 0 (else 0);
+ * every x_i is pushed into the interior of its bounds by the cold start's
+ * rule; y = y0; z = mu0 / slack on finite bounds. */
+int mds_ipm_init_warm(mds_handle *h, mds_iterate *it, const mds_ipm_opts *opts,
+                      const double *x_d0, const double *y0, double mu0);
+
 /* One IPM iteration: convergence test, barrier update, Newton step with
  * inertia correction and refinement, fraction to the boundary, filter
  * backtracking line search, update with the bound-multiplier safeguard.
@@ -284,6 +295,8 @@ typedef struct {
   int32_t min_width;    /* fewest columns a panel factors (except the last)   */
   int32_t panel;        /* 0: register-resident panel, 1: panel in memory    */
   int32_t precision;    /* MDS_FP64, MDS_FP32 or MDS_BF16                     */
+  int32_t panel_threads; /* workgroup size of the panel kernel                */
+  int32_t pad;
   int64_t workspace_bytes;
 } mds_info;
 int mds_get_info(const mds_handle *h, mds_info *out_host);
@@ -344,14 +357,43 @@ int mds_batch_create(mds_batch **out, const mds_batch_problem *probs_host, int32
                      size_t workspace_bytes);
 /* Solve every problem: for each, condense, factor with the inertia
  * correction loop (delta_c = 1e-8 mu^(1/4) on a singular M), solve and
- * back-substitute, in one persistent kernel (hipGraph replay).  results_host
- * (may be NULL) receives count entries.  Synchronizes. */
+ * back-substitute, in one persistent kernel (hipGraph replay on the batch's
+ * own stream, after the caller's stream has drained).  results_host (may be
+ * NULL) receives count entries.  Synchronizes. */
 int mds_batch_run(mds_batch *b, double mu, mds_batch_result *results_host);
 /* Time each candidate (panel width x grid) once and keep the fastest;
  * chosen_host (may be NULL) receives it.  Runs the batch several times. */
 int mds_batch_autotune(mds_batch *b, double mu, mds_batch_opts *chosen_host);
 int mds_batch_get_config(const mds_batch *b, mds_batch_opts *out_host);
+/* Text of the last HIP failure of a batch call. */
+const char *mds_batch_last_error(const mds_batch *b);
 void mds_batch_destroy(mds_batch *b);
+
+/* ---- learned warm start: the multilayer perceptron ------------------------ */
+
+/* MLP dims[0] -> dims[1] -> dims[2] -> dims[3] with GELU (erf form) after the
+ * two hidden layers, trained by mean-squared error with Adam (beta 0.9 /
+ * 0.999, eps 1e-8) in FP32 on FP32 MFMA; inference in FP32 or on BF16 MFMA
+ * with FP32 accumulation.  Parameters are one FP32 vector: W0 (dims[0] x
+ * dims[1], row-major), b0, W1, b1, W2, b2.  Activations are row-major
+ * (batch x features) device arrays. */
+typedef struct mds_mlp mds_mlp;
+size_t mds_mlp_workspace_bytes(const int32_t dims[4], int32_t max_batch);
+int mds_mlp_create(mds_mlp **out, const int32_t dims[4], int32_t max_batch, void *stream,
+                   void *workspace, size_t workspace_bytes);
+void mds_mlp_destroy(mds_mlp *M);
+int32_t mds_mlp_param_count(const mds_mlp *M);
+/* Host copies of the parameters; set resets the Adam state.  Synchronize. */
+int mds_mlp_set_params(mds_mlp *M, const float *params_host);
+int mds_mlp_get_params(const mds_mlp *M, float *params_host);
+/* Gradient of the last training step (host).  Synchronizes. */
+int mds_mlp_get_grad(const mds_mlp *M, float *grad_host);
+/* Y = MLP(X), precision MDS_FP32 or MDS_BF16.  Async. */
+int mds_mlp_forward(mds_mlp *M, const float *X, int32_t batch, int32_t precision, float *Y);
+/* One Adam step on mean((MLP(X) - T)^2); *loss_host (may be NULL) gets the
+ * loss before the step.  Synchronizes. */
+int mds_mlp_train_step(mds_mlp *M, const float *X, const float *T, int32_t batch, float lr,
+                       double *loss_host);
 
 #ifdef __cplusplus
 }

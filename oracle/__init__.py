@@ -106,6 +106,9 @@ def lib():
         L.or_ipm.argtypes = [P, C.POINTER(OrIpmOpts), _dp, _dp, _dp, _dp, _ip,
                              C.POINTER(OrIpmTrace)]
         L.or_ipm.restype = C.c_int
+        L.or_ipm_warm.argtypes = [P, C.POINTER(OrIpmOpts), _dp, _dp, C.c_double, _dp, _dp, _dp,
+                                  _dp, _ip, C.POINTER(OrIpmTrace)]
+        L.or_ipm_warm.restype = C.c_int
         _lib = L
     return _lib
 
@@ -356,14 +359,23 @@ def theta(P: Problem, x):
 IPM_STATUS = {4: "converged", 5: "ls_fail", 6: "maxiter", 2: "inertia_fail", 7: "nonfinite"}
 
 
-def ipm(P: Problem, tol=1e-8, mu0=0.1, max_iter=200, refine_steps=2, dw_max=1e20):
-    """Whole filter line-search IPM.  Returns dict with x, y, zl, zu, status, iters, trace."""
+def ipm(P: Problem, tol=1e-8, mu0=0.1, max_iter=200, refine_steps=2, dw_max=1e20,
+        warm=None):
+    """Whole filter line-search IPM.  warm: None (cold start) or a dict with
+    x_d, y and mu0 (warm start).  Returns dict with x, y, zl, zu, status,
+    iters, trace."""
     n = P.n_d + P.n_s
     x, zl, zu, y = _buf(n), _buf(n), _buf(n), _buf(P.m)
     it = np.zeros(1, dtype=np.int32)
     opts = OrIpmOpts(tol, mu0, max_iter, refine_steps, dw_max)
     tr = (OrIpmTrace * (max_iter + 1))()
-    st = lib().or_ipm(P.ptr, C.byref(opts), _d(x), _d(y), _d(zl), _d(zu), _i(it), tr)
+    if warm is None:
+        st = lib().or_ipm(P.ptr, C.byref(opts), _d(x), _d(y), _d(zl), _d(zu), _i(it), tr)
+    else:
+        xd0 = _f64(warm["x_d"]) if P.n_d else _buf(1)
+        y0 = _f64(warm["y"]) if P.m else _buf(1)
+        st = lib().or_ipm_warm(P.ptr, C.byref(opts), _d(xd0), _d(y0), float(warm["mu0"]),
+                               _d(x), _d(y), _d(zl), _d(zu), _i(it), tr)
     iters = int(it[0])
     rows = []
     for k in range(min(iters + 1, max_iter)):

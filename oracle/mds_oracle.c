@@ -595,8 +595,64 @@ double or_theta(const orq_problem *P, const double *x) {
 
 typedef struct { double th, ph; } fentry;
 
+/* Start point of a warm start (a reading of our own; the paper has no warm
+ * start): the proposed x_d and y; x_s from the stationarity of the separable
+ * sparse block without bound multipliers, x_s = -(g + J_s' y) / w where
+ * w > 0 (else 0); every x_i then projected into the interior of its bounds by
+ * the same kappa_1/kappa_2 rule as the cold start; z_l = mu0 / (x - l),
+ * z_u = mu0 / (u - x) on finite bounds (0 otherwise). */
+static void warm_point(const orq_problem *P, const double *xd0, const double *y0, double mu0,
+                       double *x, double *y, double *zl, double *zu) {
+  const int nd = P->n_d, ns = P->n_s, m = P->m, n = nd + ns;
+  const double kappa1 = 1e-2, kappa2 = 1e-2;
+  double *jty = (double *)calloc((size_t)(ns > 0 ? ns : 1), sizeof(double));
+  /* J_s' y, accumulated over rows in ascending order for every column */
+  for (int r = 0; r < m; ++r)
+    for (int a = P->rp[r]; a < P->rp[r + 1]; ++a) jty[P->ci[a]] = jty[P->ci[a]] + P->v[a] * y0[r];
+  for (int i = 0; i < n; ++i) {
+    double xi;
+    if (i < nd) xi = xd0[i];
+    else {
+      const double wi = P->w[i - nd];
+      xi = (wi > 0.0) ? -(P->g[i - nd] + jty[i - nd]) / wi : 0.0;
+    }
+    double l = P->xl[i], u = P->xu[i];
+    int hl = isfinite(l), hu = isfinite(u);
+    if (hl && hu) {
+      double pl = fmin(kappa1 * fmax(1.0, fabs(l)), kappa2 * (u - l));
+      double pu = fmin(kappa1 * fmax(1.0, fabs(u)), kappa2 * (u - l));
+      xi = fmin(fmax(xi, l + pl), u - pu);
+    } else if (hl) {
+      xi = fmax(xi, l + kappa1 * fmax(1.0, fabs(l)));
+    } else if (hu) {
+      xi = fmin(xi, u - kappa1 * fmax(1.0, fabs(u)));
+    }
+    x[i] = xi;
+    zl[i] = hl ? mu0 / (xi - l) : 0.0;
+    zu[i] = hu ? mu0 / (u - xi) : 0.0;
+  }
+  for (int r = 0; r < m; ++r) y[r] = y0[r];
+  free(jty);
+}
+
+static int ipm_from(const orq_problem *P, const or_ipm_opts *o, const double *xd0,
+                    const double *y0, double mu0_warm, double *x, double *y, double *zl,
+                    double *zu, int32_t *iters, or_ipm_trace *trace);
+
 int or_ipm(const orq_problem *P, const or_ipm_opts *o, double *x, double *y, double *zl,
            double *zu, int32_t *iters, or_ipm_trace *trace) {
+  return ipm_from(P, o, NULL, NULL, 0.0, x, y, zl, zu, iters, trace);
+}
+
+int or_ipm_warm(const orq_problem *P, const or_ipm_opts *o, const double *xd0, const double *y0,
+                double mu0, double *x, double *y, double *zl, double *zu, int32_t *iters,
+                or_ipm_trace *trace) {
+  return ipm_from(P, o, xd0, y0, mu0, x, y, zl, zu, iters, trace);
+}
+
+static int ipm_from(const orq_problem *P, const or_ipm_opts *o, const double *xd0,
+                    const double *y0, double mu0_warm, double *x, double *y, double *zl,
+                    double *zu, int32_t *iters, or_ipm_trace *trace) {
   const int nd = P->n_d, ns = P->n_s, m = P->m, n = nd + ns;
   /* Waechter & Biegler (2006) defaults */
   const double tau_min = 0.99, kappa_eps = 10.0, kappa_mu = 0.2, theta_mu = 1.5;
@@ -623,7 +679,12 @@ int or_ipm(const orq_problem *P, const or_ipm_opts *o, double *x, double *y, dou
     zu[i] = hu ? 1.0 : 0.0;
   }
   for (int r = 0; r < m; ++r) y[r] = 0.0;
-  double mu = o->mu0, tau = fmax(tau_min, 1.0 - mu), dw_last = 0.0;
+  double mu = o->mu0;
+  if (xd0) {
+    warm_point(P, xd0, y0, mu0_warm, x, y, zl, zu);
+    mu = mu0_warm;
+  }
+  double tau = fmax(tau_min, 1.0 - mu), dw_last = 0.0;
   double th0 = or_theta(P, x);
   double theta_max = 1e4 * fmax(1.0, th0), theta_min = 1e-4 * fmax(1.0, th0);
   fentry *filt = (fentry *)malloc(sizeof(fentry) * (size_t)(o->max_iter + 1));

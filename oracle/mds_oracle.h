@@ -150,6 +150,11 @@ typedef struct {       /* one row per iteration */
  * or hold max_iter rows. */
 int or_ipm(const orq_problem *P, const or_ipm_opts *o, double *x, double *y, double *zl,
            double *zu, int32_t *iters, or_ipm_trace *trace);
+/* The same IPM from a warm start: proposed x_d (n_d), y (m) and barrier
+ * parameter mu0 (see warm_point in mds_oracle.c for the completed point). */
+int or_ipm_warm(const orq_problem *P, const or_ipm_opts *o, const double *xd0, const double *y0,
+                double mu0, double *x, double *y, double *zl, double *zu, int32_t *iters,
+                or_ipm_trace *trace);
 
 #ifdef __cplusplus
 }

@@ -37,7 +37,7 @@ class Dims(C.Structure):
 
 class Options(C.Structure):
     _fields_ = [("nb", C.c_int32), ("panel", C.c_int32), ("precision", C.c_int32),
-                ("reserved", C.c_int32 * 5)]
+                ("panel_threads", C.c_int32), ("reserved", C.c_int32 * 4)]
 
 
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2}
@@ -87,7 +87,8 @@ T_CLASSES = ("condense", "panel", "trailing", "solve", "permute")
 
 class Info(C.Structure):
     _fields_ = [("nb", C.c_int32), ("min_width", C.c_int32), ("panel", C.c_int32),
-                ("precision", C.c_int32), ("workspace_bytes", C.c_int64)]
+                ("precision", C.c_int32), ("panel_threads", C.c_int32), ("pad", C.c_int32),
+                ("workspace_bytes", C.c_int64)]
 
 
 class BatchProblem(C.Structure):
@@ -132,6 +133,8 @@ SIGNATURES = {
     "mds_merit": (C.c_int, [_vp, _vp, C.c_double, _dp, _dp, _dp]),
     "mds_ipm_init": (C.c_int, [_vp, C.POINTER(Iterate), C.POINTER(IpmOpts)]),
     "mds_ipm_step": (C.c_int, [_vp, C.POINTER(Iterate), C.POINTER(StepInfo)]),
+    "mds_ipm_init_warm": (C.c_int, [_vp, C.POINTER(Iterate), C.POINTER(IpmOpts), _vp, _vp,
+                                    C.c_double]),
     "mds_ipm_solve": (C.c_int, [_vp, C.POINTER(Iterate), C.POINTER(IpmOpts),
                                 C.POINTER(StepInfo), C.c_int32, _ip]),
     "mds_get_matrix": (C.c_int, [_vp, _dp]),
@@ -148,6 +151,16 @@ SIGNATURES = {
     "mds_batch_autotune": (C.c_int, [_vp, C.c_double, C.POINTER(BatchOpts)]),
     "mds_batch_get_config": (C.c_int, [_vp, C.POINTER(BatchOpts)]),
     "mds_batch_destroy": (None, [_vp]),
+    "mds_batch_last_error": (C.c_char_p, [_vp]),
+    "mds_mlp_workspace_bytes": (C.c_size_t, [_ip, C.c_int32]),
+    "mds_mlp_create": (C.c_int, [C.POINTER(_vp), _ip, C.c_int32, _vp, _vp, C.c_size_t]),
+    "mds_mlp_destroy": (None, [_vp]),
+    "mds_mlp_param_count": (C.c_int32, [_vp]),
+    "mds_mlp_set_params": (C.c_int, [_vp, C.POINTER(C.c_float)]),
+    "mds_mlp_get_params": (C.c_int, [_vp, C.POINTER(C.c_float)]),
+    "mds_mlp_get_grad": (C.c_int, [_vp, C.POINTER(C.c_float)]),
+    "mds_mlp_forward": (C.c_int, [_vp, _vp, C.c_int32, C.c_int32, _vp]),
+    "mds_mlp_train_step": (C.c_int, [_vp, _vp, _vp, C.c_int32, C.c_float, _dp]),
     "mds_status_string": (C.c_char_p, [C.c_int]),
     "mds_last_error": (C.c_char_p, [_vp]),
 }
@@ -190,7 +203,7 @@ class Solver:
 
     def __init__(self, n_d: int, n_s: int, m: int, nnz_s: int, nb: int = 0,
                  device: str = "cuda:0", stream=None, panel: str = "auto",
-                 precision: str = "fp64"):
+                 precision: str = "fp64", panel_threads: int = 0):
         torch = _torch()
         if not torch.cuda.is_available():
             raise MdsError("no ROCm GPU visible: the mdsipm library has no CPU path")
@@ -200,7 +213,10 @@ class Solver:
         if precision not in PRECISIONS:
             raise MdsError(f"precision must be one of {sorted(PRECISIONS)}")
         self.precision = precision
-        self.opts = Options(nb, 1 if panel == "mem" else 0, PRECISIONS[precision])
+        if panel not in ("auto", "mem", "reg"):
+            raise MdsError("panel must be 'auto', 'mem' or 'reg'")
+        self.opts = Options(nb, {"auto": 0, "mem": 1, "reg": 2}[panel], PRECISIONS[precision],
+                            int(panel_threads))
         self.n_d, self.n_s, self.m = n_d, n_s, m
         self.N, self.n = n_d + m, n_d + n_s
         L = lib()
@@ -363,6 +379,25 @@ class Solver:
         self._check(st, "mds_ipm_step")
         return st, _step_dict(info)
 
+    def ipm_solve_warm(self, x_d0, y0, mu0, tol=1e-8, max_iter=200, refine_steps=2,
+                       dw_max=1e20):
+        """IPM from a proposed start (mds_ipm_init_warm), stepped to the end."""
+        it = self.new_iterate()
+        xd, yy = self.dev(x_d0), self.dev(y0)
+        self._opts = IpmOpts(tol, float(mu0), max_iter, refine_steps, dw_max)
+        st = lib().mds_ipm_init_warm(self.h, C.byref(it["c"]), C.byref(self._opts), _ptr(xd),
+                                     _ptr(yy), float(mu0))
+        self._check(st, "mds_ipm_init_warm")
+        trace = []
+        while True:
+            code, info = self.ipm_step(it)
+            trace.append(info)
+            if code != 0:
+                break
+        return dict(status=STATUS_NAMES.get(code, code), code=code, iters=it["c"].iter,
+                    trace=trace, x=it["x"], y=it["y"], zl=it["zl"], zu=it["zu"],
+                    mu=it["c"].mu)
+
     def ipm_solve(self, it=None, tol=1e-8, mu0=0.1, max_iter=200, refine_steps=2, dw_max=1e20):
         it = it if it is not None else self.new_iterate()
         opts = IpmOpts(tol, mu0, max_iter, refine_steps, dw_max)
@@ -382,7 +417,8 @@ class Solver:
         self._check(lib().mds_get_info(self.h, C.byref(i)), "mds_get_info")
         prec = {v: k for k, v in PRECISIONS.items()}[i.precision]
         return dict(nb=i.nb, min_width=i.min_width, panel="reg" if i.panel == 0 else "mem",
-                    precision=prec, workspace_bytes=i.workspace_bytes)
+                    precision=prec, panel_threads=i.panel_threads,
+                    workspace_bytes=i.workspace_bytes)
 
     # ---- timing ---------------------------------------------------------
     def set_timing(self, enable: bool):
@@ -432,10 +468,10 @@ def _step_dict(s):
 
 
 def solver_for(prob: dict, nb: int = 0, device: str = "cuda:0", panel: str = "auto",
-               precision: str = "fp64") -> Solver:
+               precision: str = "fp64", panel_threads: int = 0) -> Solver:
     """Create a Solver sized for a problem dict and attach the problem."""
     s = Solver(prob["n_d"], prob["n_s"], prob["m"], len(prob["v"]), nb=nb, device=device,
-               panel=panel, precision=precision)
+               panel=panel, precision=precision, panel_threads=panel_threads)
     s.set_problem(prob)
     return s
 
@@ -513,7 +549,8 @@ class Batch:
         res = (BatchResult * self.count)()
         st = lib().mds_batch_run(self.h, float(mu), res)
         if st != 0:
-            raise MdsError(f"mds_batch_run: {lib().mds_status_string(st).decode()}")
+            raise MdsError(f"mds_batch_run: {lib().mds_status_string(st).decode()} "
+                           f"({lib().mds_batch_last_error(self.h).decode()})")
         return [dict(inertia=(r.npos, r.nzero, r.nneg), trials=r.trials, delta_w=r.delta_w,
                      delta_c=r.delta_c, t_start=r.t_start, t_done=r.t_done, status=r.status,
                      slot=r.slot) for r in res]
@@ -522,7 +559,8 @@ class Batch:
         o = BatchOpts()
         st = lib().mds_batch_autotune(self.h, float(mu), C.byref(o))
         if st != 0:
-            raise MdsError(f"mds_batch_autotune: {lib().mds_status_string(st).decode()}")
+            raise MdsError(f"mds_batch_autotune: {lib().mds_status_string(st).decode()} "
+                           f"({lib().mds_batch_last_error(self.h).decode()})")
         return dict(nb=o.nb, grid=o.grid, use_graph=bool(o.use_graph))
 
     def config(self):
@@ -532,3 +570,81 @@ class Batch:
 
     def solution(self, p):
         return [t.detach().cpu().numpy() for t in self.out[p]]
+
+
+class MLP:
+    """The warm-start perceptron (mds_mlp_*): dims = (in, h, h, out)."""
+
+    def __init__(self, dims, max_batch, device="cuda:0"):
+        torch = _torch()
+        if not torch.cuda.is_available():
+            raise MdsError("no ROCm GPU visible: the mdsipm library has no CPU path")
+        self.torch, self.device = torch, torch.device(device)
+        self.dims = (C.c_int32 * 4)(*[int(d) for d in dims])
+        self.max_batch = int(max_batch)
+        L = lib()
+        nbytes = L.mds_mlp_workspace_bytes(self.dims, self.max_batch)
+        if nbytes == 0:
+            raise MdsError("invalid MLP dimensions")
+        with torch.cuda.device(self.device):
+            self.stream = torch.cuda.current_stream(self.device)
+            self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+            aligned = (self.ws.data_ptr() + 255) & ~255
+            h = C.c_void_p()
+            st = L.mds_mlp_create(C.byref(h), self.dims, self.max_batch,
+                                  C.c_void_p(self.stream.cuda_stream), C.c_void_p(aligned), nbytes)
+        if st != 0:
+            raise MdsError(f"mds_mlp_create: {L.mds_status_string(st).decode()}")
+        self.h = h
+        self.nparam = L.mds_mlp_param_count(h)
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().mds_mlp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _f32(self, a):
+        t = self.torch.as_tensor(np.ascontiguousarray(a, dtype=np.float32))
+        return t.to(self.device).contiguous()
+
+    def set_params(self, p):
+        p = np.ascontiguousarray(p, dtype=np.float32)
+        assert p.size == self.nparam
+        st = lib().mds_mlp_set_params(self.h, p.ctypes.data_as(C.POINTER(C.c_float)))
+        if st != 0:
+            raise MdsError("mds_mlp_set_params failed")
+
+    def get_params(self):
+        p = np.empty(self.nparam, dtype=np.float32)
+        lib().mds_mlp_get_params(self.h, p.ctypes.data_as(C.POINTER(C.c_float)))
+        return p
+
+    def get_grad(self):
+        p = np.empty(self.nparam, dtype=np.float32)
+        lib().mds_mlp_get_grad(self.h, p.ctypes.data_as(C.POINTER(C.c_float)))
+        return p
+
+    def forward(self, X, precision="fp32"):
+        Xd = X if isinstance(X, self.torch.Tensor) else self._f32(X)
+        B = Xd.shape[0]
+        Y = self.torch.empty((B, self.dims[3]), dtype=self.torch.float32, device=self.device)
+        st = lib().mds_mlp_forward(self.h, _ptr(Xd), B, PRECISIONS[precision], _ptr(Y))
+        if st != 0:
+            raise MdsError(f"mds_mlp_forward: {lib().mds_status_string(st).decode()}")
+        return Y
+
+    def train_step(self, X, T, lr):
+        Xd = X if isinstance(X, self.torch.Tensor) else self._f32(X)
+        Td = T if isinstance(T, self.torch.Tensor) else self._f32(T)
+        loss = C.c_double()
+        st = lib().mds_mlp_train_step(self.h, _ptr(Xd), _ptr(Td), Xd.shape[0], float(lr),
+                                      C.byref(loss))
+        if st != 0:
+            raise MdsError(f"mds_mlp_train_step: {lib().mds_status_string(st).decode()}")
+        return loss.value

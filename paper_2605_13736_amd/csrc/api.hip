@@ -155,29 +155,42 @@ bool dims_ok(const mds_dims *d) {
          d->nnz_s < ((int64_t)1 << 30);
 }
 
-// Panel choice: the register-resident kernel for N <= 4096 (panel width up
-// to its register tile), else the kernel that keeps the panel in memory.
 struct PanelChoice {
   bool reg;
-  int nb, adv;
+  int nb, adv, threads;
 };
 
+// workgroup size of the register panel: the option, else 512
+int panel_threads_of(const mds_options *o) {
+  return (o && o->panel_threads == 1024) ? 1024 : 512;
+}
+
+// Panel choice.  panel option 1: memory panel; 2: register panel (N <= 4096);
+// 0 (automatic): the register panel while its tile keeps nb >= 16
+// (N <= 2048 with 512 threads), else the memory panel, whose wider panels
+// cost less trailing-update traffic than the register panel's nb = 8 at
+// N = 4096.  The mixed-precision modes need the register panel.
 PanelChoice panel_of(const mds_dims &d, const mds_options *o) {
   const int N = d.n_d + d.m;
-  const bool force_mem = o && o->panel == 1;
-  const int rnb = bk_reg_nb(N);
+  const int popt = o ? o->panel : 0;
+  const int thr = panel_threads_of(o);
+  const int rnb = bk_reg_nb(N, thr);
   PanelChoice c{};
   const int prec = o ? o->precision : MDS_FP64;
   if (prec != MDS_FP64 && prec != MDS_FP32 && prec != MDS_BF16) return c;  // nb = 0: invalid
-  if (prec != MDS_FP64 && (rnb == 0 || force_mem)) return c;
-  if (rnb > 0 && !force_mem) {
+  if (popt < 0 || popt > 2) return c;
+  if (prec != MDS_FP64 && (rnb == 0 || popt == 1)) return c;
+  if (popt == 2 && rnb == 0) return c;
+  const bool use_reg =
+      rnb > 0 && (popt == 2 || prec != MDS_FP64 || (popt == 0 && rnb >= 16));
+  if (use_reg) {
     int nb = (o && o->nb > 0) ? o->nb : rnb;
     nb = std::min(std::max(nb, 2), rnb);
-    c = {true, nb, std::max(nb - 1, 1)};
+    c = {true, nb, std::max(nb - 1, 1), thr};
   } else {
     int nb = (o && o->nb > 0) ? o->nb : default_nb(N);
     nb = std::min(std::max(nb, 2), kMaxNb);
-    c = {false, nb, nb};
+    c = {false, nb, nb, 0};
   }
   return c;
 }
@@ -224,7 +237,8 @@ int factor_impl(mds_handle *h, mds_inertia *out) {
       float *Y = h->w.X32[(b + 1) & 1];
       {
         TimedLaunch t(h, MDS_T_PANEL);
-        launch_bk_panel_reg(S(h), N, h->nb, h->alpha_bk, X, h->w.M, h->w.src, h->w.W, h->w.dd,
+        launch_bk_panel_reg(S(h), h->panel_threads, N, h->nb, h->alpha_bk, X, h->w.M, h->w.src,
+                            h->w.W, h->w.dd,
                             h->w.ds, h->w.ipiv, h->w.blk, h->w.fst, h->w.panel_k0);
       }
       if ((long)N - (long)(b + 1) * h->adv > 0) {
@@ -243,7 +257,8 @@ int factor_impl(mds_handle *h, mds_inertia *out) {
     {
       TimedLaunch t(h, MDS_T_PANEL);
       if (h->panel_reg)
-        launch_bk_panel_reg(S(h), N, h->nb, h->alpha_bk, X, Y, h->w.src, h->w.W, h->w.dd,
+        launch_bk_panel_reg(S(h), h->panel_threads, N, h->nb, h->alpha_bk, X, Y, h->w.src, h->w.W,
+                            h->w.dd,
                             h->w.ds, h->w.ipiv, h->w.blk, h->w.fst, h->w.panel_k0);
       else
         launch_bk_panel(S(h), N, h->nb, h->alpha_bk, h->w.M, h->w.W, h->w.dd, h->w.ds,
@@ -708,6 +723,7 @@ int mds_create(mds_handle **out, const mds_dims *dims, const mds_options *opts, 
   const PanelChoice pc = panel_of(*dims, opts);
   h->nb = nb;
   h->panel_reg = pc.reg;
+  h->panel_threads = pc.threads;
   h->precision = prec;
   h->adv = pc.adv;
   h->max_panels = h->N / pc.adv + 2;
@@ -928,6 +944,32 @@ int mds_ipm_init(mds_handle *h, mds_iterate *it, const mds_ipm_opts *opts) {
   return MDS_OK;
 }
 
+int mds_ipm_init_warm(mds_handle *h, mds_iterate *it, const mds_ipm_opts *opts,
+                      const double *x_d0, const double *y0, double mu0) {
+  TRY(check_ready(h));
+  if (!it || (h->n > 0 && (!it->x || !it->zl || !it->zu)) || (MM(h) > 0 && !it->y))
+    return set_err(h, MDS_ENULL, "iterate missing");
+  if ((ND(h) > 0 && !x_d0) || (MM(h) > 0 && !y0)) return set_err(h, MDS_ENULL, "start point missing");
+  if (!(mu0 > 0.0) || !std::isfinite(mu0)) return set_err(h, MDS_EINVAL, "mu0 must be positive");
+  mds_ipm_opts o{1e-8, 0.1, 200, 2, 1e20};
+  if (opts) o = *opts;
+  h->ipm = o;
+  ipm_init_warm(S(h), ND(h), NS(h), MM(h), h->P.xl, h->P.xu, h->P.w, h->P.g, h->w.csc_ptr,
+                h->w.csc_row, h->w.csc_val, x_d0, y0, mu0, it->x, it->y, it->zl, it->zu);
+  HIPCHK(hipGetLastError());
+  it->mu = mu0;
+  it->tau = std::max(0.99, 1.0 - it->mu);
+  it->iter = 0;
+  h->dw_last = 0.0;
+  h->filter.clear();
+  double th0 = 0.0;
+  TRY(merit_impl(h, it->x, it->mu, nullptr, nullptr, &th0));
+  h->theta_max = 1e4 * std::max(1.0, th0);
+  h->theta_min = 1e-4 * std::max(1.0, th0);
+  h->ipm_ready = true;
+  return MDS_OK;
+}
+
 int mds_ipm_step(mds_handle *h, mds_iterate *it, mds_step_info *info) {
   TRY(check_ready(h));
   if (!h->ipm_ready) return set_err(h, MDS_ESTATE, "mds_ipm_init must precede mds_ipm_step");
@@ -1116,6 +1158,7 @@ int mds_get_info(const mds_handle *h, mds_info *out) {
   out->min_width = h->adv;
   out->panel = h->panel_reg ? 0 : 1;
   out->precision = h->precision;
+  out->panel_threads = h->panel_reg ? h->panel_threads : 1024;
   out->workspace_bytes = (int64_t)h->ws_bytes;
   return MDS_OK;
 }

@@ -11,6 +11,7 @@
 // chooses the panel width and the grid by timing candidates (autotune).
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -422,7 +423,8 @@ __global__ __launch_bounds__(BT) void k_batch(int count, const int32_t *__restri
 }  // namespace
 
 struct mds_batch_impl {
-  hipStream_t stream = nullptr;
+  hipStream_t caller = nullptr;  // the caller's stream (inputs are ordered on it)
+  hipStream_t stream = nullptr;  // the batch's own stream (capturable)
   int count = 0, Nmax = 0, nsmax = 0, nslots = 0;
   int nb = BNB, grid = 0;
   bool use_graph = true;
@@ -483,12 +485,18 @@ bool batch_layout(const mds_batch_problem *ps, int count, const mds_batch_opts *
   return true;
 }
 
+int fail(mds_batch_impl *b, int code, const char *what, hipError_t e) {
+  snprintf(b->err, sizeof(b->err), "%s: %s", what, hipGetErrorString(e));
+  return code;
+}
+
 int launch_batch(mds_batch_impl *b) {
   k_batch_reset<<<1, 64, 0, b->stream>>>(b->d_queue, b->d_t0);
   k_batch<<<(unsigned)b->grid, BT, 0, b->stream>>>(b->count, b->d_order, b->d_probs, b->d_slots,
                                                     b->nb, b->alpha, b->d_dc, b->d_queue, b->d_t0,
                                                     b->d_results);
-  return hipGetLastError() == hipSuccess ? MDS_OK : MDS_EHIP;
+  const hipError_t e = hipGetLastError();
+  return e == hipSuccess ? MDS_OK : fail(b, MDS_EHIP, "batch launch", e);
 }
 
 int run_once(mds_batch_impl *b) {
@@ -498,17 +506,21 @@ int run_once(mds_batch_impl *b) {
     if (b->graph) (void)hipGraphDestroy(b->graph);
     b->gexec = nullptr;
     b->graph = nullptr;
-    if (hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
-      return MDS_EHIP;
+    hipError_t e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return fail(b, MDS_EHIP, "hipStreamBeginCapture", e);
     const int st = launch_batch(b);
     hipGraph_t g = nullptr;
-    if (hipStreamEndCapture(b->stream, &g) != hipSuccess || st != MDS_OK) return MDS_EHIP;
+    e = hipStreamEndCapture(b->stream, &g);
+    if (e != hipSuccess) return fail(b, MDS_EHIP, "hipStreamEndCapture", e);
+    if (st != MDS_OK) return st;
     b->graph = g;
-    if (hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0) != hipSuccess) return MDS_EHIP;
+    e = hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) return fail(b, MDS_EHIP, "hipGraphInstantiate", e);
     b->g_nb = b->nb;
     b->g_grid = b->grid;
   }
-  return hipGraphLaunch(b->gexec, b->stream) == hipSuccess ? MDS_OK : MDS_EHIP;
+  const hipError_t e = hipGraphLaunch(b->gexec, b->stream);
+  return e == hipSuccess ? MDS_OK : fail(b, MDS_EHIP, "hipGraphLaunch", e);
 }
 
 }  // namespace
@@ -545,7 +557,11 @@ int mds_batch_create(mds_batch **out, const mds_batch_problem *probs_host, int32
   }
   mds_batch *b = new (std::nothrow) mds_batch();
   if (!b) return MDS_EINVAL;
-  b->stream = (hipStream_t)stream;
+  b->caller = (hipStream_t)stream;
+  if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess) {
+    delete b;
+    return MDS_EHIP;
+  }
   b->count = count;
   b->Nmax = L.Nmax;
   b->nsmax = L.nsmax;
@@ -571,7 +587,7 @@ int mds_batch_create(mds_batch **out, const mds_batch_problem *probs_host, int32
   char *csc_base = base + o;
   o += L.csc_total;
   std::vector<ProbDev> hp(count);
-  hipStream_t s = b->stream;
+  hipStream_t s = b->caller;
   for (int p = 0; p < count; ++p) {
     const mds_batch_problem &q = probs_host[p];
     char *c = csc_base + L.csc_off[p];
@@ -648,6 +664,7 @@ int mds_batch_create(mds_batch **out, const mds_batch_problem *probs_host, int32
                            s) == hipSuccess &&
             hipGetLastError() == hipSuccess && hipStreamSynchronize(s) == hipSuccess;
   if (!ok) {
+    (void)hipStreamDestroy(b->stream);
     delete b;
     return MDS_EHIP;
   }
@@ -660,9 +677,12 @@ int mds_batch_run(mds_batch *b, double mu, mds_batch_result *results_host) {
   if (!b) return MDS_ENULL;
   if (!(mu >= 0.0)) return MDS_EINVAL;
   const double dc = 1e-8 * std::pow(mu, 0.25);
-  if (hipMemcpyAsync(b->d_dc, &dc, 8, hipMemcpyHostToDevice, b->stream) != hipSuccess)
-    return MDS_EHIP;
-  if (hipStreamSynchronize(b->stream) != hipSuccess) return MDS_EHIP;
+  // inputs and outputs are ordered on the caller's stream
+  hipError_t e = hipStreamSynchronize(b->caller);
+  if (e != hipSuccess) return fail(b, MDS_EHIP, "caller stream", e);
+  e = hipMemcpyAsync(b->d_dc, &dc, 8, hipMemcpyHostToDevice, b->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+  if (e != hipSuccess) return fail(b, MDS_EHIP, "batch parameters", e);
   int st = run_once(b);
   if (st != MDS_OK) return st;
   unsigned long long t0 = 0;
@@ -740,10 +760,13 @@ int mds_batch_get_config(const mds_batch *b, mds_batch_opts *out_host) {
   return MDS_OK;
 }
 
+const char *mds_batch_last_error(const mds_batch *b) { return b ? b->err : "null batch"; }
+
 void mds_batch_destroy(mds_batch *b) {
   if (!b) return;
   if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->stream) (void)hipStreamDestroy(b->stream);
   delete b;
 }
 

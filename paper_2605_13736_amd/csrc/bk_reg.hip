@@ -24,52 +24,62 @@ __global__ __launch_bounds__(T) void k_bk_panel_reg(int N, int nb, double alpha,
 
 }  // namespace
 
-// Panel variant for a matrix of order N: 512 threads and R rows per thread
-// (R * 512 >= N), with the register tile NB chosen so that R * NB <= 64
-// doubles of L per thread.
-int bk_reg_rows(int N) {
-  for (int r = 1; r <= 8; r *= 2)
-    if (N <= r * TMAX) return r;
+// Panel variant for a matrix of order N and a workgroup of T threads (512 or
+// 1024): R rows per thread with R * T >= N, and the register tile NB chosen
+// so that R * NB = 64 doubles of L per thread at T = 512 (VGPR budget 256)
+// and 32 at T = 1024 (budget 128).
+int bk_reg_rows(int N, int threads) {
+  const int T = (threads == 1024) ? 1024 : TMAX;
+  const int rmax = (T == 1024) ? 4 : 8;
+  for (int r = 1; r <= rmax; r *= 2)
+    if (N <= r * T) return r;
   return 0;
 }
 
-int bk_reg_nb(int N) {
-  switch (bk_reg_rows(N)) {
-    case 1: return 32;
-    case 2: return 32;
-    case 4: return 16;
-    case 8: return 8;
-    default: return 0;
-  }
+int bk_reg_nb(int N, int threads) {
+  const int r = bk_reg_rows(N, threads);
+  if (r == 0) return 0;
+  if (threads == 1024) return 32 / r;
+  return (r == 1) ? 32 : 64 / r;
 }
 
 template <typename TX>
-static void panel_reg(hipStream_t s, int N, int nb, double alpha, const TX *X, double *Lout,
-                      int32_t *src_out, double *W, double *dd, double *ds, int32_t *ipiv,
-                      int32_t *blk, FacState *st, int32_t *panel_k0) {
-#define MDS_PANEL_REG(R_, NB_)                                                                \
-  k_bk_panel_reg<TMAX, R_, NB_, TX><<<1, TMAX, 0, s>>>(N, nb, alpha, X, Lout, src_out, W, dd, \
-                                                       ds, ipiv, blk, st, panel_k0)
-  switch (bk_reg_rows(N)) {
-    case 1: MDS_PANEL_REG(1, 32); break;
-    case 2: MDS_PANEL_REG(2, 32); break;
-    case 4: MDS_PANEL_REG(4, 16); break;
-    case 8: MDS_PANEL_REG(8, 8); break;
-    default: break;
+static void panel_reg(hipStream_t s, int threads, int N, int nb, double alpha, const TX *X,
+                      double *Lout, int32_t *src_out, double *W, double *dd, double *ds,
+                      int32_t *ipiv, int32_t *blk, FacState *st, int32_t *panel_k0) {
+#define MDS_PANEL_REG(T_, R_, NB_)                                                             \
+  k_bk_panel_reg<T_, R_, NB_, TX><<<1, T_, 0, s>>>(N, nb, alpha, X, Lout, src_out, W, dd, ds, \
+                                                   ipiv, blk, st, panel_k0)
+  const int r = bk_reg_rows(N, threads);
+  if (threads == 1024) {
+    switch (r) {
+      case 1: MDS_PANEL_REG(1024, 1, 32); break;
+      case 2: MDS_PANEL_REG(1024, 2, 16); break;
+      case 4: MDS_PANEL_REG(1024, 4, 8); break;
+      default: break;
+    }
+  } else {
+    switch (r) {
+      case 1: MDS_PANEL_REG(TMAX, 1, 32); break;
+      case 2: MDS_PANEL_REG(TMAX, 2, 32); break;
+      case 4: MDS_PANEL_REG(TMAX, 4, 16); break;
+      case 8: MDS_PANEL_REG(TMAX, 8, 8); break;
+      default: break;
+    }
   }
 #undef MDS_PANEL_REG
 }
 
-void launch_bk_panel_reg(hipStream_t s, int N, int nb, double alpha, const double *X,
+void launch_bk_panel_reg(hipStream_t s, int threads, int N, int nb, double alpha, const double *X,
                          double *Lout, int32_t *src_out, double *W, double *dd, double *ds,
                          int32_t *ipiv, int32_t *blk, FacState *st, int32_t *panel_k0) {
-  panel_reg(s, N, nb, alpha, X, Lout, src_out, W, dd, ds, ipiv, blk, st, panel_k0);
+  panel_reg(s, threads, N, nb, alpha, X, Lout, src_out, W, dd, ds, ipiv, blk, st, panel_k0);
 }
 
-void launch_bk_panel_reg(hipStream_t s, int N, int nb, double alpha, const float *X,
+void launch_bk_panel_reg(hipStream_t s, int threads, int N, int nb, double alpha, const float *X,
                          double *Lout, int32_t *src_out, double *W, double *dd, double *ds,
                          int32_t *ipiv, int32_t *blk, FacState *st, int32_t *panel_k0) {
-  panel_reg(s, N, nb, alpha, X, Lout, src_out, W, dd, ds, ipiv, blk, st, panel_k0);
+  panel_reg(s, threads, N, nb, alpha, X, Lout, src_out, W, dd, ds, ipiv, blk, st, panel_k0);
 }
 
 }  // namespace mds

@@ -72,6 +72,7 @@ struct mds_handle {
   mds_dims dims{};
   int N = 0, n = 0, nb = 16, max_panels = 0;
   bool panel_reg = false;  // register-resident panel kernel
+  int panel_threads = 512; // its workgroup size
   int precision = MDS_FP64;
   int adv = 16;            // least number of columns a panel factors
   mds::Work w{};
@@ -128,13 +129,14 @@ void launch_bk_trailing(hipStream_t s, int N, int nb, int adv, int slot, const d
                         const double *X, double *Y, const double *Lsrc, const int32_t *src,
                         const FacState *st, const int32_t *panel_k0);
 
-// bk_reg.hip: register-resident panel for N <= 4096 (X in FP64 or FP32)
-int bk_reg_rows(int N);
-int bk_reg_nb(int N);
-void launch_bk_panel_reg(hipStream_t s, int N, int nb, double alpha, const double *X,
+// bk_reg.hip: register-resident panel for N <= 4096 (X in FP64 or FP32),
+// workgroup of `threads` = 512 or 1024
+int bk_reg_rows(int N, int threads);
+int bk_reg_nb(int N, int threads);
+void launch_bk_panel_reg(hipStream_t s, int threads, int N, int nb, double alpha, const double *X,
                          double *Lout, int32_t *src_out, double *W, double *dd, double *ds,
                          int32_t *ipiv, int32_t *blk, FacState *st, int32_t *panel_k0);
-void launch_bk_panel_reg(hipStream_t s, int N, int nb, double alpha, const float *X,
+void launch_bk_panel_reg(hipStream_t s, int threads, int N, int nb, double alpha, const float *X,
                          double *Lout, int32_t *src_out, double *W, double *dd, double *ds,
                          int32_t *ipiv, int32_t *blk, FacState *st, int32_t *panel_k0);
 

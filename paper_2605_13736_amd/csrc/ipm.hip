@@ -43,6 +43,49 @@ __global__ void k_init_point(int n, int m, const double *__restrict__ xl,
   if (i < m) y[i] = 0.0;
 }
 
+// Warm start: x_d = xd0, x_s = -(g + J_s' y0) / w (w > 0; else 0), every x_i
+// projected into its bounds as in the cold start, y = y0, z = mu0 / slack on
+// finite bounds.  J_s' y0 is accumulated per column over its rows in
+// ascending order (CSC), as plain multiply-then-add.
+__global__ void k_init_warm(int nd, int ns, int m, const double *__restrict__ xl,
+                            const double *__restrict__ xu, const double *__restrict__ w,
+                            const double *__restrict__ g, const int32_t *__restrict__ cptr,
+                            const int32_t *__restrict__ crow, const double *__restrict__ cval,
+                            const double *__restrict__ xd0, const double *__restrict__ y0,
+                            double mu0, double *__restrict__ x, double *__restrict__ y,
+                            double *__restrict__ zl, double *__restrict__ zu) {
+  const double kappa1 = 1e-2, kappa2 = 1e-2;
+  const int n = nd + ns;
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    double xi;
+    if (i < nd) {
+      xi = xd0[i];
+    } else {
+      const int k = i - nd;
+      double t = 0.0;
+      for (int e = cptr[k]; e < cptr[k + 1]; ++e) t = t + cval[e] * y0[crow[e]];
+      const double wk = w[k];
+      xi = (wk > 0.0) ? -(g[k] + t) / wk : 0.0;
+    }
+    const double l = xl[i], u = xu[i];
+    const bool hl = isfinite(l), hu = isfinite(u);
+    if (hl && hu) {
+      const double pl = fmin(kappa1 * fmax(1.0, fabs(l)), kappa2 * (u - l));
+      const double pu = fmin(kappa1 * fmax(1.0, fabs(u)), kappa2 * (u - l));
+      xi = fmin(fmax(xi, l + pl), u - pu);
+    } else if (hl) {
+      xi = fmax(xi, l + kappa1 * fmax(1.0, fabs(l)));
+    } else if (hu) {
+      xi = fmin(xi, u - kappa1 * fmax(1.0, fabs(u)));
+    }
+    x[i] = xi;
+    zl[i] = hl ? mu0 / (xi - l) : 0.0;
+    zu[i] = hu ? mu0 / (u - xi) : 0.0;
+  }
+  if (i < m) y[i] = y0[i];
+}
+
 // gf[0:nd] holds H x_d on entry; gradient of f completed in place.
 __global__ void k_grad_finish(int nd, int ns, const double *__restrict__ c,
                               const double *__restrict__ w, const double *__restrict__ g,
@@ -416,6 +459,16 @@ void ipm_init_point(hipStream_t s, int n, int m, const double *xl, const double 
   const int len = n > m ? n : m;
   if (len <= 0) return;
   k_init_point<<<grid1(len, 256), 256, 0, s>>>(n, m, xl, xu, x, y, zl, zu);
+}
+
+void ipm_init_warm(hipStream_t s, int nd, int ns, int m, const double *xl, const double *xu,
+                   const double *w, const double *g, const int32_t *cptr, const int32_t *crow,
+                   const double *cval, const double *xd0, const double *y0, double mu0,
+                   double *x, double *y, double *zl, double *zu) {
+  const int len = (nd + ns) > m ? (nd + ns) : m;
+  if (len <= 0) return;
+  k_init_warm<<<grid1(len, 256), 256, 0, s>>>(nd, ns, m, xl, xu, w, g, cptr, crow, cval, xd0, y0,
+                                              mu0, x, y, zl, zu);
 }
 
 void ipm_grad_finish(hipStream_t s, int nd, int ns, const double *c, const double *w,

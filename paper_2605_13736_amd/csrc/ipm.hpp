@@ -9,6 +9,10 @@ namespace mds {
 
 void ipm_init_point(hipStream_t s, int n, int m, const double *xl, const double *xu, double *x,
                     double *y, double *zl, double *zu);
+void ipm_init_warm(hipStream_t s, int nd, int ns, int m, const double *xl, const double *xu,
+                   const double *w, const double *g, const int32_t *cptr, const int32_t *crow,
+                   const double *cval, const double *xd0, const double *y0, double mu0,
+                   double *x, double *y, double *zl, double *zu);
 void ipm_grad_finish(hipStream_t s, int nd, int ns, const double *c, const double *w,
                      const double *g, const double *x, double *gf);
 void ipm_sigma_rhs(hipStream_t s, int n, const double *x, const double *zl, const double *zu,

@@ -79,7 +79,7 @@ __device__ inline void panel_reg_dev(int N, int nb, double alpha,
                                                     int32_t *__restrict__ blk, FacState *st,
                                                     int32_t *__restrict__ panel_k0) {
   constexpr int NWV = T / 64;
-  static_assert(NB <= 64, "one lane per panel column");
+  static_assert(NB <= 64 && NB % 8 == 0, "one lane per panel column, chunks of 8");
   __shared__ double s_wk[NB], s_wi[NB];            // W rows of the pivot k and of imax
   __shared__ double s_cA[NB], s_cB[NB], s_cC[NB];  // W = L D coefficients per panel column
   __shared__ double s_lrow[NB];                    // L row of imax / of the next pivot
@@ -152,13 +152,22 @@ __device__ inline void panel_reg_dev(int N, int nb, double alpha,
     double a[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) a[r] = s_acur[r * T + tid];
+    // columns t < j in chunks of 8: one batch of LDS reads per chunk
 #pragma unroll
-    for (int t = 0; t < NB; ++t) {
-      if (t < j) {
+    for (int t0 = 0; t0 < NB; t0 += 8) {
+      if (t0 < j) {
         keep_branch();
-        const double w = s_wk[t];
+        double wv[8];
 #pragma unroll
-        for (int r = 0; r < R; ++r) a[r] = fma(-Lr[r][t], w, a[r]);
+        for (int u = 0; u < 8; ++u) wv[u] = s_wk[t0 + u];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          if (t0 + u < j) {
+            keep_branch();
+#pragma unroll
+            for (int r = 0; r < R; ++r) a[r] = fma(-Lr[r][t0 + u], wv[u], a[r]);
+          }
+        }
       }
     }
     double bv = -1.0;
@@ -229,12 +238,20 @@ __device__ inline void panel_reg_dev(int N, int nb, double alpha,
       }
       __syncthreads();
 #pragma unroll
-      for (int t = 0; t < NB; ++t) {
-        if (t < j) {
+      for (int t0 = 0; t0 < NB; t0 += 8) {
+        if (t0 < j) {
           keep_branch();
-          const double w = s_wi[t];
+          double wv[8];
 #pragma unroll
-          for (int r = 0; r < R; ++r) wic[r] = fma(-Lr[r][t], w, wic[r]);
+          for (int u = 0; u < 8; ++u) wv[u] = s_wi[t0 + u];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            if (t0 + u < j) {
+              keep_branch();
+#pragma unroll
+              for (int r = 0; r < R; ++r) wic[r] = fma(-Lr[r][t0 + u], wv[u], wic[r]);
+            }
+          }
         }
       }
       double rv = 0.0;
@@ -279,6 +296,8 @@ __device__ inline void panel_reg_dev(int N, int nb, double alpha,
       Dc = aii;
       det = Da * Dc - Db * Db;
     }
+    // one reciprocal per step (wave-uniform), multipliers by multiplication
+    const double rD = (kind == 4) ? 1.0 / det : (kind == 3) ? 1.0 / aii : 1.0 / akk;
 
     // ---- multipliers, new positions, next column ------------------------------
     double l0[R], l1[R];
@@ -291,14 +310,14 @@ __device__ inline void panel_reg_dev(int N, int nb, double alpha,
       if (kind == 4) {
         act[r] = pr >= k + 1 && pr != q;
         const double x0 = s_wkc[r * T + tid], y0 = s_wic[r * T + tid];
-        l0[r] = (x0 * Dc - y0 * Db) / det;
-        l1[r] = (y0 * Da - x0 * Db) / det;
+        l0[r] = (x0 * Dc - y0 * Db) * rD;
+        l1[r] = (y0 * Da - x0 * Db) * rD;
       } else if (kind == 3) {
         act[r] = pr >= k && pr != q;
-        l0[r] = s_wic[r * T + tid] / aii;
+        l0[r] = s_wic[r * T + tid] * rD;
       } else {
         act[r] = pr > k;
-        l0[r] = (kind == 0) ? 0.0 : s_wkc[r * T + tid] / akk;
+        l0[r] = (kind == 0) ? 0.0 : s_wkc[r * T + tid] * rD;
       }
       int np = pr;
       if (sw) {

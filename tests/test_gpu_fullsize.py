@@ -32,10 +32,11 @@ def big():
     return dict(prob=prob, P=P, sig=sig, rx=rx, ry=ry, dsb=prob["w"] + sig[nd:], nd=nd)
 
 
-def test_fullsize_condense_factor_solve(big):
+@pytest.mark.parametrize("panel", ["auto", "reg"])
+def test_fullsize_condense_factor_solve(big, panel):
     prob, P, nd = big["prob"], big["P"], big["nd"]
-    say("N=4096 condense/factor/solve")
-    S = mds.solver_for(prob)
+    say(f"N=4096 condense/factor/solve panel={panel}")
+    S = mds.solver_for(prob, panel=panel)
     S.condense(big["sig"][:nd], big["dsb"], 0.0, 0.0)
     M = S.get_matrix()
     Mo, _ = oracle.condense(P, big["sig"][:nd], big["dsb"], 0.0, 0.0)

@@ -80,12 +80,18 @@ def _factor_check(S, Mo):
     return oracle.inertia(ipo, ddo, dso), info_o
 
 
-@pytest.mark.parametrize("panel", ["auto", "mem"])
+PANELS = {"auto": dict(panel="auto"), "mem": dict(panel="mem"), "reg": dict(panel="reg"),
+          "reg1024": dict(panel="reg", panel_threads=1024)}
+
+
+@pytest.mark.parametrize("panel", list(PANELS))
 @pytest.mark.parametrize("idx", range(len(CASES)))
 def test_factor_pivots_and_inertia_exact(idx, panel):
     prob, st, nb = _case(idx, seed=1)
     say(f"factor case={CASES[idx]} panel={panel}")
-    S = mds.solver_for(prob, nb=nb, panel=panel)
+    if panel == "reg1024" and nb > 32:
+        nb = 32
+    S = mds.solver_for(prob, nb=nb, **PANELS[panel])
     S.condense(st["sigma_d"], st["dsbase"], 0.0, 0.0)
     Mo, _ = oracle.condense(oracle.Problem(prob), st["sigma_d"], st["dsbase"], 0.0, 0.0)
     status, inn, _ = S.factor_inertia()
@@ -126,15 +132,15 @@ def test_factor_branch_matrices(case):
     assert inn["info"] == info_o
 
 
-@pytest.mark.parametrize("panel", ["auto", "mem"])
+@pytest.mark.parametrize("panel", list(PANELS))
 @pytest.mark.parametrize("N,nb", [(64, 8), (129, 16), (250, 16), (400, 64), (700, 0),
-                                  (1300, 0), (2100, 0)])
+                                  (1300, 0), (2100, 0), (3000, 0)])
 def test_factor_random_symmetric(N, nb, panel):
     rng = np.random.default_rng(N)
     A = rng.standard_normal((N, N))
     A = A + A.T
     say(f"random symmetric N={N} nb={nb} panel={panel}")
-    S = mds.solver_for(_dense_problem(A), nb=nb, panel=panel)
+    S = mds.solver_for(_dense_problem(A), nb=nb, **PANELS[panel])
     S.condense(np.zeros(N), np.zeros(0), 0.0, 0.0)
     status, inn, _ = S.factor_inertia()
     ino, _ = _factor_check(S, A)
