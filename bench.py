@@ -173,6 +173,65 @@ def batch_section(count, mu=0.05, singles=6):
                                    "from the batch mean)")
 
 
+def warmstart_section(n_train, n_held, hidden=1024, steps=600):
+    """Learned warm start on a family of N = 192 problems (the C0 shapes; only
+    b varies): cold FP64 IPM solves generate the training set; the perceptron
+    b -> (x_d, y, log10 mu0) is trained with the library's kernels; held-out
+    problems are solved warm (BF16 inference, cold fallback) and cold."""
+    import numpy as np
+    import torch
+    import paper_2605_13736_amd as mds
+    import synth
+    from paper_2605_13736_amd import warmstart
+    base = synth.config_problem(0)
+    train = [synth.family_member(base, p) for p in range(n_train)]
+    held = [synth.family_member(base, 10 ** 6 + p) for p in range(n_held)]
+    t0 = time.perf_counter()
+    X, T, _, _ = warmstart.solve_family(train)
+    t_data = time.perf_counter() - t0
+    ws = warmstart.WarmStart(base["m"], base["n_d"], hidden=hidden, max_batch=256)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    losses = ws.fit(X, T, steps=steps, lr=1e-3, batch=128)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    S = mds.solver_for(base)
+    cold_it, warm_it, cold_t, warm_t, fb, err = [], [], 0.0, 0.0, 0, 0.0
+    for q in held:
+        S.P["b"].copy_(S.dev(q["b"]))
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        c = S.ipm_solve()
+        torch.cuda.synchronize()
+        cold_t += time.perf_counter() - t1
+        xc = c["x"].cpu().numpy().copy()
+        t1 = time.perf_counter()
+        w = ws.solve(S, q["b"])
+        torch.cuda.synchronize()
+        warm_t += time.perf_counter() - t1
+        cold_it.append(c["iters"])
+        warm_it.append(w["warm_iters"])
+        fb += int(w["fallback"])
+        err = max(err, float(np.abs(w["x"].cpu().numpy() - xc).max()))
+    Xn = np.zeros((1, base["m"]), dtype=np.float32)
+    ws.net.forward(Xn, "bf16")
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(20):
+        ws.net.forward(Xn, "bf16")
+    torch.cuda.synchronize()
+    t_inf = (time.perf_counter() - t1) / 20
+    return dict(workload=f"family of N=192 problems (n_d=64, n_s=2000, m=128; b varies), "
+                         f"{len(X)} training / {n_held} held-out",
+                mlp=f"{base['m']}-{hidden}-{hidden}-{base['n_d'] + base['m'] + 1}, GELU, "
+                    "FP32-MFMA training, BF16-MFMA inference",
+                data_s=t_data, train_s=t_train, train_steps=steps,
+                loss_first=losses[0], loss_last=losses[-1], inference_ms=t_inf * 1e3,
+                cold_iters_mean=float(np.mean(cold_it)), warm_iters_mean=float(np.mean(warm_it)),
+                fallback_rate=fb / n_held, cold_solves_per_s=n_held / cold_t,
+                warm_solves_per_s=n_held / warm_t, max_abs_x_diff_vs_cold=err)
+
+
 def cpu_baseline(prob, N):
     import numpy as np
     import oracle
@@ -205,6 +264,8 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--batch-count", type=int, default=128)
+    ap.add_argument("--no-warmstart", action="store_true")
+    ap.add_argument("--ws-train", type=int, default=256)
     ap.add_argument("--calib-copy", action="store_true",
                     help="only run a plain 256 MiB device copy (calibrates HBM counters)")
     args = ap.parse_args()
@@ -290,7 +351,8 @@ def main():
     roof["frac"] = roof["achieved"] / roof["peak"]
     roof["kernel"] = {"panel": "k_bk_panel_reg" if info0["panel"] == "reg" else "k_bk_panel",
                       "trailing": "k_bk_trailing",
-                      "solve": "k_ldl_solve", "condense": "k_condense_dense"}[dom]
+                      "solve": "k_trsv_fwd+k_trsv_bwd", "condense": "k_condense_dense",
+                      "permute": "k_std_sweep+k_std_apply"}[dom]
     meas = MEASURED_TRAFFIC.get(roof["kernel"])
     roof["traffic"] = meas[0] if meas else None
     if meas:
@@ -335,6 +397,9 @@ def main():
     if not args.no_batch:
         log("batch section")
         out["batch"] = batch_section(args.batch_count)
+    if not args.no_warmstart:
+        log("learned warm start section")
+        out["warmstart"] = warmstart_section(args.ws_train, 16)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob, N)
     print(json.dumps(out), flush=True)

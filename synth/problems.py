@@ -131,3 +131,20 @@ def interior_iterate(prob: dict, seed: int) -> dict:
     return dict(x=rng.uniform(-0.9, 0.9, n), y=rng.standard_normal(prob["m"]),
                 zl=10.0 ** rng.uniform(-3, 1, n), zu=10.0 ** rng.uniform(-3, 1, n),
                 mu=float(10.0 ** rng.uniform(-6, -1)))
+
+
+def family_member(prob: dict, p: int, cfg: int = 4) -> dict:
+    """Problem p of a family that shares prob's matrices, objective and bounds:
+    only the constraint right-hand side changes, b = J x0 with x0 drawn
+    U[-0.5, 0.5]^n from the seed (cfg, p, 3)."""
+    rng = np.random.default_rng(np.random.SeedSequence([cfg, p, 3]))
+    nd, ns, m = prob["n_d"], prob["n_s"], prob["m"]
+    x0 = rng.uniform(-0.5, 0.5, nd + ns)
+    b = prob["Jd"] @ x0[:nd] if nd > 0 else np.zeros(m)
+    b = np.array(b, dtype=np.float64)
+    for i in range(m):
+        for a in range(prob["rp"][i], prob["rp"][i + 1]):
+            b[i] += prob["v"][a] * x0[nd + prob["ci"][a]]
+    q = dict(prob)
+    q["b"] = b
+    return q
