@@ -80,7 +80,10 @@ typedef struct {
  * accumulation; pivot search, L, the 1x1/2x2 D blocks and the solves stay
  * FP64, and mds_refine runs GMRES-based iterative refinement in FP64 on the
  * full Newton system, preconditioned by the low-precision factorization.
- * The mixed modes need the register-resident panel (N <= 4096). */
+ * The low-precision factorization is of the equilibrated S M S with
+ * S = diag(1 / sqrt(max_j |M_ij|)) (same inertia as M); mds_get_factor
+ * returns that factor.  The mixed modes need the register-resident panel
+ * (N <= 4096). */
 enum { MDS_FP64 = 0, MDS_FP32 = 1, MDS_BF16 = 2 };
 
 typedef struct {

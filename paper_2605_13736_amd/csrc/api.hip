@@ -83,7 +83,7 @@ int resolve_timings(mds_handle *h) {
 enum Slot {
   S_M, S_M2, S_SRC, S_W, S_DD, S_DS, S_IPIV, S_BLK, S_PK0, S_FST, S_INVD, S_CPTR, S_CROW, S_CVAL, S_CFILL,
   S_FLAGS, S_RED, S_SCAL, S_Z, S_Z2, S_HMAP, S_PERM, S_COLP, S_TRSV, S_SIG, S_RX, S_RY, S_DSB, S_DX, S_DY, S_DZL, S_DZU, S_XT, S_RES,
-  S_COR, S_PREV, S_KX, S_TN, S_TM, S_TN2, S_KNH, S_KNJD, S_KNY, S_KNJS, S_X32A, S_X32B, S_GV,
+  S_COR, S_PREV, S_KX, S_TN, S_TM, S_TN2, S_KNH, S_KNJD, S_KNY, S_KNJS, S_X32A, S_X32B, S_EQ, S_GV,
   S_GZ, S_GRHS, S_GX, S_GW, S_GPART, S_GCOEF, S_COUNT
 };
 
@@ -103,6 +103,7 @@ Layout make_layout(const mds_dims &d, int nb, bool pingpong, int precision) {
   const bool mixed = precision != MDS_FP64;
   bytes[S_M2] = (pingpong && !mixed) ? 8 * N * N : 0;
   bytes[S_X32A] = bytes[S_X32B] = mixed ? 4 * N * N : 0;
+  bytes[S_EQ] = mixed ? 8 * N : 0;
   const size_t nK = n + m, R = (size_t)kGmresRestart;
   bytes[S_GV] = mixed ? 8 * nK * (R + 1) : 0;
   bytes[S_GZ] = mixed ? 8 * nK * R : 0;
@@ -230,7 +231,7 @@ int factor_impl(mds_handle *h, mds_inertia *out) {
     // buffers; L (FP64) goes to M, which then holds the whole factor
     {
       TimedLaunch t(h, MDS_T_CONDENSE);
-      launch_to_f32(S(h), (int64_t)N * N, h->w.M, h->w.X32[0]);
+      launch_equilibrate_f32(S(h), N, h->w.M, h->w.eq, h->w.X32[0]);
     }
     for (int b = 0; b < slots; ++b) {
       const float *X = h->w.X32[b & 1];
@@ -353,8 +354,11 @@ int solve_impl(mds_handle *h, const double *r_d, const double *r_s, const double
   ensure_std(h);
   {
     TimedLaunch t(h, MDS_T_SOLVE);
+    // mixed precision factors S M S: M^{-1} = S (S M S)^{-1} S
+    if (h->precision != MDS_FP64) launch_vscale(S(h), N, h->w.eq, h->w.z);
     launch_std_solve(S(h), N, h->w.M, h->w.dd, h->w.ds, h->w.blk, h->w.perm, h->w.z, h->w.z2,
                      h->w.z, h->w.trsv);
+    if (h->precision != MDS_FP64) launch_vscale(S(h), N, h->w.eq, h->w.z);
   }
   h->nsolves++;
   if (nd > 0) HIPCHK(hipMemcpyAsync(dx_d, h->w.z, 8 * (size_t)nd, hipMemcpyDeviceToDevice, S(h)));
@@ -737,6 +741,7 @@ int mds_create(mds_handle **out, const mds_dims *dims, const mds_options *opts, 
   w.M2 = D(S_M2);
   w.X32[0] = (float *)(base + L.off[S_X32A]);
   w.X32[1] = (float *)(base + L.off[S_X32B]);
+  w.eq = D(S_EQ);
   w.gV = D(S_GV);
   w.gZ = D(S_GZ);
   w.grhs = D(S_GRHS);

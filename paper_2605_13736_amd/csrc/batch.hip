@@ -113,31 +113,56 @@ __device__ __attribute__((noinline)) void trailing_wg(int N, int k0, int kend, c
     while (ti * (ti + 1) / 2 > x) --ti;
     const int tj = x - ti * (ti + 1) / 2;
     const int i0 = kend + ti * TW, c0 = kend + tj * TW;
+    // Every load of the tile is issued before the first use: the panel's map
+    // for the tile's rows (lanes 0-31) and columns (lanes 32-63), the W and L
+    // operands of every k-step, then the un-updated entries.
+    const int li = (lane < 32) ? i0 + lane : c0 + (lane - 32);
+    const int sidx = (li < N) ? src[li] : 0;
+    constexpr int KS = (BNB + 1 + 3) / 4;  // a panel has at most nb + 1 columns
+    double av[KS][2], bv[KS][2];
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const int tt = 4 * ks + l4;
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        const int c = c0 + a * 16 + l16;
+        av[ks][a] = (tt < jw && c < N) ? W[(size_t)c + (size_t)tt * ld] : 0.0;
+      }
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        const int i = i0 + b * 16 + l16;
+        bv[ks][b] = (tt < jw && i < N) ? Y[(size_t)i + (size_t)(k0 + tt) * ld] : 0.0;
+      }
+    }
+    const bool diag = (ti == tj);
+    double xv[2][2][4];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int cl = a * 16 + l4 + 4 * r, il = b * 16 + l16;
+          const int si = __shfl(sidx, il), sc = __shfl(sidx, 32 + cl);
+          const int c = c0 + cl, i = i0 + il;
+          const bool ok = c < N && i < N && (!diag || i >= c);
+          xv[a][b][r] = ok ? X[(size_t)si + (size_t)sc * ld] : 0.0;
+        }
     d4 acc[2][2];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
       for (int b = 0; b < 2; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
-    for (int t0 = 0; t0 < jw; t0 += 4) {
-      const int tt = t0 + l4;
-      double av[2], bv[2];
 #pragma unroll
-      for (int a = 0; a < 2; ++a) {
-        const int c = c0 + a * 16 + l16;
-        av[a] = (tt < jw && c < N) ? W[(size_t)c + (size_t)tt * ld] : 0.0;
+    for (int ks = 0; ks < KS; ++ks) {
+      if (4 * ks < jw) {
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int b = 0; b < 2; ++b)
+            acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[ks][a], bv[ks][b], acc[a][b], 0, 0, 0);
       }
-#pragma unroll
-      for (int b = 0; b < 2; ++b) {
-        const int i = i0 + b * 16 + l16;
-        bv[b] = (tt < jw && i < N) ? Y[(size_t)i + (size_t)(k0 + tt) * ld] : 0.0;
-      }
-#pragma unroll
-      for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int b = 0; b < 2; ++b)
-          acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
     }
-    const bool diag = (ti == tj);
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -148,7 +173,7 @@ __device__ __attribute__((noinline)) void trailing_wg(int N, int k0, int kend, c
           const int c = c0 + a * 16 + l4 + 4 * r;
           const int i = i0 + b * 16 + l16;
           if (c < N && i < N && (!diag || i >= c)) {
-            const double v = X[(size_t)src[i] + (size_t)src[c] * ld] - acc[a][b][r];
+            const double v = xv[a][b][r] - acc[a][b][r];
             Y[(size_t)i + (size_t)c * ld] = v;
             t[c - c0][i - i0] = v;
           }

@@ -1,3 +1,8 @@
+// Mixed-precision factorization helpers.  The low-precision factorization
+// works on the equilibrated S M S (S = diag(1/sqrt(row max |M|))), which has
+// the inertia of M and entries of comparable size, so FP32/BF16 rounding is
+// relative to each row's scale; the solve undoes S on both sides.
+//
 // Mixed-precision trailing update of the blocked Bunch-Kaufman factorization:
 // the trailing matrix is stored in FP32 and the rank-w product L21 W21' runs
 // on FP32 MFMA (v_mfma_f32_16x16x4f32) or on BF16 MFMA with FP32 accumulation
@@ -128,10 +133,35 @@ __global__ __launch_bounds__(256) void k_trailing_lp(int N, int nb, const double
   }
 }
 
-__global__ void k_to_f32(int64_t n, const double *__restrict__ a, float *__restrict__ b) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// Symmetric equilibration s_j = 1 / sqrt(max_i |M_ij|) (1 for a zero
+// column): one wave per column of the full symmetric M, so the column maximum
+// is the row maximum.
+__global__ void k_row_scale(int N, const double *__restrict__ M, double *__restrict__ s) {
+  const int lane = threadIdx.x & 63;
+  const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (j >= N) return;
+  double mx = 0.0;
+  for (int i = lane; i < N; i += 64) mx = fmax(mx, fabs(M[(size_t)i + (size_t)j * N]));
+  for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off));
+  if (lane == 0) s[j] = (mx > 0.0 && isfinite(mx)) ? 1.0 / sqrt(mx) : 1.0;
+}
+
+// b = (float)(s_i a_ij s_j), rounded once from FP64
+__global__ void k_to_f32_scaled(int N, const double *__restrict__ a, const double *__restrict__ s,
+                                float *__restrict__ b) {
+  const int64_t n = (int64_t)N * N;
+  const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t e = i; e < n; e += stride) b[e] = (float)a[e];
+  for (int64_t e = i0; e < n; e += stride) {
+    const int i = (int)(e % N), j = (int)(e / N);
+    b[e] = (float)((s[i] * a[e]) * s[j]);
+  }
+}
+
+// v = s .* v
+__global__ void k_vscale(int n, const double *__restrict__ s, double *__restrict__ v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) v[i] = s[i] * v[i];
 }
 
 }  // namespace
@@ -149,10 +179,16 @@ void launch_trailing_lp(hipStream_t s, int mode, int N, int nb, int adv, int slo
     k_trailing_lp<1><<<(unsigned)tiles, 256, 0, s>>>(N, nb, W, X, Y, Lsrc, src, st, panel_k0, slot);
 }
 
-void launch_to_f32(hipStream_t s, int64_t n, const double *a, float *b) {
-  if (n <= 0) return;
+void launch_equilibrate_f32(hipStream_t s, int N, const double *M, double *scale, float *b) {
+  if (N <= 0) return;
+  k_row_scale<<<(unsigned)((N + 3) / 4), 256, 0, s>>>(N, M, scale);
+  const int64_t n = (int64_t)N * N;
   const int64_t blocks = std::min<int64_t>((n + 255) / 256, 8192);
-  k_to_f32<<<(unsigned)blocks, 256, 0, s>>>(n, a, b);
+  k_to_f32_scaled<<<(unsigned)blocks, 256, 0, s>>>(N, M, scale, b);
+}
+
+void launch_vscale(hipStream_t s, int n, const double *scale, double *v) {
+  if (n > 0) k_vscale<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(n, scale, v);
 }
 
 }  // namespace mds

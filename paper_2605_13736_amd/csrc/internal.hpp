@@ -32,6 +32,7 @@ struct Work {
   double *M;          // N x N, full symmetric, column-major; L after factoring
   double *M2;         // second N x N buffer (register panel: ping-pong + L of even panels)
   float *X32[2];      // mixed precision: FP32 ping-pong buffers of the trailing matrix
+  double *eq;         // mixed precision: equilibration S (N)
   int32_t *src;       // N: logical -> physical index map of the last panel
   double *W;          // N x (nb + 2) panel workspace (updated columns)
   double *dd, *ds;    // D diagonal / sub-diagonal (N)
@@ -144,7 +145,9 @@ void launch_bk_panel_reg(hipStream_t s, int threads, int N, int nb, double alpha
 void launch_trailing_lp(hipStream_t s, int mode, int N, int nb, int adv, int slot,
                         const double *W, const float *X, float *Y, const double *Lsrc,
                         const int32_t *src, const FacState *st, const int32_t *panel_k0);
-void launch_to_f32(hipStream_t s, int64_t n, const double *a, float *b);
+// scale = 1/sqrt(row max |M|), b = FP32(S M S); v = scale .* v
+void launch_equilibrate_f32(hipStream_t s, int N, const double *M, double *scale, float *b);
+void launch_vscale(hipStream_t s, int n, const double *scale, double *v);
 
 // gmres.hip: Krylov products (partial[c * kDotBlocks + b]) and updates
 void launch_dots(hipStream_t s, int64_t n, int ncol, const double *V, int64_t ldv,

@@ -282,12 +282,32 @@ __global__ __launch_bounds__(RB) void k_red_ftb1(int64_t n, const double *__rest
   block_reduce8(v, red + (size_t)blockIdx.x * 8);
 }
 
-__global__ void k_red_final(int nb, const double *__restrict__ red, double *__restrict__ out) {
-  const int s = threadIdx.x;
-  if (s >= 8) return;
-  double t = red[s];
-  for (int b = 1; b < nb; ++b) t = (s < 4) ? fmax(t, red[(size_t)b * 8 + s]) : t + red[(size_t)b * 8 + s];
-  out[s] = t;
+// 256 threads: thread t combines the records t, t + 256, ... in increasing
+// order, then a fixed pairwise tree over the threads (max for slots 0-3, sum
+// for slots 4-7); the order depends only on nb.
+__global__ __launch_bounds__(256) void k_red_final(int nb, const double *__restrict__ red,
+                                                   double *__restrict__ out) {
+  __shared__ double sh[8][256];
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int s = 0; s < 8; ++s) {
+    double v = (s < 4) ? -INFINITY : 0.0;
+    for (int b = t; b < nb; b += 256) {
+      const double x = red[(size_t)b * 8 + s];
+      v = (s < 4) ? fmax(v, x) : v + x;
+    }
+    sh[s][t] = v;
+  }
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w) {
+#pragma unroll
+      for (int s = 0; s < 8; ++s)
+        sh[s][t] = (s < 4) ? fmax(sh[s][t], sh[s][t + w]) : sh[s][t] + sh[s][t + w];
+    }
+    __syncthreads();
+  }
+  if (t < 8) out[t] = sh[t][0];
 }
 
 __global__ void k_axpy_to(int n, const double *__restrict__ x, const double *__restrict__ dx,
@@ -401,17 +421,22 @@ __global__ __launch_bounds__(RB) void k_red_knorm(int nd, int ns, int m,
 
 // absolute row sums: x_d rows of [H + diag(sig + dw)], |J_d| column sums
 // (x_d rows of J_d'), and y rows |J_d| + |J_s|; J_s column sums for x_s rows.
+// Row sums of |H + diag(sig) + dw I|.  H is exactly symmetric (checked when
+// the problem is set), so row i's sum is column i's: one wave per column,
+// reading along the column.
 __global__ void k_abs_hrow(int nd, const double *__restrict__ H, const double *__restrict__ sig,
                            double dw, double *__restrict__ out) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nd) return;
+  const int lane = threadIdx.x & 63;
+  const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (j >= nd) return;
   double t = 0.0;
-  for (int j = 0; j < nd; ++j) {
+  for (int i = lane; i < nd; i += 64) {
     double h = H[(size_t)i + (size_t)j * nd];
-    if (i == j) h = h + sig[i] + dw;
+    if (i == j) h = h + sig[j] + dw;
     t += fabs(h);
   }
-  out[i] = t;
+  t = wave_sum(t);
+  if (lane == 0) out[j] = t;
 }
 
 __global__ void k_abs_jdcol(int m, int nd, const double *__restrict__ Jd,
@@ -425,15 +450,25 @@ __global__ void k_abs_jdcol(int m, int nd, const double *__restrict__ Jd,
   if (lane == 0) out[j] = s;
 }
 
-__global__ void k_abs_yrow(int m, int nd, const double *__restrict__ Jd,
-                           const int32_t *__restrict__ rp, const double *__restrict__ v,
-                           double *__restrict__ out) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= m) return;
+// Row sums of |[J_d J_s]|: 64 rows per block of 256 threads, the four waves
+// take every fourth column, partials combined in wave order.
+__global__ __launch_bounds__(256) void k_abs_yrow(int m, int nd, const double *__restrict__ Jd,
+                                                  const int32_t *__restrict__ rp,
+                                                  const double *__restrict__ v,
+                                                  double *__restrict__ out) {
+  __shared__ double sh[4][64];
+  const int lane = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const int i = blockIdx.x * 64 + lane;
   double t = 0.0;
-  for (int j = 0; j < nd; ++j) t += fabs(Jd[(size_t)i + (size_t)j * m]);
-  for (int a = rp[i]; a < rp[i + 1]; ++a) t += fabs(v[a]);
-  out[i] = t;
+  if (i < m)
+    for (int j = g; j < nd; j += 4) t += fabs(Jd[(size_t)i + (size_t)j * m]);
+  sh[g][lane] = t;
+  __syncthreads();
+  if (g == 0 && i < m) {
+    double u = (sh[0][lane] + sh[1][lane]) + (sh[2][lane] + sh[3][lane]);
+    for (int a = rp[i]; a < rp[i + 1]; ++a) u += fabs(v[a]);
+    out[i] = u;
+  }
 }
 
 __global__ void k_abs_jscol(int ns, const int32_t *__restrict__ cptr,
@@ -506,7 +541,7 @@ void ipm_red_opt(hipStream_t s, int n, int m, const double *x, const double *y, 
                  const double *jty, const double *cx, double mu, double *red, double *out) {
   const unsigned g = red_grid(n > m ? n : m);
   k_red_opt<<<g, RB, 0, s>>>(n, m, x, y, zl, zu, xl, xu, gf, jty, cx, mu, red);
-  k_red_final<<<1, 64, 0, s>>>((int)g, red, out);
+  k_red_final<<<1, 256, 0, s>>>((int)g, red, out);
 }
 
 void ipm_red_merit(hipStream_t s, int nd, int ns, int m, const double *x, const double *hx,
@@ -515,14 +550,14 @@ void ipm_red_merit(hipStream_t s, int nd, int ns, int m, const double *x, const 
   const int n = nd + ns;
   const unsigned gr = red_grid(n > m ? n : m);
   k_red_merit<<<gr, RB, 0, s>>>(nd, ns, m, x, hx, c, w, g, xl, xu, cx, red);
-  k_red_final<<<1, 64, 0, s>>>((int)gr, red, out);
+  k_red_final<<<1, 256, 0, s>>>((int)gr, red, out);
 }
 
 void ipm_red_gphi(hipStream_t s, int n, const double *gf, const double *x, const double *xl,
                   const double *xu, const double *dx, double mu, double *red, double *out) {
   const unsigned g = red_grid(n);
   k_red_gphi<<<g, RB, 0, s>>>(n, gf, x, xl, xu, dx, mu, red);
-  k_red_final<<<1, 64, 0, s>>>((int)g, red, out);
+  k_red_final<<<1, 256, 0, s>>>((int)g, red, out);
 }
 
 void ipm_red_ftb(hipStream_t s, int n, const double *x, const double *xl, const double *xu,
@@ -530,14 +565,14 @@ void ipm_red_ftb(hipStream_t s, int n, const double *x, const double *xl, const 
                  const double *dzu, double tau, double *red, double *out) {
   const unsigned g = red_grid(n);
   k_red_ftb<<<g, RB, 0, s>>>(n, x, xl, xu, dx, zl, zu, dzl, dzu, tau, red);
-  k_red_final<<<1, 64, 0, s>>>((int)g, red, out);
+  k_red_final<<<1, 256, 0, s>>>((int)g, red, out);
 }
 
 void ipm_red_ftb1(hipStream_t s, int64_t n, const double *v, const double *dv, double tau,
                   double *red, double *out) {
   const unsigned g = red_grid(n);
   k_red_ftb1<<<g, RB, 0, s>>>(n, v, dv, tau, red);
-  k_red_final<<<1, 64, 0, s>>>((int)g, red, out);
+  k_red_final<<<1, 256, 0, s>>>((int)g, red, out);
 }
 
 void ipm_red_amax3(hipStream_t s, int64_t na, const double *a, int64_t nb, const double *b,
@@ -546,7 +581,7 @@ void ipm_red_amax3(hipStream_t s, int64_t na, const double *a, int64_t nb, const
   len = len > nc ? len : nc;
   const unsigned g = red_grid(len);
   k_red_amax3<<<g, RB, 0, s>>>(na, a, nb, b, nc, c, red);
-  k_red_final<<<1, 64, 0, s>>>((int)g, red, out);
+  k_red_final<<<1, 256, 0, s>>>((int)g, red, out);
 }
 
 void ipm_axpy_to(hipStream_t s, int n, const double *x, const double *dx, double a, double *out) {
@@ -592,16 +627,16 @@ void kkt_norm_parts(hipStream_t s, int nd, int ns, int m, const double *H, const
                     double *hrow, double *jdcol, double *yrow, double *jscol, double *red,
                     double *out) {
   if (nd > 0) {
-    k_abs_hrow<<<grid1(nd, 256), 256, 0, s>>>(nd, H, sig, dw, hrow);
+    k_abs_hrow<<<grid1(nd, 4), 256, 0, s>>>(nd, H, sig, dw, hrow);
     k_abs_jdcol<<<grid1(nd, 4), 256, 0, s>>>(m, nd, Jd, jdcol);
   }
-  if (m > 0) k_abs_yrow<<<grid1(m, 256), 256, 0, s>>>(m, nd, Jd, rp, v, yrow);
+  if (m > 0) k_abs_yrow<<<grid1(m, 64), 256, 0, s>>>(m, nd, Jd, rp, v, yrow);
   if (ns > 0) k_abs_jscol<<<grid1(ns, 256), 256, 0, s>>>(ns, cptr, cval, jscol);
   int64_t len = nd > ns ? nd : ns;
   len = len > m ? len : m;
   const unsigned g = red_grid(len);
   k_red_knorm<<<g, RB, 0, s>>>(nd, ns, m, hrow, sig, dw, jdcol, dsb, jscol, yrow, dc, red);
-  k_red_final<<<1, 64, 0, s>>>((int)g, red, out);
+  k_red_final<<<1, 256, 0, s>>>((int)g, red, out);
 }
 
 }  // namespace mds
