@@ -77,7 +77,7 @@ def mixed_section(prob, N, reps=3):
     it = synth.interior_iterate(prob, 0)
     nd = prob["n_d"]
     out, ref = {}, None
-    for prec in ("fp64", "fp32", "bf16"):
+    for prec in ("fp64", "fp32", "bf16x3", "bf16"):
         S = mds.solver_for(prob, precision=prec)
         sig, rx, ry = S.sigma_rhs(it["x"], it["y"], it["zl"], it["zu"], it["mu"])
         dsb = S.dev(prob["w"]) + sig[nd:]

@@ -75,16 +75,18 @@ typedef struct {
 } mds_dims;
 
 /* Precision of the trailing updates of the factorization.  MDS_FP64: every
- * step in FP64.  MDS_FP32 / MDS_BF16: the trailing matrix is stored in FP32
- * and its rank-w updates run on FP32 MFMA, or on BF16 MFMA with FP32
- * accumulation; pivot search, L, the 1x1/2x2 D blocks and the solves stay
+ * step in FP64.  MDS_FP32 / MDS_BF16 / MDS_BF16X3: the trailing matrix is
+ * stored in FP32 and its rank-w updates run on FP32 MFMA, on BF16 MFMA with
+ * FP32 accumulation, or on three BF16 MFMAs per product with each operand
+ * split into a BF16 high part and a BF16 residual (FP32 accumulation);
+ * pivot search, L, the 1x1/2x2 D blocks and the solves stay
  * FP64, and mds_refine runs GMRES-based iterative refinement in FP64 on the
  * full Newton system, preconditioned by the low-precision factorization.
  * The low-precision factorization is of the equilibrated S M S with
  * S = diag(1 / sqrt(max_j |M_ij|)) (same inertia as M); mds_get_factor
  * returns that factor.  The mixed modes need the register-resident panel
  * (N <= 4096). */
-enum { MDS_FP64 = 0, MDS_FP32 = 1, MDS_BF16 = 2 };
+enum { MDS_FP64 = 0, MDS_FP32 = 1, MDS_BF16 = 2, MDS_BF16X3 = 3 };
 
 typedef struct {
   int32_t nb;          /* panel width of the blocked factorization (0: default) */
@@ -92,7 +94,7 @@ typedef struct {
                           allows nb >= 16, i.e. N <= 2048; FP64 only),
                           1: panel kept in device memory,
                           2: register-resident panel (N <= 4096)               */
-  int32_t precision;   /* MDS_FP64 (default), MDS_FP32 or MDS_BF16             */
+  int32_t precision;   /* MDS_FP64 (default), MDS_FP32, MDS_BF16, MDS_BF16X3   */
   int32_t panel_threads; /* register panel workgroup: 512 (default) or 1024     */
   int32_t reserved[4];
 } mds_options;

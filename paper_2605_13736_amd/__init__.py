@@ -40,7 +40,7 @@ class Options(C.Structure):
                 ("panel_threads", C.c_int32), ("reserved", C.c_int32 * 4)]
 
 
-PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2}
+PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2, "bf16x3": 3}
 
 
 class Problem(C.Structure):

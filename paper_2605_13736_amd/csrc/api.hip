@@ -178,7 +178,8 @@ PanelChoice panel_of(const mds_dims &d, const mds_options *o) {
   const int rnb = bk_reg_nb(N, thr);
   PanelChoice c{};
   const int prec = o ? o->precision : MDS_FP64;
-  if (prec != MDS_FP64 && prec != MDS_FP32 && prec != MDS_BF16) return c;  // nb = 0: invalid
+  if (prec != MDS_FP64 && prec != MDS_FP32 && prec != MDS_BF16 && prec != MDS_BF16X3)
+    return c;  // nb = 0: invalid
   if (popt < 0 || popt > 2) return c;
   if (prec != MDS_FP64 && (rnb == 0 || popt == 1)) return c;
   if (popt == 2 && rnb == 0) return c;

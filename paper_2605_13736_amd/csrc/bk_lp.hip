@@ -27,7 +27,12 @@ __device__ inline short to_bf16(float x) {
   return (short)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
 }
 
-// MODE 1: FP32 products; MODE 2: BF16 products.  256 threads per 64 x 64
+__device__ inline float bf16_to_f32(short h) { return __uint_as_float(((uint32_t)(uint16_t)h) << 16); }
+
+// MODE 1: FP32 products; MODE 2: BF16 products; MODE 3: split BF16 products,
+// each FP32 operand v = hi + lo with hi = bf16(v), lo = bf16(v - hi), and
+// a b ~ hi_a hi_b + hi_a lo_b + lo_a hi_b (three BF16 MFMAs, FP32
+// accumulation; the dropped lo lo term is 2^-16 relative).  256 threads per 64 x 64
 // lower tile; wave w computes the 32 x 32 quarter (c rows wc.., i columns wi..)
 // of D[c][i] = sum_t W[c, t] L[i, t] as 2 x 2 MFMA blocks of 16 x 16.
 template <int MODE>
@@ -81,6 +86,38 @@ __global__ __launch_bounds__(256) void k_trailing_lp(int N, int nb, const double
 #pragma unroll
         for (int b = 0; b < 2; ++b)
           acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a], bv[b], acc[a][b], 0, 0, 0);
+    }
+  } else if (MODE == 3) {
+    for (int t0 = 0; t0 < jw; t0 += 16) {
+      s4 ah[2], al[2], bh[2], bl[2];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int t = t0 + 4 * l4 + e;
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+          const int c = wc + a * 16 + l16;
+          const float v = (t < jw && c < N) ? (float)W[(size_t)c + (size_t)t * ld] : 0.f;
+          const short h = to_bf16(v);
+          ah[a][e] = h;
+          al[a][e] = to_bf16(v - bf16_to_f32(h));
+        }
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          const int i = wi + b * 16 + l16;
+          const float v = (t < jw && i < N) ? (float)Lsrc[(size_t)i + (size_t)(k0 + t) * ld] : 0.f;
+          const short h = to_bf16(v);
+          bh[b][e] = h;
+          bl[b][e] = to_bf16(v - bf16_to_f32(h));
+        }
+      }
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al[a], bh[b], acc[a][b], 0, 0, 0);
+          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[a], bl[b], acc[a][b], 0, 0, 0);
+          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[a], bh[b], acc[a][b], 0, 0, 0);
+        }
     }
   } else {
     for (int t0 = 0; t0 < jw; t0 += 16) {
@@ -175,6 +212,8 @@ void launch_trailing_lp(hipStream_t s, int mode, int N, int nb, int adv, int slo
   const long tiles = nt * (nt + 1) / 2;
   if (mode == 2)
     k_trailing_lp<2><<<(unsigned)tiles, 256, 0, s>>>(N, nb, W, X, Y, Lsrc, src, st, panel_k0, slot);
+  else if (mode == 3)
+    k_trailing_lp<3><<<(unsigned)tiles, 256, 0, s>>>(N, nb, W, X, Y, Lsrc, src, st, panel_k0, slot);
   else
     k_trailing_lp<1><<<(unsigned)tiles, 256, 0, s>>>(N, nb, W, X, Y, Lsrc, src, st, panel_k0, slot);
 }
