@@ -84,16 +84,24 @@ typedef struct {
  * full Newton system, preconditioned by the low-precision factorization.
  * The low-precision factorization is of the equilibrated S M S with
  * S = diag(1 / sqrt(max_j |M_ij|)) (same inertia as M); mds_get_factor
- * returns that factor.  The mixed modes need the register-resident panel
- * (N <= 4096). */
+ * returns that factor.  The mixed modes need a register-resident panel
+ * (panel 2 or 3). */
 enum { MDS_FP64 = 0, MDS_FP32 = 1, MDS_BF16 = 2, MDS_BF16X3 = 3 };
 
 typedef struct {
   int32_t nb;          /* panel width of the blocked factorization (0: default) */
   int32_t panel;       /* 0: automatic (register-resident panel when its tile
-                          allows nb >= 16, i.e. N <= 2048; FP64 only),
-                          1: panel kept in device memory,
-                          2: register-resident panel (N <= 4096)               */
+                          allows nb >= 16, i.e. N <= 2048; above that the
+                          memory panel in FP64, the cooperative panel in the
+                          mixed modes),
+                          1: panel kept in device memory (FP64 only),
+                          2: register-resident panel, one workgroup (N <= 4096),
+                          3: register-resident panel over ceil(N / 1024)
+                             cooperating workgroups, nb <= 32 (any N); its
+                             workgroups exchange pivot data through the
+                             workspace and must run concurrently: an
+                             exchange wait longer than ~0.7 s ends the
+                             factorization with MDS_EHIP                      */
   int32_t precision;   /* MDS_FP64 (default), MDS_FP32, MDS_BF16, MDS_BF16X3   */
   int32_t panel_threads; /* register panel workgroup: 512 (default) or 1024     */
   int32_t reserved[4];
@@ -298,8 +306,9 @@ int mds_get_inv_ds(mds_handle *h, double *inv_d_host);
 typedef struct {
   int32_t nb;           /* panel width limit                                  */
   int32_t min_width;    /* fewest columns a panel factors (except the last)   */
-  int32_t panel;        /* 0: register-resident panel, 1: panel in memory    */
-  int32_t precision;    /* MDS_FP64, MDS_FP32 or MDS_BF16                     */
+  int32_t panel;        /* 0: register-resident panel, 1: panel in memory,
+                           2: cooperative register-resident panel            */
+  int32_t precision;    /* MDS_FP64, MDS_FP32, MDS_BF16 or MDS_BF16X3          */
   int32_t panel_threads; /* workgroup size of the panel kernel                */
   int32_t pad;
   int64_t workspace_bytes;

@@ -40,6 +40,9 @@ class Options(C.Structure):
                 ("panel_threads", C.c_int32), ("reserved", C.c_int32 * 4)]
 
 
+# panel kernels: automatic choice, panel in device memory, register-resident
+# (one workgroup), register-resident over several cooperating workgroups
+PANELS = {"auto": 0, "mem": 1, "reg": 2, "coop": 3}
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2, "bf16x3": 3}
 
 
@@ -213,9 +216,9 @@ class Solver:
         if precision not in PRECISIONS:
             raise MdsError(f"precision must be one of {sorted(PRECISIONS)}")
         self.precision = precision
-        if panel not in ("auto", "mem", "reg"):
-            raise MdsError("panel must be 'auto', 'mem' or 'reg'")
-        self.opts = Options(nb, {"auto": 0, "mem": 1, "reg": 2}[panel], PRECISIONS[precision],
+        if panel not in PANELS:
+            raise MdsError("panel must be one of " + ", ".join(PANELS))
+        self.opts = Options(nb, PANELS[panel], PRECISIONS[precision],
                             int(panel_threads))
         self.n_d, self.n_s, self.m = n_d, n_s, m
         self.N, self.n = n_d + m, n_d + n_s
@@ -416,7 +419,7 @@ class Solver:
         i = Info()
         self._check(lib().mds_get_info(self.h, C.byref(i)), "mds_get_info")
         prec = {v: k for k, v in PRECISIONS.items()}[i.precision]
-        return dict(nb=i.nb, min_width=i.min_width, panel="reg" if i.panel == 0 else "mem",
+        return dict(nb=i.nb, min_width=i.min_width, panel=("reg", "mem", "coop")[i.panel],
                     precision=prec, panel_threads=i.panel_threads,
                     workspace_bytes=i.workspace_bytes)
 

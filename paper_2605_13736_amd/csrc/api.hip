@@ -84,7 +84,7 @@ enum Slot {
   S_M, S_M2, S_SRC, S_W, S_DD, S_DS, S_IPIV, S_BLK, S_PK0, S_FST, S_INVD, S_CPTR, S_CROW, S_CVAL, S_CFILL,
   S_FLAGS, S_RED, S_SCAL, S_Z, S_Z2, S_HMAP, S_PERM, S_COLP, S_TRSV, S_SIG, S_RX, S_RY, S_DSB, S_DX, S_DY, S_DZL, S_DZU, S_XT, S_RES,
   S_COR, S_PREV, S_KX, S_TN, S_TM, S_TN2, S_KNH, S_KNJD, S_KNY, S_KNJS, S_X32A, S_X32B, S_EQ, S_GV,
-  S_GZ, S_GRHS, S_GX, S_GW, S_GPART, S_GCOEF, S_COUNT
+  S_GZ, S_GRHS, S_GX, S_GW, S_GPART, S_GCOEF, S_XCH, S_COUNT
 };
 
 struct Layout {
@@ -110,6 +110,7 @@ Layout make_layout(const mds_dims &d, int nb, bool pingpong, int precision) {
   bytes[S_GRHS] = bytes[S_GX] = bytes[S_GW] = mixed ? 8 * nK : 0;
   bytes[S_GPART] = 8 * (size_t)kDotBlocks * (R + 2);
   bytes[S_GCOEF] = 8 * (R + 2);
+  bytes[S_XCH] = 8 * 2 * (size_t)kCoopMaxP * kCoopSlotWords;
   bytes[S_SRC] = 4 * N;
   bytes[S_W] = 8 * N * (size_t)(nb + 2);
   bytes[S_DD] = bytes[S_DS] = 8 * N;
@@ -157,7 +158,8 @@ bool dims_ok(const mds_dims *d) {
 }
 
 struct PanelChoice {
-  bool reg;
+  bool reg;   // panel output in the ping-pong layout (register or cooperative panel)
+  bool coop;  // cooperative panel over several workgroups
   int nb, adv, threads;
 };
 
@@ -167,10 +169,12 @@ int panel_threads_of(const mds_options *o) {
 }
 
 // Panel choice.  panel option 1: memory panel; 2: register panel (N <= 4096);
+// 3: cooperative register panel over several workgroups (any N);
 // 0 (automatic): the register panel while its tile keeps nb >= 16
 // (N <= 2048 with 512 threads), else the memory panel, whose wider panels
 // cost less trailing-update traffic than the register panel's nb = 8 at
-// N = 4096.  The mixed-precision modes need the register panel.
+// N = 4096.  The mixed-precision modes need a register-resident panel (2 or
+// 3; automatic: 2 up to N = 4096, else 3).
 PanelChoice panel_of(const mds_dims &d, const mds_options *o) {
   const int N = d.n_d + d.m;
   const int popt = o ? o->panel : 0;
@@ -180,19 +184,24 @@ PanelChoice panel_of(const mds_dims &d, const mds_options *o) {
   const int prec = o ? o->precision : MDS_FP64;
   if (prec != MDS_FP64 && prec != MDS_FP32 && prec != MDS_BF16 && prec != MDS_BF16X3)
     return c;  // nb = 0: invalid
-  if (popt < 0 || popt > 2) return c;
-  if (prec != MDS_FP64 && (rnb == 0 || popt == 1)) return c;
+  if (popt < 0 || popt > 3) return c;
+  if (prec != MDS_FP64 && popt == 1) return c;
   if (popt == 2 && rnb == 0) return c;
   const bool use_reg =
-      rnb > 0 && (popt == 2 || prec != MDS_FP64 || (popt == 0 && rnb >= 16));
+      rnb > 0 && (popt == 2 || (popt == 0 && (rnb >= 16 || prec != MDS_FP64)));
+  const bool use_coop = !use_reg && (popt == 3 || (popt == 0 && prec != MDS_FP64));
   if (use_reg) {
     int nb = (o && o->nb > 0) ? o->nb : rnb;
     nb = std::min(std::max(nb, 2), rnb);
-    c = {true, nb, std::max(nb - 1, 1), thr};
+    c = {true, false, nb, std::max(nb - 1, 1), thr};
+  } else if (use_coop) {
+    int nb = (o && o->nb > 0) ? o->nb : bk_coop_nb();
+    nb = std::min(std::max(nb, 2), bk_coop_nb());
+    c = {true, true, nb, std::max(nb - 1, 1), 512};
   } else {
     int nb = (o && o->nb > 0) ? o->nb : default_nb(N);
     nb = std::min(std::max(nb, 2), kMaxNb);
-    c = {false, nb, nb, 0};
+    c = {false, false, nb, nb, 0};
   }
   return c;
 }
@@ -239,9 +248,13 @@ int factor_impl(mds_handle *h, mds_inertia *out) {
       float *Y = h->w.X32[(b + 1) & 1];
       {
         TimedLaunch t(h, MDS_T_PANEL);
-        launch_bk_panel_reg(S(h), h->panel_threads, N, h->nb, h->alpha_bk, X, h->w.M, h->w.src,
-                            h->w.W, h->w.dd,
-                            h->w.ds, h->w.ipiv, h->w.blk, h->w.fst, h->w.panel_k0);
+        if (h->panel_coop)
+          launch_bk_panel_coop(S(h), N, h->nb, h->alpha_bk, X, h->w.M, h->w.src, h->w.W, h->w.dd,
+                               h->w.ds, h->w.ipiv, h->w.blk, h->w.fst, h->w.panel_k0, h->w.xch);
+        else
+          launch_bk_panel_reg(S(h), h->panel_threads, N, h->nb, h->alpha_bk, X, h->w.M, h->w.src,
+                              h->w.W, h->w.dd, h->w.ds, h->w.ipiv, h->w.blk, h->w.fst,
+                              h->w.panel_k0);
       }
       if ((long)N - (long)(b + 1) * h->adv > 0) {
         TimedLaunch t(h, MDS_T_TRAILING);
@@ -258,7 +271,10 @@ int factor_impl(mds_handle *h, mds_inertia *out) {
     if (h->panel_reg && !(b & 1)) Y = h->w.M2;
     {
       TimedLaunch t(h, MDS_T_PANEL);
-      if (h->panel_reg)
+      if (h->panel_coop)
+        launch_bk_panel_coop(S(h), N, h->nb, h->alpha_bk, X, Y, h->w.src, h->w.W, h->w.dd,
+                             h->w.ds, h->w.ipiv, h->w.blk, h->w.fst, h->w.panel_k0, h->w.xch);
+      else if (h->panel_reg)
         launch_bk_panel_reg(S(h), h->panel_threads, N, h->nb, h->alpha_bk, X, Y, h->w.src, h->w.W,
                             h->w.dd,
                             h->w.ds, h->w.ipiv, h->w.blk, h->w.fst, h->w.panel_k0);
@@ -276,6 +292,7 @@ int factor_impl(mds_handle *h, mds_inertia *out) {
   FacState st{};
   HIPCHK(hipMemcpyAsync(&st, h->w.fst, sizeof(st), hipMemcpyDeviceToHost, S(h)));
   HIPCHK(hipStreamSynchronize(S(h)));
+  if (st.xerr) return set_err(h, MDS_EHIP, "cooperative panel: exchange wait timed out");
   if (st.k != N) return set_err(h, MDS_EHIP, "factorization stopped at %d of %d", st.k, N);
   out->npos = st.npos;
   out->nzero = st.nzero;
@@ -728,6 +745,7 @@ int mds_create(mds_handle **out, const mds_dims *dims, const mds_options *opts, 
   const PanelChoice pc = panel_of(*dims, opts);
   h->nb = nb;
   h->panel_reg = pc.reg;
+  h->panel_coop = pc.coop;
   h->panel_threads = pc.threads;
   h->precision = prec;
   h->adv = pc.adv;
@@ -772,6 +790,7 @@ int mds_create(mds_handle **out, const mds_dims *dims, const mds_options *opts, 
   w.perm = I(S_PERM);
   w.colpanel = I(S_COLP);
   w.trsv = I(S_TRSV);
+  w.xch = (uint64_t *)(base + L.off[S_XCH]);
   w.sig = D(S_SIG);
   w.rx = D(S_RX);
   w.ry = D(S_RY);
@@ -795,6 +814,9 @@ int mds_create(mds_handle **out, const mds_dims *dims, const mds_options *opts, 
   if (std_prepare() != hipSuccess ||
       hipMemsetAsync(w.trsv, 0, 4 * (4 + 2 * (size_t)std_solve_blocks(h->N)), h->stream) !=
           hipSuccess ||
+      hipMemsetAsync(w.xch, 0, 8 * 2 * (size_t)kCoopMaxP * kCoopSlotWords, h->stream) !=
+          hipSuccess ||
+      hipMemsetAsync(w.fst, 0, sizeof(FacState), h->stream) != hipSuccess ||
       hipStreamSynchronize(h->stream) != hipSuccess) {
     delete h;
     return MDS_EHIP;
@@ -1162,7 +1184,7 @@ int mds_get_info(const mds_handle *h, mds_info *out) {
   if (!h || !out) return MDS_ENULL;
   out->nb = h->nb;
   out->min_width = h->adv;
-  out->panel = h->panel_reg ? 0 : 1;
+  out->panel = h->panel_coop ? 2 : h->panel_reg ? 0 : 1;
   out->precision = h->precision;
   out->panel_threads = h->panel_reg ? h->panel_threads : 1024;
   out->workspace_bytes = (int64_t)h->ws_bytes;

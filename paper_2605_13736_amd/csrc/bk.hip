@@ -33,6 +33,7 @@
 #include <climits>
 
 #include "internal.hpp"
+#include "wave.hpp"
 
 namespace mds {
 namespace {
@@ -49,20 +50,9 @@ __device__ inline void amax_combine(double &v, int &i, double v2, int i2) {
   }
 }
 
-__device__ inline void wave_argmax(double &v, int &i) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    double v2 = __shfl_xor(v, off);
-    int i2 = __shfl_xor(i, off);
-    amax_combine(v, i, v2, i2);
-  }
-}
+__device__ inline void wave_argmax(double &v, int &i) { wave::amax(v, i); }
 
-__device__ inline double wave_max(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
-  return v;
-}
+__device__ inline double wave_max(double v) { return wave::max(v); }
 
 __global__ void k_fac_reset(FacState *st, int32_t *panel_k0) {
   if (threadIdx.x == 0) {
@@ -70,6 +60,7 @@ __global__ void k_fac_reset(FacState *st, int32_t *panel_k0) {
     st->npanel = 0;
     st->info = 0;
     st->npos = st->nzero = st->nneg = st->n2x2 = 0;
+    st->xerr = 0;
     panel_k0[0] = 0;
   }
 }

@@ -1,0 +1,688 @@
+// Cooperative register-resident Bunch-Kaufman panel (Sec. 2.3) for orders
+// too large for one workgroup's registers: P workgroups (one per CU) each
+// keep the multipliers of their own block of rows in registers and take the
+// same pivot decisions from data exchanged once or twice per pivot.
+//
+// Workgroup g of T threads owns the physical rows
+//   rho = k0 + g (T R) + t + T r,   t < T, r < R,
+// of the buffer X (the trailing matrix in logical order at the panel start).
+// Interchanges move logical positions, never data: pos[r] is the logical
+// position of an owned row, and s_map (replicated in every workgroup) maps a
+// logical position to its physical row, which addresses the un-updated
+// columns of X.  Each pivot step is the one of the single-workgroup register
+// panel, with its two workgroup-wide reductions widened to the grid:
+//
+//   X1 (every step): each workgroup publishes its largest off-diagonal
+//      candidate of the updated column k (magnitude, position, signed value,
+//      L row) and, when it owns them, the rows at positions k, k+1, k+2
+//      (updated column-k value and L row).  Every workgroup reads all of it in
+//      one round trip and derives colmax, imax, a_kk, the W row of imax and,
+//      later, the L row of the next pivot.
+//   X3 (when the first test fails): per-wave partial maxima of the updated
+//      column imax, a_ii from its owner, and the column-imax values at
+//      positions k, k+1, k+2.
+//
+// Exchange words are 64 bits: 32 data bits under a 32-bit tag that names the
+// panel launch and the exchange, written and read with relaxed agent-scope
+// atomics.  A reader accepts a word when its tag is the expected one, so no
+// fence or flag orders the payload.  Two buffers (by exchange parity)
+// suffice: a workgroup writes exchange e only after reading every
+// workgroup's exchange e-1, which each of them published after reading e-2.
+// Every wait is bounded by the wall clock; an expired wait sets FacState::xerr
+// and the workgroups leave (later panels of the same factorization return at
+// once), so the grid always drains.
+#include <climits>
+
+#include "panel_reg.hpp"
+
+namespace mds {
+namespace {
+
+using panel::amax_combine;
+using panel::keep_branch;
+using panel::lds_wave_sync;
+using panel::w_lane;
+
+constexpr int kCoopMaxN = 20480;  // LDS map of logical positions
+constexpr unsigned long long kCoopWaitTicks = 1ull << 26;  // ~0.67 s of the 100 MHz clock
+
+__device__ inline void put_u32(uint64_t *p, uint32_t v, uint32_t tag) {
+  __hip_atomic_store(p, ((uint64_t)tag << 32) | (uint64_t)v, __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void put_f64(uint64_t *p, double v, uint32_t tag) {
+  const uint64_t b = (uint64_t)__double_as_longlong(v);
+  put_u32(p, (uint32_t)(b >> 32), tag);
+  put_u32(p + 1, (uint32_t)b, tag);
+}
+__device__ inline uint64_t get_w(const uint64_t *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline bool tag_ok(uint64_t w, uint32_t tag) { return (uint32_t)(w >> 32) == tag; }
+__device__ inline double as_f64(uint64_t hi, uint64_t lo) {
+  return __longlong_as_double((long long)(((hi & 0xffffffffull) << 32) | (lo & 0xffffffffull)));
+}
+
+template <int T, int R, int NB, int PMAX, typename TX>
+__global__ __launch_bounds__(T) void k_bk_panel_coop(int N, int nb, double alpha, int Pmax,
+                                                     const TX *__restrict__ X,
+                                                     double *__restrict__ Lout,
+                                                     int32_t *__restrict__ src_out,
+                                                     double *__restrict__ W,
+                                                     double *__restrict__ dd,
+                                                     double *__restrict__ ds,
+                                                     int32_t *__restrict__ ipiv,
+                                                     int32_t *__restrict__ blk, FacState *st,
+                                                     int32_t *__restrict__ panel_k0,
+                                                     uint64_t *__restrict__ xch) {
+  constexpr int NWV = T / 64;
+  constexpr int RW = T * R;
+  constexpr int NR = NB + 1;          // row record: value + L row
+  constexpr int PREC = 2 * NR;        // words of a row record
+  constexpr int X1_CAND = 3;          // [0] position, [1,2] magnitude, then the row record
+  constexpr int X1_POS = X1_CAND + PREC;
+  constexpr int X3_AII = 2 * NWV;     // after the per-wave partial maxima
+  constexpr int X3_POS = X3_AII + 2;
+  constexpr int U1 = ((PMAX + 3) * NR + 63) / 64;  // row-record pairs per lane
+  constexpr int U3 = (PMAX * NWV + 63) / 64;       // partial maxima per lane
+  static_assert(NB % 8 == 0 && NR <= 64 && NWV <= 64, "tile");
+  static_assert(X1_POS + 3 * PREC <= kCoopSlotWords && X3_POS + 6 <= kCoopSlotWords, "slot");
+
+  __shared__ double s_wk[NB], s_wi[NB], s_cA[NB], s_cB[NB], s_cC[NB], s_nrow[NB];
+  __shared__ double s_acur[R * T], s_wkc[R * T], s_wic[R * T];
+  __shared__ int s_map[kCoopMaxN];
+  __shared__ double s_cv[NWV];
+  __shared__ int s_ci[NWV];
+  __shared__ double s_crow[NWV][NR];  // wave candidates: signed value + L row
+  __shared__ double s_prow[3][NR];    // owned rows at positions k, k+1, k+2
+  __shared__ double s_xb[PMAX + 3][NR];  // X1: candidate rows, then position rows
+  __shared__ double s_xwic[3];
+  __shared__ double s_colmax, s_rowmax, s_aii;
+  __shared__ int s_imax, s_gw, s_k0, s_abort;
+  __shared__ uint32_t s_tag0;
+
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int g = blockIdx.x;
+  if (tid == 0) {
+    s_k0 = st->k;
+    s_tag0 = st->xtag;
+    s_abort = st->xerr;
+  }
+  if (tid < NB) {
+    s_wk[tid] = 0.0;
+    s_wi[tid] = 0.0;
+    s_cA[tid] = 0.0;
+    s_cB[tid] = 0.0;
+    s_cC[tid] = 0.0;
+  }
+  __syncthreads();
+  const int k0 = s_k0;
+  if (k0 >= N || s_abort) return;
+  const int P = min(Pmax, (N - k0 + RW - 1) / RW);
+  if (g >= P) return;
+  const int ld = N;  // N <= 20480: every offset fits in 32 bits
+  const int gbase = k0 + g * RW;
+  const uint32_t tagb = ((s_tag0 % 0xffffffu) + 1u) << 8;
+  auto slot = [&](int par, int wg) { return xch + (size_t)(par * kCoopMaxP + wg) * kCoopSlotWords; };
+  auto owner = [&](int phys) { return (phys - k0) / RW; };
+
+  double Lr[R][NB];
+  double pre1[R], pre2[R];
+  int pos[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+#pragma unroll
+    for (int t = 0; t < NB; ++t) Lr[r][t] = 0.0;
+    const int rho = gbase + tid + T * r;
+    pos[r] = (rho < N) ? rho : -1;
+    s_acur[r * T + tid] = (rho < N) ? (double)X[rho + k0 * ld] : 0.0;
+    pre1[r] = pre2[r] = 0.0;
+  }
+  for (int i = tid; i < N - k0; i += T) s_map[i] = k0 + i;
+  __syncthreads();
+
+  int k = k0, j = 0, c = 0;
+  int c_pos = 0, c_zero = 0, c_neg = 0, c_2x2 = 0, first_zero = 0;
+  int pj = -1;
+  bool p2 = false;
+  double pA0 = 0.0, pB0 = 0.0, pA1 = 0.0;
+
+  while (j < nb - 1 && k < N) {
+    if (tid == 0 && pj >= 0) {
+      s_cA[pj] = pA0;
+      s_cB[pj] = pB0;
+      if (p2) {
+        s_cA[pj + 1] = pA1;
+        s_cC[pj + 1] = pB0;
+      }
+    }
+    // ---- prefetch the un-updated column k+1 --------------------------------
+    {
+      const int sc1 = (k + 1 < N) ? s_map[k + 1 - k0] : 0;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int rho = gbase + tid + T * r;
+        if (pos[r] >= k && k + 1 < N) pre1[r] = (double)X[rho + sc1 * ld];
+      }
+    }
+    // ---- updated column k, this workgroup's candidates ----------------------
+    double a[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) a[r] = s_acur[r * T + tid];
+#pragma unroll
+    for (int t0 = 0; t0 < NB; t0 += 8) {
+      if (t0 < j) {
+        keep_branch();
+        double wv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) wv[u] = s_wk[t0 + u];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          if (t0 + u < j) {
+            keep_branch();
+#pragma unroll
+            for (int r = 0; r < R; ++r) a[r] = fma(-Lr[r][t0 + u], wv[u], a[r]);
+          }
+        }
+      }
+    }
+    double bv = -1.0;
+    int bi = INT_MAX, br = -1;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      if (pos[r] >= k) {
+        s_wkc[r * T + tid] = a[r];
+        if (pos[r] != k) {
+          const double v = fabs(a[r]);
+          if (v > bv || (v == bv && pos[r] < bi)) {
+            bv = v;
+            bi = pos[r];
+            br = r;
+          }
+        }
+        const int po = pos[r] - k;
+        if (po <= 2) {
+          keep_branch();
+          s_prow[po][0] = a[r];
+#pragma unroll
+          for (int t = 0; t < NB; ++t) s_prow[po][1 + t] = Lr[r][t];
+        }
+      }
+    }
+    const int mybi = bi;
+    wave::amax(bv, bi);
+    if (lane == 0) {
+      s_cv[wid] = bv;
+      s_ci[wid] = bi;
+    }
+    if (mybi != INT_MAX && mybi == bi) {
+      keep_branch();
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        if (br == r) {
+          keep_branch();
+          s_crow[wid][0] = a[r];
+#pragma unroll
+          for (int t = 0; t < NB; ++t) s_crow[wid][1 + t] = Lr[r][t];
+        }
+      }
+    }
+    __syncthreads();
+
+    // ---- X1: publish, then read every workgroup's (wave 0) ------------------
+    if (wid == 0) {
+      double cv = -1.0;
+      int ci = INT_MAX, cw = 0;
+      if (lane < NWV) {
+        cv = s_cv[lane];
+        ci = s_ci[lane];
+        cw = lane;
+      }
+      wave::amax(cv, ci, cw);  // every lane: lanes <= NB publish the winner's row
+      const int par = c & 1;
+      const uint32_t tag = tagb + (uint32_t)c;
+      uint64_t *mine = slot(par, g);
+      if (lane == 0) {
+        put_u32(mine, (uint32_t)ci, tag);
+        put_f64(mine + 1, cv, tag);
+      }
+      if (lane < NR) put_f64(mine + X1_CAND + 2 * lane, s_crow[cw][lane], tag);
+      // owners of the rows at positions k, k+1, k+2 (-1: past N)
+      const int o0 = owner(s_map[k - k0]);
+      const int o1 = (k + 1 < N) ? owner(s_map[k + 1 - k0]) : -1;
+      const int o2 = (k + 2 < N) ? owner(s_map[k + 2 - k0]) : -1;
+      if (lane < NR) {
+        if (o0 == g) put_f64(mine + X1_POS + 2 * lane, s_prow[0][lane], tag);
+        if (o1 == g) put_f64(mine + X1_POS + PREC + 2 * lane, s_prow[1][lane], tag);
+        if (o2 == g) put_f64(mine + X1_POS + 2 * PREC + 2 * lane, s_prow[2][lane], tag);
+      }
+      // one round trip reads all: headers in lanes < P, row records spread
+      // over the wave (pair p = lane + 64 u: record p / NR, word p % NR)
+      uint64_t h0 = 0, h1 = 0, h2 = 0, whi[U1], wlo[U1];
+      const uint64_t t0 = wall_clock64();
+      bool done = false;
+      for (;;) {
+        bool ok = true;
+        if (lane < P) {
+          const uint64_t *sp = slot(par, lane);
+          h0 = get_w(sp);
+          h1 = get_w(sp + 1);
+          h2 = get_w(sp + 2);
+        }
+#pragma unroll
+        for (int u = 0; u < U1; ++u) {
+          const int p = lane + 64 * u, rec = p / NR, w = p % NR;
+          const uint64_t *ap = nullptr;
+          const int ip = rec - P, op = (ip == 0) ? o0 : (ip == 1) ? o1 : o2;
+          if (rec < P) ap = slot(par, rec) + X1_CAND + 2 * w;
+          else if (ip < 3 && op >= 0) ap = slot(par, op) + X1_POS + ip * PREC + 2 * w;
+          if (ap) {
+            whi[u] = get_w(ap);
+            wlo[u] = get_w(ap + 1);
+          } else {
+            whi[u] = wlo[u] = (uint64_t)tag << 32;
+          }
+        }
+        if (lane < P) ok = tag_ok(h0, tag) && tag_ok(h1, tag) && tag_ok(h2, tag);
+#pragma unroll
+        for (int u = 0; u < U1; ++u) ok = ok && tag_ok(whi[u], tag) && tag_ok(wlo[u], tag);
+        if (__ballot(!ok) == 0) {
+          done = true;
+          break;
+        }
+        if (wall_clock64() - t0 > kCoopWaitTicks) break;
+      }
+      if (!done) {
+        if (lane == 0) {
+          __hip_atomic_store(&st->xerr, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          s_abort = 1;
+        }
+      } else {
+#pragma unroll
+        for (int u = 0; u < U1; ++u) {
+          const int p = lane + 64 * u, rec = p / NR, w = p % NR;
+          if (rec < P + 3) s_xb[rec][w] = as_f64(whi[u], wlo[u]);
+        }
+        double gv = -1.0;
+        int gi = INT_MAX, gw = 0;
+        if (lane < P) {
+          gv = as_f64(h1, h2);
+          gi = (int)(uint32_t)h0;
+          gw = lane;
+        }
+        wave::amax(gv, gi, gw);
+        if (gv < 0.0) {
+          gv = 0.0;
+          gi = k;
+        }
+        lds_wave_sync();
+        // W row of imax from its L row (used when the first test fails)
+        if (lane < NB)
+          s_wi[lane] = w_lane<NB>(&s_xb[gw][1], s_cA, s_cB, s_cC, lane, 0, false, false, 0.0,
+                                  0.0, 0.0);
+        if (lane == 0) {
+          s_colmax = gv;
+          s_imax = gi;
+          s_gw = gw;
+        }
+      }
+    }
+    __syncthreads();
+    if (s_abort) return;
+    ++c;
+    const double colmax = s_colmax;
+    const int imax = s_imax;
+    const double akk = s_xb[P][0], absakk = fabs(akk);
+
+    // ---- Bunch-Kaufman decision ----------------------------------------------
+    int kind;  // 0 zero, 1 1x1, 2 1x1 (second test), 3 1x1 swap, 4 2x2
+    int kstep = 1, q = k;
+    double aii = 0.0, wki = 0.0;
+    if (fmax(absakk, colmax) == 0.0 || isnan(absakk)) {
+      kind = 0;
+    } else if (absakk >= alpha * colmax) {
+      kind = 1;
+    } else {
+      const int src_i = s_map[imax - k0];
+      const int src_k2 = (k + 2 < N) ? s_map[k + 2 - k0] : 0;
+      double wic[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int rho = gbase + tid + T * r;
+        wic[r] = 0.0;
+        if (pos[r] >= k) {
+          wic[r] = (double)X[rho + src_i * ld];
+          if (k + 2 < N) pre2[r] = (double)X[rho + src_k2 * ld];
+        }
+      }
+#pragma unroll
+      for (int t0 = 0; t0 < NB; t0 += 8) {
+        if (t0 < j) {
+          keep_branch();
+          double wv[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) wv[u] = s_wi[t0 + u];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            if (t0 + u < j) {
+              keep_branch();
+#pragma unroll
+              for (int r = 0; r < R; ++r) wic[r] = fma(-Lr[r][t0 + u], wv[u], wic[r]);
+            }
+          }
+        }
+      }
+      // ---- X3: partial maxima of the updated column imax -----------------------
+      const int par = c & 1;
+      const uint32_t tag = tagb + (uint32_t)c;
+      uint64_t *mine = slot(par, g);
+      double rv = 0.0;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        if (pos[r] >= k) {
+          s_wic[r * T + tid] = wic[r];
+          if (pos[r] == imax) put_f64(mine + X3_AII, wic[r], tag);
+          else rv = fmax(rv, fabs(wic[r]));
+          const int po = pos[r] - k;
+          if (po <= 2) put_f64(mine + X3_POS + 2 * po, wic[r], tag);
+        }
+      }
+      rv = wave::max(rv);
+      if (lane == 0) put_f64(mine + 2 * wid, rv, tag);
+      if (wid == 0) {
+        const int oi = owner(src_i);
+        // lane 1 + i < 4 reads the column-imax value at position k + i
+        const int ol = (lane >= 1 && lane <= 3 && k + lane - 1 < N)
+                           ? owner(s_map[k + lane - 1 - k0]) : -1;
+        uint64_t phi[U3], plo[U3], ahi = 0, alo = 0;
+        const uint64_t t0 = wall_clock64();
+        bool done = false;
+        for (;;) {
+          bool ok = true;
+#pragma unroll
+          for (int u = 0; u < U3; ++u) {
+            const int p = lane + 64 * u;
+            if (p < P * NWV) {
+              const uint64_t *ap = slot(par, p / NWV) + 2 * (p % NWV);
+              phi[u] = get_w(ap);
+              plo[u] = get_w(ap + 1);
+            } else {
+              phi[u] = plo[u] = (uint64_t)tag << 32;
+            }
+          }
+          // lane 0: a_ii; lanes 1..3: the column-imax values at positions k..k+2
+          if (lane == 0) {
+            const uint64_t *ap = slot(par, oi) + X3_AII;
+            ahi = get_w(ap);
+            alo = get_w(ap + 1);
+          } else if (lane <= 3) {
+            if (ol >= 0) {
+              const uint64_t *ap = slot(par, ol) + X3_POS + 2 * (lane - 1);
+              ahi = get_w(ap);
+              alo = get_w(ap + 1);
+            } else {
+              ahi = alo = (uint64_t)tag << 32;
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < U3; ++u) ok = ok && tag_ok(phi[u], tag) && tag_ok(plo[u], tag);
+          if (lane <= 3) ok = ok && tag_ok(ahi, tag) && tag_ok(alo, tag);
+          if (__ballot(!ok) == 0) {
+            done = true;
+            break;
+          }
+          if (wall_clock64() - t0 > kCoopWaitTicks) break;
+        }
+        if (!done) {
+          if (lane == 0) {
+            __hip_atomic_store(&st->xerr, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            s_abort = 1;
+          }
+        } else {
+          double m = 0.0;
+#pragma unroll
+          for (int u = 0; u < U3; ++u)
+            if (lane + 64 * u < P * NWV) m = fmax(m, as_f64(phi[u], plo[u]));
+          m = wave::max(m);
+          if (lane == 0) {
+            s_rowmax = m;
+            s_aii = as_f64(ahi, alo);
+          } else if (lane <= 3) {
+            s_xwic[lane - 1] = as_f64(ahi, alo);
+          }
+        }
+      }
+      __syncthreads();
+      if (s_abort) return;
+      ++c;
+      const double rowmax = s_rowmax;
+      aii = s_aii;
+      wki = s_xb[s_gw][0];
+      if (absakk >= alpha * colmax * (colmax / rowmax)) {
+        kind = 2;
+      } else if (fabs(aii) >= alpha * rowmax) {
+        kind = 3;
+        q = imax;
+      } else {
+        kind = 4;
+        q = imax;
+        kstep = 2;
+      }
+    }
+    const int p = k + kstep - 1;
+    const bool sw = (q != p);
+    const int kn = k + kstep;
+    double Da = akk, Dc = 0.0, Db = 0.0, det = 1.0;
+    if (kind == 3) Da = aii;
+    const double Dw = (kind == 0) ? 0.0 : Da;
+    if (kind == 4) {
+      Db = wki;
+      Dc = aii;
+      det = Da * Dc - Db * Db;
+    }
+    const double rD = (kind == 4) ? 1.0 / det : (kind == 3) ? 1.0 / aii : 1.0 / akk;
+
+    // ---- multipliers, new positions, next column ------------------------------
+    double l0[R], l1[R];
+    bool act[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int pr = pos[r];
+      l1[r] = 0.0;
+      if (kind == 4) {
+        act[r] = pr >= k + 1 && pr != q;
+        const double x0 = s_wkc[r * T + tid], y0 = s_wic[r * T + tid];
+        l0[r] = (x0 * Dc - y0 * Db) * rD;
+        l1[r] = (y0 * Da - x0 * Db) * rD;
+      } else if (kind == 3) {
+        act[r] = pr >= k && pr != q;
+        l0[r] = s_wic[r * T + tid] * rD;
+      } else {
+        act[r] = pr > k;
+        l0[r] = (kind == 0) ? 0.0 : s_wkc[r * T + tid] * rD;
+      }
+      int np = pr;
+      if (sw) {
+        if (pr == p) np = q;
+        else if (pr == q) np = p;
+      }
+      pos[r] = np;
+      double an = pre1[r];
+      if (kind == 3 && q == k + 1) an = s_acur[r * T + tid];
+      if (kind == 4 && q != k + 2) an = pre2[r];
+      s_acur[r * T + tid] = an;
+    }
+#pragma unroll
+    for (int t = 0; t < NB; ++t) {
+      if (t == j) {
+        keep_branch();
+#pragma unroll
+        for (int r = 0; r < R; ++r) Lr[r][t] = act[r] ? l0[r] : Lr[r][t];
+      }
+      if (kind == 4 && t == j + 1) {
+        keep_branch();
+#pragma unroll
+        for (int r = 0; r < R; ++r) Lr[r][t] = act[r] ? l1[r] : Lr[r][t];
+      }
+    }
+
+    // ---- W row of the next pivot, from the exchanged rows (wave 0) -------------
+    if (wid == 0 && kn < N) {
+      // the row at position kn came from position k + inx before the interchange
+      const int inx = (kind == 4) ? ((q == k + 2) ? 1 : 2) : (kind == 3 && q == k + 1) ? 0 : 1;
+      const double x0 = s_xb[P + inx][0], y0 = s_xwic[inx];
+      double n0, n1 = 0.0;
+      if (kind == 4) {
+        n0 = (x0 * Dc - y0 * Db) * rD;
+        n1 = (y0 * Da - x0 * Db) * rD;
+      } else if (kind == 3) {
+        n0 = y0 * rD;
+      } else {
+        n0 = (kind == 0) ? 0.0 : x0 * rD;
+      }
+      if (lane < NB) {
+        double v = s_xb[P + inx][1 + lane];
+        if (lane == j) v = n0;
+        if (kind == 4 && lane == j + 1) v = n1;
+        s_nrow[lane] = v;
+      }
+      lds_wave_sync();
+      if (lane < NB)
+        s_wk[lane] = w_lane<NB>(s_nrow, s_cA, s_cB, s_cC, lane, j, true, kind == 4,
+                                (kind == 4) ? Da : Dw, Dc, Db);
+    }
+
+    // ---- pivot records and map -------------------------------------------------
+    if (tid == 0) {
+      if (sw) {
+        const int t0 = s_map[p - k0];
+        s_map[p - k0] = s_map[q - k0];
+        s_map[q - k0] = t0;
+      }
+      if (kind == 4) {
+        if (g == 0) {
+          dd[k] = Da;
+          dd[k + 1] = Dc;
+          ds[k] = Db;
+          ds[k + 1] = 0.0;
+          ipiv[k] = -(q + 1);
+          ipiv[k + 1] = -(q + 1);
+          blk[k] = 2;
+          blk[k + 1] = 3;
+        }
+        c_pos++;
+        c_neg++;
+        c_2x2++;
+      } else {
+        if (g == 0) {
+          dd[k] = Da;
+          ds[k] = 0.0;
+          ipiv[k] = q + 1;
+          blk[k] = 1;
+        }
+        if (Da > 0.0) c_pos++;
+        else if (Da < 0.0) c_neg++;
+        else {
+          c_zero++;
+          if (first_zero == 0) first_zero = k + 1;
+        }
+      }
+    }
+    pj = j;
+    p2 = (kind == 4);
+    pA0 = (kind == 4) ? Da : Dw;
+    pB0 = Db;
+    pA1 = Dc;
+    j += kstep;
+    k = kn;
+    __syncthreads();
+  }
+
+  // ---- write the panel's multipliers and W = L D for the trailing rows ---------
+  const int kend = k, jend = j;
+  if (tid == 0 && pj >= 0) {
+    s_cA[pj] = pA0;
+    s_cB[pj] = pB0;
+    if (p2) {
+      s_cA[pj + 1] = pA1;
+      s_cC[pj + 1] = pB0;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int pr = pos[r];
+    if (pr < 0) continue;
+    const int rho = gbase + tid + T * r;
+#pragma unroll
+    for (int t = 0; t < NB; ++t)
+      if (t < jend && pr > k0 + t) Lout[pr + (k0 + t) * ld] = Lr[r][t];
+    if (pr >= kend) {
+#pragma unroll
+      for (int t = 0; t < NB; ++t) {
+        if (t < jend) {
+          double v = Lr[r][t] * s_cA[t];
+          if (t + 1 < NB) v = v + Lr[r][t + 1 < NB ? t + 1 : t] * s_cB[t];
+          if (t >= 1) v = v + Lr[r][t >= 1 ? t - 1 : 0] * s_cC[t];
+          W[pr + t * ld] = v;
+        }
+      }
+      src_out[pr] = rho;
+    }
+  }
+  if (g == 0 && tid == 0) {
+    const int b = st->npanel;
+    panel_k0[b + 1] = kend;
+    st->npanel = b + 1;
+    st->k = kend;
+    st->npos += c_pos;
+    st->nzero += c_zero;
+    st->nneg += c_neg;
+    st->n2x2 += c_2x2;
+    if (st->info == 0 && first_zero != 0) st->info = first_zero;
+    st->xtag = s_tag0 + 1u;
+  }
+}
+
+// Variants: (threads, rows per thread, register tile, most workgroups)
+constexpr int kCoopT = 512, kCoopR = 2, kCoopNB = 32;
+constexpr int kCoopP = (kCoopMaxN + kCoopT * kCoopR - 1) / (kCoopT * kCoopR);
+
+}  // namespace
+
+int bk_coop_rows_per_wg() { return kCoopT * kCoopR; }
+int bk_coop_nb() { return kCoopNB; }
+int bk_coop_wgs(int N) { return (N + kCoopT * kCoopR - 1) / (kCoopT * kCoopR); }
+
+// The exchange reads of X1 hold (PMAX + 3) (NB + 1) / 64 word pairs per lane
+// in registers, so the grid size picks the smallest instantiation.
+template <typename TX>
+static void panel_coop(hipStream_t s, int N, int nb, double alpha, const TX *X, double *Lout,
+                       int32_t *src_out, double *W, double *dd, double *ds, int32_t *ipiv,
+                       int32_t *blk, FacState *st, int32_t *panel_k0, uint64_t *xch) {
+  const int P = bk_coop_wgs(N);
+#define MDS_COOP(PM_)                                                                  \
+  k_bk_panel_coop<kCoopT, kCoopR, kCoopNB, PM_, TX><<<P, kCoopT, 0, s>>>(              \
+      N, nb, alpha, P, X, Lout, src_out, W, dd, ds, ipiv, blk, st, panel_k0, xch)
+  if (P <= 4) MDS_COOP(4);
+  else if (P <= 8) MDS_COOP(8);
+  else if (P <= 12) MDS_COOP(12);
+  else MDS_COOP(kCoopP);
+#undef MDS_COOP
+}
+
+void launch_bk_panel_coop(hipStream_t s, int N, int nb, double alpha, const double *X,
+                          double *Lout, int32_t *src_out, double *W, double *dd, double *ds,
+                          int32_t *ipiv, int32_t *blk, FacState *st, int32_t *panel_k0,
+                          uint64_t *xch) {
+  panel_coop(s, N, nb, alpha, X, Lout, src_out, W, dd, ds, ipiv, blk, st, panel_k0, xch);
+}
+
+void launch_bk_panel_coop(hipStream_t s, int N, int nb, double alpha, const float *X,
+                          double *Lout, int32_t *src_out, double *W, double *dd, double *ds,
+                          int32_t *ipiv, int32_t *blk, FacState *st, int32_t *panel_k0,
+                          uint64_t *xch) {
+  panel_coop(s, N, nb, alpha, X, Lout, src_out, W, dd, ds, ipiv, blk, st, panel_k0, xch);
+}
+
+}  // namespace mds

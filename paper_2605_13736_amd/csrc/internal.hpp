@@ -17,6 +17,8 @@ constexpr int kMaxNb = 64;           // largest supported panel width
 constexpr int kRedBlocks = 1024;     // partial-reduction slots
 constexpr int kDotBlocks = 64;       // blocks per column of a Krylov dot product
 constexpr int kGmresRestart = 20;    // GMRES restart length of the mixed-precision refinement
+constexpr int kCoopMaxP = 32;        // cooperative panel: most workgroups
+constexpr int kCoopSlotWords = 512;  // cooperative panel: 64-bit exchange words per workgroup and parity
 
 // Device-side factorization progress, written by the panel kernel.
 struct FacState {
@@ -24,7 +26,8 @@ struct FacState {
   int32_t npanel;  // panels completed
   int32_t info;    // 1-based index of the first exact zero pivot, or 0
   int32_t npos, nzero, nneg, n2x2;
-  int32_t pad;
+  uint32_t xtag;  // cooperative panel: launch counter behind its exchange tags (never reset)
+  int32_t xerr;   // cooperative panel: an exchange wait expired
 };
 
 // Pointers into the caller's workspace.
@@ -54,6 +57,7 @@ struct Work {
   int32_t *perm;      // N: final row permutation of the factorization
   int32_t *colpanel;  // N: panel of each column
   int32_t *trsv;      // solve epoch, error word, pad, per-block flags (2 x blocks)
+  uint64_t *xch;      // cooperative panel exchange words
   // Newton / IPM vectors
   double *sig, *rx, *ry, *dsb;       // n, n, m, n_s
   double *dx, *dy, *dzl, *dzu, *xt;  // n, m, n, n, n
@@ -72,7 +76,8 @@ struct mds_handle {
   hipStream_t stream = nullptr;
   mds_dims dims{};
   int N = 0, n = 0, nb = 16, max_panels = 0;
-  bool panel_reg = false;  // register-resident panel kernel
+  bool panel_reg = false;  // register-resident panel kernel (ping-pong layout)
+  bool panel_coop = false; // ... spread over several workgroups
   int panel_threads = 512; // its workgroup size
   int precision = MDS_FP64;
   int adv = 16;            // least number of columns a panel factors
@@ -140,6 +145,21 @@ void launch_bk_panel_reg(hipStream_t s, int threads, int N, int nb, double alpha
 void launch_bk_panel_reg(hipStream_t s, int threads, int N, int nb, double alpha, const float *X,
                          double *Lout, int32_t *src_out, double *W, double *dd, double *ds,
                          int32_t *ipiv, int32_t *blk, FacState *st, int32_t *panel_k0);
+
+// bk_coop.hip: cooperative register panel over several workgroups (any N up
+// to the solver limit; X in FP64 or FP32); xch: 2 * kCoopMaxP * kCoopSlotWords
+// exchange words, zeroed once
+int bk_coop_rows_per_wg();
+int bk_coop_nb();
+int bk_coop_wgs(int N);
+void launch_bk_panel_coop(hipStream_t s, int N, int nb, double alpha, const double *X,
+                          double *Lout, int32_t *src_out, double *W, double *dd, double *ds,
+                          int32_t *ipiv, int32_t *blk, FacState *st, int32_t *panel_k0,
+                          uint64_t *xch);
+void launch_bk_panel_coop(hipStream_t s, int N, int nb, double alpha, const float *X,
+                          double *Lout, int32_t *src_out, double *W, double *dd, double *ds,
+                          int32_t *ipiv, int32_t *blk, FacState *st, int32_t *panel_k0,
+                          uint64_t *xch);
 
 // bk_lp.hip: FP32-storage trailing update (mode MDS_FP32 or MDS_BF16 products)
 void launch_trailing_lp(hipStream_t s, int mode, int N, int nb, int adv, int slot,

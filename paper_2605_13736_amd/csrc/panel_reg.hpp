@@ -26,6 +26,7 @@
 #include <climits>
 
 #include "internal.hpp"
+#include "wave.hpp"
 
 namespace mds {
 namespace panel {
@@ -180,12 +181,7 @@ __device__ inline void panel_reg_dev(int N, int nb, double alpha,
         else amax_combine(bv, bi, fabs(a[r]), pos[r]);
       }
     }
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-      const double v2 = __shfl_xor(bv, off);
-      const int i2 = __shfl_xor(bi, off);
-      amax_combine(bv, bi, v2, i2);
-    }
+    wave::amax(bv, bi);
     if (lane == 0) {
       s_rv[wid] = bv;
       s_ri[wid] = bi;
@@ -263,8 +259,7 @@ __device__ inline void panel_reg_dev(int N, int nb, double alpha,
           else rv = fmax(rv, fabs(wic[r]));
         }
       }
-#pragma unroll
-      for (int off = 32; off > 0; off >>= 1) rv = fmax(rv, __shfl_xor(rv, off));
+      rv = wave::max(rv);
       if (lane == 0) s_rv[wid] = rv;
       __syncthreads();
       double rowmax = 0.0;

@@ -81,7 +81,7 @@ def _factor_check(S, Mo):
 
 
 PANELS = {"auto": dict(panel="auto"), "mem": dict(panel="mem"), "reg": dict(panel="reg"),
-          "reg1024": dict(panel="reg", panel_threads=1024)}
+          "reg1024": dict(panel="reg", panel_threads=1024), "coop": dict(panel="coop")}
 
 
 @pytest.mark.parametrize("panel", list(PANELS))
@@ -89,7 +89,7 @@ PANELS = {"auto": dict(panel="auto"), "mem": dict(panel="mem"), "reg": dict(pane
 def test_factor_pivots_and_inertia_exact(idx, panel):
     prob, st, nb = _case(idx, seed=1)
     say(f"factor case={CASES[idx]} panel={panel}")
-    if panel == "reg1024" and nb > 32:
+    if panel in ("reg1024", "coop") and nb > 32:
         nb = 32
     S = mds.solver_for(prob, nb=nb, **PANELS[panel])
     S.condense(st["sigma_d"], st["dsbase"], 0.0, 0.0)
