@@ -349,7 +349,8 @@ def main():
         roof = dict(bound="hbm", achieved=per_launch / avg_s / 1e9, peak=HBM_PEAK_GBS,
                     unit="GB/s")
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["kernel"] = {"panel": "k_bk_panel_reg" if info0["panel"] == "reg" else "k_bk_panel",
+    panel_kernel = {"reg": "k_bk_panel_reg", "coop": "k_bk_panel_coop"}.get(info0["panel"], "k_bk_panel")
+    roof["kernel"] = {"panel": panel_kernel,
                       "trailing": "k_bk_trailing",
                       "solve": "k_trsv_fwd+k_trsv_bwd", "condense": "k_condense_dense",
                       "permute": "k_std_sweep+k_std_apply"}[dom]

@@ -171,10 +171,10 @@ int panel_threads_of(const mds_options *o) {
 // Panel choice.  panel option 1: memory panel; 2: register panel (N <= 4096);
 // 3: cooperative register panel over several workgroups (any N);
 // 0 (automatic): the register panel while its tile keeps nb >= 16
-// (N <= 2048 with 512 threads), else the memory panel, whose wider panels
-// cost less trailing-update traffic than the register panel's nb = 8 at
-// N = 4096.  The mixed-precision modes need a register-resident panel (2 or
-// 3; automatic: 2 up to N = 4096, else 3).
+// (N <= 2048 with 512 threads), else the cooperative panel (nb = 32, about
+// 6 us per pivot at N = 4096 against 7-8 us for the memory panel, and half
+// the trailing-update traffic).  The mixed-precision modes need a
+// register-resident panel (2 or 3).
 PanelChoice panel_of(const mds_dims &d, const mds_options *o) {
   const int N = d.n_d + d.m;
   const int popt = o ? o->panel : 0;
@@ -187,9 +187,8 @@ PanelChoice panel_of(const mds_dims &d, const mds_options *o) {
   if (popt < 0 || popt > 3) return c;
   if (prec != MDS_FP64 && popt == 1) return c;
   if (popt == 2 && rnb == 0) return c;
-  const bool use_reg =
-      rnb > 0 && (popt == 2 || (popt == 0 && (rnb >= 16 || prec != MDS_FP64)));
-  const bool use_coop = !use_reg && (popt == 3 || (popt == 0 && prec != MDS_FP64));
+  const bool use_reg = rnb > 0 && (popt == 2 || (popt == 0 && rnb >= 16));
+  const bool use_coop = !use_reg && (popt == 3 || popt == 0);
   if (use_reg) {
     int nb = (o && o->nb > 0) ? o->nb : rnb;
     nb = std::min(std::max(nb, 2), rnb);

@@ -1,5 +1,7 @@
 """Parity at the benchmarked size (n_d = 1024, n_s = 200000, m = 3072, N = 4096),
-in the launch configuration the benchmark times (default panel choice).
+in the launch configuration the benchmark times (default panel choice: the
+cooperative register panel), and with the single-workgroup register and
+memory panels.
 
 * M is compared bit for bit with the oracle's condensation (all N^2 entries);
 * the pivot sequence and inertia are compared with the oracle's unblocked
@@ -32,7 +34,7 @@ def big():
     return dict(prob=prob, P=P, sig=sig, rx=rx, ry=ry, dsb=prob["w"] + sig[nd:], nd=nd)
 
 
-@pytest.mark.parametrize("panel", ["auto", "reg"])
+@pytest.mark.parametrize("panel", ["auto", "reg", "mem"])
 def test_fullsize_condense_factor_solve(big, panel):
     prob, P, nd = big["prob"], big["P"], big["nd"]
     say(f"N=4096 condense/factor/solve panel={panel}")

@@ -111,6 +111,28 @@ def test_mixed_ipm_converges_to_oracle_solution(prec):
     assert np.abs(x - r_o["x"]).max() <= 1e-7 * max(1.0, np.abs(r_o["x"]).max())
 
 
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_mixed_cooperative_panel(prec):
+    # N = 1200 over two cooperating workgroups, nb = 32
+    nd, ns, m, r, _ = CASES[4]
+    prob = synth.make_problem(nd, ns, m, r, cfg=504, p=0)
+    st = synth.kkt_state(prob, 0, (-1.0, 1.0))
+    say(f"mixed {prec} cooperative panel N={nd + m}")
+    S = mds.solver_for(prob, panel="coop", precision=prec)
+    assert S.info()["panel"] == "coop" and S.info()["nb"] == 32
+    S.condense(st["sigma_d"], st["dsbase"], 1e-6, 1e-9)
+    S.factor_inertia()
+    (rd, rs, ry), info = S.refine(st["r_d"], st["r_s"], st["r_y"], 60, 1e-14)
+    P = oracle.Problem(prob)
+    F = oracle.Factor(P).once(st["sigma_d"], st["dsbase"], 1e-6, 1e-9)
+    od, os_, oy, _ = F.solve(st["r_d"], st["r_s"], st["r_y"])
+    got = np.concatenate([_np(rd), _np(rs), _np(ry)])
+    ref = np.concatenate([od, os_, oy])
+    assert info["eta"] <= 1e-12
+    assert info["steps"] <= ITER_CAP[prec]
+    assert np.abs(got - ref).max() <= 1e-8 * max(np.abs(ref).max(), 1e-300)
+
+
 def test_mixed_needs_register_panel():
     prob = synth.make_problem(10, 40, 27, 3, cfg=520, p=0)
     with pytest.raises(mds.MdsError):
