@@ -271,7 +271,10 @@ int mds_ipm_init(mds_handle *h, mds_iterate *it, const mds_ipm_opts *opts);
  * and y0 (m) device arrays, barrier parameter mu0 > 0.  x_s is completed from
  * the sparse block's stationarity, -(g + J_s' y0) / w where w > 0 (else 0);
  * every x_i is pushed into the interior of its bounds by the cold start's
- * rule; y = y0; z = mu0 / slack on finite bounds. */
+ * rule; y = y0; z = mu0 / slack on finite bounds, plus the part of the dual
+ * residual r = grad f(x) + J' y0 the bound can carry (r > 0 added to z_l,
+ * -r > 0 to z_u), so that the start is near-stationary when the proposal is
+ * near a solution. */
 int mds_ipm_init_warm(mds_handle *h, mds_iterate *it, const mds_ipm_opts *opts,
                       const double *x_d0, const double *y0, double mu0);
 
@@ -385,11 +388,12 @@ void mds_batch_destroy(mds_batch *b);
 /* ---- learned warm start: the multilayer perceptron ------------------------ */
 
 /* MLP dims[0] -> dims[1] -> dims[2] -> dims[3] with GELU (erf form) after the
- * two hidden layers, trained by mean-squared error with Adam (beta 0.9 /
+ * two hidden layers and a linear skip path from the input to the output
+ * (Y = H2 W2 + b2 + X Ws), trained by mean-squared error with Adam (beta 0.9 /
  * 0.999, eps 1e-8) in FP32 on FP32 MFMA; inference in FP32 or on BF16 MFMA
  * with FP32 accumulation.  Parameters are one FP32 vector: W0 (dims[0] x
- * dims[1], row-major), b0, W1, b1, W2, b2.  Activations are row-major
- * (batch x features) device arrays. */
+ * dims[1], row-major), b0, W1, b1, W2, b2, Ws (dims[0] x dims[3]).
+ * Activations are row-major (batch x features) device arrays. */
 typedef struct mds_mlp mds_mlp;
 size_t mds_mlp_workspace_bytes(const int32_t dims[4], int32_t max_batch);
 int mds_mlp_create(mds_mlp **out, const int32_t dims[4], int32_t max_batch, void *stream,

@@ -599,8 +599,12 @@ typedef struct { double th, ph; } fentry;
  * start): the proposed x_d and y; x_s from the stationarity of the separable
  * sparse block without bound multipliers, x_s = -(g + J_s' y) / w where
  * w > 0 (else 0); every x_i then projected into the interior of its bounds by
- * the same kappa_1/kappa_2 rule as the cold start; z_l = mu0 / (x - l),
- * z_u = mu0 / (u - x) on finite bounds (0 otherwise). */
+ * the same kappa_1/kappa_2 rule as the cold start.  Bound multipliers: the
+ * centred z_l = mu0 / (x - l), z_u = mu0 / (u - x) on finite bounds (0
+ * otherwise), plus the part of the dual residual r = grad f(x) + J' y that
+ * the bound can carry (stationarity of the Lagrangian asks z_l - z_u = r):
+ * r_i > 0 is added to z_l,i when l_i is finite, -r_i > 0 to z_u,i when u_i is
+ * finite. */
 static void warm_point(const orq_problem *P, const double *xd0, const double *y0, double mu0,
                        double *x, double *y, double *zl, double *zu) {
   const int nd = P->n_d, ns = P->n_s, m = P->m, n = nd + ns;
@@ -631,7 +635,18 @@ static void warm_point(const orq_problem *P, const double *xd0, const double *y0
     zl[i] = hl ? mu0 / (xi - l) : 0.0;
     zu[i] = hu ? mu0 / (u - xi) : 0.0;
   }
+  double *gf = (double *)calloc((size_t)(n > 0 ? n : 1), sizeof(double));
+  double *jt = (double *)calloc((size_t)(n > 0 ? n : 1), sizeof(double));
+  grad_f(P, x, gf);
+  jac_t(P, y0, jt);
+  for (int i = 0; i < n; ++i) {
+    const double r = gf[i] + jt[i];
+    if (r > 0.0 && isfinite(P->xl[i])) zl[i] = zl[i] + r;
+    if (r < 0.0 && isfinite(P->xu[i])) zu[i] = zu[i] - r;
+  }
   for (int r = 0; r < m; ++r) y[r] = y0[r];
+  free(gf);
+  free(jt);
   free(jty);
 }
 

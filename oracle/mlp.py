@@ -3,10 +3,12 @@ imported by tests/, smoke() and the benchmark's CPU baseline, never by the
 library path).
 
 The model is in0 -> h -> h -> out with GELU after the two hidden layers,
-GELU(z) = z Phi(z) with Phi the standard normal CDF (the erf form), trained
-on the mean-squared error mean((Y - T)^2) with Adam (Kingma & Ba; beta1 0.9,
-beta2 0.999, eps 1e-8, bias-corrected moments).  Parameters are one flat
-vector: W0 (in0 x h, row-major), b0, W1 (h x h), b1, W2 (h x out), b2.
+GELU(z) = z Phi(z) with Phi the standard normal CDF (the erf form), plus a
+linear skip path from the input to the output: Y = H2 W2 + b2 + X Ws.  It is
+trained on the mean-squared error mean((Y - T)^2) with Adam (Kingma & Ba;
+beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected moments).  Parameters are one
+flat vector: W0 (in0 x h, row-major), b0, W1 (h x h), b1, W2 (h x out), b2,
+Ws (in0 x out).
 Everything is written from the definitions, in float64, one layer at a time.
 """
 from __future__ import annotations
@@ -26,7 +28,7 @@ def gelu_grad(z):
 
 def shapes(dims):
     return [(dims[0], dims[1]), (dims[1],), (dims[1], dims[2]), (dims[2],), (dims[2], dims[3]),
-            (dims[3],)]
+            (dims[3],), (dims[0], dims[3])]
 
 
 def n_params(dims):
@@ -43,11 +45,11 @@ def unpack(params, dims):
 
 
 def init_params(dims, seed):
-    """He-style normal weights (std sqrt(2/fan_in)), zero biases."""
+    """He-style normal weights (std sqrt(2/fan_in)), zero biases, zero skip."""
     rng = np.random.default_rng(np.random.SeedSequence([55, seed]))
     parts = []
-    for s in shapes(dims):
-        if len(s) == 2:
+    for q, s in enumerate(shapes(dims)):
+        if len(s) == 2 and q < 6:
             parts.append(rng.standard_normal(s) * np.sqrt(2.0 / s[0]))
         else:
             parts.append(np.zeros(s))
@@ -55,19 +57,19 @@ def init_params(dims, seed):
 
 
 def forward(params, dims, X):
-    W0, b0, W1, b1, W2, b2 = unpack(params, dims)
+    W0, b0, W1, b1, W2, b2, Ws = unpack(params, dims)
     X = np.asarray(X, dtype=np.float64)
     Z1 = X @ W0 + b0
     H1 = gelu(Z1)
     Z2 = H1 @ W1 + b1
     H2 = gelu(Z2)
-    Y = H2 @ W2 + b2
+    Y = H2 @ W2 + b2 + X @ Ws
     return Y, (X, Z1, H1, Z2, H2)
 
 
 def loss_and_grad(params, dims, X, T):
     """Mean-squared error and its gradient by the chain rule, layer by layer."""
-    W0, b0, W1, b1, W2, b2 = unpack(params, dims)
+    W0, b0, W1, b1, W2, b2, Ws = unpack(params, dims)
     Y, (X, Z1, H1, Z2, H2) = forward(params, dims, X)
     D = Y - np.asarray(T, dtype=np.float64)
     L = float(np.mean(D * D))
@@ -80,7 +82,8 @@ def loss_and_grad(params, dims, X, T):
     dZ1 = (dZ2 @ W1.T) * gelu_grad(Z1)
     gW0 = X.T @ dZ1
     gb0 = dZ1.sum(axis=0)
-    g = np.concatenate([a.ravel() for a in (gW0, gb0, gW1, gb1, gW2, gb2)])
+    gWs = X.T @ dY
+    g = np.concatenate([a.ravel() for a in (gW0, gb0, gW1, gb1, gW2, gb2, gWs)])
     return L, g
 
 

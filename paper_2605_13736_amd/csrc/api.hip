@@ -983,6 +983,9 @@ int mds_ipm_init_warm(mds_handle *h, mds_iterate *it, const mds_ipm_opts *opts,
   h->ipm = o;
   ipm_init_warm(S(h), ND(h), NS(h), MM(h), h->P.xl, h->P.xu, h->P.w, h->P.g, h->w.csc_ptr,
                 h->w.csc_row, h->w.csc_val, x_d0, y0, mu0, it->x, it->y, it->zl, it->zu);
+  eval_grad_constr(h, it->x, MM(h) > 0 ? it->y : nullptr, nullptr);
+  if (MM(h) == 0 && h->n > 0) HIPCHK(hipMemsetAsync(h->w.tn2, 0, 8 * (size_t)h->n, S(h)));
+  ipm_warm_duals(S(h), h->n, h->P.xl, h->P.xu, h->w.tn, h->w.tn2, it->zl, it->zu);
   HIPCHK(hipGetLastError());
   it->mu = mu0;
   it->tau = std::max(0.99, 1.0 - it->mu);

@@ -86,6 +86,19 @@ __global__ void k_init_warm(int nd, int ns, int m, const double *__restrict__ xl
   if (i < m) y[i] = y0[i];
 }
 
+// Warm start, bound multipliers: add to the centred mu0 / s the part of the
+// dual residual r = grad f(x) + J'y each finite bound can carry
+// (stationarity asks z_l - z_u = r): r > 0 to z_l, -r > 0 to z_u.
+__global__ void k_warm_duals(int n, const double *__restrict__ xl, const double *__restrict__ xu,
+                             const double *__restrict__ gf, const double *__restrict__ jty,
+                             double *__restrict__ zl, double *__restrict__ zu) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double r = gf[i] + jty[i];
+  if (r > 0.0 && isfinite(xl[i])) zl[i] = zl[i] + r;
+  if (r < 0.0 && isfinite(xu[i])) zu[i] = zu[i] - r;
+}
+
 // gf[0:nd] holds H x_d on entry; gradient of f completed in place.
 __global__ void k_grad_finish(int nd, int ns, const double *__restrict__ c,
                               const double *__restrict__ w, const double *__restrict__ g,
@@ -504,6 +517,12 @@ void ipm_init_warm(hipStream_t s, int nd, int ns, int m, const double *xl, const
   if (len <= 0) return;
   k_init_warm<<<grid1(len, 256), 256, 0, s>>>(nd, ns, m, xl, xu, w, g, cptr, crow, cval, xd0, y0,
                                               mu0, x, y, zl, zu);
+}
+
+void ipm_warm_duals(hipStream_t s, int n, const double *xl, const double *xu, const double *gf,
+                    const double *jty, double *zl, double *zu) {
+  if (n <= 0) return;
+  k_warm_duals<<<grid1(n, 256), 256, 0, s>>>(n, xl, xu, gf, jty, zl, zu);
 }
 
 void ipm_grad_finish(hipStream_t s, int nd, int ns, const double *c, const double *w,

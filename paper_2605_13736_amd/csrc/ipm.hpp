@@ -13,6 +13,9 @@ void ipm_init_warm(hipStream_t s, int nd, int ns, int m, const double *xl, const
                    const double *w, const double *g, const int32_t *cptr, const int32_t *crow,
                    const double *cval, const double *xd0, const double *y0, double mu0,
                    double *x, double *y, double *zl, double *zu);
+// zl, zu += the bound-carried parts of r = gf + jty (warm start)
+void ipm_warm_duals(hipStream_t s, int n, const double *xl, const double *xu, const double *gf,
+                    const double *jty, double *zl, double *zu);
 void ipm_grad_finish(hipStream_t s, int nd, int ns, const double *c, const double *w,
                      const double *g, const double *x, double *gf);
 void ipm_sigma_rhs(hipStream_t s, int n, const double *x, const double *zl, const double *zu,

@@ -1,5 +1,6 @@
 // Warm-start model: a multilayer perceptron in0 -> h -> h -> out with GELU
-// (exact, erf form) after the two hidden layers, trained by mean-squared
+// (exact, erf form) after the two hidden layers and a linear skip path from
+// the input to the output (Y = H2 W2 + b2 + X Ws), trained by mean-squared
 // error with Adam, all in own HIP kernels.  Training products run on FP32
 // MFMA (v_mfma_f32_16x16x4f32); inference can run on BF16 MFMA with FP32
 // accumulation (v_mfma_f32_16x16x16bf16_1k).  Row-major activations
@@ -182,10 +183,10 @@ struct mds_mlp {
   int d[4] = {0, 0, 0, 0};  // in, h, h, out
   int max_batch = 0;
   int64_t step = 0;
-  // parameters and Adam state (device, FP32): W0 b0 W1 b1 W2 b2 contiguous
+  // parameters and Adam state (device, FP32): W0 b0 W1 b1 W2 b2 Ws contiguous
   float *param = nullptr, *grad = nullptr, *m1 = nullptr, *m2 = nullptr;
   int64_t nparam = 0;
-  int64_t off_w[3] = {0, 0, 0}, off_b[3] = {0, 0, 0};
+  int64_t off_w[3] = {0, 0, 0}, off_b[3] = {0, 0, 0}, off_s = 0;
   // activations: A0 (input copy not needed), Z1, H1, Z2, H2, Y; gradients dH, dZ
   float *z[3] = {nullptr, nullptr, nullptr}, *h[3] = {nullptr, nullptr, nullptr};
   float *dA = nullptr, *dB = nullptr;
@@ -199,7 +200,7 @@ size_t mds_mlp_workspace_bytes(const int32_t dims[4], int32_t max_batch) {
   for (int i = 0; i < 4; ++i)
     if (dims[i] <= 0 || dims[i] > (1 << 20)) return 0;
   const int64_t np = (int64_t)dims[0] * dims[1] + dims[1] + (int64_t)dims[1] * dims[2] + dims[2] +
-                     (int64_t)dims[2] * dims[3] + dims[3];
+                     (int64_t)dims[2] * dims[3] + dims[3] + (int64_t)dims[0] * dims[3];
   const int64_t wmax = std::max(std::max(dims[1], dims[2]), std::max(dims[3], dims[0]));
   const int64_t act = (int64_t)max_batch * (dims[1] + dims[2] + dims[3]);
   const int64_t nblk = ((int64_t)max_batch * dims[3] + 255) / 256;
@@ -225,6 +226,8 @@ int mds_mlp_create(mds_mlp **out, const int32_t dims[4], int32_t max_batch, void
     M->off_b[l] = o;
     o += dims[l + 1];
   }
+  M->off_s = o;
+  o += (int64_t)dims[0] * dims[3];
   M->nparam = o;
   float *p = (float *)workspace;
   M->param = p;
@@ -260,7 +263,8 @@ void mds_mlp_destroy(mds_mlp *M) { delete M; }
 
 int32_t mds_mlp_param_count(const mds_mlp *M) { return M ? (int32_t)M->nparam : 0; }
 
-// params: W0 (in x h) b0 W1 (h x h) b1 W2 (h x out) b2, row-major, FP32, host
+// params: W0 (in x h) b0 W1 (h x h) b1 W2 (h x out) b2 Ws (in x out),
+// row-major, FP32, host
 int mds_mlp_set_params(mds_mlp *M, const float *params_host) {
   if (!M || !params_host) return MDS_ENULL;
   if (hipMemcpyAsync(M->param, params_host, 4 * (size_t)M->nparam, hipMemcpyHostToDevice,
@@ -296,6 +300,9 @@ int mds_mlp_forward(mds_mlp *M, const float *X, int32_t batch, int32_t precision
          M->param + M->off_b[l], M->z[l], outp, N, l < 2 ? 1 : 0, 0);
     in = outp;
   }
+  // skip path: Y += X Ws
+  gemm(M->stream, mode, batch, M->d[3], M->d[0], X, M->d[0], 1, M->param + M->off_s, M->d[3], 1,
+       nullptr, nullptr, Y, M->d[3], 0, 1);
   return hipGetLastError() == hipSuccess ? MDS_OK : MDS_EHIP;
 }
 
@@ -315,6 +322,9 @@ int mds_mlp_train_step(mds_mlp *M, const float *X, const float *T, int32_t batch
   const unsigned nblk = g256(ny);
   float *dY = M->dA;
   k_mse<<<nblk, 256, 0, s>>>(ny, Yout, T, 2.0f / (float)ny, dY, M->part);
+  // skip path: dWs = X' dY  (in x out)
+  gemm(s, 0, d[0], d[3], batch, X, 1, d[0], dY, d[3], 1, nullptr, nullptr, M->grad + M->off_s, d[3],
+       0, 0);
   // backward through the three layers
   float *dcur = dY;  // gradient w.r.t. the layer output (after activation)
   for (int l = 2; l >= 0; --l) {

@@ -10,9 +10,10 @@ arranges arrays (normalisation, batching) and the host-side schedule.
 
 Targets per training problem: x_d* and y* of the converged cold solve, and
 log10 of the barrier parameter at the first cold iteration whose scaled
-optimality error is <= 1e-1 (a point of the cold path about as far from the
-solution as a learned guess is; a smaller mu0 leaves a guess far off the
-central path and costs iterations).
+optimality error is <= 1e-2.  The warm start completes x_s from y and takes
+bound multipliers that carry the dual residual of the proposal (see
+mds_ipm_init_warm), so a proposal near the solution starts near-stationary
+and a small mu0 pays off.
 """
 from __future__ import annotations
 
@@ -21,7 +22,7 @@ import numpy as np
 from . import MLP, solver_for
 
 
-def mu_target(trace, level=1e-1):
+def mu_target(trace, level=1e-2):
     for row in trace:
         if row["E0"] <= level:
             return row["mu"]
@@ -50,7 +51,9 @@ def solve_family(problems, device="cuda:0"):
 
 
 class WarmStart:
-    """Perceptron b -> (x_d, y, log10 mu0) with per-feature normalisation."""
+    """Perceptron b -> (x_d, y, log10 mu0) with per-feature normalisation; its
+    linear skip path carries the affine part of the map (what a least-squares
+    fit would find), the GELU layers the rest."""
 
     def __init__(self, m, n_d, hidden=1024, max_batch=256, device="cuda:0", seed=0):
         self.m, self.n_d = m, n_d
@@ -64,12 +67,19 @@ class WarmStart:
         rng = np.random.default_rng(np.random.SeedSequence([55, seed]))
         d = self.dims
         parts = []
-        for (a, b) in ((d[0], d[1]), (d[1], d[2]), (d[2], d[3])):
-            parts.append(rng.standard_normal((a, b)) * np.sqrt(2.0 / a))
+        for q, (a, b) in enumerate(((d[0], d[1]), (d[1], d[2]), (d[2], d[3]))):
+            # the output layer of the GELU branch starts at zero, so training
+            # first fits the skip path and the branch grows from there
+            w = rng.standard_normal((a, b)) * np.sqrt(2.0 / a)
+            parts.append(w if q < 2 else np.zeros((a, b)))
             parts.append(np.zeros(b))
+        parts.append(np.zeros((d[0], d[3])))  # skip path starts at zero
         return np.concatenate([p.ravel() for p in parts]).astype(np.float32)
 
-    def fit(self, X, T, steps=300, lr=1e-3, batch=64):
+    def fit(self, X, T, steps=300, lr=1e-3, batch=64, noise=0.0):
+        """Adam on minibatches of the normalised data; noise > 0 adds
+        N(0, noise^2) to the normalised inputs of every minibatch (for the
+        linear part the same as a ridge penalty, for the branch a smoothing)."""
         self.xm, self.xs = X.mean(0), X.std(0) + 1e-12
         self.tm, self.ts = T.mean(0), T.std(0) + 1e-12
         Xn = ((X - self.xm) / self.xs).astype(np.float32)
@@ -79,7 +89,10 @@ class WarmStart:
         losses = []
         for s in range(steps):
             idx = self.rng.choice(n, batch, replace=False)
-            losses.append(self.net.train_step(Xn[idx], Tn[idx], lr))
+            xb = Xn[idx]
+            if noise > 0.0:
+                xb = xb + (noise * self.rng.standard_normal(xb.shape)).astype(np.float32)
+            losses.append(self.net.train_step(xb, Tn[idx], lr))
         return losses
 
     def predict(self, b, precision="bf16"):

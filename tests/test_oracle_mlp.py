@@ -48,7 +48,7 @@ def test_loss_gradient_matches_finite_differences():
 
 def test_identity_regime_reduces_to_linear_map():
     # with large positive pre-activations GELU is the identity, so the network
-    # is the affine map X W0 W1 W2 + (b0 W1 + b1) W2 + b2
+    # is the affine map X W0 W1 W2 + (b0 W1 + b1) W2 + b2, plus the skip X Ws
     dims = (2, 3, 3, 2)
     W0 = np.array([[1.0, 0.5, 0.2], [0.3, 1.0, 0.4]])
     W1 = np.eye(3)
@@ -56,10 +56,11 @@ def test_identity_regime_reduces_to_linear_map():
     b0 = np.full(3, 40.0)
     b1 = np.zeros(3)
     b2 = np.array([0.5, -0.5])
-    p = np.concatenate([W0.ravel(), b0, W1.ravel(), b1, W2.ravel(), b2])
+    Ws = np.array([[2.0, -1.0], [0.0, 3.0]])
+    p = np.concatenate([W0.ravel(), b0, W1.ravel(), b1, W2.ravel(), b2, Ws.ravel()])
     X = np.array([[0.1, 0.2], [-0.3, 0.4]])
     Y, _ = mlp.forward(p, dims, X)
-    ref = (X @ W0 + b0) @ W1 @ W2 + b2
+    ref = (X @ W0 + b0) @ W1 @ W2 + b2 + X @ Ws
     assert np.allclose(Y, ref, rtol=1e-14, atol=1e-12)
 
 
@@ -104,3 +105,42 @@ def test_oracle_warm_start_point_definition():
             Jx[i] += prob["v"][a] * x[4 + prob["ci"][a]]
     theta = np.abs(Jx - prob["b"]).sum()
     assert r["trace"][0]["theta"] == pytest.approx(theta, rel=1e-12)
+
+
+def test_oracle_warm_start_multipliers_carry_dual_residual():
+    # start point (no iteration): z_l = mu0/(x-l) + max(r, 0), z_u = mu0/(u-x)
+    # + max(-r, 0) with r = grad f(x) + J'y0, so that z_l - z_u - mu0/(x-l)
+    # + mu0/(u-x) is the stationarity residual of the start
+    prob = synth.make_problem(4, 12, 3, 2, cfg=900, p=0)
+    P = oracle.Problem(prob)
+    xd0 = np.array([0.2, -0.3, 0.0, 0.95])
+    y0 = np.array([0.5, -1.0, 2.0])
+    mu0 = 0.01
+    st = oracle.ipm(P, warm=dict(x_d=xd0, y=y0, mu0=mu0), max_iter=0)
+    x = st["x"]
+    nd, ns, m = prob["n_d"], prob["n_s"], prob["m"]
+    H = np.asarray(prob["H"], dtype=np.float64).reshape(nd, nd, order="F")
+    Jd = np.asarray(prob["Jd"], dtype=np.float64).reshape(m, nd, order="F")
+    Js = np.zeros((m, ns))
+    for i in range(m):
+        for a in range(prob["rp"][i], prob["rp"][i + 1]):
+            Js[i, prob["ci"][a]] = prob["v"][a]
+    grad = np.concatenate([H @ x[:nd] + prob["c"], prob["w"] * x[nd:] + prob["g"]])
+    r = grad + np.concatenate([Jd.T @ y0, Js.T @ y0])
+    sl, su = x - prob["xl"], prob["xu"] - x
+    assert np.allclose(st["zl"], mu0 / sl + np.maximum(r, 0.0), rtol=1e-12, atol=1e-14)
+    assert np.allclose(st["zu"], mu0 / su + np.maximum(-r, 0.0), rtol=1e-12, atol=1e-14)
+    assert np.array_equal(st["y"], y0)
+
+
+def test_oracle_warm_start_from_solution_saves_iterations():
+    # from the converged primal-dual point with a small barrier parameter the
+    # near-stationary start needs several iterations fewer than the cold start
+    prob = synth.config_problem(0)
+    P = oracle.Problem(prob)
+    cold = oracle.ipm(P)
+    nd = prob["n_d"]
+    warm = oracle.ipm(P, warm=dict(x_d=cold["x"][:nd], y=cold["y"], mu0=1e-4))
+    assert warm["status"] == "converged"
+    assert warm["iters"] <= cold["iters"] - 3
+    assert np.abs(warm["x"] - cold["x"]).max() <= 1e-5
