@@ -296,3 +296,36 @@ def test_problem_validation_errors():
     S.set_problem(prob)
     with pytest.raises(mds.MdsError, match="call order"):
         S.solve(np.zeros(4), np.zeros(10), np.zeros(3))
+
+
+@pytest.mark.parametrize("N", [1025, 2049, 4097])
+def test_cooperative_panel_workgroup_boundaries(N):
+    # one row past a multiple of 1024: the last workgroup owns a single row
+    rng = np.random.default_rng(N)
+    A = rng.standard_normal((N, N))
+    A = A + A.T
+    say(f"cooperative panel N={N} vs oracle")
+    S = mds.solver_for(_dense_problem(A), panel="coop")
+    S.condense(np.zeros(N), np.zeros(0), 0.0, 0.0)
+    status, inn, _ = S.factor_inertia()
+    ino, _ = _factor_check(S, A)
+    assert (inn["npos"], inn["nzero"], inn["nneg"]) == ino
+
+
+def test_cooperative_panel_nine_workgroups_matches_memory_panel():
+    # N = 9000: 9 workgroups (the 12-workgroup variant of the kernel); the
+    # memory panel, pinned against the oracle at smaller sizes, is the reference
+    N = 9000
+    rng = np.random.default_rng(N)
+    A = rng.standard_normal((N, N))
+    A = A + A.T
+    say("cooperative panel N=9000 vs memory panel")
+    out = {}
+    for panel in ("coop", "mem"):
+        S = mds.solver_for(_dense_problem(A), panel=panel)
+        S.condense(np.zeros(N), np.zeros(0), 0.0, 0.0)
+        _, inn, _ = S.factor_inertia()
+        out[panel] = (S.get_factor()[3], (inn["npos"], inn["nzero"], inn["nneg"]))
+        del S
+    assert np.array_equal(out["coop"][0], out["mem"][0])
+    assert out["coop"][1] == out["mem"][1]
