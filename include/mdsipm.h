@@ -102,7 +102,9 @@ typedef struct {
                              exchange wait longer than ~0.7 s ends the
                              factorization with MDS_EHIP                      */
   int32_t precision;   /* MDS_FP64 (default), MDS_FP32, MDS_BF16, MDS_BF16X3   */
-  int32_t panel_threads; /* register panel workgroup: 512 (default) or 1024     */
+  int32_t panel_threads; /* register panel workgroup: 64, 128, 256, 512 or
+                            1024 (0: 128 up to N = 128, 256 up to N = 256,
+                            else 512); the cooperative panel uses 512         */
   int32_t reserved[4];
 } mds_options;
 

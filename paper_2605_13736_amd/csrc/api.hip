@@ -163,9 +163,14 @@ struct PanelChoice {
   int nb, adv, threads;
 };
 
-// workgroup size of the register panel: the option, else 512
-int panel_threads_of(const mds_options *o) {
-  return (o && o->panel_threads == 1024) ? 1024 : 512;
+// workgroup size of the single-workgroup register panel: the option
+// (64, 128, 256, 512 or 1024), else by order: 128 threads up to N = 128,
+// 256 up to N = 256 (one row per thread: a pivot step waits on fewer waves,
+// ~9% faster than 512 threads at N = 192), else 512
+int panel_threads_of(const mds_options *o, int N) {
+  const int t = o ? o->panel_threads : 0;
+  if (t == 64 || t == 128 || t == 256 || t == 512 || t == 1024) return t;
+  return (N <= 128) ? 128 : (N <= 256) ? 256 : 512;
 }
 
 // Panel choice.  panel option 1: memory panel; 2: register panel (N <= 4096);
@@ -178,7 +183,7 @@ int panel_threads_of(const mds_options *o) {
 PanelChoice panel_of(const mds_dims &d, const mds_options *o) {
   const int N = d.n_d + d.m;
   const int popt = o ? o->panel : 0;
-  const int thr = panel_threads_of(o);
+  const int thr = panel_threads_of(o, N);
   const int rnb = bk_reg_nb(N, thr);
   PanelChoice c{};
   const int prec = o ? o->precision : MDS_FP64;

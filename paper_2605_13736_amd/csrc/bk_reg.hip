@@ -24,11 +24,18 @@ __global__ __launch_bounds__(T) void k_bk_panel_reg(int N, int nb, double alpha,
 
 }  // namespace
 
-// Panel variant for a matrix of order N and a workgroup of T threads (512 or
-// 1024): R rows per thread with R * T >= N, and the register tile NB chosen
-// so that R * NB = 64 doubles of L per thread at T = 512 (VGPR budget 256)
-// and 32 at T = 1024 (budget 128).
+// Panel variant for a matrix of order N and a workgroup of T threads: R rows
+// per thread with R * T >= N, and the register tile NB chosen so that
+// R * NB = 64 doubles of L per thread at T = 512 (VGPR budget 256) and 32 at
+// T = 1024 (budget 128).  Workgroups of 64, 128 or 256 threads (one or two
+// waves per SIMD at most) take up to 2 rows per thread with nb = 32: for
+// small orders fewer waves wait at each barrier of a pivot step.
 int bk_reg_rows(int N, int threads) {
+  if (threads == 64 || threads == 128 || threads == 256) {
+    for (int r = 1; r <= 2; ++r)
+      if (N <= r * threads) return r;
+    return 0;
+  }
   const int T = (threads == 1024) ? 1024 : TMAX;
   const int rmax = (T == 1024) ? 4 : 8;
   for (int r = 1; r <= rmax; r *= 2)
@@ -39,6 +46,7 @@ int bk_reg_rows(int N, int threads) {
 int bk_reg_nb(int N, int threads) {
   const int r = bk_reg_rows(N, threads);
   if (r == 0) return 0;
+  if (threads == 64 || threads == 128 || threads == 256) return 32;
   if (threads == 1024) return 32 / r;
   return (r == 1) ? 32 : 64 / r;
 }
@@ -51,7 +59,17 @@ static void panel_reg(hipStream_t s, int threads, int N, int nb, double alpha, c
   k_bk_panel_reg<T_, R_, NB_, TX><<<1, T_, 0, s>>>(N, nb, alpha, X, Lout, src_out, W, dd, ds, \
                                                    ipiv, blk, st, panel_k0)
   const int r = bk_reg_rows(N, threads);
-  if (threads == 1024) {
+  if (threads == 64 || threads == 128 || threads == 256) {
+    switch (threads * 10 + r) {
+      case 641: MDS_PANEL_REG(64, 1, 32); break;
+      case 642: MDS_PANEL_REG(64, 2, 32); break;
+      case 1281: MDS_PANEL_REG(128, 1, 32); break;
+      case 1282: MDS_PANEL_REG(128, 2, 32); break;
+      case 2561: MDS_PANEL_REG(256, 1, 32); break;
+      case 2562: MDS_PANEL_REG(256, 2, 32); break;
+      default: break;
+    }
+  } else if (threads == 1024) {
     switch (r) {
       case 1: MDS_PANEL_REG(1024, 1, 32); break;
       case 2: MDS_PANEL_REG(1024, 2, 16); break;

@@ -81,6 +81,7 @@ def _factor_check(S, Mo):
 
 
 PANELS = {"auto": dict(panel="auto"), "mem": dict(panel="mem"), "reg": dict(panel="reg"),
+          "reg512": dict(panel="reg", panel_threads=512),
           "reg1024": dict(panel="reg", panel_threads=1024), "coop": dict(panel="coop")}
 
 
