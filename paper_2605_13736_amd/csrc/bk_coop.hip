@@ -156,15 +156,6 @@ __global__ __launch_bounds__(T) void k_bk_panel_coop(int N, int nb, double alpha
         s_cC[pj + 1] = pB0;
       }
     }
-    // ---- prefetch the un-updated column k+1 --------------------------------
-    {
-      const int sc1 = (k + 1 < N) ? s_map[k + 1 - k0] : 0;
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const int rho = gbase + tid + T * r;
-        if (pos[r] >= k && k + 1 < N) pre1[r] = (double)X[rho + sc1 * ld];
-      }
-    }
     // ---- updated column k, this workgroup's candidates ----------------------
     double a[R];
 #pragma unroll
@@ -184,6 +175,17 @@ __global__ __launch_bounds__(T) void k_bk_panel_coop(int N, int nb, double alpha
             for (int r = 0; r < R; ++r) a[r] = fma(-Lr[r][t0 + u], wv[u], a[r]);
           }
         }
+      }
+    }
+    // ---- prefetch the un-updated column k+1 (needed at the end of the step;
+    //      issued after the column update's LDS reads so that no wait for
+    //      older memory operations ahead of them includes it) ----------------
+    {
+      const int sc1 = (k + 1 < N) ? s_map[k + 1 - k0] : 0;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int rho = gbase + tid + T * r;
+        if (pos[r] >= k && k + 1 < N) pre1[r] = (double)X[rho + sc1 * ld];
       }
     }
     double bv = -1.0;
@@ -257,35 +259,39 @@ __global__ __launch_bounds__(T) void k_bk_panel_coop(int N, int nb, double alpha
         if (o2 == g) put_f64(mine + X1_POS + 2 * PREC + 2 * lane, s_prow[2][lane], tag);
       }
       // one round trip reads all: headers in lanes < P, row records spread
-      // over the wave (pair p = lane + 64 u: record p / NR, word p % NR)
-      uint64_t h0 = 0, h1 = 0, h2 = 0, whi[U1], wlo[U1];
+      // over the wave (pair p = lane + 64 u: record p / NR, word p % NR).
+      // Every lane issues every load (a lane with nothing to read loads its
+      // own slot's first word and ignores it), so the loads leave back to
+      // back and one wait covers them.
+      const uint64_t *hp = slot(par, lane < P ? lane : g);
+      const uint64_t *ap[U1];
+      bool need[U1];
+#pragma unroll
+      for (int u = 0; u < U1; ++u) {
+        const int p = lane + 64 * u, rec = p / NR, w = p % NR;
+        const int ip = rec - P, op = (ip == 0) ? o0 : (ip == 1) ? o1 : o2;
+        need[u] = rec < P || (ip < 3 && op >= 0);
+        ap[u] = (rec < P) ? slot(par, rec) + X1_CAND + 2 * w
+                : (ip < 3 && op >= 0) ? slot(par, op) + X1_POS + ip * PREC + 2 * w
+                : slot(par, g);
+      }
+      uint64_t h0, h1, h2, whi[U1], wlo[U1];
       const uint64_t t0 = wall_clock64();
       bool done = false;
       for (;;) {
-        bool ok = true;
-        if (lane < P) {
-          const uint64_t *sp = slot(par, lane);
-          h0 = get_w(sp);
-          h1 = get_w(sp + 1);
-          h2 = get_w(sp + 2);
-        }
+        h0 = get_w(hp);
+        h1 = get_w(hp + 1);
+        h2 = get_w(hp + 2);
 #pragma unroll
         for (int u = 0; u < U1; ++u) {
-          const int p = lane + 64 * u, rec = p / NR, w = p % NR;
-          const uint64_t *ap = nullptr;
-          const int ip = rec - P, op = (ip == 0) ? o0 : (ip == 1) ? o1 : o2;
-          if (rec < P) ap = slot(par, rec) + X1_CAND + 2 * w;
-          else if (ip < 3 && op >= 0) ap = slot(par, op) + X1_POS + ip * PREC + 2 * w;
-          if (ap) {
-            whi[u] = get_w(ap);
-            wlo[u] = get_w(ap + 1);
-          } else {
-            whi[u] = wlo[u] = (uint64_t)tag << 32;
-          }
+          whi[u] = get_w(ap[u]);
+          wlo[u] = get_w(ap[u] + 1);
         }
-        if (lane < P) ok = tag_ok(h0, tag) && tag_ok(h1, tag) && tag_ok(h2, tag);
+        // branch-free checks: every load is consumed on every path, so no
+        // later wait mistakes one of them for an outstanding one
+        bool ok = (lane >= P) | (tag_ok(h0, tag) & tag_ok(h1, tag) & tag_ok(h2, tag));
 #pragma unroll
-        for (int u = 0; u < U1; ++u) ok = ok && tag_ok(whi[u], tag) && tag_ok(wlo[u], tag);
+        for (int u = 0; u < U1; ++u) ok = ok & ((!need[u]) | (tag_ok(whi[u], tag) & tag_ok(wlo[u], tag)));
         if (__ballot(!ok) == 0) {
           done = true;
           break;
@@ -301,7 +307,7 @@ __global__ __launch_bounds__(T) void k_bk_panel_coop(int N, int nb, double alpha
 #pragma unroll
         for (int u = 0; u < U1; ++u) {
           const int p = lane + 64 * u, rec = p / NR, w = p % NR;
-          if (rec < P + 3) s_xb[rec][w] = as_f64(whi[u], wlo[u]);
+          if (rec < P + 3) s_xb[rec][w] = need[u] ? as_f64(whi[u], wlo[u]) : 0.0;
         }
         double gv = -1.0;
         int gi = INT_MAX, gw = 0;
@@ -394,39 +400,33 @@ __global__ __launch_bounds__(T) void k_bk_panel_coop(int N, int nb, double alpha
         // lane 1 + i < 4 reads the column-imax value at position k + i
         const int ol = (lane >= 1 && lane <= 3 && k + lane - 1 < N)
                            ? owner(s_map[k + lane - 1 - k0]) : -1;
-        uint64_t phi[U3], plo[U3], ahi = 0, alo = 0;
+        // unconditional loads (see X1): partial maxima, then lane 0: a_ii,
+        // lanes 1..3: the column-imax values at positions k..k+2
+        const uint64_t *pp[U3];
+#pragma unroll
+        for (int u = 0; u < U3; ++u) {
+          const int p = lane + 64 * u;
+          pp[u] = (p < P * NWV) ? slot(par, p / NWV) + 2 * (p % NWV) : slot(par, g);
+        }
+        const bool needa = (lane == 0) || (lane <= 3 && ol >= 0);
+        const uint64_t *aq = (lane == 0) ? slot(par, oi) + X3_AII
+                             : (lane <= 3 && ol >= 0) ? slot(par, ol) + X3_POS + 2 * (lane - 1)
+                             : slot(par, g);
+        uint64_t phi[U3], plo[U3], ahi, alo;
         const uint64_t t0 = wall_clock64();
         bool done = false;
         for (;;) {
-          bool ok = true;
 #pragma unroll
           for (int u = 0; u < U3; ++u) {
-            const int p = lane + 64 * u;
-            if (p < P * NWV) {
-              const uint64_t *ap = slot(par, p / NWV) + 2 * (p % NWV);
-              phi[u] = get_w(ap);
-              plo[u] = get_w(ap + 1);
-            } else {
-              phi[u] = plo[u] = (uint64_t)tag << 32;
-            }
+            phi[u] = get_w(pp[u]);
+            plo[u] = get_w(pp[u] + 1);
           }
-          // lane 0: a_ii; lanes 1..3: the column-imax values at positions k..k+2
-          if (lane == 0) {
-            const uint64_t *ap = slot(par, oi) + X3_AII;
-            ahi = get_w(ap);
-            alo = get_w(ap + 1);
-          } else if (lane <= 3) {
-            if (ol >= 0) {
-              const uint64_t *ap = slot(par, ol) + X3_POS + 2 * (lane - 1);
-              ahi = get_w(ap);
-              alo = get_w(ap + 1);
-            } else {
-              ahi = alo = (uint64_t)tag << 32;
-            }
-          }
+          ahi = get_w(aq);
+          alo = get_w(aq + 1);
+          bool ok = (!needa) | (tag_ok(ahi, tag) & tag_ok(alo, tag));
 #pragma unroll
-          for (int u = 0; u < U3; ++u) ok = ok && tag_ok(phi[u], tag) && tag_ok(plo[u], tag);
-          if (lane <= 3) ok = ok && tag_ok(ahi, tag) && tag_ok(alo, tag);
+          for (int u = 0; u < U3; ++u)
+            ok = ok & ((lane + 64 * u >= P * NWV) | (tag_ok(phi[u], tag) & tag_ok(plo[u], tag)));
           if (__ballot(!ok) == 0) {
             done = true;
             break;
@@ -448,7 +448,7 @@ __global__ __launch_bounds__(T) void k_bk_panel_coop(int N, int nb, double alpha
             s_rowmax = m;
             s_aii = as_f64(ahi, alo);
           } else if (lane <= 3) {
-            s_xwic[lane - 1] = as_f64(ahi, alo);
+            s_xwic[lane - 1] = needa ? as_f64(ahi, alo) : 0.0;
           }
         }
       }
