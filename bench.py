@@ -115,8 +115,10 @@ def mixed_section(prob, N, reps=3):
 def batch_section(count, mu=0.05, singles=6):
     """The scenario batch: count problems with N = 4 U{64..512}, n_d = N/4,
     m = 3N/4, n_s = 50N, 4 nonzeros per row of J_s, each at a seeded barrier
-    state; solved by the persistent kernel after autotuning.  Also times a
-    loop of single-problem FP64 solves on the first `singles` problems."""
+    state; solved by the persistent kernel after autotuning, in FP64 and in
+    the scope's form (FP32 storage and FP32-MFMA trailing tiles, FP64
+    refinement on the full system).  Also times a loop of single-problem FP64
+    solves on the first `singles` problems."""
     import numpy as np
     import torch
     import paper_2605_13736_amd as mds
@@ -132,16 +134,27 @@ def batch_section(count, mu=0.05, singles=6):
         items.append(it)
         N = sz["N"]
         flops += N ** 3 / 3.0 + 2.0 * N ** 2
-    B = mds.Batch(items)
-    B.run(mu)
-    cfg = B.autotune(mu)
-    torch.cuda.synchronize()
-    reps = 3
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        res = B.run(mu)
-    dt = (time.perf_counter() - t0) / reps
-    lat_ms = np.array([r["t_done"] for r in res], dtype=np.float64) / 1e5  # 100 MHz ticks
+    def timed(precision):
+        B = mds.Batch(items, precision=precision)
+        B.run(mu)
+        cfg = B.autotune(mu)
+        torch.cuda.synchronize()
+        reps = 3
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            res = B.run(mu)
+        dt = (time.perf_counter() - t0) / reps
+        lat = np.array([r["t_done"] for r in res], dtype=np.float64) / 1e5  # 100 MHz ticks
+        sols = [np.concatenate(B.solution(p)) for p in range(count)]
+        B.close()
+        del B
+        torch.cuda.empty_cache()
+        return dt, res, lat, cfg, sols
+
+    dt, res, lat_ms, cfg, x64 = timed("fp64")
+    dt32, res32, lat32, cfg32, x32 = timed("fp32")
+    diff32 = max(float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+                 for a, b in zip(x32, x64))
     # loop of single-problem solves (same systems, FP64 path, inertia correction)
     t_single = 0.0
     for p in range(singles):
@@ -170,7 +183,18 @@ def batch_section(count, mu=0.05, singles=6):
                 single_loop_ms_per_problem=per_single * 1e3,
                 speedup_vs_single_loop=per_single * count / dt,
                 single_loop_sample=f"first {singles} problems of the batch (sizes differ "
-                                   "from the batch mean)")
+                                   "from the batch mean)",
+                fp32_mfma_fp64_refinement=dict(
+                    problems_per_s=count / dt32, ms_per_batch=dt32 * 1e3,
+                    tflops_nominal=flops / dt32 / 1e12,
+                    latency_ms_p50=float(np.percentile(lat32, 50)),
+                    latency_ms_p99=float(np.percentile(lat32, 99)),
+                    autotuned=cfg32,
+                    refine_steps_max=max(r["refine_steps"] for r in res32),
+                    refine_steps_mean=float(np.mean([r["refine_steps"] for r in res32])),
+                    max_rel_diff_vs_fp64_batch=diff32,
+                    speedup_vs_fp64_batch=dt / dt32,
+                    speedup_vs_single_loop=per_single * count / dt32))
 
 
 def warmstart_section(n_train, n_held, hidden=128, steps=3000, lr=3e-3, noise=0.5):

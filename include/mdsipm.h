@@ -353,13 +353,23 @@ typedef struct {
   int64_t t_start, t_done;
   int32_t status;                         /* 0 or MDS_INERTIA_FAIL              */
   int32_t slot;                           /* workgroup that solved it           */
+  int32_t refine_steps, pad;              /* FP64 refinement steps (MDS_FP32)   */
+  double residual;                        /* max|r - Kx| / max|r| before the last
+                                             refinement step (MDS_FP32)          */
 } mds_batch_result;
 
 typedef struct {
   int32_t nb;         /* panel width, 2..16 (0: 16)                              */
   int32_t grid;       /* persistent workgroups = scratch slots (0: min(count, 256)) */
   int32_t use_graph;  /* 0: plain launches; otherwise replay a captured hipGraph */
-  int32_t reserved[5];
+  int32_t precision;  /* MDS_FP64 (0, default) or MDS_FP32: equilibrated S M S
+                         stored in FP32, trailing tiles on FP32 MFMA (panel
+                         decisions, L and D in FP64), then FP64 iterative
+                         refinement on the full Newton system,
+                         x += K^-1 (r - K x) through the FP32 factor          */
+  int32_t refine_steps; /* MDS_FP32: refinement steps at most (0: 10); a step
+                         whose correction is below 1e-15 max|x| ends it       */
+  int32_t reserved[3];
 } mds_batch_opts;
 
 typedef struct mds_batch mds_batch;
@@ -375,9 +385,10 @@ int mds_batch_create(mds_batch **out, const mds_batch_problem *probs_host, int32
                      size_t workspace_bytes);
 /* Solve every problem: for each, condense, factor with the inertia
  * correction loop (delta_c = 1e-8 mu^(1/4) on a singular M), solve and
- * back-substitute, in one persistent kernel (hipGraph replay on the batch's
- * own stream, after the caller's stream has drained).  results_host (may be
- * NULL) receives count entries.  Synchronizes. */
+ * back-substitute (MDS_FP32: then refine in FP64), in one persistent kernel
+ * (hipGraph replay on the batch's own stream, after the caller's stream has
+ * drained).  results_host (may be NULL) receives count entries.
+ * Synchronizes. */
 int mds_batch_run(mds_batch *b, double mu, mds_batch_result *results_host);
 /* Time each candidate (panel width x grid) once and keep the fastest;
  * chosen_host (may be NULL) receives it.  Runs the batch several times. */

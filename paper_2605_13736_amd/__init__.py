@@ -106,12 +106,14 @@ class BatchResult(C.Structure):
     _fields_ = [("npos", C.c_int32), ("nzero", C.c_int32), ("nneg", C.c_int32),
                 ("trials", C.c_int32), ("delta_w", C.c_double), ("delta_c", C.c_double),
                 ("t_start", C.c_int64), ("t_done", C.c_int64), ("status", C.c_int32),
-                ("slot", C.c_int32)]
+                ("slot", C.c_int32), ("refine_steps", C.c_int32), ("pad", C.c_int32),
+                ("residual", C.c_double)]
 
 
 class BatchOpts(C.Structure):
     _fields_ = [("nb", C.c_int32), ("grid", C.c_int32), ("use_graph", C.c_int32),
-                ("reserved", C.c_int32 * 5)]
+                ("precision", C.c_int32), ("refine_steps", C.c_int32),
+                ("reserved", C.c_int32 * 3)]
 
 
 class Timings(C.Structure):
@@ -485,7 +487,8 @@ class Batch:
     items: list of dicts with the problem arrays of a synthetic problem dict
     (H, Jd, rp, ci, v, n_d, n_s, m) plus sigma_d, dsbase, r_d, r_s, r_y."""
 
-    def __init__(self, items, nb=0, grid=0, use_graph=True, device="cuda:0"):
+    def __init__(self, items, nb=0, grid=0, use_graph=True, device="cuda:0", precision="fp64",
+                 refine_steps=0):
         torch = _torch()
         if not torch.cuda.is_available():
             raise MdsError("no ROCm GPU visible: the mdsipm library has no CPU path")
@@ -519,7 +522,10 @@ class Batch:
                                     _ptr(ci), _ptr(v), *[_ptr(t) for t in ins],
                                     *[_ptr(t) for t in o])
         self.descs = descs
-        self.opts = BatchOpts(int(nb), int(grid), 1 if use_graph else 0)
+        if precision not in ("fp64", "fp32"):
+            raise MdsError("batch precision must be 'fp64' or 'fp32'")
+        self.opts = BatchOpts(int(nb), int(grid), 1 if use_graph else 0, PRECISIONS[precision],
+                              int(refine_steps))
         L = lib()
         nbytes = L.mds_batch_workspace_bytes(descs, self.count, C.byref(self.opts))
         if nbytes == 0:
@@ -556,7 +562,8 @@ class Batch:
                            f"({lib().mds_batch_last_error(self.h).decode()})")
         return [dict(inertia=(r.npos, r.nzero, r.nneg), trials=r.trials, delta_w=r.delta_w,
                      delta_c=r.delta_c, t_start=r.t_start, t_done=r.t_done, status=r.status,
-                     slot=r.slot) for r in res]
+                     slot=r.slot, refine_steps=r.refine_steps, residual=r.residual)
+                for r in res]
 
     def autotune(self, mu=0.0):
         o = BatchOpts()
@@ -564,12 +571,16 @@ class Batch:
         if st != 0:
             raise MdsError(f"mds_batch_autotune: {lib().mds_status_string(st).decode()} "
                            f"({lib().mds_batch_last_error(self.h).decode()})")
-        return dict(nb=o.nb, grid=o.grid, use_graph=bool(o.use_graph))
+        return dict(nb=o.nb, grid=o.grid, use_graph=bool(o.use_graph),
+                    precision="fp32" if o.precision == PRECISIONS["fp32"] else "fp64",
+                    refine_steps=o.refine_steps)
 
     def config(self):
         o = BatchOpts()
         lib().mds_batch_get_config(self.h, C.byref(o))
-        return dict(nb=o.nb, grid=o.grid, use_graph=bool(o.use_graph))
+        return dict(nb=o.nb, grid=o.grid, use_graph=bool(o.use_graph),
+                    precision="fp32" if o.precision == PRECISIONS["fp32"] else "fp64",
+                    refine_steps=o.refine_steps)
 
     def solution(self, p):
         return [t.detach().cpu().numpy() for t in self.out[p]]

@@ -9,6 +9,12 @@
 // Each workgroup owns one slot of scratch buffers sized for the largest
 // problem.  The host captures the queue reset and the kernel in a hipGraph and
 // chooses the panel width and the grid by timing candidates (autotune).
+//
+// Mixed precision: M is equilibrated (S M S, S = diag(1/sqrt(max_j |M_ij|)))
+// and stored in FP32, the trailing tiles run on FP32 MFMA with the panel's W
+// and L rounded to FP32, every panel decision and L, D stay FP64; the solution
+// is then refined in FP64 on the full (uncondensed) Newton system,
+// x += K^-1 (r - K x) through the low-precision factor.
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
@@ -29,6 +35,7 @@ constexpr int TW = 32;    // per-wave trailing tile
 constexpr int NWAVE = BT / 64;
 
 typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
 
 struct ProbDev {
   int32_t nd, ns, m, nnz;
@@ -45,6 +52,9 @@ struct SlotDev {
   double *buf[2], *W, *dd, *ds, *inv_d;
   int32_t *src, *ipiv, *blk, *pk0;
   FacState *st;
+  float *x32[2];  // mixed precision: FP32 ping-pong halves of buf[1]
+  double *eq;     // mixed precision: equilibration S (N)
+  double *res;    // residual of the full system (n_d + n_s + m)
 };
 
 struct ResultDev {
@@ -52,6 +62,8 @@ struct ResultDev {
   double delta_w, delta_c;
   int64_t t_start, t_done;
   int32_t status, pad;
+  int32_t refine_steps, pad2;
+  double residual;  // max |r - K x| / max |r| before the last correction
 };
 
 // ---- condensation (bit-identical to k_condense_dense / k_condense_schur) ----
@@ -190,12 +202,155 @@ __device__ __attribute__((noinline)) void trailing_wg(int N, int k0, int kend, c
   }
 }
 
+// Mixed precision: the same tiles with FP32 storage of the trailing matrix
+// and FP32 MFMA products; W and L (FP64, L in Lsrc) are rounded on load.
+// v_mfma_f32_16x16x4f32: result register r of lane l holds row 4 (l/16) + r.
+__device__ __attribute__((noinline)) void trailing_wg_lp(int N, int k0, int kend, const double *W,
+                                                         const double *Lsrc, const float *X,
+                                                         float *Y, const int32_t *src,
+                                                         double (*s_t)[TW + 1]) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int l16 = lane & 15, l4 = lane >> 4;
+  const int jw = kend - k0, n = N - kend;
+  const int nt = (n + TW - 1) / TW;
+  const int ntiles = nt * (nt + 1) / 2;
+  const size_t ld = (size_t)N;
+  double(*t)[TW + 1] = s_t + wv * TW;
+  for (int x = wv; x < ntiles; x += NWAVE) {
+    int ti = (int)((sqrt(8.0 * (double)x + 1.0) - 1.0) * 0.5);
+    while ((ti + 1) * (ti + 2) / 2 <= x) ++ti;
+    while (ti * (ti + 1) / 2 > x) --ti;
+    const int tj = x - ti * (ti + 1) / 2;
+    const int i0 = kend + ti * TW, c0 = kend + tj * TW;
+    const int li = (lane < 32) ? i0 + lane : c0 + (lane - 32);
+    const int sidx = (li < N) ? src[li] : 0;
+    constexpr int KS = (BNB + 1 + 3) / 4;
+    float av[KS][2], bv[KS][2];
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const int tt = 4 * ks + l4;
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        const int c = c0 + a * 16 + l16;
+        av[ks][a] = (tt < jw && c < N) ? (float)W[(size_t)c + (size_t)tt * ld] : 0.f;
+      }
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        const int i = i0 + b * 16 + l16;
+        bv[ks][b] = (tt < jw && i < N) ? (float)Lsrc[(size_t)i + (size_t)(k0 + tt) * ld] : 0.f;
+      }
+    }
+    const bool diag = (ti == tj);
+    float xv[2][2][4];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int cl = a * 16 + 4 * l4 + r, il = b * 16 + l16;
+          const int si = __shfl(sidx, il), sc = __shfl(sidx, 32 + cl);
+          const int c = c0 + cl, i = i0 + il;
+          const bool ok = c < N && i < N && (!diag || i >= c);
+          xv[a][b][r] = ok ? X[(size_t)si + (size_t)sc * ld] : 0.f;
+        }
+    f4 acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) acc[a][b] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      if (4 * ks < jw) {
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int b = 0; b < 2; ++b)
+            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[ks][a], bv[ks][b], acc[a][b], 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int c = c0 + a * 16 + 4 * l4 + r;
+          const int i = i0 + b * 16 + l16;
+          if (c < N && i < N && (!diag || i >= c)) {
+            const float v = xv[a][b][r] - acc[a][b][r];
+            Y[(size_t)i + (size_t)c * ld] = v;
+            t[c - c0][i - i0] = (double)v;
+          }
+        }
+    __builtin_amdgcn_wave_barrier();
+    __asm__ __volatile__("s_waitcnt lgkmcnt(0)" ::: "memory");
+    for (int e = lane; e < TW * TW; e += 64) {
+      const int cl = e & (TW - 1), il = e / TW;
+      const int c = c0 + cl, i = i0 + il;
+      if (c < N && i < N && i > c && (!diag || il >= cl)) Y[(size_t)c + (size_t)i * ld] = (float)t[cl][il];
+    }
+    __builtin_amdgcn_wave_barrier();
+    __asm__ __volatile__("s_waitcnt lgkmcnt(0)" ::: "memory");
+  }
+}
+
+// Mixed precision: S = diag(1/sqrt(max_j |M_ij|)) (1 on a zero row) and
+// X = FP32(S M S), the same scaling as the single-problem path.
+__device__ __attribute__((noinline)) void equilibrate_wg(int N, const double *M, double *eq,
+                                                         float *X) {
+  const int tid = threadIdx.x;
+  const size_t ld = (size_t)N;
+  for (int i = tid; i < N; i += BT) {
+    double mx = 0.0;
+    for (int j = 0; j < N; ++j) mx = fmax(mx, fabs(M[(size_t)i + (size_t)j * ld]));
+    eq[i] = (mx > 0.0) ? 1.0 / sqrt(mx) : 1.0;
+  }
+  __syncthreads();
+  for (int j = 0; j < N; ++j) {
+    const double sj = eq[j];
+    for (int i = tid; i < N; i += BT)
+      X[(size_t)i + (size_t)j * ld] = (float)((eq[i] * M[(size_t)i + (size_t)j * ld]) * sj);
+  }
+  __syncthreads();
+}
+
 // The phases are kept out of line so that each gets its own register
 // allocation (the panel needs most of the register file for L).
 __device__ __attribute__((noinline)) void panel_call(int N, int nb, double alpha, const double *X,
                                                      double *Y, const SlotDev &S) {
   panel::panel_reg_dev<BT, BR, BNB, double>(N, nb, alpha, X, Y, S.src, S.W, S.dd, S.ds, S.ipiv,
                                             S.blk, S.st, S.pk0);
+}
+
+__device__ __attribute__((noinline)) void panel_call_lp(int N, int nb, double alpha,
+                                                        const float *X, const SlotDev &S) {
+  panel::panel_reg_dev<BT, BR, BNB, float>(N, nb, alpha, X, S.buf[0], S.src, S.W, S.dd, S.ds,
+                                           S.ipiv, S.blk, S.st, S.pk0);
+}
+
+// Mixed precision: blocked factorization of X32[0] = FP32(S M S); L (FP64)
+// of every panel lands in buf[0].
+__device__ void factor_wg_lp(int N, int nb, double alpha, const SlotDev &S,
+                             double (*s_t)[TW + 1]) {
+  const int tid = threadIdx.x;
+  if (tid == 0) {
+    FacState z{};
+    *S.st = z;
+    S.pk0[0] = 0;
+  }
+  __syncthreads();
+  for (int b = 0;; ++b) {
+    const int k0 = S.st->k;
+    if (k0 >= N) break;
+    const float *X = S.x32[b & 1];
+    float *Y = S.x32[(b + 1) & 1];
+    panel_call_lp(N, nb, alpha, X, S);
+    __syncthreads();
+    const int kend = S.st->k;
+    if (kend < N) trailing_wg_lp(N, k0, kend, S.W, S.buf[0], X, Y, S.src, s_t);
+    __syncthreads();
+  }
 }
 
 // ---- blocked factorization of the slot's buf[0] --------------------------------
@@ -222,14 +377,16 @@ __device__ void factor_wg(int N, int nb, double alpha, const SlotDev &S,
 }
 
 // ---- LDL' solve in the panels' row frames (z in LDS) ----------------------------
-__device__ __attribute__((noinline)) void solve_wg(int N, const SlotDev &S, double *z, double *s_part) {
+// L of panel b: buf[(b + 1) % 2] (FP64 ping-pong) or buf[0] (mixed precision).
+__device__ __attribute__((noinline)) void solve_wg(int N, const SlotDev &S, double *z, double *s_part,
+                                                   bool mixed) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int np = S.st->npanel;
   const size_t ld = (size_t)N;
   // forward: P_b, then L_b
   for (int b = 0; b < np; ++b) {
     const int k0 = S.pk0[b], k1 = S.pk0[b + 1];
-    const double *Lb = S.buf[(b + 1) & 1];
+    const double *Lb = mixed ? S.buf[0] : S.buf[(b + 1) & 1];
     if (tid == 0) {
       for (int k = k0; k < k1;) {
         int p, q;
@@ -284,7 +441,7 @@ __device__ __attribute__((noinline)) void solve_wg(int N, const SlotDev &S, doub
   // backward: L_b', then P_b'
   for (int b = np - 1; b >= 0; --b) {
     const int k0 = S.pk0[b], k1 = S.pk0[b + 1], w = k1 - k0;
-    const double *Lb = S.buf[(b + 1) & 1];
+    const double *Lb = mixed ? S.buf[0] : S.buf[(b + 1) & 1];
     double acc[BNB + 1];
 #pragma unroll
     for (int c = 0; c <= BNB; ++c) acc[c] = 0.0;
@@ -342,6 +499,114 @@ __device__ __attribute__((noinline)) void solve_wg(int N, const SlotDev &S, doub
   }
 }
 
+// Maximum of v over the workgroup (every thread; s_part holds NWAVE doubles).
+__device__ inline double block_max(double v, double *s_part) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  v = wave::max(v);
+  __syncthreads();
+  if (lane == 0) s_part[wv] = v;
+  __syncthreads();
+  double m = 0.0;
+  for (int q = 0; q < NWAVE; ++q) m = fmax(m, s_part[q]);
+  __syncthreads();
+  return m;
+}
+
+// Condensed solve of the full Newton system for the right-hand side
+// (rd, rs, ry): z = [rd; ry - J_s (inv_d .* rs)], [x_d; x_y] = M^-1 z through
+// the factor (S-scaled on both sides in mixed precision), then
+// x_s = inv_d .* (rs - J_s' x_y).  Writes x, or adds it to x when accumulate;
+// returns max |increment| and max |x| (after) over the workgroup.
+__device__ __attribute__((noinline)) void kkt_solve_wg(const ProbDev &P, const SlotDev &S, bool mixed,
+                                                      const double *rd, const double *rs,
+                                                      const double *ry, bool accumulate,
+                                                      double *s_z, double *s_part, double *cmax,
+                                                      double *xmax) {
+  const int tid = threadIdx.x, nd = P.nd, N = P.nd + P.m;
+  for (int i = tid; i < N; i += BT) {
+    double t;
+    if (i < nd) {
+      t = rd[i];
+    } else {
+      const int r = i - nd;
+      t = ry[r];
+      for (int a = P.rp[r]; a < P.rp[r + 1]; ++a) {
+        const int k = P.ci[a];
+        t = t - P.v[a] * (S.inv_d[k] * rs[k]);
+      }
+    }
+    s_z[i] = mixed ? S.eq[i] * t : t;
+  }
+  __syncthreads();
+  solve_wg(N, S, s_z, s_part, mixed);
+  if (mixed) {
+    for (int i = tid; i < N; i += BT) s_z[i] = S.eq[i] * s_z[i];
+    __syncthreads();
+  }
+  double cm = 0.0, xm = 0.0;
+  for (int i = tid; i < N; i += BT) {
+    double *dst = (i < nd) ? &P.dx_d[i] : &P.dy[i - nd];
+    const double c = s_z[i];
+    const double v = accumulate ? *dst + c : c;
+    *dst = v;
+    cm = fmax(cm, fabs(c));
+    xm = fmax(xm, fabs(v));
+  }
+  for (int k = tid; k < P.ns; k += BT) {
+    double t = rs[k];
+    for (int e = P.cptr[k]; e < P.cptr[k + 1]; ++e) t = t - P.cval[e] * s_z[nd + P.crow[e]];
+    const double c = S.inv_d[k] * t;
+    const double v = accumulate ? P.dx_s[k] + c : c;
+    P.dx_s[k] = v;
+    cm = fmax(cm, fabs(c));
+    xm = fmax(xm, fabs(v));
+  }
+  __syncthreads();
+  *cmax = block_max(cm, s_part);
+  *xmax = block_max(xm, s_part);
+}
+
+// res = r - K x on the full Newton system
+//   K = [[H + diag(Sigma_d) + dw I, 0, J_d'], [0, diag(dsbase) + dw I, J_s'],
+//        [J_d, J_s, -dc I]]
+// in FP64 (res: n_d, n_s, m consecutive); returns max |res| / max |r|.
+__device__ __attribute__((noinline)) double residual_wg(const ProbDev &P, const SlotDev &S, double dw,
+                                                        double dc, double *s_part) {
+  const int tid = threadIdx.x, nd = P.nd, ns = P.ns, m = P.m;
+  double *res = S.res;
+  double rm = 0.0, bm = 0.0;
+  for (int i = tid; i < nd; i += BT) {
+    double t = P.r_d[i];
+    bm = fmax(bm, fabs(t));
+    for (int j = 0; j < nd; ++j) t = t - P.H[(size_t)i + (size_t)j * nd] * P.dx_d[j];
+    t = t - (P.sigma_d[i] + dw) * P.dx_d[i];
+    for (int r = 0; r < m; ++r) t = t - P.Jd[(size_t)r + (size_t)i * m] * P.dy[r];
+    res[i] = t;
+    rm = fmax(rm, fabs(t));
+  }
+  for (int k = tid; k < ns; k += BT) {
+    double t = P.r_s[k];
+    bm = fmax(bm, fabs(t));
+    t = t - (P.dsbase[k] + dw) * P.dx_s[k];
+    for (int e = P.cptr[k]; e < P.cptr[k + 1]; ++e) t = t - P.cval[e] * P.dy[P.crow[e]];
+    res[nd + k] = t;
+    rm = fmax(rm, fabs(t));
+  }
+  for (int r = tid; r < m; r += BT) {
+    double t = P.r_y[r];
+    bm = fmax(bm, fabs(t));
+    for (int i = 0; i < nd; ++i) t = t - P.Jd[(size_t)r + (size_t)i * m] * P.dx_d[i];
+    for (int a = P.rp[r]; a < P.rp[r + 1]; ++a) t = t - P.v[a] * P.dx_s[P.ci[a]];
+    t = t + dc * P.dy[r];
+    res[nd + ns + r] = t;
+    rm = fmax(rm, fabs(t));
+  }
+  __syncthreads();
+  rm = block_max(rm, s_part);
+  bm = block_max(bm, s_part);
+  return (bm > 0.0) ? rm / bm : rm;
+}
+
 __global__ void k_batch_reset(int32_t *queue, unsigned long long *t0) {
   if (threadIdx.x == 0) {
     queue[0] = 0;
@@ -350,12 +615,17 @@ __global__ void k_batch_reset(int32_t *queue, unsigned long long *t0) {
 }
 
 // The persistent kernel.  dc_sing = 1e-8 mu^(1/4), computed on the host.
+// MIXED: FP32 trailing storage and products, then up to refine_max FP64
+// refinement steps (stop when the correction is below 1e-15 of the solution).
+// One instantiation per mode: each holds one register panel and its LDS.
+template <bool MIXED>
 __global__ __launch_bounds__(BT) void k_batch(int count, const int32_t *__restrict__ order,
                                               const ProbDev *__restrict__ probs,
                                               const SlotDev *__restrict__ slots, int nb,
                                               double alpha, const double *dc_sing_p,
                                               int32_t *queue, unsigned long long *t0,
-                                              ResultDev *results) {
+                                              ResultDev *results, int refine_max) {
+  constexpr bool mixed = MIXED;
   const double dc_sing = *dc_sing_p;
   __shared__ double s_t[NWAVE * TW][TW + 1];
   __shared__ double s_z[BMAX_N];
@@ -379,7 +649,12 @@ __global__ __launch_bounds__(BT) void k_batch(int count, const int32_t *__restri
     int trials = 1, status = 0;
     double dw = 0.0, dc = 0.0;
     condense_wg(P, S.inv_d, 0.0, 0.0, S.buf[0]);
-    factor_wg(N, nb, alpha, S, s_t);
+    if constexpr (MIXED) {
+      equilibrate_wg(N, S.buf[0], S.eq, S.x32[0]);
+      factor_wg_lp(N, nb, alpha, S, s_t);
+    } else {
+      factor_wg(N, nb, alpha, S, s_t);
+    }
     bool ok = S.st->npos == P.nd && S.st->nzero == 0 && S.st->nneg == P.m;
     if (!ok) {
       dc = (S.st->nzero > 0) ? dc_sing : 0.0;
@@ -387,7 +662,12 @@ __global__ __launch_bounds__(BT) void k_batch(int count, const int32_t *__restri
       for (;;) {
         trials++;
         condense_wg(P, S.inv_d, dw, dc, S.buf[0]);
-        factor_wg(N, nb, alpha, S, s_t);
+        if constexpr (MIXED) {
+          equilibrate_wg(N, S.buf[0], S.eq, S.x32[0]);
+          factor_wg_lp(N, nb, alpha, S, s_t);
+        } else {
+          factor_wg(N, nb, alpha, S, s_t);
+        }
         ok = S.st->npos == P.nd && S.st->nzero == 0 && S.st->nneg == P.m;
         if (ok) break;
         dw = kw_plus_bar * dw;
@@ -397,34 +677,21 @@ __global__ __launch_bounds__(BT) void k_batch(int count, const int32_t *__restri
         }
       }
     }
-    // condensed right-hand side, solve, back-substitution
-    for (int i = tid; i < N; i += BT) {
-      double t;
-      if (i < P.nd) {
-        t = P.r_d[i];
-      } else {
-        const int r = i - P.nd;
-        t = P.r_y[r];
-        for (int a = P.rp[r]; a < P.rp[r + 1]; ++a) {
-          const int k = P.ci[a];
-          t = t - P.v[a] * (S.inv_d[k] * P.r_s[k]);
-        }
+    // condensed right-hand side, solve, back-substitution; in mixed
+    // precision FP64 refinement on the full system
+    double cmax, xmax, rel = 0.0;
+    kkt_solve_wg(P, S, mixed, P.r_d, P.r_s, P.r_y, false, s_z, s_part, &cmax, &xmax);
+    int steps = 0;
+    if constexpr (MIXED) {
+      const double *res = S.res;
+      while (steps < refine_max) {
+        rel = residual_wg(P, S, dw, dc, s_part);
+        kkt_solve_wg(P, S, true, res, res + P.nd, res + P.nd + P.ns, true, s_z, s_part, &cmax,
+                     &xmax);
+        ++steps;
+        if (cmax <= 1e-15 * xmax) break;
       }
-      s_z[i] = t;
     }
-    __syncthreads();
-    solve_wg(N, S, s_z, s_part);
-    for (int i = tid; i < N; i += BT) {
-      if (i < P.nd) P.dx_d[i] = s_z[i];
-      else P.dy[i - P.nd] = s_z[i];
-    }
-    __syncthreads();
-    for (int k = tid; k < P.ns; k += BT) {
-      double t = P.r_s[k];
-      for (int e = P.cptr[k]; e < P.cptr[k + 1]; ++e) t = t - P.cval[e] * s_z[P.nd + P.crow[e]];
-      P.dx_s[k] = S.inv_d[k] * t;
-    }
-    __syncthreads();
     if (tid == 0) {
       ResultDev r;
       r.npos = S.st->npos;
@@ -437,6 +704,9 @@ __global__ __launch_bounds__(BT) void k_batch(int count, const int32_t *__restri
       r.t_done = (int64_t)wall_clock64();
       r.status = status;
       r.pad = (int32_t)blockIdx.x;
+      r.refine_steps = steps;
+      r.pad2 = 0;
+      r.residual = rel;
       results[pid] = r;
     }
   }
@@ -453,6 +723,8 @@ struct mds_batch_impl {
   int count = 0, Nmax = 0, nsmax = 0, nslots = 0;
   int nb = BNB, grid = 0;
   bool use_graph = true;
+  int mixed = 0;       // 1: FP32 trailing storage and products + FP64 refinement
+  int refine_max = 0;  // refinement steps at most (mixed precision)
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
   int g_nb = -1, g_grid = -1;
@@ -499,7 +771,7 @@ bool batch_layout(const mds_batch_problem *ps, int count, const mds_batch_opts *
   const size_t N = (size_t)L.Nmax;
   L.slot_bytes = 2 * al256(8 * N * N) + al256(8 * N * (kMaxNb + 2)) + 2 * al256(8 * N) +
                  al256(8 * (size_t)std::max(L.nsmax, 1)) + 3 * al256(4 * N) + al256(4 * (N + 4)) +
-                 al256(sizeof(FacState));
+                 al256(sizeof(FacState)) + al256(8 * N) + al256(8 * (N + (size_t)L.nsmax));
   L.probs = al256(sizeof(ProbDev) * count);
   L.slots = al256(sizeof(SlotDev) * L.nslots);
   L.order = al256(4 * (size_t)count);
@@ -517,9 +789,14 @@ int fail(mds_batch_impl *b, int code, const char *what, hipError_t e) {
 
 int launch_batch(mds_batch_impl *b) {
   k_batch_reset<<<1, 64, 0, b->stream>>>(b->d_queue, b->d_t0);
-  k_batch<<<(unsigned)b->grid, BT, 0, b->stream>>>(b->count, b->d_order, b->d_probs, b->d_slots,
-                                                    b->nb, b->alpha, b->d_dc, b->d_queue, b->d_t0,
-                                                    b->d_results);
+  if (b->mixed)
+    k_batch<true><<<(unsigned)b->grid, BT, 0, b->stream>>>(
+        b->count, b->d_order, b->d_probs, b->d_slots, b->nb, b->alpha, b->d_dc, b->d_queue,
+        b->d_t0, b->d_results, b->refine_max);
+  else
+    k_batch<false><<<(unsigned)b->grid, BT, 0, b->stream>>>(
+        b->count, b->d_order, b->d_probs, b->d_slots, b->nb, b->alpha, b->d_dc, b->d_queue,
+        b->d_t0, b->d_results, b->refine_max);
   const hipError_t e = hipGetLastError();
   return e == hipSuccess ? MDS_OK : fail(b, MDS_EHIP, "batch launch", e);
 }
@@ -572,6 +849,8 @@ int mds_batch_create(mds_batch **out, const mds_batch_problem *probs_host, int32
   if (!batch_layout(probs_host, count, opts, L)) return MDS_EDIMS;
   if (bytes < L.total || ((uintptr_t)workspace & 255) != 0) return MDS_EWORKSPACE;
   if (opts && (opts->nb < 0 || opts->nb == 1 || opts->nb > BNB)) return MDS_EINVAL;
+  if (opts && opts->precision != MDS_FP64 && opts->precision != MDS_FP32) return MDS_EINVAL;
+  if (opts && (opts->refine_steps < 0 || opts->refine_steps > 100)) return MDS_EINVAL;
   for (int p = 0; p < count; ++p) {
     const mds_batch_problem &q = probs_host[p];
     if ((q.n_d > 0 && (!q.H || !q.sigma_d || !q.r_d || !q.dx_d)) ||
@@ -594,6 +873,8 @@ int mds_batch_create(mds_batch **out, const mds_batch_problem *probs_host, int32
   b->grid = L.nslots;
   b->nb = (opts && opts->nb > 0) ? opts->nb : BNB;
   b->use_graph = !(opts && opts->use_graph == 0);
+  b->mixed = (opts && opts->precision == MDS_FP32) ? 1 : 0;
+  b->refine_max = (opts && opts->refine_steps > 0) ? opts->refine_steps : 10;
   b->alpha = (1.0 + std::sqrt(17.0)) / 8.0;
   char *base = (char *)workspace;
   size_t o = 0;
@@ -674,6 +955,13 @@ int mds_batch_create(mds_batch **out, const mds_batch_problem *probs_host, int32
     S.pk0 = (int32_t *)c;
     c += al256(4 * (N + 4));
     S.st = (FacState *)c;
+    c += al256(sizeof(FacState));
+    S.eq = (double *)c;
+    c += al256(8 * N);
+    S.res = (double *)c;
+    // mixed precision: two FP32 N x N halves of buf[1]
+    S.x32[0] = (float *)S.buf[1];
+    S.x32[1] = (float *)S.buf[1] + N * N;
   }
   // largest problems first (LPT), ties by index
   std::vector<int32_t> order(count);
@@ -730,6 +1018,9 @@ int mds_batch_run(mds_batch *b, double mu, mds_batch_result *results_host) {
       o.t_done = r.t_done - (int64_t)t0;
       o.status = r.status;
       o.slot = r.pad;
+      o.refine_steps = r.refine_steps;
+      o.pad = 0;
+      o.residual = r.residual;
     }
   }
   return MDS_OK;
@@ -772,6 +1063,8 @@ int mds_batch_autotune(mds_batch *b, double mu, mds_batch_opts *chosen_host) {
     chosen_host->nb = bnb;
     chosen_host->grid = bgrid;
     chosen_host->use_graph = b->use_graph ? 1 : 0;
+    chosen_host->precision = b->mixed ? MDS_FP32 : MDS_FP64;
+    chosen_host->refine_steps = b->refine_max;
   }
   return MDS_OK;
 }
@@ -782,6 +1075,8 @@ int mds_batch_get_config(const mds_batch *b, mds_batch_opts *out_host) {
   out_host->nb = b->nb;
   out_host->grid = b->grid;
   out_host->use_graph = b->use_graph ? 1 : 0;
+  out_host->precision = b->mixed ? MDS_FP32 : MDS_FP64;
+  out_host->refine_steps = b->refine_max;
   return MDS_OK;
 }
 

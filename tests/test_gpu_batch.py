@@ -110,3 +110,25 @@ def test_batch_rejects_oversize():
               r_y=st["r_y"])
     with pytest.raises(mds.MdsError):
         mds.Batch([it])
+
+
+def test_batch_mixed_precision_refined_to_fp64(batch_and_ref):
+    # FP32 storage of S M S and FP32-MFMA trailing tiles, FP64 refinement on
+    # the full system: per problem the inertia, trials and shifts of the
+    # oracle's correction loop, the solution within 1e-8 of the oracle's, a
+    # few refinement steps, and bitwise identical graph replays
+    _, refs = batch_and_ref
+    items = _items()
+    say("mixed-precision batch (FP32 trailing, FP64 refinement)")
+    B = mds.Batch([it for _, _, it in items], precision="fp32")
+    assert B.config()["precision"] == "fp32"
+    res = B.run(MU)
+    _check(B, res, refs)
+    steps = [r["refine_steps"] for r in res]
+    say(f"  refinement steps {steps}, residual before the last step "
+        f"{max(r['residual'] for r in res):.1e}")
+    assert 1 <= min(steps) and max(steps) <= 6
+    first = [np.concatenate(B.solution(p)).copy() for p in range(B.count)]
+    B.run(MU)
+    for p in range(B.count):
+        assert np.array_equal(np.concatenate(B.solution(p)), first[p]), p
