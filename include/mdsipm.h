@@ -100,11 +100,16 @@ typedef struct {
                              workgroups exchange pivot data through the
                              workspace and must run concurrently: an
                              exchange wait longer than ~0.7 s ends the
-                             factorization with MDS_EHIP                      */
+                             factorization with MDS_EHIP,
+                          4: unblocked factorization of the whole M held in
+                             one workgroup's LDS (FP64, N <= 199; the
+                             interchanges are applied to whole rows, so the
+                             factor is in standard form at once)            */
   int32_t precision;   /* MDS_FP64 (default), MDS_FP32, MDS_BF16, MDS_BF16X3   */
   int32_t panel_threads; /* register panel workgroup: 64, 128, 256, 512 or
                             1024 (0: 128 up to N = 128, 256 up to N = 256,
-                            else 512); the cooperative panel uses 512         */
+                            else 512); the cooperative panel uses 512; the
+                            LDS factorization 256 or 512 (0: 512)           */
   int32_t reserved[4];
 } mds_options;
 
@@ -311,7 +316,8 @@ typedef struct {
   int32_t nb;           /* panel width limit                                  */
   int32_t min_width;    /* fewest columns a panel factors (except the last)   */
   int32_t panel;        /* 0: register-resident panel, 1: panel in memory,
-                           2: cooperative register-resident panel            */
+                           2: cooperative register-resident panel,
+                           3: whole M in one workgroup's LDS                 */
   int32_t precision;    /* MDS_FP64, MDS_FP32, MDS_BF16 or MDS_BF16X3          */
   int32_t panel_threads; /* workgroup size of the panel kernel                */
   int32_t pad;

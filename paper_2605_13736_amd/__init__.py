@@ -41,8 +41,9 @@ class Options(C.Structure):
 
 
 # panel kernels: automatic choice, panel in device memory, register-resident
-# (one workgroup), register-resident over several cooperating workgroups
-PANELS = {"auto": 0, "mem": 1, "reg": 2, "coop": 3}
+# (one workgroup), register-resident over several cooperating workgroups,
+# whole matrix in one workgroup's LDS (unblocked, N <= 199)
+PANELS = {"auto": 0, "mem": 1, "reg": 2, "coop": 3, "lds": 4}
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2, "bf16x3": 3}
 
 
@@ -421,7 +422,7 @@ class Solver:
         i = Info()
         self._check(lib().mds_get_info(self.h, C.byref(i)), "mds_get_info")
         prec = {v: k for k, v in PRECISIONS.items()}[i.precision]
-        return dict(nb=i.nb, min_width=i.min_width, panel=("reg", "mem", "coop")[i.panel],
+        return dict(nb=i.nb, min_width=i.min_width, panel=("reg", "mem", "coop", "lds")[i.panel],
                     precision=prec, panel_threads=i.panel_threads,
                     workspace_bytes=i.workspace_bytes)
 

@@ -161,6 +161,7 @@ struct PanelChoice {
   bool reg;   // panel output in the ping-pong layout (register or cooperative panel)
   bool coop;  // cooperative panel over several workgroups
   int nb, adv, threads;
+  bool lds;   // unblocked factorization of the whole M in one workgroup's LDS
 };
 
 // workgroup size of the single-workgroup register panel: the option
@@ -174,7 +175,8 @@ int panel_threads_of(const mds_options *o, int N) {
 }
 
 // Panel choice.  panel option 1: memory panel; 2: register panel (N <= 4096);
-// 3: cooperative register panel over several workgroups (any N);
+// 3: cooperative register panel over several workgroups (any N); 4: the
+// whole M in one workgroup's LDS (FP64, N <= bk_lds_max_n());
 // 0 (automatic): the register panel while its tile keeps nb >= 16
 // (N <= 2048 with 512 threads), else the cooperative panel (nb = 32, about
 // 6 us per pivot at N = 4096 against 7-8 us for the memory panel, and half
@@ -189,23 +191,29 @@ PanelChoice panel_of(const mds_dims &d, const mds_options *o) {
   const int prec = o ? o->precision : MDS_FP64;
   if (prec != MDS_FP64 && prec != MDS_FP32 && prec != MDS_BF16 && prec != MDS_BF16X3)
     return c;  // nb = 0: invalid
-  if (popt < 0 || popt > 3) return c;
-  if (prec != MDS_FP64 && popt == 1) return c;
+  if (popt < 0 || popt > 4) return c;
+  if (prec != MDS_FP64 && (popt == 1 || popt == 4)) return c;
+  if (popt == 4) {
+    if (N > bk_lds_max_n()) return c;
+    const int t = o->panel_threads;
+    const int nb = default_nb(N);
+    return PanelChoice{false, false, nb, nb, (t == 256) ? 256 : 512, true};
+  }
   if (popt == 2 && rnb == 0) return c;
   const bool use_reg = rnb > 0 && (popt == 2 || (popt == 0 && rnb >= 16));
   const bool use_coop = !use_reg && (popt == 3 || popt == 0);
   if (use_reg) {
     int nb = (o && o->nb > 0) ? o->nb : rnb;
     nb = std::min(std::max(nb, 2), rnb);
-    c = {true, false, nb, std::max(nb - 1, 1), thr};
+    c = {true, false, nb, std::max(nb - 1, 1), thr, false};
   } else if (use_coop) {
     int nb = (o && o->nb > 0) ? o->nb : bk_coop_nb();
     nb = std::min(std::max(nb, 2), bk_coop_nb());
-    c = {true, true, nb, std::max(nb - 1, 1), 512};
+    c = {true, true, nb, std::max(nb - 1, 1), 512, false};
   } else {
     int nb = (o && o->nb > 0) ? o->nb : default_nb(N);
     nb = std::min(std::max(nb, 2), kMaxNb);
-    c = {false, false, nb, nb, 0};
+    c = {false, false, nb, nb, 0, false};
   }
   return c;
 }
@@ -240,7 +248,11 @@ int factor_impl(mds_handle *h, mds_inertia *out) {
   const int N = h->N;
   launch_fac_reset(S(h), h->w.fst, h->w.panel_k0);
   const int slots = (N + h->adv - 1) / h->adv;
-  if (h->precision != MDS_FP64) {
+  if (h->panel_lds) {
+    TimedLaunch t(h, MDS_T_PANEL);
+    launch_bk_lds(S(h), h->panel_threads, N, h->alpha_bk, h->w.M, h->w.dd, h->w.ds, h->w.ipiv,
+                  h->w.blk, h->w.perm, h->w.fst);
+  } else if (h->precision != MDS_FP64) {
     // mixed precision: the trailing matrix lives in the FP32 ping-pong
     // buffers; L (FP64) goes to M, which then holds the whole factor
     {
@@ -267,7 +279,7 @@ int factor_impl(mds_handle *h, mds_inertia *out) {
       }
     }
   }
-  for (int b = 0; b < (h->precision == MDS_FP64 ? slots : 0); ++b) {
+  for (int b = 0; b < (h->precision == MDS_FP64 && !h->panel_lds ? slots : 0); ++b) {
     // register panel: slot b reads buffer b%2 and writes its L and the
     // updated trailing matrix into the other buffer
     double *X = h->w.M, *Y = h->w.M;
@@ -305,7 +317,7 @@ int factor_impl(mds_handle *h, mds_inertia *out) {
   out->info = st.info;
   h->have_factor = true;
   h->have_M = false;
-  h->std_ready = false;
+  h->std_ready = h->panel_lds;  // that kernel writes the standard form itself
   return MDS_OK;
 }
 
@@ -750,6 +762,7 @@ int mds_create(mds_handle **out, const mds_dims *dims, const mds_options *opts, 
   h->nb = nb;
   h->panel_reg = pc.reg;
   h->panel_coop = pc.coop;
+  h->panel_lds = pc.lds;
   h->panel_threads = pc.threads;
   h->precision = prec;
   h->adv = pc.adv;
@@ -815,7 +828,7 @@ int mds_create(mds_handle **out, const mds_dims *dims, const mds_options *opts, 
   w.kn_jd = D(S_KNJD);
   w.kn_y = D(S_KNY);
   w.kn_js = D(S_KNJS);
-  if (std_prepare() != hipSuccess ||
+  if (std_prepare() != hipSuccess || bk_lds_prepare() != hipSuccess ||
       hipMemsetAsync(w.trsv, 0, 4 * (4 + 2 * (size_t)std_solve_blocks(h->N)), h->stream) !=
           hipSuccess ||
       hipMemsetAsync(w.xch, 0, 8 * 2 * (size_t)kCoopMaxP * kCoopSlotWords, h->stream) !=
@@ -1191,9 +1204,9 @@ int mds_get_info(const mds_handle *h, mds_info *out) {
   if (!h || !out) return MDS_ENULL;
   out->nb = h->nb;
   out->min_width = h->adv;
-  out->panel = h->panel_coop ? 2 : h->panel_reg ? 0 : 1;
+  out->panel = h->panel_lds ? 3 : h->panel_coop ? 2 : h->panel_reg ? 0 : 1;
   out->precision = h->precision;
-  out->panel_threads = h->panel_reg ? h->panel_threads : 1024;
+  out->panel_threads = (h->panel_reg || h->panel_lds) ? h->panel_threads : 1024;
   out->workspace_bytes = (int64_t)h->ws_bytes;
   return MDS_OK;
 }

@@ -78,6 +78,7 @@ struct mds_handle {
   int N = 0, n = 0, nb = 16, max_panels = 0;
   bool panel_reg = false;  // register-resident panel kernel (ping-pong layout)
   bool panel_coop = false; // ... spread over several workgroups
+  bool panel_lds = false;  // whole M in one workgroup's LDS, unblocked
   int panel_threads = 512; // its workgroup size
   int precision = MDS_FP64;
   int adv = 16;            // least number of columns a panel factors
@@ -160,6 +161,16 @@ void launch_bk_panel_coop(hipStream_t s, int N, int nb, double alpha, const floa
                           double *Lout, int32_t *src_out, double *W, double *dd, double *ds,
                           int32_t *ipiv, int32_t *blk, FacState *st, int32_t *panel_k0,
                           uint64_t *xch);
+
+// bk_lds.hip: unblocked factorization of an M held whole in one
+// workgroup's LDS (N <= bk_lds_max_n(), threads 256 or 512); writes the
+// standard-form L into M's strictly lower part, dd, ds, ipiv, blk, perm and
+// the final FacState
+size_t bk_lds_bytes(int N);
+int bk_lds_max_n();
+hipError_t bk_lds_prepare();
+void launch_bk_lds(hipStream_t s, int threads, int N, double alpha, double *M, double *dd,
+                   double *ds, int32_t *ipiv, int32_t *blk, int32_t *perm, FacState *st);
 
 // bk_lp.hip: FP32-storage trailing update (mode MDS_FP32 or MDS_BF16 products)
 void launch_trailing_lp(hipStream_t s, int mode, int N, int nb, int adv, int slot,

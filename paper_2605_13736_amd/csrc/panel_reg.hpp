@@ -158,16 +158,15 @@ __device__ inline void panel_reg_dev(int N, int nb, double alpha,
     for (int t0 = 0; t0 < NB; t0 += 8) {
       if (t0 < j) {
         keep_branch();
+        // columns t >= j: L = 0 and the W entry forced to 0, so their
+        // products add an exact zero (no per-column branch)
         double wv[8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) wv[u] = s_wk[t0 + u];
+        for (int u = 0; u < 8; ++u) wv[u] = (t0 + u < j) ? s_wk[t0 + u] : 0.0;
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
-          if (t0 + u < j) {
-            keep_branch();
 #pragma unroll
-            for (int r = 0; r < R; ++r) a[r] = fma(-Lr[r][t0 + u], wv[u], a[r]);
-          }
+          for (int r = 0; r < R; ++r) a[r] = fma(-Lr[r][t0 + u], wv[u], a[r]);
         }
       }
     }
@@ -237,16 +236,15 @@ __device__ inline void panel_reg_dev(int N, int nb, double alpha,
       for (int t0 = 0; t0 < NB; t0 += 8) {
         if (t0 < j) {
           keep_branch();
+          // columns t >= j: L = 0 and the W entry forced to 0, so their
+          // products add an exact zero (no per-column branch)
           double wv[8];
 #pragma unroll
-          for (int u = 0; u < 8; ++u) wv[u] = s_wi[t0 + u];
+          for (int u = 0; u < 8; ++u) wv[u] = (t0 + u < j) ? s_wi[t0 + u] : 0.0;
 #pragma unroll
           for (int u = 0; u < 8; ++u) {
-            if (t0 + u < j) {
-              keep_branch();
 #pragma unroll
-              for (int r = 0; r < R; ++r) wic[r] = fma(-Lr[r][t0 + u], wv[u], wic[r]);
-            }
+            for (int r = 0; r < R; ++r) wic[r] = fma(-Lr[r][t0 + u], wv[u], wic[r]);
           }
         }
       }

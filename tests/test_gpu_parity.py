@@ -82,13 +82,17 @@ def _factor_check(S, Mo):
 
 PANELS = {"auto": dict(panel="auto"), "mem": dict(panel="mem"), "reg": dict(panel="reg"),
           "reg512": dict(panel="reg", panel_threads=512),
-          "reg1024": dict(panel="reg", panel_threads=1024), "coop": dict(panel="coop")}
+          "reg1024": dict(panel="reg", panel_threads=1024), "coop": dict(panel="coop"),
+          "lds": dict(panel="lds")}
+LDS_MAX_N = 199
 
 
 @pytest.mark.parametrize("panel", list(PANELS))
 @pytest.mark.parametrize("idx", range(len(CASES)))
 def test_factor_pivots_and_inertia_exact(idx, panel):
     prob, st, nb = _case(idx, seed=1)
+    if panel == "lds" and prob["n_d"] + prob["m"] > LDS_MAX_N:
+        pytest.skip("the LDS factorization holds N <= 199")
     say(f"factor case={CASES[idx]} panel={panel}")
     if panel in ("reg1024", "coop") and nb > 32:
         nb = 32
@@ -137,6 +141,8 @@ def test_factor_branch_matrices(case):
 @pytest.mark.parametrize("N,nb", [(64, 8), (129, 16), (250, 16), (400, 64), (700, 0),
                                   (1300, 0), (2100, 0), (3000, 0)])
 def test_factor_random_symmetric(N, nb, panel):
+    if panel == "lds" and N > LDS_MAX_N:
+        pytest.skip("the LDS factorization holds N <= 199")
     rng = np.random.default_rng(N)
     A = rng.standard_normal((N, N))
     A = A + A.T
