@@ -301,6 +301,10 @@ __global__ __launch_bounds__(NT) void k_bk_panel(int N, int nb, double alpha,
 // l holds A[l%16][l/16], operand B lane l holds B[l/16][l%16], and result
 // register r of lane l holds D[l/16 + 4r][l%16].
 constexpr int TT = 64;
+constexpr int TS = 36;        // panel columns staged in LDS per chunk (multiple of 4)
+constexpr int TS1 = TS + 1;   // odd row stride of the staged panels
+constexpr int TSTAGE = TT * TS / 256;  // staged entries per thread and panel
+static_assert(TT * TS % 256 == 0 && 2 * TT * TS1 >= TT * (TT + 1), "staging");
 
 // X: matrix the panel read (entry (x, c) at X[src(x) + src(c) N]); Y: output
 // buffer (may equal X when src is null); Lsrc: buffer holding the panel's L.
@@ -311,7 +315,11 @@ __global__ __launch_bounds__(256) void k_bk_trailing(int N, int nb, const double
                                                      const FacState *__restrict__ st,
                                                      const int32_t *__restrict__ panel_k0,
                                                      int slot) {
-  __shared__ double s_t[TT][TT + 1];
+  // the staged panels (W rows c0.., L rows i0..) and, after the products,
+  // the tile's transpose share one buffer
+  __shared__ double s_buf[2 * TT * TS1];
+  double(*s_t)[TT + 1] = reinterpret_cast<double(*)[TT + 1]>(s_buf);
+  double *s_w = s_buf, *s_l = s_buf + TT * TS1;
   // only slots whose panel ran in this factorization have valid bounds
   if (slot >= st->npanel) return;
   const int k0 = panel_k0[slot], kend = panel_k0[slot + 1];
@@ -331,33 +339,77 @@ __global__ __launch_bounds__(256) void k_bk_trailing(int N, int nb, const double
   const int wc = c0 + (wv & 1) * 32, wi = i0 + (wv >> 1) * 32;
   const int l16 = lane & 15, l4 = lane >> 4;
 
+  const bool diag = (ti == tj);
+  // the entries this lane updates, loaded before the product loop so that
+  // their memory latency overlaps it
+  int si[2], sc[2][4];
+#pragma unroll
+  for (int b = 0; b < 2; ++b) {
+    const int i = wi + b * 16 + l16;
+    si[b] = (i < N) ? (src ? src[i] : i) : 0;
+  }
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int c = wc + a * 16 + l4 + 4 * r;
+      sc[a][r] = (c < N) ? (src ? src[c] : c) : 0;
+    }
+  double xv[2][2][4];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int c = wc + a * 16 + l4 + 4 * r;
+        const int i = wi + b * 16 + l16;
+        xv[a][b][r] = (c < N && i < N && (!diag || i >= c))
+                          ? X[(size_t)si[b] + (size_t)sc[a][r] * ld] : 0.0;
+      }
+
   d4 acc[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
 
-  for (int t0 = 0; t0 < jw; t0 += 4) {
-    const int t = t0 + l4;
-    double av[2], bv[2];
+  // panel columns in chunks of TS: every load of a chunk is issued before
+  // the LDS stores, so one memory latency covers the chunk
+  for (int tb = 0; tb < jw; tb += TS) {
+    const int tw = min(TS, jw - tb);
+    if (tb > 0) __syncthreads();  // the previous chunk has been read
+    double vw[TSTAGE], vl[TSTAGE];
 #pragma unroll
-    for (int a = 0; a < 2; ++a) {
-      const int c = wc + a * 16 + l16;
-      av[a] = (t < jw && c < N) ? W[(size_t)c + (size_t)t * ld] : 0.0;
+    for (int u = 0; u < TSTAGE; ++u) {
+      const int e = tid + 256 * u, r = e & (TT - 1), t = e >> 6;
+      const int c = c0 + r, i = i0 + r;
+      vw[u] = (t < tw && c < N) ? W[(size_t)c + (size_t)(tb + t) * ld] : 0.0;
+      vl[u] = (t < tw && i < N) ? Lsrc[(size_t)i + (size_t)(k0 + tb + t) * ld] : 0.0;
     }
 #pragma unroll
-    for (int b = 0; b < 2; ++b) {
-      const int i = wi + b * 16 + l16;
-      bv[b] = (t < jw && i < N) ? Lsrc[(size_t)i + (size_t)(k0 + t) * ld] : 0.0;
+    for (int u = 0; u < TSTAGE; ++u) {
+      const int e = tid + 256 * u, r = e & (TT - 1), t = e >> 6;
+      s_w[r * TS1 + t] = vw[u];
+      s_l[r * TS1 + t] = vl[u];
     }
+    __syncthreads();
+    for (int t0 = 0; t0 < tw; t0 += 4) {
+      const int t = t0 + l4;  // < TS; entries past tw are zero
+      double av[2], bv[2];
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+      for (int a = 0; a < 2; ++a) av[a] = s_w[(wc - c0 + a * 16 + l16) * TS1 + t];
 #pragma unroll
-      for (int b = 0; b < 2; ++b)
-        acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+      for (int b = 0; b < 2; ++b) bv[b] = s_l[(wi - i0 + b * 16 + l16) * TS1 + t];
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+          acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+    }
   }
+  __syncthreads();  // the staging buffer becomes the transpose tile
 
-  const bool diag = (ti == tj);
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -367,8 +419,7 @@ __global__ __launch_bounds__(256) void k_bk_trailing(int N, int nb, const double
         const int c = wc + a * 16 + l4 + 4 * r;
         const int i = wi + b * 16 + l16;
         if (c < N && i < N && (!diag || i >= c)) {
-          const int si = src ? src[i] : i, sc = src ? src[c] : c;
-          const double v = X[(size_t)si + (size_t)sc * ld] - acc[a][b][r];
+          const double v = xv[a][b][r] - acc[a][b][r];
           Y[(size_t)i + (size_t)c * ld] = v;
           s_t[c - c0][i - i0] = v;
         }

@@ -61,6 +61,36 @@ __global__ __launch_bounds__(256) void k_trailing_lp(int N, int nb, const double
   const int wc = c0 + (wv & 1) * 32, wi = i0 + (wv >> 1) * 32;
   const int l16 = lane & 15, l4 = lane >> 4;
 
+  const bool diag = (ti == tj);
+  // the entries this lane updates, loaded before the product loop so that
+  // their memory latency overlaps it (FP32-accumulating MFMA result: lane l,
+  // register r holds row 4 (l / 16) + r, column l % 16)
+  int si[2], sc[2][4];
+#pragma unroll
+  for (int b = 0; b < 2; ++b) {
+    const int i = wi + b * 16 + l16;
+    si[b] = (i < N) ? (src ? src[i] : i) : 0;
+  }
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int c = wc + a * 16 + 4 * l4 + r;
+      sc[a][r] = (c < N) ? (src ? src[c] : c) : 0;
+    }
+  float xv[2][2][4];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int c = wc + a * 16 + 4 * l4 + r;
+        const int i = wi + b * 16 + l16;
+        xv[a][b][r] = (c < N && i < N && (!diag || i >= c))
+                          ? X[(size_t)si[b] + (size_t)sc[a][r] * ld] : 0.f;
+      }
+
   f4 acc[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
@@ -144,20 +174,16 @@ __global__ __launch_bounds__(256) void k_trailing_lp(int N, int nb, const double
     }
   }
 
-  const bool diag = (ti == tj);
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        // 16 x 16 FP32-accumulating MFMA result: lane l, register r holds
-        // row 4 (l / 16) + r, column l % 16
         const int c = wc + a * 16 + 4 * l4 + r;
         const int i = wi + b * 16 + l16;
         if (c < N && i < N && (!diag || i >= c)) {
-          const int si = src ? src[i] : i, sc = src ? src[c] : c;
-          const float v = X[(size_t)si + (size_t)sc * ld] - acc[a][b][r];
+          const float v = xv[a][b][r] - acc[a][b][r];
           Y[(size_t)i + (size_t)c * ld] = v;
           s_t[c - c0][i - i0] = v;
         }

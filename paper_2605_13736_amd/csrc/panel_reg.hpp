@@ -17,9 +17,10 @@
 //
 // Every VALU instruction of a pivot step costs a wave several cycles, so the
 // step is written for a small instruction count: register indices are
-// static, columns not yet factored are skipped by wave-uniform branches, and
-// the W row (L D) of a pivot candidate is formed lane-parallel by the wave
-// that owns the row.
+// static, groups of 8 columns not yet factored are skipped by wave-uniform
+// branches (inside a group, a column not yet factored has L = 0 and its W
+// entry is forced to 0, an exact no-op), and the W row (L D) of a pivot
+// candidate is formed lane-parallel by the wave that owns the row.
 //
 // The panel stops once j >= nb - 1 (width nb - 1, or nb after a final 2x2),
 // so that a 2x2 pivot always fits the register tile.
