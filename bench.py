@@ -34,7 +34,8 @@ HBM_PEAK_GBS = 8000.0
 # the counters of a 256 MiB copy (the profile file gives the commands and the
 # factors); valid for the kernel source as profiled.
 MEASURED_TRAFFIC = {
-    "k_bk_panel_coop": (2225807.0, "profiles/bk_panel_coop_ipm_newton_step_n4096.md"),
+    "k_bk_panel_coop": (2224787.0, "profiles/bk_panel_coop_ipm_newton_step_n4096.md"),
+    "k_bk_trailing": (84613300.0, "profiles/bk_trailing_ipm_newton_step_n4096.md"),
 }
 FP64_MFMA_PEAK_TFS = 78.6
 
@@ -280,6 +281,26 @@ def cpu_baseline(prob, N):
                 seconds=dt)
 
 
+def ipm_solves_section(nrep=5):
+    """Whole FP64 IPMs on the N = 192 workload: solves per second."""
+    import torch
+
+    import paper_2605_13736_amd as mds
+    import synth
+    prob0 = synth.config_problem(0)
+    S0 = mds.solver_for(prob0)
+    r = S0.ipm_solve()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(nrep):
+        r = S0.ipm_solve()
+    torch.cuda.synchronize()
+    d0 = (time.perf_counter() - t1) / nrep
+    return {"workload": "whole FP64 IPM to E_0 <= 1e-8, n_d=64 n_s=2000 m=128 (N=192)",
+            "solves_per_s": 1.0 / d0, "iters": r["iters"], "status": r["status"],
+            "panel": S0.info()["panel"]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -288,6 +309,8 @@ def main():
     ap.add_argument("--nb", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ipm-solves", action="store_true")
+    ap.add_argument("--ipm-only", action="store_true",
+                    help="run only the whole-IPM section (N = 192) and print it (profiling)")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--batch-count", type=int, default=512)
@@ -305,6 +328,9 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"calib_copy_bytes_read": x.numel() * 8,
                           "calib_copy_bytes_written": x.numel() * 8, "launches": 3}))
+        return
+    if args.ipm_only:
+        print(json.dumps({"ipm_solves": ipm_solves_section()}))
         return
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
@@ -418,19 +444,7 @@ def main():
     }
 
     if not args.no_ipm_solves:
-        prob0 = synth.config_problem(0)
-        S0 = mds.solver_for(prob0)
-        r = S0.ipm_solve()
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        nrep = 5
-        for _ in range(nrep):
-            r = S0.ipm_solve()
-        torch.cuda.synchronize()
-        d0 = (time.perf_counter() - t1) / nrep
-        out["ipm_solves"] = {"workload": "whole FP64 IPM to E_0 <= 1e-8, n_d=64 n_s=2000 m=128 "
-                                         "(N=192)", "solves_per_s": 1.0 / d0,
-                             "iters": r["iters"], "status": r["status"]}
+        out["ipm_solves"] = ipm_solves_section()
     if not args.no_mixed:
         log("mixed precision section")
         out["mixed"] = mixed_section(prob, N)
