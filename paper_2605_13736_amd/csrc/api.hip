@@ -585,16 +585,16 @@ int refine_impl(mds_handle *h, const double *r_d, const double *r_s, const doubl
   const size_t nt = (size_t)nd + ns + m;
   double *res = h->w.res, *cor = h->w.cor, *prev = h->w.prev, *kx = h->w.kx;
   TRY(solve_impl(h, r_d, r_s, r_y, dx_d, dx_s, dy));
+  // ||K||_inf parts and ||r||_inf: two reductions, one read-back
   kkt_norm_parts(S(h), nd, ns, m, h->P.H, h->sigma_d, h->dw, h->P.J_d, h->P.Js_rowptr,
                  h->P.Js_val, h->w.csc_ptr, h->w.csc_val, h->dsbase, h->dc, h->w.kn_h,
                  h->w.kn_jd, h->w.kn_y, h->w.kn_js, h->w.red, h->w.scal);
+  ipm_red_amax3(S(h), nd, r_d, ns, r_s, m, r_y, h->w.red, h->w.scal + 8);
   HIPCHK(hipGetLastError());
-  double s8[8];
-  TRY(read_scal(h, s8, 8));
-  const double nK = std::max(s8[0], std::max(s8[1], s8[2]));
-  double a3[3];
-  TRY(amax3(h, nd, r_d, ns, r_s, m, r_y, a3));
-  const double nr = std::max(a3[0], std::max(a3[1], a3[2]));
+  double s16[16];
+  TRY(read_scal(h, s16, 16));
+  const double nK = std::max(s16[0], std::max(s16[1], s16[2]));
+  const double nr = std::max(s16[8], std::max(s16[9], s16[10]));
   double eta_prev = INFINITY, eta = 0.0, rres = 0.0;
   int steps = 0;
   for (;;) {
@@ -602,11 +602,13 @@ int refine_impl(mds_handle *h, const double *r_d, const double *r_s, const doubl
     vec_sub(S(h), nd, r_d, kx, res);
     vec_sub(S(h), ns, r_s, kx + nd, res + nd);
     vec_sub(S(h), m, r_y, kx + nd + ns, res + nd + ns);
-    double rr[3], xx[3];
-    TRY(amax3(h, nd, res, ns, res + nd, m, res + nd + ns, rr));
-    TRY(amax3(h, nd, dx_d, ns, dx_s, m, dy, xx));
-    const double nres = std::max(rr[0], std::max(rr[1], rr[2]));
-    const double nx = std::max(xx[0], std::max(xx[1], xx[2]));
+    // ||res||_inf and ||x||_inf: one read-back
+    ipm_red_amax3(S(h), nd, res, ns, res + nd, m, res + nd + ns, h->w.red, h->w.scal);
+    ipm_red_amax3(S(h), nd, dx_d, ns, dx_s, m, dy, h->w.red, h->w.scal + 8);
+    HIPCHK(hipGetLastError());
+    TRY(read_scal(h, s16, 16));
+    const double nres = std::max(s16[0], std::max(s16[1], s16[2]));
+    const double nx = std::max(s16[8], std::max(s16[9], s16[10]));
     const double den = nK * nx + nr;
     eta = (den > 0.0) ? nres / den : 0.0;
     rres = (nr > 0.0) ? nres / nr : 0.0;
@@ -630,8 +632,7 @@ int refine_impl(mds_handle *h, const double *r_d, const double *r_s, const doubl
     steps++;
   }
   HIPCHK(hipGetLastError());
-  HIPCHK(hipStreamSynchronize(S(h)));
-  TRY(solve_status(h));
+  TRY(solve_status(h));  // synchronizes
   (void)nt;
   if (info) {
     info->eta = eta;
@@ -692,7 +693,29 @@ int opt_error_impl(mds_handle *h, const double *x, const double *y, const double
   return MDS_OK;
 }
 
-int merit_impl(mds_handle *h, const double *x, double mu, double *f, double *phi, double *theta) {
+// E_0 and E_mu at one mu from one reduction pass and one read-back.
+int opt_error_pair(mds_handle *h, const double *x, const double *y, const double *zl,
+                   const double *zu, double mu, double *E0, double *Emu) {
+  const int n = h->n, m = MM(h);
+  const double s_max = 100.0;
+  eval_grad_constr(h, x, y, nullptr);
+  ipm_red_opt_pair(S(h), n, m, x, y, zl, zu, h->P.xl, h->P.xu, h->w.tn, h->w.tn2, h->w.tm, mu,
+                   h->w.red, h->w.scal);
+  HIPCHK(hipGetLastError());
+  double s[8];
+  TRY(read_scal(h, s, 8));
+  const double dual = s[0], prim = s[1], cmu = s[2], c0 = s[3], y1 = s[4], z1 = s[5];
+  const double nz = s[6];
+  const double sd = (m + nz > 0) ? std::max(s_max, (y1 + z1) / ((double)m + nz)) / s_max : 1.0;
+  const double sc = (nz > 0) ? std::max(s_max, z1 / nz) / s_max : 1.0;
+  *Emu = std::max(std::max(dual / sd, prim), cmu / sc);
+  *E0 = std::max(std::max(dual / sd, prim), c0 / sc);
+  return MDS_OK;
+}
+
+// Launches the merit reductions at x into out[0..7] (slot 4: f, 5: sum of
+// log-slacks, 6: theta); h->w.tn and h->w.tm are overwritten.
+void merit_launch(mds_handle *h, const double *x, double *out) {
   const int nd = ND(h), ns = NS(h), m = MM(h);
   const mds_problem &P = h->P;
   double *hx = h->w.tn, *cx = h->w.tm;
@@ -706,7 +729,11 @@ int merit_impl(mds_handle *h, const double *x, double mu, double *f, double *phi
     }
     ipm_constr_finish(S(h), m, P.b, cx, nullptr);
   }
-  ipm_red_merit(S(h), nd, ns, m, x, hx, P.c, P.w, P.g, P.xl, P.xu, cx, h->w.red, h->w.scal);
+  ipm_red_merit(S(h), nd, ns, m, x, hx, P.c, P.w, P.g, P.xl, P.xu, cx, h->w.red, out);
+}
+
+int merit_impl(mds_handle *h, const double *x, double mu, double *f, double *phi, double *theta) {
+  merit_launch(h, x, h->w.scal);
   HIPCHK(hipGetLastError());
   double s[8];
   TRY(read_scal(h, s, 8));
@@ -1018,7 +1045,9 @@ int mds_ipm_init_warm(mds_handle *h, mds_iterate *it, const mds_ipm_opts *opts,
   return MDS_OK;
 }
 
-int mds_ipm_step(mds_handle *h, mds_iterate *it, mds_step_info *info) {
+// sync_end: wait for the iterate update before returning (mds_ipm_step);
+// mds_ipm_solve leaves it stream-ordered between its own steps.
+static int ipm_step_impl(mds_handle *h, mds_iterate *it, mds_step_info *info, bool sync_end) {
   TRY(check_ready(h));
   if (!h->ipm_ready) return set_err(h, MDS_ESTATE, "mds_ipm_init must precede mds_ipm_step");
   if (!it) return set_err(h, MDS_ENULL, "iterate missing");
@@ -1036,15 +1065,15 @@ int mds_ipm_step(mds_handle *h, mds_iterate *it, mds_step_info *info) {
 
   I.mu = mu;
   if (it->iter >= h->ipm.max_iter) return I.status = MDS_IPM_MAXITER;
-  double E0 = 0.0;
-  TRY(opt_error_impl(h, x, y, zl, zu, 0.0, &E0, nullptr));
+  double E0 = 0.0, Emu0 = 0.0;  // E_0 and E_mu at the incoming mu, one pass
+  TRY(opt_error_pair(h, x, y, zl, zu, mu, &E0, &Emu0));
   I.E0 = E0;
   if (!std::isfinite(E0)) return I.status = MDS_IPM_NONFINITE;
   if (E0 <= h->ipm.tol) return I.status = MDS_IPM_CONVERGED;
   // barrier update while the barrier subproblem is solved to kappa_eps * mu
-  for (;;) {
-    double Emu = 0.0;
-    TRY(opt_error_impl(h, x, y, zl, zu, mu, &Emu, nullptr));
+  for (bool first = true;; first = false) {
+    double Emu = Emu0;
+    if (!first) TRY(opt_error_impl(h, x, y, zl, zu, mu, &Emu, nullptr));
     if (!(Emu <= kappa_eps * mu)) break;
     const double mnew = std::max(h->ipm.tol / 10.0, std::min(kappa_mu * mu, std::pow(mu, theta_mu)));
     if (!(mnew < mu)) break;
@@ -1082,20 +1111,21 @@ int mds_ipm_step(mds_handle *h, mds_iterate *it, mds_step_info *info) {
   if (rst < 0) return rst;
   I.eta = ri.eta;
   I.solves = 1 + ri.steps;
+  // fraction to the boundary, grad(phi_mu)' dx and the merit values at x:
+  // three reductions into separate records, read back together
   ipm_dz(S(h), n, x, zl, zu, P.xl, P.xu, dx, mu, dzl, dzu);
   ipm_red_ftb(S(h), n, x, P.xl, P.xu, dx, zl, zu, dzl, dzu, tau, h->w.red, h->w.scal);
-  HIPCHK(hipGetLastError());
-  double s8[8];
-  TRY(read_scal(h, s8, 8));
-  const double a_pr = -s8[0], a_du = -s8[1];
-  // grad(phi_mu)' dx at x (needs grad f: recompute, refinement used the scratch)
+  // grad f at x (the refinement used the scratch), read by the gphi reduction
+  // before the merit products overwrite it
   eval_grad_constr(h, x, nullptr, nullptr);
-  ipm_red_gphi(S(h), n, h->w.tn, x, P.xl, P.xu, dx, mu, h->w.red, h->w.scal);
+  ipm_red_gphi(S(h), n, h->w.tn, x, P.xl, P.xu, dx, mu, h->w.red, h->w.scal + 8);
+  merit_launch(h, x, h->w.scal + 16);
   HIPCHK(hipGetLastError());
-  TRY(read_scal(h, s8, 8));
-  const double gphi = s8[4];
-  double th = 0.0, ph = 0.0;
-  TRY(merit_impl(h, x, mu, nullptr, &ph, &th));
+  double s24[24];
+  TRY(read_scal(h, s24, 24));
+  const double a_pr = -s24[0], a_du = -s24[1];
+  const double gphi = s24[8 + 4];
+  const double ph = s24[16 + 4] - mu * s24[16 + 5], th = s24[16 + 6];
   double amin;
   if (gphi < 0.0) {
     amin = std::min(gamma_theta, gamma_phi * th / (-gphi));
@@ -1143,12 +1173,16 @@ int mds_ipm_step(mds_handle *h, mds_iterate *it, mds_step_info *info) {
   if (augment) h->filter.emplace_back((1.0 - gamma_theta) * th, ph - gamma_phi * th);
   ipm_accept(S(h), n, m, xt, x, y, dy, zl, zu, dzl, dzu, P.xl, P.xu, alpha, a_du, mu);
   HIPCHK(hipGetLastError());
-  HIPCHK(hipStreamSynchronize(S(h)));
+  if (sync_end) HIPCHK(hipStreamSynchronize(S(h)));
   it->mu = mu;
   it->tau = tau;
   it->iter++;
   I.status = MDS_OK;
   return MDS_OK;
+}
+
+int mds_ipm_step(mds_handle *h, mds_iterate *it, mds_step_info *info) {
+  return ipm_step_impl(h, it, info, true);
 }
 
 int mds_ipm_solve(mds_handle *h, mds_iterate *it, const mds_ipm_opts *opts,
@@ -1158,11 +1192,13 @@ int mds_ipm_solve(mds_handle *h, mds_iterate *it, const mds_ipm_opts *opts,
   int rows = 0;
   for (;;) {
     mds_step_info info{};
-    st = mds_ipm_step(h, it, &info);
+    // the next step's first read-back orders it after this step's update
+    st = ipm_step_impl(h, it, &info, false);
     if (trace_host && rows < trace_cap) trace_host[rows] = info;
     rows++;
     if (st != MDS_OK) break;
   }
+  if (hipStreamSynchronize(S(h)) != hipSuccess) return set_err(h, MDS_EHIP, "stream sync failed");
   if (iters_host) *iters_host = it->iter;
   return st;
 }

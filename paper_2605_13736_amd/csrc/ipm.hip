@@ -168,6 +168,9 @@ __global__ void k_dz(int n, const double *__restrict__ x, const double *__restri
 
 // slot 0: max dual infeasibility, 1: max |J x - b|, 2/3: max complementarity
 // (lower/upper), 4: sum |y|, 5: sum of bound multipliers, 6: finite bounds
+// PAIR: slot 2 = both complementarity maxima at mu, slot 3 = both at mu = 0
+// (E_mu and E_0 from one pass; the maxima are the same numbers either way)
+template <bool PAIR>
 __global__ __launch_bounds__(RB) void k_red_opt(int n, int m, const double *__restrict__ x,
                                                 const double *__restrict__ y,
                                                 const double *__restrict__ zl,
@@ -186,13 +189,25 @@ __global__ __launch_bounds__(RB) void k_red_opt(int n, int m, const double *__re
       double r = gf[e] + jty[e];
       if (isfinite(xl[e])) {
         r = r - zl[e];
-        v[2] = fmax(v[2], fabs((x[e] - xl[e]) * zl[e] - mu));
+        const double sz = (x[e] - xl[e]) * zl[e];
+        if (PAIR) {
+          v[2] = fmax(v[2], fabs(sz - mu));
+          v[3] = fmax(v[3], fabs(sz - 0.0));
+        } else {
+          v[2] = fmax(v[2], fabs(sz - mu));
+        }
         v[5] += fabs(zl[e]);
         v[6] += 1.0;
       }
       if (isfinite(xu[e])) {
         r = r + zu[e];
-        v[3] = fmax(v[3], fabs((xu[e] - x[e]) * zu[e] - mu));
+        const double sz = (xu[e] - x[e]) * zu[e];
+        if (PAIR) {
+          v[2] = fmax(v[2], fabs(sz - mu));
+          v[3] = fmax(v[3], fabs(sz - 0.0));
+        } else {
+          v[3] = fmax(v[3], fabs(sz - mu));
+        }
         v[5] += fabs(zu[e]);
         v[6] += 1.0;
       }
@@ -559,7 +574,16 @@ void ipm_red_opt(hipStream_t s, int n, int m, const double *x, const double *y, 
                  const double *zu, const double *xl, const double *xu, const double *gf,
                  const double *jty, const double *cx, double mu, double *red, double *out) {
   const unsigned g = red_grid(n > m ? n : m);
-  k_red_opt<<<g, RB, 0, s>>>(n, m, x, y, zl, zu, xl, xu, gf, jty, cx, mu, red);
+  k_red_opt<false><<<g, RB, 0, s>>>(n, m, x, y, zl, zu, xl, xu, gf, jty, cx, mu, red);
+  k_red_final<<<1, 256, 0, s>>>((int)g, red, out);
+}
+
+void ipm_red_opt_pair(hipStream_t s, int n, int m, const double *x, const double *y,
+                      const double *zl, const double *zu, const double *xl, const double *xu,
+                      const double *gf, const double *jty, const double *cx, double mu,
+                      double *red, double *out) {
+  const unsigned g = red_grid(n > m ? n : m);
+  k_red_opt<true><<<g, RB, 0, s>>>(n, m, x, y, zl, zu, xl, xu, gf, jty, cx, mu, red);
   k_red_final<<<1, 256, 0, s>>>((int)g, red, out);
 }
 

@@ -29,6 +29,11 @@ void ipm_dz(hipStream_t s, int n, const double *x, const double *zl, const doubl
 void ipm_red_opt(hipStream_t s, int n, int m, const double *x, const double *y, const double *zl,
                  const double *zu, const double *xl, const double *xu, const double *gf,
                  const double *jty, const double *cx, double mu, double *red, double *out);
+// as ipm_red_opt, but slot 2 holds max(lower, upper) complementarity at mu
+// and slot 3 the same at mu = 0
+void ipm_red_opt_pair(hipStream_t s, int n, int m, const double *x, const double *y, const double *zl,
+                 const double *zu, const double *xl, const double *xu, const double *gf,
+                 const double *jty, const double *cx, double mu, double *red, double *out);
 void ipm_red_merit(hipStream_t s, int nd, int ns, int m, const double *x, const double *hx,
                    const double *c, const double *w, const double *g, const double *xl,
                    const double *xu, const double *cx, double *red, double *out);
