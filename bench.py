@@ -311,6 +311,8 @@ def main():
     ap.add_argument("--no-ipm-solves", action="store_true")
     ap.add_argument("--ipm-only", action="store_true",
                     help="run only the whole-IPM section (N = 192) and print it (profiling)")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="run only the scenario-batch section and print it (profiling)")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--batch-count", type=int, default=512)
@@ -331,6 +333,9 @@ def main():
         return
     if args.ipm_only:
         print(json.dumps({"ipm_solves": ipm_solves_section()}))
+        return
+    if args.batch_only:
+        print(json.dumps({"batch": batch_section(args.batch_count)}))
         return
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
