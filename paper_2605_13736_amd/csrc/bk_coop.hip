@@ -127,7 +127,10 @@ __global__ __launch_bounds__(T) void k_bk_panel_coop(int N, int nb, double alpha
   auto owner = [&](int phys) { return (phys - k0) / RW; };
 
   double Lr[R][NB];
-  double pre1[R], pre2[R];
+  // prefetched un-updated column values, kept in the storage type and
+  // widened where used: a widening next to a conditional load would make the
+  // compiler wait for the load there
+  TX pre1[R], pre2[R];
   int pos[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
@@ -136,7 +139,7 @@ __global__ __launch_bounds__(T) void k_bk_panel_coop(int N, int nb, double alpha
     const int rho = gbase + tid + T * r;
     pos[r] = (rho < N) ? rho : -1;
     s_acur[r * T + tid] = (rho < N) ? (double)X[rho + k0 * ld] : 0.0;
-    pre1[r] = pre2[r] = 0.0;
+    pre1[r] = pre2[r] = (TX)0;
   }
   for (int i = tid; i < N - k0; i += T) s_map[i] = k0 + i;
   __syncthreads();
@@ -184,7 +187,7 @@ __global__ __launch_bounds__(T) void k_bk_panel_coop(int N, int nb, double alpha
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         const int rho = gbase + tid + T * r;
-        if (pos[r] >= k && k + 1 < N) pre1[r] = (double)X[rho + sc1 * ld];
+        if (pos[r] >= k && k + 1 < N) pre1[r] = X[rho + sc1 * ld];
       }
     }
     double bv = -1.0;
@@ -357,7 +360,7 @@ __global__ __launch_bounds__(T) void k_bk_panel_coop(int N, int nb, double alpha
         wic[r] = 0.0;
         if (pos[r] >= k) {
           wic[r] = (double)X[rho + src_i * ld];
-          if (k + 2 < N) pre2[r] = (double)X[rho + src_k2 * ld];
+          if (k + 2 < N) pre2[r] = X[rho + src_k2 * ld];
         }
       }
 #pragma unroll
@@ -505,9 +508,9 @@ __global__ __launch_bounds__(T) void k_bk_panel_coop(int N, int nb, double alpha
         else if (pr == q) np = p;
       }
       pos[r] = np;
-      double an = pre1[r];
+      double an = (double)pre1[r];
       if (kind == 3 && q == k + 1) an = s_acur[r * T + tid];
-      if (kind == 4 && q != k + 2) an = pre2[r];
+      if (kind == 4 && q != k + 2) an = (double)pre2[r];
       s_acur[r * T + tid] = an;
     }
 #pragma unroll

@@ -20,6 +20,10 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 typedef short s4 __attribute__((ext_vector_type(4)));
 
 constexpr int TT = 64;
+constexpr int TSL = 48;        // panel columns staged in LDS per chunk (multiple of 16)
+constexpr int TSL1 = TSL + 1;  // odd row stride of the staged panels
+constexpr int TSTL = TT * TSL / 256;  // staged entries per thread and panel
+static_assert(TT * TSL % 256 == 0 && 2 * TT * TSL1 >= TT * (TT + 1), "staging");
 
 // round-to-nearest-even FP32 -> BF16 (finite inputs)
 __device__ inline short to_bf16(float x) {
@@ -43,7 +47,11 @@ __global__ __launch_bounds__(256) void k_trailing_lp(int N, int nb, const double
                                                      const FacState *__restrict__ st,
                                                      const int32_t *__restrict__ panel_k0,
                                                      int slot) {
-  __shared__ float s_t[TT][TT + 1];
+  // the staged panels (FP32: W rows c0.., L rows i0..) and, after the
+  // products, the tile's transpose share one buffer
+  __shared__ float s_buf[2 * TT * TSL1];
+  float(*s_t)[TT + 1] = reinterpret_cast<float(*)[TT + 1]>(s_buf);
+  float *s_w = s_buf, *s_l = s_buf + TT * TSL1;
   if (slot >= st->npanel) return;
   const int k0 = panel_k0[slot], kend = panel_k0[slot + 1];
   if (kend >= N || kend <= k0 || kend - k0 > nb + 1) return;
@@ -97,82 +105,96 @@ __global__ __launch_bounds__(256) void k_trailing_lp(int N, int nb, const double
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = f4{0.f, 0.f, 0.f, 0.f};
 
-  if (MODE == 1) {
-    for (int t0 = 0; t0 < jw; t0 += 4) {
-      const int t = t0 + l4;
-      float av[2], bv[2];
+  // panel columns in chunks of TSL, rounded to FP32 once while staging; every
+  // load of a chunk is issued before the LDS stores (one memory latency per
+  // chunk instead of one per product step)
+  for (int tb = 0; tb < jw; tb += TSL) {
+    const int tw = min(TSL, jw - tb);
+    if (tb > 0) __syncthreads();  // the previous chunk has been read
+    double vw[TSTL], vl[TSTL];
 #pragma unroll
-      for (int a = 0; a < 2; ++a) {
-        const int c = wc + a * 16 + l16;
-        av[a] = (t < jw && c < N) ? (float)W[(size_t)c + (size_t)t * ld] : 0.f;
-      }
-#pragma unroll
-      for (int b = 0; b < 2; ++b) {
-        const int i = wi + b * 16 + l16;
-        bv[b] = (t < jw && i < N) ? (float)Lsrc[(size_t)i + (size_t)(k0 + t) * ld] : 0.f;
-      }
-#pragma unroll
-      for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int b = 0; b < 2; ++b)
-          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a], bv[b], acc[a][b], 0, 0, 0);
+    for (int u = 0; u < TSTL; ++u) {
+      const int e = tid + 256 * u, r = e & (TT - 1), t = e >> 6;
+      const int c = c0 + r, i = i0 + r;
+      vw[u] = (t < tw && c < N) ? W[(size_t)c + (size_t)(tb + t) * ld] : 0.0;
+      vl[u] = (t < tw && i < N) ? Lsrc[(size_t)i + (size_t)(k0 + tb + t) * ld] : 0.0;
     }
-  } else if (MODE == 3) {
-    for (int t0 = 0; t0 < jw; t0 += 16) {
-      s4 ah[2], al[2], bh[2], bl[2];
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int t = t0 + 4 * l4 + e;
-#pragma unroll
-        for (int a = 0; a < 2; ++a) {
-          const int c = wc + a * 16 + l16;
-          const float v = (t < jw && c < N) ? (float)W[(size_t)c + (size_t)t * ld] : 0.f;
-          const short h = to_bf16(v);
-          ah[a][e] = h;
-          al[a][e] = to_bf16(v - bf16_to_f32(h));
-        }
-#pragma unroll
-        for (int b = 0; b < 2; ++b) {
-          const int i = wi + b * 16 + l16;
-          const float v = (t < jw && i < N) ? (float)Lsrc[(size_t)i + (size_t)(k0 + t) * ld] : 0.f;
-          const short h = to_bf16(v);
-          bh[b][e] = h;
-          bl[b][e] = to_bf16(v - bf16_to_f32(h));
-        }
-      }
-#pragma unroll
-      for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int b = 0; b < 2; ++b) {
-          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al[a], bh[b], acc[a][b], 0, 0, 0);
-          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[a], bl[b], acc[a][b], 0, 0, 0);
-          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[a], bh[b], acc[a][b], 0, 0, 0);
-        }
+    for (int u = 0; u < TSTL; ++u) {
+      const int e = tid + 256 * u, r = e & (TT - 1), t = e >> 6;
+      s_w[r * TSL1 + t] = (float)vw[u];
+      s_l[r * TSL1 + t] = (float)vl[u];
     }
-  } else {
-    for (int t0 = 0; t0 < jw; t0 += 16) {
-      s4 av[2], bv[2];
+    __syncthreads();
+    const float *wr[2], *lr[2];  // this lane's rows of the staged panels
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int t = t0 + 4 * l4 + e;
+    for (int a = 0; a < 2; ++a) wr[a] = s_w + (wc - c0 + a * 16 + l16) * TSL1;
 #pragma unroll
-        for (int a = 0; a < 2; ++a) {
-          const int c = wc + a * 16 + l16;
-          av[a][e] = to_bf16((t < jw && c < N) ? (float)W[(size_t)c + (size_t)t * ld] : 0.f);
-        }
+    for (int b = 0; b < 2; ++b) lr[b] = s_l + (wi - i0 + b * 16 + l16) * TSL1;
+    if (MODE == 1) {
+      for (int t0 = 0; t0 < tw; t0 += 4) {
+        const int t = t0 + l4;  // < TSL; entries past tw are zero
+        float av[2], bv[2];
 #pragma unroll
-        for (int b = 0; b < 2; ++b) {
-          const int i = wi + b * 16 + l16;
-          bv[b][e] = to_bf16((t < jw && i < N) ? (float)Lsrc[(size_t)i + (size_t)(k0 + t) * ld] : 0.f);
-        }
+        for (int a = 0; a < 2; ++a) av[a] = wr[a][t];
+#pragma unroll
+        for (int b = 0; b < 2; ++b) bv[b] = lr[b][t];
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int b = 0; b < 2; ++b)
+            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a], bv[b], acc[a][b], 0, 0, 0);
       }
+    } else if (MODE == 3) {
+      for (int t0 = 0; t0 < tw; t0 += 16) {
+        s4 ah[2], al[2], bh[2], bl[2];
 #pragma unroll
-      for (int a = 0; a < 2; ++a)
+        for (int e = 0; e < 4; ++e) {
+          const int t = t0 + 4 * l4 + e;  // < TSL
 #pragma unroll
-        for (int b = 0; b < 2; ++b)
-          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av[a], bv[b], acc[a][b], 0, 0, 0);
+          for (int a = 0; a < 2; ++a) {
+            const float v = wr[a][t];
+            const short h = to_bf16(v);
+            ah[a][e] = h;
+            al[a][e] = to_bf16(v - bf16_to_f32(h));
+          }
+#pragma unroll
+          for (int b = 0; b < 2; ++b) {
+            const float v = lr[b][t];
+            const short h = to_bf16(v);
+            bh[b][e] = h;
+            bl[b][e] = to_bf16(v - bf16_to_f32(h));
+          }
+        }
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int b = 0; b < 2; ++b) {
+            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al[a], bh[b], acc[a][b], 0, 0, 0);
+            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[a], bl[b], acc[a][b], 0, 0, 0);
+            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[a], bh[b], acc[a][b], 0, 0, 0);
+          }
+      }
+    } else {
+      for (int t0 = 0; t0 < tw; t0 += 16) {
+        s4 av[2], bv[2];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int t = t0 + 4 * l4 + e;  // < TSL
+#pragma unroll
+          for (int a = 0; a < 2; ++a) av[a][e] = to_bf16(wr[a][t]);
+#pragma unroll
+          for (int b = 0; b < 2; ++b) bv[b][e] = to_bf16(lr[b][t]);
+        }
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int b = 0; b < 2; ++b)
+            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av[a], bv[b], acc[a][b], 0, 0, 0);
+      }
     }
   }
+  __syncthreads();  // the staging buffer becomes the transpose tile
 
 #pragma unroll
   for (int a = 0; a < 2; ++a)

@@ -110,7 +110,10 @@ __device__ inline void panel_reg_dev(int N, int nb, double alpha,
   const int ld = N;  // N <= 4096: every offset fits in 32 bits
 
   double Lr[R][NB];
-  double pre1[R], pre2[R];
+  // prefetched un-updated column values, kept in the storage type and
+  // widened where used: a widening next to a conditional load would make the
+  // compiler wait for the load there
+  TX pre1[R], pre2[R];
   int pos[R];  // logical position of the owned physical row (-1: past N)
 #pragma unroll
   for (int r = 0; r < R; ++r) {
@@ -120,7 +123,7 @@ __device__ inline void panel_reg_dev(int N, int nb, double alpha,
     pos[r] = (rho < N) ? rho : -1;
     s_map[r * T + tid] = rho;
     s_acur[r * T + tid] = (rho < N) ? (double)X[rho + k0 * ld] : 0.0;
-    pre1[r] = pre2[r] = 0.0;
+    pre1[r] = pre2[r] = (TX)0;
   }
   __syncthreads();
 
@@ -147,7 +150,7 @@ __device__ inline void panel_reg_dev(int N, int nb, double alpha,
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         const int rho = k0 + tid + T * r;
-        if (pos[r] >= k && k + 1 < N) pre1[r] = (double)X[rho + sc1 * ld];
+        if (pos[r] >= k && k + 1 < N) pre1[r] = X[rho + sc1 * ld];
       }
     }
     // ---- updated column k and its largest off-diagonal magnitude -----------
@@ -218,7 +221,7 @@ __device__ inline void panel_reg_dev(int N, int nb, double alpha,
         wic[r] = 0.0;
         if (pos[r] >= k) {
           wic[r] = (double)X[rho + src_i * ld];
-          if (k + 2 < N) pre2[r] = (double)X[rho + src_k2 * ld];
+          if (k + 2 < N) pre2[r] = X[rho + src_k2 * ld];
         }
         if (pos[r] == imax) {
           own = true;
@@ -319,9 +322,9 @@ __device__ inline void panel_reg_dev(int N, int nb, double alpha,
         else if (pr == q) np = p;
       }
       pos[r] = np;
-      double an = pre1[r];
+      double an = (double)pre1[r];
       if (kind == 3 && q == k + 1) an = s_acur[r * T + tid];
-      if (kind == 4 && q != k + 2) an = pre2[r];
+      if (kind == 4 && q != k + 2) an = (double)pre2[r];
       s_acur[r * T + tid] = an;
     }
 #pragma unroll
