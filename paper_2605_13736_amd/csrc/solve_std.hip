@@ -42,7 +42,6 @@ __global__ __launch_bounds__(SW) void k_std_sweep(int N, const int32_t *__restri
                                                   int32_t *__restrict__ colpanel) {
   extern __shared__ int s_h[];
   __shared__ int s_p[kMaxNb + 2], s_q[kMaxNb + 2];
-  __shared__ int s_ns;
   const int tid = threadIdx.x;
   const int np = st->npanel;
   for (int x = tid; x < N; x += SW) s_h[x] = x;
@@ -52,27 +51,19 @@ __global__ __launch_bounds__(SW) void k_std_sweep(int N, const int32_t *__restri
     int32_t *hb = hmap + (size_t)b * N;
     for (int x = k1 + tid; x < N; x += SW) hb[x] = s_h[x];
     for (int c = k0 + tid; c < k1; c += SW) colpanel[c] = b;
-    if (tid == 0) {
-      int ns = 0;
-      for (int k = k0; k < k1;) {
-        if (blk[k] == 1) {
-          s_p[ns] = k;
-          s_q[ns] = ipiv[k] - 1;
-          k += 1;
-        } else {
-          s_p[ns] = k + 1;
-          s_q[ns] = -ipiv[k] - 1;
-          k += 2;
-        }
-        ++ns;
-      }
-      s_ns = ns;
+    // the panel's transpositions in pivot order, read in parallel: entry k
+    // gives (k, q) for a 1x1 pivot, (k + 1, q) for the first row of a 2x2
+    // one and nothing for its second row
+    if (tid < k1 - k0) {
+      const int k = k0 + tid, bk = blk[k], iv = ipiv[k];
+      s_p[tid] = (bk == 1) ? k : (bk == 2) ? k + 1 : -1;
+      s_q[tid] = (bk == 1) ? iv - 1 : -iv - 1;
     }
     __syncthreads();
     if (tid == 0) {
-      for (int e = s_ns - 1; e >= 0; --e) {
+      for (int e = k1 - k0 - 1; e >= 0; --e) {
         const int p = s_p[e], q = s_q[e];
-        if (p != q) {
+        if (p >= 0 && p != q) {
           const int t = s_h[p];
           s_h[p] = s_h[q];
           s_h[q] = t;
