@@ -417,28 +417,47 @@ __device__ void factor_wg(int N, int nb, double alpha, const SlotDev &S,
 
 // ---- LDL' solve in the panels' row frames (z in LDS) ----------------------------
 // L of panel b: buf[(b + 1) % 2] (FP64 ping-pong) or buf[0] (mixed precision).
+// Per panel, the pivot records are read in parallel into s_pq (one entry
+// per thread: (k, q) for a 1x1 pivot, (k + 1, q) for the first row of a 2x2
+// one, p = -1 for its second row) and the panel's diagonal block of L into
+// s_db (w x w, one load per entry, all in flight at once); the sequential
+// steps then touch only LDS and broadcast a lane's value with readlane.
+constexpr int BDB = BNB + 1;  // widest panel (a final 2x2 pivot)
+
+__device__ inline void panel_records(const SlotDev &S, int k0, int w, int *s_pq) {
+  const int tid = threadIdx.x;
+  if (tid < w) {
+    const int k = k0 + tid, bk = S.blk[k], iv = S.ipiv[k];
+    s_pq[2 * tid] = (bk == 1) ? k : (bk == 2) ? k + 1 : -1;
+    s_pq[2 * tid + 1] = (bk == 1) ? iv - 1 : -iv - 1;
+  }
+}
+
+__device__ inline void diag_block(const double *Lb, size_t ld, int k0, int w, double *s_db) {
+  const int tid = threadIdx.x;
+  if (tid < BDB * BDB) {
+    const int r = tid % BDB, c = tid / BDB;
+    if (r < w && c < w) s_db[r * BDB + c] = Lb[(size_t)(k0 + r) + (size_t)(k0 + c) * ld];
+  }
+}
+
 __device__ __attribute__((noinline)) void solve_wg(int N, const SlotDev &S, double *z, double *s_part,
-                                                   bool mixed) {
+                                                   bool mixed, double *s_db, int *s_pq) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int np = S.st->npanel;
   const size_t ld = (size_t)N;
   // forward: P_b, then L_b
   for (int b = 0; b < np; ++b) {
     const int k0 = S.pk0[b], k1 = S.pk0[b + 1];
+    const int w = k1 - k0;
     const double *Lb = mixed ? S.buf[0] : S.buf[(b + 1) & 1];
+    panel_records(S, k0, w, s_pq);
+    diag_block(Lb, ld, k0, w, s_db);
+    __syncthreads();
     if (tid == 0) {
-      for (int k = k0; k < k1;) {
-        int p, q;
-        if (S.blk[k] == 1) {
-          p = k;
-          q = S.ipiv[k] - 1;
-          k += 1;
-        } else {
-          p = k + 1;
-          q = -S.ipiv[k] - 1;
-          k += 2;
-        }
-        if (p != q) {
+      for (int e = 0; e < w; ++e) {
+        const int p = s_pq[2 * e], q = s_pq[2 * e + 1];
+        if (p >= 0 && p != q) {
           const double t = z[p];
           z[p] = z[q];
           z[q] = t;
@@ -446,12 +465,11 @@ __device__ __attribute__((noinline)) void solve_wg(int N, const SlotDev &S, doub
       }
     }
     __syncthreads();
-    const int w = k1 - k0;
     if (wv == 0) {
       double v = (lane < w) ? z[k0 + lane] : 0.0;
       for (int c = 0; c + 1 < w; ++c) {
-        const double zc = __shfl(v, c);
-        if (lane > c && lane < w) v = fma(-Lb[(size_t)(k0 + lane) + (size_t)(k0 + c) * ld], zc, v);
+        const double zc = wave::lane_read(v, c);
+        if (lane > c && lane < w) v = fma(-s_db[lane * BDB + c], zc, v);
       }
       if (lane < w) z[k0 + lane] = v;
     }
@@ -481,6 +499,8 @@ __device__ __attribute__((noinline)) void solve_wg(int N, const SlotDev &S, doub
   for (int b = np - 1; b >= 0; --b) {
     const int k0 = S.pk0[b], k1 = S.pk0[b + 1], w = k1 - k0;
     const double *Lb = mixed ? S.buf[0] : S.buf[(b + 1) & 1];
+    panel_records(S, k0, w, s_pq);
+    diag_block(Lb, ld, k0, w, s_db);
     double acc[BNB + 1];
 #pragma unroll
     for (int c = 0; c <= BNB; ++c) acc[c] = 0.0;
@@ -492,8 +512,7 @@ __device__ __attribute__((noinline)) void solve_wg(int N, const SlotDev &S, doub
     }
 #pragma unroll
     for (int c = 0; c <= BNB; ++c) {
-      double v = acc[c];
-      for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+      const double v = wave::sum(acc[c]);
       if (lane == 0) s_part[wv * (BNB + 1) + c] = v;
     }
     __syncthreads();
@@ -505,29 +524,16 @@ __device__ __attribute__((noinline)) void solve_wg(int N, const SlotDev &S, doub
         v = z[k0 + lane] - s;
       }
       for (int c = w - 1; c > 0; --c) {
-        const double xc = __shfl(v, c);
-        if (lane < c) v = fma(-Lb[(size_t)(k0 + c) + (size_t)(k0 + lane) * ld], xc, v);
+        const double xc = wave::lane_read(v, c);
+        if (lane < c) v = fma(-s_db[c * BDB + lane], xc, v);
       }
       if (lane < w) z[k0 + lane] = v;
     }
     __syncthreads();
     if (tid == 0) {
-      int ks[BNB + 2], ne = 0;
-      for (int k = k0; k < k1;) {
-        ks[ne++] = k;
-        k += (S.blk[k] == 1) ? 1 : 2;
-      }
-      for (int e = ne - 1; e >= 0; --e) {
-        const int k = ks[e];
-        int p, q;
-        if (S.blk[k] == 1) {
-          p = k;
-          q = S.ipiv[k] - 1;
-        } else {
-          p = k + 1;
-          q = -S.ipiv[k] - 1;
-        }
-        if (p != q) {
+      for (int e = w - 1; e >= 0; --e) {
+        const int p = s_pq[2 * e], q = s_pq[2 * e + 1];
+        if (p >= 0 && p != q) {
           const double t = z[p];
           z[p] = z[q];
           z[q] = t;
@@ -559,8 +565,8 @@ __device__ inline double block_max(double v, double *s_part) {
 __device__ __attribute__((noinline)) void kkt_solve_wg(const ProbDev &P, const SlotDev &S, bool mixed,
                                                       const double *rd, const double *rs,
                                                       const double *ry, bool accumulate,
-                                                      double *s_z, double *s_part, double *cmax,
-                                                      double *xmax) {
+                                                      double *s_z, double *s_part, double *s_db,
+                                                      int *s_pq, double *cmax, double *xmax) {
   const int tid = threadIdx.x, nd = P.nd, N = P.nd + P.m;
   for (int i = tid; i < N; i += BT) {
     double t;
@@ -577,7 +583,7 @@ __device__ __attribute__((noinline)) void kkt_solve_wg(const ProbDev &P, const S
     s_z[i] = mixed ? S.eq[i] * t : t;
   }
   __syncthreads();
-  solve_wg(N, S, s_z, s_part, mixed);
+  solve_wg(N, S, s_z, s_part, mixed, s_db, s_pq);
   if (mixed) {
     for (int i = tid; i < N; i += BT) s_z[i] = S.eq[i] * s_z[i];
     __syncthreads();
@@ -669,6 +675,11 @@ __global__ __launch_bounds__(BT) void k_batch(int count, const int32_t *__restri
   __shared__ double s_t[NWAVE * TW][TW + 1];
   __shared__ double s_z[BMAX_N];
   __shared__ double s_part[NWAVE * (BNB + 1)];
+  // the solves' diagonal block and pivot records live in the trailing
+  // update's transpose tiles, which no solve uses
+  double *s_db = &s_t[0][0];
+  int *s_pq = (int *)(s_db + BDB * BDB);
+  static_assert(BDB * BDB * 8 + 2 * BDB * 4 <= NWAVE * TW * (TW + 1) * 8, "solve staging");
   __shared__ int s_p;
   const int tid = threadIdx.x;
   const SlotDev S = slots[blockIdx.x];
@@ -719,13 +730,13 @@ __global__ __launch_bounds__(BT) void k_batch(int count, const int32_t *__restri
     // condensed right-hand side, solve, back-substitution; in mixed
     // precision FP64 refinement on the full system
     double cmax, xmax, rel = 0.0;
-    kkt_solve_wg(P, S, mixed, P.r_d, P.r_s, P.r_y, false, s_z, s_part, &cmax, &xmax);
+    kkt_solve_wg(P, S, mixed, P.r_d, P.r_s, P.r_y, false, s_z, s_part, s_db, s_pq, &cmax, &xmax);
     int steps = 0;
     if constexpr (MIXED) {
       const double *res = S.res;
       while (steps < refine_max) {
         rel = residual_wg(P, S, dw, dc, s_part);
-        kkt_solve_wg(P, S, true, res, res + P.nd, res + P.nd + P.ns, true, s_z, s_part, &cmax,
+        kkt_solve_wg(P, S, true, res, res + P.nd, res + P.nd + P.ns, true, s_z, s_part, s_db, s_pq, &cmax,
                      &xmax);
         ++steps;
         if (cmax <= 1e-15 * xmax) break;

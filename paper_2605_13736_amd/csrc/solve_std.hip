@@ -23,6 +23,7 @@
 // block has been dispatched before its dependants; waits are bounded by a
 // wall-clock limit and set an error word instead of hanging.
 #include "internal.hpp"
+#include "wave.hpp"
 
 namespace mds {
 namespace {
@@ -198,7 +199,7 @@ __global__ __launch_bounds__(TB) void k_trsv_fwd(int N, const double *__restrict
     for (int u = 0; u < NR; ++u) {
       if (u < nr) {
 #pragma unroll
-        for (int t = 0; t < 16; ++t) acc = fma(-lv[u][t], __shfl(yv[u], t), acc);
+        for (int t = 0; t < 16; ++t) acc = fma(-lv[u][t], wave::lane_read(yv[u], t), acc);
       }
     }
     j += nr;
@@ -209,7 +210,7 @@ __global__ __launch_bounds__(TB) void k_trsv_fwd(int N, const double *__restrict
     double v = live ? z[row] : 0.0;
     v += (s_part[0][r] + s_part[1][r]) + (s_part[2][r] + s_part[3][r]);
     for (int c = 0; c < BS - 1; ++c) {
-      const double yc = __shfl(v, c);
+      const double yc = wave::lane_read(v, c);
       if (r > c) v = fma(-s_d[r][c], yc, v);
     }
     if (live) __hip_atomic_store(&z[row], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -275,7 +276,7 @@ __global__ __launch_bounds__(TB) void k_trsv_bwd(int N, int nblk, const double *
     double v = (live ? z[row] : 0.0) + s;
     // unit upper L11': last row first
     for (int c = BS - 1; c > 0; --c) {
-      const double xc = __shfl(v, c);
+      const double xc = wave::lane_read(v, c);
       if (r < c) v = fma(-s_d[c][r], xc, v);
     }
     if (live) __hip_atomic_store(&z[row], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
