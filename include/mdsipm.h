@@ -217,6 +217,16 @@ int mds_set_problem(mds_handle *h, const mds_problem *p);
 int mds_condense(mds_handle *h, const double *sigma_d, const double *dsbase,
                  double delta_w, double delta_c);
 
+/* Optional per-row diagonal of the (2,2) block: every later condensation
+ * subtracts dcv[r] from M22(r, r) after delta_c, and the full Newton system
+ * used by refinement and the backward error carries -delta_c - dcv[r] in its
+ * (y, y) block.  This is how the inverse barrier diagonal of inequality rows
+ * (-D_h^{-1}) enters the compressed form of Sec. 2.2 when the constraints
+ * include inequalities.  dcv: device array (m), caller-owned, finite and
+ * >= 0 (checked: MDS_EINVAL otherwise, nothing changes), valid while set;
+ * NULL clears it.  Invalidates the current M and factor.  Synchronizes. */
+int mds_set_m22_diag(mds_handle *h, const double *dcv);
+
 /* Bunch-Kaufman LDL' of the condensed M with its inertia (Sec. 2.3, kernel
  * class K4).  reg == NULL: factor M as last condensed.  reg != NULL: run the
  * inertia-correction loop (Sec. 2.1): factor with zero shifts, then re-condense

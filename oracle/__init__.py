@@ -71,6 +71,7 @@ def lib():
         P = C.POINTER(OrqProblem)
         F = C.POINTER(OrFactor)
         L.or_condense.argtypes = [P, _dp, _dp, C.c_double, C.c_double, _dp, _dp]
+        L.or_condense_dcv.argtypes = [P, _dp, _dp, C.c_double, C.c_double, _dp, _dp, _dp]
         L.or_rhs_condense.argtypes = [P, _dp, _dp, _dp, _dp]
         L.or_backsub.argtypes = [P, _dp, _dp, _dp, _dp]
         L.or_bk.argtypes = [C.c_int32, _dp, _ip, _dp, _dp, _ip]
@@ -172,13 +173,19 @@ def _buf(n, dtype=np.float64):
     return np.zeros(max(int(n), 1), dtype=dtype)
 
 
-def condense(P: Problem, sigma_d, dsbase, dw=0.0, dc=0.0):
-    """Condensed matrix M (N x N, full symmetric) and inv_d = 1/(dsbase+dw)."""
+def condense(P: Problem, sigma_d, dsbase, dw=0.0, dc=0.0, dcv=None):
+    """Condensed matrix M (N x N, full symmetric) and inv_d = 1/(dsbase+dw).
+    dcv (m, optional): per-row diagonal subtracted from M22 after dc."""
     N = P.N
     M = _buf(N * N)
     inv_d = _buf(P.n_s)
-    lib().or_condense(P.ptr, _d(_f64(sigma_d) if P.n_d else _buf(1)),
-                      _d(_f64(dsbase) if P.n_s else _buf(1)), dw, dc, _d(M), _d(inv_d))
+    sd = _d(_f64(sigma_d) if P.n_d else _buf(1))
+    db = _d(_f64(dsbase) if P.n_s else _buf(1))
+    if dcv is None:
+        lib().or_condense(P.ptr, sd, db, dw, dc, _d(M), _d(inv_d))
+    else:
+        dv = _f64(dcv) if P.m else _buf(1)
+        lib().or_condense_dcv(P.ptr, sd, db, dw, dc, _d(dv), _d(M), _d(inv_d))
     return M[:N * N].reshape((N, N), order="F"), inv_d[:P.n_s]
 
 

@@ -21,11 +21,13 @@
 #define IDX(i, j, ld) ((size_t)(j) * (size_t)(ld) + (size_t)(i))
 
 /* ======================================================================== */
-/* Condensation: Sec. 2.2, eq. (compressed) with no inequality block.        */
+/* Condensation: Sec. 2.2, eq. (compressed).  dcv (optional, m entries) is
+ * the per-row diagonal by which inequality rows enter the (2,2) block
+ * (-D_h^{-1} of the compressed form); NULL when there is none.             */
 /* ======================================================================== */
 
-void or_condense(const orq_problem *P, const double *sigma_d, const double *dsbase,
-                 double dw, double dc, double *M, double *inv_d) {
+void or_condense_dcv(const orq_problem *P, const double *sigma_d, const double *dsbase,
+                     double dw, double dc, const double *dcv, double *M, double *inv_d) {
   const int nd = P->n_d, ns = P->n_s, m = P->m, N = nd + m;
   for (int k = 0; k < ns; ++k) inv_d[k] = 1.0 / (dsbase[k] + dw);
   /* (1,1) block: H + Sigma_d + dw I  (Q_{x_d} with its shift) */
@@ -41,8 +43,8 @@ void or_condense(const orq_problem *P, const double *sigma_d, const double *dsba
       M[IDX(nd + i, j, N)] = P->Jd[IDX(i, j, m)];
       M[IDX(j, nd + i, N)] = P->Jd[IDX(i, j, m)];
     }
-  /* (2,2) block: -J_s D_s^{-1} J_s' - dc I.  Entry (i,j), i >= j, sums over the
-   * shared columns k of rows i and j in ascending k. */
+  /* (2,2) block: -J_s D_s^{-1} J_s' - dc I - diag(dcv).  Entry (i,j), i >= j,
+   * sums over the shared columns k of rows i and j in ascending k. */
   for (int j = 0; j < m; ++j)
     for (int i = j; i < m; ++i) {
       double acc = 0.0;
@@ -56,10 +58,18 @@ void or_condense(const orq_problem *P, const double *sigma_d, const double *dsba
           ++a; ++b;
         }
       }
-      if (i == j) acc = acc - dc;
+      if (i == j) {
+        acc = acc - dc;
+        if (dcv) acc = acc - dcv[i];
+      }
       M[IDX(nd + i, nd + j, N)] = acc;
       M[IDX(nd + j, nd + i, N)] = acc;
     }
+}
+
+void or_condense(const orq_problem *P, const double *sigma_d, const double *dsbase,
+                 double dw, double dc, double *M, double *inv_d) {
+  or_condense_dcv(P, sigma_d, dsbase, dw, dc, NULL, M, inv_d);
 }
 
 void or_rhs_condense(const orq_problem *P, const double *inv_d, const double *r_s,

@@ -44,6 +44,8 @@ typedef struct {
 
 /* ---- condensation (Sec. 2.2, eq. (compressed), 2x2-block form) ---------- */
 /* M (N x N, N = n_d + m, full symmetric, column-major) and inv_d = 1/(dsbase+dw). */
+void or_condense_dcv(const orq_problem *P, const double *sigma_d, const double *dsbase,
+                     double dw, double dc, const double *dcv, double *M, double *inv_d);
 void or_condense(const orq_problem *P, const double *sigma_d, const double *dsbase,
                  double dw, double dc, double *M, double *inv_d);
 /* rhat = r_y - J_s (inv_d .* r_s) */

@@ -145,6 +145,7 @@ SIGNATURES = {
                                 C.POINTER(StepInfo), C.c_int32, _ip]),
     "mds_get_matrix": (C.c_int, [_vp, _dp]),
     "mds_get_factor": (C.c_int, [_vp, _dp, _dp, _dp, _ip]),
+    "mds_set_m22_diag": (C.c_int, [_vp, _vp]),
     "mds_get_inv_ds": (C.c_int, [_vp, _dp]),
     "mds_get_info": (C.c_int, [_vp, C.POINTER(Info)]),
     "mds_set_timing": (C.c_int, [_vp, C.c_int]),
@@ -303,6 +304,18 @@ class Solver:
         self._keep["sigma_d"], self._keep["dsbase"] = sd, db
         st = lib().mds_condense(self.h, _ptr(sd), _ptr(db), float(delta_w), float(delta_c))
         return self._check(st, "mds_condense")
+
+    def set_m22_diag(self, dcv=None):
+        """Per-row diagonal subtracted from M22 (None clears); kept alive here."""
+        if dcv is None:
+            self._keep.pop("dcv", None)
+            st = lib().mds_set_m22_diag(self.h, None)
+        else:
+            t = self.dev(dcv)
+            st = lib().mds_set_m22_diag(self.h, _ptr(t))
+            if st == 0:
+                self._keep["dcv"] = t
+        return self._check(st, "mds_set_m22_diag")
 
     def factor_inertia(self, mu=0.0, reg=None):
         """reg None: factor as condensed.  reg dict (delta_w_last, delta_w_max):

@@ -233,7 +233,7 @@ int condense_impl(mds_handle *h, double dw, double dc) {
     launch_inv_d(S(h), NS(h), h->dsbase, dw, h->w.inv_d);
     launch_condense_dense(S(h), ND(h), MM(h), h->P.H, h->P.J_d, h->sigma_d, dw, h->w.M);
     launch_condense_schur(S(h), ND(h), MM(h), h->N, h->P.Js_rowptr, h->P.Js_col, h->P.Js_val,
-                          h->w.csc_ptr, h->w.csc_row, h->w.csc_val, h->w.inv_d, dc, h->w.M);
+                          h->w.csc_ptr, h->w.csc_row, h->w.csc_val, h->w.inv_d, dc, h->dcv, h->w.M);
   }
   HIPCHK(hipGetLastError());
   h->dw = dw;
@@ -420,7 +420,8 @@ void kkt_matvec(mds_handle *h, const double *dxd, const double *dxs, const doubl
       launch_spmv_csr(S(h), m, P.Js_rowptr, P.Js_col, P.Js_val, dxs, 0.0, oy);
     }
   }
-  kkt_finish(S(h), nd, ns, m, h->sigma_d, h->dsbase, h->dw, h->dc, dxd, dxs, dy, od, os, oy);
+  kkt_finish(S(h), nd, ns, m, h->sigma_d, h->dsbase, h->dw, h->dc, h->dcv, dxd, dxs, dy, od, os,
+             oy);
 }
 
 int read_scal(mds_handle *h, double *dst, int count) {
@@ -483,7 +484,7 @@ int gmres_refine(mds_handle *h, const double *r_d, const double *r_s, const doub
   vec_copy(S(h), m, r_y, r + nd + ns);
   TRY(solve_impl(h, r, r + nd, r + nd + ns, x, x + nd, x + nd + ns));
   kkt_norm_parts(S(h), nd, ns, m, h->P.H, h->sigma_d, h->dw, h->P.J_d, h->P.Js_rowptr,
-                 h->P.Js_val, h->w.csc_ptr, h->w.csc_val, h->dsbase, h->dc, h->w.kn_h,
+                 h->P.Js_val, h->w.csc_ptr, h->w.csc_val, h->dsbase, h->dc, h->dcv, h->w.kn_h,
                  h->w.kn_jd, h->w.kn_y, h->w.kn_js, h->w.red, h->w.scal);
   HIPCHK(hipGetLastError());
   double s8[8];
@@ -587,7 +588,7 @@ int refine_impl(mds_handle *h, const double *r_d, const double *r_s, const doubl
   TRY(solve_impl(h, r_d, r_s, r_y, dx_d, dx_s, dy));
   // ||K||_inf parts and ||r||_inf: two reductions, one read-back
   kkt_norm_parts(S(h), nd, ns, m, h->P.H, h->sigma_d, h->dw, h->P.J_d, h->P.Js_rowptr,
-                 h->P.Js_val, h->w.csc_ptr, h->w.csc_val, h->dsbase, h->dc, h->w.kn_h,
+                 h->P.Js_val, h->w.csc_ptr, h->w.csc_val, h->dsbase, h->dc, h->dcv, h->w.kn_h,
                  h->w.kn_jd, h->w.kn_y, h->w.kn_js, h->w.red, h->w.scal);
   ipm_red_amax3(S(h), nd, r_d, ns, r_s, m, r_y, h->w.red, h->w.scal + 8);
   HIPCHK(hipGetLastError());
@@ -916,6 +917,23 @@ int mds_condense(mds_handle *h, const double *sigma_d, const double *dsbase, dou
   h->sigma_d = sigma_d;
   h->dsbase = dsbase;
   return condense_impl(h, delta_w, delta_c);
+}
+
+int mds_set_m22_diag(mds_handle *h, const double *dcv) {
+  TRY(check_ready(h));
+  if (dcv && MM(h) > 0) {
+    int32_t bad = 0;
+    HIPCHK(hipMemsetAsync(h->w.flags, 0, 4, S(h)));
+    check_nonneg(S(h), MM(h), dcv, h->w.flags);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(&bad, h->w.flags, 4, hipMemcpyDeviceToHost, S(h)));
+    HIPCHK(hipStreamSynchronize(S(h)));
+    if (bad) return set_err(h, MDS_EINVAL, "M22 diagonal: entries must be finite and nonnegative");
+  }
+  h->dcv = (MM(h) > 0) ? dcv : nullptr;
+  h->have_M = false;
+  h->have_factor = false;
+  return MDS_OK;
 }
 
 int mds_factor_inertia(mds_handle *h, mds_reg *reg, double mu, mds_inertia *out_host) {

@@ -8,7 +8,8 @@
 // assembled matrix is bitwise reproducible:
 //   M11 = H, diagonal (H_ii + Sigma_d,i) + dw;   M21 = J_d;   M12 = J_d';
 //   M22(i,j) = 0 - sum_k (J_ik * Dinv_k) * J_jk  over the shared columns k of
-//              rows i >= j in ascending k, then - dc on the diagonal.
+//              rows i >= j in ascending k, then - dc on the diagonal and,
+//              when a per-row diagonal is set, - dcv[r] after it.
 #include "internal.hpp"
 
 namespace mds {
@@ -71,7 +72,7 @@ __global__ void k_condense_schur(int nd, int m, int N, const int32_t *__restrict
                                  const int32_t *__restrict__ crow,
                                  const double *__restrict__ cval,
                                  const double *__restrict__ inv_d, double dc,
-                                 double *__restrict__ M) {
+                                 const double *__restrict__ dcv, double *__restrict__ M) {
   int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= m) return;
   const size_t col = (size_t)(nd + r) * N;
@@ -90,6 +91,7 @@ __global__ void k_condense_schur(int nd, int m, int N, const int32_t *__restrict
   }
   const size_t dpos = (size_t)(nd + r) + col;
   M[dpos] = M[dpos] - dc;
+  if (dcv) M[dpos] = M[dpos] - dcv[r];
 }
 
 __global__ void k_rhs_condense(int m, const int32_t *__restrict__ rp,
@@ -262,10 +264,10 @@ void launch_condense_dense(hipStream_t s, int nd, int m, const double *H, const 
 void launch_condense_schur(hipStream_t s, int nd, int m, int N, const int32_t *rp,
                            const int32_t *ci, const double *v, const int32_t *cptr,
                            const int32_t *crow, const double *cval, const double *inv_d,
-                           double dc, double *M) {
+                           double dc, const double *dcv, double *M) {
   if (m <= 0) return;
   k_condense_schur<<<grid1(m, 128), 128, 0, s>>>(nd, m, N, rp, ci, v, cptr, crow, cval, inv_d,
-                                                 dc, M);
+                                                 dc, dcv, M);
 }
 
 void launch_rhs_condense(hipStream_t s, int m, const int32_t *rp, const int32_t *ci,

@@ -79,6 +79,7 @@ struct mds_handle {
   bool panel_reg = false;  // register-resident panel kernel (ping-pong layout)
   bool panel_coop = false; // ... spread over several workgroups
   bool panel_lds = false;  // whole M in one workgroup's LDS, unblocked
+  const double *dcv = nullptr;  // optional per-row diagonal subtracted from M22 (m)
   int panel_threads = 512; // its workgroup size
   int precision = MDS_FP64;
   int adv = 16;            // least number of columns a panel factors
@@ -115,7 +116,7 @@ void launch_condense_dense(hipStream_t s, int nd, int m, const double *H, const 
 void launch_condense_schur(hipStream_t s, int nd, int m, int N, const int32_t *rp,
                            const int32_t *ci, const double *v, const int32_t *cptr,
                            const int32_t *crow, const double *cval, const double *inv_d,
-                           double dc, double *M);
+                           double dc, const double *dcv, double *M);
 void launch_rhs_condense(hipStream_t s, int m, const int32_t *rp, const int32_t *ci,
                          const double *v, const double *inv_d, const double *r_s,
                          const double *r_y, double *out);

@@ -399,10 +399,16 @@ __global__ void k_kkt_d(int nd, const double *__restrict__ sig, double dw,
   if (i < nd) o_d[i] = fma(sig[i] + dw, dxd[i], o_d[i]);
 }
 
-// third block row (y): o_y = J dx - dc dy (o_y holds J dx on entry)
-__global__ void k_kkt_y(int m, double dc, const double *__restrict__ dy, double *__restrict__ o_y) {
+// third block row (y): o_y = J dx - dc dy - dcv .* dy (o_y holds J dx on
+// entry; dcv, the optional per-row diagonal, may be null)
+__global__ void k_kkt_y(int m, double dc, const double *__restrict__ dcv,
+                        const double *__restrict__ dy, double *__restrict__ o_y) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < m) o_y[i] = fma(-dc, dy[i], o_y[i]);
+  if (i < m) {
+    double o = fma(-dc, dy[i], o_y[i]);
+    if (dcv) o = fma(-dcv[i], dy[i], o);
+    o_y[i] = o;
+  }
 }
 
 // slot 0: max |a|, slot 1: max |b|, slot 2: max |c|  (infinity norms)
@@ -433,6 +439,7 @@ __global__ __launch_bounds__(RB) void k_red_knorm(int nd, int ns, int m,
                                                   const double *__restrict__ dsb,
                                                   const double *__restrict__ jscol,
                                                   const double *__restrict__ yrow, double dc,
+                                                  const double *__restrict__ dcv,
                                                   double *__restrict__ red) {
   double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   const int64_t stride = (int64_t)gridDim.x * RB;
@@ -441,7 +448,7 @@ __global__ __launch_bounds__(RB) void k_red_knorm(int nd, int ns, int m,
   for (int64_t e = (int64_t)blockIdx.x * RB + threadIdx.x; e < len; e += stride) {
     if (e < nd) v[0] = fmax(v[0], hrow[e] + jdcol[e]);
     if (e < ns) v[1] = fmax(v[1], fabs(dsb[e] + dw) + jscol[e]);
-    if (e < m) v[2] = fmax(v[2], yrow[e] + fabs(dc));
+    if (e < m) v[2] = fmax(v[2], yrow[e] + fabs(dc) + (dcv ? fabs(dcv[e]) : 0.0));
   }
   (void)sig;
   block_reduce8(v, red + (size_t)blockIdx.x * 8);
@@ -656,19 +663,28 @@ void vec_add_inplace(hipStream_t s, int64_t n, const double *a, double *out) {
   k_add_inplace<<<grid1(n, 256), 256, 0, s>>>(n, a, out);
 }
 
+__global__ void k_check_nonneg(int64_t n, const double *__restrict__ v, int32_t *bad) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && !(v[i] >= 0.0 && v[i] < INFINITY)) atomicOr(bad, 1);
+}
+
+void check_nonneg(hipStream_t s, int64_t n, const double *v, int32_t *bad) {
+  if (n > 0) k_check_nonneg<<<grid1(n, 256), 256, 0, s>>>(n, v, bad);
+}
+
 void kkt_finish(hipStream_t s, int nd, int ns, int m, const double *sig, const double *dsb,
-                double dw, double dc, const double *dxd, const double *dxs, const double *dy,
-                double *od, double *os, double *oy) {
+                double dw, double dc, const double *dcv, const double *dxd, const double *dxs,
+                const double *dy, double *od, double *os, double *oy) {
   if (nd > 0) k_kkt_d<<<grid1(nd, 256), 256, 0, s>>>(nd, sig, dw, dxd, od);
   if (ns > 0) k_kkt_s<<<grid1(ns, 256), 256, 0, s>>>(ns, dsb, dw, dxs, os);
-  if (m > 0) k_kkt_y<<<grid1(m, 256), 256, 0, s>>>(m, dc, dy, oy);
+  if (m > 0) k_kkt_y<<<grid1(m, 256), 256, 0, s>>>(m, dc, dcv, dy, oy);
 }
 
 void kkt_norm_parts(hipStream_t s, int nd, int ns, int m, const double *H, const double *sig,
                     double dw, const double *Jd, const int32_t *rp, const double *v,
                     const int32_t *cptr, const double *cval, const double *dsb, double dc,
-                    double *hrow, double *jdcol, double *yrow, double *jscol, double *red,
-                    double *out) {
+                    const double *dcv, double *hrow, double *jdcol, double *yrow, double *jscol,
+                    double *red, double *out) {
   if (nd > 0) {
     k_abs_hrow<<<grid1(nd, 4), 256, 0, s>>>(nd, H, sig, dw, hrow);
     k_abs_jdcol<<<grid1(nd, 4), 256, 0, s>>>(m, nd, Jd, jdcol);
@@ -678,7 +694,7 @@ void kkt_norm_parts(hipStream_t s, int nd, int ns, int m, const double *H, const
   int64_t len = nd > ns ? nd : ns;
   len = len > m ? len : m;
   const unsigned g = red_grid(len);
-  k_red_knorm<<<g, RB, 0, s>>>(nd, ns, m, hrow, sig, dw, jdcol, dsb, jscol, yrow, dc, red);
+  k_red_knorm<<<g, RB, 0, s>>>(nd, ns, m, hrow, sig, dw, jdcol, dsb, jscol, yrow, dc, dcv, red);
   k_red_final<<<1, 256, 0, s>>>((int)g, red, out);
 }
 

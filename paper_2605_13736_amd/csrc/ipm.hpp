@@ -54,12 +54,15 @@ void vec_copy(hipStream_t s, int64_t n, const double *src, double *dst);
 void vec_sub(hipStream_t s, int64_t n, const double *a, const double *b, double *out);
 void vec_add_inplace(hipStream_t s, int64_t n, const double *a, double *out);
 void kkt_finish(hipStream_t s, int nd, int ns, int m, const double *sig, const double *dsb,
-                double dw, double dc, const double *dxd, const double *dxs, const double *dy,
-                double *od, double *os, double *oy);
+                double dw, double dc, const double *dcv, const double *dxd, const double *dxs,
+                const double *dy, double *od, double *os, double *oy);
+// *bad |= 1 when some v[i] is negative or not finite
+void check_nonneg(hipStream_t s, int64_t n, const double *v, int32_t *bad);
 void kkt_norm_parts(hipStream_t s, int nd, int ns, int m, const double *H, const double *sig,
                     double dw, const double *Jd, const int32_t *rp, const double *v,
                     const int32_t *cptr, const double *cval, const double *dsb, double dc,
-                    double *hrow, double *jdcol, double *yrow, double *jscol, double *red,
+                    const double *dcv, double *hrow, double *jdcol, double *yrow, double *jscol,
+                    double *red,
                     double *out);
 
 }  // namespace mds

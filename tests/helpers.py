@@ -20,9 +20,9 @@ def dense_js(prob):
     return J
 
 
-def full_kkt(prob, sigma_d, dsbase, dw=0.0, dc=0.0):
-    """K = [[H+diag(sigma_d)+dw I, 0, Jd'], [0, diag(dsbase)+dw I, Js'], [Jd, Js, -dc I]]
-    with unknown order [x_d, x_s, y]."""
+def full_kkt(prob, sigma_d, dsbase, dw=0.0, dc=0.0, dcv=None):
+    """K = [[H+diag(sigma_d)+dw I, 0, Jd'], [0, diag(dsbase)+dw I, Js'],
+    [Jd, Js, -dc I - diag(dcv)]] with unknown order [x_d, x_s, y]."""
     nd, ns, m = prob["n_d"], prob["n_s"], prob["m"]
     n = nd + ns
     K = np.zeros((n + m, n + m))
@@ -36,6 +36,8 @@ def full_kkt(prob, sigma_d, dsbase, dw=0.0, dc=0.0):
     K[n:, nd:n] = Js
     K[nd:n, n:] = Js.T
     K[n:, n:] = -dc * np.eye(m)
+    if dcv is not None:
+        K[n:, n:] -= np.diag(np.asarray(dcv, dtype=float))
     return K
 
 
