@@ -318,6 +318,10 @@ int mds_get_matrix(mds_handle *h, double *M_host);
  * and LAPACK-style 1-based ipiv (lower).  Any pointer may be NULL. */
 int mds_get_factor(mds_handle *h, double *L_host, double *dd_host, double *ds_host,
                    int32_t *ipiv_host);
+/* Copy the pivot sequence (N, LAPACK-style 1-based, lower: k+1 for a 1x1
+ * pivot without interchange, q+1 after interchanging k and q, -(q+1) on both
+ * rows of a 2x2 pivot) to host.  Synchronizes. */
+int mds_get_pivots(mds_handle *h, int32_t *ipiv_host);
 /* Copy D^{-1}_s (n_s) to host. */
 int mds_get_inv_ds(mds_handle *h, double *inv_d_host);
 

@@ -146,6 +146,7 @@ SIGNATURES = {
     "mds_get_matrix": (C.c_int, [_vp, _dp]),
     "mds_get_factor": (C.c_int, [_vp, _dp, _dp, _dp, _ip]),
     "mds_set_m22_diag": (C.c_int, [_vp, _vp]),
+    "mds_get_pivots": (C.c_int, [_vp, _ip]),
     "mds_get_inv_ds": (C.c_int, [_vp, _dp]),
     "mds_get_info": (C.c_int, [_vp, C.POINTER(Info)]),
     "mds_set_timing": (C.c_int, [_vp, C.c_int]),
@@ -467,6 +468,11 @@ class Solver:
         self._check(st, "mds_get_factor")
         Lm = L[:N * N].reshape((N, N), order="F") + np.eye(N)
         return Lm, dd[:N], ds[:N], ipiv[:N]
+
+    def get_pivots(self):
+        ipiv = np.empty(max(self.N, 1), dtype=np.int32)
+        self._check(lib().mds_get_pivots(self.h, ipiv.ctypes.data_as(_ip)), "mds_get_pivots")
+        return ipiv[:self.N]
 
     def get_inv_ds(self):
         out = np.empty(max(self.n_s, 1))

@@ -1247,6 +1247,14 @@ int mds_get_factor(mds_handle *h, double *L_host, double *dd_host, double *ds_ho
   return MDS_OK;
 }
 
+int mds_get_pivots(mds_handle *h, int32_t *ipiv_host) {
+  if (!h || !ipiv_host) return MDS_ENULL;
+  if (!h->have_factor) return set_err(h, MDS_ESTATE, "no factorization");
+  HIPCHK(hipMemcpyAsync(ipiv_host, h->w.ipiv, 4 * (size_t)h->N, hipMemcpyDeviceToHost, S(h)));
+  HIPCHK(hipStreamSynchronize(S(h)));
+  return MDS_OK;
+}
+
 int mds_get_inv_ds(mds_handle *h, double *inv_d_host) {
   if (!h || !inv_d_host) return MDS_ENULL;
   HIPCHK(hipMemcpyAsync(inv_d_host, h->w.inv_d, 8 * (size_t)NS(h), hipMemcpyDeviceToHost, S(h)));

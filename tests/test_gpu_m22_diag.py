@@ -63,6 +63,7 @@ def test_m22_diag_correction_and_refined_solve(seed):
     S.condense(st["sigma_d"], st["dsbase"], 0.0, 0.0)
     status, inn, reg = S.factor_inertia(mu=1e-2, reg=dict(delta_w_last=0.0))
     assert (inn["npos"], inn["nzero"], inn["nneg"]) == (20, 0, 30)
+    assert np.array_equal(S.get_pivots(), S.get_factor()[3])
     (rd, rs, ry), info = S.refine(st["r_d"], st["r_s"], st["r_y"], 5, 1e-14)
     assert info["eta"] <= 1e-10
     K = full_kkt(prob, st["sigma_d"], st["dsbase"], reg["delta_w"], reg["delta_c"], dcv)
