@@ -244,20 +244,22 @@ int condense_impl(mds_handle *h, double dw, double dc) {
 }
 
 // Blocked Bunch-Kaufman of the current M; reads back the inertia.
-int factor_impl(mds_handle *h, mds_inertia *out) {
+// The launches of one factorization, on stream s.  Their number depends only
+// on N and the panel's least width, so the sequence is fixed per handle.
+void factor_launches(mds_handle *h, hipStream_t s) {
   const int N = h->N;
-  launch_fac_reset(S(h), h->w.fst, h->w.panel_k0);
+  launch_fac_reset(s, h->w.fst, h->w.panel_k0);
   const int slots = (N + h->adv - 1) / h->adv;
   if (h->panel_lds) {
     TimedLaunch t(h, MDS_T_PANEL);
-    launch_bk_lds(S(h), h->panel_threads, N, h->alpha_bk, h->w.M, h->w.dd, h->w.ds, h->w.ipiv,
+    launch_bk_lds(s, h->panel_threads, N, h->alpha_bk, h->w.M, h->w.dd, h->w.ds, h->w.ipiv,
                   h->w.blk, h->w.perm, h->w.fst);
   } else if (h->precision != MDS_FP64) {
     // mixed precision: the trailing matrix lives in the FP32 ping-pong
     // buffers; L (FP64) goes to M, which then holds the whole factor
     {
       TimedLaunch t(h, MDS_T_CONDENSE);
-      launch_equilibrate_f32(S(h), N, h->w.M, h->w.eq, h->w.X32[0]);
+      launch_equilibrate_f32(s, N, h->w.M, h->w.eq, h->w.X32[0]);
     }
     for (int b = 0; b < slots; ++b) {
       const float *X = h->w.X32[b & 1];
@@ -265,16 +267,16 @@ int factor_impl(mds_handle *h, mds_inertia *out) {
       {
         TimedLaunch t(h, MDS_T_PANEL);
         if (h->panel_coop)
-          launch_bk_panel_coop(S(h), N, h->nb, h->alpha_bk, X, h->w.M, h->w.src, h->w.W, h->w.dd,
+          launch_bk_panel_coop(s, N, h->nb, h->alpha_bk, X, h->w.M, h->w.src, h->w.W, h->w.dd,
                                h->w.ds, h->w.ipiv, h->w.blk, h->w.fst, h->w.panel_k0, h->w.xch);
         else
-          launch_bk_panel_reg(S(h), h->panel_threads, N, h->nb, h->alpha_bk, X, h->w.M, h->w.src,
+          launch_bk_panel_reg(s, h->panel_threads, N, h->nb, h->alpha_bk, X, h->w.M, h->w.src,
                               h->w.W, h->w.dd, h->w.ds, h->w.ipiv, h->w.blk, h->w.fst,
                               h->w.panel_k0);
       }
       if ((long)N - (long)(b + 1) * h->adv > 0) {
         TimedLaunch t(h, MDS_T_TRAILING);
-        launch_trailing_lp(S(h), h->precision, N, h->nb, h->adv, b, h->w.W, X, Y, h->w.M,
+        launch_trailing_lp(s, h->precision, N, h->nb, h->adv, b, h->w.W, X, Y, h->w.M,
                            h->w.src, h->w.fst, h->w.panel_k0);
       }
     }
@@ -288,22 +290,56 @@ int factor_impl(mds_handle *h, mds_inertia *out) {
     {
       TimedLaunch t(h, MDS_T_PANEL);
       if (h->panel_coop)
-        launch_bk_panel_coop(S(h), N, h->nb, h->alpha_bk, X, Y, h->w.src, h->w.W, h->w.dd,
+        launch_bk_panel_coop(s, N, h->nb, h->alpha_bk, X, Y, h->w.src, h->w.W, h->w.dd,
                              h->w.ds, h->w.ipiv, h->w.blk, h->w.fst, h->w.panel_k0, h->w.xch);
       else if (h->panel_reg)
-        launch_bk_panel_reg(S(h), h->panel_threads, N, h->nb, h->alpha_bk, X, Y, h->w.src, h->w.W,
+        launch_bk_panel_reg(s, h->panel_threads, N, h->nb, h->alpha_bk, X, Y, h->w.src, h->w.W,
                             h->w.dd,
                             h->w.ds, h->w.ipiv, h->w.blk, h->w.fst, h->w.panel_k0);
       else
-        launch_bk_panel(S(h), N, h->nb, h->alpha_bk, h->w.M, h->w.W, h->w.dd, h->w.ds,
+        launch_bk_panel(s, N, h->nb, h->alpha_bk, h->w.M, h->w.W, h->w.dd, h->w.ds,
                         h->w.ipiv, h->w.blk, h->w.fst, h->w.panel_k0);
     }
     if ((long)N - (long)(b + 1) * h->adv > 0) {
       TimedLaunch t(h, MDS_T_TRAILING);
-      launch_bk_trailing(S(h), N, h->nb, h->adv, b, h->w.W, X, Y, Y,
+      launch_bk_trailing(s, N, h->nb, h->adv, b, h->w.W, X, Y, Y,
                          h->panel_reg ? h->w.src : nullptr, h->w.fst, h->w.panel_k0);
     }
   }
+}
+
+// Without per-launch timing, the factorization's launches are captured once
+// into a hipGraph (on a private stream) and replayed on the handle's stream:
+// ~266 dependent launches at N = 4096 leave smaller gaps that way.  Any
+// failure to capture falls back to plain launches for the handle's life.
+void capture_factor(mds_handle *h) {
+  h->fac_graph_off = true;
+  if (!h->cap_stream && hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+    h->cap_stream = nullptr;
+    (void)hipGetLastError();
+    return;
+  }
+  if (hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    (void)hipGetLastError();
+    return;
+  }
+  factor_launches(h, h->cap_stream);
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(h->cap_stream, &g);
+  if (e == hipSuccess && g && hipGraphInstantiate(&h->fac_exec, g, nullptr, nullptr, 0) == hipSuccess)
+    h->fac_graph_off = false;
+  else
+    h->fac_exec = nullptr;
+  if (g) (void)hipGraphDestroy(g);
+  (void)hipGetLastError();
+}
+
+int factor_impl(mds_handle *h, mds_inertia *out) {
+  const int N = h->N;
+  const bool graph = !h->timing && !h->panel_lds && !h->fac_graph_off;
+  if (graph && !h->fac_exec) capture_factor(h);
+  if (graph && h->fac_exec) HIPCHK(hipGraphLaunch(h->fac_exec, S(h)));
+  else factor_launches(h, S(h));
   HIPCHK(hipGetLastError());
   FacState st{};
   HIPCHK(hipMemcpyAsync(&st, h->w.fst, sizeof(st), hipMemcpyDeviceToHost, S(h)));
@@ -873,6 +909,8 @@ int mds_create(mds_handle **out, const mds_dims *dims, const mds_options *opts, 
 void mds_destroy(mds_handle *h) {
   if (!h) return;
   for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
+  if (h->fac_exec) (void)hipGraphExecDestroy(h->fac_exec);
+  if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
   delete h;
 }
 

@@ -80,6 +80,10 @@ struct mds_handle {
   bool panel_coop = false; // ... spread over several workgroups
   bool panel_lds = false;  // whole M in one workgroup's LDS, unblocked
   const double *dcv = nullptr;  // optional per-row diagonal subtracted from M22 (m)
+  // captured launch sequence of one factorization (replayed without timing)
+  hipGraphExec_t fac_exec = nullptr;
+  hipStream_t cap_stream = nullptr;
+  bool fac_graph_off = false;
   int panel_threads = 512; // its workgroup size
   int precision = MDS_FP64;
   int adv = 16;            // least number of columns a panel factors
