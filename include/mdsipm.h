@@ -92,7 +92,9 @@ typedef struct {
   int32_t nb;          /* panel width of the blocked factorization (0: default) */
   int32_t panel;       /* 0: automatic (register-resident panel when its tile
                           allows nb >= 16, i.e. N <= 2048; above that the
-                          cooperative panel),
+                          cooperative panel, which hands over to the
+                          one-workgroup register panel once at most 1024
+                          rows remain),
                           1: panel kept in device memory (FP64 only),
                           2: register-resident panel, one workgroup (N <= 4096),
                           3: register-resident panel over ceil(N / 1024)

@@ -162,6 +162,7 @@ struct PanelChoice {
   bool coop;  // cooperative panel over several workgroups
   int nb, adv, threads;
   bool lds;   // unblocked factorization of the whole M in one workgroup's LDS
+  bool tail = false;  // cooperative: the register panel once the rows left fit one workgroup
 };
 
 // workgroup size of the single-workgroup register panel: the option
@@ -180,8 +181,10 @@ int panel_threads_of(const mds_options *o, int N) {
 // 0 (automatic): the register panel while its tile keeps nb >= 16
 // (N <= 2048 with 512 threads), else the cooperative panel (nb = 32, about
 // 6 us per pivot at N = 4096 against 7-8 us for the memory panel, and half
-// the trailing-update traffic).  The mixed-precision modes need a
-// register-resident panel (2 or 3).
+// the trailing-update traffic), which hands over to the register panel once
+// at most bk_reg_tail_rows() rows remain (option 3 keeps the cooperative
+// panel to the end).  The mixed-precision modes need a register-resident
+// panel (2 or 3).
 PanelChoice panel_of(const mds_dims &d, const mds_options *o) {
   const int N = d.n_d + d.m;
   const int popt = o ? o->panel : 0;
@@ -210,6 +213,7 @@ PanelChoice panel_of(const mds_dims &d, const mds_options *o) {
     int nb = (o && o->nb > 0) ? o->nb : bk_coop_nb();
     nb = std::min(std::max(nb, 2), bk_coop_nb());
     c = {true, true, nb, std::max(nb - 1, 1), 512, false};
+    c.tail = (popt == 0);
   } else {
     int nb = (o && o->nb > 0) ? o->nb : default_nb(N);
     nb = std::min(std::max(nb, 2), kMaxNb);
@@ -243,6 +247,24 @@ int condense_impl(mds_handle *h, double dw, double dc) {
   return MDS_OK;
 }
 
+// Panel of slot b on the ping-pong layout: the cooperative panel, or the
+// register panel over its last rows (every panel before slot b factored at
+// least adv columns, so at most N - b * adv rows remain).
+template <typename TX>
+void launch_reg_panel(mds_handle *h, hipStream_t s, int b, const TX *X, double *Y) {
+  const int N = h->N;
+  const long left = (long)N - (long)b * h->adv;
+  if (h->panel_coop && !(h->panel_tail && left <= bk_reg_tail_rows()))
+    launch_bk_panel_coop(s, N, h->nb, h->alpha_bk, X, Y, h->w.src, h->w.W, h->w.dd, h->w.ds,
+                         h->w.ipiv, h->w.blk, h->w.fst, h->w.panel_k0, h->w.xch);
+  else if (h->panel_coop)
+    launch_bk_panel_reg_tail(s, (int)left, N, h->nb, h->alpha_bk, X, Y, h->w.src, h->w.W,
+                             h->w.dd, h->w.ds, h->w.ipiv, h->w.blk, h->w.fst, h->w.panel_k0);
+  else
+    launch_bk_panel_reg(s, h->panel_threads, N, h->nb, h->alpha_bk, X, Y, h->w.src, h->w.W,
+                        h->w.dd, h->w.ds, h->w.ipiv, h->w.blk, h->w.fst, h->w.panel_k0);
+}
+
 // Blocked Bunch-Kaufman of the current M; reads back the inertia.
 // The launches of one factorization, on stream s.  Their number depends only
 // on N and the panel's least width, so the sequence is fixed per handle.
@@ -266,13 +288,7 @@ void factor_launches(mds_handle *h, hipStream_t s) {
       float *Y = h->w.X32[(b + 1) & 1];
       {
         TimedLaunch t(h, MDS_T_PANEL);
-        if (h->panel_coop)
-          launch_bk_panel_coop(s, N, h->nb, h->alpha_bk, X, h->w.M, h->w.src, h->w.W, h->w.dd,
-                               h->w.ds, h->w.ipiv, h->w.blk, h->w.fst, h->w.panel_k0, h->w.xch);
-        else
-          launch_bk_panel_reg(s, h->panel_threads, N, h->nb, h->alpha_bk, X, h->w.M, h->w.src,
-                              h->w.W, h->w.dd, h->w.ds, h->w.ipiv, h->w.blk, h->w.fst,
-                              h->w.panel_k0);
+        launch_reg_panel(h, s, b, X, h->w.M);
       }
       if ((long)N - (long)(b + 1) * h->adv > 0) {
         TimedLaunch t(h, MDS_T_TRAILING);
@@ -289,13 +305,8 @@ void factor_launches(mds_handle *h, hipStream_t s) {
     if (h->panel_reg && !(b & 1)) Y = h->w.M2;
     {
       TimedLaunch t(h, MDS_T_PANEL);
-      if (h->panel_coop)
-        launch_bk_panel_coop(s, N, h->nb, h->alpha_bk, X, Y, h->w.src, h->w.W, h->w.dd,
-                             h->w.ds, h->w.ipiv, h->w.blk, h->w.fst, h->w.panel_k0, h->w.xch);
-      else if (h->panel_reg)
-        launch_bk_panel_reg(s, h->panel_threads, N, h->nb, h->alpha_bk, X, Y, h->w.src, h->w.W,
-                            h->w.dd,
-                            h->w.ds, h->w.ipiv, h->w.blk, h->w.fst, h->w.panel_k0);
+      if (h->panel_reg)
+        launch_reg_panel(h, s, b, (const double *)X, Y);
       else
         launch_bk_panel(s, N, h->nb, h->alpha_bk, h->w.M, h->w.W, h->w.dd, h->w.ds,
                         h->w.ipiv, h->w.blk, h->w.fst, h->w.panel_k0);
@@ -344,7 +355,9 @@ int factor_impl(mds_handle *h, mds_inertia *out) {
   FacState st{};
   HIPCHK(hipMemcpyAsync(&st, h->w.fst, sizeof(st), hipMemcpyDeviceToHost, S(h)));
   HIPCHK(hipStreamSynchronize(S(h)));
-  if (st.xerr) return set_err(h, MDS_EHIP, "cooperative panel: exchange wait timed out");
+  if (st.xerr)
+    return set_err(h, MDS_EHIP,
+                   "panel aborted: cooperative exchange wait timed out, or rows beyond the register tile");
   if (st.k != N) return set_err(h, MDS_EHIP, "factorization stopped at %d of %d", st.k, N);
   out->npos = st.npos;
   out->nzero = st.nzero;
@@ -826,6 +839,7 @@ int mds_create(mds_handle **out, const mds_dims *dims, const mds_options *opts, 
   h->nb = nb;
   h->panel_reg = pc.reg;
   h->panel_coop = pc.coop;
+  h->panel_tail = pc.tail;
   h->panel_lds = pc.lds;
   h->panel_threads = pc.threads;
   h->precision = prec;

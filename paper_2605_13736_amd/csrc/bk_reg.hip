@@ -1,5 +1,5 @@
-// Register-resident Bunch-Kaufman panel kernel (Sec. 2.3) for N <= 4096; the
-// workgroup-level body is panel::panel_reg_dev.
+// Register-resident Bunch-Kaufman panel kernel (Sec. 2.3): N <= 4096, or the
+// last rows of a cooperative factorization; the body is panel::panel_reg_dev.
 #include "panel_reg.hpp"
 
 namespace mds {
@@ -86,6 +86,38 @@ static void panel_reg(hipStream_t s, int threads, int N, int nb, double alpha, c
     }
   }
 #undef MDS_PANEL_REG
+}
+
+// Tail of a cooperative factorization: once at most 2 * 512 rows remain, one
+// workgroup of 512 threads holds them in its registers at the cooperative
+// panel's tile width (32), and a pivot step needs no grid-wide exchange.
+// rows bounds N - k0 from above (the host knows k0 >= panels * (nb - 1)).
+int bk_reg_tail_rows() { return 2 * TMAX; }
+
+template <typename TX>
+static void panel_reg_tail(hipStream_t s, int rows, int N, int nb, double alpha, const TX *X,
+                           double *Lout, int32_t *src_out, double *W, double *dd, double *ds,
+                           int32_t *ipiv, int32_t *blk, FacState *st, int32_t *panel_k0) {
+  if (rows <= TMAX)
+    k_bk_panel_reg<TMAX, 1, 32, TX><<<1, TMAX, 0, s>>>(N, nb, alpha, X, Lout, src_out, W, dd, ds,
+                                                       ipiv, blk, st, panel_k0);
+  else if (rows <= 2 * TMAX)
+    k_bk_panel_reg<TMAX, 2, 32, TX><<<1, TMAX, 0, s>>>(N, nb, alpha, X, Lout, src_out, W, dd, ds,
+                                                       ipiv, blk, st, panel_k0);
+}
+
+void launch_bk_panel_reg_tail(hipStream_t s, int rows, int N, int nb, double alpha,
+                              const double *X, double *Lout, int32_t *src_out, double *W,
+                              double *dd, double *ds, int32_t *ipiv, int32_t *blk, FacState *st,
+                              int32_t *panel_k0) {
+  panel_reg_tail(s, rows, N, nb, alpha, X, Lout, src_out, W, dd, ds, ipiv, blk, st, panel_k0);
+}
+
+void launch_bk_panel_reg_tail(hipStream_t s, int rows, int N, int nb, double alpha,
+                              const float *X, double *Lout, int32_t *src_out, double *W,
+                              double *dd, double *ds, int32_t *ipiv, int32_t *blk, FacState *st,
+                              int32_t *panel_k0) {
+  panel_reg_tail(s, rows, N, nb, alpha, X, Lout, src_out, W, dd, ds, ipiv, blk, st, panel_k0);
 }
 
 void launch_bk_panel_reg(hipStream_t s, int threads, int N, int nb, double alpha, const double *X,

@@ -78,6 +78,7 @@ struct mds_handle {
   int N = 0, n = 0, nb = 16, max_panels = 0;
   bool panel_reg = false;  // register-resident panel kernel (ping-pong layout)
   bool panel_coop = false; // ... spread over several workgroups
+  bool panel_tail = false; // ... with the register panel once its rows fit one workgroup
   bool panel_lds = false;  // whole M in one workgroup's LDS, unblocked
   const double *dcv = nullptr;  // optional per-row diagonal subtracted from M22 (m)
   // captured launch sequence of one factorization (replayed without timing)
@@ -145,6 +146,17 @@ void launch_bk_trailing(hipStream_t s, int N, int nb, int adv, int slot, const d
 // workgroup of `threads` = 512 or 1024
 int bk_reg_rows(int N, int threads);
 int bk_reg_nb(int N, int threads);
+// register panel over the last rows of a cooperative factorization (rows >=
+// N - k0, rows <= bk_reg_tail_rows(), nb <= 32)
+int bk_reg_tail_rows();
+void launch_bk_panel_reg_tail(hipStream_t s, int rows, int N, int nb, double alpha,
+                              const double *X, double *Lout, int32_t *src_out, double *W,
+                              double *dd, double *ds, int32_t *ipiv, int32_t *blk, FacState *st,
+                              int32_t *panel_k0);
+void launch_bk_panel_reg_tail(hipStream_t s, int rows, int N, int nb, double alpha,
+                              const float *X, double *Lout, int32_t *src_out, double *W,
+                              double *dd, double *ds, int32_t *ipiv, int32_t *blk, FacState *st,
+                              int32_t *panel_k0);
 void launch_bk_panel_reg(hipStream_t s, int threads, int N, int nb, double alpha, const double *X,
                          double *Lout, int32_t *src_out, double *W, double *dd, double *ds,
                          int32_t *ipiv, int32_t *blk, FacState *st, int32_t *panel_k0);

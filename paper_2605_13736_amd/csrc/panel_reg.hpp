@@ -1,7 +1,7 @@
 #pragma once
 // Register-resident Bunch-Kaufman panel (Sec. 2.3), as a workgroup-level
 // device function shared by the panel kernel and the batched kernel: same decisions and the
-// same output layout as the panel in bk.hip, for N <= 4096.
+// same output layout as the panel in bk.hip, for at most R * T rows left.
 //
 // One workgroup of 512 threads (two waves per SIMD).  Thread t owns the
 // physical rows rho = k0 + t + 512 r (r < R) of the buffer X for the whole
@@ -107,7 +107,13 @@ __device__ inline void panel_reg_dev(int N, int nb, double alpha,
   __syncthreads();
   const int k0 = s_k0;
   if (k0 >= N) return;
-  const int ld = N;  // N <= 4096: every offset fits in 32 bits
+  // the tile must hold every remaining row (the host guarantees it); if not,
+  // the factorization is flagged as failed rather than left incomplete
+  if (N - k0 > R * T) {
+    if (tid == 0) st->xerr = 1;
+    return;
+  }
+  const int ld = N;  // N <= 20480 (a cooperative factorization's tail): offsets fit in 32 bits
 
   double Lr[R][NB];
   // prefetched un-updated column values, kept in the storage type and

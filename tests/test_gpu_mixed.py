@@ -133,6 +133,28 @@ def test_mixed_cooperative_panel(prec):
     assert np.abs(got - ref).max() <= 1e-8 * max(np.abs(ref).max(), 1e-300)
 
 
+def test_mixed_automatic_panel_register_tail():
+    # N = 2200: the automatic choice runs the cooperative panel on the FP32
+    # trailing matrix and the register panel over its last <= 1024 rows
+    nd, ns, m, r = 500, 6000, 1700, 5
+    prob = synth.make_problem(nd, ns, m, r, cfg=530, p=0)
+    st = synth.kkt_state(prob, 0, (-1.0, 1.0))
+    say(f"mixed fp32 automatic panel (register tail) N={nd + m}")
+    S = mds.solver_for(prob, precision="fp32")
+    assert S.info()["panel"] == "coop"
+    S.condense(st["sigma_d"], st["dsbase"], 1e-6, 1e-9)
+    S.factor_inertia()
+    (rd, rs, ry), info = S.refine(st["r_d"], st["r_s"], st["r_y"], 60, 1e-14)
+    P = oracle.Problem(prob)
+    F = oracle.Factor(P).once(st["sigma_d"], st["dsbase"], 1e-6, 1e-9)
+    od, os_, oy, _ = F.solve(st["r_d"], st["r_s"], st["r_y"])
+    got = np.concatenate([_np(rd), _np(rs), _np(ry)])
+    ref = np.concatenate([od, os_, oy])
+    assert info["eta"] <= 1e-12
+    assert info["steps"] <= ITER_CAP["fp32"]
+    assert np.abs(got - ref).max() <= 1e-8 * max(np.abs(ref).max(), 1e-300)
+
+
 def test_mixed_needs_register_panel():
     prob = synth.make_problem(10, 40, 27, 3, cfg=520, p=0)
     with pytest.raises(mds.MdsError):

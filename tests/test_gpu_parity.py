@@ -319,6 +319,32 @@ def test_cooperative_panel_workgroup_boundaries(N):
     assert (inn["npos"], inn["nzero"], inn["nneg"]) == ino
 
 
+@pytest.mark.parametrize("N", [2049, 3000])
+def test_automatic_panel_register_tail(N):
+    # above N = 2048 the automatic choice runs the cooperative panel and hands
+    # over to the one-workgroup register panel for the last (<= 1024) rows;
+    # the pivot sequence must still be the oracle's, and the factor the same
+    # as the cooperative panel's run to the end, up to rounding
+    rng = np.random.default_rng(N + 7)
+    A = rng.standard_normal((N, N))
+    A = A + A.T
+    say(f"automatic panel (register tail) N={N} vs oracle")
+    S = mds.solver_for(_dense_problem(A))
+    assert S.info()["panel"] == "coop"
+    S.condense(np.zeros(N), np.zeros(0), 0.0, 0.0)
+    _, inn, _ = S.factor_inertia()
+    ino, _ = _factor_check(S, A)
+    assert (inn["npos"], inn["nzero"], inn["nneg"]) == ino
+    L_auto, _, _, piv_auto = S.get_factor()
+    del S
+    C = mds.solver_for(_dense_problem(A), panel="coop")
+    C.condense(np.zeros(N), np.zeros(0), 0.0, 0.0)
+    C.factor_inertia()
+    L_coop, _, _, piv_coop = C.get_factor()
+    assert np.array_equal(piv_auto, piv_coop)
+    assert np.max(np.abs(L_auto - L_coop)) <= 1e-10 * max(1.0, np.max(np.abs(L_coop)))
+
+
 def test_cooperative_panel_nine_workgroups_matches_memory_panel():
     # N = 9000: 9 workgroups (the 12-workgroup variant of the kernel); the
     # memory panel, pinned against the oracle at smaller sizes, is the reference
