@@ -34,8 +34,8 @@ HBM_PEAK_GBS = 8000.0
 # the counters of a 256 MiB copy (the profile file gives the commands and the
 # factors); valid for the kernel source as profiled.
 MEASURED_TRAFFIC = {
-    "k_bk_panel_coop": (2225396.0, "profiles/bk_panel_coop_ipm_newton_step_n4096.md"),
-    "k_bk_trailing": (84683965.0, "profiles/bk_trailing_ipm_newton_step_n4096.md"),
+    "k_bk_panel_coop": (2742787.0, "profiles/bk_panel_coop_ipm_newton_step_n4096.md"),
+    "k_bk_trailing": (84686820.0, "profiles/bk_trailing_ipm_newton_step_n4096.md"),
 }
 FP64_MFMA_PEAK_TFS = 78.6
 
@@ -44,13 +44,19 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def panel_bytes_per_launch(N, launches_per_factor):
-    """Algorithmic HBM bytes of one panel launch, averaged over a factorization:
+def panel_bytes_per_launch(N, launches_per_factor, adv=None):
+    """Algorithmic HBM bytes of one panel launch, averaged over its launches:
     a panel of width w starting at k0 reads its w columns (rows >= k0) once,
     reads one pivot-candidate column per pivot, and writes L and W once:
-    4 * (N - k0) * w * 8 bytes.  Summed over the factorization this is
-    4 * 8 * N (N + 1) / 2 whatever the widths; divided by the launches."""
-    return 4.0 * 8.0 * N * (N + 1) / 2.0 / max(launches_per_factor, 1)
+    4 * (N - k0) * w * 8 bytes, i.e. 4 * 8 * (N - c) per column c.  Over a
+    whole factorization this is 4 * 8 * N (N + 1) / 2 whatever the widths.
+    When the launches cover only the first columns (a cooperative panel that
+    hands the last rows to another kernel), they cover launches * adv columns
+    (adv = nb - 1 per panel, nominal: a panel ending on a 2x2 pivot takes one
+    more)."""
+    n = max(launches_per_factor, 1)
+    K = N if adv is None else min(N, n * adv)
+    return 4.0 * 8.0 * (K * N - K * (K - 1) / 2.0) / n
 
 
 def trailing_bytes_per_launch(N, w):
@@ -103,7 +109,7 @@ def mixed_section(prob, N, reps=3):
         x = torch.cat([a, b, c]).cpu().numpy()
         if ref is None:
             ref = x
-        fac_ms = (tim["panel"]["ms"] + tim["trailing"]["ms"]) / reps
+        fac_ms = (tim["panel"]["ms"] + tim["panel_tail"]["ms"] + tim["trailing"]["ms"]) / reps
         out[prec] = dict(ms_condense_factor_refine=dt * 1e3, ms_factor=fac_ms,
                          tflops_nominal=(N ** 3 / 3.0 + 2.0 * N ** 2) / dt / 1e12,
                          refine_iterations=info["steps"], eta=info["eta"],
@@ -400,11 +406,14 @@ def main():
     nlaunch = max(tim[dom]["launches"], 1)
     avg_s = tim[dom]["ms"] / 1e3 / nlaunch
     if dom == "panel":
-        per_launch = panel_bytes_per_launch(N, tim["panel"]["launches"] / max(efacs, 1))
+        tail = tim["panel_tail"]["launches"] > 0
+        per_launch = panel_bytes_per_launch(N, tim["panel"]["launches"] / max(efacs, 1),
+                                            adv=max(nb - 1, 1) if tail else None)
         roof = dict(bound="hbm", achieved=per_launch / avg_s / 1e9, peak=HBM_PEAK_GBS,
                     unit="GB/s")
     elif dom == "trailing":
-        per_launch = trailing_bytes_per_launch(N, N / max(tim["panel"]["launches"] / max(efacs, 1), 1))
+        npan = tim["panel"]["launches"] + tim["panel_tail"]["launches"]
+        per_launch = trailing_bytes_per_launch(N, N / max(npan / max(efacs, 1), 1))
         roof = dict(bound="hbm", achieved=per_launch / avg_s / 1e9, peak=HBM_PEAK_GBS,
                     unit="GB/s")
     elif dom == "solve":
@@ -418,7 +427,7 @@ def main():
                     unit="GB/s")
     roof["frac"] = roof["achieved"] / roof["peak"]
     panel_kernel = {"reg": "k_bk_panel_reg", "coop": "k_bk_panel_coop"}.get(info0["panel"], "k_bk_panel")
-    roof["kernel"] = {"panel": panel_kernel,
+    roof["kernel"] = {"panel": panel_kernel, "panel_tail": "k_bk_panel_reg",
                       "trailing": "k_bk_trailing",
                       "solve": "k_trsv_fwd+k_trsv_bwd", "condense": "k_condense_dense",
                       "permute": "k_std_sweep+k_std_apply"}[dom]
@@ -428,7 +437,7 @@ def main():
         roof["traffic_source"] = meas[1]
     roof["avg_launch_us"] = avg_s * 1e6
     roof["bytes_per_launch"] = per_launch
-    fac_ms = (tim["panel"]["ms"] + tim["trailing"]["ms"]) / max(efacs, 1)
+    fac_ms = (tim["panel"]["ms"] + tim["panel_tail"]["ms"] + tim["trailing"]["ms"]) / max(efacs, 1)
     factor_tfs = (N ** 3 / 3.0) / (fac_ms / 1e3) / 1e12
 
     out = {

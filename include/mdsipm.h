@@ -182,9 +182,11 @@ typedef struct {       /* one IPM iteration (host) */
 /* Per-kernel-class device time, accumulated while timing is enabled
  * (hipEvents recorded around each launch on the handle's stream).  PERMUTE is
  * the conversion of a new factor to standard form before its first solve;
- * SOLVE is one triangular-solve sequence (permute, L, D, L', permute). */
+ * SOLVE is one triangular-solve sequence (permute, L, D, L', permute);
+ * PANEL_TAIL holds the register-panel launches that finish a cooperative
+ * factorization (PANEL then holds only the cooperative ones). */
 enum { MDS_T_CONDENSE = 0, MDS_T_PANEL = 1, MDS_T_TRAILING = 2, MDS_T_SOLVE = 3,
-       MDS_T_PERMUTE = 4, MDS_T_CLASSES = 5 };
+       MDS_T_PERMUTE = 4, MDS_T_PANEL_TAIL = 5, MDS_T_CLASSES = 6 };
 typedef struct {
   double ms[MDS_T_CLASSES];     /* summed kernel time per class            */
   int64_t launches[MDS_T_CLASSES];

@@ -86,7 +86,7 @@ class StepInfo(C.Structure):
                 ("backtracks", C.c_int32), ("status", C.c_int32)]
 
 
-T_CLASSES = ("condense", "panel", "trailing", "solve", "permute")
+T_CLASSES = ("condense", "panel", "trailing", "solve", "permute", "panel_tail")
 
 
 class Info(C.Structure):

@@ -250,11 +250,15 @@ int condense_impl(mds_handle *h, double dw, double dc) {
 // Panel of slot b on the ping-pong layout: the cooperative panel, or the
 // register panel over its last rows (every panel before slot b factored at
 // least adv columns, so at most N - b * adv rows remain).
+bool is_tail_slot(const mds_handle *h, int b) {
+  return h->panel_coop && h->panel_tail && (long)h->N - (long)b * h->adv <= bk_reg_tail_rows();
+}
+
 template <typename TX>
 void launch_reg_panel(mds_handle *h, hipStream_t s, int b, const TX *X, double *Y) {
   const int N = h->N;
   const long left = (long)N - (long)b * h->adv;
-  if (h->panel_coop && !(h->panel_tail && left <= bk_reg_tail_rows()))
+  if (h->panel_coop && !is_tail_slot(h, b))
     launch_bk_panel_coop(s, N, h->nb, h->alpha_bk, X, Y, h->w.src, h->w.W, h->w.dd, h->w.ds,
                          h->w.ipiv, h->w.blk, h->w.fst, h->w.panel_k0, h->w.xch);
   else if (h->panel_coop)
@@ -287,7 +291,7 @@ void factor_launches(mds_handle *h, hipStream_t s) {
       const float *X = h->w.X32[b & 1];
       float *Y = h->w.X32[(b + 1) & 1];
       {
-        TimedLaunch t(h, MDS_T_PANEL);
+        TimedLaunch t(h, is_tail_slot(h, b) ? MDS_T_PANEL_TAIL : MDS_T_PANEL);
         launch_reg_panel(h, s, b, X, h->w.M);
       }
       if ((long)N - (long)(b + 1) * h->adv > 0) {
@@ -304,7 +308,7 @@ void factor_launches(mds_handle *h, hipStream_t s) {
     if (h->panel_reg && (b & 1)) X = h->w.M2;
     if (h->panel_reg && !(b & 1)) Y = h->w.M2;
     {
-      TimedLaunch t(h, MDS_T_PANEL);
+      TimedLaunch t(h, is_tail_slot(h, b) ? MDS_T_PANEL_TAIL : MDS_T_PANEL);
       if (h->panel_reg)
         launch_reg_panel(h, s, b, (const double *)X, Y);
       else
