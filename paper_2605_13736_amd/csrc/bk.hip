@@ -325,7 +325,11 @@ __global__ __launch_bounds__(256) void k_bk_trailing(int N, int nb, const double
   const int k0 = panel_k0[slot], kend = panel_k0[slot + 1];
   if (kend >= N || kend <= k0 || kend - k0 > nb + 1) return;
   const int jw = kend - k0;
-  const int nt = (N - kend + TT - 1) / TT;
+  // tiles start at the 16-row (128-byte) boundary at or below kend, so that a
+  // tile's 64-row column segments cover 4 cache lines rather than 5 (when
+  // N is a multiple of 16); rows and columns below kend are masked
+  const int a0 = kend & ~15;
+  const int nt = (N - a0 + TT - 1) / TT;
   // triangular tile index -> (ti >= tj)
   const int x = blockIdx.x;
   int ti = (int)((sqrt(8.0 * (double)x + 1.0) - 1.0) * 0.5);
@@ -333,7 +337,7 @@ __global__ __launch_bounds__(256) void k_bk_trailing(int N, int nb, const double
   while (ti * (ti + 1) / 2 > x) --ti;
   const int tj = x - ti * (ti + 1) / 2;
   if (ti >= nt) return;
-  const int i0 = kend + ti * TT, c0 = kend + tj * TT;
+  const int i0 = a0 + ti * TT, c0 = a0 + tj * TT;
   const size_t ld = (size_t)N;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int wc = c0 + (wv & 1) * 32, wi = i0 + (wv >> 1) * 32;
@@ -346,14 +350,14 @@ __global__ __launch_bounds__(256) void k_bk_trailing(int N, int nb, const double
 #pragma unroll
   for (int b = 0; b < 2; ++b) {
     const int i = wi + b * 16 + l16;
-    si[b] = (i < N) ? (src ? src[i] : i) : 0;
+    si[b] = (i >= kend && i < N) ? (src ? src[i] : i) : 0;
   }
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int c = wc + a * 16 + l4 + 4 * r;
-      sc[a][r] = (c < N) ? (src ? src[c] : c) : 0;
+      sc[a][r] = (c >= kend && c < N) ? (src ? src[c] : c) : 0;
     }
   double xv[2][2][4];
 #pragma unroll
@@ -364,7 +368,7 @@ __global__ __launch_bounds__(256) void k_bk_trailing(int N, int nb, const double
       for (int r = 0; r < 4; ++r) {
         const int c = wc + a * 16 + l4 + 4 * r;
         const int i = wi + b * 16 + l16;
-        xv[a][b][r] = (c < N && i < N && (!diag || i >= c))
+        xv[a][b][r] = (c >= kend && c < N && i < N && (!diag || i >= c))
                           ? X[(size_t)si[b] + (size_t)sc[a][r] * ld] : 0.0;
       }
 
@@ -384,8 +388,8 @@ __global__ __launch_bounds__(256) void k_bk_trailing(int N, int nb, const double
     for (int u = 0; u < TSTAGE; ++u) {
       const int e = tid + 256 * u, r = e & (TT - 1), t = e >> 6;
       const int c = c0 + r, i = i0 + r;
-      vw[u] = (t < tw && c < N) ? W[(size_t)c + (size_t)(tb + t) * ld] : 0.0;
-      vl[u] = (t < tw && i < N) ? Lsrc[(size_t)i + (size_t)(k0 + tb + t) * ld] : 0.0;
+      vw[u] = (t < tw && c >= kend && c < N) ? W[(size_t)c + (size_t)(tb + t) * ld] : 0.0;
+      vl[u] = (t < tw && i >= kend && i < N) ? Lsrc[(size_t)i + (size_t)(k0 + tb + t) * ld] : 0.0;
     }
 #pragma unroll
     for (int u = 0; u < TSTAGE; ++u) {
@@ -418,7 +422,7 @@ __global__ __launch_bounds__(256) void k_bk_trailing(int N, int nb, const double
       for (int r = 0; r < 4; ++r) {
         const int c = wc + a * 16 + l4 + 4 * r;
         const int i = wi + b * 16 + l16;
-        if (c < N && i < N && (!diag || i >= c)) {
+        if (c >= kend && c < N && i < N && (!diag || i >= c)) {
           const double v = xv[a][b][r] - acc[a][b][r];
           Y[(size_t)i + (size_t)c * ld] = v;
           s_t[c - c0][i - i0] = v;
@@ -429,7 +433,8 @@ __global__ __launch_bounds__(256) void k_bk_trailing(int N, int nb, const double
   for (int e = tid; e < TT * TT; e += 256) {
     const int cl = e & (TT - 1), il = e >> 6;
     const int c = c0 + cl, i = i0 + il;
-    if (c < N && i < N && i > c && (!diag || il >= cl)) Y[(size_t)c + (size_t)i * ld] = s_t[cl][il];
+    if (c >= kend && c < N && i < N && i > c && (!diag || il >= cl))
+      Y[(size_t)c + (size_t)i * ld] = s_t[cl][il];
   }
 }
 
@@ -449,10 +454,11 @@ void launch_bk_trailing(hipStream_t s, int N, int nb, int adv, int slot, const d
                         const double *X, double *Y, const double *Lsrc, const int32_t *src,
                         const FacState *st, const int32_t *panel_k0) {
   // every panel before this slot has at least adv columns, so the trailing
-  // matrix after slot `slot` has at most N - (slot+1)*adv rows
+  // matrix after slot `slot` has at most N - (slot+1)*adv rows; the kernel's
+  // tiles start up to 15 rows earlier (at a 16-row boundary)
   const long rem = (long)N - (long)(slot + 1) * adv;
   if (rem <= 0) return;
-  const long nt = (rem + TT - 1) / TT;
+  const long nt = (rem + 15 + TT - 1) / TT;
   const long tiles = nt * (nt + 1) / 2;
   k_bk_trailing<<<(unsigned)tiles, 256, 0, s>>>(N, nb, W, X, Y, Lsrc, src, st, panel_k0, slot);
 }
