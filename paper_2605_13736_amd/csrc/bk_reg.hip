@@ -98,9 +98,13 @@ template <typename TX>
 static void panel_reg_tail(hipStream_t s, int rows, int N, int nb, double alpha, const TX *X,
                            double *Lout, int32_t *src_out, double *W, double *dd, double *ds,
                            int32_t *ipiv, int32_t *blk, FacState *st, int32_t *panel_k0) {
-  if (rows <= TMAX)
-    k_bk_panel_reg<TMAX, 1, 32, TX><<<1, TMAX, 0, s>>>(N, nb, alpha, X, Lout, src_out, W, dd, ds,
-                                                       ipiv, blk, st, panel_k0);
+  // up to 512 rows: 256 threads (fewer waves wait at each barrier of a step)
+  if (rows <= 256)
+    k_bk_panel_reg<256, 1, 32, TX><<<1, 256, 0, s>>>(N, nb, alpha, X, Lout, src_out, W, dd, ds,
+                                                     ipiv, blk, st, panel_k0);
+  else if (rows <= 512)
+    k_bk_panel_reg<256, 2, 32, TX><<<1, 256, 0, s>>>(N, nb, alpha, X, Lout, src_out, W, dd, ds,
+                                                     ipiv, blk, st, panel_k0);
   else if (rows <= 2 * TMAX)
     k_bk_panel_reg<TMAX, 2, 32, TX><<<1, TMAX, 0, s>>>(N, nb, alpha, X, Lout, src_out, W, dd, ds,
                                                        ipiv, blk, st, panel_k0);
