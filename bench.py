@@ -34,8 +34,8 @@ HBM_PEAK_GBS = 8000.0
 # the counters of a 256 MiB copy (the profile file gives the commands and the
 # factors); valid for the kernel source as profiled.
 MEASURED_TRAFFIC = {
-    "k_bk_panel_coop": (2742780.0, "profiles/bk_panel_coop_ipm_newton_step_n4096.md"),
-    "k_bk_trailing": (75935297.0, "profiles/bk_trailing_ipm_newton_step_n4096.md"),
+    "k_bk_panel_coop": (2742650.0, "profiles/bk_panel_coop_ipm_newton_step_n4096.md"),
+    "k_bk_trailing": (75934233.0, "profiles/bk_trailing_ipm_newton_step_n4096.md"),
 }
 FP64_MFMA_PEAK_TFS = 78.6
 
