@@ -105,7 +105,7 @@ static void panel_reg_tail(hipStream_t s, int rows, int N, int nb, double alpha,
   else if (rows <= 512)
     k_bk_panel_reg<256, 2, 32, TX><<<1, 256, 0, s>>>(N, nb, alpha, X, Lout, src_out, W, dd, ds,
                                                      ipiv, blk, st, panel_k0);
-  else if (rows <= 2 * TMAX)
+  else  // rows beyond 1024 would break the caller's bound: the kernel's guard flags them
     k_bk_panel_reg<TMAX, 2, 32, TX><<<1, TMAX, 0, s>>>(N, nb, alpha, X, Lout, src_out, W, dd, ds,
                                                        ipiv, blk, st, panel_k0);
 }
