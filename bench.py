@@ -215,7 +215,7 @@ def warmstart_section(n_train, n_held, hidden=128, steps=3000, lr=3e-3, noise=0.
     import paper_2605_13736_amd as mds
     import synth
     from paper_2605_13736_amd import warmstart
-    base = synth.config_problem(0)
+    base = synth.config_problem(synth.IPM_N192)
     train = [synth.family_member(base, p) for p in range(n_train)]
     held = [synth.family_member(base, 10 ** 6 + p) for p in range(n_held)]
     t0 = time.perf_counter()
@@ -293,7 +293,7 @@ def ipm_solves_section(nrep=5):
 
     import paper_2605_13736_amd as mds
     import synth
-    prob0 = synth.config_problem(0)
+    prob0 = synth.config_problem(synth.IPM_N192)
     S0 = mds.solver_for(prob0)
     r = S0.ipm_solve()
     torch.cuda.synchronize()
@@ -354,8 +354,8 @@ def main():
     import paper_2605_13736_amd as mds
     import synth
 
-    cfg = synth.CONFIGS[1]
-    prob = synth.config_problem(1)
+    cfg = synth.CONFIGS[synth.OPF_N4096]
+    prob = synth.config_problem(synth.OPF_N4096)
     N = cfg["n_d"] + cfg["m"]
     log(f"workload N={N} n_s={cfg['n_s']} nnz={len(prob['v'])}")
     S = mds.solver_for(prob, nb=args.nb)

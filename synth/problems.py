@@ -24,11 +24,13 @@ from __future__ import annotations
 
 import numpy as np
 
-# named workloads: (n_d, n_s, m, nnz per row of J_s)
+# named workloads: (n_d, n_s, m, nnz per row of J_s); the key also seeds the
+# workload's random stream
+IPM_N192, OPF_N4096, LARGE_N16384 = 0, 1, 2
 CONFIGS = {
-    0: dict(n_d=64, n_s=2000, m=128, r=4),        # whole FP64 IPM, N = 192
-    1: dict(n_d=1024, n_s=200000, m=3072, r=6),   # OPF-scale step, N = 4096
-    2: dict(n_d=4096, n_s=1000000, m=12288, r=8), # large condensed system, N = 16384
+    IPM_N192: dict(n_d=64, n_s=2000, m=128, r=4),            # whole FP64 IPM, N = 192
+    OPF_N4096: dict(n_d=1024, n_s=200000, m=3072, r=6),      # OPF-scale step, N = 4096
+    LARGE_N16384: dict(n_d=4096, n_s=1000000, m=12288, r=8), # large condensed system
 }
 
 

@@ -35,7 +35,7 @@ def say(msg):
 
 @pytest.fixture(scope="module")
 def c2():
-    prob = synth.config_problem(2)
+    prob = synth.config_problem(synth.LARGE_N16384)
     st = synth.kkt_state(prob, 2)
     return dict(prob=prob, st=st, P=oracle.Problem(prob))
 

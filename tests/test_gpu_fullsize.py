@@ -26,7 +26,7 @@ def say(msg):
 
 @pytest.fixture(scope="module")
 def big():
-    prob = synth.config_problem(1)
+    prob = synth.config_problem(synth.OPF_N4096)
     it = synth.interior_iterate(prob, 0)
     P = oracle.Problem(prob)
     sig, rx, ry = oracle.sigma_rhs(P, it["x"], it["y"], it["zl"], it["zu"], it["mu"])

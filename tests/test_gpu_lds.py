@@ -126,7 +126,7 @@ def test_lds_ipm_matches_oracle(variant):
     """Whole IPM on the N = 192 workload (and a nonconvex variant whose
     correction loop fires): status, iterations, per-iteration inertia,
     trials and backtracks identical to the oracle's."""
-    prob = (synth.config_problem(0) if variant == "workload"
+    prob = (synth.config_problem(synth.IPM_N192) if variant == "workload"
             else synth.make_problem(64, 2000, 128, 4, cfg=0, p=1, s_scale=6.0))
     say(f"lds IPM N=192 {variant}")
     r_o = oracle.ipm(oracle.Problem(prob))

@@ -100,7 +100,7 @@ def test_mixed_factor_reconstructs_equilibrated_matrix(prec):
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16", "bf16x3"])
 def test_mixed_ipm_converges_to_oracle_solution(prec):
-    prob = synth.config_problem(0)
+    prob = synth.config_problem(synth.IPM_N192)
     say(f"mixed ipm N=192 {prec}")
     r_o = oracle.ipm(oracle.Problem(prob))
     S = mds.solver_for(prob, precision=prec)

@@ -67,7 +67,7 @@ def test_mlp_gradient_and_adam_match_reference():
 
 
 def test_warm_started_ipm_matches_oracle():
-    prob = synth.config_problem(0)
+    prob = synth.config_problem(synth.IPM_N192)
     say("warm-started ipm N=192")
     P = oracle.Problem(prob)
     cold = oracle.ipm(P)
@@ -90,7 +90,7 @@ def test_warm_started_ipm_matches_oracle():
 
 
 def test_learned_warm_start_end_to_end():
-    base = synth.config_problem(0)
+    base = synth.config_problem(synth.IPM_N192)
     say("learned warm start: 48 training problems, 6 held out")
     train = [synth.family_member(base, p) for p in range(48)]
     held = [synth.family_member(base, 10 ** 6 + p) for p in range(6)]
@@ -114,7 +114,7 @@ def test_learned_warm_start_saves_iterations():
     # 1024 training solves of the N = 192 family, 16 held-out problems: the
     # learned start (two GELU layers plus the linear skip path, trained on
     # input-noised minibatches) needs fewer IPM iterations than the cold start
-    base = synth.config_problem(0)
+    base = synth.config_problem(synth.IPM_N192)
     say("learned warm start gain: 1024 training problems, 16 held out")
     train = [synth.family_member(base, p) for p in range(1024)]
     held = [synth.family_member(base, 10 ** 6 + p) for p in range(16)]

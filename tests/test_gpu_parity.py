@@ -264,7 +264,7 @@ def _ipm_compare(prob, nb=0, rows_equal=True):
 
 def test_ipm_config0_matches_oracle():
     say("ipm N=192 workload")
-    _ipm_compare(synth.config_problem(0))
+    _ipm_compare(synth.config_problem(synth.IPM_N192))
 
 
 def test_ipm_nonconvex_correction_fires():

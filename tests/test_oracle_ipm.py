@@ -116,7 +116,7 @@ def _kkt_certificate(prob, r, tol):
 
 
 def test_config0_ipm_certificate_and_decoupled_variables():
-    prob = synth.config_problem(0)
+    prob = synth.config_problem(synth.IPM_N192)
     r = oracle.ipm(oracle.Problem(prob))
     assert r["status"] == "converged"
     assert r["iters"] < 200
@@ -219,7 +219,7 @@ def test_rhs_is_minus_barrier_lagrangian_gradient():
 
 
 def test_theta_zero_at_generating_point():
-    prob = synth.config_problem(0)
+    prob = synth.config_problem(synth.IPM_N192)
     P = oracle.Problem(prob)
     assert oracle.theta(P, prob["x0"]) <= 1e-12 * prob["m"]
 

@@ -74,7 +74,7 @@ def test_adam_first_step_is_signed_lr():
 
 
 def test_oracle_warm_start_from_solution_converges_to_it():
-    prob = synth.config_problem(0)
+    prob = synth.config_problem(synth.IPM_N192)
     P = oracle.Problem(prob)
     cold = oracle.ipm(P)
     nd = prob["n_d"]
@@ -136,7 +136,7 @@ def test_oracle_warm_start_multipliers_carry_dual_residual():
 def test_oracle_warm_start_from_solution_saves_iterations():
     # from the converged primal-dual point with a small barrier parameter the
     # near-stationary start needs several iterations fewer than the cold start
-    prob = synth.config_problem(0)
+    prob = synth.config_problem(synth.IPM_N192)
     P = oracle.Problem(prob)
     cold = oracle.ipm(P)
     nd = prob["n_d"]
