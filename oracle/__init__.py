@@ -41,13 +41,14 @@ class OrqProblem(C.Structure):
     _fields_ = [("n_d", C.c_int32), ("n_s", C.c_int32), ("m", C.c_int32),
                 ("H", _dp), ("c", _dp), ("w", _dp), ("g", _dp), ("Jd", _dp),
                 ("rp", _ip), ("ci", _ip), ("v", _dp), ("b", _dp),
-                ("xl", _dp), ("xu", _dp)]
+                ("xl", _dp), ("xu", _dp), ("m_I", C.c_int32), ("hl", _dp), ("hu", _dp)]
 
 
 class OrFactor(C.Structure):
     _fields_ = [("N", C.c_int32), ("dw", C.c_double), ("dc", C.c_double),
                 ("L", _dp), ("dd", _dp), ("ds", _dp), ("ipiv", _ip), ("inv_d", _dp),
-                ("inertia", C.c_int32 * 3), ("info", C.c_int32), ("trials", C.c_int32)]
+                ("inertia", C.c_int32 * 3), ("info", C.c_int32), ("trials", C.c_int32),
+                ("dcv", _dp), ("sig_h", _dp)]
 
 
 class OrIpmOpts(C.Structure):
@@ -83,6 +84,15 @@ def lib():
                                     _dp, _dp, _dp]
         L.or_kkt_norm_inf.argtypes = [P, _dp, _dp, C.c_double, C.c_double]
         L.or_kkt_norm_inf.restype = C.c_double
+        L.or_kkt_matvec_dcv.argtypes = [P, _dp, _dp, C.c_double, C.c_double, _dp, _dp, _dp,
+                                        _dp, _dp, _dp, _dp]
+        L.or_kkt_norm_inf_dcv.argtypes = [P, _dp, _dp, C.c_double, C.c_double, _dp]
+        L.or_kkt_norm_inf_dcv.restype = C.c_double
+        L.or_ineq_dcv.argtypes = [P, _dp, C.c_double, _dp]
+        L.or_newton_direction.argtypes = [P, _dp, _dp, _dp, _dp, C.c_double, C.c_int32, _dp,
+                                          _dp, _dp, _dp]
+        L.or_newton_direction.restype = C.c_int
+        L.or_factor_set_slack.argtypes = [F, _dp]
         L.or_factor_new.argtypes = [P]
         L.or_factor_new.restype = F
         L.or_factor_free.argtypes = [F]
@@ -142,11 +152,17 @@ class Problem:
         self.b = _f64(p["b"])
         self.xl = _f64(p["xl"])
         self.xu = _f64(p["xu"])
+        # inequality rows (eq. (ineq)): the last m_I rows, bounds hl <= J x <= hu
+        self.m_I = int(p.get("m_I", 0))
+        self.hl = _f64(p.get("hl", np.zeros(0)))
+        self.hu = _f64(p.get("hu", np.zeros(0)))
+        assert len(self.hl) == len(self.hu) == self.m_I <= self.m
         self._keep = [np.zeros(1)]
         self.s = OrqProblem(self.n_d, self.n_s, self.m, *[_d(self._nz(a)) for a in (
             self.H, self.c, self.w, self.g, self.Jd)], _i(self._nzi(self.rp)),
             _i(self._nzi(self.ci)), _d(self._nz(self.v)), _d(self._nz(self.b)),
-            _d(self._nz(self.xl)), _d(self._nz(self.xu)))
+            _d(self._nz(self.xl)), _d(self._nz(self.xu)), self.m_I, _d(self._nz(self.hl)),
+            _d(self._nz(self.hu)))
 
     def _nz(self, a):
         if a.size == 0:
@@ -163,6 +179,11 @@ class Problem:
     @property
     def N(self):
         return self.n_d + self.m
+
+    @property
+    def nx(self):
+        """Length of the IPM's primal vector: variables, then inequality slacks."""
+        return self.n_d + self.n_s + self.m_I
 
     @property
     def ptr(self):
@@ -240,25 +261,51 @@ def ldl_solve(L, ipiv, dd, ds, b):
     return x, st
 
 
-def kkt_matvec(P: Problem, sigma_d, dsbase, dw, dc, dx_d, dx_s, dy):
+def kkt_matvec(P: Problem, sigma_d, dsbase, dw, dc, dx_d, dx_s, dy, dcv=None):
     o_d, o_s, o_y = _buf(P.n_d), _buf(P.n_s), _buf(P.m)
     a = [_f64(v) if len(v) else _buf(1) for v in (sigma_d, dsbase, dx_d, dx_s, dy)]
-    lib().or_kkt_matvec(P.ptr, _d(a[0]), _d(a[1]), dw, dc, _d(a[2]), _d(a[3]), _d(a[4]),
-                        _d(o_d), _d(o_s), _d(o_y))
+    if dcv is None:
+        lib().or_kkt_matvec(P.ptr, _d(a[0]), _d(a[1]), dw, dc, _d(a[2]), _d(a[3]), _d(a[4]),
+                            _d(o_d), _d(o_s), _d(o_y))
+    else:
+        dv = _f64(dcv) if P.m else _buf(1)
+        lib().or_kkt_matvec_dcv(P.ptr, _d(a[0]), _d(a[1]), dw, dc, _d(dv), _d(a[2]), _d(a[3]),
+                                _d(a[4]), _d(o_d), _d(o_s), _d(o_y))
     return o_d[:P.n_d], o_s[:P.n_s], o_y[:P.m]
 
 
-def kkt_norm_inf(P: Problem, sigma_d, dsbase, dw, dc):
+def kkt_norm_inf(P: Problem, sigma_d, dsbase, dw, dc, dcv=None):
     a = [_f64(v) if len(v) else _buf(1) for v in (sigma_d, dsbase)]
-    return lib().or_kkt_norm_inf(P.ptr, _d(a[0]), _d(a[1]), dw, dc)
+    if dcv is None:
+        return lib().or_kkt_norm_inf(P.ptr, _d(a[0]), _d(a[1]), dw, dc)
+    dv = _f64(dcv) if P.m else _buf(1)
+    return lib().or_kkt_norm_inf_dcv(P.ptr, _d(a[0]), _d(a[1]), dw, dc, _d(dv))
+
+
+def ineq_dcv(P: Problem, sig_h, dw):
+    """(4,4) diagonal of the inequality rows: 0 on equality rows, 1/(sig_h + dw)."""
+    out = _buf(P.m)
+    sh = _f64(sig_h) if len(sig_h) else _buf(1)
+    lib().or_ineq_dcv(P.ptr, _d(sh), dw, _d(out))
+    return out[:P.m]
 
 
 class Factor:
     """A factored, regularised Newton system owned by the oracle."""
 
-    def __init__(self, P: Problem):
+    def __init__(self, P: Problem, sig_h=None):
+        """sig_h (m_I, optional): slack barrier diagonal; every condensation
+        then forms the inequality rows' (4,4) block 1 / (sig_h + dw)."""
         self.P = P
         self.p = lib().or_factor_new(P.ptr)
+        if sig_h is not None:
+            self._sh = _f64(sig_h) if len(sig_h) else _buf(1)
+            lib().or_factor_set_slack(self.p, _d(self._sh))
+
+    @property
+    def dcv(self):
+        m = self.P.m
+        return np.ctypeslib.as_array(self.s.dcv, shape=(max(m, 1),))[:m].copy()
 
     def __del__(self):
         try:
@@ -330,12 +377,23 @@ class Factor:
 
 
 def sigma_rhs(P: Problem, x, y, zl, zu, mu):
-    n = P.n_d + P.n_s
+    n = P.nx
     sig, rx, ry = _buf(n), _buf(n), _buf(P.m)
     a = [_f64(v) if len(v) else _buf(1) for v in (x, y, zl, zu)]
     lib().or_sigma_rhs(P.ptr, _d(a[0]), _d(a[1]), _d(a[2]), _d(a[3]), mu, _d(sig), _d(rx),
                        _d(ry))
     return sig[:n], rx[:n], ry[:P.m]
+
+
+def newton_direction(P: Problem, x, y, zl, zu, mu, refine_steps=2):
+    """One IPM iteration's Newton direction at (x, y, zl, zu) (correction loop
+    from delta_w^last = 0).  Returns (status, dx (nx), dy (m), dzl, dzu)."""
+    n = P.nx
+    dx, dzl, dzu, dy = _buf(n), _buf(n), _buf(n), _buf(P.m)
+    a = [_f64(v) if len(v) else _buf(1) for v in (x, y, zl, zu)]
+    st = lib().or_newton_direction(P.ptr, _d(a[0]), _d(a[1]), _d(a[2]), _d(a[3]), mu,
+                                   int(refine_steps), _d(dx), _d(dy), _d(dzl), _d(dzu))
+    return st, dx[:n], dy[:P.m], dzl[:n], dzu[:n]
 
 
 def ftb(v, dv, tau):
@@ -371,7 +429,7 @@ def ipm(P: Problem, tol=1e-8, mu0=0.1, max_iter=200, refine_steps=2, dw_max=1e20
     """Whole filter line-search IPM.  warm: None (cold start) or a dict with
     x_d, y and mu0 (warm start).  Returns dict with x, y, zl, zu, status,
     iters, trace."""
-    n = P.n_d + P.n_s
+    n = P.nx
     x, zl, zu, y = _buf(n), _buf(n), _buf(n), _buf(P.m)
     it = np.zeros(1, dtype=np.int32)
     opts = OrIpmOpts(tol, mu0, max_iter, refine_steps, dw_max)

@@ -275,6 +275,13 @@ int or_ldl_solve(int32_t N, const double *L, const int32_t *ipiv, const double *
 void or_kkt_matvec(const orq_problem *P, const double *sigma_d, const double *dsbase,
                    double dw, double dc, const double *dx_d, const double *dx_s,
                    const double *dy, double *o_d, double *o_s, double *o_y) {
+  or_kkt_matvec_dcv(P, sigma_d, dsbase, dw, dc, NULL, dx_d, dx_s, dy, o_d, o_s, o_y);
+}
+
+void or_kkt_matvec_dcv(const orq_problem *P, const double *sigma_d, const double *dsbase,
+                       double dw, double dc, const double *dcv, const double *dx_d,
+                       const double *dx_s, const double *dy, double *o_d, double *o_s,
+                       double *o_y) {
   const int nd = P->n_d, ns = P->n_s, m = P->m;
   for (int i = 0; i < nd; ++i) {
     double t = 0.0;
@@ -294,12 +301,18 @@ void or_kkt_matvec(const orq_problem *P, const double *sigma_d, const double *ds
     for (int j = 0; j < nd; ++j) t = t + P->Jd[IDX(r, j, m)] * dx_d[j];
     for (int a = P->rp[r]; a < P->rp[r + 1]; ++a) t = t + P->v[a] * dx_s[P->ci[a]];
     t = t - dc * dy[r];
+    if (dcv) t = t - dcv[r] * dy[r];
     o_y[r] = t;
   }
 }
 
 double or_kkt_norm_inf(const orq_problem *P, const double *sigma_d, const double *dsbase,
                        double dw, double dc) {
+  return or_kkt_norm_inf_dcv(P, sigma_d, dsbase, dw, dc, NULL);
+}
+
+double or_kkt_norm_inf_dcv(const orq_problem *P, const double *sigma_d, const double *dsbase,
+                           double dw, double dc, const double *dcv) {
   const int nd = P->n_d, ns = P->n_s, m = P->m;
   double best = 0.0;
   for (int i = 0; i < nd; ++i) {
@@ -318,7 +331,7 @@ double or_kkt_norm_inf(const orq_problem *P, const double *sigma_d, const double
   for (int k = 0; k < ns; ++k) best = fmax(best, fabs(dsbase[k] + dw) + col[k]);
   free(col);
   for (int r = 0; r < m; ++r) {
-    double t = fabs(dc);
+    double t = fabs(dc) + (dcv ? fabs(dcv[r]) : 0.0);
     for (int j = 0; j < nd; ++j) t += fabs(P->Jd[IDX(r, j, m)]);
     for (int a = P->rp[r]; a < P->rp[r + 1]; ++a) t += fabs(P->v[a]);
     best = fmax(best, t);
@@ -340,19 +353,35 @@ or_factor *or_factor_new(const orq_problem *P) {
   F->ds = (double *)malloc(sizeof(double) * (size_t)(N > 0 ? N : 1));
   F->ipiv = (int32_t *)malloc(sizeof(int32_t) * (size_t)(N > 0 ? N : 1));
   F->inv_d = (double *)malloc(sizeof(double) * (size_t)(P->n_s > 0 ? P->n_s : 1));
+  F->dcv = (double *)calloc((size_t)(P->m > 0 ? P->m : 1), sizeof(double));
+  F->sig_h = NULL;
   return F;
 }
 
 void or_factor_free(or_factor *F) {
   if (!F) return;
-  free(F->L); free(F->dd); free(F->ds); free(F->ipiv); free(F->inv_d); free(F);
+  free(F->L); free(F->dd); free(F->ds); free(F->ipiv); free(F->inv_d); free(F->dcv); free(F);
+}
+
+void or_ineq_dcv(const orq_problem *P, const double *sig_h, double dw, double *dcv) {
+  const int mE = P->m - P->m_I;
+  for (int r = 0; r < P->m; ++r) dcv[r] = (r < mE) ? 0.0 : 1.0 / (sig_h[r - mE] + dw);
+}
+
+void or_factor_set_slack(or_factor *F, const double *sig_h) { F->sig_h = sig_h; }
+
+/* the (4,4) diagonal of F's current system, or NULL when it has none */
+static const double *fac_dcv(const orq_problem *P, const or_factor *F) {
+  return (F->sig_h && P->m_I > 0) ? F->dcv : NULL;
 }
 
 void or_factor_once(const orq_problem *P, const double *sigma_d, const double *dsbase,
                     double dw, double dc, or_factor *F) {
   F->dw = dw;
   F->dc = dc;
-  or_condense(P, sigma_d, dsbase, dw, dc, F->L, F->inv_d);
+  /* the slack block's D_h carries the same shift dw as the Hessian blocks */
+  if (F->sig_h && P->m_I > 0) or_ineq_dcv(P, F->sig_h, dw, F->dcv);
+  or_condense_dcv(P, sigma_d, dsbase, dw, dc, fac_dcv(P, F), F->L, F->inv_d);
   F->info = or_bk(F->N, F->L, F->ipiv, F->dd, F->ds, NULL);
   or_inertia(F->N, F->ipiv, F->dd, F->ds, F->inertia);
 }
@@ -410,13 +439,14 @@ int or_newton_refine(const orq_problem *P, const or_factor *F, const double *sig
   double *buf = (double *)malloc(sizeof(double) * (nt * 4 + 1));
   double *res = buf, *cor = buf + nt, *prev = buf + 2 * nt, *kx = buf + 3 * nt;
   or_newton_solve(P, F, r_d, r_s, r_y, dx_d, dx_s, dy);
-  double nK = or_kkt_norm_inf(P, sigma_d, dsbase, F->dw, F->dc);
+  double nK = or_kkt_norm_inf_dcv(P, sigma_d, dsbase, F->dw, F->dc, fac_dcv(P, F));
   double nr = fmax(amax(nd, r_d), fmax(amax(ns, r_s), amax(m, r_y)));
   double eta_prev = INFINITY;
   int steps = 0;
   double eta = 0.0;
   for (;;) {
-    or_kkt_matvec(P, sigma_d, dsbase, F->dw, F->dc, dx_d, dx_s, dy, kx, kx + nd, kx + nd + ns);
+    or_kkt_matvec_dcv(P, sigma_d, dsbase, F->dw, F->dc, fac_dcv(P, F), dx_d, dx_s, dy, kx,
+                      kx + nd, kx + nd + ns);
     for (int i = 0; i < nd; ++i) res[i] = r_d[i] - kx[i];
     for (int i = 0; i < ns; ++i) res[nd + i] = r_s[i] - kx[nd + i];
     for (int i = 0; i < m; ++i) res[nd + ns + i] = r_y[i] - kx[nd + ns + i];
@@ -451,8 +481,22 @@ int or_newton_refine(const orq_problem *P, const or_factor *F, const double *sig
 /* IPM vector quantities (K1/K2).                                           */
 /* ======================================================================== */
 
+/* The primal vector of the IPM: the n variables, then one slack per
+ * inequality row; its bounds are [xl; hl] and [xu; hu]. */
+static int nx_of(const orq_problem *P) { return P->n_d + P->n_s + P->m_I; }
+static double lo_of(const orq_problem *P, int i) {
+  const int n = P->n_d + P->n_s;
+  return (i < n) ? P->xl[i] : P->hl[i - n];
+}
+static double up_of(const orq_problem *P, int i) {
+  const int n = P->n_d + P->n_s;
+  return (i < n) ? P->xu[i] : P->hu[i - n];
+}
+
+/* gradient of f over [x; d]: the objective does not depend on the slacks */
 static void grad_f(const orq_problem *P, const double *x, double *gf) {
-  const int nd = P->n_d, ns = P->n_s;
+  const int nd = P->n_d, ns = P->n_s, n = nd + ns;
+  for (int r = 0; r < P->m_I; ++r) gf[n + r] = 0.0;
   for (int i = 0; i < nd; ++i) {
     double t = 0.0;
     for (int j = 0; j < nd; ++j) {
@@ -464,20 +508,23 @@ static void grad_f(const orq_problem *P, const double *x, double *gf) {
   for (int k = 0; k < ns; ++k) gf[nd + k] = P->w[k] * x[nd + k] + P->g[k];
 }
 
-/* c(x) = J x - b */
+/* c(x, d) = J x - [b; d]: equality rows against b, inequality rows against
+ * their slack d = x[n + r - m_E] */
 static void constr(const orq_problem *P, const double *x, double *cx) {
-  const int nd = P->n_d, m = P->m;
+  const int nd = P->n_d, m = P->m, n = nd + P->n_s, mE = m - P->m_I;
   for (int r = 0; r < m; ++r) {
     double t = 0.0;
     for (int j = 0; j < nd; ++j) t = t + P->Jd[IDX(r, j, m)] * x[j];
     for (int a = P->rp[r]; a < P->rp[r + 1]; ++a) t = t + P->v[a] * x[nd + P->ci[a]];
-    cx[r] = t - P->b[r];
+    cx[r] = t - ((r < mE) ? P->b[r] : x[n + r - mE]);
   }
 }
 
-/* out = J' y */
+/* out = (Jacobian of c)' y over [x; d]: J' y, then -y_h (the slack column
+ * of an inequality row is -1) */
 static void jac_t(const orq_problem *P, const double *y, double *out) {
-  const int nd = P->n_d, ns = P->n_s, m = P->m;
+  const int nd = P->n_d, ns = P->n_s, m = P->m, mE = m - P->m_I;
+  for (int r = 0; r < P->m_I; ++r) out[nd + ns + r] = -y[mE + r];
   for (int j = 0; j < nd; ++j) {
     double t = 0.0;
     for (int r = 0; r < m; ++r) t = t + P->Jd[IDX(r, j, m)] * y[r];
@@ -490,20 +537,21 @@ static void jac_t(const orq_problem *P, const double *y, double *out) {
 
 void or_sigma_rhs(const orq_problem *P, const double *x, const double *y, const double *zl,
                   const double *zu, double mu, double *sigma, double *r_x, double *r_y) {
-  const int n = P->n_d + P->n_s, m = P->m;
-  double *gf = (double *)malloc(sizeof(double) * (size_t)n);
-  double *jy = (double *)malloc(sizeof(double) * (size_t)n);
+  const int n = nx_of(P), m = P->m;
+  double *gf = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+  double *jy = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
   grad_f(P, x, gf);
   jac_t(P, y, jy);
   for (int i = 0; i < n; ++i) {
     double s = 0.0, gb = gf[i] + jy[i];
-    if (isfinite(P->xl[i])) {
-      double sl = x[i] - P->xl[i];
+    const double lo = lo_of(P, i), up = up_of(P, i);
+    if (isfinite(lo)) {
+      double sl = x[i] - lo;
       s = s + zl[i] / sl;
       gb = gb - mu / sl;
     }
-    if (isfinite(P->xu[i])) {
-      double su = P->xu[i] - x[i];
+    if (isfinite(up)) {
+      double su = up - x[i];
       s = s + zu[i] / su;
       gb = gb + mu / su;
     }
@@ -525,10 +573,10 @@ double or_ftb(int64_t n, const double *v, const double *dv, double tau) {
 
 double or_opt_error(const orq_problem *P, const double *x, const double *y,
                     const double *zl, const double *zu, double mu, double parts[6]) {
-  const int n = P->n_d + P->n_s, m = P->m;
+  const int n = nx_of(P), m = P->m;
   const double s_max = 100.0;
-  double *gf = (double *)malloc(sizeof(double) * (size_t)n);
-  double *jy = (double *)malloc(sizeof(double) * (size_t)n);
+  double *gf = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+  double *jy = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
   double *cx = (double *)malloc(sizeof(double) * (size_t)(m > 0 ? m : 1));
   grad_f(P, x, gf);
   jac_t(P, y, jy);
@@ -537,15 +585,16 @@ double or_opt_error(const orq_problem *P, const double *x, const double *y,
   int nz = 0;
   for (int i = 0; i < n; ++i) {
     double r = gf[i] + jy[i];
-    if (isfinite(P->xl[i])) {
+    const double lo = lo_of(P, i), up = up_of(P, i);
+    if (isfinite(lo)) {
       r = r - zl[i];
-      cl = fmax(cl, fabs((x[i] - P->xl[i]) * zl[i] - mu));
+      cl = fmax(cl, fabs((x[i] - lo) * zl[i] - mu));
       z1 += fabs(zl[i]);
       nz++;
     }
-    if (isfinite(P->xu[i])) {
+    if (isfinite(up)) {
       r = r + zu[i];
-      cu = fmax(cu, fabs((P->xu[i] - x[i]) * zu[i] - mu));
+      cu = fmax(cu, fabs((up - x[i]) * zu[i] - mu));
       z1 += fabs(zu[i]);
       nz++;
     }
@@ -581,11 +630,12 @@ double or_objective(const orq_problem *P, const double *x) {
 }
 
 double or_barrier(const orq_problem *P, const double *x, double mu) {
-  const int n = P->n_d + P->n_s;
+  const int n = nx_of(P);
   double lg = 0.0;
   for (int i = 0; i < n; ++i) {
-    if (isfinite(P->xl[i])) lg = lg + log(x[i] - P->xl[i]);
-    if (isfinite(P->xu[i])) lg = lg + log(P->xu[i] - x[i]);
+    const double lo = lo_of(P, i), up = up_of(P, i);
+    if (isfinite(lo)) lg = lg + log(x[i] - lo);
+    if (isfinite(up)) lg = lg + log(up - x[i]);
   }
   return or_objective(P, x) - mu * lg;
 }
@@ -615,9 +665,12 @@ typedef struct { double th, ph; } fentry;
  * the bound can carry (stationarity of the Lagrangian asks z_l - z_u = r):
  * r_i > 0 is added to z_l,i when l_i is finite, -r_i > 0 to z_u,i when u_i is
  * finite. */
+static void push_inside(double l, double u, double *xi);
+static void init_slacks(const orq_problem *P, double *x);
+
 static void warm_point(const orq_problem *P, const double *xd0, const double *y0, double mu0,
                        double *x, double *y, double *zl, double *zu) {
-  const int nd = P->n_d, ns = P->n_s, m = P->m, n = nd + ns;
+  const int nd = P->n_d, ns = P->n_s, m = P->m, n = nd + ns, nx = nx_of(P);
   const double kappa1 = 1e-2, kappa2 = 1e-2;
   double *jty = (double *)calloc((size_t)(ns > 0 ? ns : 1), sizeof(double));
   /* J_s' y, accumulated over rows in ascending order for every column */
@@ -645,14 +698,21 @@ static void warm_point(const orq_problem *P, const double *xd0, const double *y0
     zl[i] = hl ? mu0 / (xi - l) : 0.0;
     zu[i] = hu ? mu0 / (u - xi) : 0.0;
   }
-  double *gf = (double *)calloc((size_t)(n > 0 ? n : 1), sizeof(double));
-  double *jt = (double *)calloc((size_t)(n > 0 ? n : 1), sizeof(double));
+  /* slacks: the rows' values pushed inside their bounds, centred multipliers */
+  init_slacks(P, x);
+  for (int i = n; i < nx; ++i) {
+    const double l = lo_of(P, i), u = up_of(P, i);
+    zl[i] = isfinite(l) ? mu0 / (x[i] - l) : 0.0;
+    zu[i] = isfinite(u) ? mu0 / (u - x[i]) : 0.0;
+  }
+  double *gf = (double *)calloc((size_t)(nx > 0 ? nx : 1), sizeof(double));
+  double *jt = (double *)calloc((size_t)(nx > 0 ? nx : 1), sizeof(double));
   grad_f(P, x, gf);
   jac_t(P, y0, jt);
-  for (int i = 0; i < n; ++i) {
+  for (int i = 0; i < nx; ++i) {
     const double r = gf[i] + jt[i];
-    if (r > 0.0 && isfinite(P->xl[i])) zl[i] = zl[i] + r;
-    if (r < 0.0 && isfinite(P->xu[i])) zu[i] = zu[i] - r;
+    if (r > 0.0 && isfinite(lo_of(P, i))) zl[i] = zl[i] + r;
+    if (r < 0.0 && isfinite(up_of(P, i))) zu[i] = zu[i] - r;
   }
   for (int r = 0; r < m; ++r) y[r] = y0[r];
   free(gf);
@@ -675,34 +735,111 @@ int or_ipm_warm(const orq_problem *P, const or_ipm_opts *o, const double *xd0, c
   return ipm_from(P, o, xd0, y0, mu0, x, y, zl, zu, iters, trace);
 }
 
+/* x pushed into the interior of [l, u] (Waechter & Biegler's kappa_1 = kappa_2
+ * = 1e-2 rule; infinite bounds impose nothing) */
+static void push_inside(double l, double u, double *xi) {
+  const double kappa1 = 1e-2, kappa2 = 1e-2;
+  const int hl = isfinite(l), hu = isfinite(u);
+  if (hl && hu) {
+    double pl = fmin(kappa1 * fmax(1.0, fabs(l)), kappa2 * (u - l));
+    double pu = fmin(kappa1 * fmax(1.0, fabs(u)), kappa2 * (u - l));
+    *xi = fmin(fmax(*xi, l + pl), u - pu);
+  } else if (hl) {
+    *xi = fmax(*xi, l + kappa1 * fmax(1.0, fabs(l)));
+  } else if (hu) {
+    *xi = fmin(*xi, u - kappa1 * fmax(1.0, fabs(u)));
+  }
+}
+
+/* slack of each inequality row: its value (J x)_r at the start, pushed
+ * inside [hl_r, hu_r] */
+static void init_slacks(const orq_problem *P, double *x) {
+  const int nd = P->n_d, m = P->m, n = nd + P->n_s, mE = m - P->m_I;
+  for (int r = mE; r < m; ++r) {
+    double t = 0.0;
+    for (int j = 0; j < nd; ++j) t = t + P->Jd[IDX(r, j, m)] * x[j];
+    for (int a = P->rp[r]; a < P->rp[r + 1]; ++a) t = t + P->v[a] * x[nd + P->ci[a]];
+    push_inside(P->hl[r - mE], P->hu[r - mE], &t);
+    x[n + r - mE] = t;
+  }
+}
+
+/* The Newton direction for the factored system F (Sec. 2.1, eq. (linsys4x4)
+ * with the slack step eliminated, then Sec. 2.2's condensed solve):
+ *  - the inequality rows' right-hand side gains D_h^{-1} r_d, r_d being the
+ *    slacks' part of r_x (ry2 is scratch of m entries);
+ *  - [dx; dy] from the condensed solve refined on the full system;
+ *  - the slack step from its row D_h dd - dy_h = r_d: dd = D_h^{-1}(r_d + dy_h);
+ *  - the bound-multiplier steps from the linearised complementarity
+ *    (x - l) dzl + zl dx = mu - (x - l) zl and (u - x) dzu - zu dx = mu - (u - x) zu. */
+static void step_direction(const orq_problem *P, const or_factor *F, const double *x,
+                           const double *zl, const double *zu, double mu, const double *sig,
+                           const double *dsb, const double *rx, const double *ry,
+                           int refine_steps, double *ry2, double *dx, double *dy, double *dzl,
+                           double *dzu) {
+  const int nd = P->n_d, m = P->m, n = nx_of(P), nv = nd + P->n_s, mE = m - P->m_I;
+  for (int r = 0; r < m; ++r) ry2[r] = ry[r];
+  for (int r = mE; r < m; ++r) ry2[r] = ry[r] + F->dcv[r] * rx[nv + r - mE];
+  double eta = 0.0;
+  or_newton_refine(P, F, sig, dsb, rx, rx + nd, ry2, dx, dx + nd, dy, refine_steps, 1e-14, &eta);
+  for (int r = mE; r < m; ++r) dx[nv + r - mE] = F->dcv[r] * (rx[nv + r - mE] + dy[r]);
+  for (int i = 0; i < n; ++i) {
+    const double lo = lo_of(P, i), up = up_of(P, i);
+    dzl[i] = 0.0; dzu[i] = 0.0;
+    if (isfinite(lo)) {
+      double sl = x[i] - lo;
+      dzl[i] = mu / sl - zl[i] - (zl[i] / sl) * dx[i];
+    }
+    if (isfinite(up)) {
+      double su = up - x[i];
+      dzu[i] = mu / su - zu[i] + (zu[i] / su) * dx[i];
+    }
+  }
+}
+
+int or_newton_direction(const orq_problem *P, const double *x, const double *y, const double *zl,
+                        const double *zu, double mu, int32_t refine_steps, double *dx,
+                        double *dy, double *dzl, double *dzu) {
+  const int nd = P->n_d, ns = P->n_s, m = P->m, n = nx_of(P);
+  const size_t nb = (size_t)(n > 0 ? n : 1), mb = (size_t)(m > 0 ? m : 1);
+  double *sig = (double *)malloc(sizeof(double) * nb);
+  double *rx = (double *)malloc(sizeof(double) * nb);
+  double *ry = (double *)malloc(sizeof(double) * mb);
+  double *ry2 = (double *)malloc(sizeof(double) * mb);
+  double *dsb = (double *)malloc(sizeof(double) * (size_t)(ns > 0 ? ns : 1));
+  or_factor *F = or_factor_new(P);
+  or_factor_set_slack(F, P->m_I > 0 ? sig + nd + ns : NULL);
+  or_sigma_rhs(P, x, y, zl, zu, mu, sig, rx, ry);
+  for (int k = 0; k < ns; ++k) dsb[k] = P->w[k] + sig[nd + k];
+  double dw_last = 0.0;
+  const int st = or_factor_inertia(P, sig, dsb, mu, &dw_last, 1e20, F);
+  if (st == 0)
+    step_direction(P, F, x, zl, zu, mu, sig, dsb, rx, ry, refine_steps, ry2, dx, dy, dzl, dzu);
+  or_factor_free(F);
+  free(sig); free(rx); free(ry); free(ry2); free(dsb);
+  return st;
+}
+
 static int ipm_from(const orq_problem *P, const or_ipm_opts *o, const double *xd0,
                     const double *y0, double mu0_warm, double *x, double *y, double *zl,
                     double *zu, int32_t *iters, or_ipm_trace *trace) {
-  const int nd = P->n_d, ns = P->n_s, m = P->m, n = nd + ns;
+  const int nd = P->n_d, ns = P->n_s, m = P->m, n = nx_of(P), nv = nd + ns;
   /* Waechter & Biegler (2006) defaults */
   const double tau_min = 0.99, kappa_eps = 10.0, kappa_mu = 0.2, theta_mu = 1.5;
   const double kappa_sigma = 1e10, gamma_theta = 1e-5, gamma_phi = 1e-8, delta = 1.0;
   const double s_theta = 1.1, s_phi = 2.3, eta_phi = 1e-8, gamma_alpha = 0.05;
-  const double kappa1 = 1e-2, kappa2 = 1e-2;
   int status = 6;
 
-  /* start point: x = 0 pushed into the interior of its bounds */
+  /* start point: x = 0 pushed into the interior of its bounds, each slack
+   * its row's value pushed inside the row's bounds, y = 0, z = 1 */
   for (int i = 0; i < n; ++i) {
-    double l = P->xl[i], u = P->xu[i], xi = 0.0;
-    int hl = isfinite(l), hu = isfinite(u);
-    if (hl && hu) {
-      double pl = fmin(kappa1 * fmax(1.0, fabs(l)), kappa2 * (u - l));
-      double pu = fmin(kappa1 * fmax(1.0, fabs(u)), kappa2 * (u - l));
-      xi = fmin(fmax(xi, l + pl), u - pu);
-    } else if (hl) {
-      xi = fmax(xi, l + kappa1 * fmax(1.0, fabs(l)));
-    } else if (hu) {
-      xi = fmin(xi, u - kappa1 * fmax(1.0, fabs(u)));
-    }
+    double l = lo_of(P, i), u = up_of(P, i), xi = 0.0;
+    push_inside(l, u, &xi);
     x[i] = xi;
-    zl[i] = hl ? 1.0 : 0.0;
-    zu[i] = hu ? 1.0 : 0.0;
+    zl[i] = isfinite(l) ? 1.0 : 0.0;
+    zu[i] = isfinite(u) ? 1.0 : 0.0;
   }
+  init_slacks(P, x);
   for (int r = 0; r < m; ++r) y[r] = 0.0;
   double mu = o->mu0;
   if (xd0) {
@@ -715,17 +852,21 @@ static int ipm_from(const orq_problem *P, const or_ipm_opts *o, const double *xd
   fentry *filt = (fentry *)malloc(sizeof(fentry) * (size_t)(o->max_iter + 1));
   int nf = 0;
 
-  double *sig = (double *)malloc(sizeof(double) * (size_t)n);
-  double *rx = (double *)malloc(sizeof(double) * (size_t)n);
-  double *ry = (double *)malloc(sizeof(double) * (size_t)(m > 0 ? m : 1));
+  const size_t nb = (size_t)(n > 0 ? n : 1), mb = (size_t)(m > 0 ? m : 1);
+  double *sig = (double *)malloc(sizeof(double) * nb);
+  double *rx = (double *)malloc(sizeof(double) * nb);
+  double *ry = (double *)malloc(sizeof(double) * mb);
+  double *ry2 = (double *)malloc(sizeof(double) * mb);
   double *dsb = (double *)malloc(sizeof(double) * (size_t)(ns > 0 ? ns : 1));
-  double *dx = (double *)malloc(sizeof(double) * (size_t)n);
-  double *dy = (double *)malloc(sizeof(double) * (size_t)(m > 0 ? m : 1));
-  double *dzl = (double *)malloc(sizeof(double) * (size_t)n);
-  double *dzu = (double *)malloc(sizeof(double) * (size_t)n);
-  double *xt = (double *)malloc(sizeof(double) * (size_t)n);
-  double *gf = (double *)malloc(sizeof(double) * (size_t)n);
+  double *dx = (double *)malloc(sizeof(double) * nb);
+  double *dy = (double *)malloc(sizeof(double) * mb);
+  double *dzl = (double *)malloc(sizeof(double) * nb);
+  double *dzu = (double *)malloc(sizeof(double) * nb);
+  double *xt = (double *)malloc(sizeof(double) * nb);
+  double *gf = (double *)malloc(sizeof(double) * nb);
   or_factor *F = or_factor_new(P);
+  /* the slack barrier diagonal Sigma_h sits after the variables' in sig */
+  or_factor_set_slack(F, P->m_I > 0 ? sig + nv : NULL);
 
   int it = 0;
   for (it = 0; it < o->max_iter; ++it) {
@@ -750,30 +891,18 @@ static int ipm_from(const orq_problem *P, const or_ipm_opts *o, const double *xd
       memcpy(trace[it].inertia, F->inertia, sizeof(F->inertia));
     }
     if (fst != 0) { status = 2; break; }
-    double eta = 0.0;
-    or_newton_refine(P, F, sig, dsb, rx, rx + nd, ry, dx, dx + nd, dy, o->refine_steps, 1e-14, &eta);
-    /* dual directions from the linearised complementarity */
-    for (int i = 0; i < n; ++i) {
-      dzl[i] = 0.0; dzu[i] = 0.0;
-      if (isfinite(P->xl[i])) {
-        double sl = x[i] - P->xl[i];
-        dzl[i] = mu / sl - zl[i] - (zl[i] / sl) * dx[i];
-      }
-      if (isfinite(P->xu[i])) {
-        double su = P->xu[i] - x[i];
-        dzu[i] = mu / su - zu[i] + (zu[i] / su) * dx[i];
-      }
-    }
+    step_direction(P, F, x, zl, zu, mu, sig, dsb, rx, ry, o->refine_steps, ry2, dx, dy, dzl, dzu);
     /* fraction to the boundary for slacks and bound multipliers */
     double a_pr = 1.0, a_du = 1.0;
     for (int i = 0; i < n; ++i) {
-      if (isfinite(P->xl[i])) {
-        double sl = x[i] - P->xl[i];
+      const double lo = lo_of(P, i), up = up_of(P, i);
+      if (isfinite(lo)) {
+        double sl = x[i] - lo;
         if (dx[i] < 0.0) a_pr = fmin(a_pr, -tau * sl / dx[i]);
         if (dzl[i] < 0.0) a_du = fmin(a_du, -tau * zl[i] / dzl[i]);
       }
-      if (isfinite(P->xu[i])) {
-        double su = P->xu[i] - x[i];
+      if (isfinite(up)) {
+        double su = up - x[i];
         if (-dx[i] < 0.0) a_pr = fmin(a_pr, -tau * su / (-dx[i]));
         if (dzu[i] < 0.0) a_du = fmin(a_du, -tau * zu[i] / dzu[i]);
       }
@@ -784,8 +913,9 @@ static int ipm_from(const orq_problem *P, const or_ipm_opts *o, const double *xd
     double gphi = 0.0;
     for (int i = 0; i < n; ++i) {
       double gi = gf[i];
-      if (isfinite(P->xl[i])) gi = gi - mu / (x[i] - P->xl[i]);
-      if (isfinite(P->xu[i])) gi = gi + mu / (P->xu[i] - x[i]);
+      const double lo = lo_of(P, i), up = up_of(P, i);
+      if (isfinite(lo)) gi = gi - mu / (x[i] - lo);
+      if (isfinite(up)) gi = gi + mu / (up - x[i]);
       gphi = gphi + gi * dx[i];
     }
     double amin;
@@ -835,19 +965,20 @@ static int ipm_from(const orq_problem *P, const or_ipm_opts *o, const double *xd
     for (int i = 0; i < n; ++i) x[i] = xt[i];
     for (int r = 0; r < m; ++r) y[r] = y[r] + alpha * dy[r];
     for (int i = 0; i < n; ++i) {
-      if (isfinite(P->xl[i])) {
-        double z = zl[i] + a_du * dzl[i], sl = x[i] - P->xl[i];
+      const double lo = lo_of(P, i), up = up_of(P, i);
+      if (isfinite(lo)) {
+        double z = zl[i] + a_du * dzl[i], sl = x[i] - lo;
         zl[i] = fmax(fmin(z, kappa_sigma * mu / sl), mu / (kappa_sigma * sl));
       }
-      if (isfinite(P->xu[i])) {
-        double z = zu[i] + a_du * dzu[i], su = P->xu[i] - x[i];
+      if (isfinite(up)) {
+        double z = zu[i] + a_du * dzu[i], su = up - x[i];
         zu[i] = fmax(fmin(z, kappa_sigma * mu / su), mu / (kappa_sigma * su));
       }
     }
   }
   *iters = it;
   or_factor_free(F);
-  free(filt); free(sig); free(rx); free(ry); free(dsb); free(dx); free(dy);
+  free(filt); free(sig); free(rx); free(ry); free(ry2); free(dsb); free(dx); free(dy);
   free(dzl); free(dzu); free(xt); free(gf);
   return status;
 }

@@ -25,8 +25,14 @@ extern "C" {
 
 /* Quadratic MDS test problem (the objective/constraint class of Sec. 2, with
  * constant Hessian blocks):  min 0.5 x_d'H x_d + c'x_d + sum(0.5 w x_s^2 + g x_s)
- * s.t. J_d x_d + J_s x_s = b,  xl <= x <= xu  (x = [x_d; x_s], bounds may be
- * +-INFINITY). */
+ * s.t. (J x)_r = b_r for the first m_E = m - m_I rows (eq. (coneq)),
+ *      hl_r <= (J x)_r <= hu_r for the last m_I rows (eq. (ineq)),
+ *      xl <= x <= xu  (x = [x_d; x_s], J = [J_d J_s], bounds may be +-INFINITY).
+ *
+ * The IPM works on the slack form of Sec. 2.1's reformulation: every
+ * inequality row becomes (J x)_r - d_r = 0 with a slack d_r bounded by
+ * [hl_r, hu_r].  Its primal vector has nx = n + m_I entries (x, then d), and
+ * so do its bound multipliers. */
 typedef struct {
   int32_t n_d, n_s, m;
   const double *H;      /* n_d x n_d, symmetric                     */
@@ -40,6 +46,9 @@ typedef struct {
   const double *b;      /* m                                         */
   const double *xl;     /* n                                         */
   const double *xu;     /* n                                         */
+  int32_t m_I;          /* inequality rows (the last m_I of m)       */
+  const double *hl;     /* m_I, may be -INFINITY                     */
+  const double *hu;     /* m_I, may be +INFINITY                     */
 } orq_problem;
 
 /* ---- condensation (Sec. 2.2, eq. (compressed), 2x2-block form) ---------- */
@@ -71,9 +80,17 @@ void or_inertia(int32_t N, const int32_t *ipiv, const double *dd, const double *
 int or_ldl_solve(int32_t N, const double *L, const int32_t *ipiv, const double *dd,
                  const double *ds, double *b);
 
-/* ---- full (uncondensed) KKT operator (eq. (linsys4x4), 2x2-block form) --- */
+/* ---- full (uncondensed) KKT operator (eq. (linsys4x4)) ------------------- */
 /* out = K * [dx_d; dx_s; dy] with
- * K = [[H+diag(sigma_d)+dw I, 0, Jd'], [0, diag(dsbase)+dw I, Js'], [Jd, Js, -dc I]] */
+ * K = [[H+diag(sigma_d)+dw I, 0, Jd'], [0, diag(dsbase)+dw I, Js'],
+ *      [Jd, Js, -dc I - diag(dcv)]]
+ * (dcv: the (4,4) block -D_h^{-1} of the inequality rows, NULL for none). */
+void or_kkt_matvec_dcv(const orq_problem *P, const double *sigma_d, const double *dsbase,
+                       double dw, double dc, const double *dcv, const double *dx_d,
+                       const double *dx_s, const double *dy, double *o_d, double *o_s,
+                       double *o_y);
+double or_kkt_norm_inf_dcv(const orq_problem *P, const double *sigma_d, const double *dsbase,
+                           double dw, double dc, const double *dcv);
 void or_kkt_matvec(const orq_problem *P, const double *sigma_d, const double *dsbase,
                    double dw, double dc, const double *dx_d, const double *dx_s,
                    const double *dy, double *o_d, double *o_s, double *o_y);
@@ -91,7 +108,17 @@ typedef struct {
   int32_t inertia[3];
   int32_t info;
   int32_t trials;   /* factorizations done by the last correction loop */
+  double *dcv;      /* m: (4,4) diagonal of the current system (0 on equality rows) */
+  const double *sig_h; /* m_I: slack barrier diagonal, or NULL (no (4,4) block) */
 } or_factor;
+
+/* The (4,4) block of eq. (linsys4x4) once the slack step is eliminated
+ * (Sec. 2.1 with the slack reformulation): D_h = Sigma_h + dw on the
+ * inequality rows; dcv[r] = 1 / D_h for r >= m_E, 0 for equality rows. */
+void or_ineq_dcv(const orq_problem *P, const double *sig_h, double dw, double *dcv);
+/* Attach (or detach with NULL) the slack barrier diagonal that every later
+ * condensation of F turns into its (4,4) block. */
+void or_factor_set_slack(or_factor *F, const double *sig_h);
 
 or_factor *or_factor_new(const orq_problem *P);
 void or_factor_free(or_factor *F);
@@ -116,8 +143,10 @@ int or_newton_refine(const orq_problem *P, const or_factor *F, const double *sig
                      int32_t max_steps, double eta_tol, double *eta_out);
 
 /* ---- IPM vector quantities (Sec. 2.1, kernels K1/K2) --------------------- */
-/* Sigma = zl/(x-l) + zu/(u-x); r = -(grad f + J'y - mu/(x-l) + mu/(u-x)); r_y = -(Jx-b).
- * Infinite bounds contribute nothing.  sigma (n), r_x (n), r_y (m). */
+/* Over the primal vector x = [x; d] (nx entries) and its bounds [xl; hl],
+ * [xu; hu]: Sigma = zl/(x-l) + zu/(u-x); r = -(grad L - mu/(x-l) + mu/(u-x))
+ * with grad L = [grad f + J'y; -y_h]; r_y = -c with c = [J_g x - b; J_h x - d].
+ * Infinite bounds contribute nothing.  sigma (nx), r_x (nx), r_y (m). */
 void or_sigma_rhs(const orq_problem *P, const double *x, const double *y, const double *zl,
                   const double *zu, double mu, double *sigma, double *r_x, double *r_y);
 /* Largest alpha in (0,1] with v + alpha dv >= (1-tau) v for all entries with dv < 0. */
@@ -130,6 +159,15 @@ double or_opt_error(const orq_problem *P, const double *x, const double *y,
 double or_objective(const orq_problem *P, const double *x);
 double or_barrier(const orq_problem *P, const double *x, double mu);
 double or_theta(const orq_problem *P, const double *x);
+
+/* Newton direction of the barrier problem at (x, y, zl, zu) exactly as one
+ * IPM iteration computes it: Sigma and rhs, the inertia-correction loop from
+ * delta_w^last = 0, the condensed solve with refine_steps refinement steps,
+ * the slack step and the bound-multiplier steps.  dx, dzl, dzu (nx), dy (m).
+ * Returns the correction loop's status (0, or 2 when it failed). */
+int or_newton_direction(const orq_problem *P, const double *x, const double *y, const double *zl,
+                        const double *zu, double mu, int32_t refine_steps, double *dx,
+                        double *dy, double *dzl, double *dzu);
 
 /* ---- filter line-search IPM (Sec. 2.1; Waechter & Biegler 2006) ---------- */
 typedef struct {
@@ -146,7 +184,8 @@ typedef struct {       /* one row per iteration */
   int32_t trials, backtracks;
 } or_ipm_trace;
 
-/* x (n), y (m), zl, zu (n) are outputs (start point computed inside).
+/* x, zl, zu (nx = n + m_I: variables then slacks) and y (m) are outputs
+ * (start point computed inside).
  * Returns 4 converged, 5 line-search failure, 6 max iterations, 2 inertia
  * failure, 7 non-finite values.  *iters: iterations done.  trace may be NULL
  * or hold max_iter rows. */

@@ -15,10 +15,16 @@ grids, are not available; these draws stand in for them):
 * equality constraints J_d x_d + J_s x_s = b: J_s has r distinct columns per
   row drawn uniformly without replacement (sorted), N(0,1) values; J_d is
   N(0,1)/sqrt(n_d); b = J_s x0_s + J_d x0_d with x0 ~ U[-0.5, 0.5];
-* bounds [-1, 1] on every variable.
+* bounds [-1, 1] on every variable;
+* optional inequality rows (eq. (ineq) of the paper): the last m_I rows of J
+  become hl <= (J x) <= hu around the row value at x0, hl = (J x0) - a,
+  hu = (J x0) + c with a, c ~ U[0.05, 0.5]; a quarter of the rows keep only
+  the lower bound, a quarter only the upper one (so x0 is strictly feasible
+  and some bounds bind at the solution).
 
 Draw order inside one ``SeedSequence([cfg, p])`` stream:
-x0_d, x0_s, Q, lam, G (for U), c, w, g, J_s pattern, J_s values, J_d.
+x0_d, x0_s, Q, lam, G (for U), c, w, g, J_s pattern, J_s values, J_d, and
+then (only when m_I > 0) a, c and the side selector of the inequality rows.
 """
 from __future__ import annotations
 
@@ -62,11 +68,12 @@ def _pattern(rng, m, n_s, r):
 
 
 def make_problem(n_d: int, n_s: int, m: int, r: int, cfg: int = 0, p: int = 0,
-                 h_scale: str = "n_d", s_scale: float = 1.0) -> dict:
+                 h_scale: str = "n_d", s_scale: float = 1.0, m_I: int = 0) -> dict:
     """One seeded problem.  h_scale='n_d' divides Q Q' by n_d (and J_d by
     sqrt(n_d)); '64' uses the literal constant 64 for both.  s_scale widens the
     eigenvalue range of S to U[-s_scale, s_scale] (a more nonconvex variant
-    used to exercise the inertia correction)."""
+    used to exercise the inertia correction).  m_I: number of inequality rows
+    (the last m_I of the m rows)."""
     rng = _rng(cfg, p)
     x0_d = rng.uniform(-0.5, 0.5, n_d)
     x0_s = rng.uniform(-0.5, 0.5, n_s)
@@ -91,11 +98,22 @@ def make_problem(n_d: int, n_s: int, m: int, r: int, cfg: int = 0, p: int = 0,
     bs = np.zeros(m)
     if m and rr:
         bs = (vals.reshape(m, rr) * x0_s[cols]).sum(axis=1)
-    b = bs + (Jd @ x0_d if n_d else 0.0)
+    b = np.asarray(bs + (Jd @ x0_d if n_d else 0.0), dtype=np.float64)
     n = n_d + n_s
+    if not 0 <= m_I <= m:
+        raise ValueError("m_I must lie in [0, m]")
+    hl, hu = np.zeros(0), np.zeros(0)
+    if m_I > 0:
+        lo_w = rng.uniform(0.05, 0.5, m_I)
+        up_w = rng.uniform(0.05, 0.5, m_I)
+        side = rng.integers(0, 4, m_I)   # 0: lower only, 1: upper only, else both
+        hx0 = b[m - m_I:]
+        hl = np.where(side == 1, -np.inf, hx0 - lo_w)
+        hu = np.where(side == 0, np.inf, hx0 + up_w)
     return dict(n_d=n_d, n_s=n_s, m=m, r=rr, H=np.asfortranarray(H), c=c, w=w, g=g,
-                Jd=np.asfortranarray(Jd), rp=rp, ci=ci, v=vals, b=np.asarray(b, dtype=np.float64),
-                xl=-np.ones(n), xu=np.ones(n), x0=np.concatenate([x0_d, x0_s]))
+                Jd=np.asfortranarray(Jd), rp=rp, ci=ci, v=vals, b=b,
+                xl=-np.ones(n), xu=np.ones(n), x0=np.concatenate([x0_d, x0_s]),
+                m_I=m_I, hl=hl, hu=hu)
 
 
 def config_problem(cfg: int, p: int = 0, **kw) -> dict:
