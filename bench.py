@@ -1,21 +1,29 @@
-"""Benchmark of the condensed-KKT Newton step on one MI355X.
+"""Benchmark of the condensed-KKT hot path on one MI355X.
 
-A step is one iteration of the filter line-search IPM on the OPF-scale
-workload (n_d = 1024 dense and n_s = 200000 sparse variables, m = 3072
-equality constraints, condensed size N = 4096, 6 nonzeros per row of J_s,
-seeded synthetic data): optimality test and barrier update, Newton system
-(condense + Bunch-Kaufman factorization with the inertia-correction loop),
-solve with FP64 refinement, fraction to the boundary, filter line search and
-update.  Problem data is resident in HBM before the timed region.
+Headline (the printed `value`): the large condensed system (n_d = 4096,
+n_s = 1000000, m = 12288, condensed N = 16384, 8 nonzeros per row of J_s,
+Sigma_d and D_s drawn log-uniform over 1e-8..1e8 as at the end of a barrier
+run; seeded synthetic data resident in HBM before the timed region).  One
+step is the whole Newton-system path: condense (Sec. 2.2), Bunch-Kaufman
+factorization with the inertia-correction loop (Sec. 2.1, 2.3), solve and
+back-substitution, FP64 iterative refinement on the full system to backward
+error 1e-14.  value = KKT factor+solve TFLOP/s = (N^3/3 per factorization +
+2 N^2 per solve) / wall time of the K timed steps, in FP64.
 
-Printed value: KKT factor+solve throughput in TFLOP/s, counting the nominal
-N^3/3 flops of every factorization performed (correction trials included) and
-2 N^2 per solve, divided by the wall time of the timed steps.
-
-Also reported: a per-kernel roofline for the dominant kernel (HIP events on
-the library stream over the timed region), whole-IPM solves/s on the N = 192
-workload, and the CPU oracle timed on one N = 4096 condense + factor + solve
-(the CPU baseline).
+Beside it, in the same JSON line:
+* `precision_sweep`: the same system with FP32 / split-BF16 / BF16 trailing
+  updates and FP64 GMRES refinement: time, speedup over FP64 at the same
+  backward error, GMRES iterations, and the error against the FP64 solution
+  and against the oracle's stored solution;
+* `opf_n4096`: IPM Newton steps on the OPF-scale problem (N = 4096), their
+  per-kernel breakdown, one whole IPM to E_0 <= 1e-8 (solves/s), and one
+  Newton system per precision;
+* `ipm_solves`: whole IPMs on the N = 192 problem; `batch`: 512 scenario
+  problems in one persistent launch; `warmstart`: the learned warm start;
+* `roofline` for the dominant kernel of the headline step (HIP events on the
+  library's stream), `factor` with the factorization's FP64-MFMA fraction;
+* `cpu_baseline`: the oracle on a bounded sample of the headline workload,
+  on one pinned host core and on all host cores (bit-identical results).
 """
 from __future__ import annotations
 
@@ -30,14 +38,19 @@ sys.path.insert(0, ROOT)
 
 METRIC = "KKT factor+solve TFLOP/s & IPM solves/s: mixed/learned vs FP64, 1e-8 res"
 HBM_PEAK_GBS = 8000.0
+FP64_MFMA_PEAK_TFS = 78.6
+FP32_MFMA_PEAK_TFS = 157.3
 # HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE passes, scaled by
 # the counters of a 256 MiB copy (the profile file gives the commands and the
-# factors); valid for the kernel source as profiled.
+# factors); valid for the kernel source and workload as profiled.
 MEASURED_TRAFFIC = {
-    "k_bk_panel_coop": (2742650.0, "profiles/bk_panel_coop_ipm_newton_step_n4096.md"),
-    "k_bk_trailing": (75934233.0, "profiles/bk_trailing_ipm_newton_step_n4096.md"),
+    ("k_bk_trailing", 16384): (None, "profiles/bk_trailing_kkt_n16384.md"),
+    ("k_bk_trailing", 4096): (75934233.0, "profiles/bk_trailing_ipm_newton_step_n4096.md"),
+    ("k_bk_panel_coop", 4096): (2742650.0, "profiles/bk_panel_coop_ipm_newton_step_n4096.md"),
 }
-FP64_MFMA_PEAK_TFS = 78.6
+KERNEL_OF_CLASS = {"panel_tail": "k_bk_panel_reg", "trailing": "k_bk_trailing",
+                   "solve": "k_trsv_fwd+k_trsv_bwd", "condense": "k_condense_dense",
+                   "permute": "k_std_sweep+k_std_apply"}
 
 
 def log(*a):
@@ -48,12 +61,9 @@ def panel_bytes_per_launch(N, launches_per_factor, adv=None):
     """Algorithmic HBM bytes of one panel launch, averaged over its launches:
     a panel of width w starting at k0 reads its w columns (rows >= k0) once,
     reads one pivot-candidate column per pivot, and writes L and W once:
-    4 * (N - k0) * w * 8 bytes, i.e. 4 * 8 * (N - c) per column c.  Over a
-    whole factorization this is 4 * 8 * N (N + 1) / 2 whatever the widths.
-    When the launches cover only the first columns (a cooperative panel that
-    hands the last rows to another kernel), they cover launches * adv columns
-    (adv = nb - 1 per panel, nominal: a panel ending on a 2x2 pivot takes one
-    more)."""
+    4 * (N - k0) * w * 8 bytes, i.e. 4 * 8 * (N - c) per column c.  When the
+    launches cover only the first columns (a cooperative panel that hands the
+    last rows to another kernel), they cover launches * adv columns."""
     n = max(launches_per_factor, 1)
     K = N if adv is None else min(N, n * adv)
     return 4.0 * 8.0 * (K * N - K * (K - 1) / 2.0) / n
@@ -72,17 +82,274 @@ def trailing_bytes_per_launch(N, w):
     return total / max(cnt, 1)
 
 
-def mixed_section(prob, N, reps=3):
-    """One Newton system of the workload at a seeded interior point, solved
-    to backward error 1e-14 by (a) FP64 factor + classic refinement and (b)
-    FP32 / BF16 trailing updates + FP64 GMRES refinement.  Reports the time
-    of condense + factor + refined solve, nominal TFLOP/s, refinement
-    iterations, and the max-norm error of each solution relative to FP64's."""
+def trailing_flops_per_launch(N, w):
+    """Flops of one trailing update: 2 w per lower entry of the trailing matrix."""
+    total, cnt, k0 = 0.0, 0, 0
+    while k0 + w < N:
+        n = N - (k0 + w)
+        total += (n * (n + 1) / 2) * 2.0 * w
+        cnt += 1
+        k0 += w
+    return total / max(cnt, 1)
+
+
+def host_info():
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        avail = sorted(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = list(range(os.cpu_count() or 1))
+    return dict(nproc=os.cpu_count(), cpus_available=len(avail), model=model), avail
+
+
+# ---------------------------------------------------------------- headline
+def kkt_step_section(args):
+    """The headline: K steps of condense + factor (correction loop) + refined
+    solve of the N = 16384 system in FP64, then K more with per-launch events
+    for the per-class breakdown and the roofline."""
+    import torch
+    import paper_2605_13736_amd as mds
+    import synth
+    prob = synth.config_problem(synth.LARGE_N16384)
+    st = synth.kkt_state(prob, 2)
+    N = prob["n_d"] + prob["m"]
+    S = mds.solver_for(prob, nb=args.nb)
+    info0 = S.info()
+    sd, db = S.dev(st["sigma_d"]), S.dev(st["dsbase"])
+    rd, rs, ry = S.dev(st["r_d"]), S.dev(st["r_s"]), S.dev(st["r_y"])
+    mu = 1e-8  # late barrier parameter (enters only delta_c of a singular M)
+    reg = {}
+
+    def step():
+        nonlocal reg
+        S.condense(sd, db)
+        status, inn, r = S.factor_inertia(mu, reg=dict(delta_w_last=reg.get("delta_w_last", 0.0)))
+        reg = r
+        sol, ri = S.refine(rd, rs, ry, 3, 1e-14)
+        return r["trials"], 1 + ri["steps"], ri, sol, inn
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    facs = solves = 0
+    for _ in range(args.steps):
+        f, s, ri, sol, inn = step()
+        facs += f
+        solves += s
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    value = (facs * N ** 3 / 3.0 + solves * 2.0 * N ** 2) / dt / 1e12
+    log(f"headline: {args.steps} steps in {dt:.3f}s, {facs} factorizations, {solves} solves")
+    x64 = torch.cat(sol).cpu().numpy()
+    # per-class device time with HIP event pairs on the library stream
+    S.set_timing(True)
+    torch.cuda.synchronize()
+    te = time.perf_counter()
+    efacs = 0
+    for _ in range(args.steps):
+        efacs += step()[0]
+    torch.cuda.synchronize()
+    dte = time.perf_counter() - te
+    tim = S.get_timings()
+    S.set_timing(False)
+    log("per-class device time:", json.dumps(tim))
+    out = dict(N=N, dt=dt, facs=facs, solves=solves, value=value, tim=tim, efacs=efacs,
+               dte=dte, info=info0, eta=ri["eta"], inertia=inn, x64=x64)
+    del S
+    torch.cuda.empty_cache()
+    return out, prob, st
+
+
+def roofline_of(tim, efacs, N, nb):
+    """Dominant kernel class of the event region and its roofline figure."""
+    dom = max(tim, key=lambda k: tim[k]["ms"])
+    nlaunch = max(tim[dom]["launches"], 1)
+    avg_s = tim[dom]["ms"] / 1e3 / nlaunch
+    npan = tim["panel"]["launches"] + tim["panel_tail"]["launches"]
+    w = N / max(npan / max(efacs, 1), 1)
+    if dom == "trailing":
+        kernel = "k_bk_trailing"
+        per_launch = trailing_bytes_per_launch(N, w)
+        roof = dict(bound="hbm", achieved=per_launch / avg_s / 1e9, peak=HBM_PEAK_GBS,
+                    unit="GB/s", kernel=kernel, bytes_per_launch=per_launch,
+                    flops_per_launch=trailing_flops_per_launch(N, w))
+    elif dom == "panel":
+        kernel = "k_bk_panel_coop"
+        tail = tim["panel_tail"]["launches"] > 0
+        per_launch = panel_bytes_per_launch(N, tim["panel"]["launches"] / max(efacs, 1),
+                                            adv=max(nb - 1, 1) if tail else None)
+        roof = dict(bound="hbm", achieved=per_launch / avg_s / 1e9, peak=HBM_PEAK_GBS,
+                    unit="GB/s", kernel=kernel, bytes_per_launch=per_launch,
+                    note="bound by the latency of the per-pivot chain; see latency_model")
+    else:
+        kernel = KERNEL_OF_CLASS[dom]
+        per_launch = 2.0 * (N * N / 2.0) * 8.0 if dom == "solve" else 8.0 * N * N
+        roof = dict(bound="hbm", achieved=per_launch / avg_s / 1e9, peak=HBM_PEAK_GBS,
+                    unit="GB/s", kernel=kernel, bytes_per_launch=per_launch)
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    meas = MEASURED_TRAFFIC.get((kernel, N))
+    roof["traffic"] = meas[0] if meas else None
+    if meas:
+        roof["traffic_source"] = meas[1]
+    roof["avg_launch_us"] = avg_s * 1e6
+    roof["launches"] = nlaunch
+    return roof
+
+
+def panel_latency_model(tim, efacs, N, nb):
+    """Microseconds per pivot of the cooperative panel and of its register
+    tail (a latency-bound chain: one or two grid-wide exchanges and one
+    dependent column read per pivot)."""
+    out = {}
+    for cls in ("panel", "panel_tail"):
+        n = tim[cls]["launches"]
+        if n:
+            out[cls] = dict(us_per_launch=tim[cls]["ms"] * 1e3 / n,
+                            us_per_pivot=tim[cls]["ms"] * 1e3 / n / max(nb - 1, 1),
+                            launches_per_factorization=n / max(efacs, 1))
+    return out
+
+
+def precision_sweep(prob, st, N, x64, reps=2):
+    """The headline system in each mixed mode: condense + factor (the
+    correction loop's shifts of the FP64 run are zero here) + GMRES-refined
+    solve to backward error 1e-14 (at most 60 iterations)."""
+    import numpy as np
+    import torch
+    import paper_2605_13736_amd as mds
+    gold = None
+    try:
+        g = json.load(open(os.path.join(ROOT, "tests", "golden", "kkt_n16384.json")))
+        gold = (np.asarray(g["x_index"]), np.asarray(g["x_value"]), g["x_absmax"], g["inertia"])
+    except (OSError, KeyError, ValueError):
+        pass
+    out = {}
+    for prec in ("fp64", "fp32", "bf16x3", "bf16"):
+        S = mds.solver_for(prob, precision=prec)
+        sd, db = S.dev(st["sigma_d"]), S.dev(st["dsbase"])
+        rd, rs, ry = S.dev(st["r_d"]), S.dev(st["r_s"]), S.dev(st["r_y"])
+        steps = 3 if prec == "fp64" else 60
+
+        def once():
+            S.condense(sd, db)
+            _, inn, _ = S.factor_inertia()
+            sol, info = S.refine(rd, rs, ry, steps, 1e-14)
+            return sol, info, inn
+
+        once()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            sol, info, inn = once()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        S.set_timing(True)
+        once()
+        tim = S.get_timings()
+        S.set_timing(False)
+        fac_ms = tim["panel"]["ms"] + tim["panel_tail"]["ms"] + tim["trailing"]["ms"]
+        x = torch.cat(sol).cpu().numpy()
+        rec = dict(ms_condense_factor_refine=dt * 1e3, ms_factor=fac_ms,
+                   ms_trailing=tim["trailing"]["ms"],
+                   ms_panel=tim["panel"]["ms"] + tim["panel_tail"]["ms"],
+                   tflops_nominal=(N ** 3 / 3.0 + 2.0 * N ** 2) / dt / 1e12,
+                   refine_iterations=info["steps"], eta=info["eta"],
+                   inertia=[inn["npos"], inn["nzero"], inn["nneg"]],
+                   rel_err_vs_fp64=float(np.abs(x - x64).max() / np.abs(x64).max()))
+        if gold is not None:
+            rec["rel_err_vs_oracle_sampled"] = float(
+                np.abs(x[gold[0]] - gold[1]).max() / gold[2])
+            rec["inertia_equals_oracle"] = rec["inertia"] == gold[3]
+        out[prec] = rec
+        del S
+        torch.cuda.empty_cache()
+    base = out["fp64"]["ms_condense_factor_refine"]
+    for prec, rec in out.items():
+        rec["speedup_vs_fp64"] = base / rec["ms_condense_factor_refine"]
+        rec["converged_1e-14"] = rec["eta"] <= 1e-14
+    return out
+
+
+# ---------------------------------------------------------------- N = 4096
+def opf_section(steps=10, warmup=2):
+    """IPM Newton steps on the OPF-scale workload (n_d = 1024, n_s = 200000,
+    m = 3072, N = 4096): per-step time and TFLOP/s, the per-class breakdown,
+    and one whole IPM from the cold start to E_0 <= 1e-8."""
+    import torch
+    import paper_2605_13736_amd as mds
+    import synth
+    prob = synth.config_problem(synth.OPF_N4096)
+    N = prob["n_d"] + prob["m"]
+    S = mds.solver_for(prob)
+    it = S.new_iterate()
+    S.ipm_init(it)
+
+    def step():
+        st, info = S.ipm_step(it)
+        if st != 0:
+            S.ipm_init(it)
+            st, info = S.ipm_step(it)
+        return info
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    facs = solves = 0
+    for _ in range(steps):
+        info = step()
+        facs += info["trials"]
+        solves += info["solves"]
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    S.set_timing(True)
+    efacs = 0
+    for _ in range(steps):
+        efacs += step()["trials"]
+    tim = S.get_timings()
+    S.set_timing(False)
+    fac_ms = (tim["panel"]["ms"] + tim["panel_tail"]["ms"] + tim["trailing"]["ms"]) / max(efacs, 1)
+    # whole IPM
+    r = S.ipm_solve()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    r = S.ipm_solve()
+    torch.cuda.synchronize()
+    t_ipm = time.perf_counter() - t1
+    last = r["trace"][r["iters"]] if len(r["trace"]) > r["iters"] else r["trace"][-1]
+    out = dict(workload="FP64 IPM Newton steps, n_d=1024 n_s=200000 m=3072 (N=4096), J_s 6 nnz/row",
+               ms_per_step=dt / steps * 1e3,
+               tflops=(facs * N ** 3 / 3.0 + solves * 2.0 * N ** 2) / dt / 1e12,
+               factor_ms=fac_ms, factor_tflops=(N ** 3 / 3.0) / (fac_ms / 1e3) / 1e12,
+               kernel_ms_per_step={k: v["ms"] / steps for k, v in tim.items()},
+               panel_latency=panel_latency_model(tim, efacs, N, S.info()["nb"]),
+               whole_ipm=dict(status=r["status"], iters=r["iters"], seconds=t_ipm,
+                              solves_per_s=1.0 / t_ipm, final_E0=last["E0"],
+                              last_step_eta=r["trace"][r["iters"] - 1]["eta"]))
+    del S
+    torch.cuda.empty_cache()
+    return out, prob
+
+
+def opf_mixed_section(prob, reps=3):
+    """One Newton system of the N = 4096 workload at a seeded interior point,
+    solved to backward error 1e-14 by FP64 factor + classic refinement and by
+    the mixed modes + FP64 GMRES refinement."""
+    import numpy as np
     import torch
     import paper_2605_13736_amd as mds
     import synth
     it = synth.interior_iterate(prob, 0)
     nd = prob["n_d"]
+    N = nd + prob["m"]
     out, ref = {}, None
     for prec in ("fp64", "fp32", "bf16x3", "bf16"):
         S = mds.solver_for(prob, precision=prec)
@@ -98,19 +365,15 @@ def mixed_section(prob, N, reps=3):
 
         once()
         torch.cuda.synchronize()
-        S.set_timing(True)
         t0 = time.perf_counter()
         for _ in range(reps):
-            (a, b, c), info = once()
+            sol, info = once()
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / reps
-        tim = S.get_timings()
-        S.set_timing(False)
-        x = torch.cat([a, b, c]).cpu().numpy()
+        x = torch.cat(sol).cpu().numpy()
         if ref is None:
             ref = x
-        fac_ms = (tim["panel"]["ms"] + tim["panel_tail"]["ms"] + tim["trailing"]["ms"]) / reps
-        out[prec] = dict(ms_condense_factor_refine=dt * 1e3, ms_factor=fac_ms,
+        out[prec] = dict(ms_condense_factor_refine=dt * 1e3,
                          tflops_nominal=(N ** 3 / 3.0 + 2.0 * N ** 2) / dt / 1e12,
                          refine_iterations=info["steps"], eta=info["eta"],
                          rel_err_vs_fp64=float(abs(x - ref).max() / max(abs(ref).max(), 1e-300)))
@@ -119,13 +382,31 @@ def mixed_section(prob, N, reps=3):
     return out
 
 
+def ipm_solves_section(nrep=5):
+    """Whole FP64 IPMs on the N = 192 workload: solves per second."""
+    import torch
+    import paper_2605_13736_amd as mds
+    import synth
+    prob0 = synth.config_problem(synth.IPM_N192)
+    S0 = mds.solver_for(prob0)
+    r = S0.ipm_solve()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(nrep):
+        r = S0.ipm_solve()
+    torch.cuda.synchronize()
+    d0 = (time.perf_counter() - t1) / nrep
+    return {"workload": "whole FP64 IPM to E_0 <= 1e-8, n_d=64 n_s=2000 m=128 (N=192)",
+            "solves_per_s": 1.0 / d0, "iters": r["iters"], "status": r["status"],
+            "panel": S0.info()["panel"]}
+
+
 def batch_section(count, mu=0.05, singles=6):
     """The scenario batch: count problems with N = 4 U{64..512}, n_d = N/4,
     m = 3N/4, n_s = 50N, 4 nonzeros per row of J_s, each at a seeded barrier
     state; solved by the persistent kernel after autotuning, in FP64 and in
-    the scope's form (FP32 storage and FP32-MFMA trailing tiles, FP64
-    refinement on the full system).  Also times a loop of single-problem FP64
-    solves on the first `singles` problems."""
+    the FP32-tile form with FP64 refinement.  Also times a loop of
+    single-problem FP64 solves on the first `singles` problems."""
     import numpy as np
     import torch
     import paper_2605_13736_amd as mds
@@ -141,6 +422,7 @@ def batch_section(count, mu=0.05, singles=6):
         items.append(it)
         N = sz["N"]
         flops += N ** 3 / 3.0 + 2.0 * N ** 2
+
     def timed(precision):
         B = mds.Batch(items, precision=precision)
         B.run(mu)
@@ -162,7 +444,6 @@ def batch_section(count, mu=0.05, singles=6):
     dt32, res32, lat32, cfg32, x32 = timed("fp32")
     diff32 = max(float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
                  for a, b in zip(x32, x64))
-    # loop of single-problem solves (same systems, FP64 path, inertia correction)
     t_single = 0.0
     for p in range(singles):
         it = items[p]
@@ -204,43 +485,46 @@ def batch_section(count, mu=0.05, singles=6):
                     speedup_vs_single_loop=per_single * count / dt32))
 
 
-def warmstart_section(n_train, n_held, hidden=128, steps=3000, lr=3e-3, noise=0.5):
-    """Learned warm start on a family of N = 192 problems (the C0 shapes; only
-    b varies): cold FP64 IPM solves generate the training set; the perceptron
-    b -> (x_d, y, log10 mu0) (two GELU layers plus a linear skip path) is
-    trained with the library's kernels on input-noised minibatches; held-out
-    problems are solved warm (BF16 inference, cold fallback) and cold."""
+def warmstart_section(n_train, n_held, hidden=1024, steps=2000, lr=1e-3, noise=0.5,
+                      data_budget_s=None):
+    """Learned warm start on the OPF-scale family (N = 4096; b = b0 (1 + 0.1
+    N(0,1)) per entry): cold FP64 IPM solves generate the training set (at
+    most n_train, or what data_budget_s seconds of solves produce); the
+    perceptron b (3072) -> 1024 -> 1024 -> (x_d, y, log10 mu0) (4097) with
+    GELU (plus a linear skip path) is trained with the library's kernels;
+    held-out problems are solved warm (BF16 inference, cold fallback) and
+    cold."""
     import numpy as np
     import torch
     import paper_2605_13736_amd as mds
     import synth
     from paper_2605_13736_amd import warmstart
-    base = synth.config_problem(synth.IPM_N192)
-    train = [synth.family_member(base, p) for p in range(n_train)]
-    held = [synth.family_member(base, 10 ** 6 + p) for p in range(n_held)]
+    base = synth.config_problem(synth.OPF_N4096)
     t0 = time.perf_counter()
-    X, T, _, _ = warmstart.solve_family(train)
+    train = [synth.family_member(base, p) for p in range(n_train)]
+    X, T, cold_train_iters, _ = warmstart.solve_family(train, time_budget_s=data_budget_s)
     t_data = time.perf_counter() - t0
     ws = warmstart.WarmStart(base["m"], base["n_d"], hidden=hidden, max_batch=256)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    losses = ws.fit(X, T, steps=steps, lr=lr, batch=128, noise=noise)
+    losses = ws.fit(X, T, steps=steps, lr=lr, batch=min(128, len(X)), noise=noise)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     S = mds.solver_for(base)
-    cold_it, warm_it, cold_t, warm_t, fb, err = [], [], 0.0, 0.0, 0, 0.0
-    for q in held:
+    cold_it, warm_it, cold_t, warm_t, fb, err = [], [], [], [], 0, 0.0
+    for p in range(n_held):
+        q = synth.family_member(base, 10 ** 6 + p)
         S.P["b"].copy_(S.dev(q["b"]))
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         c = S.ipm_solve()
         torch.cuda.synchronize()
-        cold_t += time.perf_counter() - t1
+        cold_t.append(time.perf_counter() - t1)
         xc = c["x"].cpu().numpy().copy()
         t1 = time.perf_counter()
         w = ws.solve(S, q["b"])
         torch.cuda.synchronize()
-        warm_t += time.perf_counter() - t1
+        warm_t.append(time.perf_counter() - t1)
         cold_it.append(c["iters"])
         warm_it.append(w["warm_iters"])
         fb += int(w["fallback"])
@@ -253,58 +537,67 @@ def warmstart_section(n_train, n_held, hidden=128, steps=3000, lr=3e-3, noise=0.
         ws.net.forward(Xn, "bf16")
     torch.cuda.synchronize()
     t_inf = (time.perf_counter() - t1) / 20
-    return dict(workload=f"family of N=192 problems (n_d=64, n_s=2000, m=128; b varies), "
-                         f"{len(X)} training / {n_held} held-out",
-                mlp=f"{base['m']}-{hidden}-{hidden}-{base['n_d'] + base['m'] + 1}, GELU, linear skip, "
+    return dict(workload=f"family of the N=4096 problem (n_d=1024, n_s=200000, m=3072), "
+                         f"b = b0 (1 + 0.1 N(0,1)); {len(X)} training solves, "
+                         f"{n_held} held-out seeds",
+                mlp=f"{ws.dims[0]}-{hidden}-{hidden}-{ws.dims[3]}, GELU, linear skip, "
                     f"FP32-MFMA training (Adam lr {lr}, {steps} steps, input noise {noise}), "
-                    "BF16-MFMA inference",
-                data_s=t_data, train_s=t_train, train_steps=steps,
-                loss_first=losses[0], loss_last=losses[-1], inference_ms=t_inf * 1e3,
+                    "BF16-MFMA inference with FP32 accumulation",
+                params=int(ws.net.nparam), data_s=t_data, train_s=t_train,
+                train_solves=len(X), loss_first=losses[0], loss_last=losses[-1],
+                inference_ms=t_inf * 1e3,
                 cold_iters_mean=float(np.mean(cold_it)), warm_iters_mean=float(np.mean(warm_it)),
                 iters_saved_frac=1.0 - float(np.mean(warm_it)) / float(np.mean(cold_it)),
-                fallback_rate=fb / n_held, cold_solves_per_s=n_held / cold_t,
-                warm_solves_per_s=n_held / warm_t, max_abs_x_diff_vs_cold=err)
+                cold_time_to_1e8_s_mean=float(np.mean(cold_t)),
+                warm_time_to_1e8_s_mean=float(np.mean(warm_t)),
+                speedup=float(np.mean(cold_t)) / float(np.mean(warm_t)),
+                fallback_rate=fb / n_held, max_abs_x_diff_vs_cold=err)
 
 
-def cpu_baseline(prob, N):
+# ---------------------------------------------------------------- CPU
+def cpu_baseline(prob, st, kstop):
+    """The oracle on a bounded sample of the headline workload: the first
+    kstop pivot columns of its unblocked Bunch-Kaufman elimination of the
+    N = 16384 condensed matrix (the condensation itself is timed and
+    reported apart), on one host core pinned with sched_setaffinity and on
+    every available core (the elimination's columns split over threads,
+    bit-identical results)."""
     import numpy as np
     import oracle
-    import synth
+    info, avail = host_info()
     P = oracle.Problem(prob)
-    it = synth.interior_iterate(prob, 0)
-    nd = prob["n_d"]
-    sig, rx, ry = oracle.sigma_rhs(P, it["x"], it["y"], it["zl"], it["zu"], it["mu"])
-    dsb = prob["w"] + sig[nd:]
-    F = oracle.Factor(P)
     t = time.perf_counter()
-    F.once(sig[:nd], dsb, 0.0, 0.0)
-    F.solve(rx[:nd], rx[nd:], ry)
-    dt = time.perf_counter() - t
-    flops = N ** 3 / 3.0 + 2.0 * N ** 2
-    return dict(value=flops / dt / 1e12, unit="TFLOP/s", cores=1, kind="oracle",
-                sample=f"one condense + unblocked Bunch-Kaufman factor + solve of the N={N} "
-                       f"system at a seeded interior point, {dt:.1f} s on 1 host core",
-                seconds=dt)
-
-
-def ipm_solves_section(nrep=5):
-    """Whole FP64 IPMs on the N = 192 workload: solves per second."""
-    import torch
-
-    import paper_2605_13736_amd as mds
-    import synth
-    prob0 = synth.config_problem(synth.IPM_N192)
-    S0 = mds.solver_for(prob0)
-    r = S0.ipm_solve()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    for _ in range(nrep):
-        r = S0.ipm_solve()
-    torch.cuda.synchronize()
-    d0 = (time.perf_counter() - t1) / nrep
-    return {"workload": "whole FP64 IPM to E_0 <= 1e-8, n_d=64 n_s=2000 m=128 (N=192)",
-            "solves_per_s": 1.0 / d0, "iters": r["iters"], "status": r["status"],
-            "panel": S0.info()["panel"]}
+    M, _ = oracle.condense(P, st["sigma_d"], st["dsbase"], 0.0, 0.0)
+    t_cond = time.perf_counter() - t
+    N = M.shape[0]
+    flops = sum(float(N - k - 1) * float(N - k) for k in range(kstop))
+    res = {}
+    old_aff = set(avail)
+    for label, cpus in (("one_core", [avail[0]]), ("all_cores", avail)):
+        A = np.asfortranarray(M.copy())
+        try:
+            os.sched_setaffinity(0, set(cpus))
+        except (AttributeError, OSError):
+            pass
+        oracle.set_threads(len(cpus))
+        t = time.perf_counter()
+        _, ipiv = oracle.bk_partial(A, kstop)
+        res[label] = (time.perf_counter() - t, len(cpus), ipiv[:kstop].copy())
+        oracle.set_threads(1)
+        try:
+            os.sched_setaffinity(0, old_aff)
+        except (AttributeError, OSError):
+            pass
+    t1, c1, p1 = res["one_core"]
+    tn, cn, pn = res["all_cores"]
+    return dict(value=flops / t1 / 1e12, unit="TFLOP/s", cores=c1, kind="oracle",
+                sample=f"the first {kstop} pivot columns of the oracle's unblocked Bunch-Kaufman "
+                       f"elimination of the N={N} condensed matrix ({flops:.3g} flops, "
+                       f"{t1:.1f} s on one core pinned to cpu {avail[0]}); the condensation "
+                       f"took {t_cond:.1f} s",
+                seconds=t1, host=info,
+                all_cores=dict(value=flops / tn / 1e12, cores=cn, seconds=tn,
+                               pivots_identical_to_one_core=bool(np.array_equal(p1, pn))))
 
 
 def main():
@@ -313,20 +606,31 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--nb", type=int, default=0)
+    ap.add_argument("--headline-only", action="store_true",
+                    help="run only the headline steps and print them (profiling)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-kstop", type=int, default=60)
+    ap.add_argument("--no-sweep", action="store_true")
+    ap.add_argument("--no-opf", action="store_true")
     ap.add_argument("--no-ipm-solves", action="store_true")
-    ap.add_argument("--ipm-only", action="store_true",
-                    help="run only the whole-IPM section (N = 192) and print it (profiling)")
-    ap.add_argument("--batch-only", action="store_true",
-                    help="run only the scenario-batch section and print it (profiling)")
-    ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--batch-count", type=int, default=512)
+    ap.add_argument("--batch-only", action="store_true",
+                    help="run only the scenario-batch section and print it (profiling)")
+    ap.add_argument("--opf-only", action="store_true",
+                    help="run only the N = 4096 section and print it (profiling)")
     ap.add_argument("--no-warmstart", action="store_true")
-    ap.add_argument("--ws-train", type=int, default=1024)
+    ap.add_argument("--ws-train", type=int, default=400)
+    ap.add_argument("--ws-budget", type=float, default=60.0,
+                    help="seconds of cold solves that generate warm-start training data")
+    ap.add_argument("--ws-held", type=int, default=16)
     ap.add_argument("--calib-copy", action="store_true",
                     help="only run a plain 256 MiB device copy (calibrates HBM counters)")
     args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
+              "(the multi-GPU sharding is a design only)", file=sys.stderr)
+        sys.exit(2)
     if args.calib_copy:
         import torch
         x = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
@@ -337,139 +641,63 @@ def main():
         print(json.dumps({"calib_copy_bytes_read": x.numel() * 8,
                           "calib_copy_bytes_written": x.numel() * 8, "launches": 3}))
         return
-    if args.ipm_only:
-        print(json.dumps({"ipm_solves": ipm_solves_section()}))
-        return
     if args.batch_only:
         print(json.dumps({"batch": batch_section(args.batch_count)}))
         return
-    if args.gpus != 1:
-        print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
-              "(the multi-GPU sharding is a design only)", file=sys.stderr)
-        sys.exit(2)
+    if args.opf_only:
+        print(json.dumps({"opf_n4096": opf_section(args.steps, args.warmup)[0]}))
+        return
 
-    import numpy as np
-    import torch
-
-    import paper_2605_13736_amd as mds
-    import synth
-
-    cfg = synth.CONFIGS[synth.OPF_N4096]
-    prob = synth.config_problem(synth.OPF_N4096)
-    N = cfg["n_d"] + cfg["m"]
-    log(f"workload N={N} n_s={cfg['n_s']} nnz={len(prob['v'])}")
-    S = mds.solver_for(prob, nb=args.nb)
-    info0 = S.info()
-    nb = info0["nb"]
-    it = S.new_iterate()
-    S.ipm_init(it)
-
-    def step():
-        st, info = S.ipm_step(it)
-        if st != 0:  # converged (or failed): restart from the cold start point
-            S.ipm_init(it)
-            st, info = S.ipm_step(it)
-        return info
-
-    for _ in range(args.warmup):
-        step()
-    # throughput: K steps with no event records between the launches
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    facs = solves = 0
-    for _ in range(args.steps):
-        info = step()
-        facs += info["trials"]
-        solves += info["solves"]
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    flops = facs * N ** 3 / 3.0 + solves * 2.0 * N ** 2
-    value = flops / dt / 1e12
-    log(f"timed {args.steps} steps in {dt:.3f}s: {facs} factorizations, {solves} solves")
-    # per-kernel-class device time: K more steps with HIP event pairs around
-    # every launch on the library's stream (the events add launch gaps, so
-    # this region is not the throughput one)
-    S.set_timing(True)
-    torch.cuda.synchronize()
-    te = time.perf_counter()
-    efacs = 0
-    for _ in range(args.steps):
-        efacs += step()["trials"]
-    torch.cuda.synchronize()
-    dte = time.perf_counter() - te
-    tim = S.get_timings()
-    S.set_timing(False)
-    log("per-class device time:", json.dumps(tim))
-
-    # dominant kernel roofline
-    dom = max(tim, key=lambda k: tim[k]["ms"])
-    nlaunch = max(tim[dom]["launches"], 1)
-    avg_s = tim[dom]["ms"] / 1e3 / nlaunch
-    if dom == "panel":
-        tail = tim["panel_tail"]["launches"] > 0
-        per_launch = panel_bytes_per_launch(N, tim["panel"]["launches"] / max(efacs, 1),
-                                            adv=max(nb - 1, 1) if tail else None)
-        roof = dict(bound="hbm", achieved=per_launch / avg_s / 1e9, peak=HBM_PEAK_GBS,
-                    unit="GB/s")
-    elif dom == "trailing":
-        npan = tim["panel"]["launches"] + tim["panel_tail"]["launches"]
-        per_launch = trailing_bytes_per_launch(N, N / max(npan / max(efacs, 1), 1))
-        roof = dict(bound="hbm", achieved=per_launch / avg_s / 1e9, peak=HBM_PEAK_GBS,
-                    unit="GB/s")
-    elif dom == "solve":
-        per_launch = 2.0 * (N * N / 2.0) * 8.0
-        roof = dict(bound="hbm", achieved=per_launch / avg_s / 1e9, peak=HBM_PEAK_GBS,
-                    unit="GB/s")
-    else:
-        m, nd = cfg["m"], cfg["n_d"]
-        per_launch = 8.0 * (N * N + m * nd + nd * nd)
-        roof = dict(bound="hbm", achieved=per_launch / avg_s / 1e9, peak=HBM_PEAK_GBS,
-                    unit="GB/s")
-    roof["frac"] = roof["achieved"] / roof["peak"]
-    panel_kernel = {"reg": "k_bk_panel_reg", "coop": "k_bk_panel_coop"}.get(info0["panel"], "k_bk_panel")
-    roof["kernel"] = {"panel": panel_kernel, "panel_tail": "k_bk_panel_reg",
-                      "trailing": "k_bk_trailing",
-                      "solve": "k_trsv_fwd+k_trsv_bwd", "condense": "k_condense_dense",
-                      "permute": "k_std_sweep+k_std_apply"}[dom]
-    meas = MEASURED_TRAFFIC.get(roof["kernel"])
-    roof["traffic"] = meas[0] if meas else None
-    if meas:
-        roof["traffic_source"] = meas[1]
-    roof["avg_launch_us"] = avg_s * 1e6
-    roof["bytes_per_launch"] = per_launch
+    h, prob, st = kkt_step_section(args)
+    N, nb = h["N"], h["info"]["nb"]
+    tim, efacs = h["tim"], h["efacs"]
     fac_ms = (tim["panel"]["ms"] + tim["panel_tail"]["ms"] + tim["trailing"]["ms"]) / max(efacs, 1)
     factor_tfs = (N ** 3 / 3.0) / (fac_ms / 1e3) / 1e12
-
     out = {
-        "metric": METRIC, "value": value, "unit": "TFLOP/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt / args.steps * 1e3,
+        "metric": METRIC, "value": h["value"], "unit": "TFLOP/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": h["dt"] / args.steps * 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"FP64 IPM Newton steps, n_d=1024 n_s=200000 m=3072 (N={N}), "
-                               "J_s 6 nnz/row, seeded synthetic", "N": N, "nb": nb,
-                   "panel": info0["panel"], "precision": "fp64"},
-        "roofline": roof,
+        "config": {"workload": f"KKT factor+solve of one Newton system, n_d=4096 n_s=1000000 "
+                               f"m=12288 (N={N}), J_s 8 nnz/row, Sigma_d and D_s log-uniform "
+                               "1e-8..1e8, FP64 refinement to backward error 1e-14, "
+                               "seeded synthetic", "N": N, "nb": nb,
+                   "panel": h["info"]["panel"], "precision": "fp64"},
+        "roofline": roofline_of(tim, efacs, N, nb),
         "factor": {"ms_per_factorization": fac_ms, "tflops": factor_tfs,
+                   "bound": "mfma", "peak_tflops": FP64_MFMA_PEAK_TFS,
                    "frac_fp64_mfma_peak": factor_tfs / FP64_MFMA_PEAK_TFS,
-                   "factorizations": facs, "solves": solves},
-        "kernel_ms": {k: v["ms"] for k, v in tim.items()},
-        "event_region": {"steps": args.steps, "ms_per_step": dte / args.steps * 1e3,
+                   "factorizations": h["facs"], "solves": h["solves"],
+                   "eta": h["eta"],
+                   "inertia": [h["inertia"]["npos"], h["inertia"]["nzero"], h["inertia"]["nneg"]]},
+        "kernel_ms_per_step": {k: v["ms"] / args.steps for k, v in tim.items()},
+        "panel_latency": panel_latency_model(tim, efacs, N, nb),
+        "event_region": {"steps": args.steps, "ms_per_step": h["dte"] / args.steps * 1e3,
                          "factorizations": efacs},
     }
-
+    if args.headline_only:
+        print(json.dumps(out), flush=True)
+        return
+    if not args.no_sweep:
+        log("precision sweep")
+        out["precision_sweep"] = precision_sweep(prob, st, N, h["x64"])
+    if not args.no_opf:
+        log("N = 4096 section")
+        opf, prob1 = opf_section()
+        opf["mixed"] = opf_mixed_section(prob1)
+        out["opf_n4096"] = opf
     if not args.no_ipm_solves:
         out["ipm_solves"] = ipm_solves_section()
-    if not args.no_mixed:
-        log("mixed precision section")
-        out["mixed"] = mixed_section(prob, N)
     if not args.no_batch:
         log("batch section")
         out["batch"] = batch_section(args.batch_count)
     if not args.no_warmstart:
         log("learned warm start section")
-        out["warmstart"] = warmstart_section(args.ws_train, 32)
+        out["warmstart"] = warmstart_section(args.ws_train, args.ws_held,
+                                             data_budget_s=args.ws_budget)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(prob, N)
+        log("cpu baseline")
+        out["cpu_baseline"] = cpu_baseline(prob, st, args.cpu_kstop)
     print(json.dumps(out), flush=True)
 
 

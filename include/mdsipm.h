@@ -4,21 +4,29 @@
  * Nonlinear Optimization Library HiOp to Accelerator-Based Hardware
  * Architectures".
  *
- * Problem class (Sec. 2, eqs. (obj)-(bounds), equality constraints only):
+ * Problem class (Sec. 2, eqs. (obj)-(bounds), with linear constraints):
  *     min  0.5 x_d'H x_d + c'x_d + sum_i (0.5 w_i x_s,i^2 + g_i x_s,i)
- *     s.t. J_d x_d + J_s x_s = b,   xl <= x <= xu,   x = [x_d; x_s].
+ *     s.t. (J x)_r = b_r          for the first m_E = m - m_I rows (eq. (coneq)),
+ *          hl_r <= (J x)_r <= hu_r for the last m_I rows (eq. (ineq)),
+ *          xl <= x <= xu,   x = [x_d; x_s],   J = [J_d J_s].
  * Assumption A1 (no cross Hessian) and A2 (diagonal, nonnegative Hessian of
  * the sparse block: w >= 0) hold by construction of this class.
  *
- * Newton system (Sec. 2.1, eq. (linsys4x4) without the inequality block):
+ * Newton system (Sec. 2.1, eq. (linsys4x4); the equality and inequality rows
+ * of J are kept in one block y = [y_g; y_h]):
  *     [[H + Sigma_d + dw I, 0,               J_d'],   [dx_d]   [r_d]
  *      [0,                  D_s,             J_s'],   [dx_s] = [r_s]
- *      [J_d,                J_s,            -dc I]]   [dy  ]   [r_y]
- * with D_s = w + Sigma_s + dw (diagonal, positive).  Eliminating dx_s
- * (Sec. 2.2, eq. (compressed)) leaves the dense symmetric indefinite
- *     M = [[H + Sigma_d + dw I, J_d'], [J_d, -J_s D_s^{-1} J_s' - dc I]]
+ *      [J_d,                J_s,     -dc I - Dh ]]   [dy  ]   [r_y]
+ * with D_s = w + Sigma_s + dw (diagonal, positive) and Dh = diag(dcv) the
+ * (4,4) block -D_h^{-1} of the inequality rows (zero on equality rows).
+ * Eliminating dx_s (Sec. 2.2, eq. (compressed)) leaves the dense symmetric
+ * indefinite
+ *     M = [[H + Sigma_d + dw I, J_d'], [J_d, -J_s D_s^{-1} J_s' - dc I - Dh]]
  * of size N = n_d + m, factored by Bunch-Kaufman LDL' (Sec. 2.3); its inertia
  * plus In(D_s) = (n_s,0,0) is the inertia of the full system (Haynsworth).
+ * The IPM turns the inequality rows into equalities (J x)_r - d_r = 0 with a
+ * bounded slack d (hl <= d <= hu) and eliminates the slack step: with Sigma_h
+ * the slack's barrier diagonal, D_h = Sigma_h + dw and dcv = 1 / D_h.
  *
  * Conventions
  *  - All array pointers are DEVICE pointers (hipMalloc'd or framework-owned
@@ -71,6 +79,8 @@ enum {
 
 typedef struct {
   int32_t n_d, n_s, m; /* N = n_d + m is the condensed size, N <= 20480 */
+  int32_t m_I;         /* inequality rows: the last m_I of the m rows of J
+                          (0 <= m_I <= m; 0: equality constraints only)  */
   int64_t nnz_s;       /* nonzeros of J_s */
 } mds_dims;
 
@@ -100,9 +110,12 @@ typedef struct {
                           3: register-resident panel over ceil(N / 1024)
                              cooperating workgroups, nb <= 32 (any N); its
                              workgroups exchange pivot data through the
-                             workspace and must run concurrently: an
-                             exchange wait longer than ~0.7 s ends the
-                             factorization with MDS_EHIP,
+                             workspace and must run concurrently: when an
+                             exchange wait expires (~0.7 s) the matrix is
+                             condensed again and factored by the memory
+                             panel in FP64 (the factor then is an FP64 one
+                             in every precision mode; mds_get_fallbacks
+                             counts these),
                           4: unblocked factorization of the whole M held in
                              one workgroup's LDS (FP64, N <= 199; the
                              interchanges are applied to whole rows, so the
@@ -127,8 +140,13 @@ typedef struct {
   const int32_t *Js_rowptr; /* m+1                                           */
   const int32_t *Js_col;  /* nnz_s                                           */
   const double *Js_val;   /* nnz_s                                           */
-  const double *b;        /* m                                               */
+  const double *b;        /* m_E = m - m_I: right-hand side of the equality
+                             rows (the entries of inequality rows are not
+                             read)                                           */
   const double *xl, *xu;  /* n = n_d + n_s; +-INFINITY allowed, xl < xu      */
+  const double *hl, *hu;  /* m_I: bounds of the inequality rows, +-INFINITY
+                             allowed, hl < hu, at least one finite (eq.
+                             (ineq)); may be NULL when m_I = 0               */
 } mds_problem;
 
 typedef struct {
@@ -154,8 +172,11 @@ typedef struct {
   int32_t pad;
 } mds_refine_info;
 
-/* IPM iterate.  x, y, zl, zu are device arrays (n, m, n, n); the scalars are
- * host values that mds_ipm_init sets and mds_ipm_step updates. */
+/* IPM iterate.  x, zl, zu are device arrays of n + m_I entries: the n
+ * variables followed by the m_I inequality slacks d (x[n + r] is the slack
+ * of inequality row m_E + r, hl_r <= d_r <= hu_r) and their bound
+ * multipliers; y (m) holds the multipliers of all rows.  The scalars are host
+ * values that mds_ipm_init sets and mds_ipm_step updates. */
 typedef struct {
   double *x, *y, *zl, *zu;
   double mu, tau;
@@ -169,6 +190,10 @@ typedef struct {
   int32_t max_iter;    /* (200)                                              */
   int32_t refine_steps;/* refinement steps per Newton solve (2)              */
   double dw_max;       /* correction cap (1e20)                              */
+  int32_t gmres_max;   /* mixed precision: GMRES iterations per Newton solve
+                          (0: 60); a solve that stops above backward error
+                          1e-14 is redone from an FP64 factorization         */
+  int32_t pad;
 } mds_ipm_opts;
 
 typedef struct {       /* one IPM iteration (host) */
@@ -177,6 +202,12 @@ typedef struct {       /* one IPM iteration (host) */
   int32_t trials;      /* factorizations (inertia-correction trials)          */
   int32_t solves;      /* LDL' solves (1 + refinement corrections)            */
   int32_t backtracks, status;
+  int32_t fallback;    /* bit 0: the mixed-precision refinement stopped above
+                          its tolerance and the step was recomputed from an
+                          FP64 factorization of the same Newton system;
+                          bit 1: a cooperative panel's exchange wait expired
+                          and the memory panel refactored the matrix        */
+  int32_t pad;
 } mds_step_info;
 
 /* Per-kernel-class device time, accumulated while timing is enabled
@@ -228,7 +259,10 @@ int mds_condense(mds_handle *h, const double *sigma_d, const double *dsbase,
  * (-D_h^{-1}) enters the compressed form of Sec. 2.2 when the constraints
  * include inequalities.  dcv: device array (m), caller-owned, finite and
  * >= 0 (checked: MDS_EINVAL otherwise, nothing changes), valid while set;
- * NULL clears it.  Invalidates the current M and factor.  Synchronizes. */
+ * NULL clears it, and so does mds_set_problem.  The IPM computes this block
+ * itself from its inequality slacks, so mds_ipm_init and mds_ipm_init_warm
+ * return MDS_ESTATE while a caller's diagonal is set.  Invalidates the
+ * current M and factor.  Synchronizes. */
 int mds_set_m22_diag(mds_handle *h, const double *dcv);
 
 /* Bunch-Kaufman LDL' of the condensed M with its inertia (Sec. 2.3, kernel
@@ -263,8 +297,12 @@ int mds_refine(mds_handle *h, const double *r_d, const double *r_s, const double
 
 /* ---- IPM vector kernels (Sec. 2.1, kernel classes K1/K2) ------------------ */
 
-/* sigma = zl/(x-xl) + zu/(xu-x); r_x = -(grad f + J'y - mu/(x-xl) + mu/(xu-x));
- * r_y = -(J x - b).  Infinite bounds contribute nothing.  Async. */
+/* Barrier diagonal and Newton right-hand side at an iterate (layout of
+ * mds_iterate: x, zl, zu, sigma and r_x have n + m_I entries, the slacks
+ * d after the variables).  sigma = zl/(x-xl) + zu/(xu-x);
+ * r_x = -(grad L - mu/(x-xl) + mu/(xu-x)) with grad L = [grad f + J'y; -y_h]
+ * (the slack entries get y_h + barrier terms); r_y = -c with
+ * c = [J_g x - b; J_h x - d].  Infinite bounds contribute nothing.  Async. */
 int mds_sigma_rhs(mds_handle *h, const double *x, const double *y, const double *zl,
                   const double *zu, double mu, double *sigma, double *r_x, double *r_y);
 
@@ -278,14 +316,19 @@ int mds_ftb(mds_handle *h, int64_t n, const double *v, const double *dv, double 
 int mds_opt_error(mds_handle *h, const double *x, const double *y, const double *zl,
                   const double *zu, double mu, double *E_host, double *parts_host);
 
-/* Objective f, barrier function phi_mu and theta = ||J x - b||_1.  Synchronizes. */
+/* Objective f, barrier function phi_mu (log-barrier over every finite bound
+ * of the variables and the slacks) and theta = ||c(x, d)||_1.  x has n + m_I
+ * entries.  Synchronizes. */
 int mds_merit(mds_handle *h, const double *x, double mu, double *f_host, double *phi_host,
               double *theta_host);
 
 /* ---- filter line-search IPM (Sec. 2.1) ------------------------------------ */
 
-/* Set the start point (x = 0 pushed inside its bounds, y = 0, z = 1 on finite
- * bounds) and reset the filter and correction state.  opts may be NULL. */
+/* Set the start point (x = 0 pushed inside its bounds, each slack d_r the
+ * row value (J x)_r pushed inside [hl_r, hu_r] by the same rule, y = 0,
+ * z = 1 on finite bounds) and reset the filter and correction state.  opts
+ * may be NULL.  MDS_ESTATE while a caller's (2,2) diagonal is set
+ * (mds_set_m22_diag). */
 int mds_ipm_init(mds_handle *h, mds_iterate *it, const mds_ipm_opts *opts);
 
 /* mds_ipm_init from a proposed start (the learned warm start): x_d0 (n_d)
@@ -295,7 +338,8 @@ int mds_ipm_init(mds_handle *h, mds_iterate *it, const mds_ipm_opts *opts);
  * rule; y = y0; z = mu0 / slack on finite bounds, plus the part of the dual
  * residual r = grad f(x) + J' y0 the bound can carry (r > 0 added to z_l,
  * -r > 0 to z_u), so that the start is near-stationary when the proposal is
- * near a solution. */
+ * near a solution.  Slacks: d = (J x)_h pushed inside [hl, hu], their
+ * multipliers mu0 / slack plus the part of -y_h they can carry. */
 int mds_ipm_init_warm(mds_handle *h, mds_iterate *it, const mds_ipm_opts *opts,
                       const double *x_d0, const double *y0, double mu0);
 
@@ -342,6 +386,23 @@ typedef struct {
   int64_t workspace_bytes;
 } mds_info;
 int mds_get_info(const mds_handle *h, mds_info *out_host);
+
+/* Robustness counters since mds_create (host): coop_aborts = cooperative
+ * factorizations whose exchange wait expired and which the memory panel
+ * redid; fp64_refactors = mixed-precision Newton solves of mds_ipm_step that
+ * were redone from an FP64 factorization. */
+typedef struct {
+  int64_t coop_aborts, fp64_refactors;
+} mds_fallbacks;
+int mds_get_fallbacks(const mds_handle *h, mds_fallbacks *out_host);
+
+/* Test hook for the failure paths, in the spirit of fault injection from the
+ * host: flag MDS_DEBUG_COOP_ABORT makes every later cooperative panel launch
+ * report an expired exchange wait at once (each workgroup leaves before its
+ * first exchange, so every kernel still ends normally), which exercises the
+ * memory-panel refactorization.  0 clears the flags.  Synchronizes. */
+enum { MDS_DEBUG_COOP_ABORT = 1 };
+int mds_set_debug(mds_handle *h, int32_t flags);
 
 /* Enable (1) or disable (0) per-launch timing; enabling clears the totals. */
 int mds_set_timing(mds_handle *h, int enable);

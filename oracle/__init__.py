@@ -24,8 +24,8 @@ _SRC = os.path.join(_HERE, "mds_oracle.c")
 def build(force: bool = True) -> str:
     """Compile liboracle.so with gcc (no BLAS, no contraction)."""
     if force or not os.path.exists(_LIB_PATH):
-        cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
-               "-std=c11", "-Wall", "-o", _LIB_PATH + ".tmp", _SRC, "-lm"]
+        cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC",
+               "-shared", "-std=c11", "-Wall", "-o", _LIB_PATH + ".tmp", _SRC, "-lm"]
         subprocess.run(cmd, check=True)
         os.replace(_LIB_PATH + ".tmp", _LIB_PATH)
     return _LIB_PATH
@@ -78,6 +78,9 @@ def lib():
         L.or_bk.argtypes = [C.c_int32, _dp, _ip, _dp, _dp, _ip]
         L.or_bk.restype = C.c_int
         L.or_inertia.argtypes = [C.c_int32, _ip, _dp, _dp, _ip]
+        L.or_bk_partial.argtypes = [C.c_int32, _dp, _ip, _dp, _dp, C.c_int32]
+        L.or_bk_partial.restype = C.c_int
+        L.or_set_threads.argtypes = [C.c_int32]
         L.or_ldl_solve.argtypes = [C.c_int32, _dp, _ip, _dp, _dp, _dp]
         L.or_ldl_solve.restype = C.c_int
         L.or_kkt_matvec.argtypes = [P, _dp, _dp, C.c_double, C.c_double, _dp, _dp, _dp,
@@ -242,6 +245,21 @@ def bk(A):
     info = lib().or_bk(N, _d(W), _i(ipiv), _d(dd), _d(ds), _i(kind))
     L = np.tril(W[:N * N].reshape((N, N), order="F"), -1) + np.eye(N)
     return L, dd[:N], ds[:N], ipiv[:N], info, kind[:N]
+
+
+def set_threads(n: int):
+    """Threads of the oracle's elimination (bit-identical results for any n)."""
+    lib().or_set_threads(int(n))
+
+
+def bk_partial(A, kstop):
+    """The first kstop pivot columns of the Bunch-Kaufman elimination of A
+    (a timing sample); A is overwritten (column-major float64, N x N)."""
+    N = A.shape[0]
+    ipiv = _buf(N, np.int32)
+    dd, ds = _buf(N), _buf(N)
+    return lib().or_bk_partial(N, _d(A.reshape(-1, order="F")), _i(ipiv), _d(dd), _d(ds),
+                               int(kstop)), ipiv
 
 
 def inertia(ipiv, dd, ds):

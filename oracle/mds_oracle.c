@@ -17,6 +17,16 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* Threads of the Bunch-Kaufman elimination (1 unless set).  Each entry of
+ * the trailing triangle is updated by one thread with the same expression,
+ * so every thread count gives bit-identical factors. */
+static int g_threads = 1;
+
+void or_set_threads(int32_t n) { g_threads = (n > 0) ? n : 1; }
 
 #define IDX(i, j, ld) ((size_t)(j) * (size_t)(ld) + (size_t)(i))
 
@@ -103,7 +113,20 @@ static void swap_d(double *a, double *b) {
   double t = *a; *a = *b; *b = t;
 }
 
+static int bk_until(int32_t N, double *A, int32_t *ipiv, double *dd, double *ds, int32_t *kind,
+                    int32_t kstop);
+
 int or_bk(int32_t N, double *A, int32_t *ipiv, double *dd, double *ds, int32_t *kind) {
+  return bk_until(N, A, ipiv, dd, ds, kind, N);
+}
+
+int or_bk_partial(int32_t N, double *A, int32_t *ipiv, double *dd, double *ds, int32_t kstop) {
+  return bk_until(N, A, ipiv, dd, ds, NULL, kstop);
+}
+
+/* The elimination of or_bk, stopped once kstop pivot columns are done. */
+static int bk_until(int32_t N, double *A, int32_t *ipiv, double *dd, double *ds, int32_t *kind,
+                    int32_t kstop) {
   const double alpha = (1.0 + sqrt(17.0)) / 8.0;
   int info = 0;
   double *w0 = (double *)malloc(sizeof(double) * (size_t)(N > 0 ? N : 1));
@@ -112,7 +135,7 @@ int or_bk(int32_t N, double *A, int32_t *ipiv, double *dd, double *ds, int32_t *
   double *l1 = (double *)malloc(sizeof(double) * (size_t)(N > 0 ? N : 1));
   for (int i = 0; i < N; ++i) { dd[i] = 0.0; ds[i] = 0.0; }
   int k = 0;
-  while (k < N) {
+  while (k < N && k < kstop) {
     double absakk = fabs(A[IDX(k, k, N)]);
     /* column maximum below the diagonal; the first index wins ties */
     int imax = k;
@@ -160,7 +183,9 @@ int or_bk(int32_t N, double *A, int32_t *ipiv, double *dd, double *ds, int32_t *
       dd[k] = d;
       ipiv[k] = kp + 1;
       for (int i = k + 1; i < N; ++i) { w0[i] = A[IDX(i, k, N)]; l0[i] = w0[i] / d; }
-      /* rank-1 update of the trailing lower triangle: A -= l w' */
+      /* rank-1 update of the trailing lower triangle: A -= l w' (columns
+       * split over the threads; each entry's expression is unchanged) */
+#pragma omp parallel for schedule(dynamic, 8) num_threads(g_threads) if (g_threads > 1 && N - k > 256)
       for (int j = k + 1; j < N; ++j)
         for (int i = j; i < N; ++i) A[IDX(i, j, N)] = A[IDX(i, j, N)] - l0[i] * w0[j];
       for (int i = k + 1; i < N; ++i) A[IDX(i, k, N)] = l0[i];
@@ -179,6 +204,7 @@ int or_bk(int32_t N, double *A, int32_t *ipiv, double *dd, double *ds, int32_t *
         l1[i] = (y * a - x * b) / det;
       }
       /* rank-2 update: A -= [l0 l1] [w0 w1]' */
+#pragma omp parallel for schedule(dynamic, 8) num_threads(g_threads) if (g_threads > 1 && N - k > 256)
       for (int j = k + 2; j < N; ++j)
         for (int i = j; i < N; ++i)
           A[IDX(i, j, N)] = A[IDX(i, j, N)] - (l0[i] * w0[j] + l1[i] * w1[j]);

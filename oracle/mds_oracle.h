@@ -73,6 +73,12 @@ void or_backsub(const orq_problem *P, const double *inv_d, const double *r_s,
  * branch taken at pivot step k (0 zero column, 1 plain 1x1, 2 1x1 after the
  * second test, 3 1x1 with swap, 4 2x2). */
 int or_bk(int32_t N, double *A, int32_t *ipiv, double *dd, double *ds, int32_t *kind);
+/* or_bk stopped after the pivot columns 0 .. kstop-1 (a 2x2 pivot may end
+ * one column later): a bounded sample of the factorization's work. */
+int or_bk_partial(int32_t N, double *A, int32_t *ipiv, double *dd, double *ds, int32_t kstop);
+/* Threads of the elimination (default 1); results are bit-identical for
+ * every count. */
+void or_set_threads(int32_t n);
 /* inertia (npos, nzero, nneg) from D */
 void or_inertia(int32_t N, const int32_t *ipiv, const double *dd, const double *ds,
                 int32_t out[3]);

@@ -24,6 +24,7 @@ MDS_IPM_CONVERGED = 4
 MDS_IPM_LS_FAIL = 5
 MDS_IPM_MAXITER = 6
 MDS_IPM_NONFINITE = 7
+MDS_DEBUG_COOP_ABORT = 1
 STATUS_NAMES = {4: "converged", 5: "ls_fail", 6: "maxiter", 2: "inertia_fail", 7: "nonfinite"}
 
 _vp = C.c_void_p
@@ -32,7 +33,8 @@ _ip = C.POINTER(C.c_int32)
 
 
 class Dims(C.Structure):
-    _fields_ = [("n_d", C.c_int32), ("n_s", C.c_int32), ("m", C.c_int32), ("nnz_s", C.c_int64)]
+    _fields_ = [("n_d", C.c_int32), ("n_s", C.c_int32), ("m", C.c_int32), ("m_I", C.c_int32),
+                ("nnz_s", C.c_int64)]
 
 
 class Options(C.Structure):
@@ -50,7 +52,7 @@ PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2, "bf16x3": 3}
 class Problem(C.Structure):
     _fields_ = [("H", _vp), ("c", _vp), ("w", _vp), ("g", _vp), ("J_d", _vp),
                 ("Js_rowptr", _vp), ("Js_col", _vp), ("Js_val", _vp), ("b", _vp),
-                ("xl", _vp), ("xu", _vp)]
+                ("xl", _vp), ("xu", _vp), ("hl", _vp), ("hu", _vp)]
 
 
 class Inertia(C.Structure):
@@ -75,7 +77,8 @@ class Iterate(C.Structure):
 
 class IpmOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("mu0", C.c_double), ("max_iter", C.c_int32),
-                ("refine_steps", C.c_int32), ("dw_max", C.c_double)]
+                ("refine_steps", C.c_int32), ("dw_max", C.c_double), ("gmres_max", C.c_int32),
+                ("pad", C.c_int32)]
 
 
 class StepInfo(C.Structure):
@@ -83,7 +86,12 @@ class StepInfo(C.Structure):
                 ("phi", C.c_double), ("alpha_pr", C.c_double), ("alpha_du", C.c_double),
                 ("delta_w", C.c_double), ("delta_c", C.c_double), ("eta", C.c_double),
                 ("inertia", C.c_int32 * 3), ("trials", C.c_int32), ("solves", C.c_int32),
-                ("backtracks", C.c_int32), ("status", C.c_int32)]
+                ("backtracks", C.c_int32), ("status", C.c_int32), ("fallback", C.c_int32),
+                ("pad", C.c_int32)]
+
+
+class Fallbacks(C.Structure):
+    _fields_ = [("coop_aborts", C.c_int64), ("fp64_refactors", C.c_int64)]
 
 
 T_CLASSES = ("condense", "panel", "trailing", "solve", "permute", "panel_tail")
@@ -150,6 +158,8 @@ SIGNATURES = {
     "mds_get_inv_ds": (C.c_int, [_vp, _dp]),
     "mds_get_info": (C.c_int, [_vp, C.POINTER(Info)]),
     "mds_set_timing": (C.c_int, [_vp, C.c_int]),
+    "mds_get_fallbacks": (C.c_int, [_vp, C.POINTER(Fallbacks)]),
+    "mds_set_debug": (C.c_int, [_vp, C.c_int32]),
     "mds_get_timings": (C.c_int, [_vp, C.POINTER(Timings)]),
     "mds_batch_workspace_bytes": (C.c_size_t, [C.POINTER(BatchProblem), C.c_int32,
                                                C.POINTER(BatchOpts)]),
@@ -211,13 +221,13 @@ class Solver:
 
     def __init__(self, n_d: int, n_s: int, m: int, nnz_s: int, nb: int = 0,
                  device: str = "cuda:0", stream=None, panel: str = "auto",
-                 precision: str = "fp64", panel_threads: int = 0):
+                 precision: str = "fp64", panel_threads: int = 0, m_I: int = 0):
         torch = _torch()
         if not torch.cuda.is_available():
             raise MdsError("no ROCm GPU visible: the mdsipm library has no CPU path")
         self.torch = torch
         self.device = torch.device(device)
-        self.dims = Dims(n_d, n_s, m, nnz_s)
+        self.dims = Dims(n_d, n_s, m, m_I, nnz_s)
         if precision not in PRECISIONS:
             raise MdsError(f"precision must be one of {sorted(PRECISIONS)}")
         self.precision = precision
@@ -225,8 +235,9 @@ class Solver:
             raise MdsError("panel must be one of " + ", ".join(PANELS))
         self.opts = Options(nb, PANELS[panel], PRECISIONS[precision],
                             int(panel_threads))
-        self.n_d, self.n_s, self.m = n_d, n_s, m
+        self.n_d, self.n_s, self.m, self.m_I = n_d, n_s, m, m_I
         self.N, self.n = n_d + m, n_d + n_s
+        self.nx = self.n + m_I  # IPM primal vector: variables, then inequality slacks
         L = lib()
         nbytes = L.mds_workspace_bytes(C.byref(self.dims), C.byref(self.opts))
         if nbytes == 0:
@@ -291,7 +302,10 @@ class Solver:
             b=self.dev(np.asarray(prob["b"], dtype=np.float64)),
             xl=self.dev(np.asarray(prob["xl"], dtype=np.float64)),
             xu=self.dev(np.asarray(prob["xu"], dtype=np.float64)),
+            hl=self.dev(np.asarray(prob.get("hl", np.zeros(0)), dtype=np.float64)),
+            hu=self.dev(np.asarray(prob.get("hu", np.zeros(0)), dtype=np.float64)),
         )
+        assert T["hl"].numel() == self.m_I and T["hu"].numel() == self.m_I
         assert T["H"].numel() == nd * nd and T["J_d"].numel() == m * nd
         self.P = T
         self.cp = Problem(*[_ptr(T[k]) for k, _ in Problem._fields_])
@@ -352,7 +366,7 @@ class Solver:
     # ---- vector kernels -------------------------------------------------
     def sigma_rhs(self, x, y, zl, zu, mu):
         a = [self.dev(v) for v in (x, y, zl, zu)]
-        sig, rx, ry = self.empty(self.n), self.empty(self.n), self.empty(self.m)
+        sig, rx, ry = self.empty(self.nx), self.empty(self.nx), self.empty(self.m)
         st = lib().mds_sigma_rhs(self.h, *[_ptr(t) for t in a], float(mu), _ptr(sig), _ptr(rx),
                                  _ptr(ry))
         self._check(st, "mds_sigma_rhs")
@@ -382,14 +396,15 @@ class Solver:
 
     # ---- IPM ------------------------------------------------------------
     def new_iterate(self):
-        it = dict(x=self.empty(self.n), y=self.empty(self.m), zl=self.empty(self.n),
-                  zu=self.empty(self.n))
+        it = dict(x=self.empty(self.nx), y=self.empty(self.m), zl=self.empty(self.nx),
+                  zu=self.empty(self.nx))
         it["c"] = Iterate(_ptr(it["x"]), _ptr(it["y"]), _ptr(it["zl"]), _ptr(it["zu"]),
                           0.0, 0.0, 0, 0)
         return it
 
-    def ipm_init(self, it, tol=1e-8, mu0=0.1, max_iter=200, refine_steps=2, dw_max=1e20):
-        self._opts = IpmOpts(tol, mu0, max_iter, refine_steps, dw_max)
+    def ipm_init(self, it, tol=1e-8, mu0=0.1, max_iter=200, refine_steps=2, dw_max=1e20,
+                 gmres_max=0):
+        self._opts = IpmOpts(tol, mu0, max_iter, refine_steps, dw_max, gmres_max, 0)
         st = lib().mds_ipm_init(self.h, C.byref(it["c"]), C.byref(self._opts))
         return self._check(st, "mds_ipm_init")
 
@@ -400,11 +415,11 @@ class Solver:
         return st, _step_dict(info)
 
     def ipm_solve_warm(self, x_d0, y0, mu0, tol=1e-8, max_iter=200, refine_steps=2,
-                       dw_max=1e20):
+                       dw_max=1e20, gmres_max=0):
         """IPM from a proposed start (mds_ipm_init_warm), stepped to the end."""
         it = self.new_iterate()
         xd, yy = self.dev(x_d0), self.dev(y0)
-        self._opts = IpmOpts(tol, float(mu0), max_iter, refine_steps, dw_max)
+        self._opts = IpmOpts(tol, float(mu0), max_iter, refine_steps, dw_max, gmres_max, 0)
         st = lib().mds_ipm_init_warm(self.h, C.byref(it["c"]), C.byref(self._opts), _ptr(xd),
                                      _ptr(yy), float(mu0))
         self._check(st, "mds_ipm_init_warm")
@@ -418,9 +433,10 @@ class Solver:
                     trace=trace, x=it["x"], y=it["y"], zl=it["zl"], zu=it["zu"],
                     mu=it["c"].mu)
 
-    def ipm_solve(self, it=None, tol=1e-8, mu0=0.1, max_iter=200, refine_steps=2, dw_max=1e20):
+    def ipm_solve(self, it=None, tol=1e-8, mu0=0.1, max_iter=200, refine_steps=2, dw_max=1e20,
+                  gmres_max=0):
         it = it if it is not None else self.new_iterate()
-        opts = IpmOpts(tol, mu0, max_iter, refine_steps, dw_max)
+        opts = IpmOpts(tol, mu0, max_iter, refine_steps, dw_max, gmres_max, 0)
         cap = max_iter + 2
         tr = (StepInfo * cap)()
         iters = C.c_int32()
@@ -439,6 +455,14 @@ class Solver:
         return dict(nb=i.nb, min_width=i.min_width, panel=("reg", "mem", "coop", "lds")[i.panel],
                     precision=prec, panel_threads=i.panel_threads,
                     workspace_bytes=i.workspace_bytes)
+
+    def fallbacks(self):
+        f = Fallbacks()
+        self._check(lib().mds_get_fallbacks(self.h, C.byref(f)), "mds_get_fallbacks")
+        return dict(coop_aborts=int(f.coop_aborts), fp64_refactors=int(f.fp64_refactors))
+
+    def set_debug(self, flags: int):
+        self._check(lib().mds_set_debug(self.h, int(flags)), "mds_set_debug")
 
     # ---- timing ---------------------------------------------------------
     def set_timing(self, enable: bool):
@@ -489,14 +513,15 @@ def _step_dict(s):
     return dict(mu=s.mu, E0=s.E0, theta=s.theta, phi=s.phi, alpha_pr=s.alpha_pr,
                 alpha_du=s.alpha_du, dw=s.delta_w, dc=s.delta_c, eta=s.eta,
                 inertia=tuple(s.inertia), trials=s.trials, solves=s.solves,
-                backtracks=s.backtracks, status=s.status)
+                backtracks=s.backtracks, status=s.status, fallback=s.fallback)
 
 
 def solver_for(prob: dict, nb: int = 0, device: str = "cuda:0", panel: str = "auto",
                precision: str = "fp64", panel_threads: int = 0) -> Solver:
     """Create a Solver sized for a problem dict and attach the problem."""
     s = Solver(prob["n_d"], prob["n_s"], prob["m"], len(prob["v"]), nb=nb, device=device,
-               panel=panel, precision=precision, panel_threads=panel_threads)
+               panel=panel, precision=precision, panel_threads=panel_threads,
+               m_I=int(prob.get("m_I", 0)))
     s.set_problem(prob)
     return s
 

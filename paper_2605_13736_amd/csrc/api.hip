@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdarg>
+#include <cstddef>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -83,8 +84,8 @@ int resolve_timings(mds_handle *h) {
 enum Slot {
   S_M, S_M2, S_SRC, S_W, S_DD, S_DS, S_IPIV, S_BLK, S_PK0, S_FST, S_INVD, S_CPTR, S_CROW, S_CVAL, S_CFILL,
   S_FLAGS, S_RED, S_SCAL, S_Z, S_Z2, S_HMAP, S_PERM, S_COLP, S_TRSV, S_SIG, S_RX, S_RY, S_DSB, S_DX, S_DY, S_DZL, S_DZU, S_XT, S_RES,
-  S_COR, S_PREV, S_KX, S_TN, S_TM, S_TN2, S_KNH, S_KNJD, S_KNY, S_KNJS, S_X32A, S_X32B, S_EQ, S_GV,
-  S_GZ, S_GRHS, S_GX, S_GW, S_GPART, S_GCOEF, S_XCH, S_COUNT
+  S_COR, S_PREV, S_KX, S_TN, S_TM, S_TN2, S_KNH, S_KNJD, S_KNY, S_KNJS, S_EQ, S_GV,
+  S_GZ, S_GRHS, S_GX, S_GW, S_GPART, S_GCOEF, S_XCH, S_XLE, S_XUE, S_DCV, S_RY2, S_COUNT
 };
 
 struct Layout {
@@ -96,14 +97,19 @@ int default_nb(int N) { return (N >= 64) ? 16 : 8; }
 
 Layout make_layout(const mds_dims &d, int nb, bool pingpong, int precision) {
   const size_t nd = d.n_d, ns = d.n_s, m = d.m, N = nd + m, n = nd + ns;
+  const size_t nx = n + (size_t)d.m_I;
   const size_t nnz = (size_t)d.nnz_s;
   const size_t maxp = N / (size_t)std::max(nb - 1, 1) + 2;
   size_t bytes[S_COUNT] = {};
   bytes[S_M] = 8 * N * N;
   const bool mixed = precision != MDS_FP64;
-  bytes[S_M2] = (pingpong && !mixed) ? 8 * N * N : 0;
-  bytes[S_X32A] = bytes[S_X32B] = mixed ? 4 * N * N : 0;
+  // ping-pong partner of M; in a mixed-precision handle the same bytes hold
+  // the two FP32 buffers of the trailing matrix (and serve as M2 again when
+  // a Newton system is refactored in FP64)
+  bytes[S_M2] = (pingpong || mixed) ? 8 * N * N : 0;
   bytes[S_EQ] = mixed ? 8 * N : 0;
+  bytes[S_XLE] = bytes[S_XUE] = 8 * nx;
+  bytes[S_DCV] = bytes[S_RY2] = 8 * m;
   const size_t nK = n + m, R = (size_t)kGmresRestart;
   bytes[S_GV] = mixed ? 8 * nK * (R + 1) : 0;
   bytes[S_GZ] = mixed ? 8 * nK * R : 0;
@@ -129,13 +135,13 @@ Layout make_layout(const mds_dims &d, int nb, bool pingpong, int precision) {
   bytes[S_HMAP] = 4 * maxp * N;
   bytes[S_PERM] = bytes[S_COLP] = 4 * N;
   bytes[S_TRSV] = 4 * (4 + 2 * (size_t)std_solve_blocks((int)N));
-  bytes[S_SIG] = bytes[S_RX] = 8 * n;
+  bytes[S_SIG] = bytes[S_RX] = 8 * nx;
   bytes[S_RY] = 8 * m;
   bytes[S_DSB] = 8 * ns;
-  bytes[S_DX] = bytes[S_DZL] = bytes[S_DZU] = bytes[S_XT] = 8 * n;
+  bytes[S_DX] = bytes[S_DZL] = bytes[S_DZU] = bytes[S_XT] = 8 * nx;
   bytes[S_DY] = 8 * m;
   bytes[S_RES] = bytes[S_COR] = bytes[S_PREV] = bytes[S_KX] = 8 * (n + m);
-  bytes[S_TN] = bytes[S_TN2] = 8 * n;
+  bytes[S_TN] = bytes[S_TN2] = 8 * nx;
   bytes[S_TM] = 8 * m;
   bytes[S_KNH] = bytes[S_KNJD] = 8 * nd;
   bytes[S_KNY] = 8 * m;
@@ -152,7 +158,8 @@ Layout make_layout(const mds_dims &d, int nb, bool pingpong, int precision) {
 }
 
 bool dims_ok(const mds_dims *d) {
-  return d && d->n_d >= 0 && d->n_s >= 0 && d->m >= 0 && d->nnz_s >= 0 &&
+  return d && d->n_d >= 0 && d->n_s >= 0 && d->m >= 0 && d->nnz_s >= 0 && d->m_I >= 0 &&
+         d->m_I <= d->m &&
          (int64_t)d->n_d + d->m <= std_max_n() && (int64_t)d->n_d + d->n_s < ((int64_t)1 << 30) &&
          d->nnz_s < ((int64_t)1 << 30);
 }
@@ -232,12 +239,20 @@ inline int MM(mds_handle *h) { return h->dims.m; }
 // ---- internal building blocks -------------------------------------------------
 
 int condense_impl(mds_handle *h, double dw, double dc) {
+  // (4,4) block of the inequality rows: the IPM's 1 / (Sigma_h + dw), which
+  // follows the shift, or the caller's fixed diagonal
+  h->dcv_cur = h->dcv_user;
+  if (h->sig_h && h->mI > 0) {
+    ipm_ineq_dcv(S(h), MM(h), h->mE, h->sig_h, dw, h->w.dcv);
+    h->dcv_cur = h->w.dcv;
+  }
   {
     TimedLaunch t(h, MDS_T_CONDENSE);
     launch_inv_d(S(h), NS(h), h->dsbase, dw, h->w.inv_d);
     launch_condense_dense(S(h), ND(h), MM(h), h->P.H, h->P.J_d, h->sigma_d, dw, h->w.M);
     launch_condense_schur(S(h), ND(h), MM(h), h->N, h->P.Js_rowptr, h->P.Js_col, h->P.Js_val,
-                          h->w.csc_ptr, h->w.csc_row, h->w.csc_val, h->w.inv_d, dc, h->dcv, h->w.M);
+                          h->w.csc_ptr, h->w.csc_row, h->w.csc_val, h->w.inv_d, dc, h->dcv_cur,
+                          h->w.M);
   }
   HIPCHK(hipGetLastError());
   h->dw = dw;
@@ -280,7 +295,7 @@ void factor_launches(mds_handle *h, hipStream_t s) {
     TimedLaunch t(h, MDS_T_PANEL);
     launch_bk_lds(s, h->panel_threads, N, h->alpha_bk, h->w.M, h->w.dd, h->w.ds, h->w.ipiv,
                   h->w.blk, h->w.perm, h->w.fst);
-  } else if (h->precision != MDS_FP64) {
+  } else if (h->precision != MDS_FP64 && !h->force64) {
     // mixed precision: the trailing matrix lives in the FP32 ping-pong
     // buffers; L (FP64) goes to M, which then holds the whole factor
     {
@@ -301,7 +316,8 @@ void factor_launches(mds_handle *h, hipStream_t s) {
       }
     }
   }
-  for (int b = 0; b < (h->precision == MDS_FP64 && !h->panel_lds ? slots : 0); ++b) {
+  const bool fp64 = h->precision == MDS_FP64 || h->force64;
+  for (int b = 0; b < (fp64 && !h->panel_lds ? slots : 0); ++b) {
     // register panel: slot b reads buffer b%2 and writes its L and the
     // updated trailing matrix into the other buffer
     double *X = h->w.M, *Y = h->w.M;
@@ -349,20 +365,62 @@ void capture_factor(mds_handle *h) {
   (void)hipGetLastError();
 }
 
+// FP64 factorization of M in place by the memory panel (no exchanges between
+// workgroups): the fallback of the cooperative panel.  Every panel advances
+// at least nb columns.
+void factor_launches_mem(mds_handle *h, hipStream_t s) {
+  const int N = h->N, nb = h->nb;
+  launch_fac_reset(s, h->w.fst, h->w.panel_k0);
+  const int slots = (N + nb - 1) / nb;
+  for (int b = 0; b < slots; ++b) {
+    {
+      TimedLaunch t(h, MDS_T_PANEL);
+      launch_bk_panel(s, N, nb, h->alpha_bk, h->w.M, h->w.W, h->w.dd, h->w.ds, h->w.ipiv,
+                      h->w.blk, h->w.fst, h->w.panel_k0);
+    }
+    if ((long)N - (long)(b + 1) * nb > 0) {
+      TimedLaunch t(h, MDS_T_TRAILING);
+      launch_bk_trailing(s, N, nb, nb, b, h->w.W, h->w.M, h->w.M, h->w.M, nullptr, h->w.fst,
+                         h->w.panel_k0);
+    }
+  }
+}
+
+int read_fac_state(mds_handle *h, FacState *st) {
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipMemcpyAsync(st, h->w.fst, sizeof(*st), hipMemcpyDeviceToHost, S(h)));
+  HIPCHK(hipStreamSynchronize(S(h)));
+  return MDS_OK;
+}
+
 int factor_impl(mds_handle *h, mds_inertia *out) {
   const int N = h->N;
-  const bool graph = !h->timing && !h->panel_lds && !h->fac_graph_off;
-  if (graph && !h->fac_exec) capture_factor(h);
-  if (graph && h->fac_exec) HIPCHK(hipGraphLaunch(h->fac_exec, S(h)));
-  else factor_launches(h, S(h));
-  HIPCHK(hipGetLastError());
   FacState st{};
-  HIPCHK(hipMemcpyAsync(&st, h->w.fst, sizeof(st), hipMemcpyDeviceToHost, S(h)));
-  HIPCHK(hipStreamSynchronize(S(h)));
-  if (st.xerr)
-    return set_err(h, MDS_EHIP,
-                   "panel aborted: cooperative exchange wait timed out, or rows beyond the register tile");
+  bool mem = h->coop_off;
+  if (!mem) {
+    const bool graph = !h->timing && !h->panel_lds && !h->fac_graph_off && !h->force64;
+    if (graph && !h->fac_exec) capture_factor(h);
+    if (graph && h->fac_exec) HIPCHK(hipGraphLaunch(h->fac_exec, S(h)));
+    else factor_launches(h, S(h));
+    TRY(read_fac_state(h, &st));
+    if (st.xerr && h->panel_coop) {
+      // an exchange wait of the cooperative panel expired (its workgroups
+      // were not all resident): condense again (the ping-pong buffers hold a
+      // partial factor) and factor in place with the memory panel
+      h->n_coop_abort++;
+      mem = true;
+      TRY(condense_impl(h, h->dw, h->dc));
+    } else if (st.xerr) {
+      return set_err(h, MDS_EHIP, "panel aborted: rows beyond the register tile");
+    }
+  }
+  if (mem) {
+    factor_launches_mem(h, S(h));
+    TRY(read_fac_state(h, &st));
+  }
   if (st.k != N) return set_err(h, MDS_EHIP, "factorization stopped at %d of %d", st.k, N);
+  h->fac_lowprec = !mem && !h->panel_lds && h->precision != MDS_FP64 && !h->force64;
+  h->fac_pingpong = !mem && h->panel_reg && !h->fac_lowprec;
   out->npos = st.npos;
   out->nzero = st.nzero;
   out->nneg = st.nneg;
@@ -378,7 +436,7 @@ int factor_impl(mds_handle *h, mds_inertia *out) {
 void ensure_std(mds_handle *h) {
   if (h->std_ready) return;
   TimedLaunch t(h, MDS_T_PERMUTE);
-  const int pingpong = (h->panel_reg && h->precision == MDS_FP64) ? 1 : 0;
+  const int pingpong = h->fac_pingpong ? 1 : 0;
   launch_std_form(S(h), h->N, h->w.M, h->w.M2, pingpong, h->w.ipiv, h->w.blk,
                   h->w.panel_k0, h->w.fst, h->w.hmap, h->w.perm, h->w.colpanel, h->w.M);
   h->std_ready = true;
@@ -442,10 +500,10 @@ int solve_impl(mds_handle *h, const double *r_d, const double *r_s, const double
   {
     TimedLaunch t(h, MDS_T_SOLVE);
     // mixed precision factors S M S: M^{-1} = S (S M S)^{-1} S
-    if (h->precision != MDS_FP64) launch_vscale(S(h), N, h->w.eq, h->w.z);
+    if (h->fac_lowprec) launch_vscale(S(h), N, h->w.eq, h->w.z);
     launch_std_solve(S(h), N, h->w.M, h->w.dd, h->w.ds, h->w.blk, h->w.perm, h->w.z, h->w.z2,
                      h->w.z, h->w.trsv);
-    if (h->precision != MDS_FP64) launch_vscale(S(h), N, h->w.eq, h->w.z);
+    if (h->fac_lowprec) launch_vscale(S(h), N, h->w.eq, h->w.z);
   }
   h->nsolves++;
   if (nd > 0) HIPCHK(hipMemcpyAsync(dx_d, h->w.z, 8 * (size_t)nd, hipMemcpyDeviceToDevice, S(h)));
@@ -473,8 +531,8 @@ void kkt_matvec(mds_handle *h, const double *dxd, const double *dxs, const doubl
       launch_spmv_csr(S(h), m, P.Js_rowptr, P.Js_col, P.Js_val, dxs, 0.0, oy);
     }
   }
-  kkt_finish(S(h), nd, ns, m, h->sigma_d, h->dsbase, h->dw, h->dc, h->dcv, dxd, dxs, dy, od, os,
-             oy);
+  kkt_finish(S(h), nd, ns, m, h->sigma_d, h->dsbase, h->dw, h->dc, h->dcv_cur, dxd, dxs, dy, od,
+             os, oy);
 }
 
 int read_scal(mds_handle *h, double *dst, int count) {
@@ -537,7 +595,7 @@ int gmres_refine(mds_handle *h, const double *r_d, const double *r_s, const doub
   vec_copy(S(h), m, r_y, r + nd + ns);
   TRY(solve_impl(h, r, r + nd, r + nd + ns, x, x + nd, x + nd + ns));
   kkt_norm_parts(S(h), nd, ns, m, h->P.H, h->sigma_d, h->dw, h->P.J_d, h->P.Js_rowptr,
-                 h->P.Js_val, h->w.csc_ptr, h->w.csc_val, h->dsbase, h->dc, h->dcv, h->w.kn_h,
+                 h->P.Js_val, h->w.csc_ptr, h->w.csc_val, h->dsbase, h->dc, h->dcv_cur, h->w.kn_h,
                  h->w.kn_jd, h->w.kn_y, h->w.kn_js, h->w.red, h->w.scal);
   HIPCHK(hipGetLastError());
   double s8[8];
@@ -633,7 +691,7 @@ int gmres_refine(mds_handle *h, const double *r_d, const double *r_s, const doub
 int refine_impl(mds_handle *h, const double *r_d, const double *r_s, const double *r_y,
                 double *dx_d, double *dx_s, double *dy, int max_steps, double eta_tol,
                 mds_refine_info *info) {
-  if (h->precision != MDS_FP64)
+  if (h->fac_lowprec)
     return gmres_refine(h, r_d, r_s, r_y, dx_d, dx_s, dy, max_steps, eta_tol, info);
   const int nd = ND(h), ns = NS(h), m = MM(h);
   const size_t nt = (size_t)nd + ns + m;
@@ -641,7 +699,7 @@ int refine_impl(mds_handle *h, const double *r_d, const double *r_s, const doubl
   TRY(solve_impl(h, r_d, r_s, r_y, dx_d, dx_s, dy));
   // ||K||_inf parts and ||r||_inf: two reductions, one read-back
   kkt_norm_parts(S(h), nd, ns, m, h->P.H, h->sigma_d, h->dw, h->P.J_d, h->P.Js_rowptr,
-                 h->P.Js_val, h->w.csc_ptr, h->w.csc_val, h->dsbase, h->dc, h->dcv, h->w.kn_h,
+                 h->P.Js_val, h->w.csc_ptr, h->w.csc_val, h->dsbase, h->dc, h->dcv_cur, h->w.kn_h,
                  h->w.kn_jd, h->w.kn_y, h->w.kn_js, h->w.red, h->w.scal);
   ipm_red_amax3(S(h), nd, r_d, ns, r_s, m, r_y, h->w.red, h->w.scal + 8);
   HIPCHK(hipGetLastError());
@@ -696,9 +754,11 @@ int refine_impl(mds_handle *h, const double *r_d, const double *r_s, const doubl
   return (eta <= eta_tol) ? MDS_OK : MDS_REFINE_NOCONV;
 }
 
-// gf = grad f(x) -> tn; jty = J'y -> tn2; cx = J x - b -> tm (and r_y = -cx if ry)
+// Over the IPM's primal vector x = [variables; slacks] (nx entries):
+// gf = grad f -> tn (0 on the slacks); jty = J'y -> tn2 (-y_h on the
+// slacks); cx = c(x) = J x - [b; d] -> tm (and r_y = -c if ry).
 void eval_grad_constr(mds_handle *h, const double *x, const double *y, double *ry) {
-  const int nd = ND(h), ns = NS(h), m = MM(h);
+  const int nd = ND(h), ns = NS(h), m = MM(h), n = h->n;
   const mds_problem &P = h->P;
   double *gf = h->w.tn, *jty = h->w.tn2, *cx = h->w.tm;
   launch_gemv_n(S(h), nd, nd, P.H, nd, x, 0.0, gf);
@@ -710,6 +770,7 @@ void eval_grad_constr(mds_handle *h, const double *x, const double *y, double *r
     }
     launch_spmv_csc(S(h), ns, h->w.csc_ptr, h->w.csc_row, h->w.csc_val, y, 0.0, jty + nd);
   }
+  ipm_slack_grad(S(h), h->mI, h->mE, y, gf + n, jty + n);
   if (m > 0) {
     if (nd > 0) {
       launch_gemv_n(S(h), m, nd, P.J_d, m, x, 0.0, cx);
@@ -717,16 +778,16 @@ void eval_grad_constr(mds_handle *h, const double *x, const double *y, double *r
     } else {
       launch_spmv_csr(S(h), m, P.Js_rowptr, P.Js_col, P.Js_val, x + nd, 0.0, cx);
     }
-    ipm_constr_finish(S(h), m, P.b, cx, ry);
+    ipm_constr_finish(S(h), m, h->mE, P.b, x + n, cx, ry);
   }
 }
 
 int opt_error_impl(mds_handle *h, const double *x, const double *y, const double *zl,
                    const double *zu, double mu, double *E, double *parts) {
-  const int n = h->n, m = MM(h);
+  const int n = h->nx, m = MM(h);
   const double s_max = 100.0;
   eval_grad_constr(h, x, y, nullptr);
-  ipm_red_opt(S(h), n, m, x, y, zl, zu, h->P.xl, h->P.xu, h->w.tn, h->w.tn2, h->w.tm, mu,
+  ipm_red_opt(S(h), n, m, x, y, zl, zu, h->w.xl_e, h->w.xu_e, h->w.tn, h->w.tn2, h->w.tm, mu,
               h->w.red, h->w.scal);
   HIPCHK(hipGetLastError());
   double s[8];
@@ -750,11 +811,11 @@ int opt_error_impl(mds_handle *h, const double *x, const double *y, const double
 // E_0 and E_mu at one mu from one reduction pass and one read-back.
 int opt_error_pair(mds_handle *h, const double *x, const double *y, const double *zl,
                    const double *zu, double mu, double *E0, double *Emu) {
-  const int n = h->n, m = MM(h);
+  const int n = h->nx, m = MM(h);
   const double s_max = 100.0;
   eval_grad_constr(h, x, y, nullptr);
-  ipm_red_opt_pair(S(h), n, m, x, y, zl, zu, h->P.xl, h->P.xu, h->w.tn, h->w.tn2, h->w.tm, mu,
-                   h->w.red, h->w.scal);
+  ipm_red_opt_pair(S(h), n, m, x, y, zl, zu, h->w.xl_e, h->w.xu_e, h->w.tn, h->w.tn2, h->w.tm,
+                   mu, h->w.red, h->w.scal);
   HIPCHK(hipGetLastError());
   double s[8];
   TRY(read_scal(h, s, 8));
@@ -767,8 +828,9 @@ int opt_error_pair(mds_handle *h, const double *x, const double *y, const double
   return MDS_OK;
 }
 
-// Launches the merit reductions at x into out[0..7] (slot 4: f, 5: sum of
-// log-slacks, 6: theta); h->w.tn and h->w.tm are overwritten.
+// Launches the merit reductions at x = [variables; slacks] into out[0..7]
+// (slot 4: f, 5: sum of log-slacks of the variables and the slacks, 6:
+// theta); h->w.tn and h->w.tm are overwritten.
 void merit_launch(mds_handle *h, const double *x, double *out) {
   const int nd = ND(h), ns = NS(h), m = MM(h);
   const mds_problem &P = h->P;
@@ -781,9 +843,10 @@ void merit_launch(mds_handle *h, const double *x, double *out) {
     } else {
       launch_spmv_csr(S(h), m, P.Js_rowptr, P.Js_col, P.Js_val, x + nd, 0.0, cx);
     }
-    ipm_constr_finish(S(h), m, P.b, cx, nullptr);
+    ipm_constr_finish(S(h), m, h->mE, P.b, x + h->n, cx, nullptr);
   }
-  ipm_red_merit(S(h), nd, ns, m, x, hx, P.c, P.w, P.g, P.xl, P.xu, cx, h->w.red, out);
+  ipm_red_merit(S(h), nd, ns, h->nx, m, x, hx, P.c, P.w, P.g, h->w.xl_e, h->w.xu_e, cx,
+                h->w.red, out);
 }
 
 int merit_impl(mds_handle *h, const double *x, double mu, double *f, double *phi, double *theta) {
@@ -827,6 +890,14 @@ int mds_create(mds_handle **out, const mds_dims *dims, const mds_options *opts, 
   if (nb == 0) return MDS_EINVAL;
   const int prec = opts ? opts->precision : MDS_FP64;
   const Layout L = make_layout(*dims, nb, panel_of(*dims, opts).reg, prec);
+  const PanelChoice pc = panel_of(*dims, opts);
+  // every workgroup of the cooperative panel must be resident at once; if
+  // the device cannot guarantee it, the memory panel (FP64) factors instead
+  bool coop_off = false;
+  if (pc.coop && !bk_coop_resident(dims->n_d + dims->m)) {
+    if (prec != MDS_FP64) return MDS_EINVAL;
+    coop_off = true;
+  }
   if (!workspace) return MDS_ENULL;
   if (workspace_bytes < L.total || ((uintptr_t)workspace & 255) != 0) return MDS_EWORKSPACE;
   mds_handle *h = new (std::nothrow) mds_handle();
@@ -839,7 +910,10 @@ int mds_create(mds_handle **out, const mds_dims *dims, const mds_options *opts, 
   h->dims = *dims;
   h->N = dims->n_d + dims->m;
   h->n = dims->n_d + dims->n_s;
-  const PanelChoice pc = panel_of(*dims, opts);
+  h->mI = dims->m_I;
+  h->mE = dims->m - dims->m_I;
+  h->nx = h->n + h->mI;
+  h->coop_off = coop_off;
   h->nb = nb;
   h->panel_reg = pc.reg;
   h->panel_coop = pc.coop;
@@ -857,8 +931,12 @@ int mds_create(mds_handle **out, const mds_dims *dims, const mds_options *opts, 
   Work &w = h->w;
   w.M = D(S_M);
   w.M2 = D(S_M2);
-  w.X32[0] = (float *)(base + L.off[S_X32A]);
-  w.X32[1] = (float *)(base + L.off[S_X32B]);
+  w.X32[0] = (float *)(base + L.off[S_M2]);
+  w.X32[1] = w.X32[0] + (size_t)h->N * (size_t)h->N;
+  w.xl_e = D(S_XLE);
+  w.xu_e = D(S_XUE);
+  w.dcv = D(S_DCV);
+  w.ry2 = D(S_RY2);
   w.eq = D(S_EQ);
   w.gV = D(S_GV);
   w.gZ = D(S_GZ);
@@ -936,15 +1014,20 @@ int mds_set_problem(mds_handle *h, const mds_problem *p) {
   if (!h || !p) return MDS_ENULL;
   const mds_dims &d = h->dims;
   const int64_t nd = d.n_d, ns = d.n_s, m = d.m;
+  const int64_t mI = d.m_I, mE = m - mI;
   if ((nd > 0 && (!p->H || !p->c)) || (ns > 0 && (!p->w || !p->g)) ||
-      (m > 0 && nd > 0 && !p->J_d) || (m > 0 && !p->b) || !p->Js_rowptr ||
-      (d.nnz_s > 0 && (!p->Js_col || !p->Js_val)) || (nd + ns > 0 && (!p->xl || !p->xu)))
+      (m > 0 && nd > 0 && !p->J_d) || (mE > 0 && !p->b) || !p->Js_rowptr ||
+      (d.nnz_s > 0 && (!p->Js_col || !p->Js_val)) || (nd + ns > 0 && (!p->xl || !p->xu)) ||
+      (mI > 0 && (!p->hl || !p->hu)))
     return set_err(h, MDS_ENULL, "problem array missing");
   h->have_problem = false;
   h->have_M = h->have_factor = false;
   h->ipm_ready = false;
+  h->dcv_user = h->dcv_cur = nullptr;
+  h->sig_h = nullptr;
   HIPCHK(hipMemsetAsync(h->w.flags, 0, 64, S(h)));
   launch_validate(S(h), d, *p, h->w.flags);
+  check_ineq_bounds(S(h), (int)mI, p->hl, p->hu, h->w.flags + 5);
   HIPCHK(hipGetLastError());
   int32_t f[16];
   HIPCHK(hipMemcpyAsync(f, h->w.flags, 64, hipMemcpyDeviceToHost, S(h)));
@@ -954,7 +1037,15 @@ int mds_set_problem(mds_handle *h, const mds_problem *p) {
   if (f[1]) return set_err(h, MDS_EDS_NONPOS, "w has a negative entry");
   if (f[2]) return set_err(h, MDS_EDS_NONPOS, "bounds violate xl < xu");
   if (f[4]) return set_err(h, MDS_EINVAL, "H is not exactly symmetric");
+  if (f[5])
+    return set_err(h, MDS_EDS_NONPOS,
+                   "inequality bounds violate hl < hu or are both infinite");
   h->P = *p;
+  // bounds of the IPM's primal vector: the variables', then the slacks'
+  vec_copy(S(h), nd + ns, p->xl, h->w.xl_e);
+  vec_copy(S(h), nd + ns, p->xu, h->w.xu_e);
+  vec_copy(S(h), mI, p->hl, h->w.xl_e + nd + ns);
+  vec_copy(S(h), mI, p->hu, h->w.xu_e + nd + ns);
   launch_csc_build(S(h), (int)m, (int)ns, d.nnz_s, p->Js_rowptr, p->Js_col, p->Js_val,
                    h->w.csc_ptr, h->w.csc_row, h->w.csc_val, h->w.csc_fill);
   HIPCHK(hipGetLastError());
@@ -986,7 +1077,7 @@ int mds_set_m22_diag(mds_handle *h, const double *dcv) {
     HIPCHK(hipStreamSynchronize(S(h)));
     if (bad) return set_err(h, MDS_EINVAL, "M22 diagonal: entries must be finite and nonnegative");
   }
-  h->dcv = (MM(h) > 0) ? dcv : nullptr;
+  h->dcv_user = (MM(h) > 0) ? dcv : nullptr;
   h->have_M = false;
   h->have_factor = false;
   return MDS_OK;
@@ -1030,10 +1121,10 @@ int mds_refine(mds_handle *h, const double *r_d, const double *r_s, const double
 int mds_sigma_rhs(mds_handle *h, const double *x, const double *y, const double *zl,
                   const double *zu, double mu, double *sigma, double *r_x, double *r_y) {
   TRY(check_ready(h));
-  if ((h->n > 0 && (!x || !zl || !zu || !sigma || !r_x)) || (MM(h) > 0 && (!y || !r_y)))
+  if ((h->nx > 0 && (!x || !zl || !zu || !sigma || !r_x)) || (MM(h) > 0 && (!y || !r_y)))
     return set_err(h, MDS_ENULL, "vector missing");
   eval_grad_constr(h, x, y, r_y);
-  ipm_sigma_rhs(S(h), h->n, x, zl, zu, h->P.xl, h->P.xu, h->w.tn, h->w.tn2, mu, sigma, r_x);
+  ipm_sigma_rhs(S(h), h->nx, x, zl, zu, h->w.xl_e, h->w.xu_e, h->w.tn, h->w.tn2, mu, sigma, r_x);
   HIPCHK(hipGetLastError());
   return MDS_OK;
 }
@@ -1068,14 +1159,47 @@ int mds_merit(mds_handle *h, const double *x, double mu, double *f_host, double 
   return merit_impl(h, x, mu, f_host, phi_host, theta_host);
 }
 
+}  // extern "C"
+
+namespace {
+
+// Slacks of the inequality rows at the start: the row values of J_h x pushed
+// into [hl, hu] (x holds the start's variables).
+void init_slacks(mds_handle *h, double *x) {
+  if (h->mI <= 0) return;
+  const int nd = ND(h), m = MM(h), n = h->n;
+  const mds_problem &P = h->P;
+  double *cx = h->w.tm;
+  if (nd > 0) {
+    launch_gemv_n(S(h), m, nd, P.J_d, m, x, 0.0, cx);
+    launch_spmv_csr(S(h), m, P.Js_rowptr, P.Js_col, P.Js_val, x + nd, 1.0, cx);
+  } else {
+    launch_spmv_csr(S(h), m, P.Js_rowptr, P.Js_col, P.Js_val, x + nd, 0.0, cx);
+  }
+  ipm_slack_project(S(h), h->mI, cx + h->mE, P.hl, P.hu, x + n);
+}
+
+int ipm_opts_check(mds_handle *h, mds_iterate *it) {
+  if (!it || (h->nx > 0 && (!it->x || !it->zl || !it->zu)) || (MM(h) > 0 && !it->y))
+    return set_err(h, MDS_ENULL, "iterate missing");
+  if (h->dcv_user)
+    return set_err(h, MDS_ESTATE,
+                   "a caller's M22 diagonal is set: the IPM forms that block from its slacks");
+  return MDS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 int mds_ipm_init(mds_handle *h, mds_iterate *it, const mds_ipm_opts *opts) {
   TRY(check_ready(h));
-  if (!it || (h->n > 0 && (!it->x || !it->zl || !it->zu)) || (MM(h) > 0 && !it->y))
-    return set_err(h, MDS_ENULL, "iterate missing");
-  mds_ipm_opts o{1e-8, 0.1, 200, 2, 1e20};
+  TRY(ipm_opts_check(h, it));
+  mds_ipm_opts o{1e-8, 0.1, 200, 2, 1e20, 0, 0};
   if (opts) o = *opts;
   h->ipm = o;
-  ipm_init_point(S(h), h->n, MM(h), h->P.xl, h->P.xu, it->x, it->y, it->zl, it->zu);
+  ipm_init_point(S(h), h->nx, MM(h), h->w.xl_e, h->w.xu_e, it->x, it->y, it->zl, it->zu);
+  init_slacks(h, it->x);
   HIPCHK(hipGetLastError());
   it->mu = o.mu0;
   it->tau = std::max(0.99, 1.0 - it->mu);
@@ -1093,18 +1217,23 @@ int mds_ipm_init(mds_handle *h, mds_iterate *it, const mds_ipm_opts *opts) {
 int mds_ipm_init_warm(mds_handle *h, mds_iterate *it, const mds_ipm_opts *opts,
                       const double *x_d0, const double *y0, double mu0) {
   TRY(check_ready(h));
-  if (!it || (h->n > 0 && (!it->x || !it->zl || !it->zu)) || (MM(h) > 0 && !it->y))
-    return set_err(h, MDS_ENULL, "iterate missing");
+  TRY(ipm_opts_check(h, it));
   if ((ND(h) > 0 && !x_d0) || (MM(h) > 0 && !y0)) return set_err(h, MDS_ENULL, "start point missing");
   if (!(mu0 > 0.0) || !std::isfinite(mu0)) return set_err(h, MDS_EINVAL, "mu0 must be positive");
-  mds_ipm_opts o{1e-8, 0.1, 200, 2, 1e20};
+  mds_ipm_opts o{1e-8, 0.1, 200, 2, 1e20, 0, 0};
   if (opts) o = *opts;
   h->ipm = o;
+  // the slacks' entries first take the cold start's values (multipliers
+  // mu0 / slack below), then the variables' warm values and the slacks
+  ipm_init_point(S(h), h->nx, 0, h->w.xl_e, h->w.xu_e, it->x, it->y, it->zl, it->zu);
   ipm_init_warm(S(h), ND(h), NS(h), MM(h), h->P.xl, h->P.xu, h->P.w, h->P.g, h->w.csc_ptr,
                 h->w.csc_row, h->w.csc_val, x_d0, y0, mu0, it->x, it->y, it->zl, it->zu);
+  init_slacks(h, it->x);
+  ipm_slack_duals(S(h), h->mI, h->w.xl_e + h->n, h->w.xu_e + h->n, it->x + h->n, mu0,
+                  it->zl + h->n, it->zu + h->n);
   eval_grad_constr(h, it->x, MM(h) > 0 ? it->y : nullptr, nullptr);
   if (MM(h) == 0 && h->n > 0) HIPCHK(hipMemsetAsync(h->w.tn2, 0, 8 * (size_t)h->n, S(h)));
-  ipm_warm_duals(S(h), h->n, h->P.xl, h->P.xu, h->w.tn, h->w.tn2, it->zl, it->zu);
+  ipm_warm_duals(S(h), h->nx, h->w.xl_e, h->w.xu_e, h->w.tn, h->w.tn2, it->zl, it->zu);
   HIPCHK(hipGetLastError());
   it->mu = mu0;
   it->tau = std::max(0.99, 1.0 - it->mu);
@@ -1129,8 +1258,9 @@ static int ipm_step_impl(mds_handle *h, mds_iterate *it, mds_step_info *info, bo
   const double tau_min = 0.99, kappa_eps = 10.0, kappa_mu = 0.2, theta_mu = 1.5;
   const double gamma_theta = 1e-5, gamma_phi = 1e-8, delta = 1.0, s_theta = 1.1, s_phi = 2.3;
   const double eta_phi = 1e-8, gamma_alpha = 0.05;
-  const int nd = ND(h), ns = NS(h), m = MM(h), n = h->n;
+  const int nd = ND(h), ns = NS(h), m = MM(h), n = h->nx;  // n: variables + slacks
   const mds_problem &P = h->P;
+  const double *xl = h->w.xl_e, *xu = h->w.xu_e;
   mds_step_info loc{};
   mds_step_info &I = info ? *info : loc;
   memset(&I, 0, sizeof(I));
@@ -1156,43 +1286,71 @@ static int ipm_step_impl(mds_handle *h, mds_iterate *it, mds_step_info *info, bo
     h->filter.clear();
   }
   I.mu = mu;
-  // Newton system with inertia correction and refinement
-  double *sig = h->w.sig, *rx = h->w.rx, *ry = h->w.ry, *dsb = h->w.dsb;
+  // Newton system with inertia correction and refinement.  With inequality
+  // rows the slack step is eliminated: their (4,4) diagonal is
+  // 1 / (Sigma_h + dw) (formed by every condensation of the correction loop)
+  // and their rhs gains dcv .* r_d.
+  double *sig = h->w.sig, *rx = h->w.rx, *ry = h->w.ry, *ry2 = h->w.ry2, *dsb = h->w.dsb;
   double *dx = h->w.dx, *dy = h->w.dy, *dzl = h->w.dzl, *dzu = h->w.dzu, *xt = h->w.xt;
   TRY(mds_sigma_rhs(h, x, y, zl, zu, mu, sig, rx, ry));
   ipm_dsbase(S(h), nd, ns, P.w, sig, dsb);
   h->sigma_d = sig;
   h->dsbase = dsb;
-  mds_reg reg{};
-  reg.delta_w_last = h->dw_last;
-  reg.delta_w_max = h->ipm.dw_max;
+  h->sig_h = (h->mI > 0) ? sig + h->n : nullptr;
+  const int64_t coop_aborts0 = h->n_coop_abort;
+  const double dw_last0 = h->dw_last;
   mds_inertia in{};
-  int fst = correct_impl(h, &reg, mu, &in);
-  if (fst < 0) return fst;
-  h->dw_last = reg.delta_w_last;
-  I.delta_w = reg.delta_w;
-  I.delta_c = reg.delta_c;
-  I.inertia[0] = in.npos;
-  I.inertia[1] = in.nzero;
-  I.inertia[2] = in.nneg;
-  I.trials = reg.trials;
-  if (fst == MDS_INERTIA_FAIL) return I.status = MDS_INERTIA_FAIL;
+  // correction loop, then the condensed solve refined on the full system
+  auto newton = [&](int rsteps, mds_refine_info *ri) -> int {
+    mds_reg reg{};
+    reg.delta_w_last = dw_last0;
+    reg.delta_w_max = h->ipm.dw_max;
+    const int fst = correct_impl(h, &reg, mu, &in);
+    if (fst < 0) return fst;
+    h->dw_last = reg.delta_w_last;
+    I.delta_w = reg.delta_w;
+    I.delta_c = reg.delta_c;
+    I.inertia[0] = in.npos;
+    I.inertia[1] = in.nzero;
+    I.inertia[2] = in.nneg;
+    I.trials += reg.trials;
+    if (fst == MDS_INERTIA_FAIL) return fst;
+    vec_copy(S(h), m, ry, ry2);
+    ipm_ineq_rhs(S(h), h->mI, h->mE, h->w.dcv, rx + h->n, ry2);
+    const int rst = refine_impl(h, rx, rx + nd, ry2, dx, dx + nd, dy, rsteps, 1e-14, ri);
+    if (rst < 0) return rst;
+    I.solves += 1 + ri->steps;
+    return rst;
+  };
   mds_refine_info ri{};
   // mixed precision: the refinement budget counts GMRES iterations
   const int rsteps = (h->precision == MDS_FP64) ? h->ipm.refine_steps
-                                                : std::max(h->ipm.refine_steps, 60);
-  int rst = refine_impl(h, rx, rx + nd, ry, dx, dx + nd, dy, rsteps, 1e-14, &ri);
+                     : (h->ipm.gmres_max > 0) ? h->ipm.gmres_max : 60;
+  int rst = newton(rsteps, &ri);
+  if (rst == MDS_REFINE_NOCONV && h->fac_lowprec) {
+    // the low-precision factor did not precondition GMRES down to the
+    // tolerance: redo this Newton system from an FP64 factorization
+    h->force64 = true;
+    rst = newton(h->ipm.refine_steps, &ri);
+    h->force64 = false;
+    h->n_fp64_refactor++;
+    I.fallback |= 1;
+  }
+  h->sig_h = nullptr;
+  if (h->n_coop_abort != coop_aborts0) I.fallback |= 2;
   if (rst < 0) return rst;
+  if (rst == MDS_INERTIA_FAIL) return I.status = MDS_INERTIA_FAIL;
   I.eta = ri.eta;
-  I.solves = 1 + ri.steps;
+  // slack step from the multiplier step: dd = dcv .* (r_d + dy_h)
+  ipm_ineq_step(S(h), h->mI, h->mE, h->w.dcv, rx + h->n, dy, dx + h->n);
   // fraction to the boundary, grad(phi_mu)' dx and the merit values at x:
   // three reductions into separate records, read back together
-  ipm_dz(S(h), n, x, zl, zu, P.xl, P.xu, dx, mu, dzl, dzu);
-  ipm_red_ftb(S(h), n, x, P.xl, P.xu, dx, zl, zu, dzl, dzu, tau, h->w.red, h->w.scal);
+  ipm_dz(S(h), n, x, zl, zu, xl, xu, dx, mu, dzl, dzu);
+  ipm_red_ftb(S(h), n, x, xl, xu, dx, zl, zu, dzl, dzu, tau, h->w.red, h->w.scal);
   // grad f at x (the refinement used the scratch), read by the gphi reduction
   // before the merit products overwrite it
   eval_grad_constr(h, x, nullptr, nullptr);
-  ipm_red_gphi(S(h), n, h->w.tn, x, P.xl, P.xu, dx, mu, h->w.red, h->w.scal + 8);
+  ipm_red_gphi(S(h), n, h->w.tn, x, xl, xu, dx, mu, h->w.red, h->w.scal + 8);
   merit_launch(h, x, h->w.scal + 16);
   HIPCHK(hipGetLastError());
   double s24[24];
@@ -1245,7 +1403,7 @@ static int ipm_step_impl(mds_handle *h, mds_iterate *it, mds_step_info *info, bo
     return I.status = MDS_IPM_LS_FAIL;
   }
   if (augment) h->filter.emplace_back((1.0 - gamma_theta) * th, ph - gamma_phi * th);
-  ipm_accept(S(h), n, m, xt, x, y, dy, zl, zu, dzl, dzu, P.xl, P.xu, alpha, a_du, mu);
+  ipm_accept(S(h), n, m, xt, x, y, dy, zl, zu, dzl, dzu, xl, xu, alpha, a_du, mu);
   HIPCHK(hipGetLastError());
   if (sync_end) HIPCHK(hipStreamSynchronize(S(h)));
   it->mu = mu;
@@ -1326,6 +1484,24 @@ int mds_get_info(const mds_handle *h, mds_info *out) {
   out->precision = h->precision;
   out->panel_threads = (h->panel_reg || h->panel_lds) ? h->panel_threads : 1024;
   out->workspace_bytes = (int64_t)h->ws_bytes;
+  return MDS_OK;
+}
+
+int mds_get_fallbacks(const mds_handle *h, mds_fallbacks *out) {
+  if (!h || !out) return MDS_ENULL;
+  out->coop_aborts = h->n_coop_abort;
+  out->fp64_refactors = h->n_fp64_refactor;
+  return MDS_OK;
+}
+
+int mds_set_debug(mds_handle *h, int32_t flags) {
+  if (!h) return MDS_ENULL;
+  if (flags & ~(int32_t)MDS_DEBUG_COOP_ABORT) return set_err(h, MDS_EINVAL, "unknown debug flag");
+  const int32_t force = (flags & MDS_DEBUG_COOP_ABORT) ? 1 : 0;
+  // FacState::xforce, read by every cooperative panel launch
+  HIPCHK(hipMemcpyAsync((char *)h->w.fst + offsetof(FacState, xforce), &force, sizeof(force),
+                        hipMemcpyHostToDevice, S(h)));
+  HIPCHK(hipStreamSynchronize(S(h)));
   return MDS_OK;
 }
 

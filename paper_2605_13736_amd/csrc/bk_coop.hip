@@ -98,7 +98,7 @@ __global__ __launch_bounds__(T) void k_bk_panel_coop(int N, int nb, double alpha
   __shared__ double s_xb[PMAX + 3][NR];  // X1: candidate rows, then position rows
   __shared__ double s_xwic[3];
   __shared__ double s_colmax, s_rowmax, s_aii;
-  __shared__ int s_imax, s_gw, s_k0, s_abort;
+  __shared__ int s_imax, s_gw, s_k0, s_abort, s_force;
   __shared__ uint32_t s_tag0;
 
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
@@ -107,6 +107,7 @@ __global__ __launch_bounds__(T) void k_bk_panel_coop(int N, int nb, double alpha
     s_k0 = st->k;
     s_tag0 = st->xtag;
     s_abort = st->xerr;
+    s_force = st->xforce;
   }
   if (tid < NB) {
     s_wk[tid] = 0.0;
@@ -118,6 +119,11 @@ __global__ __launch_bounds__(T) void k_bk_panel_coop(int N, int nb, double alpha
   __syncthreads();
   const int k0 = s_k0;
   if (k0 >= N || s_abort) return;
+  if (s_force) {
+    // host-set test flag: report an expired exchange wait without waiting
+    if (tid == 0) __hip_atomic_store(&st->xerr, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return;
+  }
   const int P = min(Pmax, (N - k0 + RW - 1) / RW);
   if (g >= P) return;
   const int ld = N;  // N <= 20480: every offset fits in 32 bits
@@ -652,6 +658,36 @@ constexpr int kCoopP = (kCoopMaxN + kCoopT * kCoopR - 1) / (kCoopT * kCoopR);
 }  // namespace
 
 int bk_coop_rows_per_wg() { return kCoopT * kCoopR; }
+
+// Occupancy of the instantiation used at order N times the compute units must
+// cover its workgroups: they spin on each other's exchange words.
+bool bk_coop_resident(int N) {
+  const int P = (N + kCoopT * kCoopR - 1) / (kCoopT * kCoopR);
+  int dev = 0, cus = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  hipError_t e;
+  if (P <= 4)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &per, k_bk_panel_coop<kCoopT, kCoopR, kCoopNB, 4, double>, kCoopT, 0);
+  else if (P <= 8)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &per, k_bk_panel_coop<kCoopT, kCoopR, kCoopNB, 8, double>, kCoopT, 0);
+  else if (P <= 12)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &per, k_bk_panel_coop<kCoopT, kCoopR, kCoopNB, 12, double>, kCoopT, 0);
+  else
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &per, k_bk_panel_coop<kCoopT, kCoopR, kCoopNB, kCoopP, double>, kCoopT, 0);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return (long)per * cus >= P;
+}
 int bk_coop_nb() { return kCoopNB; }
 int bk_coop_wgs(int N) { return (N + kCoopT * kCoopR - 1) / (kCoopT * kCoopR); }
 

@@ -309,7 +309,7 @@ void launch_validate(hipStream_t s, const mds_dims &d, const mds_problem &p, int
   fin(ns, p.g);
   fin(m * nd, p.J_d);
   fin(d.nnz_s, p.Js_val);
-  fin(m, p.b);
+  fin(m - d.m_I, p.b);  // the equality rows' right-hand side
   if (ns > 0) k_check_w<<<grid1(ns, 256), 256, 0, s>>>(ns, p.w, flags);
   if (n > 0) k_check_bounds<<<grid1(n, 256), 256, 0, s>>>(n, p.xl, p.xu, flags);
   k_check_pattern<<<grid1(m + 1, 256), 256, 0, s>>>((int)m, (int)ns, d.nnz_s, p.Js_rowptr,

@@ -28,6 +28,7 @@ struct FacState {
   int32_t npos, nzero, nneg, n2x2;
   uint32_t xtag;  // cooperative panel: launch counter behind its exchange tags (never reset)
   int32_t xerr;   // cooperative panel: an exchange wait expired
+  int32_t xforce; // host-set test flag: cooperative launches report an expired wait at once
 };
 
 // Pointers into the caller's workspace.
@@ -59,10 +60,15 @@ struct Work {
   int32_t *trsv;      // solve epoch, error word, pad, per-block flags (2 x blocks)
   uint64_t *xch;      // cooperative panel exchange words
   // Newton / IPM vectors
-  double *sig, *rx, *ry, *dsb;       // n, n, m, n_s
-  double *dx, *dy, *dzl, *dzu, *xt;  // n, m, n, n, n
+  // (vectors of length nx = n + m_I hold the variables, then the slacks of
+  // the inequality rows)
+  double *sig, *rx, *ry, *dsb;       // nx, nx, m, n_s
+  double *dx, *dy, *dzl, *dzu, *xt;  // nx, m, nx, nx, nx
+  double *xl_e, *xu_e;               // nx: bounds of the variables, then of the slacks
+  double *dcv;                       // m: the IPM's (4,4) diagonal 1 / (Sigma_h + dw) (0 on equality rows)
+  double *ry2;                       // m: rhs of the y rows with the slack step eliminated
   double *res, *cor, *prev, *kx;     // n + m each (refinement)
-  double *tn, *tm, *tn2;             // scratch n, m, n
+  double *tn, *tm, *tn2;             // scratch nx, m, nx
   double *kn_h, *kn_jd, *kn_y, *kn_js;  // ||K||_inf row-sum scratch: n_d, n_d, m, n_s
   // GMRES refinement (mixed precision): basis V (nK x (restart+1)), Z = P^{-1} V
   // (nK x restart), rhs, iterate, residual / work vector, dot partials, coefficients
@@ -76,11 +82,20 @@ struct mds_handle {
   hipStream_t stream = nullptr;
   mds_dims dims{};
   int N = 0, n = 0, nb = 16, max_panels = 0;
+  int mI = 0, mE = 0, nx = 0;  // inequality rows, equality rows, n + mI
   bool panel_reg = false;  // register-resident panel kernel (ping-pong layout)
   bool panel_coop = false; // ... spread over several workgroups
   bool panel_tail = false; // ... with the register panel once its rows fit one workgroup
   bool panel_lds = false;  // whole M in one workgroup's LDS, unblocked
-  const double *dcv = nullptr;  // optional per-row diagonal subtracted from M22 (m)
+  const double *dcv_user = nullptr;  // caller's per-row diagonal subtracted from M22 (m)
+  const double *dcv_cur = nullptr;   // diagonal of the current M: dcv_user or w.dcv
+  const double *sig_h = nullptr;     // IPM: slack barrier diagonal (mI) behind w.dcv
+  // factorization mode and the kind of the current factor
+  bool force64 = false;     // factor in FP64 in a mixed-precision handle
+  bool coop_off = false;    // cooperative panel not co-resident: memory panel always
+  bool fac_lowprec = false; // current factor is of the equilibrated FP32 matrix
+  bool fac_pingpong = false;// current factor's L is spread over M and M2
+  int64_t n_coop_abort = 0, n_fp64_refactor = 0;
   // captured launch sequence of one factorization (replayed without timing)
   hipGraphExec_t fac_exec = nullptr;
   hipStream_t cap_stream = nullptr;
@@ -168,6 +183,8 @@ void launch_bk_panel_reg(hipStream_t s, int threads, int N, int nb, double alpha
 // to the solver limit; X in FP64 or FP32); xch: 2 * kCoopMaxP * kCoopSlotWords
 // exchange words, zeroed once
 int bk_coop_rows_per_wg();
+// whether the device can hold every workgroup of the panel for order N at once
+bool bk_coop_resident(int N);
 int bk_coop_nb();
 int bk_coop_wgs(int N);
 void launch_bk_panel_coop(hipStream_t s, int N, int nb, double alpha, const double *X,

@@ -131,14 +131,87 @@ __global__ void k_sigma_rhs(int n, const double *__restrict__ x, const double *_
   rx[i] = -gb;
 }
 
-// cx holds J x on entry; becomes J x - b, and r_y = -(J x - b).
-__global__ void k_constr_finish(int m, const double *__restrict__ b, double *__restrict__ cx,
+// cx holds J x on entry; becomes c = J x - [b; d] (equality rows against b,
+// inequality rows against their slack d), and r_y = -c.
+__global__ void k_constr_finish(int m, int mE, const double *__restrict__ b,
+                                const double *__restrict__ d, double *__restrict__ cx,
                                 double *__restrict__ ry) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= m) return;
-  const double t = cx[i] - b[i];
+  const double t = cx[i] - ((i < mE) ? b[i] : d[i - mE]);
   cx[i] = t;
   if (ry) ry[i] = -t;
+}
+
+// Slack entries of the Lagrangian gradient (Sec. 2, eq. (ineq) turned into
+// J_h x - d = 0): the objective does not depend on d, and the slack column
+// of the constraint Jacobian is -I, so grad f = 0 and J'y = -y_h there.
+// y may be null (gradient only).
+__global__ void k_slack_grad(int mI, int mE, const double *__restrict__ y,
+                             double *__restrict__ gf_t, double *__restrict__ jty_t) {
+  int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= mI) return;
+  gf_t[r] = 0.0;
+  if (y) jty_t[r] = -y[mE + r];
+}
+
+// d = row value of J_h x (in hx) pushed into the interior of [hl, hu] by
+// the start point's rule for bounded variables.
+__global__ void k_slack_project(int mI, const double *__restrict__ hx,
+                                const double *__restrict__ hl, const double *__restrict__ hu,
+                                double *__restrict__ d) {
+  const double kappa1 = 1e-2, kappa2 = 1e-2;
+  int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= mI) return;
+  const double l = hl[r], u = hu[r];
+  const bool fl = isfinite(l), fu = isfinite(u);
+  double v = hx[r];
+  if (fl && fu) {
+    const double pl = fmin(kappa1 * fmax(1.0, fabs(l)), kappa2 * (u - l));
+    const double pu = fmin(kappa1 * fmax(1.0, fabs(u)), kappa2 * (u - l));
+    v = fmin(fmax(v, l + pl), u - pu);
+  } else if (fl) {
+    v = fmax(v, l + kappa1 * fmax(1.0, fabs(l)));
+  } else if (fu) {
+    v = fmin(v, u - kappa1 * fmax(1.0, fabs(u)));
+  }
+  d[r] = v;
+}
+
+// Warm start of the slacks' multipliers: mu0 / slack on finite bounds.
+__global__ void k_slack_duals(int mI, const double *__restrict__ hl,
+                              const double *__restrict__ hu, const double *__restrict__ d,
+                              double mu0, double *__restrict__ vl, double *__restrict__ vu) {
+  int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= mI) return;
+  vl[r] = isfinite(hl[r]) ? mu0 / (d[r] - hl[r]) : 0.0;
+  vu[r] = isfinite(hu[r]) ? mu0 / (hu[r] - d[r]) : 0.0;
+}
+
+// (4,4) block of eq. (linsys4x4) after the slack step is eliminated:
+// dcv = 1 / (Sigma_h + dw) on inequality rows, 0 on equality rows.
+__global__ void k_ineq_dcv(int m, int mE, const double *__restrict__ sig_h, double dw,
+                           double *__restrict__ dcv) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  dcv[i] = (i < mE) ? 0.0 : 1.0 / (sig_h[i - mE] + dw);
+}
+
+// Slack step eliminated from the right-hand side: r_y,h += dcv .* r_d.
+__global__ void k_ineq_rhs(int mI, int mE, const double *__restrict__ dcv,
+                           const double *__restrict__ rd, double *__restrict__ ry) {
+  int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= mI) return;
+  ry[mE + r] = ry[mE + r] + dcv[mE + r] * rd[r];
+}
+
+// Slack step recovered from the multiplier step: dd = dcv .* (r_d + dy_h).
+__global__ void k_ineq_step(int mI, int mE, const double *__restrict__ dcv,
+                            const double *__restrict__ rd, const double *__restrict__ dy,
+                            double *__restrict__ dd) {
+  int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= mI) return;
+  dd[r] = dcv[mE + r] * (rd[r] + dy[mE + r]);
 }
 
 __global__ void k_dsbase(int nd, int ns, const double *__restrict__ w,
@@ -221,9 +294,10 @@ __global__ __launch_bounds__(RB) void k_red_opt(int n, int m, const double *__re
   block_reduce8(v, red + (size_t)blockIdx.x * 8);
 }
 
-// slot 4: f(x), 5: sum of log-slacks, 6: theta = ||J x - b||_1.
-// hx holds H x_d, cx holds J x - b.
-__global__ __launch_bounds__(RB) void k_red_merit(int nd, int ns, int m,
+// slot 4: f(x), 5: sum of log-slacks over the nx bounded entries (the
+// variables, then the inequality slacks), 6: theta = ||c||_1.
+// hx holds H x_d, cx holds c = J x - [b; d].
+__global__ __launch_bounds__(RB) void k_red_merit(int nd, int ns, int nx, int m,
                                                   const double *__restrict__ x,
                                                   const double *__restrict__ hx,
                                                   const double *__restrict__ c,
@@ -236,7 +310,7 @@ __global__ __launch_bounds__(RB) void k_red_merit(int nd, int ns, int m,
   double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   const int n = nd + ns;
   const int64_t stride = (int64_t)gridDim.x * RB;
-  const int64_t len = (n > m) ? n : m;
+  const int64_t len = (nx > m) ? nx : m;
   for (int64_t e = (int64_t)blockIdx.x * RB + threadIdx.x; e < len; e += stride) {
     if (e < nd) {
       v[4] += x[e] * (0.5 * hx[e] + c[e]);
@@ -244,7 +318,7 @@ __global__ __launch_bounds__(RB) void k_red_merit(int nd, int ns, int m,
       const double xs = x[e];
       v[4] += xs * (0.5 * w[e - nd] * xs + g[e - nd]);
     }
-    if (e < n) {
+    if (e < nx) {
       if (isfinite(xl[e])) v[5] += log(x[e] - xl[e]);
       if (isfinite(xu[e])) v[5] += log(xu[e] - x[e]);
     }
@@ -560,9 +634,44 @@ void ipm_sigma_rhs(hipStream_t s, int n, const double *x, const double *zl, cons
   k_sigma_rhs<<<grid1(n, 256), 256, 0, s>>>(n, x, zl, zu, xl, xu, gf, jty, mu, sigma, rx);
 }
 
-void ipm_constr_finish(hipStream_t s, int m, const double *b, double *cx, double *ry) {
+void ipm_constr_finish(hipStream_t s, int m, int mE, const double *b, const double *d,
+                       double *cx, double *ry) {
   if (m <= 0) return;
-  k_constr_finish<<<grid1(m, 256), 256, 0, s>>>(m, b, cx, ry);
+  k_constr_finish<<<grid1(m, 256), 256, 0, s>>>(m, mE, b, d, cx, ry);
+}
+
+void ipm_slack_grad(hipStream_t s, int mI, int mE, const double *y, double *gf_t, double *jty_t) {
+  if (mI <= 0) return;
+  k_slack_grad<<<grid1(mI, 256), 256, 0, s>>>(mI, mE, y, gf_t, jty_t);
+}
+
+void ipm_slack_project(hipStream_t s, int mI, const double *hx, const double *hl,
+                       const double *hu, double *d) {
+  if (mI <= 0) return;
+  k_slack_project<<<grid1(mI, 256), 256, 0, s>>>(mI, hx, hl, hu, d);
+}
+
+void ipm_slack_duals(hipStream_t s, int mI, const double *hl, const double *hu, const double *d,
+                     double mu0, double *vl, double *vu) {
+  if (mI <= 0) return;
+  k_slack_duals<<<grid1(mI, 256), 256, 0, s>>>(mI, hl, hu, d, mu0, vl, vu);
+}
+
+void ipm_ineq_dcv(hipStream_t s, int m, int mE, const double *sig_h, double dw, double *dcv) {
+  if (m <= 0) return;
+  k_ineq_dcv<<<grid1(m, 256), 256, 0, s>>>(m, mE, sig_h, dw, dcv);
+}
+
+void ipm_ineq_rhs(hipStream_t s, int mI, int mE, const double *dcv, const double *rd,
+                  double *ry) {
+  if (mI <= 0) return;
+  k_ineq_rhs<<<grid1(mI, 256), 256, 0, s>>>(mI, mE, dcv, rd, ry);
+}
+
+void ipm_ineq_step(hipStream_t s, int mI, int mE, const double *dcv, const double *rd,
+                   const double *dy, double *dd) {
+  if (mI <= 0) return;
+  k_ineq_step<<<grid1(mI, 256), 256, 0, s>>>(mI, mE, dcv, rd, dy, dd);
 }
 
 void ipm_dsbase(hipStream_t s, int nd, int ns, const double *w, const double *sig, double *dsb) {
@@ -594,12 +703,12 @@ void ipm_red_opt_pair(hipStream_t s, int n, int m, const double *x, const double
   k_red_final<<<1, 256, 0, s>>>((int)g, red, out);
 }
 
-void ipm_red_merit(hipStream_t s, int nd, int ns, int m, const double *x, const double *hx,
-                   const double *c, const double *w, const double *g, const double *xl,
-                   const double *xu, const double *cx, double *red, double *out) {
-  const int n = nd + ns;
-  const unsigned gr = red_grid(n > m ? n : m);
-  k_red_merit<<<gr, RB, 0, s>>>(nd, ns, m, x, hx, c, w, g, xl, xu, cx, red);
+void ipm_red_merit(hipStream_t s, int nd, int ns, int nx, int m, const double *x,
+                   const double *hx, const double *c, const double *w, const double *g,
+                   const double *xl, const double *xu, const double *cx, double *red,
+                   double *out) {
+  const unsigned gr = red_grid(nx > m ? nx : m);
+  k_red_merit<<<gr, RB, 0, s>>>(nd, ns, nx, m, x, hx, c, w, g, xl, xu, cx, red);
   k_red_final<<<1, 256, 0, s>>>((int)gr, red, out);
 }
 
@@ -670,6 +779,19 @@ __global__ void k_check_nonneg(int64_t n, const double *__restrict__ v, int32_t 
 
 void check_nonneg(hipStream_t s, int64_t n, const double *v, int32_t *bad) {
   if (n > 0) k_check_nonneg<<<grid1(n, 256), 256, 0, s>>>(n, v, bad);
+}
+
+// inequality bounds (eq. (ineq)): hl < hu, no NaN, at least one finite
+__global__ void k_check_ineq_bounds(int mI, const double *__restrict__ hl,
+                                    const double *__restrict__ hu, int32_t *bad) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= mI) return;
+  const double l = hl[r], u = hu[r];
+  if (!(l < u) || (!isfinite(l) && !isfinite(u))) atomicOr(bad, 1);
+}
+
+void check_ineq_bounds(hipStream_t s, int mI, const double *hl, const double *hu, int32_t *bad) {
+  if (mI > 0) k_check_ineq_bounds<<<grid1(mI, 256), 256, 0, s>>>(mI, hl, hu, bad);
 }
 
 void kkt_finish(hipStream_t s, int nd, int ns, int m, const double *sig, const double *dsb,

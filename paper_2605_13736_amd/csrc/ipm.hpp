@@ -21,7 +21,23 @@ void ipm_grad_finish(hipStream_t s, int nd, int ns, const double *c, const doubl
 void ipm_sigma_rhs(hipStream_t s, int n, const double *x, const double *zl, const double *zu,
                    const double *xl, const double *xu, const double *gf, const double *jty,
                    double mu, double *sigma, double *rx);
-void ipm_constr_finish(hipStream_t s, int m, const double *b, double *cx, double *ry);
+// cx: J x on entry, c = J x - [b; d] on exit; ry (may be null) = -c
+void ipm_constr_finish(hipStream_t s, int m, int mE, const double *b, const double *d,
+                       double *cx, double *ry);
+// inequality slacks: gradient entries (gf = 0, J'y = -y_h; y may be null),
+// start value (row value pushed inside [hl, hu]), the (4,4) diagonal
+// dcv = 1/(Sigma_h + dw) (0 on the mE equality rows), the rhs update
+// r_y,h += dcv .* r_d and the slack step dd = dcv .* (r_d + dy_h)
+void ipm_slack_grad(hipStream_t s, int mI, int mE, const double *y, double *gf_t, double *jty_t);
+void ipm_slack_project(hipStream_t s, int mI, const double *hx, const double *hl,
+                       const double *hu, double *d);
+void ipm_slack_duals(hipStream_t s, int mI, const double *hl, const double *hu, const double *d,
+                     double mu0, double *vl, double *vu);
+void ipm_ineq_dcv(hipStream_t s, int m, int mE, const double *sig_h, double dw, double *dcv);
+void ipm_ineq_rhs(hipStream_t s, int mI, int mE, const double *dcv, const double *rd,
+                  double *ry);
+void ipm_ineq_step(hipStream_t s, int mI, int mE, const double *dcv, const double *rd,
+                   const double *dy, double *dd);
 void ipm_dsbase(hipStream_t s, int nd, int ns, const double *w, const double *sig, double *dsb);
 void ipm_dz(hipStream_t s, int n, const double *x, const double *zl, const double *zu,
             const double *xl, const double *xu, const double *dx, double mu, double *dzl,
@@ -34,9 +50,10 @@ void ipm_red_opt(hipStream_t s, int n, int m, const double *x, const double *y, 
 void ipm_red_opt_pair(hipStream_t s, int n, int m, const double *x, const double *y, const double *zl,
                  const double *zu, const double *xl, const double *xu, const double *gf,
                  const double *jty, const double *cx, double mu, double *red, double *out);
-void ipm_red_merit(hipStream_t s, int nd, int ns, int m, const double *x, const double *hx,
-                   const double *c, const double *w, const double *g, const double *xl,
-                   const double *xu, const double *cx, double *red, double *out);
+void ipm_red_merit(hipStream_t s, int nd, int ns, int nx, int m, const double *x,
+                   const double *hx, const double *c, const double *w, const double *g,
+                   const double *xl, const double *xu, const double *cx, double *red,
+                   double *out);
 void ipm_red_gphi(hipStream_t s, int n, const double *gf, const double *x, const double *xl,
                   const double *xu, const double *dx, double mu, double *red, double *out);
 void ipm_red_ftb(hipStream_t s, int n, const double *x, const double *xl, const double *xu,
@@ -58,6 +75,8 @@ void kkt_finish(hipStream_t s, int nd, int ns, int m, const double *sig, const d
                 const double *dy, double *od, double *os, double *oy);
 // *bad |= 1 when some v[i] is negative or not finite
 void check_nonneg(hipStream_t s, int64_t n, const double *v, int32_t *bad);
+// *bad |= 1 unless hl < hu with at least one of them finite, for every row
+void check_ineq_bounds(hipStream_t s, int mI, const double *hl, const double *hu, int32_t *bad);
 void kkt_norm_parts(hipStream_t s, int nd, int ns, int m, const double *H, const double *sig,
                     double dw, const double *Jd, const int32_t *rp, const double *v,
                     const int32_t *cptr, const double *cval, const double *dsb, double dc,

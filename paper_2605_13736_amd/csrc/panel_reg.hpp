@@ -88,7 +88,7 @@ __device__ inline void panel_reg_dev(int N, int nb, double alpha,
   __shared__ double s_rv[NWV];
   __shared__ int s_ri[NWV];
   __shared__ double s_akk, s_aii, s_wki;
-  __shared__ int s_k0;
+  __shared__ int s_k0, s_err;
   // per owned row: un-updated values of the current pivot column, its updated
   // values, the updated candidate column
   __shared__ double s_acur[R * T], s_wkc[R * T], s_wic[R * T];
@@ -96,7 +96,10 @@ __device__ inline void panel_reg_dev(int N, int nb, double alpha,
   __shared__ int s_map[R * T];
 
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-  if (tid == 0) s_k0 = st->k;
+  if (tid == 0) {
+    s_k0 = st->k;
+    s_err = st->xerr;  // an earlier panel of this factorization aborted
+  }
   if (tid < NB) {
     s_wk[tid] = 0.0;
     s_wi[tid] = 0.0;
@@ -106,7 +109,7 @@ __device__ inline void panel_reg_dev(int N, int nb, double alpha,
   }
   __syncthreads();
   const int k0 = s_k0;
-  if (k0 >= N) return;
+  if (k0 >= N || s_err) return;
   // the tile must hold every remaining row (the host guarantees it); if not,
   // the factorization is flagged as failed rather than left incomplete
   if (N - k0 > R * T) {

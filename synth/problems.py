@@ -154,17 +154,12 @@ def interior_iterate(prob: dict, seed: int) -> dict:
 
 
 def family_member(prob: dict, p: int, cfg: int = 4) -> dict:
-    """Problem p of a family that shares prob's matrices, objective and bounds:
-    only the constraint right-hand side changes, b = J x0 with x0 drawn
-    U[-0.5, 0.5]^n from the seed (cfg, p, 3)."""
+    """Problem p of the warm-start family around prob: the same matrices,
+    objective and bounds, and the constraint right-hand side perturbed entry
+    by entry, b = b0 * (1 + 0.1 xi) with xi ~ N(0, 1) drawn from the seed
+    (cfg, p, 3) and b0 = prob's b."""
     rng = np.random.default_rng(np.random.SeedSequence([cfg, p, 3]))
-    nd, ns, m = prob["n_d"], prob["n_s"], prob["m"]
-    x0 = rng.uniform(-0.5, 0.5, nd + ns)
-    b = prob["Jd"] @ x0[:nd] if nd > 0 else np.zeros(m)
-    b = np.array(b, dtype=np.float64)
-    for i in range(m):
-        for a in range(prob["rp"][i], prob["rp"][i + 1]):
-            b[i] += prob["v"][a] * x0[nd + prob["ci"][a]]
+    b0 = np.asarray(prob["b"], dtype=np.float64)
     q = dict(prob)
-    q["b"] = b
+    q["b"] = b0 * (1.0 + 0.1 * rng.standard_normal(len(b0)))
     return q

@@ -38,20 +38,24 @@ def test_binding_covers_every_declared_symbol():
 
 def test_workspace_bytes_and_invalid_dims():
     L = mds.lib()
-    d = mds.Dims(64, 2000, 128, 512)
+    d = mds.Dims(64, 2000, 128, 0, 512)
     nb = L.mds_workspace_bytes(C.byref(d), None)
     assert nb >= 8 * 192 * 192
-    assert L.mds_workspace_bytes(C.byref(mds.Dims(-1, 3, 3, 0)), None) == 0
+    assert L.mds_workspace_bytes(C.byref(mds.Dims(-1, 3, 3, 0, 0)), None) == 0
     # zero sizes are legal
-    assert L.mds_workspace_bytes(C.byref(mds.Dims(0, 0, 0, 0)), None) > 0
+    assert L.mds_workspace_bytes(C.byref(mds.Dims(0, 0, 0, 0, 0)), None) > 0
+    # inequality rows: 0 <= m_I <= m; slacks enlarge the IPM vectors
+    assert L.mds_workspace_bytes(C.byref(mds.Dims(64, 2000, 128, 129, 512)), None) == 0
+    assert L.mds_workspace_bytes(C.byref(mds.Dims(64, 2000, 128, -1, 512)), None) == 0
+    assert L.mds_workspace_bytes(C.byref(mds.Dims(64, 2000, 128, 128, 512)), None) > nb
 
 
 def test_create_rejects_bad_arguments_before_device_work():
     L = mds.lib()
     h = C.c_void_p()
-    d = mds.Dims(4, 5, 3, 6)
+    d = mds.Dims(4, 5, 3, 0, 6)
     assert L.mds_create(None, C.byref(d), None, None, None, 0) == -2        # ENULL
-    assert L.mds_create(C.byref(h), C.byref(mds.Dims(-1, 0, 0, 0)), None, None, None, 0) == -3
+    assert L.mds_create(C.byref(h), C.byref(mds.Dims(-1, 0, 0, 0, 0)), None, None, None, 0) == -3
     assert L.mds_create(C.byref(h), C.byref(d), None, None, None, 1 << 20) == -2
     need = L.mds_workspace_bytes(C.byref(d), None)
     buf = C.create_string_buffer(need + 512)

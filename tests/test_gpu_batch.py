@@ -1,7 +1,8 @@
 """Batched persistent-kernel Newton solves against the oracle, problem by problem.
 
-Bars, per problem of a batch of uneven sizes (including zero-size blocks and a
-nonconvex problem whose inertia correction fires):
+Bars, per problem of a batch of uneven sizes (including zero-size blocks, a
+nonconvex problem whose inertia correction fires, and condensed sizes up to
+the largest scenario size N = 2048), in the FP64 and the FP32 forms:
 * inertia of the accepted factorization, number of correction trials and
   the shifts delta_w, delta_c identical to the oracle's correction loop;
 * solution within 1e-8 (relative, max-norm) of the oracle's solve;
@@ -30,7 +31,12 @@ SHAPES = [
     (64, 3200, 192, 4, 1.0),
     (64, 2000, 128, 4, 6.0),
     (256, 12800, 768, 4, 1.0),
+    (512, 102400, 1536, 4, 1.0),   # N = 2048, the largest scenario size
 ]
+# scenario-batch problems drawn exactly as the benchmark draws them (sizes from
+# synth.batch_sizes, seeds (3, p)) with N in (1536, 2048]: their rows reach the
+# third and fourth register rows of every thread of the batch kernel
+SCENARIOS = [9, 3]   # N = 2036, 1812
 MU = 0.05
 
 
@@ -43,6 +49,14 @@ def _items():
     for idx, (nd, ns, m, r, sc) in enumerate(SHAPES):
         prob = synth.make_problem(nd, ns, m, r, cfg=700 + idx, p=0, s_scale=sc)
         st = synth.kkt_state(prob, idx, (-1.0, 1.0))
+        it = dict(prob)
+        it.update(sigma_d=st["sigma_d"], dsbase=st["dsbase"], r_d=st["r_d"], r_s=st["r_s"],
+                  r_y=st["r_y"])
+        items.append((prob, st, it))
+    for p in SCENARIOS:
+        sz = synth.batch_sizes(p)
+        prob = synth.make_problem(sz["n_d"], sz["n_s"], sz["m"], sz["r"], cfg=3, p=p)
+        st = synth.kkt_state(prob, p, (-1.0, 1.0))
         it = dict(prob)
         it.update(sigma_d=st["sigma_d"], dsbase=st["dsbase"], r_d=st["r_d"], r_s=st["r_s"],
                   r_y=st["r_y"])

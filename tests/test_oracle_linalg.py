@@ -283,3 +283,25 @@ def test_kkt_matvec_matches_dense():
     o = oracle.kkt_matvec(P, st["sigma_d"], st["dsbase"], 0.3, 0.2, x[:7], x[7:37], x[37:])
     K = full_kkt(prob, st["sigma_d"], st["dsbase"], 0.3, 0.2)
     assert np.allclose(np.concatenate(o), K @ x, rtol=1e-13, atol=1e-13)
+
+
+def test_threaded_elimination_is_bit_identical():
+    # the columns of each rank-1/2 update are split over threads; every entry
+    # keeps its expression, so the factor does not depend on the count
+    prob = synth.make_problem(150, 3000, 450, 6, cfg=299, s_scale=3.0)
+    st = synth.kkt_state(prob, 5, (-3.0, 3.0))
+    P = oracle.Problem(prob)
+    M, _ = oracle.condense(P, st["sigma_d"], st["dsbase"], 0.0, 0.0)
+    ref = oracle.bk(M)
+    try:
+        oracle.set_threads(4)
+        got = oracle.bk(M)
+    finally:
+        oracle.set_threads(1)
+    for a, b in zip(ref[:4], got[:4]):
+        assert np.array_equal(np.asarray(a).view(np.uint8), np.asarray(b).view(np.uint8))
+    # the partial elimination is the same process stopped early
+    A = np.asfortranarray(M.copy())
+    _, ipiv = oracle.bk_partial(A, 100)
+    k = 100 if ref[3][99] > 0 or ref[3][98] == ref[3][99] else 101
+    assert np.array_equal(ipiv[:k], ref[3][:k])
