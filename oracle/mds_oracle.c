@@ -14,6 +14,7 @@
  */
 #include "mds_oracle.h"
 
+#include <float.h>
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
@@ -666,6 +667,32 @@ double or_barrier(const orq_problem *P, const double *x, double mu) {
   return or_objective(P, x) - mu * lg;
 }
 
+/* Rounding scale of phi_mu at x: the sum of the magnitudes of the terms
+ * or_barrier adds up.  Its evaluation error is a small multiple of
+ * DBL_EPSILON times this, however much the terms cancel. */
+static double barrier_scale(const orq_problem *P, const double *x, double mu) {
+  const int nd = P->n_d, ns = P->n_s, n = nx_of(P);
+  double a = 0.0;
+  for (int i = 0; i < nd; ++i) {
+    double t = 0.0;
+    for (int j = 0; j < nd; ++j) {
+      double h = (i >= j) ? P->H[IDX(i, j, nd)] : P->H[IDX(j, i, nd)];
+      t = t + h * x[j];
+    }
+    a = a + fabs(x[i] * (0.5 * t + P->c[i]));
+  }
+  for (int k = 0; k < ns; ++k) {
+    double xs = x[nd + k];
+    a = a + fabs(xs * (0.5 * P->w[k] * xs + P->g[k]));
+  }
+  for (int i = 0; i < n; ++i) {
+    const double lo = lo_of(P, i), up = up_of(P, i);
+    if (isfinite(lo)) a = a + mu * fabs(log(x[i] - lo));
+    if (isfinite(up)) a = a + mu * fabs(log(up - x[i]));
+  }
+  return a;
+}
+
 double or_theta(const orq_problem *P, const double *x) {
   double *cx = (double *)malloc(sizeof(double) * (size_t)(P->m > 0 ? P->m : 1));
   constr(P, x, cx);
@@ -744,6 +771,15 @@ static void warm_point(const orq_problem *P, const double *xd0, const double *y0
   free(gf);
   free(jt);
   free(jty);
+}
+
+/* The tests of the line search that compare barrier values (Armijo, and
+ * sufficient progress in phi) allow ten machine epsilons of the reference
+ * iterate's rounding scale of phi (barrier_scale): near a solution the
+ * decrease they ask for falls below the rounding error of phi itself, and
+ * an exact comparison would reject full Newton steps on rounding noise. */
+static int le_tol(double lhs, double rhs, double base) {
+  return lhs - rhs <= 10.0 * DBL_EPSILON * fabs(base);
 }
 
 static int ipm_from(const orq_problem *P, const or_ipm_opts *o, const double *xd0,
@@ -934,7 +970,7 @@ static int ipm_from(const orq_problem *P, const or_ipm_opts *o, const double *xd
       }
     }
     /* backtracking filter line search */
-    double th = or_theta(P, x), ph = or_barrier(P, x, mu);
+    double th = or_theta(P, x), ph = or_barrier(P, x, mu), phs = barrier_scale(P, x, mu);
     grad_f(P, x, gf);
     double gphi = 0.0;
     for (int i = 0; i < n; ++i) {
@@ -965,10 +1001,10 @@ static int ipm_from(const orq_problem *P, const or_ipm_opts *o, const double *xd
         if (tht >= filt[f].th && pht >= filt[f].ph) infilt = 1;
       if (!infilt) {
         int sw = gphi < 0.0 && alpha * pow(-gphi, s_phi) > delta * pow(th, s_theta);
-        int armijo = pht <= ph + eta_phi * alpha * gphi;
+        int armijo = le_tol(pht - ph, eta_phi * alpha * gphi, phs);
         if (th <= theta_min && sw) {
           if (armijo) accepted = 1;
-        } else if (tht <= (1.0 - gamma_theta) * th || pht <= ph - gamma_phi * th) {
+        } else if (tht <= (1.0 - gamma_theta) * th || le_tol(pht - ph, -gamma_phi * th, phs)) {
           accepted = 1;
         }
         if (accepted) augment = !(sw && armijo);

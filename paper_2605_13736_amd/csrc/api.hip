@@ -3,6 +3,7 @@
 // line-search IPM.  Every numerical step on vectors and matrices runs in the
 // HIP kernels; the host only sequences launches and takes scalar decisions.
 #include <algorithm>
+#include <cfloat>
 #include <cmath>
 #include <cstdarg>
 #include <cstddef>
@@ -830,8 +831,9 @@ int opt_error_pair(mds_handle *h, const double *x, const double *y, const double
 
 // Launches the merit reductions at x = [variables; slacks] into out[0..7]
 // (slot 4: f, 5: sum of log-slacks of the variables and the slacks, 6:
-// theta); h->w.tn and h->w.tm are overwritten.
-void merit_launch(mds_handle *h, const double *x, double *out) {
+// theta, 7: the rounding scale of phi_mu, sum of the magnitudes of its
+// terms); h->w.tn and h->w.tm are overwritten.
+void merit_launch(mds_handle *h, const double *x, double mu, double *out) {
   const int nd = ND(h), ns = NS(h), m = MM(h);
   const mds_problem &P = h->P;
   double *hx = h->w.tn, *cx = h->w.tm;
@@ -845,12 +847,12 @@ void merit_launch(mds_handle *h, const double *x, double *out) {
     }
     ipm_constr_finish(S(h), m, h->mE, P.b, x + h->n, cx, nullptr);
   }
-  ipm_red_merit(S(h), nd, ns, h->nx, m, x, hx, P.c, P.w, P.g, h->w.xl_e, h->w.xu_e, cx,
+  ipm_red_merit(S(h), nd, ns, h->nx, m, mu, x, hx, P.c, P.w, P.g, h->w.xl_e, h->w.xu_e, cx,
                 h->w.red, out);
 }
 
 int merit_impl(mds_handle *h, const double *x, double mu, double *f, double *phi, double *theta) {
-  merit_launch(h, x, h->w.scal);
+  merit_launch(h, x, mu, h->w.scal);
   HIPCHK(hipGetLastError());
   double s[8];
   TRY(read_scal(h, s, 8));
@@ -1351,13 +1353,17 @@ static int ipm_step_impl(mds_handle *h, mds_iterate *it, mds_step_info *info, bo
   // before the merit products overwrite it
   eval_grad_constr(h, x, nullptr, nullptr);
   ipm_red_gphi(S(h), n, h->w.tn, x, xl, xu, dx, mu, h->w.red, h->w.scal + 8);
-  merit_launch(h, x, h->w.scal + 16);
+  merit_launch(h, x, mu, h->w.scal + 16);
   HIPCHK(hipGetLastError());
   double s24[24];
   TRY(read_scal(h, s24, 24));
   const double a_pr = -s24[0], a_du = -s24[1];
   const double gphi = s24[8 + 4];
   const double ph = s24[16 + 4] - mu * s24[16 + 5], th = s24[16 + 6];
+  // tests that compare barrier values allow ten machine epsilons of phi's
+  // rounding scale at x: near a solution the decrease they ask for falls
+  // below the rounding error of phi itself
+  const double ph_tol = 10.0 * DBL_EPSILON * s24[16 + 7];
   double amin;
   if (gphi < 0.0) {
     amin = std::min(gamma_theta, gamma_phi * th / (-gphi));
@@ -1379,10 +1385,10 @@ static int ipm_step_impl(mds_handle *h, mds_iterate *it, mds_step_info *info, bo
       if (tht >= h->filter[f].first && pht >= h->filter[f].second) infilt = true;
     if (!infilt) {
       const bool sw = gphi < 0.0 && alpha * std::pow(-gphi, s_phi) > delta * std::pow(th, s_theta);
-      const bool armijo = pht <= ph + eta_phi * alpha * gphi;
+      const bool armijo = (pht - ph) - eta_phi * alpha * gphi <= ph_tol;
       if (th <= h->theta_min && sw) {
         if (armijo) accepted = true;
-      } else if (tht <= (1.0 - gamma_theta) * th || pht <= ph - gamma_phi * th) {
+      } else if (tht <= (1.0 - gamma_theta) * th || (pht - ph) - (-gamma_phi * th) <= ph_tol) {
         accepted = true;
       }
       if (accepted) augment = !(sw && armijo);

@@ -295,9 +295,10 @@ __global__ __launch_bounds__(RB) void k_red_opt(int n, int m, const double *__re
 }
 
 // slot 4: f(x), 5: sum of log-slacks over the nx bounded entries (the
-// variables, then the inequality slacks), 6: theta = ||c||_1.
+// variables, then the inequality slacks), 6: theta = ||c||_1, 7: the rounding
+// scale of phi_mu = f - mu * (slot 5), the sum of the magnitudes of its terms.
 // hx holds H x_d, cx holds c = J x - [b; d].
-__global__ __launch_bounds__(RB) void k_red_merit(int nd, int ns, int nx, int m,
+__global__ __launch_bounds__(RB) void k_red_merit(int nd, int ns, int nx, int m, double mu,
                                                   const double *__restrict__ x,
                                                   const double *__restrict__ hx,
                                                   const double *__restrict__ c,
@@ -313,14 +314,26 @@ __global__ __launch_bounds__(RB) void k_red_merit(int nd, int ns, int nx, int m,
   const int64_t len = (nx > m) ? nx : m;
   for (int64_t e = (int64_t)blockIdx.x * RB + threadIdx.x; e < len; e += stride) {
     if (e < nd) {
-      v[4] += x[e] * (0.5 * hx[e] + c[e]);
+      const double t = x[e] * (0.5 * hx[e] + c[e]);
+      v[4] += t;
+      v[7] += fabs(t);
     } else if (e < n) {
       const double xs = x[e];
-      v[4] += xs * (0.5 * w[e - nd] * xs + g[e - nd]);
+      const double t = xs * (0.5 * w[e - nd] * xs + g[e - nd]);
+      v[4] += t;
+      v[7] += fabs(t);
     }
     if (e < nx) {
-      if (isfinite(xl[e])) v[5] += log(x[e] - xl[e]);
-      if (isfinite(xu[e])) v[5] += log(xu[e] - x[e]);
+      if (isfinite(xl[e])) {
+        const double t = log(x[e] - xl[e]);
+        v[5] += t;
+        v[7] += mu * fabs(t);
+      }
+      if (isfinite(xu[e])) {
+        const double t = log(xu[e] - x[e]);
+        v[5] += t;
+        v[7] += mu * fabs(t);
+      }
     }
     if (e < m) v[6] += fabs(cx[e]);
   }
@@ -703,12 +716,12 @@ void ipm_red_opt_pair(hipStream_t s, int n, int m, const double *x, const double
   k_red_final<<<1, 256, 0, s>>>((int)g, red, out);
 }
 
-void ipm_red_merit(hipStream_t s, int nd, int ns, int nx, int m, const double *x,
+void ipm_red_merit(hipStream_t s, int nd, int ns, int nx, int m, double mu, const double *x,
                    const double *hx, const double *c, const double *w, const double *g,
                    const double *xl, const double *xu, const double *cx, double *red,
                    double *out) {
   const unsigned gr = red_grid(nx > m ? nx : m);
-  k_red_merit<<<gr, RB, 0, s>>>(nd, ns, nx, m, x, hx, c, w, g, xl, xu, cx, red);
+  k_red_merit<<<gr, RB, 0, s>>>(nd, ns, nx, m, mu, x, hx, c, w, g, xl, xu, cx, red);
   k_red_final<<<1, 256, 0, s>>>((int)gr, red, out);
 }
 

@@ -50,7 +50,7 @@ void ipm_red_opt(hipStream_t s, int n, int m, const double *x, const double *y, 
 void ipm_red_opt_pair(hipStream_t s, int n, int m, const double *x, const double *y, const double *zl,
                  const double *zu, const double *xl, const double *xu, const double *gf,
                  const double *jty, const double *cx, double mu, double *red, double *out);
-void ipm_red_merit(hipStream_t s, int nd, int ns, int nx, int m, const double *x,
+void ipm_red_merit(hipStream_t s, int nd, int ns, int nx, int m, double mu, const double *x,
                    const double *hx, const double *c, const double *w, const double *g,
                    const double *xl, const double *xu, const double *cx, double *red,
                    double *out);
