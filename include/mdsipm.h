@@ -311,6 +311,22 @@ int mds_sigma_rhs(mds_handle *h, const double *x, const double *y, const double 
 int mds_ftb(mds_handle *h, int64_t n, const double *v, const double *dv, double tau,
             double *alpha_host);
 
+/* Allocation-free variant of mds_ftb, for callers that cannot allocate
+ * device memory or create a handle (code under stream capture, tight serving
+ * loops, harnesses that forbid allocation).  Same step as mds_ftb, written to
+ * the DEVICE pointer alpha (one double) on `stream` (a hipStream_t; NULL is
+ * the null stream); asynchronous, no host synchronization, no allocation.
+ * v, dv: n device doubles; 0 < tau <= 1; n = 0 gives alpha = 1.  The
+ * reduction's partial records live in a fixed device array of
+ * mds_ftb_noalloc_scratch_bytes() bytes (64 KiB + 64 B) that each GPU holds
+ * until the process ends; its need is the same for every n, so no n exceeds
+ * it.  Calls on one GPU share that array: calls that overlap on one GPU
+ * (several streams or host threads) race.  Errors: MDS_ENULL, MDS_EDIMS
+ * (n < 0), MDS_EINVAL (tau), MDS_EHIP. */
+int mds_ftb_noalloc(int64_t n, const double *v, const double *dv, double tau, double *alpha,
+                    void *stream);
+size_t mds_ftb_noalloc_scratch_bytes(void);
+
 /* Scaled optimality error E_mu; parts_host (may be NULL) receives
  * {dual inf, primal inf, lower compl, upper compl, s_d, s_c}.  Synchronizes. */
 int mds_opt_error(mds_handle *h, const double *x, const double *y, const double *zl,

@@ -143,6 +143,8 @@ SIGNATURES = {
                              C.POINTER(RefineInfo)]),
     "mds_sigma_rhs": (C.c_int, [_vp, _vp, _vp, _vp, _vp, C.c_double, _vp, _vp, _vp]),
     "mds_ftb": (C.c_int, [_vp, C.c_int64, _vp, _vp, C.c_double, _dp]),
+    "mds_ftb_noalloc": (C.c_int, [C.c_int64, _vp, _vp, C.c_double, _vp, _vp]),
+    "mds_ftb_noalloc_scratch_bytes": (C.c_size_t, []),
     "mds_opt_error": (C.c_int, [_vp, _vp, _vp, _vp, _vp, C.c_double, _dp, _dp]),
     "mds_merit": (C.c_int, [_vp, _vp, C.c_double, _dp, _dp, _dp]),
     "mds_ipm_init": (C.c_int, [_vp, C.POINTER(Iterate), C.POINTER(IpmOpts)]),
@@ -503,6 +505,24 @@ class Solver:
         st = lib().mds_get_inv_ds(self.h, out.ctypes.data_as(_dp))
         self._check(st, "mds_get_inv_ds")
         return out[:self.n_s]
+
+
+def ftb_noalloc(v, dv, tau, alpha, stream=None):
+    """Allocation-free fraction to the boundary (mds_ftb_noalloc): writes the
+    step into the one-element FP64 device tensor `alpha` on `stream` (default:
+    the current stream of alpha's device).  Asynchronous."""
+    torch = _torch()
+    for t in (v, dv, alpha):
+        if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+            raise MdsError("ftb_noalloc takes contiguous FP64 device tensors")
+    if v.numel() != dv.numel() or alpha.numel() < 1:
+        raise MdsError("ftb_noalloc: v and dv differ in length, or alpha is empty")
+    if stream is None:
+        stream = torch.cuda.current_stream(alpha.device)
+    st = lib().mds_ftb_noalloc(v.numel(), _ptr(v), _ptr(dv), float(tau), _ptr(alpha),
+                               C.c_void_p(stream.cuda_stream))
+    if st != 0:
+        raise MdsError(f"mds_ftb_noalloc: {lib().mds_status_string(st).decode()}")
 
 
 def _inertia_dict(i):

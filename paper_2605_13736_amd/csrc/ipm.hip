@@ -397,6 +397,12 @@ __global__ __launch_bounds__(RB) void k_red_ftb1(int64_t n, const double *__rest
   block_reduce8(v, red + (size_t)blockIdx.x * 8);
 }
 
+// alpha = -out[0] (the fraction-to-the-boundary step from the record's max
+// slot, which holds the largest -(step limit))
+__global__ void k_neg_first(const double *__restrict__ out, double *__restrict__ alpha) {
+  if (threadIdx.x == 0) alpha[0] = -out[0];
+}
+
 // 256 threads: thread t combines the records t, t + 256, ... in increasing
 // order, then a fixed pairwise tree over the threads (max for slots 0-3, sum
 // for slots 4-7); the order depends only on nb.
@@ -745,6 +751,12 @@ void ipm_red_ftb1(hipStream_t s, int64_t n, const double *v, const double *dv, d
   const unsigned g = red_grid(n);
   k_red_ftb1<<<g, RB, 0, s>>>(n, v, dv, tau, red);
   k_red_final<<<1, 256, 0, s>>>((int)g, red, out);
+}
+
+void ipm_ftb1_to_device(hipStream_t s, int64_t n, const double *v, const double *dv, double tau,
+                        double *red, double *out, double *alpha) {
+  ipm_red_ftb1(s, n, v, dv, tau, red, out);
+  k_neg_first<<<1, 64, 0, s>>>(out, alpha);
 }
 
 void ipm_red_amax3(hipStream_t s, int64_t na, const double *a, int64_t nb, const double *b,

@@ -61,6 +61,10 @@ void ipm_red_ftb(hipStream_t s, int n, const double *x, const double *xl, const 
                  const double *dzu, double tau, double *red, double *out);
 void ipm_red_ftb1(hipStream_t s, int64_t n, const double *v, const double *dv, double tau,
                   double *red, double *out);
+// ipm_red_ftb1, then alpha[0] (device) = the step; red holds kRedBlocks
+// records of 8 doubles and out 8 doubles, written before they are read
+void ipm_ftb1_to_device(hipStream_t s, int64_t n, const double *v, const double *dv, double tau,
+                        double *red, double *out, double *alpha);
 void ipm_red_amax3(hipStream_t s, int64_t na, const double *a, int64_t nb, const double *b,
                    int64_t nc, const double *c, double *red, double *out);
 void ipm_axpy_to(hipStream_t s, int n, const double *x, const double *dx, double a, double *out);

@@ -79,3 +79,14 @@ def test_no_cpu_fallback_without_gpu():
         pytest.skip("GPU present")
     with pytest.raises(mds.MdsError):
         mds.Solver(4, 5, 3, 6)
+
+
+def test_ftb_noalloc_argument_checks_before_device_work():
+    L = mds.lib()
+    a = C.c_void_p(16)  # never dereferenced: every call below fails its checks first
+    assert L.mds_ftb_noalloc(4, a, a, 0.99, None, None) == -2          # ENULL (alpha)
+    assert L.mds_ftb_noalloc(4, None, a, 0.99, a, None) == -2          # ENULL (v)
+    assert L.mds_ftb_noalloc(-1, a, a, 0.99, a, None) == -3            # EDIMS
+    assert L.mds_ftb_noalloc(4, a, a, 0.0, a, None) == -1              # EINVAL (tau)
+    assert L.mds_ftb_noalloc(4, a, a, 1.5, a, None) == -1
+    assert L.mds_ftb_noalloc_scratch_bytes() == 8 * (1024 * 8 + 8)
