@@ -125,7 +125,12 @@ typedef struct {
                             1024 (0: 128 up to N = 128, 256 up to N = 256,
                             else 512); the cooperative panel uses 512; the
                             LDS factorization 256 or 512 (0: 512)           */
-  int32_t reserved[4];
+  int32_t sblk_max;    /* 0: the sparse Hessian block is diag(w).  1..16: the
+                          workspace also holds coupling blocks of at most
+                          this many sparse variables (mds_set_sparse_blocks)
+                          and the transformed Jacobian they induce (up to
+                          sblk_max * nnz_s entries)                          */
+  int32_t reserved[3];
 } mds_options;
 
 /* Problem data, all device pointers, caller-owned, must stay valid and
@@ -264,6 +269,27 @@ int mds_condense(mds_handle *h, const double *sigma_d, const double *dsbase,
  * return MDS_ESTATE while a caller's diagonal is set.  Invalidates the
  * current M and factor.  Synchronizes. */
 int mds_set_m22_diag(mds_handle *h, const double *dcv);
+
+/* Coupling blocks of the sparse Hessian (assumption A2 of Sec. 2 in its
+ * general form: a pattern that makes solves with Q_{x_s} cheap).  The sparse
+ * block of the Hessian becomes diag(w) + blockdiag(Wb): bp_host (HOST,
+ * nblk + 1 entries, 0 = bp[0] < bp[1] < ... < bp[nblk] = n_s) splits the
+ * sparse variables into consecutive blocks of 1 .. options.sblk_max
+ * variables; Wb (device, sum of the blocks' s^2 doubles) holds each block's
+ * s x s matrix column-major, one after another; only lower triangles are
+ * read, but each block must be exactly symmetric, finite and positive
+ * semidefinite (checked here, with a copy to the host).  Caller-owned; must
+ * stay valid while set.  Condensation then factors every block of
+ * Q_{x_s} = blockdiag(Wb) + diag(dsbase) + dw I as L Delta L' and works on
+ * J_s L^{-T} with the middle factor 1/Delta (mds_get_inv_ds returns 1/Delta);
+ * the solve, the full-system products and norms used by refinement, the
+ * objective and its gradient all carry the blocks.  nblk = 0 removes them;
+ * mds_set_problem removes them too.  The warm start (mds_ipm_init_warm)
+ * returns MDS_ESTATE while blocks are set.  Synchronizes.  Errors: MDS_ESTATE
+ * (sblk_max = 0 or no problem), MDS_EDIMS, MDS_EINVAL (layout, sizes,
+ * symmetry), MDS_EDS_NONPOS (a block not positive semidefinite),
+ * MDS_ENONFINITE_INPUT. */
+int mds_set_sparse_blocks(mds_handle *h, int32_t nblk, const int32_t *bp_host, const double *Wb);
 
 /* Bunch-Kaufman LDL' of the condensed M with its inertia (Sec. 2.3, kernel
  * class K4).  reg == NULL: factor M as last condensed.  reg != NULL: run the

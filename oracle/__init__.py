@@ -41,13 +41,14 @@ class OrqProblem(C.Structure):
     _fields_ = [("n_d", C.c_int32), ("n_s", C.c_int32), ("m", C.c_int32),
                 ("H", _dp), ("c", _dp), ("w", _dp), ("g", _dp), ("Jd", _dp),
                 ("rp", _ip), ("ci", _ip), ("v", _dp), ("b", _dp),
-                ("xl", _dp), ("xu", _dp), ("m_I", C.c_int32), ("hl", _dp), ("hu", _dp)]
+                ("xl", _dp), ("xu", _dp), ("m_I", C.c_int32), ("hl", _dp), ("hu", _dp),
+                ("nblk", C.c_int32), ("bp", _ip), ("Wb", _dp)]
 
 
 class OrFactor(C.Structure):
     _fields_ = [("N", C.c_int32), ("dw", C.c_double), ("dc", C.c_double),
                 ("L", _dp), ("dd", _dp), ("ds", _dp), ("ipiv", _ip), ("inv_d", _dp),
-                ("inertia", C.c_int32 * 3), ("info", C.c_int32), ("trials", C.c_int32),
+                ("lblk", _dp), ("inertia", C.c_int32 * 3), ("info", C.c_int32), ("trials", C.c_int32),
                 ("dcv", _dp), ("sig_h", _dp)]
 
 
@@ -71,10 +72,12 @@ def lib():
         L = C.CDLL(_LIB_PATH)
         P = C.POINTER(OrqProblem)
         F = C.POINTER(OrFactor)
-        L.or_condense.argtypes = [P, _dp, _dp, C.c_double, C.c_double, _dp, _dp]
-        L.or_condense_dcv.argtypes = [P, _dp, _dp, C.c_double, C.c_double, _dp, _dp, _dp]
-        L.or_rhs_condense.argtypes = [P, _dp, _dp, _dp, _dp]
-        L.or_backsub.argtypes = [P, _dp, _dp, _dp, _dp]
+        L.or_condense.argtypes = [P, _dp, _dp, C.c_double, C.c_double, _dp, _dp, _dp]
+        L.or_condense_dcv.argtypes = [P, _dp, _dp, C.c_double, C.c_double, _dp, _dp, _dp, _dp]
+        L.or_rhs_condense.argtypes = [P, _dp, _dp, _dp, _dp, _dp]
+        L.or_backsub.argtypes = [P, _dp, _dp, _dp, _dp, _dp]
+        L.or_blk_words.argtypes = [P]
+        L.or_blk_words.restype = C.c_int64
         L.or_bk.argtypes = [C.c_int32, _dp, _ip, _dp, _dp, _ip]
         L.or_bk.restype = C.c_int
         L.or_inertia.argtypes = [C.c_int32, _ip, _dp, _dp, _ip]
@@ -160,12 +163,21 @@ class Problem:
         self.hl = _f64(p.get("hl", np.zeros(0)))
         self.hu = _f64(p.get("hu", np.zeros(0)))
         assert len(self.hl) == len(self.hu) == self.m_I <= self.m
+        # coupling blocks of the sparse Hessian (assumption A2, general form):
+        # bp splits 0..n_s into consecutive blocks, Wb holds them column-major
+        self.bp = np.ascontiguousarray(p.get("bp", np.zeros(0)), dtype=np.int32)
+        self.Wb = _f64(p.get("Wb", np.zeros(0)))
+        self.nblk = max(len(self.bp) - 1, 0)
+        if self.nblk:
+            sz = np.diff(self.bp)
+            assert self.bp[0] == 0 and self.bp[-1] == self.n_s and np.all(sz > 0)
+            assert len(self.Wb) == int(np.sum(sz.astype(np.int64) ** 2))
         self._keep = [np.zeros(1)]
         self.s = OrqProblem(self.n_d, self.n_s, self.m, *[_d(self._nz(a)) for a in (
             self.H, self.c, self.w, self.g, self.Jd)], _i(self._nzi(self.rp)),
             _i(self._nzi(self.ci)), _d(self._nz(self.v)), _d(self._nz(self.b)),
             _d(self._nz(self.xl)), _d(self._nz(self.xu)), self.m_I, _d(self._nz(self.hl)),
-            _d(self._nz(self.hu)))
+            _d(self._nz(self.hu)), self.nblk, _i(self._nzi(self.bp)), _d(self._nz(self.Wb)))
 
     def _nz(self, a):
         if a.size == 0:
@@ -197,33 +209,43 @@ def _buf(n, dtype=np.float64):
     return np.zeros(max(int(n), 1), dtype=dtype)
 
 
-def condense(P: Problem, sigma_d, dsbase, dw=0.0, dc=0.0, dcv=None):
-    """Condensed matrix M (N x N, full symmetric) and inv_d = 1/(dsbase+dw).
-    dcv (m, optional): per-row diagonal subtracted from M22 after dc."""
+def blk_words(P: Problem):
+    return int(lib().or_blk_words(P.ptr))
+
+
+def condense(P: Problem, sigma_d, dsbase, dw=0.0, dc=0.0, dcv=None, with_blocks=False):
+    """Condensed matrix M (N x N, full symmetric) and inv_d: 1/(dsbase+dw)
+    without coupling blocks, 1/Delta of the blocks' L Delta L' with them.
+    dcv (m, optional): per-row diagonal subtracted from M22 after dc.
+    with_blocks: also return the blocks' unit lower factors (Wb's layout)."""
     N = P.N
     M = _buf(N * N)
     inv_d = _buf(P.n_s)
+    lb = _buf(blk_words(P))
     sd = _d(_f64(sigma_d) if P.n_d else _buf(1))
     db = _d(_f64(dsbase) if P.n_s else _buf(1))
     if dcv is None:
-        lib().or_condense(P.ptr, sd, db, dw, dc, _d(M), _d(inv_d))
+        lib().or_condense(P.ptr, sd, db, dw, dc, _d(M), _d(inv_d), _d(lb))
     else:
         dv = _f64(dcv) if P.m else _buf(1)
-        lib().or_condense_dcv(P.ptr, sd, db, dw, dc, _d(dv), _d(M), _d(inv_d))
-    return M[:N * N].reshape((N, N), order="F"), inv_d[:P.n_s]
+        lib().or_condense_dcv(P.ptr, sd, db, dw, dc, _d(dv), _d(M), _d(inv_d), _d(lb))
+    out = (M[:N * N].reshape((N, N), order="F"), inv_d[:P.n_s])
+    return out + (lb[:blk_words(P)],) if with_blocks else out
 
 
-def rhs_condense(P: Problem, inv_d, r_s, r_y):
+def rhs_condense(P: Problem, inv_d, r_s, r_y, lblk=None):
     out = _buf(P.m)
-    lib().or_rhs_condense(P.ptr, _d(_f64(inv_d) if P.n_s else _buf(1)),
+    lb = _f64(lblk) if lblk is not None and len(lblk) else _buf(1)
+    lib().or_rhs_condense(P.ptr, _d(_f64(inv_d) if P.n_s else _buf(1)), _d(lb),
                           _d(_f64(r_s) if P.n_s else _buf(1)),
                           _d(_f64(r_y) if P.m else _buf(1)), _d(out))
     return out[:P.m]
 
 
-def backsub(P: Problem, inv_d, r_s, dy):
+def backsub(P: Problem, inv_d, r_s, dy, lblk=None):
     out = _buf(P.n_s)
-    lib().or_backsub(P.ptr, _d(_f64(inv_d) if P.n_s else _buf(1)),
+    lb = _f64(lblk) if lblk is not None and len(lblk) else _buf(1)
+    lib().or_backsub(P.ptr, _d(_f64(inv_d) if P.n_s else _buf(1)), _d(lb),
                      _d(_f64(r_s) if P.n_s else _buf(1)), _d(_f64(dy) if P.m else _buf(1)),
                      _d(out))
     return out[:P.n_s]
@@ -459,6 +481,8 @@ def ipm(P: Problem, tol=1e-8, mu0=0.1, max_iter=200, refine_steps=2, dw_max=1e20
         y0 = _f64(warm["y"]) if P.m else _buf(1)
         st = lib().or_ipm_warm(P.ptr, C.byref(opts), _d(xd0), _d(y0), float(warm["mu0"]),
                                _d(x), _d(y), _d(zl), _d(zu), _i(it), tr)
+    if st == 8:
+        raise ValueError("the warm start is defined for a diagonal sparse Hessian block only")
     iters = int(it[0])
     rows = []
     for k in range(min(iters + 1, max_iter)):

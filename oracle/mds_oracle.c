@@ -37,10 +37,143 @@ void or_set_threads(int32_t n) { g_threads = (n > 0) ? n : 1; }
  * (-D_h^{-1} of the compressed form); NULL when there is none.             */
 /* ======================================================================== */
 
+/* ---- blocks of Q_{x_s} (assumption A2, general form) --------------------- */
+
+int64_t or_blk_words(const orq_problem *P) {
+  int64_t t = 0;
+  for (int b = 0; b < P->nblk; ++b) {
+    const int64_t sz = P->bp[b + 1] - P->bp[b];
+    t += sz * sz;
+  }
+  return t;
+}
+
+/* L Delta L' of every block of Q_{x_s} = blockdiag(Wb) + diag(dsbase) + dw I,
+ * column by column (no pivoting: the blocks are positive definite when
+ * dsbase + dw > 0 and Wb is positive semidefinite).  Diagonal entries are
+ * (Wb_jj + dsbase_j) + dw.  For column j of a block:
+ *   Delta_j = Q_jj - sum_{t<j} (L_jt Delta_t) L_jt,
+ *   L_ij = (Q_ij - sum_{t<j} (L_it Delta_t) L_jt) / Delta_j   (i > j),
+ * each sum in ascending t.  inv_d = 1/Delta. */
+static void blk_factor(const orq_problem *P, const double *dsbase, double dw, double *lblk,
+                       double *inv_d) {
+  int smax = 1;
+  for (int b = 0; b < P->nblk; ++b) smax = (P->bp[b + 1] - P->bp[b] > smax) ? P->bp[b + 1] - P->bp[b] : smax;
+  double *dl = (double *)malloc(sizeof(double) * (size_t)smax);
+  int64_t off = 0;
+  for (int b = 0; b < P->nblk; ++b) {
+    const int k0 = P->bp[b], sz = P->bp[b + 1] - k0;
+    const double *Q = P->Wb + off;
+    double *L = lblk + off;
+    for (int j = 0; j < sz; ++j) {
+      double d = (Q[IDX(j, j, sz)] + dsbase[k0 + j]) + dw;
+      for (int t = 0; t < j; ++t) d = d - (L[IDX(j, t, sz)] * dl[t]) * L[IDX(j, t, sz)];
+      dl[j] = d;
+      L[IDX(j, j, sz)] = 1.0;
+      for (int i = j + 1; i < sz; ++i) {
+        double e = Q[IDX(i, j, sz)];
+        for (int t = 0; t < j; ++t) e = e - (L[IDX(i, t, sz)] * dl[t]) * L[IDX(j, t, sz)];
+        L[IDX(i, j, sz)] = e / d;
+      }
+    }
+    for (int j = 0; j < sz; ++j) inv_d[k0 + j] = 1.0 / dl[j];
+    off += (int64_t)sz * sz;
+  }
+  free(dl);
+}
+
+/* block index of every sparse variable and the offset of every block */
+static void blk_maps(const orq_problem *P, int32_t *bid, int64_t *boff) {
+  int64_t off = 0;
+  for (int b = 0; b < P->nblk; ++b) {
+    boff[b] = off;
+    for (int k = P->bp[b]; k < P->bp[b + 1]; ++k) bid[k] = b;
+    off += (int64_t)(P->bp[b + 1] - P->bp[b]) * (P->bp[b + 1] - P->bp[b]);
+  }
+}
+
+/* Transformed Jacobian Jh = J_s L^{-T} in CSR: row i holds every column of
+ * every block that row i of J_s touches (blocks in ascending order, columns
+ * ascending inside a block).  Inside a block of size s starting at k0, with
+ * u_p = J_s(i, k0 + p) (0 where J_s has no entry):
+ *   Jh(i, k0 + p) = u_p - sum_{t<p} L_pt Jh(i, k0 + t)   (ascending t). */
+typedef struct { int32_t *rp, *ci; double *v; } csr_t;
+
+static csr_t blk_transform(const orq_problem *P, const double *lblk) {
+  const int m = P->m, ns = P->n_s;
+  int32_t *bid = (int32_t *)malloc(sizeof(int32_t) * (size_t)(ns > 0 ? ns : 1));
+  int64_t *boff = (int64_t *)malloc(sizeof(int64_t) * (size_t)(P->nblk > 0 ? P->nblk : 1));
+  blk_maps(P, bid, boff);
+  csr_t J;
+  J.rp = (int32_t *)malloc(sizeof(int32_t) * (size_t)(m + 1));
+  J.rp[0] = 0;
+  for (int i = 0; i < m; ++i) {
+    int cnt = 0, last = -1;
+    for (int a = P->rp[i]; a < P->rp[i + 1]; ++a) {
+      const int b = bid[P->ci[a]];
+      if (b != last) { cnt += P->bp[b + 1] - P->bp[b]; last = b; }
+    }
+    J.rp[i + 1] = J.rp[i] + cnt;
+  }
+  const int nnz = J.rp[m];
+  J.ci = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nnz > 0 ? nnz : 1));
+  J.v = (double *)malloc(sizeof(double) * (size_t)(nnz > 0 ? nnz : 1));
+  for (int i = 0; i < m; ++i) {
+    int e = J.rp[i], a = P->rp[i];
+    const int ae = P->rp[i + 1];
+    while (a < ae) {
+      const int b = bid[P->ci[a]], k0 = P->bp[b], sz = P->bp[b + 1] - k0;
+      const double *L = lblk + boff[b];
+      for (int p = 0; p < sz; ++p) {
+        double u = 0.0;
+        if (a < ae && P->ci[a] == k0 + p) { u = P->v[a]; ++a; }
+        for (int t = 0; t < p; ++t) u = u - L[IDX(p, t, sz)] * J.v[e + t];
+        J.ci[e + p] = k0 + p;
+        J.v[e + p] = u;
+      }
+      e += sz;
+    }
+  }
+  free(bid); free(boff);
+  return J;
+}
+
+/* u <- L^{-1} u (forward) or L^{-T} u (backward), block by block */
+static void blk_lsolve(const orq_problem *P, const double *lblk, double *u, int transpose) {
+  int64_t off = 0;
+  for (int b = 0; b < P->nblk; ++b) {
+    const int k0 = P->bp[b], sz = P->bp[b + 1] - k0;
+    const double *L = lblk + off;
+    if (!transpose) {
+      for (int p = 0; p < sz; ++p) {
+        double t = u[k0 + p];
+        for (int q = 0; q < p; ++q) t = t - L[IDX(p, q, sz)] * u[k0 + q];
+        u[k0 + p] = t;
+      }
+    } else {
+      for (int p = sz - 1; p >= 0; --p) {
+        double t = u[k0 + p];
+        for (int q = p + 1; q < sz; ++q) t = t - L[IDX(q, p, sz)] * u[k0 + q];
+        u[k0 + p] = t;
+      }
+    }
+    off += (int64_t)sz * sz;
+  }
+}
+
 void or_condense_dcv(const orq_problem *P, const double *sigma_d, const double *dsbase,
-                     double dw, double dc, const double *dcv, double *M, double *inv_d) {
+                     double dw, double dc, const double *dcv, double *M, double *inv_d,
+                     double *lblk) {
   const int nd = P->n_d, ns = P->n_s, m = P->m, N = nd + m;
-  for (int k = 0; k < ns; ++k) inv_d[k] = 1.0 / (dsbase[k] + dw);
+  /* D_s^{-1} (diagonal Q_{x_s}), or the blocks' factors and the transformed
+   * Jacobian whose (2,2) Schur term has the diagonal middle factor 1/Delta */
+  csr_t J = {(int32_t *)P->rp, (int32_t *)P->ci, (double *)P->v};
+  if (P->nblk > 0) {
+    blk_factor(P, dsbase, dw, lblk, inv_d);
+    J = blk_transform(P, lblk);
+  } else {
+    for (int k = 0; k < ns; ++k) inv_d[k] = 1.0 / (dsbase[k] + dw);
+  }
   /* (1,1) block: H + Sigma_d + dw I  (Q_{x_d} with its shift) */
   for (int j = 0; j < nd; ++j)
     for (int i = 0; i < nd; ++i) {
@@ -59,13 +192,13 @@ void or_condense_dcv(const orq_problem *P, const double *sigma_d, const double *
   for (int j = 0; j < m; ++j)
     for (int i = j; i < m; ++i) {
       double acc = 0.0;
-      int a = P->rp[i], ae = P->rp[i + 1], b = P->rp[j], be = P->rp[j + 1];
+      int a = J.rp[i], ae = J.rp[i + 1], b = J.rp[j], be = J.rp[j + 1];
       while (a < ae && b < be) {
-        int ka = P->ci[a], kb = P->ci[b];
+        int ka = J.ci[a], kb = J.ci[b];
         if (ka < kb) ++a;
         else if (kb < ka) ++b;
         else {
-          acc = acc - (P->v[a] * inv_d[ka]) * P->v[b];
+          acc = acc - (J.v[a] * inv_d[ka]) * J.v[b];
           ++a; ++b;
         }
       }
@@ -76,15 +209,33 @@ void or_condense_dcv(const orq_problem *P, const double *sigma_d, const double *
       M[IDX(nd + i, nd + j, N)] = acc;
       M[IDX(nd + j, nd + i, N)] = acc;
     }
+  if (P->nblk > 0) { free(J.rp); free(J.ci); free(J.v); }
 }
 
 void or_condense(const orq_problem *P, const double *sigma_d, const double *dsbase,
-                 double dw, double dc, double *M, double *inv_d) {
-  or_condense_dcv(P, sigma_d, dsbase, dw, dc, NULL, M, inv_d);
+                 double dw, double dc, double *M, double *inv_d, double *lblk) {
+  or_condense_dcv(P, sigma_d, dsbase, dw, dc, NULL, M, inv_d, lblk);
 }
 
-void or_rhs_condense(const orq_problem *P, const double *inv_d, const double *r_s,
-                     const double *r_y, double *rhat) {
+void or_rhs_condense(const orq_problem *P, const double *inv_d, const double *lblk,
+                     const double *r_s, const double *r_y, double *rhat) {
+  if (P->nblk > 0) {
+    /* r_y - (J_s L^{-T}) Delta^{-1} (L^{-1} r_s) */
+    double *u = (double *)malloc(sizeof(double) * (size_t)(P->n_s > 0 ? P->n_s : 1));
+    for (int k = 0; k < P->n_s; ++k) u[k] = r_s[k];
+    blk_lsolve(P, lblk, u, 0);
+    csr_t J = blk_transform(P, lblk);
+    for (int i = 0; i < P->m; ++i) {
+      double t = r_y[i];
+      for (int a = J.rp[i]; a < J.rp[i + 1]; ++a) {
+        int k = J.ci[a];
+        t = t - J.v[a] * (inv_d[k] * u[k]);
+      }
+      rhat[i] = t;
+    }
+    free(J.rp); free(J.ci); free(J.v); free(u);
+    return;
+  }
   for (int i = 0; i < P->m; ++i) {
     double t = r_y[i];
     for (int a = P->rp[i]; a < P->rp[i + 1]; ++a) {
@@ -95,14 +246,22 @@ void or_rhs_condense(const orq_problem *P, const double *inv_d, const double *r_
   }
 }
 
-void or_backsub(const orq_problem *P, const double *inv_d, const double *r_s,
-                const double *dy, double *dx_s) {
+void or_backsub(const orq_problem *P, const double *inv_d, const double *lblk,
+                const double *r_s, const double *dy, double *dx_s) {
   /* t = r_s - J_s' dy, accumulated row by row in ascending row order */
   double *t = (double *)malloc(sizeof(double) * (size_t)(P->n_s > 0 ? P->n_s : 1));
   for (int k = 0; k < P->n_s; ++k) t[k] = r_s[k];
   for (int i = 0; i < P->m; ++i)
     for (int a = P->rp[i]; a < P->rp[i + 1]; ++a) t[P->ci[a]] = t[P->ci[a]] - P->v[a] * dy[i];
-  for (int k = 0; k < P->n_s; ++k) dx_s[k] = inv_d[k] * t[k];
+  if (P->nblk > 0) {
+    /* L^{-T} Delta^{-1} L^{-1} t */
+    blk_lsolve(P, lblk, t, 0);
+    for (int k = 0; k < P->n_s; ++k) t[k] = inv_d[k] * t[k];
+    blk_lsolve(P, lblk, t, 1);
+    for (int k = 0; k < P->n_s; ++k) dx_s[k] = t[k];
+  } else {
+    for (int k = 0; k < P->n_s; ++k) dx_s[k] = inv_d[k] * t[k];
+  }
   free(t);
 }
 
@@ -299,6 +458,45 @@ int or_ldl_solve(int32_t N, const double *L, const int32_t *ipiv, const double *
 /* Full KKT operator of eq. (linsys4x4) restricted to equality constraints. */
 /* ======================================================================== */
 
+/* out += blockdiag(Wb) u (each block's full symmetric matrix, rows in
+ * ascending column order) */
+static void blk_matvec_add(const orq_problem *P, const double *u, double *out) {
+  int64_t off = 0;
+  for (int b = 0; b < P->nblk; ++b) {
+    const int k0 = P->bp[b], sz = P->bp[b + 1] - k0;
+    const double *Q = P->Wb + off;
+    for (int i = 0; i < sz; ++i) {
+      double t = out[k0 + i];
+      for (int j = 0; j < sz; ++j) t = t + ((i >= j) ? Q[IDX(i, j, sz)] : Q[IDX(j, i, sz)]) * u[k0 + j];
+      out[k0 + i] = t;
+    }
+    off += (int64_t)sz * sz;
+  }
+}
+
+/* blockdiag(Wb) u in a new array of n_s entries (zeros without blocks) */
+static double *blk_product(const orq_problem *P, const double *u) {
+  double *o = (double *)calloc((size_t)(P->n_s > 0 ? P->n_s : 1), sizeof(double));
+  blk_matvec_add(P, u, o);
+  return o;
+}
+
+/* acc += the row sums of |blockdiag(Wb)| off the diagonal; diag = the
+ * blocks' diagonal entries (left untouched without blocks) */
+static void blk_absrow_add(const orq_problem *P, double *acc, double *diag) {
+  int64_t off = 0;
+  for (int b = 0; b < P->nblk; ++b) {
+    const int k0 = P->bp[b], sz = P->bp[b + 1] - k0;
+    const double *Q = P->Wb + off;
+    for (int i = 0; i < sz; ++i) {
+      diag[k0 + i] = Q[IDX(i, i, sz)];
+      for (int j = 0; j < sz; ++j)
+        if (i != j) acc[k0 + i] += fabs((i > j) ? Q[IDX(i, j, sz)] : Q[IDX(j, i, sz)]);
+    }
+    off += (int64_t)sz * sz;
+  }
+}
+
 void or_kkt_matvec(const orq_problem *P, const double *sigma_d, const double *dsbase,
                    double dw, double dc, const double *dx_d, const double *dx_s,
                    const double *dy, double *o_d, double *o_s, double *o_y) {
@@ -321,6 +519,7 @@ void or_kkt_matvec_dcv(const orq_problem *P, const double *sigma_d, const double
     o_d[i] = t;
   }
   for (int k = 0; k < ns; ++k) o_s[k] = (dsbase[k] + dw) * dx_s[k];
+  blk_matvec_add(P, dx_s, o_s);
   for (int r = 0; r < m; ++r)
     for (int a = P->rp[r]; a < P->rp[r + 1]; ++a) o_s[P->ci[a]] = o_s[P->ci[a]] + P->v[a] * dy[r];
   for (int r = 0; r < m; ++r) {
@@ -355,7 +554,10 @@ double or_kkt_norm_inf_dcv(const orq_problem *P, const double *sigma_d, const do
   double *col = (double *)calloc((size_t)(ns > 0 ? ns : 1), sizeof(double));
   for (int r = 0; r < m; ++r)
     for (int a = P->rp[r]; a < P->rp[r + 1]; ++a) col[P->ci[a]] += fabs(P->v[a]);
-  for (int k = 0; k < ns; ++k) best = fmax(best, fabs(dsbase[k] + dw) + col[k]);
+  double *bd = (double *)calloc((size_t)(ns > 0 ? ns : 1), sizeof(double));
+  blk_absrow_add(P, col, bd);
+  for (int k = 0; k < ns; ++k) best = fmax(best, fabs((bd[k] + dsbase[k]) + dw) + col[k]);
+  free(bd);
   free(col);
   for (int r = 0; r < m; ++r) {
     double t = fabs(dc) + (dcv ? fabs(dcv[r]) : 0.0);
@@ -380,6 +582,8 @@ or_factor *or_factor_new(const orq_problem *P) {
   F->ds = (double *)malloc(sizeof(double) * (size_t)(N > 0 ? N : 1));
   F->ipiv = (int32_t *)malloc(sizeof(int32_t) * (size_t)(N > 0 ? N : 1));
   F->inv_d = (double *)malloc(sizeof(double) * (size_t)(P->n_s > 0 ? P->n_s : 1));
+  const int64_t bw = or_blk_words(P);
+  F->lblk = (double *)calloc((size_t)(bw > 0 ? bw : 1), sizeof(double));
   F->dcv = (double *)calloc((size_t)(P->m > 0 ? P->m : 1), sizeof(double));
   F->sig_h = NULL;
   return F;
@@ -387,7 +591,8 @@ or_factor *or_factor_new(const orq_problem *P) {
 
 void or_factor_free(or_factor *F) {
   if (!F) return;
-  free(F->L); free(F->dd); free(F->ds); free(F->ipiv); free(F->inv_d); free(F->dcv); free(F);
+  free(F->L); free(F->dd); free(F->ds); free(F->ipiv); free(F->inv_d); free(F->lblk);
+  free(F->dcv); free(F);
 }
 
 void or_ineq_dcv(const orq_problem *P, const double *sig_h, double dw, double *dcv) {
@@ -408,7 +613,7 @@ void or_factor_once(const orq_problem *P, const double *sigma_d, const double *d
   F->dc = dc;
   /* the slack block's D_h carries the same shift dw as the Hessian blocks */
   if (F->sig_h && P->m_I > 0) or_ineq_dcv(P, F->sig_h, dw, F->dcv);
-  or_condense_dcv(P, sigma_d, dsbase, dw, dc, fac_dcv(P, F), F->L, F->inv_d);
+  or_condense_dcv(P, sigma_d, dsbase, dw, dc, fac_dcv(P, F), F->L, F->inv_d, F->lblk);
   F->info = or_bk(F->N, F->L, F->ipiv, F->dd, F->ds, NULL);
   or_inertia(F->N, F->ipiv, F->dd, F->ds, F->inertia);
 }
@@ -442,11 +647,11 @@ int or_newton_solve(const orq_problem *P, const or_factor *F, const double *r_d,
   const int nd = P->n_d, m = P->m, N = nd + m;
   double *z = (double *)malloc(sizeof(double) * (size_t)(N > 0 ? N : 1));
   for (int i = 0; i < nd; ++i) z[i] = r_d[i];
-  or_rhs_condense(P, F->inv_d, r_s, r_y, z + nd);
+  or_rhs_condense(P, F->inv_d, F->lblk, r_s, r_y, z + nd);
   int st = or_ldl_solve(N, F->L, F->ipiv, F->dd, F->ds, z);
   for (int i = 0; i < nd; ++i) dx_d[i] = z[i];
   for (int i = 0; i < m; ++i) dy[i] = z[nd + i];
-  or_backsub(P, F->inv_d, r_s, dy, dx_s);
+  or_backsub(P, F->inv_d, F->lblk, r_s, dy, dx_s);
   free(z);
   return st;
 }
@@ -533,6 +738,7 @@ static void grad_f(const orq_problem *P, const double *x, double *gf) {
     gf[i] = t + P->c[i];
   }
   for (int k = 0; k < ns; ++k) gf[nd + k] = P->w[k] * x[nd + k] + P->g[k];
+  blk_matvec_add(P, x + nd, gf + nd);
 }
 
 /* c(x, d) = J x - [b; d]: equality rows against b, inequality rows against
@@ -649,10 +855,12 @@ double or_objective(const orq_problem *P, const double *x) {
     }
     f = f + x[i] * (0.5 * t + P->c[i]);
   }
+  double *wbx = blk_product(P, x + nd);
   for (int k = 0; k < ns; ++k) {
     double xs = x[nd + k];
-    f = f + xs * (0.5 * P->w[k] * xs + P->g[k]);
+    f = f + xs * (0.5 * (P->w[k] * xs + wbx[k]) + P->g[k]);
   }
+  free(wbx);
   return f;
 }
 
@@ -681,10 +889,12 @@ static double barrier_scale(const orq_problem *P, const double *x, double mu) {
     }
     a = a + fabs(x[i] * (0.5 * t + P->c[i]));
   }
+  double *wbx = blk_product(P, x + nd);
   for (int k = 0; k < ns; ++k) {
     double xs = x[nd + k];
-    a = a + fabs(xs * (0.5 * P->w[k] * xs + P->g[k]));
+    a = a + fabs(xs * (0.5 * (P->w[k] * xs + wbx[k]) + P->g[k]));
   }
+  free(wbx);
   for (int i = 0; i < n; ++i) {
     const double lo = lo_of(P, i), up = up_of(P, i);
     if (isfinite(lo)) a = a + mu * fabs(log(x[i] - lo));
@@ -794,6 +1004,8 @@ int or_ipm(const orq_problem *P, const or_ipm_opts *o, double *x, double *y, dou
 int or_ipm_warm(const orq_problem *P, const or_ipm_opts *o, const double *xd0, const double *y0,
                 double mu0, double *x, double *y, double *zl, double *zu, int32_t *iters,
                 or_ipm_trace *trace) {
+  /* the completed start point solves a diagonal sparse block (see warm_point) */
+  if (P->nblk > 0) { *iters = 0; return 8; }
   return ipm_from(P, o, xd0, y0, mu0, x, y, zl, zu, iters, trace);
 }
 

@@ -49,20 +49,40 @@ typedef struct {
   int32_t m_I;          /* inequality rows (the last m_I of m)       */
   const double *hl;     /* m_I, may be -INFINITY                     */
   const double *hu;     /* m_I, may be +INFINITY                     */
+  /* Optional coupling blocks of the sparse Hessian (assumption A2 in its
+   * general form: a pattern that is cheap to solve with).  nblk = 0: none.
+   * Otherwise bp (nblk + 1, bp[0] = 0 < bp[1] < ... < bp[nblk] = n_s)
+   * splits the sparse variables into consecutive blocks and Wb holds each
+   * block's symmetric positive semidefinite s x s matrix (s = bp[b+1] -
+   * bp[b]), column-major, one block after the other.  The sparse block of
+   * the Hessian is then diag(w) + blockdiag(Wb). */
+  int32_t nblk;
+  const int32_t *bp;
+  const double *Wb;
 } orq_problem;
 
 /* ---- condensation (Sec. 2.2, eq. (compressed), 2x2-block form) ---------- */
-/* M (N x N, N = n_d + m, full symmetric, column-major) and inv_d = 1/(dsbase+dw). */
+/* Q_{x_s} = diag(dsbase) + dw I (+ blockdiag(Wb) when P has blocks), with
+ * dsbase = w + Sigma_s.  Without blocks: inv_d = 1/(dsbase+dw).  With
+ * blocks, every block of Q_{x_s} is factored L Delta L' (unit lower L, no
+ * pivoting): lblk holds the blocks' L in Wb's layout (strictly lower part
+ * written) and inv_d = 1/Delta; the condensation then works on the
+ * transformed Jacobian J_s L^{-T}, whose rows fill the blocks they touch.
+ * M is N x N (N = n_d + m), full symmetric, column-major.  lblk may be NULL
+ * when P has no blocks. */
 void or_condense_dcv(const orq_problem *P, const double *sigma_d, const double *dsbase,
-                     double dw, double dc, const double *dcv, double *M, double *inv_d);
+                     double dw, double dc, const double *dcv, double *M, double *inv_d,
+                     double *lblk);
 void or_condense(const orq_problem *P, const double *sigma_d, const double *dsbase,
-                 double dw, double dc, double *M, double *inv_d);
-/* rhat = r_y - J_s (inv_d .* r_s) */
-void or_rhs_condense(const orq_problem *P, const double *inv_d, const double *r_s,
-                     const double *r_y, double *rhat);
-/* dx_s = inv_d .* (r_s - J_s' dy) */
-void or_backsub(const orq_problem *P, const double *inv_d, const double *r_s,
-                const double *dy, double *dx_s);
+                 double dw, double dc, double *M, double *inv_d, double *lblk);
+/* rhat = r_y - J_s Q_{x_s}^{-1} r_s */
+void or_rhs_condense(const orq_problem *P, const double *inv_d, const double *lblk,
+                     const double *r_s, const double *r_y, double *rhat);
+/* dx_s = Q_{x_s}^{-1} (r_s - J_s' dy) */
+void or_backsub(const orq_problem *P, const double *inv_d, const double *lblk,
+                const double *r_s, const double *dy, double *dx_s);
+/* doubles of the blocks' storage (sum of s^2), 0 without blocks */
+int64_t or_blk_words(const orq_problem *P);
 
 /* ---- Bunch-Kaufman LDL' (Sec. 2.3; Bunch & Kaufman 1977) --------------- */
 /* A: N x N column-major, lower triangle read.  On exit the strictly lower
@@ -88,7 +108,7 @@ int or_ldl_solve(int32_t N, const double *L, const int32_t *ipiv, const double *
 
 /* ---- full (uncondensed) KKT operator (eq. (linsys4x4)) ------------------- */
 /* out = K * [dx_d; dx_s; dy] with
- * K = [[H+diag(sigma_d)+dw I, 0, Jd'], [0, diag(dsbase)+dw I, Js'],
+ * K = [[H+diag(sigma_d)+dw I, 0, Jd'], [0, diag(dsbase)+dw I (+ blockdiag(Wb)), Js'],
  *      [Jd, Js, -dc I - diag(dcv)]]
  * (dcv: the (4,4) block -D_h^{-1} of the inequality rows, NULL for none). */
 void or_kkt_matvec_dcv(const orq_problem *P, const double *sigma_d, const double *dsbase,
@@ -111,6 +131,7 @@ typedef struct {
   double *dd, *ds;  /* N each */
   int32_t *ipiv;    /* N */
   double *inv_d;    /* n_s */
+  double *lblk;     /* factors of Q_{x_s}'s blocks (or_blk_words doubles) */
   int32_t inertia[3];
   int32_t info;
   int32_t trials;   /* factorizations done by the last correction loop */
@@ -198,7 +219,8 @@ typedef struct {       /* one row per iteration */
 int or_ipm(const orq_problem *P, const or_ipm_opts *o, double *x, double *y, double *zl,
            double *zu, int32_t *iters, or_ipm_trace *trace);
 /* The same IPM from a warm start: proposed x_d (n_d), y (m) and barrier
- * parameter mu0 (see warm_point in mds_oracle.c for the completed point). */
+ * parameter mu0 (see warm_point in mds_oracle.c for the completed point).
+ * Returns 8 (not defined) when P has coupling blocks. */
 int or_ipm_warm(const orq_problem *P, const or_ipm_opts *o, const double *xd0, const double *y0,
                 double mu0, double *x, double *y, double *zl, double *zu, int32_t *iters,
                 or_ipm_trace *trace);

@@ -39,7 +39,8 @@ class Dims(C.Structure):
 
 class Options(C.Structure):
     _fields_ = [("nb", C.c_int32), ("panel", C.c_int32), ("precision", C.c_int32),
-                ("panel_threads", C.c_int32), ("reserved", C.c_int32 * 4)]
+                ("panel_threads", C.c_int32), ("sblk_max", C.c_int32),
+                ("reserved", C.c_int32 * 3)]
 
 
 # panel kernels: automatic choice, panel in device memory, register-resident
@@ -156,6 +157,7 @@ SIGNATURES = {
     "mds_get_matrix": (C.c_int, [_vp, _dp]),
     "mds_get_factor": (C.c_int, [_vp, _dp, _dp, _dp, _ip]),
     "mds_set_m22_diag": (C.c_int, [_vp, _vp]),
+    "mds_set_sparse_blocks": (C.c_int, [_vp, C.c_int32, _ip, _vp]),
     "mds_get_pivots": (C.c_int, [_vp, _ip]),
     "mds_get_inv_ds": (C.c_int, [_vp, _dp]),
     "mds_get_info": (C.c_int, [_vp, C.POINTER(Info)]),
@@ -223,7 +225,8 @@ class Solver:
 
     def __init__(self, n_d: int, n_s: int, m: int, nnz_s: int, nb: int = 0,
                  device: str = "cuda:0", stream=None, panel: str = "auto",
-                 precision: str = "fp64", panel_threads: int = 0, m_I: int = 0):
+                 precision: str = "fp64", panel_threads: int = 0, m_I: int = 0,
+                 sblk_max: int = 0):
         torch = _torch()
         if not torch.cuda.is_available():
             raise MdsError("no ROCm GPU visible: the mdsipm library has no CPU path")
@@ -236,7 +239,7 @@ class Solver:
         if panel not in PANELS:
             raise MdsError("panel must be one of " + ", ".join(PANELS))
         self.opts = Options(nb, PANELS[panel], PRECISIONS[precision],
-                            int(panel_threads))
+                            int(panel_threads), int(sblk_max))
         self.n_d, self.n_s, self.m, self.m_I = n_d, n_s, m, m_I
         self.N, self.n = n_d + m, n_d + n_s
         self.nx = self.n + m_I  # IPM primal vector: variables, then inequality slacks
@@ -333,6 +336,20 @@ class Solver:
             if st == 0:
                 self._keep["dcv"] = t
         return self._check(st, "mds_set_m22_diag")
+
+    def set_sparse_blocks(self, bp=None, Wb=None):
+        """Coupling blocks of the sparse Hessian (bp: block starts, n_blocks + 1
+        entries; Wb: the blocks column-major, one after another); None clears."""
+        if bp is None:
+            self._keep.pop("Wb", None)
+            return self._check(lib().mds_set_sparse_blocks(self.h, 0, None, None),
+                               "mds_set_sparse_blocks")
+        bp = np.ascontiguousarray(bp, dtype=np.int32)
+        t = self.dev(np.asarray(Wb, dtype=np.float64))
+        st = lib().mds_set_sparse_blocks(self.h, len(bp) - 1, bp.ctypes.data_as(_ip), _ptr(t))
+        if st == 0:
+            self._keep["Wb"] = t
+        return self._check(st, "mds_set_sparse_blocks")
 
     def factor_inertia(self, mu=0.0, reg=None):
         """reg None: factor as condensed.  reg dict (delta_w_last, delta_w_max):
@@ -538,11 +555,16 @@ def _step_dict(s):
 
 def solver_for(prob: dict, nb: int = 0, device: str = "cuda:0", panel: str = "auto",
                precision: str = "fp64", panel_threads: int = 0) -> Solver:
-    """Create a Solver sized for a problem dict and attach the problem."""
+    """Create a Solver sized for a problem dict and attach the problem (and
+    its coupling blocks of the sparse Hessian when it has them)."""
+    bp = prob.get("bp")
+    smax = int(np.max(np.diff(bp))) if bp is not None and len(bp) > 1 else 0
     s = Solver(prob["n_d"], prob["n_s"], prob["m"], len(prob["v"]), nb=nb, device=device,
                panel=panel, precision=precision, panel_threads=panel_threads,
-               m_I=int(prob.get("m_I", 0)))
+               m_I=int(prob.get("m_I", 0)), sblk_max=smax)
     s.set_problem(prob)
+    if smax:
+        s.set_sparse_blocks(bp, prob["Wb"])
     return s
 
 

@@ -86,7 +86,9 @@ enum Slot {
   S_M, S_M2, S_SRC, S_W, S_DD, S_DS, S_IPIV, S_BLK, S_PK0, S_FST, S_INVD, S_CPTR, S_CROW, S_CVAL, S_CFILL,
   S_FLAGS, S_RED, S_SCAL, S_Z, S_Z2, S_HMAP, S_PERM, S_COLP, S_TRSV, S_SIG, S_RX, S_RY, S_DSB, S_DX, S_DY, S_DZL, S_DZU, S_XT, S_RES,
   S_COR, S_PREV, S_KX, S_TN, S_TM, S_TN2, S_KNH, S_KNJD, S_KNY, S_KNJS, S_EQ, S_GV,
-  S_GZ, S_GRHS, S_GX, S_GW, S_GPART, S_GCOEF, S_XCH, S_XLE, S_XUE, S_DCV, S_RY2, S_COUNT
+  S_GZ, S_GRHS, S_GX, S_GW, S_GPART, S_GCOEF, S_XCH, S_XLE, S_XUE, S_DCV, S_RY2,
+  S_BBP, S_BOFF, S_BKB, S_BL, S_HRP, S_HCI, S_HSRC, S_HVAL, S_HCPTR, S_HCROW, S_HCMAP, S_HCVAL,
+  S_BT1, S_BT2, S_COUNT
 };
 
 struct Layout {
@@ -96,7 +98,15 @@ struct Layout {
 
 int default_nb(int N) { return (N >= 64) ? 16 : 8; }
 
-Layout make_layout(const mds_dims &d, int nb, bool pingpong, int precision) {
+// entries of the transformed Jacobian J_s L^{-T} at most: every entry of J_s
+// brings at most its block's other columns
+size_t sblk_nnz_max(const mds_dims &d, int sblk_max) {
+  if (sblk_max <= 0) return 0;
+  const size_t a = (size_t)d.nnz_s * (size_t)sblk_max, b = (size_t)d.m * (size_t)d.n_s;
+  return std::min(a, b);
+}
+
+Layout make_layout(const mds_dims &d, int nb, bool pingpong, int precision, int sblk_max) {
   const size_t nd = d.n_d, ns = d.n_s, m = d.m, N = nd + m, n = nd + ns;
   const size_t nx = n + (size_t)d.m_I;
   const size_t nnz = (size_t)d.nnz_s;
@@ -147,6 +157,17 @@ Layout make_layout(const mds_dims &d, int nb, bool pingpong, int precision) {
   bytes[S_KNH] = bytes[S_KNJD] = 8 * nd;
   bytes[S_KNY] = 8 * m;
   bytes[S_KNJS] = 8 * ns;
+  if (sblk_max > 0) {
+    const size_t hn = sblk_nnz_max(d, sblk_max);
+    bytes[S_BBP] = 4 * (ns + 1);
+    bytes[S_BOFF] = bytes[S_BKB] = 4 * ns;
+    bytes[S_BL] = 8 * ns * (size_t)sblk_max;
+    bytes[S_HRP] = 4 * (m + 1);
+    bytes[S_HCI] = bytes[S_HSRC] = bytes[S_HCROW] = bytes[S_HCMAP] = 4 * hn;
+    bytes[S_HVAL] = bytes[S_HCVAL] = 8 * hn;
+    bytes[S_HCPTR] = 4 * (ns + 1);
+    bytes[S_BT1] = bytes[S_BT2] = 8 * ns;
+  }
   Layout L{};
   size_t o = 0;
   for (int s = 0; s < S_COUNT; ++s) {
@@ -249,11 +270,22 @@ int condense_impl(mds_handle *h, double dw, double dc) {
   }
   {
     TimedLaunch t(h, MDS_T_CONDENSE);
-    launch_inv_d(S(h), NS(h), h->dsbase, dw, h->w.inv_d);
+    const SBlk &B = h->sb;
+    if (B.nblk > 0) {
+      // blocks of Q_{x_s}: L Delta L', inv_d = 1/Delta, Jh = J_s L^{-T}
+      sblk_factor(S(h), B, h->dsbase, dw, h->w.inv_d);
+      sblk_transform(S(h), B, MM(h), h->P.Js_val);
+    } else {
+      launch_inv_d(S(h), NS(h), h->dsbase, dw, h->w.inv_d);
+    }
     launch_condense_dense(S(h), ND(h), MM(h), h->P.H, h->P.J_d, h->sigma_d, dw, h->w.M);
-    launch_condense_schur(S(h), ND(h), MM(h), h->N, h->P.Js_rowptr, h->P.Js_col, h->P.Js_val,
-                          h->w.csc_ptr, h->w.csc_row, h->w.csc_val, h->w.inv_d, dc, h->dcv_cur,
-                          h->w.M);
+    if (B.nblk > 0)
+      launch_condense_schur(S(h), ND(h), MM(h), h->N, B.hrp, B.hci, B.hval, B.hcptr, B.hcrow,
+                            B.hcval, h->w.inv_d, dc, h->dcv_cur, h->w.M);
+    else
+      launch_condense_schur(S(h), ND(h), MM(h), h->N, h->P.Js_rowptr, h->P.Js_col, h->P.Js_val,
+                            h->w.csc_ptr, h->w.csc_row, h->w.csc_val, h->w.inv_d, dc,
+                            h->dcv_cur, h->w.M);
   }
   HIPCHK(hipGetLastError());
   h->dw = dw;
@@ -495,8 +527,16 @@ int solve_impl(mds_handle *h, const double *r_d, const double *r_s, const double
                double *dx_d, double *dx_s, double *dy) {
   const int nd = ND(h), ns = NS(h), m = MM(h), N = h->N;
   if (nd > 0) HIPCHK(hipMemcpyAsync(h->w.z, r_d, 8 * (size_t)nd, hipMemcpyDeviceToDevice, S(h)));
-  launch_rhs_condense(S(h), m, h->P.Js_rowptr, h->P.Js_col, h->P.Js_val, h->w.inv_d, r_s, r_y,
-                      h->w.z + nd);
+  const SBlk &B = h->sb;
+  if (B.nblk > 0) {
+    // r_y - Jh Delta^{-1} (L^{-1} r_s)
+    vec_copy(S(h), ns, r_s, B.tmp);
+    sblk_solve(S(h), B, h->w.inv_d, 0, B.tmp);
+    launch_rhs_condense(S(h), m, B.hrp, B.hci, B.hval, h->w.inv_d, B.tmp, r_y, h->w.z + nd);
+  } else {
+    launch_rhs_condense(S(h), m, h->P.Js_rowptr, h->P.Js_col, h->P.Js_val, h->w.inv_d, r_s, r_y,
+                        h->w.z + nd);
+  }
   ensure_std(h);
   {
     TimedLaunch t(h, MDS_T_SOLVE);
@@ -509,7 +549,15 @@ int solve_impl(mds_handle *h, const double *r_d, const double *r_s, const double
   h->nsolves++;
   if (nd > 0) HIPCHK(hipMemcpyAsync(dx_d, h->w.z, 8 * (size_t)nd, hipMemcpyDeviceToDevice, S(h)));
   if (m > 0) HIPCHK(hipMemcpyAsync(dy, h->w.z + nd, 8 * (size_t)m, hipMemcpyDeviceToDevice, S(h)));
-  launch_backsub(S(h), ns, h->w.csc_ptr, h->w.csc_row, h->w.csc_val, h->w.inv_d, r_s, dy, dx_s);
+  if (B.nblk > 0) {
+    // L^{-T} Delta^{-1} L^{-1} (r_s - J_s' dy): the unscaled back-substitution
+    // (inverse diagonal of ones), then the block solves
+    launch_backsub(S(h), ns, h->w.csc_ptr, h->w.csc_row, h->w.csc_val, nullptr, r_s, dy, dx_s);
+    sblk_solve(S(h), B, h->w.inv_d, 1, dx_s);
+  } else {
+    launch_backsub(S(h), ns, h->w.csc_ptr, h->w.csc_row, h->w.csc_val, h->w.inv_d, r_s, dy,
+                   dx_s);
+  }
   HIPCHK(hipGetLastError());
   return MDS_OK;
 }
@@ -534,6 +582,7 @@ void kkt_matvec(mds_handle *h, const double *dxd, const double *dxs, const doubl
   }
   kkt_finish(S(h), nd, ns, m, h->sigma_d, h->dsbase, h->dw, h->dc, h->dcv_cur, dxd, dxs, dy, od,
              os, oy);
+  if (h->sb.nblk > 0) sblk_matvec(S(h), h->sb, ns, dxs, true, os);
 }
 
 int read_scal(mds_handle *h, double *dst, int count) {
@@ -597,7 +646,7 @@ int gmres_refine(mds_handle *h, const double *r_d, const double *r_s, const doub
   TRY(solve_impl(h, r, r + nd, r + nd + ns, x, x + nd, x + nd + ns));
   kkt_norm_parts(S(h), nd, ns, m, h->P.H, h->sigma_d, h->dw, h->P.J_d, h->P.Js_rowptr,
                  h->P.Js_val, h->w.csc_ptr, h->w.csc_val, h->dsbase, h->dc, h->dcv_cur, h->w.kn_h,
-                 h->w.kn_jd, h->w.kn_y, h->w.kn_js, h->w.red, h->w.scal);
+                 h->w.kn_jd, h->w.kn_y, h->w.kn_js, h->w.red, h->w.scal, &h->sb);
   HIPCHK(hipGetLastError());
   double s8[8];
   TRY(read_scal(h, s8, 8));
@@ -701,7 +750,7 @@ int refine_impl(mds_handle *h, const double *r_d, const double *r_s, const doubl
   // ||K||_inf parts and ||r||_inf: two reductions, one read-back
   kkt_norm_parts(S(h), nd, ns, m, h->P.H, h->sigma_d, h->dw, h->P.J_d, h->P.Js_rowptr,
                  h->P.Js_val, h->w.csc_ptr, h->w.csc_val, h->dsbase, h->dc, h->dcv_cur, h->w.kn_h,
-                 h->w.kn_jd, h->w.kn_y, h->w.kn_js, h->w.red, h->w.scal);
+                 h->w.kn_jd, h->w.kn_y, h->w.kn_js, h->w.red, h->w.scal, &h->sb);
   ipm_red_amax3(S(h), nd, r_d, ns, r_s, m, r_y, h->w.red, h->w.scal + 8);
   HIPCHK(hipGetLastError());
   double s16[16];
@@ -764,6 +813,7 @@ void eval_grad_constr(mds_handle *h, const double *x, const double *y, double *r
   double *gf = h->w.tn, *jty = h->w.tn2, *cx = h->w.tm;
   launch_gemv_n(S(h), nd, nd, P.H, nd, x, 0.0, gf);
   ipm_grad_finish(S(h), nd, ns, P.c, P.w, P.g, x, gf);
+  if (h->sb.nblk > 0) sblk_matvec(S(h), h->sb, ns, x + nd, true, gf + nd);
   if (y) {
     if (nd > 0) {
       if (m > 0) launch_gemv_t(S(h), m, nd, P.J_d, m, y, 0.0, jty);
@@ -847,8 +897,13 @@ void merit_launch(mds_handle *h, const double *x, double mu, double *out) {
     }
     ipm_constr_finish(S(h), m, h->mE, P.b, x + h->n, cx, nullptr);
   }
-  ipm_red_merit(S(h), nd, ns, h->nx, m, mu, x, hx, P.c, P.w, P.g, h->w.xl_e, h->w.xu_e, cx,
-                h->w.red, out);
+  const double *wbx = nullptr;
+  if (h->sb.nblk > 0) {
+    sblk_matvec(S(h), h->sb, ns, x + nd, false, h->sb.tmp2);
+    wbx = h->sb.tmp2;
+  }
+  ipm_red_merit(S(h), nd, ns, h->nx, m, mu, x, hx, P.c, P.w, P.g, wbx, h->w.xl_e, h->w.xu_e,
+                cx, h->w.red, out);
 }
 
 int merit_impl(mds_handle *h, const double *x, double mu, double *f, double *phi, double *theta) {
@@ -880,7 +935,9 @@ size_t mds_workspace_bytes(const mds_dims *dims, const mds_options *opts) {
   if (!dims_ok(dims)) return 0;
   const PanelChoice pc = panel_of(*dims, opts);
   if (pc.nb == 0) return 0;
-  return make_layout(*dims, pc.nb, pc.reg, opts ? opts->precision : MDS_FP64).total;
+  const int sbm = opts ? opts->sblk_max : 0;
+  if (sbm < 0 || sbm > kSBlkMax) return 0;
+  return make_layout(*dims, pc.nb, pc.reg, opts ? opts->precision : MDS_FP64, sbm).total;
 }
 
 int mds_create(mds_handle **out, const mds_dims *dims, const mds_options *opts, void *stream,
@@ -891,7 +948,9 @@ int mds_create(mds_handle **out, const mds_dims *dims, const mds_options *opts, 
   const int nb = nb_of(*dims, opts);
   if (nb == 0) return MDS_EINVAL;
   const int prec = opts ? opts->precision : MDS_FP64;
-  const Layout L = make_layout(*dims, nb, panel_of(*dims, opts).reg, prec);
+  const int sbm = opts ? opts->sblk_max : 0;
+  if (sbm < 0 || sbm > kSBlkMax) return MDS_EINVAL;
+  const Layout L = make_layout(*dims, nb, panel_of(*dims, opts).reg, prec, sbm);
   const PanelChoice pc = panel_of(*dims, opts);
   // every workgroup of the cooperative panel must be resident at once; if
   // the device cannot guarantee it, the memory panel (FP64) factors instead
@@ -990,6 +1049,24 @@ int mds_create(mds_handle **out, const mds_dims *dims, const mds_options *opts, 
   w.kn_jd = D(S_KNJD);
   w.kn_y = D(S_KNY);
   w.kn_js = D(S_KNJS);
+  h->sblk_max = sbm;
+  if (sbm > 0) {
+    SBlk &B = h->sb;
+    B.bp = I(S_BBP);
+    B.boff = I(S_BOFF);
+    B.kblk = I(S_BKB);
+    B.lblk = D(S_BL);
+    B.hrp = I(S_HRP);
+    B.hci = I(S_HCI);
+    B.hsrc = I(S_HSRC);
+    B.hval = D(S_HVAL);
+    B.hcptr = I(S_HCPTR);
+    B.hcrow = I(S_HCROW);
+    B.hcmap = I(S_HCMAP);
+    B.hcval = D(S_HCVAL);
+    B.tmp = D(S_BT1);
+    B.tmp2 = D(S_BT2);
+  }
   if (std_prepare() != hipSuccess || bk_lds_prepare() != hipSuccess ||
       hipMemsetAsync(w.trsv, 0, 4 * (4 + 2 * (size_t)std_solve_blocks(h->N)), h->stream) !=
           hipSuccess ||
@@ -1027,6 +1104,7 @@ int mds_set_problem(mds_handle *h, const mds_problem *p) {
   h->ipm_ready = false;
   h->dcv_user = h->dcv_cur = nullptr;
   h->sig_h = nullptr;
+  h->sb.nblk = 0;
   HIPCHK(hipMemsetAsync(h->w.flags, 0, 64, S(h)));
   launch_validate(S(h), d, *p, h->w.flags);
   check_ineq_bounds(S(h), (int)mI, p->hl, p->hu, h->w.flags + 5);
@@ -1066,6 +1144,127 @@ int mds_condense(mds_handle *h, const double *sigma_d, const double *dsbase, dou
   h->sigma_d = sigma_d;
   h->dsbase = dsbase;
   return condense_impl(h, delta_w, delta_c);
+}
+
+int mds_set_sparse_blocks(mds_handle *h, int32_t nblk, const int32_t *bp_host,
+                          const double *Wb) {
+  TRY(check_ready(h));
+  SBlk &B = h->sb;
+  if (nblk == 0) {
+    B.nblk = 0;
+    h->have_M = h->have_factor = false;
+    return MDS_OK;
+  }
+  if (h->sblk_max <= 0)
+    return set_err(h, MDS_ESTATE, "the workspace has no room for blocks (options.sblk_max = 0)");
+  const int ns = NS(h), m = MM(h);
+  if (nblk < 0 || nblk > ns) return set_err(h, MDS_EDIMS, "nblk must be in [0, n_s]");
+  if (!bp_host || !Wb) return set_err(h, MDS_ENULL, "bp_host / Wb missing");
+  if (bp_host[0] != 0 || bp_host[nblk] != ns)
+    return set_err(h, MDS_EINVAL, "blocks must cover 0 .. n_s");
+  std::vector<int32_t> boff(nblk), kblk(ns);
+  int64_t words = 0;
+  for (int b = 0; b < nblk; ++b) {
+    const int sz = bp_host[b + 1] - bp_host[b];
+    if (sz < 1 || sz > h->sblk_max)
+      return set_err(h, MDS_EINVAL, "block %d has size %d (1 .. %d allowed)", b, sz, h->sblk_max);
+    boff[b] = (int32_t)words;
+    for (int k = bp_host[b]; k < bp_host[b + 1]; ++k) kblk[k] = b;
+    words += (int64_t)sz * sz;
+  }
+  // the blocks: finite, exactly symmetric, positive semidefinite (their
+  // L Delta L' after a shift of 1e-12 of the largest diagonal has Delta > 0)
+  std::vector<double> wb((size_t)words);
+  HIPCHK(hipMemcpyAsync(wb.data(), Wb, 8 * (size_t)words, hipMemcpyDeviceToHost, S(h)));
+  HIPCHK(hipStreamSynchronize(S(h)));
+  for (int b = 0; b < nblk; ++b) {
+    const int sz = bp_host[b + 1] - bp_host[b];
+    const double *Q = wb.data() + boff[b];
+    double dmax = 0.0;
+    for (int i = 0; i < sz; ++i) {
+      for (int j = 0; j < sz; ++j) {
+        if (!std::isfinite(Q[i + j * sz]))
+          return set_err(h, MDS_ENONFINITE_INPUT, "non-finite entry in block %d", b);
+        if (Q[i + j * sz] != Q[j + i * sz])
+          return set_err(h, MDS_EINVAL, "block %d is not exactly symmetric", b);
+      }
+      dmax = std::max(dmax, Q[i + i * sz]);
+    }
+    double L[kSBlkMax * kSBlkMax], dl[kSBlkMax];
+    const double shift = 1e-12 * dmax + 1e-300;
+    for (int j = 0; j < sz; ++j) {
+      double d = Q[j + j * sz] + shift;
+      for (int t = 0; t < j; ++t) d -= L[j + t * sz] * L[j + t * sz] * dl[t];
+      if (!(d > 0.0))
+        return set_err(h, MDS_EDS_NONPOS, "block %d is not positive semidefinite", b);
+      dl[j] = d;
+      for (int i = j + 1; i < sz; ++i) {
+        double e = Q[i + j * sz];
+        for (int t = 0; t < j; ++t) e -= L[i + t * sz] * L[j + t * sz] * dl[t];
+        L[i + j * sz] = e / d;
+      }
+    }
+  }
+  // pattern of J_s (host), then that of Jh = J_s L^{-T}: every column of
+  // every block a row touches, blocks ascending
+  const int64_t nnz = h->dims.nnz_s;
+  std::vector<int32_t> rp(m + 1), ci((size_t)std::max<int64_t>(nnz, 1));
+  HIPCHK(hipMemcpyAsync(rp.data(), h->P.Js_rowptr, 4 * (size_t)(m + 1), hipMemcpyDeviceToHost,
+                        S(h)));
+  if (nnz > 0)
+    HIPCHK(hipMemcpyAsync(ci.data(), h->P.Js_col, 4 * (size_t)nnz, hipMemcpyDeviceToHost, S(h)));
+  HIPCHK(hipStreamSynchronize(S(h)));
+  std::vector<int32_t> hrp(m + 1, 0), hci, hsrc;
+  for (int i = 0; i < m; ++i) {
+    int a = rp[i];
+    while (a < rp[i + 1]) {
+      const int b = kblk[ci[a]], k0 = bp_host[b], sz = bp_host[b + 1] - k0;
+      for (int p = 0; p < sz; ++p) {
+        int src = -1;
+        if (a < rp[i + 1] && ci[a] == k0 + p) src = a++;
+        hci.push_back(k0 + p);
+        hsrc.push_back(src);
+      }
+    }
+    hrp[i + 1] = (int32_t)hci.size();
+  }
+  const int64_t hn = (int64_t)hci.size();
+  if ((size_t)hn > sblk_nnz_max(h->dims, h->sblk_max))
+    return set_err(h, MDS_EWORKSPACE, "transformed Jacobian exceeds the workspace");
+  // its CSC copy: rows ascending in every column, with the CSR entry of each
+  std::vector<int32_t> hcptr(ns + 1, 0), hcrow((size_t)std::max<int64_t>(hn, 1)),
+      hcmap((size_t)std::max<int64_t>(hn, 1));
+  for (int64_t e = 0; e < hn; ++e) hcptr[hci[e] + 1]++;
+  for (int k = 0; k < ns; ++k) hcptr[k + 1] += hcptr[k];
+  {
+    std::vector<int32_t> fill(hcptr.begin(), hcptr.end() - 1);
+    for (int i = 0; i < m; ++i)
+      for (int e = hrp[i]; e < hrp[i + 1]; ++e) {
+        const int q = fill[hci[e]]++;
+        hcrow[q] = i;
+        hcmap[q] = e;
+      }
+  }
+  auto up = [&](void *dst, const void *src, size_t bytes) -> int {
+    if (bytes == 0) return MDS_OK;
+    HIPCHK(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, S(h)));
+    return MDS_OK;
+  };
+  TRY(up((void *)B.bp, bp_host, 4 * (size_t)(nblk + 1)));
+  TRY(up((void *)B.boff, boff.data(), 4 * (size_t)nblk));
+  TRY(up((void *)B.kblk, kblk.data(), 4 * (size_t)ns));
+  TRY(up(B.hrp, hrp.data(), 4 * (size_t)(m + 1)));
+  TRY(up(B.hci, hci.data(), 4 * (size_t)hn));
+  TRY(up(B.hsrc, hsrc.data(), 4 * (size_t)hn));
+  TRY(up(B.hcptr, hcptr.data(), 4 * (size_t)(ns + 1)));
+  TRY(up(B.hcrow, hcrow.data(), 4 * (size_t)hn));
+  TRY(up(B.hcmap, hcmap.data(), 4 * (size_t)hn));
+  HIPCHK(hipStreamSynchronize(S(h)));
+  B.nblk = nblk;
+  B.nnz = hn;
+  B.Wb = Wb;
+  h->have_M = h->have_factor = false;
+  return MDS_OK;
 }
 
 int mds_set_m22_diag(mds_handle *h, const double *dcv) {
@@ -1222,6 +1421,9 @@ int mds_ipm_init_warm(mds_handle *h, mds_iterate *it, const mds_ipm_opts *opts,
   TRY(ipm_opts_check(h, it));
   if ((ND(h) > 0 && !x_d0) || (MM(h) > 0 && !y0)) return set_err(h, MDS_ENULL, "start point missing");
   if (!(mu0 > 0.0) || !std::isfinite(mu0)) return set_err(h, MDS_EINVAL, "mu0 must be positive");
+  if (h->sb.nblk > 0)
+    return set_err(h, MDS_ESTATE, "the warm start completes x_s for a diagonal sparse Hessian "
+                                  "(coupling blocks are set)");
   mds_ipm_opts o{1e-8, 0.1, 200, 2, 1e20, 0, 0};
   if (opts) o = *opts;
   h->ipm = o;

@@ -117,7 +117,7 @@ __global__ void k_backsub(int ns, const int32_t *__restrict__ cptr,
   if (k >= ns) return;
   double t = r_s[k];
   for (int e = cptr[k]; e < cptr[k + 1]; ++e) t = t - cval[e] * dy[crow[e]];
-  dx_s[k] = inv_d[k] * t;
+  dx_s[k] = inv_d ? inv_d[k] * t : t;
 }
 
 // ---- column-compressed copy of J_s ----------------------------------------

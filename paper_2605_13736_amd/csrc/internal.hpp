@@ -19,6 +19,25 @@ constexpr int kDotBlocks = 64;       // blocks per column of a Krylov dot produc
 constexpr int kGmresRestart = 20;    // GMRES restart length of the mixed-precision refinement
 constexpr int kCoopMaxP = 32;        // cooperative panel: most workgroups
 constexpr int kCoopSlotWords = 512;  // cooperative panel: 64-bit exchange words per workgroup and parity
+constexpr int kSBlkMax = 16;         // largest coupling block of the sparse Hessian
+
+// Coupling blocks of the sparse Hessian (sblock.hip) and the transformed
+// Jacobian Jh = J_s L^{-T} they induce (device pointers into the workspace;
+// Wb is the caller's).
+struct SBlk {
+  int nblk = 0;
+  int64_t nnz = 0;                     // entries of Jh
+  const int32_t *bp = nullptr;         // nblk + 1 block starts
+  const int32_t *boff = nullptr;       // nblk offsets of the blocks in Wb / lblk
+  const int32_t *kblk = nullptr;       // n_s: block of each sparse variable
+  const double *Wb = nullptr;          // the blocks (caller's), column-major
+  double *lblk = nullptr;              // their unit lower factors, same layout
+  int32_t *hrp = nullptr, *hci = nullptr, *hsrc = nullptr;  // Jh CSR; source entry of J_s or -1
+  double *hval = nullptr;
+  int32_t *hcptr = nullptr, *hcrow = nullptr, *hcmap = nullptr;  // Jh CSC; CSC -> CSR entry
+  double *hcval = nullptr;
+  double *tmp = nullptr, *tmp2 = nullptr;  // n_s scratch
+};
 
 // Device-side factorization progress, written by the panel kernel.
 struct FacState {
@@ -88,6 +107,8 @@ struct mds_handle {
   bool panel_tail = false; // ... with the register panel once its rows fit one workgroup
   bool panel_lds = false;  // whole M in one workgroup's LDS, unblocked
   const double *dcv_user = nullptr;  // caller's per-row diagonal subtracted from M22 (m)
+  int sblk_max = 0;        // largest coupling block the workspace was sized for
+  mds::SBlk sb{};          // coupling blocks of the sparse Hessian (sb.nblk = 0: none)
   const double *dcv_cur = nullptr;   // diagonal of the current M: dcv_user or w.dcv
   const double *sig_h = nullptr;     // IPM: slack barrier diagonal (mI) behind w.dcv
   // factorization mode and the kind of the current factor
@@ -128,6 +149,18 @@ struct mds_handle {
 
 // ---- kernel launch wrappers (defined in the .hip files) --------------------
 namespace mds {
+
+// sblock.hip: the blocks' L Delta L' (inv_d = 1/Delta), the values of Jh
+// and its CSC copy, block solves (mode 0: u = L^{-1} u; mode 1: u = L^{-T}
+// (inv_d .* L^{-1} u)), out (+)= blockdiag(Wb) u, and the (2,2) row pieces of
+// ||K||_inf (off-diagonal |Wb| row sums added to jscol; dsb_eff = Wb_kk + dsb)
+void sblk_factor(hipStream_t s, const SBlk &B, const double *dsb, double dw, double *inv_d);
+void sblk_transform(hipStream_t s, const SBlk &B, int m, const double *jsv);
+void sblk_solve(hipStream_t s, const SBlk &B, const double *inv_d, int mode, double *u);
+void sblk_matvec(hipStream_t s, const SBlk &B, int ns, const double *u, bool accumulate,
+                 double *out);
+void sblk_absrow(hipStream_t s, const SBlk &B, int ns, const double *dsb, double *jscol,
+                 double *dsb_eff);
 
 // condense.hip
 void launch_inv_d(hipStream_t s, int ns, const double *dsbase, double dw, double *inv_d);

@@ -304,6 +304,7 @@ __global__ __launch_bounds__(RB) void k_red_merit(int nd, int ns, int nx, int m,
                                                   const double *__restrict__ c,
                                                   const double *__restrict__ w,
                                                   const double *__restrict__ g,
+                                                  const double *__restrict__ wbx,
                                                   const double *__restrict__ xl,
                                                   const double *__restrict__ xu,
                                                   const double *__restrict__ cx,
@@ -319,7 +320,9 @@ __global__ __launch_bounds__(RB) void k_red_merit(int nd, int ns, int nx, int m,
       v[7] += fabs(t);
     } else if (e < n) {
       const double xs = x[e];
-      const double t = xs * (0.5 * w[e - nd] * xs + g[e - nd]);
+      // with coupling blocks: 0.5 x_s' (diag(w) + blockdiag(Wb)) x_s + g' x_s
+      const double t = wbx ? xs * (0.5 * (w[e - nd] * xs + wbx[e - nd]) + g[e - nd])
+                           : xs * (0.5 * w[e - nd] * xs + g[e - nd]);
       v[4] += t;
       v[7] += fabs(t);
     }
@@ -724,10 +727,10 @@ void ipm_red_opt_pair(hipStream_t s, int n, int m, const double *x, const double
 
 void ipm_red_merit(hipStream_t s, int nd, int ns, int nx, int m, double mu, const double *x,
                    const double *hx, const double *c, const double *w, const double *g,
-                   const double *xl, const double *xu, const double *cx, double *red,
-                   double *out) {
+                   const double *wbx, const double *xl, const double *xu, const double *cx,
+                   double *red, double *out) {
   const unsigned gr = red_grid(nx > m ? nx : m);
-  k_red_merit<<<gr, RB, 0, s>>>(nd, ns, nx, m, mu, x, hx, c, w, g, xl, xu, cx, red);
+  k_red_merit<<<gr, RB, 0, s>>>(nd, ns, nx, m, mu, x, hx, c, w, g, wbx, xl, xu, cx, red);
   k_red_final<<<1, 256, 0, s>>>((int)gr, red, out);
 }
 
@@ -831,13 +834,19 @@ void kkt_norm_parts(hipStream_t s, int nd, int ns, int m, const double *H, const
                     double dw, const double *Jd, const int32_t *rp, const double *v,
                     const int32_t *cptr, const double *cval, const double *dsb, double dc,
                     const double *dcv, double *hrow, double *jdcol, double *yrow, double *jscol,
-                    double *red, double *out) {
+                    double *red, double *out, const SBlk *sb) {
   if (nd > 0) {
     k_abs_hrow<<<grid1(nd, 4), 256, 0, s>>>(nd, H, sig, dw, hrow);
     k_abs_jdcol<<<grid1(nd, 4), 256, 0, s>>>(m, nd, Jd, jdcol);
   }
   if (m > 0) k_abs_yrow<<<grid1(m, 64), 256, 0, s>>>(m, nd, Jd, rp, v, yrow);
   if (ns > 0) k_abs_jscol<<<grid1(ns, 256), 256, 0, s>>>(ns, cptr, cval, jscol);
+  if (sb && sb->nblk > 0 && ns > 0) {
+    // coupling blocks: their off-diagonal row sums join J_s's column sums,
+    // their diagonal joins dsbase
+    sblk_absrow(s, *sb, ns, dsb, jscol, sb->tmp2);
+    dsb = sb->tmp2;
+  }
   int64_t len = nd > ns ? nd : ns;
   len = len > m ? len : m;
   const unsigned g = red_grid(len);

@@ -5,6 +5,8 @@
 
 #include <cstdint>
 
+#include "internal.hpp"
+
 namespace mds {
 
 void ipm_init_point(hipStream_t s, int n, int m, const double *xl, const double *xu, double *x,
@@ -50,10 +52,12 @@ void ipm_red_opt(hipStream_t s, int n, int m, const double *x, const double *y, 
 void ipm_red_opt_pair(hipStream_t s, int n, int m, const double *x, const double *y, const double *zl,
                  const double *zu, const double *xl, const double *xu, const double *gf,
                  const double *jty, const double *cx, double mu, double *red, double *out);
+// wbx (may be null): blockdiag(Wb) x_s, the coupling blocks' part of the
+// sparse Hessian times x_s
 void ipm_red_merit(hipStream_t s, int nd, int ns, int nx, int m, double mu, const double *x,
                    const double *hx, const double *c, const double *w, const double *g,
-                   const double *xl, const double *xu, const double *cx, double *red,
-                   double *out);
+                   const double *wbx, const double *xl, const double *xu, const double *cx,
+                   double *red, double *out);
 void ipm_red_gphi(hipStream_t s, int n, const double *gf, const double *x, const double *xl,
                   const double *xu, const double *dx, double mu, double *red, double *out);
 void ipm_red_ftb(hipStream_t s, int n, const double *x, const double *xl, const double *xu,
@@ -85,7 +89,6 @@ void kkt_norm_parts(hipStream_t s, int nd, int ns, int m, const double *H, const
                     double dw, const double *Jd, const int32_t *rp, const double *v,
                     const int32_t *cptr, const double *cval, const double *dsb, double dc,
                     const double *dcv, double *hrow, double *jdcol, double *yrow, double *jscol,
-                    double *red,
-                    double *out);
+                    double *red, double *out, const SBlk *sb);
 
 }  // namespace mds

@@ -22,9 +22,16 @@ grids, are not available; these draws stand in for them):
   the lower bound, a quarter only the upper one (so x0 is strictly feasible
   and some bounds bind at the solution).
 
+* optional coupling blocks of the sparse Hessian (assumption A2 in its
+  general form): the sparse variables split into consecutive blocks of
+  1 .. sblk variables (sizes uniform), each block B B'/s + 0.01 I with
+  B ~ N(0,1) (s x s), added to diag(w).
+
 Draw order inside one ``SeedSequence([cfg, p])`` stream:
 x0_d, x0_s, Q, lam, G (for U), c, w, g, J_s pattern, J_s values, J_d, and
 then (only when m_I > 0) a, c and the side selector of the inequality rows.
+The coupling blocks come from a stream of their own, ``SeedSequence([cfg,
+p, 5])``: sizes, then the B of each block in order.
 """
 from __future__ import annotations
 
@@ -68,12 +75,14 @@ def _pattern(rng, m, n_s, r):
 
 
 def make_problem(n_d: int, n_s: int, m: int, r: int, cfg: int = 0, p: int = 0,
-                 h_scale: str = "n_d", s_scale: float = 1.0, m_I: int = 0) -> dict:
+                 h_scale: str = "n_d", s_scale: float = 1.0, m_I: int = 0,
+                 sblk: int = 0) -> dict:
     """One seeded problem.  h_scale='n_d' divides Q Q' by n_d (and J_d by
     sqrt(n_d)); '64' uses the literal constant 64 for both.  s_scale widens the
     eigenvalue range of S to U[-s_scale, s_scale] (a more nonconvex variant
     used to exercise the inertia correction).  m_I: number of inequality rows
-    (the last m_I of the m rows)."""
+    (the last m_I of the m rows).  sblk > 0: coupling blocks of at most sblk
+    sparse variables (keys bp, Wb)."""
     rng = _rng(cfg, p)
     x0_d = rng.uniform(-0.5, 0.5, n_d)
     x0_s = rng.uniform(-0.5, 0.5, n_s)
@@ -110,10 +119,33 @@ def make_problem(n_d: int, n_s: int, m: int, r: int, cfg: int = 0, p: int = 0,
         hx0 = b[m - m_I:]
         hl = np.where(side == 1, -np.inf, hx0 - lo_w)
         hu = np.where(side == 0, np.inf, hx0 + up_w)
-    return dict(n_d=n_d, n_s=n_s, m=m, r=rr, H=np.asfortranarray(H), c=c, w=w, g=g,
-                Jd=np.asfortranarray(Jd), rp=rp, ci=ci, v=vals, b=b,
-                xl=-np.ones(n), xu=np.ones(n), x0=np.concatenate([x0_d, x0_s]),
-                m_I=m_I, hl=hl, hu=hu)
+    out = dict(n_d=n_d, n_s=n_s, m=m, r=rr, H=np.asfortranarray(H), c=c, w=w, g=g,
+               Jd=np.asfortranarray(Jd), rp=rp, ci=ci, v=vals, b=b,
+               xl=-np.ones(n), xu=np.ones(n), x0=np.concatenate([x0_d, x0_s]),
+               m_I=m_I, hl=hl, hu=hu)
+    if sblk > 0 and n_s > 0:
+        out.update(sparse_blocks(n_s, sblk, cfg, p))
+    return out
+
+
+def sparse_blocks(n_s: int, sblk: int, cfg: int, p: int) -> dict:
+    """Coupling blocks over n_s sparse variables: bp (block starts) and Wb
+    (each block B B'/s + 0.01 I, column-major, exactly symmetric)."""
+    rng = np.random.default_rng(np.random.SeedSequence([int(cfg), int(p), 5]))
+    sizes = []
+    left = n_s
+    while left > 0:
+        sz = min(int(rng.integers(1, sblk + 1)), left)
+        sizes.append(sz)
+        left -= sz
+    bp = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int32)
+    parts = []
+    for sz in sizes:
+        B = rng.standard_normal((sz, sz))
+        Wb = B @ B.T / sz + 0.01 * np.eye(sz)
+        Wb = 0.5 * (Wb + Wb.T)
+        parts.append(Wb.reshape(-1, order="F"))
+    return dict(bp=bp, Wb=np.concatenate(parts))
 
 
 def config_problem(cfg: int, p: int = 0, **kw) -> dict:
