@@ -218,7 +218,7 @@ def panel_latency_model(tim, efacs, N, nb):
     return out
 
 
-def precision_sweep(prob, st, N, reps=2):
+def precision_sweep(prob, st, N, reps=2, precs=("fp64", "fp32", "bf16x3", "bf16")):
     """The headline Newton matrix without shifts (the first trial of the
     correction loop) in each precision: condense + factor + refined solve to
     backward error 1e-14 (classic FP64 refinement for FP64, at most 60 FP64
@@ -234,7 +234,7 @@ def precision_sweep(prob, st, N, reps=2):
     except (OSError, KeyError, ValueError):
         pass
     out, x64 = {}, None
-    for prec in ("fp64", "fp32", "bf16x3", "bf16"):
+    for prec in precs:
         S = mds.solver_for(prob, precision=prec)
         sd, db = S.dev(st["sigma_d"]), S.dev(st["dsbase"])
         rd, rs, ry = S.dev(st["r_d"]), S.dev(st["r_s"]), S.dev(st["r_y"])
@@ -275,9 +275,10 @@ def precision_sweep(prob, st, N, reps=2):
         out[prec] = rec
         del S
         torch.cuda.empty_cache()
-    base = out["fp64"]["ms_condense_factor_refine"]
+    base = out[precs[0]]["ms_condense_factor_refine"]
     for prec, rec in out.items():
-        rec["speedup_vs_fp64"] = base / rec["ms_condense_factor_refine"]
+        if "fp64" in out:
+            rec["speedup_vs_fp64"] = base / rec["ms_condense_factor_refine"]
         rec["converged_1e-14"] = rec["eta"] <= 1e-14
     return out
 
@@ -489,6 +490,61 @@ def batch_section(count, mu=0.05, singles=6):
                     speedup_vs_single_loop=per_single * count / dt32))
 
 
+def batch_ipm_section(count, singles=4):
+    """Whole FP64 IPMs of the scenario batch in one persistent kernel (each
+    workgroup runs complete IPMs of the problems it takes, largest first):
+    count problems with N = 4 U{64..512}, n_d = N/4, m = 3N/4, n_s = 50N,
+    4 nonzeros per row of J_s.  Also times a loop of single-problem GPU IPMs
+    on the first `singles` problems."""
+    import numpy as np
+    import torch
+    import paper_2605_13736_amd as mds
+    import synth
+    probs = []
+    for p in range(count):
+        sz = synth.batch_sizes(p)
+        probs.append(synth.make_problem(sz["n_d"], sz["n_s"], sz["m"], sz["r"], cfg=3, p=p))
+    B = mds.BatchIPM(probs, max_iter=200)
+    B.solve(trace=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = B.solve(trace=False)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    iters = np.array([r["iters"] for r in res], dtype=np.float64)
+    facs = np.array([r["factorizations"] for r in res], dtype=np.float64)
+    lat = np.array([r["t_done"] for r in res], dtype=np.float64) / 1e5
+    Ns = [q["n_d"] + q["m"] for q in probs]
+    flops = sum(f * (N ** 3 / 3.0) for f, N in zip(facs, Ns))
+    conv = sum(r["status"] == "converged" for r in res)
+    B.close()
+    del B
+    torch.cuda.empty_cache()
+    t_single = 0.0
+    for p in range(singles):
+        S = mds.solver_for(probs[p])
+        S.ipm_solve()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        S.ipm_solve()
+        torch.cuda.synchronize()
+        t_single += time.perf_counter() - t1
+        del S
+    per_single = t_single / singles
+    return dict(workload=f"{count} problems, N = 4*U{{64..512}} (mean {np.mean(Ns):.0f}), "
+                         "n_d = N/4, m = 3N/4, n_s = 50N, 4 nnz/row of J_s; whole FP64 IPM "
+                         "to E_0 <= 1e-8 per problem",
+                ipm_solves_per_s=count / dt, seconds=dt, converged=int(conv),
+                iters_mean=float(iters.mean()), iters_max=int(iters.max()),
+                factorizations_total=int(facs.sum()),
+                factor_tflops_nominal=flops / dt / 1e12,
+                latency_s_p50=float(np.percentile(lat, 50)) / 1e3,
+                latency_s_p99=float(np.percentile(lat, 99)) / 1e3,
+                single_loop_s_per_problem=per_single,
+                speedup_vs_single_loop=per_single * count / dt,
+                single_loop_sample=f"first {singles} problems of the batch, one GPU IPM each")
+
+
 def warmstart_section(n_train, n_held, hidden=1024, steps=2000, lr=1e-3, noise=0.5,
                       data_budget_s=None):
     """Learned warm start on the OPF-scale family (N = 4096; b = b0 (1 + 0.1
@@ -610,6 +666,9 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--nb", type=int, default=0)
+    ap.add_argument("--sweep-precision", default="",
+                    help="profiling: only time the headline Newton matrix factored and "
+                         "refined in this precision (fp64, fp32, bf16x3, bf16) and print it")
     ap.add_argument("--headline-only", action="store_true",
                     help="run only the headline steps and print them (profiling)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -646,7 +705,16 @@ def main():
                           "calib_copy_bytes_written": x.numel() * 8, "launches": 3}))
         return
     if args.batch_only:
-        print(json.dumps({"batch": batch_section(args.batch_count)}))
+        print(json.dumps({"batch": batch_section(args.batch_count),
+                          "batch_ipm": batch_ipm_section(args.batch_count)}))
+        return
+    if args.sweep_precision:
+        import synth
+        prob = synth.config_problem(synth.LARGE_N16384)
+        st = synth.kkt_state(prob, 2)
+        N = prob["n_d"] + prob["m"]
+        print(json.dumps({"precision_sweep": precision_sweep(prob, st, N, reps=args.steps,
+                                                             precs=(args.sweep_precision,))}))
         return
     if args.opf_only:
         print(json.dumps({"opf_n4096": opf_section(args.steps, args.warmup)[0]}))
@@ -695,6 +763,9 @@ def main():
     if not args.no_batch:
         log("batch section")
         out["batch"] = batch_section(args.batch_count)
+    if not args.no_batch:
+        log("batch whole-IPM section")
+        out["batch_ipm"] = batch_ipm_section(args.batch_count)
     if not args.no_warmstart:
         log("learned warm start section")
         out["warmstart"] = warmstart_section(args.ws_train, args.ws_held,

@@ -496,7 +496,13 @@ typedef struct {
                          x += K^-1 (r - K x) through the FP32 factor          */
   int32_t refine_steps; /* MDS_FP32: refinement steps at most (0: 10); a step
                          whose correction is below 1e-15 max|x| ends it       */
-  int32_t reserved[3];
+  int32_t ipm_max_iter; /* 0: Newton systems only.  > 0 (at most 1000): the
+                         workspace also holds, per slot, the vectors of a whole
+                         IPM and, per problem, a trace of ipm_max_iter + 1
+                         iterations (mds_batch_ipm); the Newton-system arrays
+                         of mds_batch_problem may then be NULL (mds_batch_run
+                         needs them)                                          */
+  int32_t reserved[2];
 } mds_batch_opts;
 
 typedef struct mds_batch mds_batch;
@@ -517,6 +523,47 @@ int mds_batch_create(mds_batch **out, const mds_batch_problem *probs_host, int32
  * drained).  results_host (may be NULL) receives count entries.
  * Synchronizes. */
 int mds_batch_run(mds_batch *b, double mu, mds_batch_result *results_host);
+/* Whole-IPM data of one batched problem (each problem of the scenario batch
+ * an IPM of Sec. 2.1 on its own, equality constraints J x = b): objective
+ * c (n_d), w (n_s, >= 0), g (n_s); b (m); bounds xl, xu (n = n_d + n_s,
+ * +-INFINITY allowed, xl < xu); outputs: the final iterate x (n), y (m),
+ * zl, zu (n).  Device arrays, caller-owned. */
+typedef struct {
+  const double *c, *w, *g, *b, *xl, *xu;
+  double *x, *y, *zl, *zu;
+} mds_batch_ipm_problem;
+
+typedef struct {
+  int32_t status;          /* MDS_IPM_CONVERGED, MDS_IPM_LS_FAIL,
+                              MDS_IPM_MAXITER, MDS_INERTIA_FAIL or
+                              MDS_IPM_NONFINITE                               */
+  int32_t iters;           /* iterations (Newton steps) taken                */
+  double mu, E0;           /* barrier parameter and optimality error at exit */
+  int64_t t_start, t_done; /* 100 MHz ticks since the launch's first workgroup */
+  int32_t slot;            /* workgroup that solved it                       */
+  int32_t factorizations;  /* over all iterations (correction trials)       */
+} mds_batch_ipm_result;
+
+typedef struct {           /* one iteration of one problem */
+  double mu, alpha_pr, delta_w;
+  int32_t inertia[3];      /* of the accepted M                             */
+  int32_t trials, backtracks, pad;
+} mds_batch_ipm_iter;
+
+/* Whole IPMs of every problem of the batch (Sec. 1's scenario motivation; the
+ * filter line-search IPM of Sec. 2.1 with mds_ipm_step's start point,
+ * constants and tests, FP64): one persistent kernel, each workgroup running
+ * complete IPMs of the problems it takes from the queue (largest first),
+ * every reduction inside the workgroup; Newton systems through the batch's
+ * condense / blocked Bunch-Kaufman / inertia correction (delta_w^last kept
+ * per problem) / solve, then FP64 iterative refinement on the full system
+ * (<= opts.refine_steps, stop at backward error 1e-14 or no decrease).
+ * Needs a batch created with ipm_max_iter >= opts.max_iter and precision
+ * MDS_FP64 (else MDS_ESTATE).  ipm_host: count entries.  results_host and
+ * trace_host (count x (ipm_max_iter + 1) rows, problem-major; rows past a
+ * problem's last iteration are unspecified) may be NULL.  Synchronizes. */
+int mds_batch_ipm(mds_batch *b, const mds_batch_ipm_problem *ipm_host, const mds_ipm_opts *opts,
+                  mds_batch_ipm_result *results_host, mds_batch_ipm_iter *trace_host);
 /* Time each candidate (panel width x grid) once and keep the fastest;
  * chosen_host (may be NULL) receives it.  Runs the batch several times. */
 int mds_batch_autotune(mds_batch *b, double mu, mds_batch_opts *chosen_host);

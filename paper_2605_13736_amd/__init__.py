@@ -123,7 +123,24 @@ class BatchResult(C.Structure):
 class BatchOpts(C.Structure):
     _fields_ = [("nb", C.c_int32), ("grid", C.c_int32), ("use_graph", C.c_int32),
                 ("precision", C.c_int32), ("refine_steps", C.c_int32),
-                ("reserved", C.c_int32 * 3)]
+                ("ipm_max_iter", C.c_int32), ("reserved", C.c_int32 * 2)]
+
+
+class BatchIpmProblem(C.Structure):
+    _fields_ = [("c", _vp), ("w", _vp), ("g", _vp), ("b", _vp), ("xl", _vp), ("xu", _vp),
+                ("x", _vp), ("y", _vp), ("zl", _vp), ("zu", _vp)]
+
+
+class BatchIpmResult(C.Structure):
+    _fields_ = [("status", C.c_int32), ("iters", C.c_int32), ("mu", C.c_double),
+                ("E0", C.c_double), ("t_start", C.c_int64), ("t_done", C.c_int64),
+                ("slot", C.c_int32), ("factorizations", C.c_int32)]
+
+
+class BatchIpmIter(C.Structure):
+    _fields_ = [("mu", C.c_double), ("alpha_pr", C.c_double), ("delta_w", C.c_double),
+                ("inertia", C.c_int32 * 3), ("trials", C.c_int32), ("backtracks", C.c_int32),
+                ("pad", C.c_int32)]
 
 
 class Timings(C.Structure):
@@ -171,6 +188,8 @@ SIGNATURES = {
                                    C.POINTER(BatchOpts), _vp, _vp, C.c_size_t]),
     "mds_batch_run": (C.c_int, [_vp, C.c_double, C.POINTER(BatchResult)]),
     "mds_batch_autotune": (C.c_int, [_vp, C.c_double, C.POINTER(BatchOpts)]),
+    "mds_batch_ipm": (C.c_int, [_vp, C.POINTER(BatchIpmProblem), C.POINTER(IpmOpts),
+                                C.POINTER(BatchIpmResult), C.POINTER(BatchIpmIter)]),
     "mds_batch_get_config": (C.c_int, [_vp, C.POINTER(BatchOpts)]),
     "mds_batch_destroy": (None, [_vp]),
     "mds_batch_last_error": (C.c_char_p, [_vp]),
@@ -671,6 +690,108 @@ class Batch:
 
     def solution(self, p):
         return [t.detach().cpu().numpy() for t in self.out[p]]
+
+
+class BatchIPM:
+    """Whole FP64 IPMs of many independent problems in one persistent kernel
+    (mds_batch_ipm).  problems: synthetic problem dicts (equality rows only)."""
+
+    def __init__(self, problems, nb=0, grid=0, max_iter=200, device="cuda:0"):
+        torch = _torch()
+        if not torch.cuda.is_available():
+            raise MdsError("no ROCm GPU visible: the mdsipm library has no CPU path")
+        self.torch, self.device = torch, torch.device(device)
+        self.count = len(problems)
+        self.max_iter = int(max_iter)
+        self._keep = []
+        self.out = []
+        descs = (BatchProblem * self.count)()
+        ipm = (BatchIpmProblem * self.count)()
+
+        def dev(a, dt=None):
+            arr = np.asarray(a)
+            if dt is None:
+                dt = torch.int32 if arr.dtype.kind in "iu" else torch.float64
+            t = torch.as_tensor(np.ascontiguousarray(arr)).to(device=self.device, dtype=dt)
+            self._keep.append(t)
+            return t
+
+        for p, q in enumerate(problems):
+            if int(q.get("m_I", 0)) or q.get("bp") is not None:
+                raise MdsError("the batched IPM takes equality rows and a diagonal sparse Hessian")
+            nd, ns, m = int(q["n_d"]), int(q["n_s"]), int(q["m"])
+            H = dev(np.asarray(q["H"], dtype=np.float64).reshape(-1, order="F"))
+            Jd = dev(np.asarray(q["Jd"], dtype=np.float64).reshape(-1, order="F"))
+            rp = dev(np.asarray(q["rp"], dtype=np.int32), torch.int32)
+            ci = dev(np.asarray(q["ci"], dtype=np.int32), torch.int32)
+            v = dev(np.asarray(q["v"], dtype=np.float64))
+            descs[p] = BatchProblem(nd, ns, m, 0, int(len(q["v"])), _ptr(H), _ptr(Jd), _ptr(rp),
+                                    _ptr(ci), _ptr(v), *([C.c_void_p(0)] * 8))
+            data = [dev(np.asarray(q[k], dtype=np.float64)) for k in ("c", "w", "g", "b", "xl", "xu")]
+            o = [torch.empty(max(k, 1), dtype=torch.float64, device=self.device)
+                 for k in (nd + ns, m, nd + ns, nd + ns)]
+            self.out.append((o, nd + ns, m))
+            ipm[p] = BatchIpmProblem(*[_ptr(t) for t in data], *[_ptr(t) for t in o])
+        self.descs, self.ipm = descs, ipm
+        self.opts = BatchOpts(int(nb), int(grid), 0, 0, 0, self.max_iter)
+        L = lib()
+        nbytes = L.mds_batch_workspace_bytes(descs, self.count, C.byref(self.opts))
+        if nbytes == 0:
+            raise MdsError("invalid batch sizes (each problem needs 1 <= n_d + m <= 2048)")
+        with torch.cuda.device(self.device):
+            self.stream = torch.cuda.current_stream(self.device)
+            self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+            aligned = (self.ws.data_ptr() + 255) & ~255
+            h = C.c_void_p()
+            st = L.mds_batch_create(C.byref(h), descs, self.count, C.byref(self.opts),
+                                    C.c_void_p(self.stream.cuda_stream), C.c_void_p(aligned),
+                                    nbytes)
+        if st != 0:
+            raise MdsError(f"mds_batch_create: {L.mds_status_string(st).decode()}")
+        self.h = h
+        self.workspace_bytes = nbytes
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().mds_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def solve(self, tol=1e-8, mu0=0.1, max_iter=None, refine_steps=2, dw_max=1e20, trace=True):
+        mi = self.max_iter if max_iter is None else int(max_iter)
+        opts = IpmOpts(tol, mu0, mi, refine_steps, dw_max, 0, 0)
+        res = (BatchIpmResult * self.count)()
+        rows = self.max_iter + 1
+        tr = (BatchIpmIter * (self.count * rows))() if trace else None
+        st = lib().mds_batch_ipm(self.h, self.ipm, C.byref(opts), res, tr)
+        if st != 0:
+            raise MdsError(f"mds_batch_ipm: {lib().mds_status_string(st).decode()} "
+                           f"({lib().mds_batch_last_error(self.h).decode()})")
+        out = []
+        for p in range(self.count):
+            r = res[p]
+            d = dict(status=STATUS_NAMES.get(r.status, r.status), code=r.status, iters=r.iters,
+                     mu=r.mu, E0=r.E0, t_start=r.t_start, t_done=r.t_done, slot=r.slot,
+                     factorizations=r.factorizations)
+            if trace:
+                d["trace"] = [dict(mu=tr[p * rows + k].mu, alpha_pr=tr[p * rows + k].alpha_pr,
+                                   delta_w=tr[p * rows + k].delta_w,
+                                   inertia=tuple(tr[p * rows + k].inertia),
+                                   trials=tr[p * rows + k].trials,
+                                   backtracks=tr[p * rows + k].backtracks)
+                              for k in range(min(r.iters, rows))]
+            out.append(d)
+        return out
+
+    def solution(self, p):
+        (x, y, zl, zu), n, m = self.out[p]
+        return (x[:n].cpu().numpy(), y[:m].cpu().numpy(), zl[:n].cpu().numpy(),
+                zu[:n].cpu().numpy())
 
 
 class MLP:

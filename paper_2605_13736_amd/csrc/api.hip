@@ -307,8 +307,8 @@ void launch_reg_panel(mds_handle *h, hipStream_t s, int b, const TX *X, double *
   const int N = h->N;
   const long left = (long)N - (long)b * h->adv;
   if (h->panel_coop && !is_tail_slot(h, b))
-    launch_bk_panel_coop(s, N, h->nb, h->alpha_bk, X, Y, h->w.src, h->w.W, h->w.dd, h->w.ds,
-                         h->w.ipiv, h->w.blk, h->w.fst, h->w.panel_k0, h->w.xch);
+    launch_bk_panel_coop(s, (int)left, N, h->nb, h->alpha_bk, X, Y, h->w.src, h->w.W, h->w.dd,
+                         h->w.ds, h->w.ipiv, h->w.blk, h->w.fst, h->w.panel_k0, h->w.xch);
   else if (h->panel_coop)
     launch_bk_panel_reg_tail(s, (int)left, N, h->nb, h->alpha_bk, X, Y, h->w.src, h->w.W,
                              h->w.dd, h->w.ds, h->w.ipiv, h->w.blk, h->w.fst, h->w.panel_k0);

@@ -16,6 +16,7 @@
 // is then refined in FP64 on the full (uncondensed) Newton system,
 // x += K^-1 (r - K x) through the low-precision factor.
 #include <algorithm>
+#include <cfloat>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -56,6 +57,33 @@ struct SlotDev {
   double *eq;     // mixed precision: equilibration S (N)
   double *res;    // residual of the full system (n_d + n_s + m)
   const double *zero;  // 64 zeros (written at creation, never after)
+  // whole-IPM vectors (null without IPM memory): n = n_d + n_s entries
+  // (sig, rx, dx, dzl, dzu, xt, gf, jty), m (ry, dy, cx), n_s (dsb), n_d
+  // (hx), n + m (prev); filter pairs (theta, phi)
+  double *sig, *rx, *ry, *dsb, *dx, *dy, *dzl, *dzu, *xt, *gf, *jty, *cx, *hx, *prev, *filt;
+};
+
+// whole-IPM data of one problem (caller's device arrays)
+struct IpmDev {
+  const double *c, *w, *g, *b, *xl, *xu;
+  double *x, *y, *zl, *zu;
+};
+
+struct IpmResDev {
+  int32_t status, iters;
+  double mu, E0;
+  int64_t t_start, t_done;
+  int32_t slot, facs;
+};
+
+struct IpmIterDev {
+  double mu, alpha_pr, delta_w;
+  int32_t inertia[3], trials, backtracks, pad;
+};
+
+struct IpmParams {
+  double tol, mu0, dw_max;
+  int32_t max_iter, refine_steps, trace_rows, pad;
 };
 
 struct ResultDev {
@@ -763,6 +791,553 @@ __global__ __launch_bounds__(BT) void k_batch(int count, const int32_t *__restri
 }
 
 
+// ============================ whole IPM per problem ==============================
+// The filter line-search IPM of Sec. 2.1 (mds_ipm_step's iteration, with the
+// same constants, start point and tests) run by one workgroup per problem of
+// the scenario batch: every reduction is workgroup-local, so problems never
+// wait for one another and the queue keeps the device busy.  The Newton
+// systems go through the batch's own condense / factor / correction / solve
+// above, with FP64 iterative refinement on the full system as in
+// or_newton_refine (stop at backward error 1e-14, no decrease, or the step
+// limit).
+
+// deterministic workgroup sum (wave sums, then the waves in order)
+__device__ inline double block_sum(double v, double *s_part) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  v = wave::sum(v);
+  __syncthreads();
+  if (lane == 0) s_part[wv] = v;
+  __syncthreads();
+  double t = 0.0;
+  for (int q = 0; q < NWAVE; ++q) t = t + s_part[q];
+  __syncthreads();
+  return t;
+}
+
+// workgroup maximum starting from lo (fmax: NaN operands are ignored)
+__device__ inline double block_max_from(double v, double lo, double *s_part) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  v = wave::max(v);
+  __syncthreads();
+  if (lane == 0) s_part[wv] = v;
+  __syncthreads();
+  double t = lo;
+  for (int q = 0; q < NWAVE; ++q) t = fmax(t, s_part[q]);
+  __syncthreads();
+  return t;
+}
+
+// workgroup OR of a flag
+__device__ inline bool block_any(bool f, int *s_flag) {
+  __syncthreads();
+  if (threadIdx.x == 0) *s_flag = 0;
+  __syncthreads();
+  if (f) *s_flag = 1;
+  __syncthreads();
+  const bool r = *s_flag != 0;
+  __syncthreads();
+  return r;
+}
+
+// gf = grad f(x) = [H x_d + c; w .* x_s + g] (hx = H x_d), jty = J' y (when
+// y is given), cx = J x - b; each entry summed in ascending index
+__device__ __attribute__((noinline)) void ipm_eval_wg(const ProbDev &P, const IpmDev &Q, const SlotDev &S, const double *x,
+                            const double *y, double *gf, double *jty, double *cx) {
+  const int tid = threadIdx.x, nd = P.nd, ns = P.ns, m = P.m;
+  for (int i = tid; i < nd; i += BT) {
+    double t = 0.0;
+    for (int j = 0; j < nd; ++j) t = t + P.H[(size_t)i + (size_t)j * nd] * x[j];
+    S.hx[i] = t;
+    gf[i] = t + Q.c[i];
+  }
+  for (int k = tid; k < ns; k += BT) gf[nd + k] = Q.w[k] * x[nd + k] + Q.g[k];
+  if (y) {
+    for (int j = tid; j < nd; j += BT) {
+      double t = 0.0;
+      for (int r = 0; r < m; ++r) t = t + P.Jd[(size_t)r + (size_t)j * m] * y[r];
+      jty[j] = t;
+    }
+    for (int k = tid; k < ns; k += BT) {
+      double t = 0.0;
+      for (int e = P.cptr[k]; e < P.cptr[k + 1]; ++e) t = t + P.cval[e] * y[P.crow[e]];
+      jty[nd + k] = t;
+    }
+  }
+  for (int r = tid; r < m; r += BT) {
+    double t = 0.0;
+    for (int j = 0; j < nd; ++j) t = t + P.Jd[(size_t)r + (size_t)j * m] * x[j];
+    for (int a = P.rp[r]; a < P.rp[r + 1]; ++a) t = t + P.v[a] * x[nd + P.ci[a]];
+    cx[r] = t - Q.b[r];
+  }
+  __syncthreads();
+}
+
+// scaled optimality error parts at (x, y, zl, zu) from gf, jty, cx:
+// out[0] dual inf, [1] primal inf, [2] sum |y| + |z| (s_d numerator),
+// [3] number of finite bounds, [4] sum |z|; the complementarity maxima
+// depend on mu and come from ipm_compl_wg
+__device__ __attribute__((noinline)) void ipm_parts_wg(const ProbDev &P, const IpmDev &Q, const SlotDev &S,
+                             const double *x, const double *y, const double *zl,
+                             const double *zu, double *s_part, double *out) {
+  const int tid = threadIdx.x, n = P.nd + P.ns, m = P.m;
+  double dual = 0.0, z1 = 0.0, nz = 0.0, y1 = 0.0, prim = 0.0;
+  bool bad = false;
+  for (int i = tid; i < n; i += BT) {
+    double r = S.gf[i] + S.jty[i];
+    if (isfinite(Q.xl[i])) {
+      r = r - zl[i];
+      z1 += fabs(zl[i]);
+      nz += 1.0;
+    }
+    if (isfinite(Q.xu[i])) {
+      r = r + zu[i];
+      z1 += fabs(zu[i]);
+      nz += 1.0;
+    }
+    bad = bad || !isfinite(r);
+    dual = fmax(dual, fabs(r));
+  }
+  for (int r = tid; r < m; r += BT) {
+    bad = bad || !isfinite(S.cx[r]) || !isfinite(y[r]);
+    prim = fmax(prim, fabs(S.cx[r]));
+    y1 += fabs(y[r]);
+  }
+  out[0] = block_max_from(dual, 0.0, s_part);
+  out[1] = block_max_from(prim, 0.0, s_part);
+  const double zs = block_sum(z1, s_part);
+  out[2] = block_sum(y1, s_part) + zs;
+  out[3] = block_sum(nz, s_part);
+  out[4] = zs;
+  int *flag = reinterpret_cast<int *>(s_part + NWAVE);
+  if (block_any(bad, flag)) out[0] = NAN;
+}
+
+// max |(x - l) zl - mu| and max |(u - x) zu - mu| over the finite bounds
+__device__ __attribute__((noinline)) double ipm_compl_wg(const ProbDev &P, const IpmDev &Q, const double *x,
+                               const double *zl, const double *zu, double mu, double *s_part) {
+  const int tid = threadIdx.x, n = P.nd + P.ns;
+  double c = 0.0;
+  for (int i = tid; i < n; i += BT) {
+    if (isfinite(Q.xl[i])) c = fmax(c, fabs((x[i] - Q.xl[i]) * zl[i] - mu));
+    if (isfinite(Q.xu[i])) c = fmax(c, fabs((Q.xu[i] - x[i]) * zu[i] - mu));
+  }
+  return block_max_from(c, 0.0, s_part);
+}
+
+__device__ inline double ipm_error(const double *pt, double compl_, int m) {
+  const double s_max = 100.0;
+  if (!isfinite(pt[0])) return pt[0];  // a non-finite residual entry
+  const double nz = pt[3];
+  const double sd = ((double)m + nz > 0.0) ? fmax(s_max, pt[2] / ((double)m + nz)) / s_max : 1.0;
+  const double sc = (nz > 0.0) ? fmax(s_max, pt[4] / nz) / s_max : 1.0;
+  return fmax(fmax(pt[0] / sd, pt[1]), compl_ / sc);
+}
+
+// f, sum of log-slacks, theta = ||J x - b||_1 and phi's rounding scale at
+// x: out[0..3]; S.hx must hold H x_d and S.cx = J x - b
+__device__ __attribute__((noinline)) void ipm_merit_wg(const ProbDev &P, const IpmDev &Q, const SlotDev &S, const double *x,
+                             double mu, double *s_part, double *out) {
+  const int tid = threadIdx.x, nd = P.nd, n = P.nd + P.ns, m = P.m;
+  double f = 0.0, lg = 0.0, th = 0.0, sc = 0.0;
+  bool bad = false;
+  for (int i = tid; i < n; i += BT) {
+    double t;
+    if (i < nd) {
+      t = x[i] * (0.5 * S.hx[i] + Q.c[i]);
+    } else {
+      const double xs = x[i];
+      t = xs * (0.5 * Q.w[i - nd] * xs + Q.g[i - nd]);
+    }
+    f += t;
+    sc += fabs(t);
+    if (isfinite(Q.xl[i])) {
+      const double l = log(x[i] - Q.xl[i]);
+      lg += l;
+      sc += mu * fabs(l);
+    }
+    if (isfinite(Q.xu[i])) {
+      const double l = log(Q.xu[i] - x[i]);
+      lg += l;
+      sc += mu * fabs(l);
+    }
+  }
+  for (int r = tid; r < m; r += BT) th += fabs(S.cx[r]);
+  bad = !isfinite(f) || !isfinite(lg) || !isfinite(th);
+  out[0] = block_sum(f, s_part);
+  out[1] = block_sum(lg, s_part);
+  out[2] = block_sum(th, s_part);
+  out[3] = block_sum(sc, s_part);
+  int *flag = reinterpret_cast<int *>(s_part + NWAVE);
+  if (block_any(bad, flag)) out[0] = NAN;
+}
+
+// J x - b and H x_d at x only (the trial points of the line search)
+__device__ __attribute__((noinline)) void ipm_constr_wg(const ProbDev &P, const IpmDev &Q, const SlotDev &S, const double *x) {
+  const int tid = threadIdx.x, nd = P.nd, m = P.m;
+  for (int i = tid; i < nd; i += BT) {
+    double t = 0.0;
+    for (int j = 0; j < nd; ++j) t = t + P.H[(size_t)i + (size_t)j * nd] * x[j];
+    S.hx[i] = t;
+  }
+  for (int r = tid; r < m; r += BT) {
+    double t = 0.0;
+    for (int j = 0; j < nd; ++j) t = t + P.Jd[(size_t)r + (size_t)j * m] * x[j];
+    for (int a = P.rp[r]; a < P.rp[r + 1]; ++a) t = t + P.v[a] * x[nd + P.ci[a]];
+    S.cx[r] = t - Q.b[r];
+  }
+  __syncthreads();
+}
+
+// ||K||_inf of the regularised Newton matrix (row sums of |K|)
+__device__ __attribute__((noinline)) double ipm_knorm_wg(const ProbDev &P, double dw, double dc, double *s_part) {
+  const int tid = threadIdx.x, nd = P.nd, ns = P.ns, m = P.m;
+  double best = 0.0;
+  for (int i = tid; i < nd; i += BT) {
+    double t = 0.0;
+    for (int j = 0; j < nd; ++j) {
+      double h = P.H[(size_t)i + (size_t)j * nd];
+      if (i == j) h = h + P.sigma_d[i] + dw;
+      t += fabs(h);
+    }
+    for (int r = 0; r < m; ++r) t += fabs(P.Jd[(size_t)r + (size_t)i * m]);
+    best = fmax(best, t);
+  }
+  for (int k = tid; k < ns; k += BT) {
+    double t = fabs(P.dsbase[k] + dw);
+    for (int e = P.cptr[k]; e < P.cptr[k + 1]; ++e) t += fabs(P.cval[e]);
+    best = fmax(best, t);
+  }
+  for (int r = tid; r < m; r += BT) {
+    double t = fabs(dc);
+    for (int j = 0; j < nd; ++j) t += fabs(P.Jd[(size_t)r + (size_t)j * m]);
+    for (int a = P.rp[r]; a < P.rp[r + 1]; ++a) t += fabs(P.v[a]);
+    best = fmax(best, t);
+  }
+  return block_max_from(best, 0.0, s_part);
+}
+
+// max |v| over the Newton solution or right-hand side stored as three pieces
+__device__ __attribute__((noinline)) double amax3_wg(const double *a, int na, const double *b, int nb_, const double *c,
+                           int nc, double *s_part) {
+  const int tid = threadIdx.x;
+  double t = 0.0;
+  for (int i = tid; i < na; i += BT) t = fmax(t, fabs(a[i]));
+  for (int i = tid; i < nb_; i += BT) t = fmax(t, fabs(b[i]));
+  for (int i = tid; i < nc; i += BT) t = fmax(t, fabs(c[i]));
+  return block_max_from(t, 0.0, s_part);
+}
+
+// FP64 refinement of the Newton solve (P.dx_*, P.dy) on the full system with
+// right-hand side (P.r_d, P.r_s, P.r_y), as or_newton_refine
+__device__ __attribute__((noinline)) void ipm_refine_wg(const ProbDev &P, const SlotDev &S, double dw, double dc,
+                              int max_steps, double *s_z, double *s_part, double *s_db,
+                              int *s_pq) {
+  const int tid = threadIdx.x, nd = P.nd, ns = P.ns, m = P.m;
+  const int nt = nd + ns + m;
+  double cmax, xmax;
+  kkt_solve_wg(P, S, false, P.r_d, P.r_s, P.r_y, false, s_z, s_part, s_db, s_pq, &cmax, &xmax);
+  const double nK = ipm_knorm_wg(P, dw, dc, s_part);
+  const double nr = amax3_wg(P.r_d, nd, P.r_s, ns, P.r_y, m, s_part);
+  double eta_prev = INFINITY;
+  int steps = 0;
+  for (;;) {
+    residual_wg(P, S, dw, dc, s_part);  // S.res = r - K x
+    const double nres = amax3_wg(S.res, nt, nullptr, 0, nullptr, 0, s_part);
+    const double nx = amax3_wg(P.dx_d, nd, P.dx_s, ns, P.dy, m, s_part);
+    const double den = nK * nx + nr;
+    const double eta = (den > 0.0) ? nres / den : 0.0;
+    if (steps > 0 && !(eta < eta_prev)) {
+      // no decrease: keep the previous iterate
+      for (int i = tid; i < nd; i += BT) P.dx_d[i] = S.prev[i];
+      for (int i = tid; i < ns; i += BT) P.dx_s[i] = S.prev[nd + i];
+      for (int i = tid; i < m; i += BT) P.dy[i] = S.prev[nd + ns + i];
+      __syncthreads();
+      break;
+    }
+    if (eta <= 1e-14 || steps >= max_steps) break;
+    for (int i = tid; i < nd; i += BT) S.prev[i] = P.dx_d[i];
+    for (int i = tid; i < ns; i += BT) S.prev[nd + i] = P.dx_s[i];
+    for (int i = tid; i < m; i += BT) S.prev[nd + ns + i] = P.dy[i];
+    __syncthreads();
+    eta_prev = eta;
+    kkt_solve_wg(P, S, false, S.res, S.res + nd, S.res + nd + ns, true, s_z, s_part, s_db, s_pq,
+                 &cmax, &xmax);
+    ++steps;
+  }
+}
+
+// Condense + factor with the shifts, and whether In(M) = (n_d, 0, m)
+__device__ inline bool ipm_factor_wg(const ProbDev &P, const SlotDev &S, int nb, double alpha,
+                                     double dw, double dc, double (*s_t)[TW + 1]) {
+  condense_wg(P, S.inv_d, dw, dc, S.buf[0]);
+  factor_wg(P.nd + P.m, nb, alpha, S, s_t);
+  return S.st->npos == P.nd && S.st->nzero == 0 && S.st->nneg == P.m;
+}
+
+__global__ __launch_bounds__(BT) void k_batch_ipm(int count, const int32_t *__restrict__ order,
+                                                  const ProbDev *__restrict__ probs,
+                                                  const IpmDev *__restrict__ ipms,
+                                                  const SlotDev *__restrict__ slots, int nb,
+                                                  double alpha, IpmParams prm, int32_t *queue,
+                                                  unsigned long long *t0, IpmResDev *results,
+                                                  IpmIterDev *trace) {
+  __shared__ double s_t[NWAVE * TW][TW + 1];
+  __shared__ double s_z[BMAX_N];
+  __shared__ double s_part[NWAVE * (BNB + 1)];
+  double *s_db = &s_t[0][0];
+  int *s_pq = (int *)(s_db + BDB * BDB);
+  __shared__ int s_p;
+  const int tid = threadIdx.x;
+  const SlotDev S = slots[blockIdx.x];
+  if (tid == 0) atomicMin(t0, (unsigned long long)wall_clock64());
+  // Waechter & Biegler (2006) constants, as the single-problem step
+  const double tau_min = 0.99, kappa_eps = 10.0, kappa_mu = 0.2, theta_mu = 1.5;
+  const double kappa_sigma = 1e10, gamma_theta = 1e-5, gamma_phi = 1e-8, delta = 1.0;
+  const double s_theta = 1.1, s_phi = 2.3, eta_phi = 1e-8, gamma_alpha = 0.05;
+  const double dw_min = 1e-20, dw0 = 1e-4, kw_minus = 1.0 / 3.0, kw_plus = 8.0;
+  const double kw_plus_bar = 100.0, dc_bar = 1e-8, kappa_c = 0.25;
+  for (;;) {
+    if (tid == 0) s_p = atomicAdd(queue, 1);
+    __syncthreads();
+    const int p = s_p;
+    __syncthreads();
+    if (p >= count) break;
+    const int pid = order[p];
+    const IpmDev Q = ipms[pid];
+    ProbDev P = probs[pid];
+    const int nd = P.nd, ns = P.ns, m = P.m, n = nd + ns;
+    P.sigma_d = S.sig;
+    P.dsbase = S.dsb;
+    P.r_d = S.rx;
+    P.r_s = S.rx + nd;
+    P.r_y = S.ry;
+    P.dx_d = S.dx;
+    P.dx_s = S.dx + nd;
+    P.dy = S.dy;
+    const unsigned long long ts = wall_clock64();
+    double *x = Q.x, *y = Q.y, *zl = Q.zl, *zu = Q.zu;
+    // start point: x = 0 pushed inside its bounds (kappa_1 = kappa_2 = 1e-2),
+    // y = 0, z = 1 on finite bounds
+    for (int i = tid; i < n; i += BT) {
+      const double l = Q.xl[i], u = Q.xu[i];
+      const bool hl = isfinite(l), hu = isfinite(u);
+      double xi = 0.0;
+      if (hl && hu) {
+        const double pl = fmin(1e-2 * fmax(1.0, fabs(l)), 1e-2 * (u - l));
+        const double pu = fmin(1e-2 * fmax(1.0, fabs(u)), 1e-2 * (u - l));
+        xi = fmin(fmax(xi, l + pl), u - pu);
+      } else if (hl) {
+        xi = fmax(xi, l + 1e-2 * fmax(1.0, fabs(l)));
+      } else if (hu) {
+        xi = fmin(xi, u - 1e-2 * fmax(1.0, fabs(u)));
+      }
+      x[i] = xi;
+      zl[i] = hl ? 1.0 : 0.0;
+      zu[i] = hu ? 1.0 : 0.0;
+    }
+    for (int r = tid; r < m; r += BT) y[r] = 0.0;
+    __syncthreads();
+    double mu = prm.mu0, tau = fmax(tau_min, 1.0 - mu), dw_last = 0.0;
+    double mv[4], pt[5];
+    ipm_constr_wg(P, Q, S, x);
+    ipm_merit_wg(P, Q, S, x, mu, s_part, mv);
+    const double theta_max = 1e4 * fmax(1.0, mv[2]), theta_min = 1e-4 * fmax(1.0, mv[2]);
+    int nf = 0, status = MDS_IPM_MAXITER, it = 0, facs = 0;
+    double E0 = 0.0;
+    for (it = 0; it < prm.max_iter; ++it) {
+      ipm_eval_wg(P, Q, S, x, y, S.gf, S.jty, S.cx);
+      ipm_parts_wg(P, Q, S, x, y, zl, zu, s_part, pt);
+      E0 = ipm_error(pt, ipm_compl_wg(P, Q, x, zl, zu, 0.0, s_part), m);
+      if (!isfinite(E0)) {
+        status = MDS_IPM_NONFINITE;
+        break;
+      }
+      if (E0 <= prm.tol) {
+        status = MDS_IPM_CONVERGED;
+        break;
+      }
+      // barrier update while the barrier problem is solved to kappa_eps mu
+      while (ipm_error(pt, ipm_compl_wg(P, Q, x, zl, zu, mu, s_part), m) <= kappa_eps * mu) {
+        const double mnew = fmax(prm.tol / 10.0, fmin(kappa_mu * mu, pow(mu, theta_mu)));
+        if (!(mnew < mu)) break;
+        mu = mnew;
+        tau = fmax(tau_min, 1.0 - mu);
+        nf = 0;
+      }
+      // barrier diagonal and Newton right-hand side; D_s base w + Sigma_s
+      for (int i = tid; i < n; i += BT) {
+        double sg = 0.0, gb = S.gf[i] + S.jty[i];
+        if (isfinite(Q.xl[i])) {
+          const double sl = x[i] - Q.xl[i];
+          sg = sg + zl[i] / sl;
+          gb = gb - mu / sl;
+        }
+        if (isfinite(Q.xu[i])) {
+          const double su = Q.xu[i] - x[i];
+          sg = sg + zu[i] / su;
+          gb = gb + mu / su;
+        }
+        S.sig[i] = sg;
+        S.rx[i] = -gb;
+        if (i >= nd) S.dsb[i - nd] = Q.w[i - nd] + sg;
+      }
+      for (int r = tid; r < m; r += BT) S.ry[r] = -S.cx[r];
+      __syncthreads();
+      // inertia correction (Algorithm IC)
+      int trials = 1;
+      double dw = 0.0, dc = 0.0;
+      bool ok = ipm_factor_wg(P, S, nb, alpha, 0.0, 0.0, s_t);
+      if (!ok) {
+        dc = (S.st->nzero > 0) ? dc_bar * pow(mu, kappa_c) : 0.0;
+        dw = (dw_last == 0.0) ? dw0 : fmax(dw_min, kw_minus * dw_last);
+        for (;;) {
+          trials++;
+          ok = ipm_factor_wg(P, S, nb, alpha, dw, dc, s_t);
+          if (ok) {
+            dw_last = dw;
+            break;
+          }
+          dw = (dw_last == 0.0) ? kw_plus_bar * dw : kw_plus * dw;
+          if (dw > prm.dw_max) break;
+        }
+      }
+      facs += trials;
+      const int inn0 = S.st->npos, inn1 = S.st->nzero, inn2 = S.st->nneg;
+      if (!ok) {
+        status = MDS_INERTIA_FAIL;
+        break;
+      }
+      ipm_refine_wg(P, S, dw, dc, prm.refine_steps, s_z, s_part, s_db, s_pq);
+      // bound-multiplier steps and the fraction to the boundary
+      double apr = -1.0, adu = -1.0;  // largest -(step limit)
+      for (int i = tid; i < n; i += BT) {
+        double a = 0.0, b = 0.0;
+        const double d = S.dx[i];
+        if (isfinite(Q.xl[i])) {
+          const double sl = x[i] - Q.xl[i];
+          a = mu / sl - zl[i] - (zl[i] / sl) * d;
+          if (d < 0.0) apr = fmax(apr, -(-tau * sl / d));
+          if (a < 0.0) adu = fmax(adu, -(-tau * zl[i] / a));
+        }
+        if (isfinite(Q.xu[i])) {
+          const double su = Q.xu[i] - x[i];
+          b = mu / su - zu[i] + (zu[i] / su) * d;
+          if (-d < 0.0) apr = fmax(apr, -(-tau * su / (-d)));
+          if (b < 0.0) adu = fmax(adu, -(-tau * zu[i] / b));
+        }
+        S.dzl[i] = a;
+        S.dzu[i] = b;
+      }
+      const double a_pr = -block_max_from(apr, -1.0, s_part);
+      const double a_du = -block_max_from(adu, -1.0, s_part);
+      // merit at x and grad(phi)' dx
+      ipm_constr_wg(P, Q, S, x);
+      ipm_merit_wg(P, Q, S, x, mu, s_part, mv);
+      const double th = mv[2], ph = mv[0] - mu * mv[1];
+      const double ph_tol = 10.0 * DBL_EPSILON * mv[3];
+      double gp = 0.0;
+      for (int i = tid; i < n; i += BT) {
+        double gi = S.gf[i];
+        if (isfinite(Q.xl[i])) gi = gi - mu / (x[i] - Q.xl[i]);
+        if (isfinite(Q.xu[i])) gi = gi + mu / (Q.xu[i] - x[i]);
+        gp += gi * S.dx[i];
+      }
+      const double gphi = block_sum(gp, s_part);
+      double amin;
+      if (gphi < 0.0) {
+        amin = fmin(gamma_theta, gamma_phi * th / (-gphi));
+        if (th <= theta_min) amin = fmin(amin, delta * pow(th, s_theta) / pow(-gphi, s_phi));
+        amin = gamma_alpha * amin;
+      } else {
+        amin = gamma_alpha * gamma_theta;
+      }
+      double alpha_s = a_pr;
+      bool accepted = false, augment = true;
+      int nbt = 0;
+      for (;;) {
+        for (int i = tid; i < n; i += BT) S.xt[i] = x[i] + alpha_s * S.dx[i];
+        __syncthreads();
+        ipm_constr_wg(P, Q, S, S.xt);
+        ipm_merit_wg(P, Q, S, S.xt, mu, s_part, mv);
+        const double tht = mv[2], pht = mv[0] - mu * mv[1];
+        const bool okv = isfinite(tht) && isfinite(pht);
+        bool infilt = !okv || tht >= theta_max;
+        for (int f = 0; f < nf && !infilt; ++f)
+          if (tht >= S.filt[2 * f] && pht >= S.filt[2 * f + 1]) infilt = true;
+        if (!infilt) {
+          const bool sw = gphi < 0.0 && alpha_s * pow(-gphi, s_phi) > delta * pow(th, s_theta);
+          const bool armijo = (pht - ph) - eta_phi * alpha_s * gphi <= ph_tol;
+          if (th <= theta_min && sw) {
+            if (armijo) accepted = true;
+          } else if (tht <= (1.0 - gamma_theta) * th || (pht - ph) - (-gamma_phi * th) <= ph_tol) {
+            accepted = true;
+          }
+          if (accepted) augment = !(sw && armijo);
+        }
+        if (accepted) break;
+        alpha_s = 0.5 * alpha_s;
+        nbt++;
+        // alpha_min can be 0 (theta = 0 and a descent direction); past 2^-200
+        // the step is nil, and the workgroup must not spin on it
+        if (alpha_s < amin || nbt >= 200) break;
+      }
+      if (tid == 0 && it < prm.trace_rows) {
+        IpmIterDev r;
+        r.mu = mu;
+        r.alpha_pr = alpha_s;
+        r.delta_w = dw;
+        r.inertia[0] = inn0;
+        r.inertia[1] = inn1;
+        r.inertia[2] = inn2;
+        r.trials = trials;
+        r.backtracks = nbt;
+        r.pad = 0;
+        trace[(size_t)pid * prm.trace_rows + it] = r;
+      }
+      if (!accepted) {
+        status = MDS_IPM_LS_FAIL;
+        break;
+      }
+      if (augment) {
+        if (tid == 0) {
+          S.filt[2 * nf] = (1.0 - gamma_theta) * th;
+          S.filt[2 * nf + 1] = ph - gamma_phi * th;
+        }
+        nf++;
+      }
+      // accept: x, y, and the bound multipliers with the kappa_Sigma safeguard
+      for (int i = tid; i < n; i += BT) {
+        const double xi = S.xt[i];
+        x[i] = xi;
+        if (isfinite(Q.xl[i])) {
+          const double z = zl[i] + a_du * S.dzl[i], sl = xi - Q.xl[i];
+          zl[i] = fmax(fmin(z, kappa_sigma * mu / sl), mu / (kappa_sigma * sl));
+        }
+        if (isfinite(Q.xu[i])) {
+          const double z = zu[i] + a_du * S.dzu[i], su = Q.xu[i] - xi;
+          zu[i] = fmax(fmin(z, kappa_sigma * mu / su), mu / (kappa_sigma * su));
+        }
+      }
+      for (int r = tid; r < m; r += BT) y[r] = y[r] + alpha_s * S.dy[r];
+      __syncthreads();
+    }
+    if (tid == 0) {
+      IpmResDev r;
+      r.status = status;
+      r.iters = it;
+      r.mu = mu;
+      r.E0 = E0;
+      r.t_start = (int64_t)ts;
+      r.t_done = (int64_t)wall_clock64();
+      r.slot = (int32_t)blockIdx.x;
+      r.facs = facs;
+      results[pid] = r;
+    }
+    __syncthreads();
+  }
+}
+
+
 // ============================ host side ========================================
 
 }  // namespace
@@ -786,18 +1361,33 @@ struct mds_batch_impl {
   double *d_dc = nullptr;
   ResultDev *d_results = nullptr;
   std::vector<ResultDev> h_results;
+  // whole-IPM mode
+  int ipm_rows = 0;          // trace rows per problem (0: no IPM memory)
+  bool newton_io = true;     // every problem has Newton-system inputs and outputs
+  IpmDev *d_ipms = nullptr;
+  IpmResDev *d_ipm_res = nullptr;
+  IpmIterDev *d_trace = nullptr;
   char err[256] = {0};
 };
 
 namespace {
 
 size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
+inline size_t al256_(size_t b) { return ((b + 255) & ~(size_t)255) + (b == 0 ? 256 : 0); }
 
 struct BatchLayout {
   size_t probs, slots, order, ctl, results, csc_total, slot_bytes, total;
-  int Nmax, nsmax, nslots;
+  size_t ipms = 0, ipm_res = 0, trace = 0, slot_ipm = 0;
+  int Nmax, nsmax, nslots, ndmax = 0, mmax = 0, ipm_rows = 0;
   std::vector<size_t> csc_off;
 };
+
+// per-slot IPM vectors, in carving order: sig, rx, dx, dzl, dzu, xt, gf, jty
+// (n each), ry, dy, cx (m), dsb (n_s), hx (n_d), prev (n + m), filt
+size_t ipm_slot_bytes(size_t n, size_t m, size_t ns, size_t nd, int rows) {
+  return 8 * al256_(8 * n) + 3 * al256_(8 * m) + al256_(8 * ns) + al256_(8 * nd) +
+         al256_(8 * (n + m)) + al256_(16 * (size_t)(rows + 1));
+}
 
 bool batch_layout(const mds_batch_problem *ps, int count, const mds_batch_opts *o, BatchLayout &L) {
   if (!ps || count <= 0) return false;
@@ -816,6 +1406,13 @@ bool batch_layout(const mds_batch_problem *ps, int count, const mds_batch_opts *
     csc += al256(4 * ((size_t)q.n_s + 1)) + al256(4 * (size_t)q.nnz_s + 4) +
            al256(8 * (size_t)q.nnz_s + 8) + al256(4 * (size_t)q.n_s + 4);
   }
+  L.ipm_rows = (o && o->ipm_max_iter > 0) ? o->ipm_max_iter + 1 : 0;
+  size_t nmax = 0;
+  for (int p = 0; p < count; ++p) {
+    L.ndmax = std::max(L.ndmax, ps[p].n_d);
+    L.mmax = std::max(L.mmax, ps[p].m);
+    nmax = std::max(nmax, (size_t)ps[p].n_d + (size_t)ps[p].n_s);
+  }
   const int want = (o && o->grid > 0) ? o->grid : 256;
   L.nslots = std::max(1, std::min(count, want));
   const size_t N = (size_t)L.Nmax;
@@ -829,7 +1426,15 @@ bool batch_layout(const mds_batch_problem *ps, int count, const mds_batch_opts *
   L.ctl = 256;
   L.results = al256(sizeof(ResultDev) * count);
   L.csc_total = csc;
-  L.total = L.probs + L.slots + L.order + L.ctl + L.results + L.csc_total + L.slot_bytes * L.nslots;
+  if (L.ipm_rows > 0) {
+    L.slot_ipm = ipm_slot_bytes(nmax, (size_t)L.mmax, (size_t)L.nsmax, (size_t)L.ndmax,
+                                L.ipm_rows);
+    L.ipms = al256(sizeof(IpmDev) * count);
+    L.ipm_res = al256(sizeof(IpmResDev) * count);
+    L.trace = al256(sizeof(IpmIterDev) * (size_t)count * (size_t)L.ipm_rows);
+  }
+  L.total = L.probs + L.slots + L.order + L.ctl + L.results + L.csc_total +
+            (L.slot_bytes + L.slot_ipm) * L.nslots + L.ipms + L.ipm_res + L.trace;
   return true;
 }
 
@@ -902,13 +1507,19 @@ int mds_batch_create(mds_batch **out, const mds_batch_problem *probs_host, int32
   if (opts && (opts->nb < 0 || opts->nb == 1 || opts->nb > BNB)) return MDS_EINVAL;
   if (opts && opts->precision != MDS_FP64 && opts->precision != MDS_FP32) return MDS_EINVAL;
   if (opts && (opts->refine_steps < 0 || opts->refine_steps > 100)) return MDS_EINVAL;
+  if (opts && (opts->ipm_max_iter < 0 || opts->ipm_max_iter > 1000)) return MDS_EINVAL;
+  bool newton_io = true;
   for (int p = 0; p < count; ++p) {
     const mds_batch_problem &q = probs_host[p];
-    if ((q.n_d > 0 && (!q.H || !q.sigma_d || !q.r_d || !q.dx_d)) ||
-        (q.m > 0 && q.n_d > 0 && !q.J_d) || !q.Js_rowptr ||
-        (q.nnz_s > 0 && (!q.Js_col || !q.Js_val)) ||
-        (q.n_s > 0 && (!q.dsbase || !q.r_s || !q.dx_s)) || (q.m > 0 && (!q.r_y || !q.dy)))
+    if ((q.n_d > 0 && !q.H) || (q.m > 0 && q.n_d > 0 && !q.J_d) || !q.Js_rowptr ||
+        (q.nnz_s > 0 && (!q.Js_col || !q.Js_val)))
       return MDS_ENULL;
+    const bool io = !((q.n_d > 0 && (!q.sigma_d || !q.r_d || !q.dx_d)) ||
+                      (q.n_s > 0 && (!q.dsbase || !q.r_s || !q.dx_s)) ||
+                      (q.m > 0 && (!q.r_y || !q.dy)));
+    // the Newton-system arrays are required unless the batch holds IPM memory
+    if (!io && L.ipm_rows == 0) return MDS_ENULL;
+    newton_io = newton_io && io;
   }
   mds_batch *b = new (std::nothrow) mds_batch();
   if (!b) return MDS_EINVAL;
@@ -927,6 +1538,8 @@ int mds_batch_create(mds_batch **out, const mds_batch_problem *probs_host, int32
   b->mixed = (opts && opts->precision == MDS_FP32) ? 1 : 0;
   b->refine_max = (opts && opts->refine_steps > 0) ? opts->refine_steps : 10;
   b->alpha = (1.0 + std::sqrt(17.0)) / 8.0;
+  b->ipm_rows = L.ipm_rows;
+  b->newton_io = newton_io;
   char *base = (char *)workspace;
   size_t o = 0;
   b->d_probs = (ProbDev *)(base + o);
@@ -943,6 +1556,14 @@ int mds_batch_create(mds_batch **out, const mds_batch_problem *probs_host, int32
   o += L.results;
   char *csc_base = base + o;
   o += L.csc_total;
+  if (L.ipm_rows > 0) {
+    b->d_ipms = (IpmDev *)(base + o);
+    o += L.ipms;
+    b->d_ipm_res = (IpmResDev *)(base + o);
+    o += L.ipm_res;
+    b->d_trace = (IpmIterDev *)(base + o);
+    o += L.trace;
+  }
   std::vector<ProbDev> hp(count);
   hipStream_t s = b->caller;
   for (int p = 0; p < count; ++p) {
@@ -982,9 +1603,35 @@ int mds_batch_create(mds_batch **out, const mds_batch_problem *probs_host, int32
   }
   std::vector<SlotDev> hs(L.nslots);
   const size_t N = (size_t)L.Nmax;
+  const size_t nmax_ipm = [&]() {
+    size_t t = 0;
+    for (int p = 0; p < count; ++p)
+      t = std::max(t, (size_t)probs_host[p].n_d + (size_t)probs_host[p].n_s);
+    return t;
+  }();
   for (int k = 0; k < L.nslots; ++k) {
-    char *c = base + o + (size_t)k * L.slot_bytes;
+    char *c = base + o + (size_t)k * (L.slot_bytes + L.slot_ipm);
     SlotDev &S = hs[k];
+    if (L.ipm_rows > 0) {
+      char *q = c + L.slot_bytes;
+      double **vn[8] = {&S.sig, &S.rx, &S.dx, &S.dzl, &S.dzu, &S.xt, &S.gf, &S.jty};
+      for (double **v : vn) {
+        *v = (double *)q;
+        q += al256_(8 * nmax_ipm);
+      }
+      double **vm[3] = {&S.ry, &S.dy, &S.cx};
+      for (double **v : vm) {
+        *v = (double *)q;
+        q += al256_(8 * (size_t)L.mmax);
+      }
+      S.dsb = (double *)q;
+      q += al256_(8 * (size_t)L.nsmax);
+      S.hx = (double *)q;
+      q += al256_(8 * (size_t)L.ndmax);
+      S.prev = (double *)q;
+      q += al256_(8 * (nmax_ipm + (size_t)L.mmax));
+      S.filt = (double *)q;
+    }
     S.buf[0] = (double *)c;
     c += al256(8 * N * N);
     S.buf[1] = (double *)c;
@@ -1046,6 +1693,10 @@ int mds_batch_create(mds_batch **out, const mds_batch_problem *probs_host, int32
 int mds_batch_run(mds_batch *b, double mu, mds_batch_result *results_host) {
   if (!b) return MDS_ENULL;
   if (!(mu >= 0.0)) return MDS_EINVAL;
+  if (!b->newton_io) {
+    snprintf(b->err, sizeof(b->err), "the batch was created without Newton-system arrays");
+    return MDS_ESTATE;
+  }
   const double dc = 1e-8 * std::pow(mu, 0.25);
   // inputs and outputs are ordered on the caller's stream
   hipError_t e = hipStreamSynchronize(b->caller);
@@ -1078,6 +1729,110 @@ int mds_batch_run(mds_batch *b, double mu, mds_batch_result *results_host) {
       o.refine_steps = r.refine_steps;
       o.pad = 0;
       o.residual = r.residual;
+    }
+  }
+  return MDS_OK;
+}
+
+int mds_batch_ipm(mds_batch *b, const mds_batch_ipm_problem *ipm_host,
+                  const mds_ipm_opts *opts, mds_batch_ipm_result *results_host,
+                  mds_batch_ipm_iter *trace_host) {
+  if (!b || !ipm_host) return MDS_ENULL;
+  if (b->ipm_rows <= 0) {
+    snprintf(b->err, sizeof(b->err), "the batch was created without IPM memory");
+    return MDS_ESTATE;
+  }
+  if (b->mixed) {
+    snprintf(b->err, sizeof(b->err), "the whole-IPM batch runs in FP64");
+    return MDS_ESTATE;
+  }
+  mds_ipm_opts o{1e-8, 0.1, 200, 2, 1e20, 0, 0};
+  if (opts) o = *opts;
+  if (!(o.tol > 0.0) || !(o.mu0 > 0.0) || o.max_iter < 1 || o.max_iter + 1 > b->ipm_rows ||
+      o.refine_steps < 0 || !(o.dw_max > 0.0))
+    return MDS_EINVAL;
+  std::vector<IpmDev> hq(b->count);
+  for (int p = 0; p < b->count; ++p) {
+    const mds_batch_ipm_problem &q = ipm_host[p];
+    IpmDev d{};
+    d.c = q.c;
+    d.w = q.w;
+    d.g = q.g;
+    d.b = q.b;
+    d.xl = q.xl;
+    d.xu = q.xu;
+    d.x = q.x;
+    d.y = q.y;
+    d.zl = q.zl;
+    d.zu = q.zu;
+    hq[p] = d;
+  }
+  std::vector<ProbDev> hp(b->count);
+  hipError_t e = hipMemcpyAsync(hp.data(), b->d_probs, sizeof(ProbDev) * b->count,
+                                hipMemcpyDeviceToHost, b->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+  if (e != hipSuccess) return fail(b, MDS_EHIP, "batch problems", e);
+  for (int p = 0; p < b->count; ++p) {
+    const mds_batch_ipm_problem &q = ipm_host[p];
+    const int nd = hp[p].nd, ns = hp[p].ns, m = hp[p].m;
+    if ((nd > 0 && !q.c) || (ns > 0 && (!q.w || !q.g)) || (m > 0 && (!q.b || !q.y)) ||
+        (nd + ns > 0 && (!q.xl || !q.xu || !q.x || !q.zl || !q.zu)))
+      return MDS_ENULL;
+  }
+  e = hipStreamSynchronize(b->caller);
+  if (e != hipSuccess) return fail(b, MDS_EHIP, "caller stream", e);
+  e = hipMemcpyAsync(b->d_ipms, hq.data(), sizeof(IpmDev) * b->count, hipMemcpyHostToDevice,
+                     b->stream);
+  if (e != hipSuccess) return fail(b, MDS_EHIP, "ipm descriptors", e);
+  IpmParams prm{o.tol, o.mu0, o.dw_max, o.max_iter, o.refine_steps, b->ipm_rows, 0};
+  k_batch_reset<<<1, 64, 0, b->stream>>>(b->d_queue, b->d_t0);
+  k_batch_ipm<<<(unsigned)b->grid, BT, 0, b->stream>>>(b->count, b->d_order, b->d_probs,
+                                                       b->d_ipms, b->d_slots, b->nb, b->alpha,
+                                                       prm, b->d_queue, b->d_t0, b->d_ipm_res,
+                                                       b->d_trace);
+  e = hipGetLastError();
+  if (e != hipSuccess) return fail(b, MDS_EHIP, "batch ipm launch", e);
+  std::vector<IpmResDev> hr(b->count);
+  unsigned long long t0 = 0;
+  e = hipMemcpyAsync(hr.data(), b->d_ipm_res, sizeof(IpmResDev) * b->count,
+                     hipMemcpyDeviceToHost, b->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(&t0, b->d_t0, 8, hipMemcpyDeviceToHost, b->stream);
+  std::vector<IpmIterDev> ht;
+  if (e == hipSuccess && trace_host) {
+    ht.resize((size_t)b->count * b->ipm_rows);
+    e = hipMemcpyAsync(ht.data(), b->d_trace, sizeof(IpmIterDev) * ht.size(),
+                       hipMemcpyDeviceToHost, b->stream);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+  if (e != hipSuccess) return fail(b, MDS_EHIP, "batch ipm results", e);
+  if (results_host) {
+    for (int p = 0; p < b->count; ++p) {
+      const IpmResDev &r = hr[p];
+      mds_batch_ipm_result &d = results_host[p];
+      memset(&d, 0, sizeof(d));
+      d.status = r.status;
+      d.iters = r.iters;
+      d.mu = r.mu;
+      d.E0 = r.E0;
+      d.t_start = r.t_start - (int64_t)t0;
+      d.t_done = r.t_done - (int64_t)t0;
+      d.slot = r.slot;
+      d.factorizations = r.facs;
+    }
+  }
+  if (trace_host) {
+    for (size_t k = 0; k < ht.size(); ++k) {
+      const IpmIterDev &r = ht[k];
+      mds_batch_ipm_iter &d = trace_host[k];
+      memset(&d, 0, sizeof(d));
+      d.mu = r.mu;
+      d.alpha_pr = r.alpha_pr;
+      d.delta_w = r.delta_w;
+      d.inertia[0] = r.inertia[0];
+      d.inertia[1] = r.inertia[1];
+      d.inertia[2] = r.inertia[2];
+      d.trials = r.trials;
+      d.backtracks = r.backtracks;
     }
   }
   return MDS_OK;

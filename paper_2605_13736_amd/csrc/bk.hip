@@ -30,6 +30,7 @@
 // upper triangle.  With the register-resident panel (bk_reg.hip) the update
 // also applies the panel's interchanges: it reads the un-updated entry
 // through the panel's index map from one buffer and writes the other.
+#include <algorithm>
 #include <climits>
 
 #include "internal.hpp"
@@ -304,6 +305,7 @@ constexpr int TT = 64;
 constexpr int TS = 36;        // panel columns staged in LDS per chunk (multiple of 4)
 constexpr int TS1 = TS + 1;   // odd row stride of the staged panels
 constexpr int TSTAGE = TT * TS / 256;  // staged entries per thread and panel
+constexpr int kTrailingGrid = 256 * 2;  // persistent trailing update: workgroups (2 per CU at 194 VGPRs)
 static_assert(TT * TS % 256 == 0 && 2 * TT * TS1 >= TT * (TT + 1), "staging");
 
 // X: matrix the panel read (entry (x, c) at X[src(x) + src(c) N]); Y: output
@@ -438,6 +440,157 @@ __global__ __launch_bounds__(256) void k_bk_trailing(int N, int nb, const double
   }
 }
 
+// Persistent form of k_bk_trailing for panels of at most TS - 1 columns
+// (one staging chunk): a grid of a few workgroups per compute unit walks the
+// tiles (tile x, x + gridDim.x, ...), and while it computes one tile the
+// loads of its next tile (the entries it updates and the panel rows it
+// stages) are already in flight.  Per entry the arithmetic is the one of
+// k_bk_trailing, in the same order.
+__device__ inline void tr_geom(long x, int a0, int &i0, int &c0, bool &diag) {
+  int ti = (int)((sqrt(8.0 * (double)x + 1.0) - 1.0) * 0.5);
+  while ((long)(ti + 1) * (ti + 2) / 2 <= x) ++ti;
+  while ((long)ti * (ti + 1) / 2 > x) --ti;
+  const int tj = (int)(x - (long)ti * (ti + 1) / 2);
+  i0 = a0 + ti * TT;
+  c0 = a0 + tj * TT;
+  diag = (ti == tj);
+}
+
+__device__ inline void tr_load(long x, int a0, int N, int kend, int k0, int jw,
+                               const double *__restrict__ W, const double *X,
+                               const double *Lsrc, const int32_t *__restrict__ src,
+                               double (&xv)[2][2][4], double (&vw)[TSTAGE],
+                               double (&vl)[TSTAGE]) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int l16 = lane & 15, l4 = lane >> 4;
+  const size_t ld = (size_t)N;
+  int i0, c0;
+  bool diag;
+  tr_geom(x, a0, i0, c0, diag);
+  const int wc = c0 + (wv & 1) * 32, wi = i0 + (wv >> 1) * 32;
+  int si[2], sc[2][4];
+#pragma unroll
+  for (int b = 0; b < 2; ++b) {
+    const int i = wi + b * 16 + l16;
+    si[b] = (i >= kend && i < N) ? (src ? src[i] : i) : 0;
+  }
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int c = wc + a * 16 + l4 + 4 * r;
+      sc[a][r] = (c >= kend && c < N) ? (src ? src[c] : c) : 0;
+    }
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int c = wc + a * 16 + l4 + 4 * r;
+        const int i = wi + b * 16 + l16;
+        xv[a][b][r] = (c >= kend && c < N && i < N && (!diag || i >= c))
+                          ? X[(size_t)si[b] + (size_t)sc[a][r] * ld] : 0.0;
+      }
+#pragma unroll
+  for (int u = 0; u < TSTAGE; ++u) {
+    const int e = tid + 256 * u, r = e & (TT - 1), t = e >> 6;
+    const int c = c0 + r, i = i0 + r;
+    vw[u] = (t < jw && c >= kend && c < N) ? W[(size_t)c + (size_t)t * ld] : 0.0;
+    vl[u] = (t < jw && i >= kend && i < N) ? Lsrc[(size_t)i + (size_t)(k0 + t) * ld] : 0.0;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_bk_trailing_ps(int N, int nb,
+                                                        const double *__restrict__ W,
+                                                        const double *X, double *Y,
+                                                        const double *Lsrc,
+                                                        const int32_t *__restrict__ src,
+                                                        const FacState *__restrict__ st,
+                                                        const int32_t *__restrict__ panel_k0,
+                                                        int slot) {
+  __shared__ double s_buf[2 * TT * TS1];
+  double(*s_t)[TT + 1] = reinterpret_cast<double(*)[TT + 1]>(s_buf);
+  double *s_w = s_buf, *s_l = s_buf + TT * TS1;
+  if (slot >= st->npanel) return;
+  const int k0 = panel_k0[slot], kend = panel_k0[slot + 1];
+  if (kend >= N || kend <= k0 || kend - k0 > nb + 1 || kend - k0 > TS) return;
+  const int jw = kend - k0;
+  const int a0 = kend & ~15;
+  const int nt = (N - a0 + TT - 1) / TT;
+  const long ntiles = (long)nt * (nt + 1) / 2;
+  long x = blockIdx.x;
+  if (x >= ntiles) return;
+  const size_t ld = (size_t)N;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int l16 = lane & 15, l4 = lane >> 4;
+  double xn[2][2][4], vwn[TSTAGE], vln[TSTAGE];
+  tr_load(x, a0, N, kend, k0, jw, W, X, Lsrc, src, xn, vwn, vln);
+  for (; x < ntiles; x += gridDim.x) {
+    int i0, c0;
+    bool diag;
+    tr_geom(x, a0, i0, c0, diag);
+    const int wc = c0 + (wv & 1) * 32, wi = i0 + (wv >> 1) * 32;
+    double xv[2][2][4];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) xv[a][b][r] = xn[a][b][r];
+    __syncthreads();  // the previous tile is done with the staging buffer
+#pragma unroll
+    for (int u = 0; u < TSTAGE; ++u) {
+      const int e = tid + 256 * u, r = e & (TT - 1), t = e >> 6;
+      s_w[r * TS1 + t] = vwn[u];
+      s_l[r * TS1 + t] = vln[u];
+    }
+    __syncthreads();
+    const long xnext = x + gridDim.x;
+    if (xnext < ntiles) tr_load(xnext, a0, N, kend, k0, jw, W, X, Lsrc, src, xn, vwn, vln);
+    d4 acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int t0 = 0; t0 < jw; t0 += 4) {
+      const int t = t0 + l4;  // < TS; entries past jw are zero
+      double av[2], bv[2];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) av[a] = s_w[(wc - c0 + a * 16 + l16) * TS1 + t];
+#pragma unroll
+      for (int b = 0; b < 2; ++b) bv[b] = s_l[(wi - i0 + b * 16 + l16) * TS1 + t];
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+          acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+    }
+    __syncthreads();  // the staging buffer becomes the transpose tile
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int c = wc + a * 16 + l4 + 4 * r;
+          const int i = wi + b * 16 + l16;
+          if (c >= kend && c < N && i < N && (!diag || i >= c)) {
+            const double v = xv[a][b][r] - acc[a][b][r];
+            Y[(size_t)i + (size_t)c * ld] = v;
+            s_t[c - c0][i - i0] = v;
+          }
+        }
+    __syncthreads();
+    for (int e = tid; e < TT * TT; e += 256) {
+      const int cl = e & (TT - 1), il = e >> 6;
+      const int c = c0 + cl, i = i0 + il;
+      if (c >= kend && c < N && i < N && i > c && (!diag || il >= cl))
+        Y[(size_t)c + (size_t)i * ld] = s_t[cl][il];
+    }
+  }
+}
+
 }  // namespace
 
 void launch_fac_reset(hipStream_t s, FacState *st, int32_t *panel_k0) {
@@ -460,7 +613,14 @@ void launch_bk_trailing(hipStream_t s, int N, int nb, int adv, int slot, const d
   if (rem <= 0) return;
   const long nt = (rem + 15 + TT - 1) / TT;
   const long tiles = nt * (nt + 1) / 2;
-  k_bk_trailing<<<(unsigned)tiles, 256, 0, s>>>(N, nb, W, X, Y, Lsrc, src, st, panel_k0, slot);
+  if (nb + 1 <= TS) {
+    // persistent: a few workgroups per compute unit walk the tiles
+    const long grid = std::min(tiles, (long)kTrailingGrid);
+    k_bk_trailing_ps<<<(unsigned)grid, 256, 0, s>>>(N, nb, W, X, Y, Lsrc, src, st, panel_k0,
+                                                     slot);
+  } else {
+    k_bk_trailing<<<(unsigned)tiles, 256, 0, s>>>(N, nb, W, X, Y, Lsrc, src, st, panel_k0, slot);
+  }
 }
 
 }  // namespace mds

@@ -31,6 +31,7 @@
 // Every wait is bounded by the wall clock; an expired wait sets FacState::xerr
 // and the workgroups leave (later panels of the same factorization return at
 // once), so the grid always drains.
+#include <algorithm>
 #include <climits>
 
 #include "panel_reg.hpp"
@@ -692,12 +693,16 @@ int bk_coop_nb() { return kCoopNB; }
 int bk_coop_wgs(int N) { return (N + kCoopT * kCoopR - 1) / (kCoopT * kCoopR); }
 
 // The exchange reads of X1 hold (PMAX + 3) (NB + 1) / 64 word pairs per lane
-// in registers, so the grid size picks the smallest instantiation.
+// in registers (every lane issues all of them on every poll), so the grid
+// picks the smallest instantiation that covers the panel: `rows` bounds the
+// rows left at the panel's start (every earlier panel factored at least
+// nb - 1 columns), and with them its workgroups.
 template <typename TX>
-static void panel_coop(hipStream_t s, int N, int nb, double alpha, const TX *X, double *Lout,
-                       int32_t *src_out, double *W, double *dd, double *ds, int32_t *ipiv,
-                       int32_t *blk, FacState *st, int32_t *panel_k0, uint64_t *xch) {
-  const int P = bk_coop_wgs(N);
+static void panel_coop(hipStream_t s, int rows, int N, int nb, double alpha, const TX *X,
+                       double *Lout, int32_t *src_out, double *W, double *dd, double *ds,
+                       int32_t *ipiv, int32_t *blk, FacState *st, int32_t *panel_k0,
+                       uint64_t *xch) {
+  const int P = std::max(1, std::min(bk_coop_wgs(N), bk_coop_wgs(rows)));
 #define MDS_COOP(PM_)                                                                  \
   k_bk_panel_coop<kCoopT, kCoopR, kCoopNB, PM_, TX><<<P, kCoopT, 0, s>>>(              \
       N, nb, alpha, P, X, Lout, src_out, W, dd, ds, ipiv, blk, st, panel_k0, xch)
@@ -708,18 +713,18 @@ static void panel_coop(hipStream_t s, int N, int nb, double alpha, const TX *X, 
 #undef MDS_COOP
 }
 
-void launch_bk_panel_coop(hipStream_t s, int N, int nb, double alpha, const double *X,
+void launch_bk_panel_coop(hipStream_t s, int rows, int N, int nb, double alpha, const double *X,
                           double *Lout, int32_t *src_out, double *W, double *dd, double *ds,
                           int32_t *ipiv, int32_t *blk, FacState *st, int32_t *panel_k0,
                           uint64_t *xch) {
-  panel_coop(s, N, nb, alpha, X, Lout, src_out, W, dd, ds, ipiv, blk, st, panel_k0, xch);
+  panel_coop(s, rows, N, nb, alpha, X, Lout, src_out, W, dd, ds, ipiv, blk, st, panel_k0, xch);
 }
 
-void launch_bk_panel_coop(hipStream_t s, int N, int nb, double alpha, const float *X,
+void launch_bk_panel_coop(hipStream_t s, int rows, int N, int nb, double alpha, const float *X,
                           double *Lout, int32_t *src_out, double *W, double *dd, double *ds,
                           int32_t *ipiv, int32_t *blk, FacState *st, int32_t *panel_k0,
                           uint64_t *xch) {
-  panel_coop(s, N, nb, alpha, X, Lout, src_out, W, dd, ds, ipiv, blk, st, panel_k0, xch);
+  panel_coop(s, rows, N, nb, alpha, X, Lout, src_out, W, dd, ds, ipiv, blk, st, panel_k0, xch);
 }
 
 }  // namespace mds

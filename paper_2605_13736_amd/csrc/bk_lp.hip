@@ -11,6 +11,8 @@
 // the FP64 update, the un-updated entry is read through the panel's index
 // map from one buffer and the result (lower tile and its mirror) is written
 // to the other.
+#include <algorithm>
+
 #include "internal.hpp"
 
 namespace mds {
@@ -23,6 +25,7 @@ constexpr int TT = 64;
 constexpr int TSL = 48;        // panel columns staged in LDS per chunk (multiple of 16)
 constexpr int TSL1 = TSL + 1;  // odd row stride of the staged panels
 constexpr int TSTL = TT * TSL / 256;  // staged entries per thread and panel
+constexpr int kTrailingLpGrid = 256 * 2;  // persistent form: workgroups (2 per CU at <= 196 VGPRs)
 static_assert(TT * TSL % 256 == 0 && 2 * TT * TSL1 >= TT * (TT + 1), "staging");
 
 // round-to-nearest-even FP32 -> BF16 (finite inputs)
@@ -218,6 +221,208 @@ __global__ __launch_bounds__(256) void k_trailing_lp(int N, int nb, const double
   }
 }
 
+// Persistent form of k_trailing_lp for panels of at most TSL - 1 columns
+// (one staging chunk): a grid of a few workgroups per compute unit walks the
+// tiles, loading the next tile's entries and panel rows while it computes
+// the current one.  Per entry the arithmetic is the one of k_trailing_lp.
+__device__ inline void lp_geom(long x, int kend, int &i0, int &c0, bool &diag) {
+  int ti = (int)((sqrt(8.0 * (double)x + 1.0) - 1.0) * 0.5);
+  while ((long)(ti + 1) * (ti + 2) / 2 <= x) ++ti;
+  while ((long)ti * (ti + 1) / 2 > x) --ti;
+  const int tj = (int)(x - (long)ti * (ti + 1) / 2);
+  i0 = kend + ti * TT;
+  c0 = kend + tj * TT;
+  diag = (ti == tj);
+}
+
+__device__ inline void lp_load(long x, int N, int kend, int k0, int jw,
+                               const double *__restrict__ W, const float *X,
+                               const double *__restrict__ Lsrc, const int32_t *__restrict__ src,
+                               float (&xv)[2][2][4], double (&vw)[TSTL], double (&vl)[TSTL]) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int l16 = lane & 15, l4 = lane >> 4;
+  const size_t ld = (size_t)N;
+  int i0, c0;
+  bool diag;
+  lp_geom(x, kend, i0, c0, diag);
+  const int wc = c0 + (wv & 1) * 32, wi = i0 + (wv >> 1) * 32;
+  int si[2], sc[2][4];
+#pragma unroll
+  for (int b = 0; b < 2; ++b) {
+    const int i = wi + b * 16 + l16;
+    si[b] = (i < N) ? (src ? src[i] : i) : 0;
+  }
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int c = wc + a * 16 + 4 * l4 + r;
+      sc[a][r] = (c < N) ? (src ? src[c] : c) : 0;
+    }
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int c = wc + a * 16 + 4 * l4 + r;
+        const int i = wi + b * 16 + l16;
+        xv[a][b][r] = (c < N && i < N && (!diag || i >= c))
+                          ? X[(size_t)si[b] + (size_t)sc[a][r] * ld] : 0.f;
+      }
+#pragma unroll
+  for (int u = 0; u < TSTL; ++u) {
+    const int e = tid + 256 * u, r = e & (TT - 1), t = e >> 6;
+    const int c = c0 + r, i = i0 + r;
+    vw[u] = (t < jw && c < N) ? W[(size_t)c + (size_t)t * ld] : 0.0;
+    vl[u] = (t < jw && i < N) ? Lsrc[(size_t)i + (size_t)(k0 + t) * ld] : 0.0;
+  }
+}
+
+template <int MODE>
+__global__ __launch_bounds__(256) void k_trailing_lp_ps(int N, int nb,
+                                                        const double *__restrict__ W,
+                                                        const float *X, float *Y,
+                                                        const double *__restrict__ Lsrc,
+                                                        const int32_t *__restrict__ src,
+                                                        const FacState *__restrict__ st,
+                                                        const int32_t *__restrict__ panel_k0,
+                                                        int slot) {
+  __shared__ float s_buf[2 * TT * TSL1];
+  float(*s_t)[TT + 1] = reinterpret_cast<float(*)[TT + 1]>(s_buf);
+  float *s_w = s_buf, *s_l = s_buf + TT * TSL1;
+  if (slot >= st->npanel) return;
+  const int k0 = panel_k0[slot], kend = panel_k0[slot + 1];
+  if (kend >= N || kend <= k0 || kend - k0 > nb + 1 || kend - k0 > TSL) return;
+  const int jw = kend - k0;
+  const int nt = (N - kend + TT - 1) / TT;
+  const long ntiles = (long)nt * (nt + 1) / 2;
+  long x = blockIdx.x;
+  if (x >= ntiles) return;
+  const size_t ld = (size_t)N;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int l16 = lane & 15, l4 = lane >> 4;
+  float xn[2][2][4];
+  double vwn[TSTL], vln[TSTL];
+  lp_load(x, N, kend, k0, jw, W, X, Lsrc, src, xn, vwn, vln);
+  for (; x < ntiles; x += gridDim.x) {
+    int i0, c0;
+    bool diag;
+    lp_geom(x, kend, i0, c0, diag);
+    const int wc = c0 + (wv & 1) * 32, wi = i0 + (wv >> 1) * 32;
+    float xv[2][2][4];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) xv[a][b][r] = xn[a][b][r];
+    __syncthreads();  // the previous tile is done with the staging buffer
+#pragma unroll
+    for (int u = 0; u < TSTL; ++u) {
+      const int e = tid + 256 * u, r = e & (TT - 1), t = e >> 6;
+      s_w[r * TSL1 + t] = (float)vwn[u];
+      s_l[r * TSL1 + t] = (float)vln[u];
+    }
+    __syncthreads();
+    const long xnext = x + gridDim.x;
+    if (xnext < ntiles) lp_load(xnext, N, kend, k0, jw, W, X, Lsrc, src, xn, vwn, vln);
+    f4 acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) acc[a][b] = f4{0.f, 0.f, 0.f, 0.f};
+    const float *wr[2], *lr[2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a) wr[a] = s_w + (wc - c0 + a * 16 + l16) * TSL1;
+#pragma unroll
+    for (int b = 0; b < 2; ++b) lr[b] = s_l + (wi - i0 + b * 16 + l16) * TSL1;
+    if (MODE == 1) {
+      for (int t0 = 0; t0 < jw; t0 += 4) {
+        const int t = t0 + l4;
+        float av[2], bv[2];
+#pragma unroll
+        for (int a = 0; a < 2; ++a) av[a] = wr[a][t];
+#pragma unroll
+        for (int b = 0; b < 2; ++b) bv[b] = lr[b][t];
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int b = 0; b < 2; ++b)
+            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a], bv[b], acc[a][b], 0, 0, 0);
+      }
+    } else if (MODE == 3) {
+      for (int t0 = 0; t0 < jw; t0 += 16) {
+        s4 ah[2], al[2], bh[2], bl[2];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int t = t0 + 4 * l4 + e;
+#pragma unroll
+          for (int a = 0; a < 2; ++a) {
+            const float v = wr[a][t];
+            const short h = to_bf16(v);
+            ah[a][e] = h;
+            al[a][e] = to_bf16(v - bf16_to_f32(h));
+          }
+#pragma unroll
+          for (int b = 0; b < 2; ++b) {
+            const float v = lr[b][t];
+            const short h = to_bf16(v);
+            bh[b][e] = h;
+            bl[b][e] = to_bf16(v - bf16_to_f32(h));
+          }
+        }
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int b = 0; b < 2; ++b) {
+            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al[a], bh[b], acc[a][b], 0, 0, 0);
+            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[a], bl[b], acc[a][b], 0, 0, 0);
+            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[a], bh[b], acc[a][b], 0, 0, 0);
+          }
+      }
+    } else {
+      for (int t0 = 0; t0 < jw; t0 += 16) {
+        s4 av[2], bv[2];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int t = t0 + 4 * l4 + e;
+#pragma unroll
+          for (int a = 0; a < 2; ++a) av[a][e] = to_bf16(wr[a][t]);
+#pragma unroll
+          for (int b = 0; b < 2; ++b) bv[b][e] = to_bf16(lr[b][t]);
+        }
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int b = 0; b < 2; ++b)
+            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av[a], bv[b], acc[a][b], 0, 0, 0);
+      }
+    }
+    __syncthreads();  // the staging buffer becomes the transpose tile
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int c = wc + a * 16 + 4 * l4 + r;
+          const int i = wi + b * 16 + l16;
+          if (c < N && i < N && (!diag || i >= c)) {
+            const float v = xv[a][b][r] - acc[a][b][r];
+            Y[(size_t)i + (size_t)c * ld] = v;
+            s_t[c - c0][i - i0] = v;
+          }
+        }
+    __syncthreads();
+    for (int e = tid; e < TT * TT; e += 256) {
+      const int cl = e & (TT - 1), il = e >> 6;
+      const int c = c0 + cl, i = i0 + il;
+      if (c < N && i < N && i > c && (!diag || il >= cl)) Y[(size_t)c + (size_t)i * ld] = s_t[cl][il];
+    }
+  }
+}
+
 // Symmetric equilibration s_j = 1 / sqrt(max_i |M_ij|) (1 for a zero
 // column): one wave per column of the full symmetric M, so the column maximum
 // is the row maximum.
@@ -258,6 +463,17 @@ void launch_trailing_lp(hipStream_t s, int mode, int N, int nb, int adv, int slo
   if (rem <= 0) return;
   const long nt = (rem + TT - 1) / TT;
   const long tiles = nt * (nt + 1) / 2;
+  if (nb + 1 <= TSL) {
+    // persistent: a few workgroups per compute unit walk the tiles
+    const unsigned g = (unsigned)std::min(tiles, (long)kTrailingLpGrid);
+    if (mode == 2)
+      k_trailing_lp_ps<2><<<g, 256, 0, s>>>(N, nb, W, X, Y, Lsrc, src, st, panel_k0, slot);
+    else if (mode == 3)
+      k_trailing_lp_ps<3><<<g, 256, 0, s>>>(N, nb, W, X, Y, Lsrc, src, st, panel_k0, slot);
+    else
+      k_trailing_lp_ps<1><<<g, 256, 0, s>>>(N, nb, W, X, Y, Lsrc, src, st, panel_k0, slot);
+    return;
+  }
   if (mode == 2)
     k_trailing_lp<2><<<(unsigned)tiles, 256, 0, s>>>(N, nb, W, X, Y, Lsrc, src, st, panel_k0, slot);
   else if (mode == 3)

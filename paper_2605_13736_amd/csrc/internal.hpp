@@ -220,11 +220,12 @@ int bk_coop_rows_per_wg();
 bool bk_coop_resident(int N);
 int bk_coop_nb();
 int bk_coop_wgs(int N);
-void launch_bk_panel_coop(hipStream_t s, int N, int nb, double alpha, const double *X,
+// rows: at least the rows left at the panel's start (sizes the grid)
+void launch_bk_panel_coop(hipStream_t s, int rows, int N, int nb, double alpha, const double *X,
                           double *Lout, int32_t *src_out, double *W, double *dd, double *ds,
                           int32_t *ipiv, int32_t *blk, FacState *st, int32_t *panel_k0,
                           uint64_t *xch);
-void launch_bk_panel_coop(hipStream_t s, int N, int nb, double alpha, const float *X,
+void launch_bk_panel_coop(hipStream_t s, int rows, int N, int nb, double alpha, const float *X,
                           double *Lout, int32_t *src_out, double *W, double *dd, double *ds,
                           int32_t *ipiv, int32_t *blk, FacState *st, int32_t *panel_k0,
                           uint64_t *xch);
