@@ -61,7 +61,13 @@ class OrIpmTrace(C.Structure):
     _fields_ = [("mu", C.c_double), ("E0", C.c_double), ("theta", C.c_double),
                 ("phi", C.c_double), ("alpha_pr", C.c_double), ("alpha_du", C.c_double),
                 ("dw", C.c_double), ("dc", C.c_double), ("inertia", C.c_int32 * 3),
-                ("trials", C.c_int32), ("backtracks", C.c_int32)]
+                ("trials", C.c_int32), ("backtracks", C.c_int32), ("soc", C.c_int32),
+                ("resto", C.c_int32), ("pad", C.c_int32)]
+
+
+class OrNlpStats(C.Structure):
+    _fields_ = [("soc_trials", C.c_int32), ("soc_accepted", C.c_int32),
+                ("resto_iters", C.c_int32), ("resto_calls", C.c_int32)]
 
 
 def lib():
@@ -126,6 +132,12 @@ def lib():
         L.or_ipm_warm.argtypes = [P, C.POINTER(OrIpmOpts), _dp, _dp, C.c_double, _dp, _dp, _dp,
                                   _dp, _ip, C.POINTER(OrIpmTrace)]
         L.or_ipm_warm.restype = C.c_int
+        L.or_nlp_test_ipm.argtypes = [P, _dp, _dp, C.POINTER(OrIpmOpts), C.c_int32, _dp, _dp,
+                                      _dp, _dp, _ip, C.POINTER(OrIpmTrace),
+                                      C.POINTER(OrNlpStats)]
+        L.or_nlp_test_ipm.restype = C.c_int
+        L.or_nlp_test_eval.argtypes = [P, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp]
+        L.or_nlp_test_eval.restype = C.c_double
         _lib = L
     return _lib
 
@@ -492,3 +504,57 @@ def ipm(P: Problem, tol=1e-8, mu0=0.1, max_iter=200, refine_steps=2, dw_max=1e20
                          trials=t.trials, backtracks=t.backtracks))
     return dict(x=x[:n], y=y[:P.m], zl=zl[:n], zu=zu[:n], status=IPM_STATUS.get(st, st),
                 code=st, iters=iters, trace=rows)
+
+
+# ---- general NLP (external model): the separable nonlinear test family ----
+NLP_STATUS = dict(IPM_STATUS)
+NLP_STATUS[9] = "hessian_negative"
+
+
+def _trace_rows(tr, iters, max_iter):
+    rows = []
+    for k in range(min(iters + 1, max_iter)):
+        t = tr[k]
+        rows.append(dict(mu=t.mu, E0=t.E0, theta=t.theta, phi=t.phi, alpha_pr=t.alpha_pr,
+                         alpha_du=t.alpha_du, dw=t.dw, dc=t.dc, inertia=tuple(t.inertia),
+                         trials=t.trials, backtracks=t.backtracks, soc=t.soc, resto=t.resto))
+    return rows
+
+
+def nlp_test_ipm(P: Problem, Q, e, tol=1e-8, mu0=0.1, max_iter=200, refine_steps=2,
+                 dw_max=1e20, force_resto=-1):
+    """The general-NLP IPM (second-order correction, restoration) on the
+    separable nonlinear test family built on P's data: Q (m x n_d quadratic
+    coefficients of the rows), e (n_s exponential weights of the objective)."""
+    n = P.nx
+    Qf = _f64(np.asarray(Q, dtype=np.float64).reshape(-1, order="F"))
+    ef = _f64(e)
+    x, zl, zu, y = _buf(n), _buf(n), _buf(n), _buf(P.m)
+    it = np.zeros(1, dtype=np.int32)
+    opts = OrIpmOpts(tol, mu0, max_iter, refine_steps, dw_max)
+    tr = (OrIpmTrace * (max_iter + 1))()
+    stats = OrNlpStats()
+    st = lib().or_nlp_test_ipm(P.ptr, _d(Qf if Qf.size else _buf(1)), _d(ef if ef.size else _buf(1)),
+                               C.byref(opts), int(force_resto), _d(x), _d(y), _d(zl), _d(zu),
+                               _i(it), tr, C.byref(stats))
+    iters = int(it[0])
+    return dict(x=x[:n], y=y[:P.m], zl=zl[:n], zu=zu[:n], status=NLP_STATUS.get(st, st),
+                code=st, iters=iters, trace=_trace_rows(tr, iters, max_iter),
+                soc_trials=stats.soc_trials, soc_accepted=stats.soc_accepted,
+                resto_iters=stats.resto_iters, resto_calls=stats.resto_calls)
+
+
+def nlp_test_eval(P: Problem, Q, e, x, y):
+    """The test family's model at (x, y): f, gradient, constraints, Jacobian
+    values (J_d, J_s) and the Lagrangian Hessian (H, w)."""
+    nd, ns, m = P.n_d, P.n_s, P.m
+    Qf = _f64(np.asarray(Q, dtype=np.float64).reshape(-1, order="F"))
+    g, c = _buf(nd + ns), _buf(m)
+    Jd, v = _buf(m * nd), _buf(len(P.v))
+    H, w = _buf(nd * nd), _buf(ns)
+    f = lib().or_nlp_test_eval(P.ptr, _d(Qf if Qf.size else _buf(1)),
+                               _d(_f64(e) if len(e) else _buf(1)), _d(_f64(x)),
+                               _d(_f64(y) if m else _buf(1)), _d(g), _d(c), _d(Jd), _d(v),
+                               _d(H), _d(w))
+    return dict(f=f, g=g[:nd + ns], c=c[:m], Jd=Jd[:m * nd].reshape((m, nd), order="F"),
+                v=v[:len(P.v)], H=H[:nd * nd].reshape((nd, nd), order="F"), w=w[:ns])

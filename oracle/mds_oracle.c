@@ -1256,3 +1256,499 @@ static int ipm_from(const orq_problem *P, const or_ipm_opts *o, const double *xd
   free(dzl); free(dzu); free(xt); free(gf);
   return status;
 }
+
+/* ======================================================================== */
+/* General NLP through an external model (the model objects of Sec. 2.3's   */
+/* end: Jacobians and Hessians supplied by the modeling layer), with the    */
+/* filter line search's second-order correction and feasibility restoration */
+/* (the Waechter & Biegler method Sec. 2.1 names).                          */
+/* ======================================================================== */
+
+/* c(x) residual over the rows: c_r (equality rows, target 0), h_r - d_r
+ * (inequality rows against their slack); returns theta = ||.||_1 */
+static double nlp_resid(const orq_problem *P, const or_nlp_model *M, const double *x,
+                        double *res) {
+  const int m = P->m, n = P->n_d + P->n_s, mE = m - P->m_I;
+  M->constraints(M->ctx, x, res);
+  double t = 0.0;
+  for (int r = 0; r < m; ++r) {
+    if (r >= mE) res[r] = res[r] - x[n + r - mE];
+    t += fabs(res[r]);
+  }
+  return t;
+}
+
+/* sum of log-slacks over the finite bounds of [x; d], and its magnitude sum */
+static double nlp_logs(const orq_problem *P, const double *x, double *absum) {
+  const int nx = nx_of(P);
+  double lg = 0.0, a = 0.0;
+  for (int i = 0; i < nx; ++i) {
+    const double lo = lo_of(P, i), up = up_of(P, i);
+    if (isfinite(lo)) { const double t = log(x[i] - lo); lg = lg + t; a = a + fabs(t); }
+    if (isfinite(up)) { const double t = log(up - x[i]); lg = lg + t; a = a + fabs(t); }
+  }
+  if (absum) *absum = a;
+  return lg;
+}
+
+/* scaled optimality error from gf (objective gradient over [x; d]), jy
+ * (J' y over [x; d]) and res (constraint residual) */
+static double nlp_error(const orq_problem *P, const double *x, const double *y,
+                        const double *zl, const double *zu, double mu, const double *gf,
+                        const double *jy, const double *res) {
+  const int n = nx_of(P), m = P->m;
+  const double s_max = 100.0;
+  double dual = 0.0, cl = 0.0, cu = 0.0, z1 = 0.0, y1 = 0.0, prim = 0.0;
+  int nz = 0;
+  for (int i = 0; i < n; ++i) {
+    double r = gf[i] + jy[i];
+    const double lo = lo_of(P, i), up = up_of(P, i);
+    if (isfinite(lo)) { r = r - zl[i]; cl = fmax(cl, fabs((x[i] - lo) * zl[i] - mu)); z1 += fabs(zl[i]); nz++; }
+    if (isfinite(up)) { r = r + zu[i]; cu = fmax(cu, fabs((up - x[i]) * zu[i] - mu)); z1 += fabs(zu[i]); nz++; }
+    if (!isfinite(r)) return NAN;
+    dual = fmax(dual, fabs(r));
+  }
+  for (int r = 0; r < m; ++r) { prim = fmax(prim, fabs(res[r])); y1 += fabs(y[r]); }
+  double sd = (m + nz > 0) ? fmax(s_max, (y1 + z1) / (double)(m + nz)) / s_max : 1.0;
+  double sc = (nz > 0) ? fmax(s_max, z1 / (double)nz) / s_max : 1.0;
+  return fmax(fmax(dual / sd, prim), fmax(cl, cu) / sc);
+}
+
+/* objective gradient over [x; d] (the slacks carry none) */
+static void nlp_grad(const orq_problem *P, const or_nlp_model *M, const double *x, double *gf) {
+  const int n = P->n_d + P->n_s, nx = nx_of(P);
+  M->gradient(M->ctx, x, gf);
+  for (int i = n; i < nx; ++i) gf[i] = 0.0;
+}
+
+/* largest primal step in (0, 1] keeping [x; d] + a dx at least (1 - tau) of
+ * every slack to its finite bounds */
+static double nlp_ftb(const orq_problem *P, const double *x, const double *dx, double tau) {
+  const int nx = nx_of(P);
+  double a = 1.0;
+  for (int i = 0; i < nx; ++i) {
+    const double lo = lo_of(P, i), up = up_of(P, i);
+    if (isfinite(lo) && dx[i] < 0.0) a = fmin(a, -tau * (x[i] - lo) / dx[i]);
+    if (isfinite(up) && -dx[i] < 0.0) a = fmin(a, -tau * (up - x[i]) / (-dx[i]));
+  }
+  return a;
+}
+
+typedef struct {
+  double th_max, th_min;
+  fentry *filt;
+  int nf;
+} nlp_filter;
+
+static int nlp_in_filter(const nlp_filter *F, double th, double ph) {
+  if (!(isfinite(th) && isfinite(ph)) || th >= F->th_max) return 1;
+  for (int f = 0; f < F->nf; ++f)
+    if (th >= F->filt[f].th && ph >= F->filt[f].ph) return 1;
+  return 0;
+}
+
+/* the acceptance tests of one trial point (th_t, ph_t) against the current
+ * (th, ph) with step alpha; *augment receives whether the filter grows */
+static int nlp_accept(const nlp_filter *F, double th, double ph, double phs, double gphi,
+                      double alpha, double th_t, double ph_t, int *augment) {
+  const double gamma_theta = 1e-5, gamma_phi = 1e-8, delta = 1.0, s_theta = 1.1, s_phi = 2.3;
+  const double eta_phi = 1e-8;
+  if (nlp_in_filter(F, th_t, ph_t)) return 0;
+  const int sw = gphi < 0.0 && alpha * pow(-gphi, s_phi) > delta * pow(th, s_theta);
+  const int armijo = le_tol(ph_t - ph, eta_phi * alpha * gphi, phs);
+  int acc = 0;
+  if (th <= F->th_min && sw) {
+    if (armijo) acc = 1;
+  } else if (th_t <= (1.0 - gamma_theta) * th || le_tol(ph_t - ph, -gamma_phi * th, phs)) {
+    acc = 1;
+  }
+  if (acc) *augment = !(sw && armijo);
+  return acc;
+}
+
+/* Newton step of the factored system F for the right-hand side (rx, ry) of
+ * the barrier problem at x, with the slack step eliminated as in
+ * step_direction: dx over [x; d], dy; the bound-multiplier steps when dzl is
+ * given */
+static void nlp_step(const orq_problem *W, const or_factor *F, const double *x, const double *zl,
+                     const double *zu, double mu, const double *sig, const double *dsb,
+                     const double *rx, const double *ry, int refine_steps, double *ry2,
+                     double *dx, double *dy, double *dzl, double *dzu) {
+  step_direction(W, F, x, zl, zu, mu, sig, dsb, rx, ry, refine_steps, ry2, dx, dy, dzl, dzu);
+}
+
+/* Feasibility restoration (our reading of the phase Waechter & Biegler
+ * describe): from x_R, Gauss-Newton-type barrier steps on
+ *   min  zeta/2 ||D_R (x - x_R)||^2 - mu sum log(slacks)   s.t.  c(x) = 0
+ * (zeta = sqrt(mu), D_R = diag(min(1, 1/|x_R|)), no constraint curvature,
+ * bound multipliers centred at mu / slack), each step cut to the boundary
+ * fraction and backtracked until theta decreases by 1e-4 alpha theta; the
+ * phase ends when theta <= 0.9 theta(x_R) and (theta, phi) is acceptable to
+ * the filter.  Returns the restoration iterations, or -1 (failure). */
+static int nlp_restore(const orq_problem *P, const or_nlp_model *M, orq_problem *W,
+                       const nlp_filter *Flt, double mu, double tau, int refine_steps,
+                       double *x, double *y, double *zl, double *zu, or_factor *F,
+                       double *work) {
+  const int nd = P->n_d, ns = P->n_s, m = P->m, n = nd + ns, nx = nx_of(P);
+  const size_t nb = (size_t)(nx > 0 ? nx : 1), mb = (size_t)(m > 0 ? m : 1);
+  double *xR = work, *dr = xR + nb, *sig = dr + nb, *rx = sig + nb, *dx = rx + nb;
+  double *xt = dx + nb, *jy = xt + nb, *dzl = jy + nb, *dzu = dzl + nb;
+  double *res = dzu + nb, *ry = res + mb, *ry2 = ry + mb, *dy = ry2 + mb, *yr = dy + mb;
+  double *dsb = yr + mb;  /* n_s <= nb entries */
+  const double zeta = sqrt(mu);
+  for (int i = 0; i < nx; ++i) {
+    xR[i] = x[i];
+    dr[i] = fmin(1.0, 1.0 / fabs(x[i]));
+  }
+  for (int r = 0; r < m; ++r) yr[r] = 0.0;
+  const double thR = nlp_resid(P, M, x, res);
+  double dw_last = 0.0;
+  /* the factor's slack block follows this phase's barrier diagonal */
+  or_factor_set_slack(F, P->m_I > 0 ? sig + n : NULL);
+  for (int k = 0; k < 30; ++k) {
+    const double th = nlp_resid(P, M, x, res);
+    if (k > 0 && th <= 0.9 * thR) {
+      double ab = 0.0;
+      const double ph = M->objective(M->ctx, x) - mu * nlp_logs(P, x, &ab);
+      if (!nlp_in_filter(Flt, th, ph)) {
+        /* leave with centred bound multipliers */
+        for (int i = 0; i < nx; ++i) {
+          const double lo = lo_of(P, i), up = up_of(P, i);
+          zl[i] = isfinite(lo) ? mu / (x[i] - lo) : 0.0;
+          zu[i] = isfinite(up) ? mu / (up - x[i]) : 0.0;
+        }
+        return k;
+      }
+    }
+    M->jacobian(M->ctx, x, (double *)W->Jd, (double *)W->v);
+    /* proximal Hessian zeta D_R^2 (no constraint curvature) */
+    double *H = (double *)W->H, *w = (double *)W->w;
+    for (int j = 0; j < nd; ++j)
+      for (int i = 0; i < nd; ++i) H[IDX(i, j, nd)] = (i == j) ? zeta * dr[i] * dr[i] : 0.0;
+    for (int k2 = 0; k2 < ns; ++k2) w[k2] = zeta * dr[nd + k2] * dr[nd + k2];
+    jac_t(W, yr, jy);
+    for (int i = 0; i < nx; ++i) {
+      double s = 0.0, gb = zeta * dr[i] * dr[i] * (x[i] - xR[i]) + jy[i];
+      const double lo = lo_of(P, i), up = up_of(P, i);
+      if (isfinite(lo)) { const double sl = x[i] - lo; s = s + (mu / sl) / sl; gb = gb - mu / sl; }
+      if (isfinite(up)) { const double su = up - x[i]; s = s + (mu / su) / su; gb = gb + mu / su; }
+      sig[i] = s;
+      rx[i] = -gb;
+      zl[i] = isfinite(lo) ? mu / (x[i] - lo) : 0.0;
+      zu[i] = isfinite(up) ? mu / (up - x[i]) : 0.0;
+    }
+    for (int r = 0; r < m; ++r) ry[r] = -res[r];
+    for (int k2 = 0; k2 < ns; ++k2) dsb[k2] = w[k2] + sig[nd + k2];
+    if (or_factor_inertia(W, sig, dsb, mu, &dw_last, 1e20, F) != 0) return -1;
+    nlp_step(W, F, x, zl, zu, mu, sig, dsb, rx, ry, refine_steps, ry2, dx, dy, dzl, dzu);
+    double a = nlp_ftb(P, x, dx, tau);
+    for (;;) {
+      for (int i = 0; i < nx; ++i) xt[i] = x[i] + a * dx[i];
+      const double tht = nlp_resid(P, M, xt, res);
+      if (isfinite(tht) && tht <= (1.0 - 1e-4 * a) * th) break;
+      a = 0.5 * a;
+      if (a < 1e-12) return -1;
+    }
+    for (int i = 0; i < nx; ++i) x[i] = xt[i];
+    for (int r = 0; r < m; ++r) yr[r] = yr[r] + a * dy[r];
+  }
+  return -1;
+}
+
+int or_nlp_ipm(const orq_problem *P, const or_nlp_model *M, const or_ipm_opts *o,
+               int32_t force_resto, double *x, double *y, double *zl, double *zu,
+               int32_t *iters, or_ipm_trace *trace, or_nlp_stats *stats) {
+  const int nd = P->n_d, ns = P->n_s, m = P->m, n = nd + ns, nx = nx_of(P);
+  const double tau_min = 0.99, kappa_eps = 10.0, kappa_mu = 0.2, theta_mu = 1.5;
+  const double kappa_sigma = 1e10, gamma_theta = 1e-5, gamma_phi = 1e-8, delta = 1.0;
+  const double s_theta = 1.1, s_phi = 2.3, gamma_alpha = 0.05, kappa_soc = 0.99;
+  const int p_max = 4;
+  int status = 6;
+  const size_t nb = (size_t)(nx > 0 ? nx : 1), mb = (size_t)(m > 0 ? m : 1);
+  /* the working problem: P's pattern and bounds, the model's current values */
+  orq_problem W = *P;
+  double *Hb = (double *)calloc((size_t)(nd > 0 ? nd * nd : 1), sizeof(double));
+  double *Jdb = (double *)calloc((size_t)(m * nd > 0 ? m * nd : 1), sizeof(double));
+  double *vb = (double *)calloc((size_t)(P->rp[m] > 0 ? P->rp[m] : 1), sizeof(double));
+  double *wb = (double *)calloc((size_t)(ns > 0 ? ns : 1), sizeof(double));
+  W.H = Hb; W.Jd = Jdb; W.v = vb; W.w = wb; W.nblk = 0;
+  double *buf = (double *)calloc(24 * nb + 12 * mb, sizeof(double));
+  double *gf = buf, *jy = gf + nb, *sig = jy + nb, *rx = sig + nb, *dx = rx + nb;
+  double *dzl = dx + nb, *dzu = dzl + nb, *xt = dzu + nb, *xs = xt + nb, *dxs = xs + nb;
+  double *dzs = dxs + nb, *dzs2 = dzs + nb;
+  double *rwork = dzs2 + nb;  /* restoration: 10 nb + 5 mb */
+  double *res = rwork + 10 * nb + 5 * mb, *ry = res + mb, *ry2 = ry + mb, *dy = ry2 + mb;
+  double *dys = dy + mb, *csoc = dys + mb;
+  double *dsb = (double *)calloc((size_t)(ns > 0 ? ns : 1), sizeof(double));
+  fentry *filt = (fentry *)malloc(sizeof(fentry) * (size_t)(o->max_iter + 2));
+  or_factor *F = or_factor_new(P);
+  or_factor_set_slack(F, P->m_I > 0 ? sig + n : NULL);
+  or_nlp_stats st0 = {0, 0, 0, 0};
+
+  /* start point: x = 0 pushed inside its bounds, the inequality rows' slacks
+   * their values pushed inside [hl, hu], y = 0, z = 1 */
+  for (int i = 0; i < n; ++i) {
+    double xi = 0.0;
+    push_inside(P->xl[i], P->xu[i], &xi);
+    x[i] = xi;
+  }
+  M->constraints(M->ctx, x, res);
+  for (int r = m - P->m_I; r < m; ++r) {
+    double t = res[r];
+    push_inside(P->hl[r - (m - P->m_I)], P->hu[r - (m - P->m_I)], &t);
+    x[n + r - (m - P->m_I)] = t;
+  }
+  for (int i = 0; i < nx; ++i) {
+    zl[i] = isfinite(lo_of(P, i)) ? 1.0 : 0.0;
+    zu[i] = isfinite(up_of(P, i)) ? 1.0 : 0.0;
+  }
+  for (int r = 0; r < m; ++r) y[r] = 0.0;
+  double mu = o->mu0, tau = fmax(tau_min, 1.0 - mu), dw_last = 0.0;
+  const double th0 = nlp_resid(P, M, x, res);
+  nlp_filter Flt = {1e4 * fmax(1.0, th0), 1e-4 * fmax(1.0, th0), filt, 0};
+
+  int it = 0;
+  for (it = 0; it < o->max_iter; ++it) {
+    nlp_grad(P, M, x, gf);
+    const double th_x = nlp_resid(P, M, x, res);
+    M->jacobian(M->ctx, x, Jdb, vb);
+    jac_t(&W, y, jy);
+    const double E0 = nlp_error(P, x, y, zl, zu, 0.0, gf, jy, res);
+    if (trace) { memset(&trace[it], 0, sizeof(or_ipm_trace)); trace[it].E0 = E0; }
+    if (!isfinite(E0)) { status = 7; break; }
+    if (E0 <= o->tol) { status = 4; break; }
+    while (nlp_error(P, x, y, zl, zu, mu, gf, jy, res) <= kappa_eps * mu) {
+      const double mnew = fmax(o->tol / 10.0, fmin(kappa_mu * mu, pow(mu, theta_mu)));
+      if (!(mnew < mu)) break;
+      mu = mnew;
+      tau = fmax(tau_min, 1.0 - mu);
+      Flt.nf = 0;
+    }
+    M->hessian(M->ctx, x, y, Hb, wb);
+    int wbad = 0;
+    for (int k = 0; k < ns; ++k) wbad |= !(wb[k] >= 0.0);
+    if (wbad) { status = 9; break; }
+    /* barrier diagonal and Newton right-hand side over [x; d] */
+    for (int i = 0; i < nx; ++i) {
+      double s = 0.0, gb = gf[i] + jy[i];
+      const double lo = lo_of(P, i), up = up_of(P, i);
+      if (isfinite(lo)) { const double sl = x[i] - lo; s = s + zl[i] / sl; gb = gb - mu / sl; }
+      if (isfinite(up)) { const double su = up - x[i]; s = s + zu[i] / su; gb = gb + mu / su; }
+      sig[i] = s;
+      rx[i] = -gb;
+    }
+    for (int r = 0; r < m; ++r) ry[r] = -res[r];
+    for (int k = 0; k < ns; ++k) dsb[k] = wb[k] + sig[nd + k];
+    const int fst = or_factor_inertia(&W, sig, dsb, mu, &dw_last, o->dw_max, F);
+    if (trace) {
+      trace[it].mu = mu; trace[it].dw = F->dw; trace[it].dc = F->dc; trace[it].trials = F->trials;
+      memcpy(trace[it].inertia, F->inertia, sizeof(F->inertia));
+    }
+    if (fst != 0) { status = 2; break; }
+    nlp_step(&W, F, x, zl, zu, mu, sig, dsb, rx, ry, o->refine_steps, ry2, dx, dy, dzl, dzu);
+    /* fraction to the boundary */
+    double a_pr = nlp_ftb(P, x, dx, tau), a_du = 1.0;
+    for (int i = 0; i < nx; ++i) {
+      if (isfinite(lo_of(P, i)) && dzl[i] < 0.0) a_du = fmin(a_du, -tau * zl[i] / dzl[i]);
+      if (isfinite(up_of(P, i)) && dzu[i] < 0.0) a_du = fmin(a_du, -tau * zu[i] / dzu[i]);
+    }
+    /* merit values at x */
+    double labs = 0.0;
+    const double fx = M->objective(M->ctx, x);
+    const double th = th_x, ph = fx - mu * nlp_logs(P, x, &labs);
+    const double phs = fabs(fx) + mu * labs;
+    double gphi = 0.0;
+    for (int i = 0; i < nx; ++i) {
+      double gi = gf[i];
+      const double lo = lo_of(P, i), up = up_of(P, i);
+      if (isfinite(lo)) gi = gi - mu / (x[i] - lo);
+      if (isfinite(up)) gi = gi + mu / (up - x[i]);
+      gphi = gphi + gi * dx[i];
+    }
+    double amin;
+    if (gphi < 0.0) {
+      amin = fmin(gamma_theta, gamma_phi * th / (-gphi));
+      if (th <= Flt.th_min) amin = fmin(amin, delta * pow(th, s_theta) / pow(-gphi, s_phi));
+      amin = gamma_alpha * amin;
+    } else {
+      amin = gamma_alpha * gamma_theta;
+    }
+    double alpha = a_pr, alpha_y = a_pr;
+    int accepted = 0, augment = 1, nbt = 0, soc = 0;
+    const double *xacc = xt;
+    for (;;) {
+      for (int i = 0; i < nx; ++i) xt[i] = x[i] + alpha * dx[i];
+      double la = 0.0;
+      const double tht = nlp_resid(P, M, xt, csoc);
+      const double pht = M->objective(M->ctx, xt) - mu * nlp_logs(P, xt, &la);
+      if (nlp_accept(&Flt, th, ph, phs, gphi, alpha, tht, pht, &augment)) {
+        accepted = 1;
+        xacc = xt;
+        break;
+      }
+      /* second-order correction on the first trial when theta did not drop */
+      if (nbt == 0 && tht >= th) {
+        double th_old = tht, a_soc = alpha;
+        /* c_soc = alpha c(x) + c(x + alpha dx) */
+        for (int r = 0; r < m; ++r) csoc[r] = alpha * res[r] + csoc[r];
+        for (int p = 0; p < p_max; ++p) {
+          st0.soc_trials++;
+          for (int r = 0; r < m; ++r) ry[r] = -csoc[r];
+          nlp_step(&W, F, x, zl, zu, mu, sig, dsb, rx, ry, o->refine_steps, ry2, dxs, dys, dzs,
+                   dzs2);
+          a_soc = nlp_ftb(P, x, dxs, tau);
+          for (int i = 0; i < nx; ++i) xs[i] = x[i] + a_soc * dxs[i];
+          double lb = 0.0;
+          const double ths = nlp_resid(P, M, xs, ry2);
+          const double phs_t = M->objective(M->ctx, xs) - mu * nlp_logs(P, xs, &lb);
+          if (nlp_accept(&Flt, th, ph, phs, gphi, alpha, ths, phs_t, &augment)) {
+            accepted = 1;
+            soc = 1;
+            xacc = xs;
+            st0.soc_accepted++;
+            break;
+          }
+          if (!(ths <= kappa_soc * th_old)) break;
+          th_old = ths;
+          for (int r = 0; r < m; ++r) csoc[r] = a_soc * csoc[r] + ry2[r];
+        }
+        if (accepted) break;
+      }
+      alpha = 0.5 * alpha;
+      nbt++;
+      if (alpha < amin || nbt >= 200) break;
+    }
+    if (trace) {
+      trace[it].theta = th; trace[it].phi = ph; trace[it].alpha_pr = soc ? a_pr : alpha;
+      trace[it].alpha_du = a_du; trace[it].backtracks = nbt; trace[it].soc = soc;
+    }
+    if (!accepted || it == force_resto) {
+      /* the iterate that enters restoration joins the filter */
+      filt[Flt.nf].th = (1.0 - gamma_theta) * th;
+      filt[Flt.nf].ph = ph - gamma_phi * th;
+      Flt.nf++;
+      const int k = nlp_restore(P, M, &W, &Flt, mu, tau, o->refine_steps, x, y, zl, zu, F, rwork);
+      or_factor_set_slack(F, P->m_I > 0 ? sig + n : NULL);
+      st0.resto_calls++;
+      if (trace) trace[it].resto = (k >= 0) ? k : -1;
+      if (k < 0) { status = 5; break; }
+      st0.resto_iters += k;
+      continue;
+    }
+    if (augment) {
+      filt[Flt.nf].th = (1.0 - gamma_theta) * th;
+      filt[Flt.nf].ph = ph - gamma_phi * th;
+      Flt.nf++;
+    }
+    alpha_y = soc ? a_pr : alpha;
+    for (int i = 0; i < nx; ++i) x[i] = xacc[i];
+    for (int r = 0; r < m; ++r) y[r] = y[r] + alpha_y * dy[r];
+    for (int i = 0; i < nx; ++i) {
+      const double lo = lo_of(P, i), up = up_of(P, i);
+      if (isfinite(lo)) {
+        const double z = zl[i] + a_du * dzl[i], sl = x[i] - lo;
+        zl[i] = fmax(fmin(z, kappa_sigma * mu / sl), mu / (kappa_sigma * sl));
+      }
+      if (isfinite(up)) {
+        const double z = zu[i] + a_du * dzu[i], su = up - x[i];
+        zu[i] = fmax(fmin(z, kappa_sigma * mu / su), mu / (kappa_sigma * su));
+      }
+    }
+  }
+  *iters = it;
+  if (stats) *stats = st0;
+  or_factor_free(F);
+  free(filt); free(buf); free(dsb); free(Hb); free(Jdb); free(vb); free(wb);
+  return status;
+}
+
+/* ---- the nonlinear test family (separable, A1 and A2 hold) --------------- */
+/* f(x) = 0.5 x_d'H x_d + c'x_d + sum_k (0.5 w_k x_k^2 + g_k x_k + e_k (exp(x_k) - x_k))
+ * c_r(x) = (J_d x_d)_r + (J_s x_s)_r + sum_j Q_rj x_d,j^2 - b_r  (equality rows)
+ * h_r(x) = the same without b_r                                   (inequality rows)
+ * with P's H, c, w, g, J_d, J_s, b and the family's Q (m x n_d) and e (n_s). */
+typedef struct {
+  const orq_problem *P;
+  const double *Q, *e;
+} nlp_test;
+
+static double nt_f(void *ctx, const double *x) {
+  const nlp_test *T = (const nlp_test *)ctx;
+  const orq_problem *P = T->P;
+  const int nd = P->n_d, ns = P->n_s;
+  double f = or_objective(P, x);
+  for (int k = 0; k < ns; ++k) f = f + T->e[k] * (exp(x[nd + k]) - x[nd + k]);
+  return f;
+}
+static void nt_g(void *ctx, const double *x, double *g) {
+  const nlp_test *T = (const nlp_test *)ctx;
+  const orq_problem *P = T->P;
+  const int nd = P->n_d, ns = P->n_s;
+  for (int i = 0; i < nd; ++i) {
+    double t = 0.0;
+    for (int j = 0; j < nd; ++j) {
+      double h = (i >= j) ? P->H[IDX(i, j, nd)] : P->H[IDX(j, i, nd)];
+      t = t + h * x[j];
+    }
+    g[i] = t + P->c[i];
+  }
+  for (int k = 0; k < ns; ++k)
+    g[nd + k] = P->w[k] * x[nd + k] + P->g[k] + T->e[k] * (exp(x[nd + k]) - 1.0);
+}
+static void nt_c(void *ctx, const double *x, double *c) {
+  const nlp_test *T = (const nlp_test *)ctx;
+  const orq_problem *P = T->P;
+  const int nd = P->n_d, m = P->m, mE = m - P->m_I;
+  for (int r = 0; r < m; ++r) {
+    double t = 0.0;
+    for (int j = 0; j < nd; ++j) t = t + P->Jd[IDX(r, j, m)] * x[j];
+    for (int a = P->rp[r]; a < P->rp[r + 1]; ++a) t = t + P->v[a] * x[nd + P->ci[a]];
+    for (int j = 0; j < nd; ++j) t = t + T->Q[IDX(r, j, m)] * (x[j] * x[j]);
+    c[r] = (r < mE) ? t - P->b[r] : t;
+  }
+}
+static void nt_j(void *ctx, const double *x, double *Jd, double *v) {
+  const nlp_test *T = (const nlp_test *)ctx;
+  const orq_problem *P = T->P;
+  const int nd = P->n_d, m = P->m;
+  for (int j = 0; j < nd; ++j)
+    for (int r = 0; r < m; ++r)
+      Jd[IDX(r, j, m)] = P->Jd[IDX(r, j, m)] + 2.0 * T->Q[IDX(r, j, m)] * x[j];
+  for (int a = 0; a < P->rp[m]; ++a) v[a] = P->v[a];
+}
+static void nt_h(void *ctx, const double *x, const double *y, double *H, double *w) {
+  const nlp_test *T = (const nlp_test *)ctx;
+  const orq_problem *P = T->P;
+  const int nd = P->n_d, ns = P->n_s, m = P->m;
+  for (int j = 0; j < nd; ++j)
+    for (int i = 0; i < nd; ++i) H[IDX(i, j, nd)] = P->H[IDX(i, j, nd)];
+  for (int j = 0; j < nd; ++j) {
+    double t = 0.0;
+    for (int r = 0; r < m; ++r) t = t + y[r] * (2.0 * T->Q[IDX(r, j, m)]);
+    H[IDX(j, j, nd)] = H[IDX(j, j, nd)] + t;
+  }
+  for (int k = 0; k < ns; ++k) w[k] = P->w[k] + T->e[k] * exp(x[nd + k]);
+}
+
+int or_nlp_test_ipm(const orq_problem *P, const double *Q, const double *e,
+                    const or_ipm_opts *o, int32_t force_resto, double *x, double *y,
+                    double *zl, double *zu, int32_t *iters, or_ipm_trace *trace,
+                    or_nlp_stats *stats) {
+  nlp_test T = {P, Q, e};
+  or_nlp_model M = {&T, nt_f, nt_g, nt_c, nt_j, nt_h};
+  return or_nlp_ipm(P, &M, o, force_resto, x, y, zl, zu, iters, trace, stats);
+}
+
+/* the test family's model at x (for finite-difference pins): f, gradient
+ * (n), constraints (m), Jacobian values (J_d m x n_d, J_s nnz) and the
+ * Lagrangian Hessian at (x, y) (H n_d x n_d, w n_s) */
+double or_nlp_test_eval(const orq_problem *P, const double *Q, const double *e, const double *x,
+                        const double *y, double *g, double *c, double *Jd, double *v,
+                        double *H, double *w) {
+  nlp_test T = {P, Q, e};
+  nt_g(&T, x, g);
+  nt_c(&T, x, c);
+  nt_j(&T, x, Jd, v);
+  nt_h(&T, x, y, H, w);
+  return nt_f(&T, x);
+}

@@ -209,6 +209,9 @@ typedef struct {       /* one row per iteration */
   double mu, E0, theta, phi, alpha_pr, alpha_du, dw, dc;
   int32_t inertia[3];
   int32_t trials, backtracks;
+  int32_t soc;         /* general NLP: a second-order correction was accepted  */
+  int32_t resto;       /* general NLP: restoration iterations (-1: failed)     */
+  int32_t pad;
 } or_ipm_trace;
 
 /* x, zl, zu (nx = n + m_I: variables then slacks) and y (m) are outputs
@@ -224,6 +227,49 @@ int or_ipm(const orq_problem *P, const or_ipm_opts *o, double *x, double *y, dou
 int or_ipm_warm(const orq_problem *P, const or_ipm_opts *o, const double *xd0, const double *y0,
                 double mu0, double *x, double *y, double *zl, double *zu, int32_t *iters,
                 or_ipm_trace *trace);
+
+/* ---- general NLP through an external model -------------------------------- */
+/* The model objects of the problem class (Sec. 2, A1/A2 hold): objective,
+ * its gradient over x (n), the constraint values over the m rows (c_r(x),
+ * target 0, for the first m_E rows; h_r(x), bounded by [hl, hu], for the
+ * rest), the Jacobian values (J_d: m x n_d column-major; J_s: in P's CSR
+ * pattern) and the Hessian of the Lagrangian f + y'c at (x, y) (H: n_d x n_d
+ * dense; w: the diagonal of the sparse block, >= 0). */
+typedef struct {
+  void *ctx;
+  double (*objective)(void *ctx, const double *x);
+  void (*gradient)(void *ctx, const double *x, double *g);
+  void (*constraints)(void *ctx, const double *x, double *c);
+  void (*jacobian)(void *ctx, const double *x, double *Jd, double *v);
+  void (*hessian)(void *ctx, const double *x, const double *y, double *H, double *w);
+} or_nlp_model;
+
+typedef struct {
+  int32_t soc_trials, soc_accepted, resto_iters, resto_calls;
+} or_nlp_stats;
+
+/* The filter line-search IPM of or_ipm on a general NLP: the model is
+ * evaluated at every iterate, a rejected first trial point whose constraint
+ * violation did not drop gets up to four second-order corrections (the
+ * Newton system solved again with c_soc = alpha c(x) + c(x_trial), then
+ * c_soc = alpha_soc c_soc + c(x_soc)), and a line search that fails enters
+ * the feasibility restoration described at nlp_restore (force_resto >= 0
+ * also enters it at that iteration).  P supplies dimensions, the J_s pattern
+ * and the bounds.  Returns or_ipm's codes, and 9 when the model's sparse
+ * Hessian diagonal is negative. */
+int or_nlp_ipm(const orq_problem *P, const or_nlp_model *M, const or_ipm_opts *o,
+               int32_t force_resto, double *x, double *y, double *zl, double *zu,
+               int32_t *iters, or_ipm_trace *trace, or_nlp_stats *stats);
+/* or_nlp_ipm on the separable nonlinear test family built on P's data:
+ * f = P's quadratic + sum_k e_k (exp(x_s,k) - x_s,k); rows (J x)_r +
+ * sum_j Q_rj x_d,j^2 (- b_r on equality rows); Q is m x n_d column-major. */
+int or_nlp_test_ipm(const orq_problem *P, const double *Q, const double *e,
+                    const or_ipm_opts *o, int32_t force_resto, double *x, double *y,
+                    double *zl, double *zu, int32_t *iters, or_ipm_trace *trace,
+                    or_nlp_stats *stats);
+double or_nlp_test_eval(const orq_problem *P, const double *Q, const double *e, const double *x,
+                        const double *y, double *g, double *c, double *Jd, double *v,
+                        double *H, double *w);
 
 #ifdef __cplusplus
 }

@@ -195,3 +195,32 @@ def family_member(prob: dict, p: int, cfg: int = 4) -> dict:
     q = dict(prob)
     q["b"] = b0 * (1.0 + 0.1 * rng.standard_normal(len(b0)))
     return q
+
+
+def nlp_terms(prob: dict, cfg: int, p: int, q_scale: float = 0.3, e_scale: float = 1.0,
+              q_per_row: int = 2) -> dict:
+    """Nonlinear terms of the separable NLP test family on a problem dict:
+    Q (m x n_d): each row gets q_per_row quadratic coefficients U[-q_scale,
+    q_scale] on distinct random dense variables (rows r, sum_j Q_rj x_d,j^2);
+    e (n_s) ~ U[0, e_scale]: objective terms e_k (exp(x_s,k) - x_s,k).  Drawn
+    from SeedSequence([cfg, p, 7]); the problem's own draws are untouched.
+    The equality rows' b is shifted by Q's terms at the generating point x0,
+    so x0 stays feasible for them."""
+    rng = np.random.default_rng(np.random.SeedSequence([int(cfg), int(p), 7]))
+    nd, ns, m = prob["n_d"], prob["n_s"], prob["m"]
+    Q = np.zeros((m, nd))
+    if nd > 0:
+        k = min(q_per_row, nd)
+        for r in range(m):
+            cols = rng.choice(nd, size=k, replace=False)
+            Q[r, cols] = rng.uniform(-q_scale, q_scale, k)
+    e = rng.uniform(0.0, e_scale, ns)
+    x0d = prob["x0"][:nd]
+    b = np.asarray(prob["b"], dtype=np.float64).copy()
+    mE = m - int(prob.get("m_I", 0))
+    b[:mE] = b[:mE] + (Q[:mE] @ (x0d * x0d) if nd else 0.0)
+    q = dict(prob)
+    q["b"] = b
+    q["Q"] = np.asfortranarray(Q)
+    q["e"] = e
+    return q
