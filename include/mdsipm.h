@@ -67,6 +67,7 @@ enum {
   MDS_ENONFINITE_INPUT = -7,/* NaN/Inf in problem data                     */
   MDS_EDS_NONPOS = -8,      /* w < 0, xl >= xu, or D_s <= 0                */
   MDS_EPATTERN = -9,        /* CSR pattern invalid (unsorted, out of range) */
+  MDS_EMODEL = -10,         /* a model callback reported a failure          */
   /* numerical outcomes (> 0) */
   MDS_ZERO_PIVOT = 1,       /* D has an exactly zero 1x1 pivot             */
   MDS_INERTIA_FAIL = 2,     /* correction shift exceeded dw_max            */
@@ -125,12 +126,14 @@ typedef struct {
                             1024 (0: 128 up to N = 128, 256 up to N = 256,
                             else 512); the cooperative panel uses 512; the
                             LDS factorization 256 or 512 (0: 512)           */
+  int32_t nlp;         /* 1: the workspace also holds the model objects of a
+                          general NLP (mds_set_nlp)                         */
   int32_t sblk_max;    /* 0: the sparse Hessian block is diag(w).  1..16: the
                           workspace also holds coupling blocks of at most
                           this many sparse variables (mds_set_sparse_blocks)
                           and the transformed Jacobian they induce (up to
                           sblk_max * nnz_s entries)                          */
-  int32_t reserved[3];
+  int32_t reserved[2];
 } mds_options;
 
 /* Problem data, all device pointers, caller-owned, must stay valid and
@@ -212,7 +215,11 @@ typedef struct {       /* one IPM iteration (host) */
                           FP64 factorization of the same Newton system;
                           bit 1: a cooperative panel's exchange wait expired
                           and the memory panel refactored the matrix        */
-  int32_t pad;
+  int32_t nlp_event;   /* NLP mode (mds_set_nlp): 1 the accepted point came
+                          from a second-order correction; 2 the iteration
+                          ended in a feasibility restoration phase (x, z are
+                          its end point, y is kept; the phase's steps are in
+                          mds_get_nlp_stats); 0 otherwise                    */
 } mds_step_info;
 
 /* Per-kernel-class device time, accumulated while timing is enabled
@@ -243,7 +250,7 @@ void mds_destroy(mds_handle *h);
 
 /* Attach problem data; validates it (finite values, w >= 0, xl < xu, sorted
  * in-range CSR) and builds the column-compressed copy of J_s in the
- * workspace.  Synchronizes the stream. */
+ * workspace.  Leaves NLP mode (mds_set_nlp).  Synchronizes the stream. */
 int mds_set_problem(mds_handle *h, const mds_problem *p);
 
 /* ---- Newton-step hot path ------------------------------------------------ */
@@ -269,6 +276,70 @@ int mds_condense(mds_handle *h, const double *sigma_d, const double *dsbase,
  * return MDS_ESTATE while a caller's diagonal is set.  Invalidates the
  * current M and factor.  Synchronizes. */
 int mds_set_m22_diag(mds_handle *h, const double *dcv);
+
+/* ---- general NLP: model objects from an external modeling layer ----------
+ * The problem class of Sec. 2 with nonlinear f and rows (A1/A2 hold: no
+ * cross Hessian between x_d and x_s, a nonnegative diagonal Hessian of the
+ * sparse block); the model objects are supplied by the modeling layer (the
+ * end of Sec. 2.3).  Every callback runs on the calling host thread with
+ * device arrays and must have finished, or be ordered on the handle's
+ * stream, when it returns; 0 means success (any other value ends the IPM
+ * step with MDS_EMODEL).  x has n = n_d + n_s entries, y has m. */
+typedef struct {
+  void *ctx;
+  int (*objective)(void *ctx, const double *x, double *f_host);       /* f(x)        */
+  int (*gradient)(void *ctx, const double *x, double *g);             /* grad f: n   */
+  /* the m rows at x: c_r(x) (target 0) on the first m_E, h_r(x) (bounded by
+   * [hl, hu] of mds_problem) on the last m_I */
+  int (*constraints)(void *ctx, const double *x, double *c);
+  /* Jacobian values at x: J_d (m x n_d, column-major), J_s in the CSR
+   * pattern of mds_problem (nnz_s values) */
+  int (*jacobian)(void *ctx, const double *x, double *J_d, double *Js_val);
+  /* Hessian of the Lagrangian f + y'c at (x, y): H (n_d x n_d, symmetric,
+   * column-major) and the diagonal w of the sparse block (n_s, >= 0) */
+  int (*hessian)(void *ctx, const double *x, const double *y, double *H, double *w);
+} mds_nlp_model;
+
+/* Switch the handle's IPM (mds_ipm_init / mds_ipm_step / mds_ipm_solve) to
+ * the general NLP given by `model` (NULL: back to the quadratic problem of
+ * mds_set_problem, whose J_s pattern, bounds and inequality bounds the NLP
+ * keeps).  Needs a workspace created with options.nlp = 1 (the model's H,
+ * J_d, J_s values, w and gradient live there).  In NLP mode the filter line
+ * search adds the second-order correction (a rejected first trial whose
+ * constraint violation did not drop: up to four re-solves with
+ * c_soc = alpha c(x) + c(x_trial), then alpha_soc c_soc + c(x_soc)) and a
+ * feasibility restoration when the line search fails (Gauss-Newton-type
+ * barrier steps on min zeta/2 ||D_R (x - x_R)||^2 s.t. c(x) = 0, zeta =
+ * sqrt(mu), D_R = diag(min(1, 1/|x_R|)), until theta <= 0.9 theta(x_R) and
+ * the point is acceptable to the filter; at most 30 steps); a line search
+ * takes at most 200 backtracks.  The model's w must stay >= 0 (else the
+ * step returns MDS_EDS_NONPOS).  The warm start and coupling blocks are not
+ * available in NLP mode (MDS_ESTATE).  The Newton-system calls
+ * (mds_condense, mds_sigma_rhs, ...) see the model's values from its last
+ * evaluation (the quadratic problem's values right after this call).
+ * Synchronizes.  Errors: MDS_ESTATE, MDS_ENULL, MDS_EHIP. */
+int mds_set_nlp(mds_handle *h, const mds_nlp_model *model);
+/* Statistics of NLP mode since mds_ipm_init: second-order corrections tried
+ * and accepted, restoration phases entered and their steps. */
+typedef struct { int32_t soc_trials, soc_accepted, resto_calls, resto_iters; } mds_nlp_stats;
+int mds_get_nlp_stats(const mds_handle *h, mds_nlp_stats *out_host);
+
+/* A built-in model of that interface, the separable nonlinear family on an
+ * MDS problem's data (for tests and benchmarks):
+ *   f(x)  = 0.5 x_d'H x_d + c'x_d + sum_k (0.5 w_k x_s,k^2 + g_k x_s,k
+ *           + e_k (exp(x_s,k) - x_s,k)),
+ *   row r = (J_d x_d)_r + (J_s x_s)_r + sum_j Q_rj x_d,j^2, minus b_r on the
+ *           equality rows;
+ * Q (m x n_d, column-major) and e (n_s, >= 0) on the device; p's arrays are
+ * read by the callbacks (caller-owned, must outlive the model).  The model
+ * works on `stream` and needs mds_sep_model_workspace_bytes() of device
+ * workspace (256-byte aligned).  model_out receives the callbacks. */
+typedef struct mds_sep_model mds_sep_model;
+size_t mds_sep_model_workspace_bytes(void);
+int mds_sep_model_create(mds_sep_model **out, const mds_dims *dims, const mds_problem *p,
+                         const double *Q, const double *e, void *stream, void *workspace,
+                         size_t workspace_bytes, mds_nlp_model *model_out);
+void mds_sep_model_destroy(mds_sep_model *M);
 
 /* Coupling blocks of the sparse Hessian (assumption A2 of Sec. 2 in its
  * general form: a pattern that makes solves with Q_{x_s} cheap).  The sparse
@@ -442,8 +513,11 @@ int mds_get_fallbacks(const mds_handle *h, mds_fallbacks *out_host);
  * host: flag MDS_DEBUG_COOP_ABORT makes every later cooperative panel launch
  * report an expired exchange wait at once (each workgroup leaves before its
  * first exchange, so every kernel still ends normally), which exercises the
- * memory-panel refactorization.  0 clears the flags.  Synchronizes. */
-enum { MDS_DEBUG_COOP_ABORT = 1 };
+ * memory-panel refactorization.  Flag MDS_DEBUG_FORCE_RESTO makes the next
+ * IPM step in NLP mode enter the feasibility restoration after its line
+ * search, whether or not the search accepted a point (the step consumes the
+ * flag).  0 clears the flags.  Synchronizes. */
+enum { MDS_DEBUG_COOP_ABORT = 1, MDS_DEBUG_FORCE_RESTO = 2 };
 int mds_set_debug(mds_handle *h, int32_t flags);
 
 /* Enable (1) or disable (0) per-launch timing; enabling clears the totals. */

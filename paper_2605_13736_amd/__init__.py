@@ -25,6 +25,7 @@ MDS_IPM_LS_FAIL = 5
 MDS_IPM_MAXITER = 6
 MDS_IPM_NONFINITE = 7
 MDS_DEBUG_COOP_ABORT = 1
+MDS_DEBUG_FORCE_RESTO = 2
 STATUS_NAMES = {4: "converged", 5: "ls_fail", 6: "maxiter", 2: "inertia_fail", 7: "nonfinite"}
 
 _vp = C.c_void_p
@@ -39,8 +40,8 @@ class Dims(C.Structure):
 
 class Options(C.Structure):
     _fields_ = [("nb", C.c_int32), ("panel", C.c_int32), ("precision", C.c_int32),
-                ("panel_threads", C.c_int32), ("sblk_max", C.c_int32),
-                ("reserved", C.c_int32 * 3)]
+                ("panel_threads", C.c_int32), ("nlp", C.c_int32), ("sblk_max", C.c_int32),
+                ("reserved", C.c_int32 * 2)]
 
 
 # panel kernels: automatic choice, panel in device memory, register-resident
@@ -88,7 +89,24 @@ class StepInfo(C.Structure):
                 ("delta_w", C.c_double), ("delta_c", C.c_double), ("eta", C.c_double),
                 ("inertia", C.c_int32 * 3), ("trials", C.c_int32), ("solves", C.c_int32),
                 ("backtracks", C.c_int32), ("status", C.c_int32), ("fallback", C.c_int32),
-                ("pad", C.c_int32)]
+                ("nlp_event", C.c_int32)]
+
+
+# general-NLP model objects (mds_nlp_model): device pointers throughout
+NLP_OBJECTIVE = C.CFUNCTYPE(C.c_int, _vp, _vp, _dp)
+NLP_VEC = C.CFUNCTYPE(C.c_int, _vp, _vp, _vp)
+NLP_JAC = C.CFUNCTYPE(C.c_int, _vp, _vp, _vp, _vp)
+NLP_HESS = C.CFUNCTYPE(C.c_int, _vp, _vp, _vp, _vp, _vp)
+
+
+class NlpModel(C.Structure):
+    _fields_ = [("ctx", _vp), ("objective", NLP_OBJECTIVE), ("gradient", NLP_VEC),
+                ("constraints", NLP_VEC), ("jacobian", NLP_JAC), ("hessian", NLP_HESS)]
+
+
+class NlpStats(C.Structure):
+    _fields_ = [("soc_trials", C.c_int32), ("soc_accepted", C.c_int32),
+                ("resto_calls", C.c_int32), ("resto_iters", C.c_int32)]
 
 
 class Fallbacks(C.Structure):
@@ -175,6 +193,12 @@ SIGNATURES = {
     "mds_get_factor": (C.c_int, [_vp, _dp, _dp, _dp, _ip]),
     "mds_set_m22_diag": (C.c_int, [_vp, _vp]),
     "mds_set_sparse_blocks": (C.c_int, [_vp, C.c_int32, _ip, _vp]),
+    "mds_set_nlp": (C.c_int, [_vp, C.POINTER(NlpModel)]),
+    "mds_get_nlp_stats": (C.c_int, [_vp, C.POINTER(NlpStats)]),
+    "mds_sep_model_workspace_bytes": (C.c_size_t, []),
+    "mds_sep_model_create": (C.c_int, [C.POINTER(_vp), C.POINTER(Dims), C.POINTER(Problem), _vp,
+                                       _vp, _vp, _vp, C.c_size_t, C.POINTER(NlpModel)]),
+    "mds_sep_model_destroy": (None, [_vp]),
     "mds_get_pivots": (C.c_int, [_vp, _ip]),
     "mds_get_inv_ds": (C.c_int, [_vp, _dp]),
     "mds_get_info": (C.c_int, [_vp, C.POINTER(Info)]),
@@ -245,7 +269,7 @@ class Solver:
     def __init__(self, n_d: int, n_s: int, m: int, nnz_s: int, nb: int = 0,
                  device: str = "cuda:0", stream=None, panel: str = "auto",
                  precision: str = "fp64", panel_threads: int = 0, m_I: int = 0,
-                 sblk_max: int = 0):
+                 sblk_max: int = 0, nlp: bool = False):
         torch = _torch()
         if not torch.cuda.is_available():
             raise MdsError("no ROCm GPU visible: the mdsipm library has no CPU path")
@@ -258,7 +282,7 @@ class Solver:
         if panel not in PANELS:
             raise MdsError("panel must be one of " + ", ".join(PANELS))
         self.opts = Options(nb, PANELS[panel], PRECISIONS[precision],
-                            int(panel_threads), int(sblk_max))
+                            int(panel_threads), int(bool(nlp)), int(sblk_max))
         self.n_d, self.n_s, self.m, self.m_I = n_d, n_s, m, m_I
         self.N, self.n = n_d + m, n_d + n_s
         self.nx = self.n + m_I  # IPM primal vector: variables, then inequality slacks
@@ -283,6 +307,9 @@ class Solver:
         if getattr(self, "h", None):
             lib().mds_destroy(self.h)
             self.h = None
+        if getattr(self, "_sep", None):
+            lib().mds_sep_model_destroy(self._sep)
+            self._sep = None
 
     def __del__(self):
         try:
@@ -369,6 +396,52 @@ class Solver:
         if st == 0:
             self._keep["Wb"] = t
         return self._check(st, "mds_set_sparse_blocks")
+
+    # ---- general NLP ------------------------------------------------------
+    def set_nlp(self, model=None, keep=None):
+        """NLP mode with the model objects `model` (an NlpModel whose
+        callbacks and context outlive the mode; `keep` is held with it), or
+        back to the quadratic problem (None)."""
+        if model is None:
+            st = lib().mds_set_nlp(self.h, None)
+            self._check(st, "mds_set_nlp")
+            self._keep.pop("nlp", None)
+            return st
+        st = lib().mds_set_nlp(self.h, C.byref(model))
+        self._check(st, "mds_set_nlp")
+        self._keep["nlp"] = (model, keep)
+        return st
+
+    def set_sep_model(self, Q, e):
+        """NLP mode with the library's separable nonlinear model on the
+        attached problem's data: rows gain sum_j Q_rj x_d,j^2 (Q: m x n_d) and
+        the objective sum_k e_k (exp(x_s,k) - x_s,k)."""
+        torch = self.torch
+        Qd = self.dev(np.asarray(Q, dtype=np.float64).reshape(-1, order="F"))
+        ed = self.dev(np.asarray(e, dtype=np.float64))
+        assert Qd.numel() == self.m * self.n_d and ed.numel() == self.n_s
+        L = lib()
+        nbytes = L.mds_sep_model_workspace_bytes()
+        ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        aligned = (ws.data_ptr() + 255) & ~255
+        model = NlpModel()
+        sep = C.c_void_p()
+        st = L.mds_sep_model_create(C.byref(sep), C.byref(self.dims), C.byref(self.cp), _ptr(Qd),
+                                    _ptr(ed), C.c_void_p(self.stream.cuda_stream),
+                                    C.c_void_p(aligned), nbytes, C.byref(model))
+        if st != 0:
+            raise MdsError(f"mds_sep_model_create: {L.mds_status_string(st).decode()}")
+        if getattr(self, "_sep", None):
+            self.set_nlp(None)
+            L.mds_sep_model_destroy(self._sep)
+        self._sep = sep
+        return self.set_nlp(model, keep=(Qd, ed, ws))
+
+    def nlp_stats(self):
+        s = NlpStats()
+        self._check(lib().mds_get_nlp_stats(self.h, C.byref(s)), "mds_get_nlp_stats")
+        return dict(soc_trials=s.soc_trials, soc_accepted=s.soc_accepted,
+                    resto_calls=s.resto_calls, resto_iters=s.resto_iters)
 
     def factor_inertia(self, mu=0.0, reg=None):
         """reg None: factor as condensed.  reg dict (delta_w_last, delta_w_max):
@@ -569,18 +642,19 @@ def _step_dict(s):
     return dict(mu=s.mu, E0=s.E0, theta=s.theta, phi=s.phi, alpha_pr=s.alpha_pr,
                 alpha_du=s.alpha_du, dw=s.delta_w, dc=s.delta_c, eta=s.eta,
                 inertia=tuple(s.inertia), trials=s.trials, solves=s.solves,
-                backtracks=s.backtracks, status=s.status, fallback=s.fallback)
+                backtracks=s.backtracks, status=s.status, fallback=s.fallback,
+                nlp_event=s.nlp_event)
 
 
 def solver_for(prob: dict, nb: int = 0, device: str = "cuda:0", panel: str = "auto",
-               precision: str = "fp64", panel_threads: int = 0) -> Solver:
+               precision: str = "fp64", panel_threads: int = 0, nlp: bool = False) -> Solver:
     """Create a Solver sized for a problem dict and attach the problem (and
     its coupling blocks of the sparse Hessian when it has them)."""
     bp = prob.get("bp")
     smax = int(np.max(np.diff(bp))) if bp is not None and len(bp) > 1 else 0
     s = Solver(prob["n_d"], prob["n_s"], prob["m"], len(prob["v"]), nb=nb, device=device,
                panel=panel, precision=precision, panel_threads=panel_threads,
-               m_I=int(prob.get("m_I", 0)), sblk_max=smax)
+               m_I=int(prob.get("m_I", 0)), sblk_max=smax, nlp=nlp)
     s.set_problem(prob)
     if smax:
         s.set_sparse_blocks(bp, prob["Wb"])

@@ -18,7 +18,7 @@ INC = os.path.join(ROOT, "include")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmdsipm.so")
 SOURCES = ["condense.hip", "bk.hip", "bk_reg.hip", "bk_coop.hip", "bk_lds.hip", "bk_lp.hip", "solve_std.hip", "vec.hip", "gmres.hip",
-           "ipm.hip", "batch.hip", "mlp.hip", "noalloc.hip", "sblock.hip", "api.hip"]
+           "ipm.hip", "batch.hip", "mlp.hip", "noalloc.hip", "sblock.hip", "nlp.hip", "api.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

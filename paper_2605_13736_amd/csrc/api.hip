@@ -88,7 +88,8 @@ enum Slot {
   S_COR, S_PREV, S_KX, S_TN, S_TM, S_TN2, S_KNH, S_KNJD, S_KNY, S_KNJS, S_EQ, S_GV,
   S_GZ, S_GRHS, S_GX, S_GW, S_GPART, S_GCOEF, S_XCH, S_XLE, S_XUE, S_DCV, S_RY2,
   S_BBP, S_BOFF, S_BKB, S_BL, S_HRP, S_HCI, S_HSRC, S_HVAL, S_HCPTR, S_HCROW, S_HCMAP, S_HCVAL,
-  S_BT1, S_BT2, S_COUNT
+  S_BT1, S_BT2, S_NH, S_NJD, S_NV, S_NW, S_NZERO, S_NCX0, S_NCSOC, S_NYR, S_NXS, S_NDXS, S_NDYS,
+  S_NXR, S_NDR, S_NCMAP, S_COUNT
 };
 
 struct Layout {
@@ -106,7 +107,8 @@ size_t sblk_nnz_max(const mds_dims &d, int sblk_max) {
   return std::min(a, b);
 }
 
-Layout make_layout(const mds_dims &d, int nb, bool pingpong, int precision, int sblk_max) {
+Layout make_layout(const mds_dims &d, int nb, bool pingpong, int precision, int sblk_max,
+                   bool nlp) {
   const size_t nd = d.n_d, ns = d.n_s, m = d.m, N = nd + m, n = nd + ns;
   const size_t nx = n + (size_t)d.m_I;
   const size_t nnz = (size_t)d.nnz_s;
@@ -167,6 +169,15 @@ Layout make_layout(const mds_dims &d, int nb, bool pingpong, int precision, int 
     bytes[S_HVAL] = bytes[S_HCVAL] = 8 * hn;
     bytes[S_HCPTR] = 4 * (ns + 1);
     bytes[S_BT1] = bytes[S_BT2] = 8 * ns;
+  }
+  if (nlp) {
+    bytes[S_NH] = 8 * nd * nd;
+    bytes[S_NJD] = 8 * m * nd;
+    bytes[S_NV] = 8 * nnz;
+    bytes[S_NW] = 8 * ns;
+    bytes[S_NZERO] = bytes[S_NCX0] = bytes[S_NCSOC] = bytes[S_NYR] = bytes[S_NDYS] = 8 * m;
+    bytes[S_NXS] = bytes[S_NDXS] = bytes[S_NXR] = bytes[S_NDR] = 8 * nx;
+    bytes[S_NCMAP] = 4 * nnz;
   }
   Layout L{};
   size_t o = 0;
@@ -811,9 +822,14 @@ void eval_grad_constr(mds_handle *h, const double *x, const double *y, double *r
   const int nd = ND(h), ns = NS(h), m = MM(h), n = h->n;
   const mds_problem &P = h->P;
   double *gf = h->w.tn, *jty = h->w.tn2, *cx = h->w.tm;
-  launch_gemv_n(S(h), nd, nd, P.H, nd, x, 0.0, gf);
-  ipm_grad_finish(S(h), nd, ns, P.c, P.w, P.g, x, gf);
-  if (h->sb.nblk > 0) sblk_matvec(S(h), h->sb, ns, x + nd, true, gf + nd);
+  if (h->nlp_on) {
+    // the model's gradient and rows; J' y from its last Jacobian
+    if (h->nlp.gradient(h->nlp.ctx, x, gf) != 0) h->model_err = true;
+  } else {
+    launch_gemv_n(S(h), nd, nd, P.H, nd, x, 0.0, gf);
+    ipm_grad_finish(S(h), nd, ns, P.c, P.w, P.g, x, gf);
+    if (h->sb.nblk > 0) sblk_matvec(S(h), h->sb, ns, x + nd, true, gf + nd);
+  }
   if (y) {
     if (nd > 0) {
       if (m > 0) launch_gemv_t(S(h), m, nd, P.J_d, m, y, 0.0, jty);
@@ -823,6 +839,11 @@ void eval_grad_constr(mds_handle *h, const double *x, const double *y, double *r
   }
   ipm_slack_grad(S(h), h->mI, h->mE, y, gf + n, jty + n);
   if (m > 0) {
+    if (h->nlp_on) {
+      if (h->nlp.constraints(h->nlp.ctx, x, cx) != 0) h->model_err = true;
+      ipm_constr_finish(S(h), m, h->mE, h->nlp_zero, x + n, cx, ry);
+      return;
+    }
     if (nd > 0) {
       launch_gemv_n(S(h), m, nd, P.J_d, m, x, 0.0, cx);
       launch_spmv_csr(S(h), m, P.Js_rowptr, P.Js_col, P.Js_val, x + nd, 1.0, cx);
@@ -906,7 +927,64 @@ void merit_launch(mds_handle *h, const double *x, double mu, double *out) {
                 cx, h->w.red, out);
 }
 
+// NLP mode: the rows' residual at x (c(x) on the equality rows, h(x) - d on
+// the inequality rows) into w.tm
+int nlp_rows(mds_handle *h, const double *x) {
+  const int m = MM(h);
+  if (m == 0) return MDS_OK;
+  if (h->nlp.constraints(h->nlp.ctx, x, h->w.tm) != 0)
+    return set_err(h, MDS_EMODEL, "model constraints failed");
+  ipm_constr_finish(S(h), m, h->mE, h->nlp_zero, x + h->n, h->w.tm, nullptr);
+  return MDS_OK;
+}
+
+// NLP mode: theta, the log-slack sum (slot 5) and mu times its magnitude sum
+// (slot 7) of x from the residual in w.tm, into out[0..7]
+void nlp_merit_launch(mds_handle *h, const double *x, double mu, double *out) {
+  ipm_red_merit(S(h), 0, 0, h->nx, MM(h), mu, x, nullptr, nullptr, nullptr, nullptr, nullptr,
+                h->w.xl_e, h->w.xu_e, h->w.tm, h->w.red, out);
+}
+
+// NLP mode: theta at x (the residual stays in w.tm) and, when phi or scale
+// is asked for, f from the model; scale = |f| + mu sum |log|, the rounding
+// scale of phi for a model objective
+int merit_nlp(mds_handle *h, const double *x, double mu, double *f, double *phi, double *theta,
+              double *scale) {
+  TRY(nlp_rows(h, x));
+  nlp_merit_launch(h, x, mu, h->w.scal);
+  HIPCHK(hipGetLastError());
+  double fv = 0.0;
+  if (f || phi || scale) {
+    if (h->nlp.objective(h->nlp.ctx, x, &fv) != 0)
+      return set_err(h, MDS_EMODEL, "model objective failed");
+  }
+  double s[8];
+  TRY(read_scal(h, s, 8));
+  if (f) *f = fv;
+  if (phi) *phi = fv - mu * s[5];
+  if (theta) *theta = s[6];
+  if (scale) *scale = std::fabs(fv) + s[7];
+  return MDS_OK;
+}
+
+int nlp_model_ok(mds_handle *h) {
+  if (!h->model_err) return MDS_OK;
+  h->model_err = false;
+  return set_err(h, MDS_EMODEL, "a model callback failed");
+}
+
+// NLP mode: the model's Jacobian at x, and the column-compressed copy of
+// its J_s values
+int nlp_jacobian(mds_handle *h, const double *x) {
+  if (h->nlp.jacobian(h->nlp.ctx, x, h->nlp_Jd, h->nlp_v) != 0)
+    return set_err(h, MDS_EMODEL, "model Jacobian failed");
+  nlp_gather(S(h), h->dims.nnz_s, h->nlp_cmap, h->nlp_v, h->w.csc_val);
+  HIPCHK(hipGetLastError());
+  return MDS_OK;
+}
+
 int merit_impl(mds_handle *h, const double *x, double mu, double *f, double *phi, double *theta) {
+  if (h->nlp_on) return merit_nlp(h, x, mu, f, phi, theta, nullptr);
   merit_launch(h, x, mu, h->w.scal);
   HIPCHK(hipGetLastError());
   double s[8];
@@ -937,7 +1015,8 @@ size_t mds_workspace_bytes(const mds_dims *dims, const mds_options *opts) {
   if (pc.nb == 0) return 0;
   const int sbm = opts ? opts->sblk_max : 0;
   if (sbm < 0 || sbm > kSBlkMax) return 0;
-  return make_layout(*dims, pc.nb, pc.reg, opts ? opts->precision : MDS_FP64, sbm).total;
+  return make_layout(*dims, pc.nb, pc.reg, opts ? opts->precision : MDS_FP64, sbm,
+                     opts && opts->nlp != 0).total;
 }
 
 int mds_create(mds_handle **out, const mds_dims *dims, const mds_options *opts, void *stream,
@@ -950,7 +1029,8 @@ int mds_create(mds_handle **out, const mds_dims *dims, const mds_options *opts, 
   const int prec = opts ? opts->precision : MDS_FP64;
   const int sbm = opts ? opts->sblk_max : 0;
   if (sbm < 0 || sbm > kSBlkMax) return MDS_EINVAL;
-  const Layout L = make_layout(*dims, nb, panel_of(*dims, opts).reg, prec, sbm);
+  const bool nlp = opts && opts->nlp != 0;
+  const Layout L = make_layout(*dims, nb, panel_of(*dims, opts).reg, prec, sbm, nlp);
   const PanelChoice pc = panel_of(*dims, opts);
   // every workgroup of the cooperative panel must be resident at once; if
   // the device cannot guarantee it, the memory panel (FP64) factors instead
@@ -1050,6 +1130,23 @@ int mds_create(mds_handle **out, const mds_dims *dims, const mds_options *opts, 
   w.kn_y = D(S_KNY);
   w.kn_js = D(S_KNJS);
   h->sblk_max = sbm;
+  h->nlp_room = nlp;
+  if (nlp) {
+    h->nlp_H = D(S_NH);
+    h->nlp_Jd = D(S_NJD);
+    h->nlp_v = D(S_NV);
+    h->nlp_w = D(S_NW);
+    h->nlp_zero = D(S_NZERO);
+    h->nlp_cx0 = D(S_NCX0);
+    h->nlp_csoc = D(S_NCSOC);
+    h->nlp_yr = D(S_NYR);
+    h->nlp_xs = D(S_NXS);
+    h->nlp_dxs = D(S_NDXS);
+    h->nlp_dys = D(S_NDYS);
+    h->nlp_xr = D(S_NXR);
+    h->nlp_dr = D(S_NDR);
+    h->nlp_cmap = I(S_NCMAP);
+  }
   if (sbm > 0) {
     SBlk &B = h->sb;
     B.bp = I(S_BBP);
@@ -1105,6 +1202,8 @@ int mds_set_problem(mds_handle *h, const mds_problem *p) {
   h->dcv_user = h->dcv_cur = nullptr;
   h->sig_h = nullptr;
   h->sb.nblk = 0;
+  h->nlp_on = false;
+  h->nlp_force_resto = 0;
   HIPCHK(hipMemsetAsync(h->w.flags, 0, 64, S(h)));
   launch_validate(S(h), d, *p, h->w.flags);
   check_ineq_bounds(S(h), (int)mI, p->hl, p->hu, h->w.flags + 5);
@@ -1157,6 +1256,7 @@ int mds_set_sparse_blocks(mds_handle *h, int32_t nblk, const int32_t *bp_host,
   }
   if (h->sblk_max <= 0)
     return set_err(h, MDS_ESTATE, "the workspace has no room for blocks (options.sblk_max = 0)");
+  if (h->nlp_on) return set_err(h, MDS_ESTATE, "coupling blocks are not available in NLP mode");
   const int ns = NS(h), m = MM(h);
   if (nblk < 0 || nblk > ns) return set_err(h, MDS_EDIMS, "nblk must be in [0, n_s]");
   if (!bp_host || !Wb) return set_err(h, MDS_ENULL, "bp_host / Wb missing");
@@ -1267,6 +1367,81 @@ int mds_set_sparse_blocks(mds_handle *h, int32_t nblk, const int32_t *bp_host,
   return MDS_OK;
 }
 
+int mds_set_nlp(mds_handle *h, const mds_nlp_model *model) {
+  TRY(check_ready(h));
+  const mds_dims &d = h->dims;
+  const int nd = d.n_d, ns = d.n_s, m = d.m;
+  const int64_t nnz = d.nnz_s;
+  if (!model) {
+    if (h->nlp_on) {
+      // back to the quadratic problem: its values and J_s's column copy
+      h->P = h->Pq;
+      launch_csc_build(S(h), m, ns, nnz, h->P.Js_rowptr, h->P.Js_col, h->P.Js_val, h->w.csc_ptr,
+                       h->w.csc_row, h->w.csc_val, h->w.csc_fill);
+      HIPCHK(hipGetLastError());
+      HIPCHK(hipStreamSynchronize(S(h)));
+    }
+    h->nlp_on = false;
+    h->ipm_ready = h->have_M = h->have_factor = false;
+    return MDS_OK;
+  }
+  if (!h->nlp_room) return set_err(h, MDS_ESTATE, "the workspace was created without options.nlp");
+  if (!model->objective || !model->gradient || !model->constraints || !model->jacobian ||
+      !model->hessian)
+    return set_err(h, MDS_ENULL, "model callback missing");
+  if (h->sb.nblk > 0) return set_err(h, MDS_ESTATE, "coupling blocks are set");
+  if (!h->nlp_on) h->Pq = h->P;
+  const mds_problem &Q = h->Pq;
+  // the model's values start as the quadratic problem's
+  vec_copy(S(h), (int64_t)nd * nd, Q.H, h->nlp_H);
+  vec_copy(S(h), (int64_t)m * nd, Q.J_d, h->nlp_Jd);
+  vec_copy(S(h), nnz, Q.Js_val, h->nlp_v);
+  vec_copy(S(h), ns, Q.w, h->nlp_w);
+  if (m > 0) HIPCHK(hipMemsetAsync(h->nlp_zero, 0, 8 * (size_t)m, S(h)));
+  HIPCHK(hipGetLastError());
+  // J_s's column copy takes the model's values through a map from each
+  // column entry to its row-compressed entry
+  if (nnz > 0) {
+    std::vector<int32_t> cptr(ns + 1), crow(nnz), rp(m + 1), ci(nnz), map(nnz);
+    HIPCHK(hipMemcpyAsync(cptr.data(), h->w.csc_ptr, 4 * (size_t)(ns + 1), hipMemcpyDeviceToHost,
+                          S(h)));
+    HIPCHK(hipMemcpyAsync(crow.data(), h->w.csc_row, 4 * (size_t)nnz, hipMemcpyDeviceToHost, S(h)));
+    HIPCHK(hipMemcpyAsync(rp.data(), Q.Js_rowptr, 4 * (size_t)(m + 1), hipMemcpyDeviceToHost, S(h)));
+    HIPCHK(hipMemcpyAsync(ci.data(), Q.Js_col, 4 * (size_t)nnz, hipMemcpyDeviceToHost, S(h)));
+    HIPCHK(hipStreamSynchronize(S(h)));
+    for (int j = 0; j < ns; ++j) {
+      for (int32_t q = cptr[j]; q < cptr[j + 1]; ++q) {
+        const int r = crow[q];
+        const int32_t *b = ci.data() + rp[r], *e = ci.data() + rp[r + 1];
+        const int32_t *f = std::lower_bound(b, e, j);
+        if (f == e || *f != j) return set_err(h, MDS_EPATTERN, "J_s column copy out of step");
+        map[q] = (int32_t)(f - ci.data());
+      }
+    }
+    HIPCHK(hipMemcpyAsync(h->nlp_cmap, map.data(), 4 * (size_t)nnz, hipMemcpyHostToDevice, S(h)));
+  }
+  h->P.H = h->nlp_H;
+  h->P.J_d = h->nlp_Jd;
+  h->P.Js_val = h->nlp_v;
+  h->P.w = h->nlp_w;
+  h->P.b = h->nlp_zero;
+  nlp_gather(S(h), nnz, h->nlp_cmap, h->nlp_v, h->w.csc_val);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(S(h)));
+  h->nlp = *model;
+  h->nlp_on = true;
+  h->model_err = false;
+  h->nlp_stats = mds_nlp_stats{};
+  h->ipm_ready = h->have_M = h->have_factor = false;
+  return MDS_OK;
+}
+
+int mds_get_nlp_stats(const mds_handle *h, mds_nlp_stats *out) {
+  if (!h || !out) return MDS_ENULL;
+  *out = h->nlp_stats;
+  return MDS_OK;
+}
+
 int mds_set_m22_diag(mds_handle *h, const double *dcv) {
   TRY(check_ready(h));
   if (dcv && MM(h) > 0) {
@@ -1371,6 +1546,12 @@ void init_slacks(mds_handle *h, double *x) {
   const int nd = ND(h), m = MM(h), n = h->n;
   const mds_problem &P = h->P;
   double *cx = h->w.tm;
+  if (h->nlp_on) {
+    // the model's row values at x
+    if (h->nlp.constraints(h->nlp.ctx, x, cx) != 0) h->model_err = true;
+    ipm_slack_project(S(h), h->mI, cx + h->mE, P.hl, P.hu, x + n);
+    return;
+  }
   if (nd > 0) {
     launch_gemv_n(S(h), m, nd, P.J_d, m, x, 0.0, cx);
     launch_spmv_csr(S(h), m, P.Js_rowptr, P.Js_col, P.Js_val, x + nd, 1.0, cx);
@@ -1378,6 +1559,97 @@ void init_slacks(mds_handle *h, double *x) {
     launch_spmv_csr(S(h), m, P.Js_rowptr, P.Js_col, P.Js_val, x + nd, 0.0, cx);
   }
   ipm_slack_project(S(h), h->mI, cx + h->mE, P.hl, P.hu, x + n);
+}
+
+// NLP mode, feasibility restoration (a reading of the phase Waechter and
+// Biegler describe): from x_R = x, barrier steps of the problem
+//   min zeta/2 ||D_R (x - x_R)||^2 - mu sum log(slacks)  s.t.  c(x) = 0,
+// zeta = sqrt(mu), D_R = diag(min(1, 1 / |x_R|)), with the rows' curvature
+// left out (a Gauss-Newton model) and the bound multipliers centred at
+// mu / slack.  Each step is cut to the boundary fraction and halved until
+// theta drops by 1e-4 alpha theta; the phase ends once theta <= 0.9
+// theta(x_R) and the point is acceptable to the filter (at most 30 steps).
+// *k receives the steps taken, or -1 when the phase failed.  y is kept; the
+// phase's own multipliers live in nlp_yr.
+int nlp_restore(mds_handle *h, double mu, double tau, int rsteps, double *x, double *zl,
+                double *zu, int *k_out) {
+  const int nd = ND(h), ns = NS(h), m = MM(h), n = h->nx;
+  const double *xl = h->w.xl_e, *xu = h->w.xu_e;
+  double *sig = h->w.sig, *rx = h->w.rx, *ry = h->w.ry, *ry2 = h->w.ry2, *dsb = h->w.dsb;
+  double *dx = h->w.dx, *dy = h->w.dy, *dzl = h->w.dzl, *dzu = h->w.dzu, *xt = h->w.xt;
+  double *xr = h->nlp_xr, *dr = h->nlp_dr, *yr = h->nlp_yr;
+  const double zeta = std::sqrt(mu);
+  *k_out = -1;
+  nlp_resto_init(S(h), n, x, xr, dr);
+  if (m > 0) HIPCHK(hipMemsetAsync(yr, 0, 8 * (size_t)m, S(h)));
+  double thR = 0.0;
+  TRY(merit_nlp(h, x, mu, nullptr, nullptr, &thR, nullptr));
+  double dw_last = 0.0;
+  // the condensation follows this phase's barrier diagonal
+  h->sigma_d = sig;
+  h->dsbase = dsb;
+  h->sig_h = (h->mI > 0) ? sig + h->n : nullptr;
+  struct SigReset {
+    mds_handle *h;
+    ~SigReset() { h->sig_h = nullptr; }
+  } reset{h};
+  for (int k = 0; k < 30; ++k) {
+    double th = 0.0;
+    TRY(merit_nlp(h, x, mu, nullptr, nullptr, &th, nullptr));
+    if (k > 0 && th <= 0.9 * thR) {
+      double ph = 0.0;
+      TRY(merit_nlp(h, x, mu, nullptr, &ph, &th, nullptr));
+      bool infilt = !(std::isfinite(th) && std::isfinite(ph)) || th >= h->theta_max;
+      for (size_t f = 0; f < h->filter.size() && !infilt; ++f)
+        if (th >= h->filter[f].first && ph >= h->filter[f].second) infilt = true;
+      if (!infilt) {
+        nlp_center_z(S(h), n, mu, x, xl, xu, zl, zu);
+        HIPCHK(hipGetLastError());
+        *k_out = k;
+        return MDS_OK;
+      }
+    }
+    TRY(nlp_jacobian(h, x));
+    // proximal Hessian zeta D_R^2, no row curvature
+    nlp_resto_hess(S(h), nd, ns, zeta, dr, h->nlp_H, h->nlp_w);
+    // J' y_R into w.tn2 and -c(x) into ry
+    eval_grad_constr(h, x, yr, ry);
+    TRY(nlp_model_ok(h));
+    nlp_resto_rhs(S(h), n, zeta, mu, x, xr, dr, h->w.tn2, xl, xu, sig, rx, zl, zu);
+    ipm_dsbase(S(h), nd, ns, h->nlp_w, sig, dsb);
+    HIPCHK(hipGetLastError());
+    mds_reg reg{};
+    reg.delta_w_last = dw_last;
+    reg.delta_w_max = 1e20;
+    mds_inertia in{};
+    const int fst = correct_impl(h, &reg, mu, &in);
+    if (fst < 0) return fst;
+    if (fst == MDS_INERTIA_FAIL) return MDS_OK;
+    dw_last = reg.delta_w_last;
+    vec_copy(S(h), m, ry, ry2);
+    ipm_ineq_rhs(S(h), h->mI, h->mE, h->w.dcv, rx + h->n, ry2);
+    mds_refine_info ri{};
+    const int rst = refine_impl(h, rx, rx + nd, ry2, dx, dx + nd, dy, rsteps, 1e-14, &ri);
+    if (rst < 0) return rst;
+    ipm_ineq_step(S(h), h->mI, h->mE, h->w.dcv, rx + h->n, dy, dx + h->n);
+    ipm_red_ftb(S(h), n, x, xl, xu, dx, zl, zu, dzl, dzu, tau, h->w.red, h->w.scal);
+    HIPCHK(hipGetLastError());
+    double sf[8];
+    TRY(read_scal(h, sf, 8));
+    double a = -sf[0];
+    for (;;) {
+      ipm_axpy_to(S(h), n, x, dx, a, xt);
+      double tht = 0.0;
+      TRY(merit_nlp(h, xt, mu, nullptr, nullptr, &tht, nullptr));
+      if (std::isfinite(tht) && tht <= (1.0 - 1e-4 * a) * th) break;
+      a = 0.5 * a;
+      if (a < 1e-12) return MDS_OK;
+    }
+    vec_copy(S(h), n, xt, x);
+    nlp_axpby(S(h), m, a, dy, yr, yr);
+    HIPCHK(hipGetLastError());
+  }
+  return MDS_OK;
 }
 
 int ipm_opts_check(mds_handle *h, mds_iterate *it) {
@@ -1396,12 +1668,15 @@ extern "C" {
 int mds_ipm_init(mds_handle *h, mds_iterate *it, const mds_ipm_opts *opts) {
   TRY(check_ready(h));
   TRY(ipm_opts_check(h, it));
+  h->model_err = false;
+  h->nlp_stats = mds_nlp_stats{};
   mds_ipm_opts o{1e-8, 0.1, 200, 2, 1e20, 0, 0};
   if (opts) o = *opts;
   h->ipm = o;
   ipm_init_point(S(h), h->nx, MM(h), h->w.xl_e, h->w.xu_e, it->x, it->y, it->zl, it->zu);
   init_slacks(h, it->x);
   HIPCHK(hipGetLastError());
+  TRY(nlp_model_ok(h));
   it->mu = o.mu0;
   it->tau = std::max(0.99, 1.0 - it->mu);
   it->iter = 0;
@@ -1424,6 +1699,7 @@ int mds_ipm_init_warm(mds_handle *h, mds_iterate *it, const mds_ipm_opts *opts,
   if (h->sb.nblk > 0)
     return set_err(h, MDS_ESTATE, "the warm start completes x_s for a diagonal sparse Hessian "
                                   "(coupling blocks are set)");
+  if (h->nlp_on) return set_err(h, MDS_ESTATE, "the warm start is for the quadratic problem");
   mds_ipm_opts o{1e-8, 0.1, 200, 2, 1e20, 0, 0};
   if (opts) o = *opts;
   h->ipm = o;
@@ -1473,8 +1749,11 @@ static int ipm_step_impl(mds_handle *h, mds_iterate *it, mds_step_info *info, bo
 
   I.mu = mu;
   if (it->iter >= h->ipm.max_iter) return I.status = MDS_IPM_MAXITER;
+  const bool nlp = h->nlp_on;
+  if (nlp) TRY(nlp_jacobian(h, x));
   double E0 = 0.0, Emu0 = 0.0;  // E_0 and E_mu at the incoming mu, one pass
   TRY(opt_error_pair(h, x, y, zl, zu, mu, &E0, &Emu0));
+  if (nlp) TRY(nlp_model_ok(h));
   I.E0 = E0;
   if (!std::isfinite(E0)) return I.status = MDS_IPM_NONFINITE;
   if (E0 <= h->ipm.tol) return I.status = MDS_IPM_CONVERGED;
@@ -1490,6 +1769,23 @@ static int ipm_step_impl(mds_handle *h, mds_iterate *it, mds_step_info *info, bo
     h->filter.clear();
   }
   I.mu = mu;
+  if (nlp) {
+    // the Lagrangian's Hessian at (x, y); its sparse block must stay >= 0
+    if (h->nlp.hessian(h->nlp.ctx, x, y, h->nlp_H, h->nlp_w) != 0)
+      return set_err(h, MDS_EMODEL, "model Hessian failed");
+    HIPCHK(hipMemsetAsync(h->w.flags, 0, 4, S(h)));
+    nlp_check_nonneg(S(h), ns, h->nlp_w, h->w.flags);
+    HIPCHK(hipGetLastError());
+    int32_t bad = 0;
+    HIPCHK(hipMemcpyAsync(&bad, h->w.flags, 4, hipMemcpyDeviceToHost, S(h)));
+    HIPCHK(hipStreamSynchronize(S(h)));
+    if (bad) {
+      it->mu = mu;
+      it->tau = tau;
+      I.status = MDS_EDS_NONPOS;
+      return set_err(h, MDS_EDS_NONPOS, "the model's sparse Hessian w has a negative entry");
+    }
+  }
   // Newton system with inertia correction and refinement.  With inequality
   // rows the slack step is eliminated: their (4,4) diagonal is
   // 1 / (Sigma_h + dw) (formed by every condensation of the correction loop)
@@ -1497,6 +1793,7 @@ static int ipm_step_impl(mds_handle *h, mds_iterate *it, mds_step_info *info, bo
   double *sig = h->w.sig, *rx = h->w.rx, *ry = h->w.ry, *ry2 = h->w.ry2, *dsb = h->w.dsb;
   double *dx = h->w.dx, *dy = h->w.dy, *dzl = h->w.dzl, *dzu = h->w.dzu, *xt = h->w.xt;
   TRY(mds_sigma_rhs(h, x, y, zl, zu, mu, sig, rx, ry));
+  if (nlp) TRY(nlp_model_ok(h));
   ipm_dsbase(S(h), nd, ns, P.w, sig, dsb);
   h->sigma_d = sig;
   h->dsbase = dsb;
@@ -1555,17 +1852,31 @@ static int ipm_step_impl(mds_handle *h, mds_iterate *it, mds_step_info *info, bo
   // before the merit products overwrite it
   eval_grad_constr(h, x, nullptr, nullptr);
   ipm_red_gphi(S(h), n, h->w.tn, x, xl, xu, dx, mu, h->w.red, h->w.scal + 8);
-  merit_launch(h, x, mu, h->w.scal + 16);
+  if (nlp) {
+    // the gradient pass left the rows' residual at x in w.tm: keep it for
+    // the second-order correction
+    vec_copy(S(h), m, h->w.tm, h->nlp_cx0);
+    nlp_merit_launch(h, x, mu, h->w.scal + 16);
+  } else {
+    merit_launch(h, x, mu, h->w.scal + 16);
+  }
   HIPCHK(hipGetLastError());
   double s24[24];
   TRY(read_scal(h, s24, 24));
+  double fx = s24[16 + 4], fscale = 0.0;
+  if (nlp) {
+    TRY(nlp_model_ok(h));
+    if (h->nlp.objective(h->nlp.ctx, x, &fx) != 0)
+      return set_err(h, MDS_EMODEL, "model objective failed");
+    fscale = std::fabs(fx);
+  }
   const double a_pr = -s24[0], a_du = -s24[1];
   const double gphi = s24[8 + 4];
-  const double ph = s24[16 + 4] - mu * s24[16 + 5], th = s24[16 + 6];
+  const double ph = fx - mu * s24[16 + 5], th = s24[16 + 6];
   // tests that compare barrier values allow ten machine epsilons of phi's
   // rounding scale at x: near a solution the decrease they ask for falls
   // below the rounding error of phi itself
-  const double ph_tol = 10.0 * DBL_EPSILON * s24[16 + 7];
+  const double ph_tol = 10.0 * DBL_EPSILON * (fscale + s24[16 + 7]);
   double amin;
   if (gphi < 0.0) {
     amin = std::min(gamma_theta, gamma_phi * th / (-gphi));
@@ -1574,44 +1885,110 @@ static int ipm_step_impl(mds_handle *h, mds_iterate *it, mds_step_info *info, bo
   } else {
     amin = gamma_alpha * gamma_theta;
   }
-  double alpha = a_pr;
-  bool accepted = false, augment = true;
-  int nbt = 0;
-  for (;;) {
-    ipm_axpy_to(S(h), n, x, dx, alpha, xt);
-    double tht = 0.0, pht = 0.0;
-    TRY(merit_impl(h, xt, mu, nullptr, &pht, &tht));
+  // the acceptance tests of a trial point (tht, pht) reached with step al
+  auto acceptable = [&](double al, double tht, double pht, bool *aug) -> bool {
     const bool ok = std::isfinite(tht) && std::isfinite(pht);
     bool infilt = !ok || tht >= h->theta_max;
     for (size_t f = 0; f < h->filter.size() && !infilt; ++f)
       if (tht >= h->filter[f].first && pht >= h->filter[f].second) infilt = true;
-    if (!infilt) {
-      const bool sw = gphi < 0.0 && alpha * std::pow(-gphi, s_phi) > delta * std::pow(th, s_theta);
-      const bool armijo = (pht - ph) - eta_phi * alpha * gphi <= ph_tol;
-      if (th <= h->theta_min && sw) {
-        if (armijo) accepted = true;
-      } else if (tht <= (1.0 - gamma_theta) * th || (pht - ph) - (-gamma_phi * th) <= ph_tol) {
-        accepted = true;
-      }
-      if (accepted) augment = !(sw && armijo);
+    if (infilt) return false;
+    const bool sw = gphi < 0.0 && al * std::pow(-gphi, s_phi) > delta * std::pow(th, s_theta);
+    const bool armijo = (pht - ph) - eta_phi * al * gphi <= ph_tol;
+    bool acc = false;
+    if (th <= h->theta_min && sw) {
+      if (armijo) acc = true;
+    } else if (tht <= (1.0 - gamma_theta) * th || (pht - ph) - (-gamma_phi * th) <= ph_tol) {
+      acc = true;
     }
-    if (accepted) break;
+    if (acc) *aug = !(sw && armijo);
+    return acc;
+  };
+  double alpha = a_pr;
+  bool accepted = false, augment = true, soc = false;
+  int nbt = 0;
+  const double *xacc = xt;
+  for (;;) {
+    ipm_axpy_to(S(h), n, x, dx, alpha, xt);
+    double tht = 0.0, pht = 0.0;
+    TRY(merit_impl(h, xt, mu, nullptr, &pht, &tht));
+    if (acceptable(alpha, tht, pht, &augment)) {
+      accepted = true;
+      break;
+    }
+    if (nlp && nbt == 0 && tht >= th) {
+      // second-order correction of the first trial: re-solve the factored
+      // system for the rows' right-hand side -c_soc, c_soc = alpha c(x) +
+      // c(x_t) (the residual of the trial is in w.tm), then accumulate
+      // c_soc = alpha_soc c_soc + c(x_soc) while theta keeps dropping
+      const double kappa_soc = 0.99;
+      double *dxs = h->nlp_dxs, *dys = h->nlp_dys, *xs = h->nlp_xs, *cs = h->nlp_csoc;
+      nlp_axpby(S(h), m, alpha, h->nlp_cx0, h->w.tm, cs);
+      double th_old = tht;
+      for (int p = 0; p < 4; ++p) {
+        h->nlp_stats.soc_trials++;
+        nlp_axpby(S(h), m, -1.0, cs, h->nlp_zero, ry2);
+        ipm_ineq_rhs(S(h), h->mI, h->mE, h->w.dcv, rx + h->n, ry2);
+        mds_refine_info rs{};
+        const int sst = refine_impl(h, rx, rx + nd, ry2, dxs, dxs + nd, dys, rsteps, 1e-14, &rs);
+        if (sst < 0) return sst;
+        I.solves += 1 + rs.steps;
+        ipm_ineq_step(S(h), h->mI, h->mE, h->w.dcv, rx + h->n, dys, dxs + h->n);
+        // primal fraction to the boundary along dxs (slot 0)
+        ipm_red_ftb(S(h), n, x, xl, xu, dxs, zl, zu, dzl, dzu, tau, h->w.red, h->w.scal);
+        HIPCHK(hipGetLastError());
+        double sf[8];
+        TRY(read_scal(h, sf, 8));
+        const double a_soc = -sf[0];
+        ipm_axpy_to(S(h), n, x, dxs, a_soc, xs);
+        double ths = 0.0, phs = 0.0;
+        TRY(merit_nlp(h, xs, mu, nullptr, &phs, &ths, nullptr));
+        if (acceptable(alpha, ths, phs, &augment)) {
+          accepted = soc = true;
+          xacc = xs;
+          h->nlp_stats.soc_accepted++;
+          break;
+        }
+        if (!(ths <= kappa_soc * th_old)) break;
+        th_old = ths;
+        nlp_axpby(S(h), m, a_soc, cs, h->w.tm, cs);
+      }
+      if (accepted) break;
+    }
     alpha = 0.5 * alpha;
     nbt++;
-    if (alpha < amin) break;
+    if (alpha < amin || (nlp && nbt >= 200)) break;
   }
   I.theta = th;
   I.phi = ph;
-  I.alpha_pr = alpha;
+  I.alpha_pr = soc ? a_pr : alpha;
   I.alpha_du = a_du;
   I.backtracks = nbt;
+  I.nlp_event = soc ? 1 : 0;
+  const bool force = nlp && h->nlp_force_resto;
+  if (nlp && (!accepted || force)) {
+    // feasibility restoration; the iterate that enters it joins the filter
+    h->nlp_force_resto = 0;
+    h->filter.emplace_back((1.0 - gamma_theta) * th, ph - gamma_phi * th);
+    int k = -1;
+    TRY(nlp_restore(h, mu, tau, rsteps, x, zl, zu, &k));
+    h->nlp_stats.resto_calls++;
+    I.nlp_event = 2;
+    it->mu = mu;
+    it->tau = tau;
+    if (k < 0) return I.status = MDS_IPM_LS_FAIL;
+    h->nlp_stats.resto_iters += k;
+    if (sync_end) HIPCHK(hipStreamSynchronize(S(h)));
+    it->iter++;
+    I.status = MDS_OK;
+    return MDS_OK;
+  }
   if (!accepted) {
     it->mu = mu;
     it->tau = tau;
     return I.status = MDS_IPM_LS_FAIL;
   }
   if (augment) h->filter.emplace_back((1.0 - gamma_theta) * th, ph - gamma_phi * th);
-  ipm_accept(S(h), n, m, xt, x, y, dy, zl, zu, dzl, dzu, xl, xu, alpha, a_du, mu);
+  ipm_accept(S(h), n, m, xacc, x, y, dy, zl, zu, dzl, dzu, xl, xu, soc ? a_pr : alpha, a_du, mu);
   HIPCHK(hipGetLastError());
   if (sync_end) HIPCHK(hipStreamSynchronize(S(h)));
   it->mu = mu;
@@ -1704,7 +2081,9 @@ int mds_get_fallbacks(const mds_handle *h, mds_fallbacks *out) {
 
 int mds_set_debug(mds_handle *h, int32_t flags) {
   if (!h) return MDS_ENULL;
-  if (flags & ~(int32_t)MDS_DEBUG_COOP_ABORT) return set_err(h, MDS_EINVAL, "unknown debug flag");
+  if (flags & ~(int32_t)(MDS_DEBUG_COOP_ABORT | MDS_DEBUG_FORCE_RESTO))
+    return set_err(h, MDS_EINVAL, "unknown debug flag");
+  h->nlp_force_resto = (flags & MDS_DEBUG_FORCE_RESTO) ? 1 : 0;
   const int32_t force = (flags & MDS_DEBUG_COOP_ABORT) ? 1 : 0;
   // FacState::xforce, read by every cooperative panel launch
   HIPCHK(hipMemcpyAsync((char *)h->w.fst + offsetof(FacState, xforce), &force, sizeof(force),

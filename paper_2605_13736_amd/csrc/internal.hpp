@@ -107,6 +107,19 @@ struct mds_handle {
   bool panel_tail = false; // ... with the register panel once its rows fit one workgroup
   bool panel_lds = false;  // whole M in one workgroup's LDS, unblocked
   const double *dcv_user = nullptr;  // caller's per-row diagonal subtracted from M22 (m)
+  // general-NLP mode (mds_set_nlp): the model, the quadratic problem it
+  // replaced, workspace copies of the model objects and scratch of the
+  // second-order correction and the restoration
+  bool nlp_room = false, nlp_on = false, model_err = false;
+  int nlp_force_resto = 0;  // debug: the next step enters the restoration
+  mds_nlp_model nlp{};
+  mds_problem Pq{};
+  double *nlp_H = nullptr, *nlp_Jd = nullptr, *nlp_v = nullptr, *nlp_w = nullptr;
+  double *nlp_zero = nullptr, *nlp_cx0 = nullptr, *nlp_csoc = nullptr, *nlp_yr = nullptr;
+  double *nlp_xs = nullptr, *nlp_dxs = nullptr, *nlp_dys = nullptr, *nlp_xr = nullptr;
+  double *nlp_dr = nullptr;
+  int32_t *nlp_cmap = nullptr;  // CSC entry -> CSR entry of J_s
+  mds_nlp_stats nlp_stats{};
   int sblk_max = 0;        // largest coupling block the workspace was sized for
   mds::SBlk sb{};          // coupling blocks of the sparse Hessian (sb.nblk = 0: none)
   const double *dcv_cur = nullptr;   // diagonal of the current M: dcv_user or w.dcv
@@ -149,6 +162,21 @@ struct mds_handle {
 
 // ---- kernel launch wrappers (defined in the .hip files) --------------------
 namespace mds {
+
+// nlp.hip: helpers of the IPM's general-NLP mode: dst[q] = src[map[q]];
+// out = a u + v; the restoration's x_R, D_R = min(1, 1/|x_R|), proximal
+// Hessian, centred Newton system (Sigma, r_x, z) and centred multipliers
+void nlp_gather(hipStream_t s, int64_t n, const int32_t *map, const double *src, double *dst);
+void nlp_axpby(hipStream_t s, int n, double a, const double *u, const double *v, double *out);
+void nlp_resto_init(hipStream_t s, int n, const double *x, double *xr, double *dr);
+void nlp_resto_hess(hipStream_t s, int nd, int ns, double zeta, const double *dr, double *H,
+                    double *w);
+void nlp_resto_rhs(hipStream_t s, int n, double zeta, double mu, const double *x, const double *xr,
+                   const double *dr, const double *jty, const double *xl, const double *xu,
+                   double *sig, double *rx, double *zl, double *zu);
+void nlp_check_nonneg(hipStream_t s, int n, const double *w, int32_t *flag);
+void nlp_center_z(hipStream_t s, int n, double mu, const double *x, const double *xl,
+                  const double *xu, double *zl, double *zu);
 
 // sblock.hip: the blocks' L Delta L' (inv_d = 1/Delta), the values of Jh
 // and its CSC copy, block solves (mode 0: u = L^{-1} u; mode 1: u = L^{-T}
