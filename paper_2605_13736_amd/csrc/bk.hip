@@ -2,10 +2,14 @@
 // K4), right-looking, lower, left to right.
 //
 // Data layout.  M (N x N, column-major, leading dimension N) holds the
-// symmetric matrix in BOTH triangles; columns not yet factored always hold
-// the current un-updated values of the active submatrix (the lazily updated
-// form), so the column of any index is one contiguous read.  Factored columns
-// receive the unit-lower multipliers L in place (strictly lower part).
+// symmetric matrix; the condensation writes both triangles, but from then on
+// only the LOWER triangle of the active submatrix is kept current (the upper
+// one is stale after the first trailing update).  Columns not yet factored
+// hold the current un-updated values of the active submatrix (the lazily
+// updated form): the part of a column at or below the diagonal is one
+// contiguous read, the part above it is the matching row of the lower
+// triangle.  Factored columns receive the unit-lower multipliers L in place
+// (strictly lower part).
 //
 // Panel step (one workgroup, up to nb pivots).  For a panel starting at k0,
 // with W[:, t] the updated pivot column(s) of the t-th panel pivot (before
@@ -21,15 +25,17 @@
 //   otherwise                                       -> 2x2, interchange k+1<->imax
 // A zero column gives a zero 1x1 pivot (recorded in info).  An interchange
 // p<->q swaps rows p,q of the panel's L and W columns, and gives index q the
-// un-updated values of index p in both triangles of the active part.  Rows of
+// un-updated values of index p in the lower triangle of the active part.  Rows of
 // earlier panels' L are NOT permuted by later interchanges; the solve applies
 // each panel's interchanges in turn.
 //
 // Trailing update: M22 -= L21 W21' over the lower tiles of the trailing
-// matrix with FP64 MFMA (v_mfma_f64_16x16x4), each result mirrored into the
-// upper triangle.  With the register-resident panel (bk_reg.hip) the update
-// also applies the panel's interchanges: it reads the un-updated entry
-// through the panel's index map from one buffer and writes the other.
+// matrix with FP64 MFMA (v_mfma_f64_16x16x4), lower triangle only (16 bytes
+// of traffic per entry: read and write).  With the register-resident panel
+// (bk_reg.hip) the update also applies the panel's interchanges: it reads
+// the un-updated entry through the panel's index map (from the lower
+// triangle: entry (max, min) of the two physical indices) from one buffer
+// and writes the other.
 #include <algorithm>
 #include <climits>
 
@@ -142,7 +148,8 @@ __global__ __launch_bounds__(NT) void k_bk_panel(int N, int nb, double alpha,
       __syncthreads();
       double rv = 0.0;
       for (int i = k + tid; i < N; i += NT) {
-        double a = M[(size_t)i + (size_t)imax * ld];
+        // lower triangle only: rows above imax read row imax
+        double a = (i >= imax) ? M[(size_t)i + (size_t)imax * ld] : M[(size_t)imax + (size_t)i * ld];
         for (int t = 0; t < j; ++t) a = fma(-M[(size_t)i + (size_t)(k0 + t) * ld], s_wi[t], a);
         W[(size_t)i + (size_t)(j + 1) * ld] = a;
         if (i == imax) s_aii = a;
@@ -210,8 +217,8 @@ __global__ __launch_bounds__(NT) void k_bk_panel(int N, int nb, double alpha,
         }
         if (swap && i != q) {
           const double a0 = M[(size_t)i + (size_t)p * ld];
-          M[(size_t)i + (size_t)q * ld] = a0;
-          M[(size_t)q + (size_t)i * ld] = a0;
+          if (i > q) M[(size_t)i + (size_t)q * ld] = a0;
+          else M[(size_t)q + (size_t)i * ld] = a0;
         }
         M[(size_t)i + (size_t)k * ld] = (x * c - y * b) / det;
         M[(size_t)i + (size_t)(k + 1) * ld] = (y * a - x * b) / det;
@@ -250,8 +257,8 @@ __global__ __launch_bounds__(NT) void k_bk_panel(int N, int nb, double alpha,
           W[(size_t)i + (size_t)j * ld] = x;
           if (i != q) {
             const double a0 = M[(size_t)i + (size_t)p * ld];
-            M[(size_t)i + (size_t)q * ld] = a0;
-            M[(size_t)q + (size_t)i * ld] = a0;
+            if (i > q) M[(size_t)i + (size_t)q * ld] = a0;
+            else M[(size_t)q + (size_t)i * ld] = a0;
           }
         } else {
           x = W[(size_t)i + (size_t)j * ld];
@@ -306,7 +313,7 @@ constexpr int TS = 36;        // panel columns staged in LDS per chunk (multiple
 constexpr int TS1 = TS + 1;   // odd row stride of the staged panels
 constexpr int TSTAGE = TT * TS / 256;  // staged entries per thread and panel
 constexpr int kTrailingGrid = 256 * 2;  // persistent trailing update: workgroups (2 per CU at 194 VGPRs)
-static_assert(TT * TS % 256 == 0 && 2 * TT * TS1 >= TT * (TT + 1), "staging");
+static_assert(TT * TS % 256 == 0, "staging");
 
 // X: matrix the panel read (entry (x, c) at X[src(x) + src(c) N]); Y: output
 // buffer (may equal X when src is null); Lsrc: buffer holding the panel's L.
@@ -317,10 +324,8 @@ __global__ __launch_bounds__(256) void k_bk_trailing(int N, int nb, const double
                                                      const FacState *__restrict__ st,
                                                      const int32_t *__restrict__ panel_k0,
                                                      int slot) {
-  // the staged panels (W rows c0.., L rows i0..) and, after the products,
-  // the tile's transpose share one buffer
+  // the staged panels: W rows c0.., L rows i0..
   __shared__ double s_buf[2 * TT * TS1];
-  double(*s_t)[TT + 1] = reinterpret_cast<double(*)[TT + 1]>(s_buf);
   double *s_w = s_buf, *s_l = s_buf + TT * TS1;
   // only slots whose panel ran in this factorization have valid bounds
   if (slot >= st->npanel) return;
@@ -370,8 +375,10 @@ __global__ __launch_bounds__(256) void k_bk_trailing(int N, int nb, const double
       for (int r = 0; r < 4; ++r) {
         const int c = wc + a * 16 + l4 + 4 * r;
         const int i = wi + b * 16 + l16;
+        const int pi = si[b], pc = sc[a][r];  // physical row and column
         xv[a][b][r] = (c >= kend && c < N && i < N && (!diag || i >= c))
-                          ? X[(size_t)si[b] + (size_t)sc[a][r] * ld] : 0.0;
+                          ? X[(pi >= pc) ? (size_t)pi + (size_t)pc * ld : (size_t)pc + (size_t)pi * ld]
+                          : 0.0;
       }
 
   d4 acc[2][2];
@@ -414,8 +421,6 @@ __global__ __launch_bounds__(256) void k_bk_trailing(int N, int nb, const double
           acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
     }
   }
-  __syncthreads();  // the staging buffer becomes the transpose tile
-
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -424,20 +429,9 @@ __global__ __launch_bounds__(256) void k_bk_trailing(int N, int nb, const double
       for (int r = 0; r < 4; ++r) {
         const int c = wc + a * 16 + l4 + 4 * r;
         const int i = wi + b * 16 + l16;
-        if (c >= kend && c < N && i < N && (!diag || i >= c)) {
-          const double v = xv[a][b][r] - acc[a][b][r];
-          Y[(size_t)i + (size_t)c * ld] = v;
-          s_t[c - c0][i - i0] = v;
-        }
+        if (c >= kend && c < N && i < N && (!diag || i >= c))
+          Y[(size_t)i + (size_t)c * ld] = xv[a][b][r] - acc[a][b][r];
       }
-  __syncthreads();
-  // mirror into the upper triangle: element (c, i) for i > c, coalesced along c
-  for (int e = tid; e < TT * TT; e += 256) {
-    const int cl = e & (TT - 1), il = e >> 6;
-    const int c = c0 + cl, i = i0 + il;
-    if (c >= kend && c < N && i < N && i > c && (!diag || il >= cl))
-      Y[(size_t)c + (size_t)i * ld] = s_t[cl][il];
-  }
 }
 
 // Persistent form of k_bk_trailing for panels of at most TS - 1 columns
@@ -489,8 +483,10 @@ __device__ inline void tr_load(long x, int a0, int N, int kend, int k0, int jw,
       for (int r = 0; r < 4; ++r) {
         const int c = wc + a * 16 + l4 + 4 * r;
         const int i = wi + b * 16 + l16;
+        const int pi = si[b], pc = sc[a][r];  // physical row and column
         xv[a][b][r] = (c >= kend && c < N && i < N && (!diag || i >= c))
-                          ? X[(size_t)si[b] + (size_t)sc[a][r] * ld] : 0.0;
+                          ? X[(pi >= pc) ? (size_t)pi + (size_t)pc * ld : (size_t)pc + (size_t)pi * ld]
+                          : 0.0;
       }
 #pragma unroll
   for (int u = 0; u < TSTAGE; ++u) {
@@ -510,7 +506,6 @@ __global__ __launch_bounds__(256) void k_bk_trailing_ps(int N, int nb,
                                                         const int32_t *__restrict__ panel_k0,
                                                         int slot) {
   __shared__ double s_buf[2 * TT * TS1];
-  double(*s_t)[TT + 1] = reinterpret_cast<double(*)[TT + 1]>(s_buf);
   double *s_w = s_buf, *s_l = s_buf + TT * TS1;
   if (slot >= st->npanel) return;
   const int k0 = panel_k0[slot], kend = panel_k0[slot + 1];
@@ -566,7 +561,6 @@ __global__ __launch_bounds__(256) void k_bk_trailing_ps(int N, int nb,
         for (int b = 0; b < 2; ++b)
           acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
     }
-    __syncthreads();  // the staging buffer becomes the transpose tile
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -575,19 +569,9 @@ __global__ __launch_bounds__(256) void k_bk_trailing_ps(int N, int nb,
         for (int r = 0; r < 4; ++r) {
           const int c = wc + a * 16 + l4 + 4 * r;
           const int i = wi + b * 16 + l16;
-          if (c >= kend && c < N && i < N && (!diag || i >= c)) {
-            const double v = xv[a][b][r] - acc[a][b][r];
-            Y[(size_t)i + (size_t)c * ld] = v;
-            s_t[c - c0][i - i0] = v;
-          }
+          if (c >= kend && c < N && i < N && (!diag || i >= c))
+            Y[(size_t)i + (size_t)c * ld] = xv[a][b][r] - acc[a][b][r];
         }
-    __syncthreads();
-    for (int e = tid; e < TT * TT; e += 256) {
-      const int cl = e & (TT - 1), il = e >> 6;
-      const int c = c0 + cl, i = i0 + il;
-      if (c >= kend && c < N && i < N && i > c && (!diag || il >= cl))
-        Y[(size_t)c + (size_t)i * ld] = s_t[cl][il];
-    }
   }
 }
 

@@ -42,6 +42,7 @@ namespace {
 using panel::amax_combine;
 using panel::keep_branch;
 using panel::lds_wave_sync;
+using panel::sym_at;
 using panel::w_lane;
 
 constexpr int kCoopMaxN = 20480;  // LDS map of logical positions
@@ -194,7 +195,7 @@ __global__ __launch_bounds__(T) void k_bk_panel_coop(int N, int nb, double alpha
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         const int rho = gbase + tid + T * r;
-        if (pos[r] >= k && k + 1 < N) pre1[r] = X[rho + sc1 * ld];
+        if (pos[r] >= k && k + 1 < N) pre1[r] = sym_at(X, rho, sc1, ld);
       }
     }
     double bv = -1.0;
@@ -366,8 +367,8 @@ __global__ __launch_bounds__(T) void k_bk_panel_coop(int N, int nb, double alpha
         const int rho = gbase + tid + T * r;
         wic[r] = 0.0;
         if (pos[r] >= k) {
-          wic[r] = (double)X[rho + src_i * ld];
-          if (k + 2 < N) pre2[r] = X[rho + src_k2 * ld];
+          wic[r] = (double)sym_at(X, rho, src_i, ld);
+          if (k + 2 < N) pre2[r] = sym_at(X, rho, src_k2, ld);
         }
       }
 #pragma unroll

@@ -9,8 +9,8 @@
 // (v_mfma_f32_16x16x16bf16_1k).  The panel (pivot search, D blocks, L and W)
 // stays FP64: L and W are rounded to the product's input type here.  As in
 // the FP64 update, the un-updated entry is read through the panel's index
-// map from one buffer and the result (lower tile and its mirror) is written
-// to the other.
+// map from the lower triangle of one buffer and the lower tile of the result
+// is written to the other.
 #include <algorithm>
 
 #include "internal.hpp"
@@ -26,7 +26,7 @@ constexpr int TSL = 48;        // panel columns staged in LDS per chunk (multipl
 constexpr int TSL1 = TSL + 1;  // odd row stride of the staged panels
 constexpr int TSTL = TT * TSL / 256;  // staged entries per thread and panel
 constexpr int kTrailingLpGrid = 256 * 2;  // persistent form: workgroups (2 per CU at <= 196 VGPRs)
-static_assert(TT * TSL % 256 == 0 && 2 * TT * TSL1 >= TT * (TT + 1), "staging");
+static_assert(TT * TSL % 256 == 0, "staging");
 
 // round-to-nearest-even FP32 -> BF16 (finite inputs)
 __device__ inline short to_bf16(float x) {
@@ -50,10 +50,8 @@ __global__ __launch_bounds__(256) void k_trailing_lp(int N, int nb, const double
                                                      const FacState *__restrict__ st,
                                                      const int32_t *__restrict__ panel_k0,
                                                      int slot) {
-  // the staged panels (FP32: W rows c0.., L rows i0..) and, after the
-  // products, the tile's transpose share one buffer
+  // the staged panels (FP32: W rows c0.., L rows i0..)
   __shared__ float s_buf[2 * TT * TSL1];
-  float(*s_t)[TT + 1] = reinterpret_cast<float(*)[TT + 1]>(s_buf);
   float *s_w = s_buf, *s_l = s_buf + TT * TSL1;
   if (slot >= st->npanel) return;
   const int k0 = panel_k0[slot], kend = panel_k0[slot + 1];
@@ -98,8 +96,10 @@ __global__ __launch_bounds__(256) void k_trailing_lp(int N, int nb, const double
       for (int r = 0; r < 4; ++r) {
         const int c = wc + a * 16 + 4 * l4 + r;
         const int i = wi + b * 16 + l16;
+        const int pi = si[b], pc = sc[a][r];  // physical row and column
         xv[a][b][r] = (c < N && i < N && (!diag || i >= c))
-                          ? X[(size_t)si[b] + (size_t)sc[a][r] * ld] : 0.f;
+                          ? X[(pi >= pc) ? (size_t)pi + (size_t)pc * ld : (size_t)pc + (size_t)pi * ld]
+                          : 0.f;
       }
 
   f4 acc[2][2];
@@ -197,8 +197,6 @@ __global__ __launch_bounds__(256) void k_trailing_lp(int N, int nb, const double
       }
     }
   }
-  __syncthreads();  // the staging buffer becomes the transpose tile
-
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -207,18 +205,8 @@ __global__ __launch_bounds__(256) void k_trailing_lp(int N, int nb, const double
       for (int r = 0; r < 4; ++r) {
         const int c = wc + a * 16 + 4 * l4 + r;
         const int i = wi + b * 16 + l16;
-        if (c < N && i < N && (!diag || i >= c)) {
-          const float v = xv[a][b][r] - acc[a][b][r];
-          Y[(size_t)i + (size_t)c * ld] = v;
-          s_t[c - c0][i - i0] = v;
-        }
+        if (c < N && i < N && (!diag || i >= c)) Y[(size_t)i + (size_t)c * ld] = xv[a][b][r] - acc[a][b][r];
       }
-  __syncthreads();
-  for (int e = tid; e < TT * TT; e += 256) {
-    const int cl = e & (TT - 1), il = e >> 6;
-    const int c = c0 + cl, i = i0 + il;
-    if (c < N && i < N && i > c && (!diag || il >= cl)) Y[(size_t)c + (size_t)i * ld] = s_t[cl][il];
-  }
 }
 
 // Persistent form of k_trailing_lp for panels of at most TSL - 1 columns
@@ -267,8 +255,10 @@ __device__ inline void lp_load(long x, int N, int kend, int k0, int jw,
       for (int r = 0; r < 4; ++r) {
         const int c = wc + a * 16 + 4 * l4 + r;
         const int i = wi + b * 16 + l16;
+        const int pi = si[b], pc = sc[a][r];  // physical row and column
         xv[a][b][r] = (c < N && i < N && (!diag || i >= c))
-                          ? X[(size_t)si[b] + (size_t)sc[a][r] * ld] : 0.f;
+                          ? X[(pi >= pc) ? (size_t)pi + (size_t)pc * ld : (size_t)pc + (size_t)pi * ld]
+                          : 0.f;
       }
 #pragma unroll
   for (int u = 0; u < TSTL; ++u) {
@@ -289,7 +279,6 @@ __global__ __launch_bounds__(256) void k_trailing_lp_ps(int N, int nb,
                                                         const int32_t *__restrict__ panel_k0,
                                                         int slot) {
   __shared__ float s_buf[2 * TT * TSL1];
-  float(*s_t)[TT + 1] = reinterpret_cast<float(*)[TT + 1]>(s_buf);
   float *s_w = s_buf, *s_l = s_buf + TT * TSL1;
   if (slot >= st->npanel) return;
   const int k0 = panel_k0[slot], kend = panel_k0[slot + 1];
@@ -399,7 +388,6 @@ __global__ __launch_bounds__(256) void k_trailing_lp_ps(int N, int nb,
             acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av[a], bv[b], acc[a][b], 0, 0, 0);
       }
     }
-    __syncthreads();  // the staging buffer becomes the transpose tile
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -408,18 +396,8 @@ __global__ __launch_bounds__(256) void k_trailing_lp_ps(int N, int nb,
         for (int r = 0; r < 4; ++r) {
           const int c = wc + a * 16 + 4 * l4 + r;
           const int i = wi + b * 16 + l16;
-          if (c < N && i < N && (!diag || i >= c)) {
-            const float v = xv[a][b][r] - acc[a][b][r];
-            Y[(size_t)i + (size_t)c * ld] = v;
-            s_t[c - c0][i - i0] = v;
-          }
+          if (c < N && i < N && (!diag || i >= c)) Y[(size_t)i + (size_t)c * ld] = xv[a][b][r] - acc[a][b][r];
         }
-    __syncthreads();
-    for (int e = tid; e < TT * TT; e += 256) {
-      const int cl = e & (TT - 1), il = e >> 6;
-      const int c = c0 + cl, i = i0 + il;
-      if (c < N && i < N && i > c && (!diag || il >= cl)) Y[(size_t)c + (size_t)i * ld] = s_t[cl][il];
-    }
   }
 }
 

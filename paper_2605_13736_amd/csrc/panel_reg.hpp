@@ -32,6 +32,14 @@
 namespace mds {
 namespace panel {
 
+// Entry (r, c) of the symmetric trailing matrix, of which only the lower
+// triangle is kept current: (r, c) itself when r >= c, else its mirror (c, r).
+// Offsets fit in 32 bits (N <= 20480).
+template <typename TX>
+__device__ inline TX sym_at(const TX *X, int r, int c, int ld) {
+  return X[(r >= c) ? r + c * ld : c + r * ld];
+}
+
 __device__ inline void amax_combine(double &v, int &i, double v2, int i2) {
   if (v2 > v || (v2 == v && i2 < i)) {
     v = v2;
@@ -159,7 +167,7 @@ __device__ inline void panel_reg_dev(int N, int nb, double alpha,
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         const int rho = k0 + tid + T * r;
-        if (pos[r] >= k && k + 1 < N) pre1[r] = X[rho + sc1 * ld];
+        if (pos[r] >= k && k + 1 < N) pre1[r] = sym_at(X, rho, sc1, ld);
       }
     }
     // ---- updated column k and its largest off-diagonal magnitude -----------
@@ -229,8 +237,8 @@ __device__ inline void panel_reg_dev(int N, int nb, double alpha,
         const int rho = k0 + tid + T * r;
         wic[r] = 0.0;
         if (pos[r] >= k) {
-          wic[r] = (double)X[rho + src_i * ld];
-          if (k + 2 < N) pre2[r] = X[rho + src_k2 * ld];
+          wic[r] = (double)sym_at(X, rho, src_i, ld);
+          if (k + 2 < N) pre2[r] = sym_at(X, rho, src_k2, ld);
         }
         if (pos[r] == imax) {
           own = true;
