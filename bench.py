@@ -44,8 +44,8 @@ FP32_MFMA_PEAK_TFS = 157.3
 # the counters of a 256 MiB copy (the profile file gives the commands and the
 # factors); valid for the kernel source and workload as profiled.
 MEASURED_TRAFFIC = {
-    ("k_bk_trailing", 16384): (None, "profiles/bk_trailing_kkt_n16384.md"),
-    ("k_bk_trailing", 4096): (75934233.0, "profiles/bk_trailing_ipm_newton_step_n4096.md"),
+    ("k_bk_trailing", 16384): (858823869.7, "profiles/bk_trailing_kkt_n16384.md"),
+    ("k_bk_trailing", 4096): (None, "profiles/bk_trailing_ipm_newton_step_n4096.md"),
     ("k_bk_panel_coop", 4096): (2742650.0, "profiles/bk_panel_coop_ipm_newton_step_n4096.md"),
 }
 KERNEL_OF_CLASS = {"panel_tail": "k_bk_panel_reg", "trailing": "k_bk_trailing",
@@ -69,14 +69,14 @@ def panel_bytes_per_launch(N, launches_per_factor, adv=None):
     return 4.0 * 8.0 * (K * N - K * (K - 1) / 2.0) / n
 
 
-def trailing_bytes_per_launch(N, w):
+def trailing_bytes_per_launch(N, w, elem=8.0):
     """Algorithmic bytes of one trailing update (panels of width w): read and
-    write the lower trailing triangle, write its mirror, read the L and W
-    panels."""
+    write the lower trailing triangle (elem bytes per entry: 8 in FP64, 4 in
+    FP32 storage), read the L and W panels (FP64)."""
     total, cnt, k0 = 0.0, 0, 0
     while k0 + w < N:
         n = N - (k0 + w)
-        total += (n * (n + 1) / 2) * 8.0 * 3 + 2.0 * n * w * 8.0
+        total += (n * (n + 1) / 2) * elem * 2 + 2.0 * n * w * 8.0
         cnt += 1
         k0 += w
     return total / max(cnt, 1)
@@ -161,53 +161,60 @@ def kkt_step_section(args):
     tim = S.get_timings()
     S.set_timing(False)
     log("per-class device time:", json.dumps(tim))
+    # pivot statistics of the last factorization and the exchange floor of
+    # the cooperative panel at its first panels' width (outside the timed
+    # regions)
+    pstats = S.panel_stats()
+    P = min(32, (N + 1023) // 1024)
+    xfloor = dict(P=P, first_exchange_us=S.probe_exchange(P, 2000, 69),
+                  second_exchange_us=S.probe_exchange(P, 2000, 16),
+                  words=dict(first=69, second=16), rounds=2000)
     out = dict(N=N, dt=dt, facs=facs, solves=solves, value=value, tim=tim, efacs=efacs,
-               dte=dte, info=info0, eta=ri["eta"], inertia=inn, x64=x64)
+               dte=dte, info=info0, eta=ri["eta"], inertia=inn, x64=x64, pstats=pstats,
+               xfloor=xfloor)
     del S
     torch.cuda.empty_cache()
     return out, prob, st
 
 
-def roofline_of(tim, efacs, N, nb):
-    """Dominant kernel class of the event region and its roofline figure."""
-    dom = max(tim, key=lambda k: tim[k]["ms"])
-    nlaunch = max(tim[dom]["launches"], 1)
-    avg_s = tim[dom]["ms"] / 1e3 / nlaunch
+def roofline_of(tim, efacs, N, nb, pstats=None, xfloor=None):
+    """The factorization, the step's dominant work (cooperative panel, its
+    register tail and the trailing updates), against FP64 MFMA; inside it the
+    trailing update against HBM (its own roofline, with the counter traffic)
+    and the panel's latency model (microseconds per pivot step against the
+    measured exchange round trip)."""
+    fac_ms = (tim["panel"]["ms"] + tim["panel_tail"]["ms"] + tim["trailing"]["ms"]) / max(efacs, 1)
+    factor_tfs = (N ** 3 / 3.0) / (fac_ms / 1e3) / 1e12
     npan = tim["panel"]["launches"] + tim["panel_tail"]["launches"]
     w = N / max(npan / max(efacs, 1), 1)
-    if dom == "trailing":
-        kernel = "k_bk_trailing"
-        per_launch = trailing_bytes_per_launch(N, w)
-        roof = dict(bound="hbm", achieved=per_launch / avg_s / 1e9, peak=HBM_PEAK_GBS,
-                    unit="GB/s", kernel=kernel, bytes_per_launch=per_launch,
-                    flops_per_launch=trailing_flops_per_launch(N, w))
-    elif dom == "panel":
-        kernel = "k_bk_panel_coop"
-        tail = tim["panel_tail"]["launches"] > 0
-        per_launch = panel_bytes_per_launch(N, tim["panel"]["launches"] / max(efacs, 1),
-                                            adv=max(nb - 1, 1) if tail else None)
-        roof = dict(bound="hbm", achieved=per_launch / avg_s / 1e9, peak=HBM_PEAK_GBS,
-                    unit="GB/s", kernel=kernel, bytes_per_launch=per_launch,
-                    note="bound by the latency of the per-pivot chain; see latency_model")
-    else:
-        kernel = KERNEL_OF_CLASS[dom]
-        per_launch = 2.0 * (N * N / 2.0) * 8.0 if dom == "solve" else 8.0 * N * N
-        roof = dict(bound="hbm", achieved=per_launch / avg_s / 1e9, peak=HBM_PEAK_GBS,
-                    unit="GB/s", kernel=kernel, bytes_per_launch=per_launch)
-    roof["frac"] = roof["achieved"] / roof["peak"]
-    meas = MEASURED_TRAFFIC.get((kernel, N))
-    roof["traffic"] = meas[0] if meas else None
-    if meas:
-        roof["traffic_source"] = meas[1]
-    roof["avg_launch_us"] = avg_s * 1e6
-    roof["launches"] = nlaunch
-    return roof
+    trl = tim["trailing"]
+    nl = max(trl["launches"], 1)
+    avg_s = trl["ms"] / 1e3 / nl
+    per_launch = trailing_bytes_per_launch(N, w)
+    meas = MEASURED_TRAFFIC.get(("k_bk_trailing", N))
+    trailing = dict(kernel="k_bk_trailing_ps", bound="hbm", achieved=per_launch / avg_s / 1e9,
+                    peak=HBM_PEAK_GBS, unit="GB/s", frac=per_launch / avg_s / 1e9 / HBM_PEAK_GBS,
+                    traffic=meas[0] if meas else None, bytes_per_launch=per_launch,
+                    flops_per_launch=trailing_flops_per_launch(N, w),
+                    avg_launch_us=avg_s * 1e6, launches=nl, ms_per_factorization=trl["ms"] / max(efacs, 1))
+    if meas and meas[0] is not None:
+        trailing["traffic_source"] = meas[1]
+        trailing["traffic_over_algorithmic"] = meas[0] / per_launch
+    return dict(bound="mfma", kernel="factorization (k_bk_panel_coop, k_bk_panel_reg tail, "
+                                     "k_bk_trailing_ps)",
+                achieved=factor_tfs, peak=FP64_MFMA_PEAK_TFS, unit="TFLOP/s",
+                frac=factor_tfs / FP64_MFMA_PEAK_TFS, traffic=None,
+                flops_per_launch=N ** 3 / 3.0, avg_launch_us=fac_ms * 1e3, launches=efacs,
+                trailing=trailing, panel=panel_latency_model(tim, efacs, N, nb, pstats, xfloor))
 
 
-def panel_latency_model(tim, efacs, N, nb):
-    """Microseconds per pivot of the cooperative panel and of its register
-    tail (a latency-bound chain: one or two grid-wide exchanges and one
-    dependent column read per pivot)."""
+def panel_latency_model(tim, efacs, N, nb, pstats=None, xfloor=None):
+    """Microseconds per pivot step of the cooperative panel and of its
+    register tail (a latency-bound chain: one or two grid-wide exchanges and
+    one dependent column read per step), and, with the pivot statistics and
+    the measured exchange round trip, the floor that the exchanges alone set
+    (first exchange every step, the second on the steps whose first test
+    fails)."""
     out = {}
     for cls in ("panel", "panel_tail"):
         n = tim[cls]["launches"]
@@ -215,6 +222,18 @@ def panel_latency_model(tim, efacs, N, nb):
             out[cls] = dict(us_per_launch=tim[cls]["ms"] * 1e3 / n,
                             us_per_pivot=tim[cls]["ms"] * 1e3 / n / max(nb - 1, 1),
                             launches_per_factorization=n / max(efacs, 1))
+    if pstats and pstats.get("coop_steps") and tim["panel"]["launches"]:
+        per_fac = tim["panel"]["launches"] / max(efacs, 1)
+        steps_per_launch = pstats["coop_steps"] / per_fac
+        us_step = tim["panel"]["ms"] * 1e3 / tim["panel"]["launches"] / steps_per_launch
+        f2 = pstats["coop_second"] / pstats["coop_steps"]
+        m = dict(steps_per_factorization=pstats["coop_steps"], second_exchange_frac=f2,
+                 us_per_step=us_step, n2x2=pstats["n2x2"])
+        if xfloor:
+            floor = xfloor["first_exchange_us"] + f2 * xfloor["second_exchange_us"]
+            m.update(exchange_floor_us_per_step=floor, step_over_floor=us_step / floor,
+                     probe=xfloor)
+        out["coop_model"] = m
     return out
 
 
@@ -321,6 +340,11 @@ def opf_section(steps=10, warmup=2):
         efacs += step()["trials"]
     tim = S.get_timings()
     S.set_timing(False)
+    pstats = S.panel_stats()
+    P = (N + 1023) // 1024
+    xfloor = dict(P=P, first_exchange_us=S.probe_exchange(P, 2000, 69),
+                  second_exchange_us=S.probe_exchange(P, 2000, 16),
+                  words=dict(first=69, second=16), rounds=2000)
     fac_ms = (tim["panel"]["ms"] + tim["panel_tail"]["ms"] + tim["trailing"]["ms"]) / max(efacs, 1)
     # whole IPM
     r = S.ipm_solve()
@@ -335,7 +359,7 @@ def opf_section(steps=10, warmup=2):
                tflops=(facs * N ** 3 / 3.0 + solves * 2.0 * N ** 2) / dt / 1e12,
                factor_ms=fac_ms, factor_tflops=(N ** 3 / 3.0) / (fac_ms / 1e3) / 1e12,
                kernel_ms_per_step={k: v["ms"] / steps for k, v in tim.items()},
-               panel_latency=panel_latency_model(tim, efacs, N, S.info()["nb"]),
+               panel_latency=panel_latency_model(tim, efacs, N, S.info()["nb"], pstats, xfloor),
                whole_ipm=dict(status=r["status"], iters=r["iters"], seconds=t_ipm,
                               solves_per_s=1.0 / t_ipm, final_E0=last["E0"],
                               last_step_eta=r["trace"][r["iters"] - 1]["eta"]))
@@ -735,7 +759,7 @@ def main():
                                "1e-8..1e8, FP64 refinement to backward error 1e-14, "
                                "seeded synthetic", "N": N, "nb": nb,
                    "panel": h["info"]["panel"], "precision": "fp64"},
-        "roofline": roofline_of(tim, efacs, N, nb),
+        "roofline": roofline_of(tim, efacs, N, nb, h.get("pstats"), h.get("xfloor")),
         "factor": {"ms_per_factorization": fac_ms, "tflops": factor_tfs,
                    "bound": "mfma", "peak_tflops": FP64_MFMA_PEAK_TFS,
                    "frac_fp64_mfma_peak": factor_tfs / FP64_MFMA_PEAK_TFS,
@@ -743,7 +767,7 @@ def main():
                    "eta": h["eta"],
                    "inertia": [h["inertia"]["npos"], h["inertia"]["nzero"], h["inertia"]["nneg"]]},
         "kernel_ms_per_step": {k: v["ms"] / args.steps for k, v in tim.items()},
-        "panel_latency": panel_latency_model(tim, efacs, N, nb),
+        "panel_latency": panel_latency_model(tim, efacs, N, nb, h.get("pstats"), h.get("xfloor")),
         "event_region": {"steps": args.steps, "ms_per_step": h["dte"] / args.steps * 1e3,
                          "factorizations": efacs},
     }

@@ -509,6 +509,26 @@ typedef struct {
 } mds_fallbacks;
 int mds_get_fallbacks(const mds_handle *h, mds_fallbacks *out_host);
 
+/* Pivot statistics of the last factorization (host): panels, steps of the
+ * cooperative panel and how many of them took its second exchange (the
+ * candidate column, when the first Bunch-Kaufman test of Sec. 2.3 fails),
+ * and 2x2 pivots.  Synchronizes. */
+typedef struct {
+  int32_t panels, coop_steps, coop_second, n2x2;
+} mds_panel_stats;
+int mds_get_panel_stats(mds_handle *h, mds_panel_stats *out_host);
+
+/* Latency probe of the cooperative panel's exchange (the floor of its
+ * per-pivot chain): P workgroups (1..32) of 512 threads run `rounds`
+ * exchanges in which every workgroup publishes `words` tagged 64-bit words
+ * (1..512, P * words <= 2048) and reads every workgroup's words in one
+ * round trip, with no other work.  *us_per_round_host receives the wall
+ * time per round.  Uses the handle's exchange buffer: do not overlap it with
+ * a factorization on another stream.  The P workgroups must be resident at
+ * once (else MDS_EHIP after the bounded wait).  Synchronizes. */
+int mds_probe_exchange(mds_handle *h, int32_t P, int32_t rounds, int32_t words,
+                       double *us_per_round_host);
+
 /* Test hook for the failure paths, in the spirit of fault injection from the
  * host: flag MDS_DEBUG_COOP_ABORT makes every later cooperative panel launch
  * report an expired exchange wait at once (each workgroup leaves before its

@@ -104,6 +104,11 @@ class NlpModel(C.Structure):
                 ("constraints", NLP_VEC), ("jacobian", NLP_JAC), ("hessian", NLP_HESS)]
 
 
+class PanelStats(C.Structure):
+    _fields_ = [("panels", C.c_int32), ("coop_steps", C.c_int32), ("coop_second", C.c_int32),
+                ("n2x2", C.c_int32)]
+
+
 class NlpStats(C.Structure):
     _fields_ = [("soc_trials", C.c_int32), ("soc_accepted", C.c_int32),
                 ("resto_calls", C.c_int32), ("resto_iters", C.c_int32)]
@@ -194,6 +199,8 @@ SIGNATURES = {
     "mds_set_m22_diag": (C.c_int, [_vp, _vp]),
     "mds_set_sparse_blocks": (C.c_int, [_vp, C.c_int32, _ip, _vp]),
     "mds_set_nlp": (C.c_int, [_vp, C.POINTER(NlpModel)]),
+    "mds_get_panel_stats": (C.c_int, [_vp, C.POINTER(PanelStats)]),
+    "mds_probe_exchange": (C.c_int, [_vp, C.c_int32, C.c_int32, C.c_int32, _dp]),
     "mds_get_nlp_stats": (C.c_int, [_vp, C.POINTER(NlpStats)]),
     "mds_sep_model_workspace_bytes": (C.c_size_t, []),
     "mds_sep_model_create": (C.c_int, [C.POINTER(_vp), C.POINTER(Dims), C.POINTER(Problem), _vp,
@@ -566,6 +573,21 @@ class Solver:
         return dict(nb=i.nb, min_width=i.min_width, panel=("reg", "mem", "coop", "lds")[i.panel],
                     precision=prec, panel_threads=i.panel_threads,
                     workspace_bytes=i.workspace_bytes)
+
+    def panel_stats(self):
+        """Pivot statistics of the last factorization (mds_get_panel_stats)."""
+        p = PanelStats()
+        self._check(lib().mds_get_panel_stats(self.h, C.byref(p)), "mds_get_panel_stats")
+        return dict(panels=p.panels, coop_steps=p.coop_steps, coop_second=p.coop_second,
+                    n2x2=p.n2x2)
+
+    def probe_exchange(self, P, rounds=2000, words=3):
+        """Microseconds per exchange round trip of P cooperating workgroups
+        (mds_probe_exchange)."""
+        us = C.c_double()
+        self._check(lib().mds_probe_exchange(self.h, int(P), int(rounds), int(words),
+                                             C.byref(us)), "mds_probe_exchange")
+        return us.value
 
     def fallbacks(self):
         f = Fallbacks()

@@ -2072,6 +2072,38 @@ int mds_get_info(const mds_handle *h, mds_info *out) {
   return MDS_OK;
 }
 
+int mds_get_panel_stats(mds_handle *h, mds_panel_stats *out) {
+  if (!h || !out) return MDS_ENULL;
+  FacState st{};
+  HIPCHK(hipMemcpyAsync(&st, h->w.fst, sizeof(st), hipMemcpyDeviceToHost, S(h)));
+  HIPCHK(hipStreamSynchronize(S(h)));
+  out->panels = st.npanel;
+  out->coop_steps = st.csteps;
+  out->coop_second = st.cx3;
+  out->n2x2 = st.n2x2;
+  return MDS_OK;
+}
+
+int mds_probe_exchange(mds_handle *h, int32_t P, int32_t rounds, int32_t words,
+                       double *us_per_round_host) {
+  if (!h || !us_per_round_host) return MDS_ENULL;
+  if (rounds < 1 || rounds > (1 << 20)) return set_err(h, MDS_EINVAL, "rounds must be in [1, 2^20]");
+  int32_t *err = h->w.flags + 15;
+  uint64_t *out = reinterpret_cast<uint64_t *>(h->w.scal);
+  HIPCHK(hipMemsetAsync(err, 0, 4, S(h)));
+  if (bk_xch_probe(S(h), P, rounds, words, h->w.xch, err, out) != 0)
+    return set_err(h, MDS_EINVAL, "P in [1, 32], words in [1, 512], P * words <= 2048");
+  HIPCHK(hipGetLastError());
+  int32_t e = 0;
+  uint64_t ticks = 0;
+  HIPCHK(hipMemcpyAsync(&e, err, 4, hipMemcpyDeviceToHost, S(h)));
+  HIPCHK(hipMemcpyAsync(&ticks, out, 8, hipMemcpyDeviceToHost, S(h)));
+  HIPCHK(hipStreamSynchronize(S(h)));
+  if (e) return set_err(h, MDS_EHIP, "an exchange wait expired (workgroups not co-resident)");
+  *us_per_round_host = (double)ticks / 100.0 / (double)rounds;  // 100 MHz wall clock
+  return MDS_OK;
+}
+
 int mds_get_fallbacks(const mds_handle *h, mds_fallbacks *out) {
   if (!h || !out) return MDS_ENULL;
   out->coop_aborts = h->n_coop_abort;

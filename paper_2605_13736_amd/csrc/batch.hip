@@ -138,7 +138,8 @@ __device__ __attribute__((noinline)) void condense_wg(const ProbDev &P, double *
 
 // ---- trailing update: every wave takes 32 x 32 lower tiles on its own --------
 // D[c][i] = sum_t W[c, t] L[i, t]; Y(i, c) = X(src i, src c) - D[c][i] for the
-// lower tile, mirrored through the wave's LDS tile.
+// lower tile only (every reader takes entries above the diagonal from the
+// lower triangle).
 typedef __attribute__((address_space(1))) const double gdouble;
 typedef __attribute__((address_space(1))) const float gfloat;
 typedef __attribute__((address_space(1))) const int32_t gint;
@@ -164,7 +165,7 @@ __device__ __attribute__((noinline)) void trailing_wg(int N, int k0, int kend, c
   const int nt = (n + TW - 1) / TW;
   const int ntiles = nt * (nt + 1) / 2;
   const size_t ld = (size_t)N;
-  double(*t)[TW + 1] = s_t + wv * TW;
+  (void)s_t;
   for (int x = wv; x < ntiles; x += NWAVE) {
     int ti = (int)((sqrt(8.0 * (double)x + 1.0) - 1.0) * 0.5);
     while ((ti + 1) * (ti + 2) / 2 <= x) ++ti;
@@ -204,7 +205,8 @@ __device__ __attribute__((noinline)) void trailing_wg(int N, int k0, int kend, c
           const int si = __shfl(sidx, il), sc = __shfl(sidx, 32 + cl);
           const int c = c0 + cl, i = i0 + il;
           const bool ok = c < N && i < N && (!diag || i >= c);
-          xv[a][b][r] = ok ? X[(size_t)si + (size_t)sc * ld] : 0.0;
+          // lower triangle only: entry (max, min) of the physical indices
+          xv[a][b][r] = ok ? X[(si >= sc) ? (size_t)si + (size_t)sc * ld : (size_t)sc + (size_t)si * ld] : 0.0;
         }
     d4 acc[2][2];
 #pragma unroll
@@ -230,21 +232,8 @@ __device__ __attribute__((noinline)) void trailing_wg(int N, int k0, int kend, c
           // FP64 16 x 16 MFMA result: lane l, register r holds row l/16 + 4 r
           const int c = c0 + a * 16 + l4 + 4 * r;
           const int i = i0 + b * 16 + l16;
-          if (c < N && i < N && (!diag || i >= c)) {
-            const double v = xv[a][b][r] - acc[a][b][r];
-            Y[(size_t)i + (size_t)c * ld] = v;
-            t[c - c0][i - i0] = v;
-          }
+          if (c < N && i < N && (!diag || i >= c)) Y[(size_t)i + (size_t)c * ld] = xv[a][b][r] - acc[a][b][r];
         }
-    __builtin_amdgcn_wave_barrier();
-    __asm__ __volatile__("s_waitcnt lgkmcnt(0)" ::: "memory");
-    for (int e = lane; e < TW * TW; e += 64) {
-      const int cl = e & (TW - 1), il = e / TW;
-      const int c = c0 + cl, i = i0 + il;
-      if (c < N && i < N && i > c && (!diag || il >= cl)) Y[(size_t)c + (size_t)i * ld] = t[cl][il];
-    }
-    __builtin_amdgcn_wave_barrier();
-    __asm__ __volatile__("s_waitcnt lgkmcnt(0)" ::: "memory");
   }
 }
 
@@ -274,7 +263,7 @@ __device__ __attribute__((noinline)) void trailing_wg_lp(int N, int k0, int kend
   const int nt = (n + TW - 1) / TW;
   const int ntiles = nt * (nt + 1) / 2;
   const size_t ld = (size_t)N;
-  double(*t)[TW + 1] = s_t + wv * TW;
+  (void)s_t;
   for (int x = wv; x < ntiles; x += NWAVE) {
     int ti = (int)((sqrt(8.0 * (double)x + 1.0) - 1.0) * 0.5);
     while ((ti + 1) * (ti + 2) / 2 <= x) ++ti;
@@ -311,7 +300,7 @@ __device__ __attribute__((noinline)) void trailing_wg_lp(int N, int k0, int kend
           const int si = __shfl(sidx, il), sc = __shfl(sidx, 32 + cl);
           const int c = c0 + cl, i = i0 + il;
           const bool ok = c < N && i < N && (!diag || i >= c);
-          xv[a][b][r] = gX[(unsigned)(ok ? si + sc * N : zX)];
+          xv[a][b][r] = gX[(unsigned)(ok ? ((si >= sc) ? si + sc * N : sc + si * N) : zX)];
         }
     float av[KS][2], bv[KS][2];
 #pragma unroll
@@ -344,21 +333,8 @@ __device__ __attribute__((noinline)) void trailing_wg_lp(int N, int k0, int kend
         for (int r = 0; r < 4; ++r) {
           const int c = c0 + a * 16 + 4 * l4 + r;
           const int i = i0 + b * 16 + l16;
-          if (c < N && i < N && (!diag || i >= c)) {
-            const float v = xv[a][b][r] - acc[a][b][r];
-            oY[(unsigned)(i + c * N)] = v;
-            t[c - c0][i - i0] = (double)v;
-          }
+          if (c < N && i < N && (!diag || i >= c)) oY[(unsigned)(i + c * N)] = xv[a][b][r] - acc[a][b][r];
         }
-    __builtin_amdgcn_wave_barrier();
-    __asm__ __volatile__("s_waitcnt lgkmcnt(0)" ::: "memory");
-    for (int e = lane; e < TW * TW; e += 64) {
-      const int cl = e & (TW - 1), il = e / TW;
-      const int c = c0 + cl, i = i0 + il;
-      if (c < N && i < N && i > c && (!diag || il >= cl)) oY[(unsigned)(c + i * N)] = (float)t[cl][il];
-    }
-    __builtin_amdgcn_wave_barrier();
-    __asm__ __volatile__("s_waitcnt lgkmcnt(0)" ::: "memory");
   }
 }
 

@@ -68,6 +68,7 @@ __global__ void k_fac_reset(FacState *st, int32_t *panel_k0) {
     st->info = 0;
     st->npos = st->nzero = st->nneg = st->n2x2 = 0;
     st->xerr = 0;
+    st->csteps = st->cx3 = 0;
     panel_k0[0] = 0;
   }
 }

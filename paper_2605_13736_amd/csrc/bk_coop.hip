@@ -85,7 +85,9 @@ __global__ __launch_bounds__(T) void k_bk_panel_coop(int N, int nb, double alpha
   constexpr int X1_POS = X1_CAND + PREC;
   constexpr int X3_AII = 2 * NWV;     // after the per-wave partial maxima
   constexpr int X3_POS = X3_AII + 2;
-  constexpr int U1 = ((PMAX + 3) * NR + 63) / 64;  // row-record pairs per lane
+  // waves that read the first exchange: all of them on the wide grids
+  constexpr int XW = (PMAX >= 12) ? NWV : 1;
+  constexpr int U1 = ((PMAX + 3) * NR + 64 * XW - 1) / (64 * XW);  // row-record pairs per lane
   constexpr int U3 = (PMAX * NWV + 63) / 64;       // partial maxima per lane
   static_assert(NB % 8 == 0 && NR <= 64 && NWV <= 64, "tile");
   static_assert(X1_POS + 3 * PREC <= kCoopSlotWords && X3_POS + 6 <= kCoopSlotWords, "slot");
@@ -101,6 +103,7 @@ __global__ __launch_bounds__(T) void k_bk_panel_coop(int N, int nb, double alpha
   __shared__ double s_xwic[3];
   __shared__ double s_colmax, s_rowmax, s_aii;
   __shared__ int s_imax, s_gw, s_k0, s_abort, s_force;
+  __shared__ int s_xok[2][NWV];  // X1 poll: bit 0 all tags seen, bit 1 wait expired
   __shared__ uint32_t s_tag0;
 
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
@@ -153,12 +156,13 @@ __global__ __launch_bounds__(T) void k_bk_panel_coop(int N, int nb, double alpha
   __syncthreads();
 
   int k = k0, j = 0, c = 0;
-  int c_pos = 0, c_zero = 0, c_neg = 0, c_2x2 = 0, first_zero = 0;
+  int c_pos = 0, c_zero = 0, c_neg = 0, c_2x2 = 0, first_zero = 0, nsteps = 0;
   int pj = -1;
   bool p2 = false;
   double pA0 = 0.0, pB0 = 0.0, pA1 = 0.0;
 
   while (j < nb - 1 && k < N) {
+    ++nsteps;
     if (tid == 0 && pj >= 0) {
       s_cA[pj] = pA0;
       s_cB[pj] = pB0;
@@ -241,7 +245,13 @@ __global__ __launch_bounds__(T) void k_bk_panel_coop(int N, int nb, double alpha
     }
     __syncthreads();
 
-    // ---- X1: publish, then read every workgroup's (wave 0) ------------------
+    // ---- X1: publish (wave 0), then every wave reads its share ----------------
+    const int par = c & 1;
+    const uint32_t tag = tagb + (uint32_t)c;
+    // owners of the rows at positions k, k+1, k+2 (-1: past N)
+    const int o0 = owner(s_map[k - k0]);
+    const int o1 = (k + 1 < N) ? owner(s_map[k + 1 - k0]) : -1;
+    const int o2 = (k + 2 < N) ? owner(s_map[k + 2 - k0]) : -1;
     if (wid == 0) {
       double cv = -1.0;
       int ci = INT_MAX, cw = 0;
@@ -251,44 +261,46 @@ __global__ __launch_bounds__(T) void k_bk_panel_coop(int N, int nb, double alpha
         cw = lane;
       }
       wave::amax(cv, ci, cw);  // every lane: lanes <= NB publish the winner's row
-      const int par = c & 1;
-      const uint32_t tag = tagb + (uint32_t)c;
       uint64_t *mine = slot(par, g);
       if (lane == 0) {
         put_u32(mine, (uint32_t)ci, tag);
         put_f64(mine + 1, cv, tag);
       }
       if (lane < NR) put_f64(mine + X1_CAND + 2 * lane, s_crow[cw][lane], tag);
-      // owners of the rows at positions k, k+1, k+2 (-1: past N)
-      const int o0 = owner(s_map[k - k0]);
-      const int o1 = (k + 1 < N) ? owner(s_map[k + 1 - k0]) : -1;
-      const int o2 = (k + 2 < N) ? owner(s_map[k + 2 - k0]) : -1;
       if (lane < NR) {
         if (o0 == g) put_f64(mine + X1_POS + 2 * lane, s_prow[0][lane], tag);
         if (o1 == g) put_f64(mine + X1_POS + PREC + 2 * lane, s_prow[1][lane], tag);
         if (o2 == g) put_f64(mine + X1_POS + 2 * PREC + 2 * lane, s_prow[2][lane], tag);
       }
-      // one round trip reads all: headers in lanes < P, row records spread
-      // over the wave (pair p = lane + 64 u: record p / NR, word p % NR).
-      // Every lane issues every load (a lane with nothing to read loads its
-      // own slot's first word and ignores it), so the loads leave back to
-      // back and one wait covers them.
-      const uint64_t *hp = slot(par, lane < P ? lane : g);
+    }
+    // One round trip reads all: the headers in wave 0's lanes < P, the row
+    // records spread over the XW reading waves (pair p = lane + 64 (wid + XW
+    // u): record p / NR, word p % NR).  Every lane issues every load (a lane
+    // with nothing to read loads its own slot's first word and ignores it),
+    // so the loads leave back to back and one wait covers them.  With one
+    // reading wave its ballot decides; with all waves reading (the wide
+    // grids, where one wave's U1 pairs next to its register tile would spill
+    // to scratch) the waves agree through LDS after each poll
+    // (double-buffered by poll parity): done when every wave saw all its
+    // tags, time-out when any wave's wait expired.
+    if (wid < XW) {
+      const uint64_t *hp = slot(par, (wid == 0 && lane < P) ? lane : g);
       const uint64_t *ap[U1];
       bool need[U1];
 #pragma unroll
       for (int u = 0; u < U1; ++u) {
-        const int p = lane + 64 * u, rec = p / NR, w = p % NR;
+        const int p = lane + 64 * (wid + XW * u), rec = p / NR, w = p % NR;
         const int ip = rec - P, op = (ip == 0) ? o0 : (ip == 1) ? o1 : o2;
         need[u] = rec < P || (ip < 3 && op >= 0);
         ap[u] = (rec < P) ? slot(par, rec) + X1_CAND + 2 * w
                 : (ip < 3 && op >= 0) ? slot(par, op) + X1_POS + ip * PREC + 2 * w
                 : slot(par, g);
       }
+      const bool hneed = (wid == 0) && (lane < P);
       uint64_t h0, h1, h2, whi[U1], wlo[U1];
       const uint64_t t0 = wall_clock64();
       bool done = false;
-      for (;;) {
+      for (int it = 0;; ++it) {
         h0 = get_w(hp);
         h1 = get_w(hp + 1);
         h2 = get_w(hp + 2);
@@ -299,26 +311,52 @@ __global__ __launch_bounds__(T) void k_bk_panel_coop(int N, int nb, double alpha
         }
         // branch-free checks: every load is consumed on every path, so no
         // later wait mistakes one of them for an outstanding one
-        bool ok = (lane >= P) | (tag_ok(h0, tag) & tag_ok(h1, tag) & tag_ok(h2, tag));
+        bool ok = (!hneed) | (tag_ok(h0, tag) & tag_ok(h1, tag) & tag_ok(h2, tag));
 #pragma unroll
         for (int u = 0; u < U1; ++u) ok = ok & ((!need[u]) | (tag_ok(whi[u], tag) & tag_ok(wlo[u], tag)));
-        if (__ballot(!ok) == 0) {
-          done = true;
-          break;
+        const bool wok = __ballot(!ok) == 0;
+        const bool expired = wall_clock64() - t0 > kCoopWaitTicks;
+        if constexpr (XW == 1) {
+          if (wok) {
+            done = true;
+            break;
+          }
+          if (expired) break;
+        } else {
+          if (lane == 0) s_xok[it & 1][wid] = (wok ? 1 : 0) | (expired ? 2 : 0);
+          __syncthreads();
+          int all = 1, any_exp = 0;
+#pragma unroll
+          for (int q = 0; q < XW; ++q) {
+            const int v = s_xok[it & 1][q];
+            all &= v;
+            any_exp |= v >> 1;
+          }
+          if (all & 1) {
+            done = true;
+            break;
+          }
+          if (any_exp) break;
         }
-        if (wall_clock64() - t0 > kCoopWaitTicks) break;
       }
       if (!done) {
-        if (lane == 0) {
+        if (tid == 0) {
           __hip_atomic_store(&st->xerr, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           s_abort = 1;
         }
       } else {
 #pragma unroll
         for (int u = 0; u < U1; ++u) {
-          const int p = lane + 64 * u, rec = p / NR, w = p % NR;
+          const int p = lane + 64 * (wid + XW * u), rec = p / NR, w = p % NR;
           if (rec < P + 3) s_xb[rec][w] = need[u] ? as_f64(whi[u], wlo[u]) : 0.0;
         }
+      }
+      if constexpr (XW == 1) {
+        lds_wave_sync();
+      } else {
+        __syncthreads();
+      }
+      if (!s_abort && wid == 0) {
         double gv = -1.0;
         int gi = INT_MAX, gw = 0;
         if (lane < P) {
@@ -331,7 +369,6 @@ __global__ __launch_bounds__(T) void k_bk_panel_coop(int N, int nb, double alpha
           gv = 0.0;
           gi = k;
         }
-        lds_wave_sync();
         // W row of imax from its L row (used when the first test fails)
         if (lane < NB)
           s_wi[lane] = w_lane<NB>(&s_xb[gw][1], s_cA, s_cB, s_cC, lane, 0, false, false, 0.0,
@@ -650,7 +687,83 @@ __global__ __launch_bounds__(T) void k_bk_panel_coop(int N, int nb, double alpha
     st->n2x2 += c_2x2;
     if (st->info == 0 && first_zero != 0) st->info = first_zero;
     st->xtag = s_tag0 + 1u;
+    // every step takes the first exchange; c counts both
+    st->csteps += nsteps;
+    st->cx3 += c - nsteps;
   }
+}
+
+// Exchange probe: P workgroups of T threads run `rounds` exchanges of the
+// cooperative panel's kind with no other work.  In each round every
+// workgroup's wave 0 publishes `words` tagged words; then all waves read every
+// workgroup's words in one round trip (word q = thread + T u of the P *
+// words), polling until every tag matches, and agree through LDS as the
+// panel's first exchange does.  Tags are 1..255 in the low bits with zero
+// launch bits, which no panel launch uses, so stale probe words are never
+// taken for panel data.  out[0] = wall-clock ticks (100 MHz) of workgroup 0
+// over all rounds; *err = 1 when a wait expired (every workgroup then
+// leaves).
+template <int T, int U>
+__global__ __launch_bounds__(T) void k_xch_probe(int P, int rounds, int words,
+                                                 uint64_t *__restrict__ xch,
+                                                 int32_t *__restrict__ err,
+                                                 uint64_t *__restrict__ out) {
+  constexpr int NWV = T / 64;
+  __shared__ int s_ok[2][NWV];
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6, g = blockIdx.x;
+  auto slot = [&](int par, int wg) { return xch + (size_t)(par * kCoopMaxP + wg) * kCoopSlotWords; };
+  const uint64_t t_start = wall_clock64();
+  int it = 0;
+  for (int e = 0; e < rounds; ++e) {
+    const int par = e & 1;
+    const uint32_t tag = (uint32_t)(e % 255) + 1u;
+    uint64_t *mine = slot(par, g);
+    if (wid == 0)
+      for (int w = lane; w < words; w += 64) put_u32(mine + w, (uint32_t)(w + e), tag);
+    const uint64_t *ap[U];
+    bool need[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int q = tid + T * u, rec = q / words, w = q % words;
+      need[u] = rec < P;
+      ap[u] = need[u] ? slot(par, rec) + w : mine;
+    }
+    uint64_t v[U];
+    const uint64_t t0 = wall_clock64();
+    bool done = false;
+    for (;; ++it) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) v[u] = get_w(ap[u]);
+      bool ok = true;
+#pragma unroll
+      for (int u = 0; u < U; ++u) ok = ok & ((!need[u]) | tag_ok(v[u], tag));
+      const bool wok = __ballot(!ok) == 0;
+      const bool expired = wall_clock64() - t0 > kCoopWaitTicks;
+      if (lane == 0) s_ok[it & 1][wid] = (wok ? 1 : 0) | (expired ? 2 : 0);
+      __syncthreads();
+      int all = 1, any_exp = 0;
+#pragma unroll
+      for (int q = 0; q < NWV; ++q) {
+        const int x = s_ok[it & 1][q];
+        all &= x;
+        any_exp |= x >> 1;
+      }
+      if (all & 1) {
+        done = true;
+        ++it;
+        break;
+      }
+      if (any_exp) {
+        ++it;
+        break;
+      }
+    }
+    if (!done) {
+      if (tid == 0) __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return;
+    }
+  }
+  if (g == 0 && tid == 0) out[0] = wall_clock64() - t_start;
 }
 
 // Variants: (threads, rows per thread, register tile, most workgroups)
@@ -712,6 +825,16 @@ static void panel_coop(hipStream_t s, int rows, int N, int nb, double alpha, con
   else if (P <= 12) MDS_COOP(12);
   else MDS_COOP(kCoopP);
 #undef MDS_COOP
+}
+
+int bk_xch_probe(hipStream_t s, int P, int rounds, int words, uint64_t *xch, int32_t *err,
+                 uint64_t *out) {
+  constexpr int U = 4;  // words read per thread: P * words <= 4 * 512
+  if (P < 1 || P > kCoopMaxP || words < 1 || words > kCoopSlotWords || P * words > U * kCoopT ||
+      rounds < 1)
+    return -1;
+  k_xch_probe<kCoopT, U><<<P, kCoopT, 0, s>>>(P, rounds, words, xch, err, out);
+  return 0;
 }
 
 void launch_bk_panel_coop(hipStream_t s, int rows, int N, int nb, double alpha, const double *X,

@@ -48,6 +48,8 @@ struct FacState {
   uint32_t xtag;  // cooperative panel: launch counter behind its exchange tags (never reset)
   int32_t xerr;   // cooperative panel: an exchange wait expired
   int32_t xforce; // host-set test flag: cooperative launches report an expired wait at once
+  int32_t csteps; // cooperative panel: pivot steps of this factorization
+  int32_t cx3;    // ... of which took the second exchange (the candidate column)
 };
 
 // Pointers into the caller's workspace.
@@ -249,6 +251,10 @@ bool bk_coop_resident(int N);
 int bk_coop_nb();
 int bk_coop_wgs(int N);
 // rows: at least the rows left at the panel's start (sizes the grid)
+// Exchange round-trip probe of the cooperative panel (P <= kCoopMaxP workgroups,
+// words <= kCoopSlotWords per workgroup, P * words <= 2048); -1: bad sizes.
+int bk_xch_probe(hipStream_t s, int P, int rounds, int words, uint64_t *xch, int32_t *err,
+                 uint64_t *out);
 void launch_bk_panel_coop(hipStream_t s, int rows, int N, int nb, double alpha, const double *X,
                           double *Lout, int32_t *src_out, double *W, double *dd, double *ds,
                           int32_t *ipiv, int32_t *blk, FacState *st, int32_t *panel_k0,

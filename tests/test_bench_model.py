@@ -27,9 +27,13 @@ def test_panel_bytes_sum_over_columns(N, nb):
 
 
 def test_trailing_bytes_small_case():
-    # N = 10, panels of width 4: trailing matrices of order 6 and 2
+    # N = 10, panels of width 4: trailing matrices of order 6 and 2; the
+    # lower triangle is read and written (no mirror), L and W read once
     got = bench.trailing_bytes_per_launch(10, 4)
     tot = 0.0
     for n in (6, 2):
-        tot += 24.0 * n * (n + 1) / 2 + 2 * 8.0 * n * 4
+        tot += 16.0 * n * (n + 1) / 2 + 2 * 8.0 * n * 4
     assert got == pytest.approx(tot / 2)
+    got32 = bench.trailing_bytes_per_launch(10, 4, elem=4.0)
+    tot32 = sum(8.0 * n * (n + 1) / 2 + 2 * 8.0 * n * 4 for n in (6, 2))
+    assert got32 == pytest.approx(tot32 / 2)
