@@ -586,7 +586,9 @@ def warmstart_section(n_train, n_held, hidden=1024, steps=2000, lr=1e-3, noise=0
     base = synth.config_problem(synth.OPF_N4096)
     t0 = time.perf_counter()
     train = [synth.family_member(base, p) for p in range(n_train)]
-    X, T, cold_train_iters, _ = warmstart.solve_family(train, time_budget_s=data_budget_s)
+    X, T, cold_train_iters, _ = warmstart.solve_family(
+        train, time_budget_s=data_budget_s,
+        progress=lambda k, t: log(f"warm start: {k} training solves in {t:.0f} s"))
     t_data = time.perf_counter() - t0
     ws = warmstart.WarmStart(base["m"], base["n_d"], hidden=hidden, max_batch=256)
     torch.cuda.synchronize()
@@ -597,6 +599,8 @@ def warmstart_section(n_train, n_held, hidden=1024, steps=2000, lr=1e-3, noise=0
     S = mds.solver_for(base)
     cold_it, warm_it, cold_t, warm_t, fb, err = [], [], [], [], 0, 0.0
     for p in range(n_held):
+        if p and p % 10 == 0:
+            log(f"warm start: {p} of {n_held} held-out problems")
         q = synth.family_member(base, 10 ** 6 + p)
         S.P["b"].copy_(S.dev(q["b"]))
         torch.cuda.synchronize()
@@ -711,6 +715,8 @@ def main():
     ap.add_argument("--ws-budget", type=float, default=60.0,
                     help="seconds of cold solves that generate warm-start training data")
     ap.add_argument("--ws-held", type=int, default=16)
+    ap.add_argument("--warmstart-only", action="store_true",
+                    help="run only the learned warm-start section and print it")
     ap.add_argument("--calib-copy", action="store_true",
                     help="only run a plain 256 MiB device copy (calibrates HBM counters)")
     args = ap.parse_args()
@@ -739,6 +745,10 @@ def main():
         N = prob["n_d"] + prob["m"]
         print(json.dumps({"precision_sweep": precision_sweep(prob, st, N, reps=args.steps,
                                                              precs=(args.sweep_precision,))}))
+        return
+    if args.warmstart_only:
+        print(json.dumps({"warmstart": warmstart_section(args.ws_train, args.ws_held,
+                                                         data_budget_s=args.ws_budget)}))
         return
     if args.opf_only:
         print(json.dumps({"opf_n4096": opf_section(args.steps, args.warmup)[0]}))

@@ -40,6 +40,7 @@
 #include <climits>
 
 #include "internal.hpp"
+#include "tile_order.hpp"
 #include "wave.hpp"
 
 namespace mds {
@@ -313,7 +314,7 @@ constexpr int TT = 64;
 constexpr int TS = 36;        // panel columns staged in LDS per chunk (multiple of 4)
 constexpr int TS1 = TS + 1;   // odd row stride of the staged panels
 constexpr int TSTAGE = TT * TS / 256;  // staged entries per thread and panel
-constexpr int kTrailingGrid = 256 * 2;  // persistent trailing update: workgroups (2 per CU at 194 VGPRs)
+constexpr int kTrailingGrid = kTileGrid;  // persistent trailing update: 512 workgroups (2 per CU at 194 VGPRs)
 static_assert(TT * TS % 256 == 0, "staging");
 
 // X: matrix the panel read (entry (x, c) at X[src(x) + src(c) N]); Y: output
@@ -437,21 +438,11 @@ __global__ __launch_bounds__(256) void k_bk_trailing(int N, int nb, const double
 
 // Persistent form of k_bk_trailing for panels of at most TS - 1 columns
 // (one staging chunk): a grid of a few workgroups per compute unit walks the
-// tiles (tile x, x + gridDim.x, ...), and while it computes one tile the
+// tiles in row-major triangular order, and while it computes one tile the
 // loads of its next tile (the entries it updates and the panel rows it
 // stages) are already in flight.  Per entry the arithmetic is the one of
 // k_bk_trailing, in the same order.
-__device__ inline void tr_geom(long x, int a0, int &i0, int &c0, bool &diag) {
-  int ti = (int)((sqrt(8.0 * (double)x + 1.0) - 1.0) * 0.5);
-  while ((long)(ti + 1) * (ti + 2) / 2 <= x) ++ti;
-  while ((long)ti * (ti + 1) / 2 > x) --ti;
-  const int tj = (int)(x - (long)ti * (ti + 1) / 2);
-  i0 = a0 + ti * TT;
-  c0 = a0 + tj * TT;
-  diag = (ti == tj);
-}
-
-__device__ inline void tr_load(long x, int a0, int N, int kend, int k0, int jw,
+__device__ inline void tr_load(int i0, int c0, bool diag, int N, int kend, int k0, int jw,
                                const double *__restrict__ W, const double *X,
                                const double *Lsrc, const int32_t *__restrict__ src,
                                double (&xv)[2][2][4], double (&vw)[TSTAGE],
@@ -459,9 +450,6 @@ __device__ inline void tr_load(long x, int a0, int N, int kend, int k0, int jw,
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int l16 = lane & 15, l4 = lane >> 4;
   const size_t ld = (size_t)N;
-  int i0, c0;
-  bool diag;
-  tr_geom(x, a0, i0, c0, diag);
   const int wc = c0 + (wv & 1) * 32, wi = i0 + (wv >> 1) * 32;
   int si[2], sc[2][4];
 #pragma unroll
@@ -514,18 +502,24 @@ __global__ __launch_bounds__(256) void k_bk_trailing_ps(int N, int nb,
   const int jw = kend - k0;
   const int a0 = kend & ~15;
   const int nt = (N - a0 + TT - 1) / TT;
-  const long ntiles = (long)nt * (nt + 1) / 2;
-  long x = blockIdx.x;
-  if (x >= ntiles) return;
+  // plain row-major order: measured at N = 16384, the super-tile order of
+  // tile_order.hpp cut this kernel's fetched bytes by 17% but made it 3.5%
+  // slower (188.8 against 182.4 us per launch); the FP32 update keeps it
+  const bool xcd = false;
+  const long nslots = tile_slots(nt, xcd);
   const size_t ld = (size_t)N;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int l16 = lane & 15, l4 = lane >> 4;
+  // first slot of this workgroup that holds a tile
+  long x = blockIdx.x;
+  int ti = 0, tj = 0;
+  while (x < nslots && !tile_of(x, nt, xcd, ti, tj)) x += gridDim.x;
+  if (x >= nslots) return;
   double xn[2][2][4], vwn[TSTAGE], vln[TSTAGE];
-  tr_load(x, a0, N, kend, k0, jw, W, X, Lsrc, src, xn, vwn, vln);
-  for (; x < ntiles; x += gridDim.x) {
-    int i0, c0;
-    bool diag;
-    tr_geom(x, a0, i0, c0, diag);
+  tr_load(a0 + ti * TT, a0 + tj * TT, ti == tj, N, kend, k0, jw, W, X, Lsrc, src, xn, vwn, vln);
+  while (x < nslots) {
+    const int i0 = a0 + ti * TT, c0 = a0 + tj * TT;
+    const bool diag = (ti == tj);
     const int wc = c0 + (wv & 1) * 32, wi = i0 + (wv >> 1) * 32;
     double xv[2][2][4];
 #pragma unroll
@@ -542,8 +536,13 @@ __global__ __launch_bounds__(256) void k_bk_trailing_ps(int N, int nb,
       s_l[r * TS1 + t] = vln[u];
     }
     __syncthreads();
-    const long xnext = x + gridDim.x;
-    if (xnext < ntiles) tr_load(xnext, a0, N, kend, k0, jw, W, X, Lsrc, src, xn, vwn, vln);
+    // the next slot that holds a tile, its loads in flight during this one
+    long xnext = x + gridDim.x;
+    int tin = 0, tjn = 0;
+    while (xnext < nslots && !tile_of(xnext, nt, xcd, tin, tjn)) xnext += gridDim.x;
+    if (xnext < nslots)
+      tr_load(a0 + tin * TT, a0 + tjn * TT, tin == tjn, N, kend, k0, jw, W, X, Lsrc, src, xn, vwn,
+              vln);
     d4 acc[2][2];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
@@ -573,6 +572,9 @@ __global__ __launch_bounds__(256) void k_bk_trailing_ps(int N, int nb,
           if (c >= kend && c < N && i < N && (!diag || i >= c))
             Y[(size_t)i + (size_t)c * ld] = xv[a][b][r] - acc[a][b][r];
         }
+    x = xnext;
+    ti = tin;
+    tj = tjn;
   }
 }
 

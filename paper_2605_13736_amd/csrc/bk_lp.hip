@@ -14,6 +14,7 @@
 #include <algorithm>
 
 #include "internal.hpp"
+#include "tile_order.hpp"
 
 namespace mds {
 namespace {
@@ -25,7 +26,7 @@ constexpr int TT = 64;
 constexpr int TSL = 48;        // panel columns staged in LDS per chunk (multiple of 16)
 constexpr int TSL1 = TSL + 1;  // odd row stride of the staged panels
 constexpr int TSTL = TT * TSL / 256;  // staged entries per thread and panel
-constexpr int kTrailingLpGrid = 256 * 2;  // persistent form: workgroups (2 per CU at <= 196 VGPRs)
+constexpr int kTrailingLpGrid = kTileGrid;  // persistent form: 512 workgroups (2 per CU at <= 196 VGPRs)
 static_assert(TT * TSL % 256 == 0, "staging");
 
 // round-to-nearest-even FP32 -> BF16 (finite inputs)
@@ -213,26 +214,13 @@ __global__ __launch_bounds__(256) void k_trailing_lp(int N, int nb, const double
 // (one staging chunk): a grid of a few workgroups per compute unit walks the
 // tiles, loading the next tile's entries and panel rows while it computes
 // the current one.  Per entry the arithmetic is the one of k_trailing_lp.
-__device__ inline void lp_geom(long x, int kend, int &i0, int &c0, bool &diag) {
-  int ti = (int)((sqrt(8.0 * (double)x + 1.0) - 1.0) * 0.5);
-  while ((long)(ti + 1) * (ti + 2) / 2 <= x) ++ti;
-  while ((long)ti * (ti + 1) / 2 > x) --ti;
-  const int tj = (int)(x - (long)ti * (ti + 1) / 2);
-  i0 = kend + ti * TT;
-  c0 = kend + tj * TT;
-  diag = (ti == tj);
-}
-
-__device__ inline void lp_load(long x, int N, int kend, int k0, int jw,
+__device__ inline void lp_load(int i0, int c0, bool diag, int N, int kend, int k0, int jw,
                                const double *__restrict__ W, const float *X,
                                const double *__restrict__ Lsrc, const int32_t *__restrict__ src,
                                float (&xv)[2][2][4], double (&vw)[TSTL], double (&vl)[TSTL]) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int l16 = lane & 15, l4 = lane >> 4;
   const size_t ld = (size_t)N;
-  int i0, c0;
-  bool diag;
-  lp_geom(x, kend, i0, c0, diag);
   const int wc = c0 + (wv & 1) * 32, wi = i0 + (wv >> 1) * 32;
   int si[2], sc[2][4];
 #pragma unroll
@@ -285,19 +273,22 @@ __global__ __launch_bounds__(256) void k_trailing_lp_ps(int N, int nb,
   if (kend >= N || kend <= k0 || kend - k0 > nb + 1 || kend - k0 > TSL) return;
   const int jw = kend - k0;
   const int nt = (N - kend + TT - 1) / TT;
-  const long ntiles = (long)nt * (nt + 1) / 2;
-  long x = blockIdx.x;
-  if (x >= ntiles) return;
+  const bool xcd = gridDim.x == (unsigned)kTileGrid;
+  const long nslots = tile_slots(nt, xcd);
   const size_t ld = (size_t)N;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int l16 = lane & 15, l4 = lane >> 4;
+  // first slot of this workgroup that holds a tile (order of tile_order.hpp)
+  long x = blockIdx.x;
+  int ti = 0, tj = 0;
+  while (x < nslots && !tile_of(x, nt, xcd, ti, tj)) x += gridDim.x;
+  if (x >= nslots) return;
   float xn[2][2][4];
   double vwn[TSTL], vln[TSTL];
-  lp_load(x, N, kend, k0, jw, W, X, Lsrc, src, xn, vwn, vln);
-  for (; x < ntiles; x += gridDim.x) {
-    int i0, c0;
-    bool diag;
-    lp_geom(x, kend, i0, c0, diag);
+  lp_load(kend + ti * TT, kend + tj * TT, ti == tj, N, kend, k0, jw, W, X, Lsrc, src, xn, vwn, vln);
+  while (x < nslots) {
+    const int i0 = kend + ti * TT, c0 = kend + tj * TT;
+    const bool diag = (ti == tj);
     const int wc = c0 + (wv & 1) * 32, wi = i0 + (wv >> 1) * 32;
     float xv[2][2][4];
 #pragma unroll
@@ -314,8 +305,13 @@ __global__ __launch_bounds__(256) void k_trailing_lp_ps(int N, int nb,
       s_l[r * TSL1 + t] = (float)vln[u];
     }
     __syncthreads();
-    const long xnext = x + gridDim.x;
-    if (xnext < ntiles) lp_load(xnext, N, kend, k0, jw, W, X, Lsrc, src, xn, vwn, vln);
+    // the next slot that holds a tile, its loads in flight during this one
+    long xnext = x + gridDim.x;
+    int tin = 0, tjn = 0;
+    while (xnext < nslots && !tile_of(xnext, nt, xcd, tin, tjn)) xnext += gridDim.x;
+    if (xnext < nslots)
+      lp_load(kend + tin * TT, kend + tjn * TT, tin == tjn, N, kend, k0, jw, W, X, Lsrc, src, xn,
+              vwn, vln);
     f4 acc[2][2];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
@@ -398,6 +394,9 @@ __global__ __launch_bounds__(256) void k_trailing_lp_ps(int N, int nb,
           const int i = wi + b * 16 + l16;
           if (c < N && i < N && (!diag || i >= c)) Y[(size_t)i + (size_t)c * ld] = xv[a][b][r] - acc[a][b][r];
         }
+    x = xnext;
+    ti = tin;
+    tj = tjn;
   }
 }
 

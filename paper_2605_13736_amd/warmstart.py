@@ -29,18 +29,21 @@ def mu_target(trace, level=1e-2):
     return trace[-1]["mu"]
 
 
-def solve_family(problems, device="cuda:0", time_budget_s=None):
+def solve_family(problems, device="cuda:0", time_budget_s=None, progress=None):
     """Cold IPM solves of a list of family members on one Solver (the
     matrices are shared; only b is replaced), in order, stopping early once
-    time_budget_s seconds have passed (None: no limit).  Returns X (b's),
+    time_budget_s seconds have passed (None: no limit).  progress(count,
+    seconds), when given, is called every 25 solves.  Returns X (b's),
     targets and per-problem iteration counts / solutions."""
     import time
     S = solver_for(problems[0], device=device)
     X, T, iters, xs = [], [], [], []
     t0 = time.perf_counter()
-    for q in problems:
+    for k, q in enumerate(problems):
         if time_budget_s is not None and X and time.perf_counter() - t0 > time_budget_s:
             break
+        if progress is not None and k and k % 25 == 0:
+            progress(k, time.perf_counter() - t0)
         S.P["b"].copy_(S.dev(q["b"]))
         r = S.ipm_solve()
         if r["status"] != "converged":
