@@ -45,8 +45,8 @@ FP32_MFMA_PEAK_TFS = 157.3
 # factors); valid for the kernel source and workload as profiled.
 MEASURED_TRAFFIC = {
     ("k_bk_trailing", 16384): (858823869.7, "profiles/bk_trailing_kkt_n16384.md"),
-    ("k_bk_trailing", 4096): (None, "profiles/bk_trailing_ipm_newton_step_n4096.md"),
-    ("k_bk_panel_coop", 4096): (2742650.0, "profiles/bk_panel_coop_ipm_newton_step_n4096.md"),
+    ("k_bk_trailing", 4096): (52698050.0, "profiles/bk_trailing_ipm_newton_step_n4096.md"),
+    ("k_bk_panel_coop", 4096): (3669981.0, "profiles/bk_panel_coop_ipm_newton_step_n4096.md"),
 }
 KERNEL_OF_CLASS = {"panel_tail": "k_bk_panel_reg", "trailing": "k_bk_trailing",
                    "solve": "k_trsv_fwd+k_trsv_bwd", "condense": "k_condense_dense",
@@ -715,6 +715,8 @@ def main():
     ap.add_argument("--ws-budget", type=float, default=60.0,
                     help="seconds of cold solves that generate warm-start training data")
     ap.add_argument("--ws-held", type=int, default=16)
+    ap.add_argument("--ipm-only", action="store_true",
+                    help="run only the whole-IPM section (N = 192) and print it (profiling)")
     ap.add_argument("--warmstart-only", action="store_true",
                     help="run only the learned warm-start section and print it")
     ap.add_argument("--calib-copy", action="store_true",
@@ -745,6 +747,9 @@ def main():
         N = prob["n_d"] + prob["m"]
         print(json.dumps({"precision_sweep": precision_sweep(prob, st, N, reps=args.steps,
                                                              precs=(args.sweep_precision,))}))
+        return
+    if args.ipm_only:
+        print(json.dumps({"ipm_solves": ipm_solves_section()}))
         return
     if args.warmstart_only:
         print(json.dumps({"warmstart": warmstart_section(args.ws_train, args.ws_held,
