@@ -105,6 +105,8 @@ __global__ __launch_bounds__(T) void k_bk_panel_coop(int N, int nb, double alpha
   __shared__ int s_imax, s_gw, s_k0, s_abort, s_force;
   __shared__ int s_xok[2][NWV];  // X1 poll: bit 0 all tags seen, bit 1 wait expired
   __shared__ uint32_t s_tag0;
+  __shared__ double s_pdd[NB], s_pds[NB];  // the panel's D and pivot records (written at its end)
+  __shared__ int s_pip[NB], s_pbk[NB];
 
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int g = blockIdx.x;
@@ -179,11 +181,12 @@ __global__ __launch_bounds__(T) void k_bk_panel_coop(int N, int nb, double alpha
     for (int t0 = 0; t0 < NB; t0 += 8) {
       if (t0 < j) {
         keep_branch();
-        // columns t >= j: L = 0 and the W entry forced to 0, so their
-        // products add an exact zero (no per-column branch)
+        // columns t >= j: L = 0 and the W entries are zeros too (a W row
+        // comes from an L row, which ends before column j), so their
+        // products add an exact zero (no per-column branch or select)
         double wv[8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) wv[u] = (t0 + u < j) ? s_wk[t0 + u] : 0.0;
+        for (int u = 0; u < 8; ++u) wv[u] = s_wk[t0 + u];
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
 #pragma unroll
@@ -412,11 +415,11 @@ __global__ __launch_bounds__(T) void k_bk_panel_coop(int N, int nb, double alpha
       for (int t0 = 0; t0 < NB; t0 += 8) {
         if (t0 < j) {
           keep_branch();
-          // columns t >= j: L = 0 and the W entry forced to 0, so their
-          // products add an exact zero (no per-column branch)
+          // columns t >= j: L = 0 and the W entries are zeros too, so
+          // their products add an exact zero (no per-column select)
           double wv[8];
 #pragma unroll
-          for (int u = 0; u < 8; ++u) wv[u] = (t0 + u < j) ? s_wi[t0 + u] : 0.0;
+          for (int u = 0; u < 8; ++u) wv[u] = s_wi[t0 + u];
 #pragma unroll
           for (int u = 0; u < 8; ++u) {
 #pragma unroll
@@ -558,6 +561,9 @@ __global__ __launch_bounds__(T) void k_bk_panel_coop(int N, int nb, double alpha
       if (kind == 4 && q != k + 2) an = (double)pre2[r];
       s_acur[r * T + tid] = an;
     }
+    // the step's column(s) of the register tile (j is uniform: one scalar
+    // compare per column, which every wave runs on the compute unit's shared
+    // scalar unit; the 2x2 pivot's second column only on 2x2 steps)
 #pragma unroll
     for (int t = 0; t < NB; ++t) {
       if (t == j) {
@@ -565,10 +571,16 @@ __global__ __launch_bounds__(T) void k_bk_panel_coop(int N, int nb, double alpha
 #pragma unroll
         for (int r = 0; r < R; ++r) Lr[r][t] = act[r] ? l0[r] : Lr[r][t];
       }
-      if (kind == 4 && t == j + 1) {
-        keep_branch();
+    }
+    if (kind == 4) {
+      keep_branch();
 #pragma unroll
-        for (int r = 0; r < R; ++r) Lr[r][t] = act[r] ? l1[r] : Lr[r][t];
+      for (int t = 1; t < NB; ++t) {
+        if (t == j + 1) {
+          keep_branch();
+#pragma unroll
+          for (int r = 0; r < R; ++r) Lr[r][t] = act[r] ? l1[r] : Lr[r][t];
+        }
       }
     }
 
@@ -605,27 +617,26 @@ __global__ __launch_bounds__(T) void k_bk_panel_coop(int N, int nb, double alpha
         s_map[p - k0] = s_map[q - k0];
         s_map[q - k0] = t0;
       }
+      // the pivot records go to global memory at the end of the panel: a
+      // store here would make this wave wait for its prefetch of the next
+      // column at the next write of the store's source registers
       if (kind == 4) {
-        if (g == 0) {
-          dd[k] = Da;
-          dd[k + 1] = Dc;
-          ds[k] = Db;
-          ds[k + 1] = 0.0;
-          ipiv[k] = -(q + 1);
-          ipiv[k + 1] = -(q + 1);
-          blk[k] = 2;
-          blk[k + 1] = 3;
-        }
+        s_pdd[j] = Da;
+        s_pdd[j + 1] = Dc;
+        s_pds[j] = Db;
+        s_pds[j + 1] = 0.0;
+        s_pip[j] = -(q + 1);
+        s_pip[j + 1] = -(q + 1);
+        s_pbk[j] = 2;
+        s_pbk[j + 1] = 3;
         c_pos++;
         c_neg++;
         c_2x2++;
       } else {
-        if (g == 0) {
-          dd[k] = Da;
-          ds[k] = 0.0;
-          ipiv[k] = q + 1;
-          blk[k] = 1;
-        }
+        s_pdd[j] = Da;
+        s_pds[j] = 0.0;
+        s_pip[j] = q + 1;
+        s_pbk[j] = 1;
         if (Da > 0.0) c_pos++;
         else if (Da < 0.0) c_neg++;
         else {
@@ -655,6 +666,14 @@ __global__ __launch_bounds__(T) void k_bk_panel_coop(int N, int nb, double alpha
     }
   }
   __syncthreads();
+  if (g == 0) {
+    for (int t = tid; t < jend; t += T) {
+      dd[k0 + t] = s_pdd[t];
+      ds[k0 + t] = s_pds[t];
+      ipiv[k0 + t] = s_pip[t];
+      blk[k0 + t] = s_pbk[t];
+    }
+  }
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int pr = pos[r];

@@ -93,6 +93,8 @@ __device__ inline void panel_reg_dev(int N, int nb, double alpha,
   __shared__ double s_wk[NB], s_wi[NB];            // W rows of the pivot k and of imax
   __shared__ double s_cA[NB], s_cB[NB], s_cC[NB];  // W = L D coefficients per panel column
   __shared__ double s_lrow[NB];                    // L row of imax / of the next pivot
+  __shared__ double s_pdd[NB], s_pds[NB];          // D and pivot records (written at the end)
+  __shared__ int s_pip[NB], s_pbk[NB];
   __shared__ double s_rv[NWV];
   __shared__ int s_ri[NWV];
   __shared__ double s_akk, s_aii, s_wki;
@@ -179,11 +181,12 @@ __device__ inline void panel_reg_dev(int N, int nb, double alpha,
     for (int t0 = 0; t0 < NB; t0 += 8) {
       if (t0 < j) {
         keep_branch();
-        // columns t >= j: L = 0 and the W entry forced to 0, so their
-        // products add an exact zero (no per-column branch)
+        // columns t >= j: L = 0 and the W entries are zeros too (a W row
+        // comes from an L row, which ends before column j), so their
+        // products add an exact zero (no per-column branch or select)
         double wv[8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) wv[u] = (t0 + u < j) ? s_wk[t0 + u] : 0.0;
+        for (int u = 0; u < 8; ++u) wv[u] = s_wk[t0 + u];
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
 #pragma unroll
@@ -257,11 +260,11 @@ __device__ inline void panel_reg_dev(int N, int nb, double alpha,
       for (int t0 = 0; t0 < NB; t0 += 8) {
         if (t0 < j) {
           keep_branch();
-          // columns t >= j: L = 0 and the W entry forced to 0, so their
-          // products add an exact zero (no per-column branch)
+          // columns t >= j: L = 0 and the W entries are zeros too, so
+          // their products add an exact zero (no per-column select)
           double wv[8];
 #pragma unroll
-          for (int u = 0; u < 8; ++u) wv[u] = (t0 + u < j) ? s_wi[t0 + u] : 0.0;
+          for (int u = 0; u < 8; ++u) wv[u] = s_wi[t0 + u];
 #pragma unroll
           for (int u = 0; u < 8; ++u) {
 #pragma unroll
@@ -344,6 +347,9 @@ __device__ inline void panel_reg_dev(int N, int nb, double alpha,
       if (kind == 4 && q != k + 2) an = (double)pre2[r];
       s_acur[r * T + tid] = an;
     }
+    // the step's column(s) of the register tile (j is uniform: one scalar
+    // compare per column, which every wave runs on the compute unit's shared
+    // scalar unit; the 2x2 pivot's second column only on 2x2 steps)
 #pragma unroll
     for (int t = 0; t < NB; ++t) {
       if (t == j) {
@@ -351,10 +357,16 @@ __device__ inline void panel_reg_dev(int N, int nb, double alpha,
 #pragma unroll
         for (int r = 0; r < R; ++r) Lr[r][t] = act[r] ? l0[r] : Lr[r][t];
       }
-      if (kind == 4 && t == j + 1) {
-        keep_branch();
+    }
+    if (kind == 4) {
+      keep_branch();
 #pragma unroll
-        for (int r = 0; r < R; ++r) Lr[r][t] = act[r] ? l1[r] : Lr[r][t];
+      for (int t = 1; t < NB; ++t) {
+        if (t == j + 1) {
+          keep_branch();
+#pragma unroll
+          for (int r = 0; r < R; ++r) Lr[r][t] = act[r] ? l1[r] : Lr[r][t];
+        }
       }
     }
 #pragma unroll
@@ -373,23 +385,26 @@ __device__ inline void panel_reg_dev(int N, int nb, double alpha,
         s_map[p - k0] = s_map[q - k0];
         s_map[q - k0] = t0;
       }
+      // the pivot records go to global memory at the end of the panel: a
+      // store here would make this wave wait for its prefetch of the next
+      // column at the next write of the store's source registers
       if (kind == 4) {
-        dd[k] = Da;
-        dd[k + 1] = Dc;
-        ds[k] = Db;
-        ds[k + 1] = 0.0;
-        ipiv[k] = -(q + 1);
-        ipiv[k + 1] = -(q + 1);
-        blk[k] = 2;
-        blk[k + 1] = 3;
+        s_pdd[j] = Da;
+        s_pdd[j + 1] = Dc;
+        s_pds[j] = Db;
+        s_pds[j + 1] = 0.0;
+        s_pip[j] = -(q + 1);
+        s_pip[j + 1] = -(q + 1);
+        s_pbk[j] = 2;
+        s_pbk[j + 1] = 3;
         c_pos++;
         c_neg++;
         c_2x2++;
       } else {
-        dd[k] = Da;
-        ds[k] = 0.0;
-        ipiv[k] = q + 1;
-        blk[k] = 1;
+        s_pdd[j] = Da;
+        s_pds[j] = 0.0;
+        s_pip[j] = q + 1;
+        s_pbk[j] = 1;
         if (Da > 0.0) c_pos++;
         else if (Da < 0.0) c_neg++;
         else {
@@ -425,6 +440,12 @@ __device__ inline void panel_reg_dev(int N, int nb, double alpha,
     }
   }
   __syncthreads();
+  for (int t = tid; t < jend; t += T) {
+    dd[k0 + t] = s_pdd[t];
+    ds[k0 + t] = s_pds[t];
+    ipiv[k0 + t] = s_pip[t];
+    blk[k0 + t] = s_pbk[t];
+  }
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int pr = pos[r];
