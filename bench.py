@@ -177,31 +177,50 @@ def kkt_step_section(args):
     return out, prob, st
 
 
+def factor_ms_of(tim, efacs):
+    """Device time of one factorization: the event pair around each whole
+    factorization on the handle's stream (with look-ahead its panels and
+    trailing updates overlap, so the per-class sum would count the overlap
+    twice); the per-class sum for timings without that class."""
+    f = tim.get("factor", {})
+    if f.get("launches"):
+        return f["ms"] / f["launches"]
+    return (tim["panel"]["ms"] + tim["panel_tail"]["ms"] + tim["trailing"]["ms"]) / max(efacs, 1)
+
+
 def roofline_of(tim, efacs, N, nb, pstats=None, xfloor=None):
     """The factorization, the step's dominant work (cooperative panel, its
     register tail and the trailing updates), against FP64 MFMA; inside it the
     trailing update against HBM (its own roofline, with the counter traffic)
     and the panel's latency model (microseconds per pivot step against the
     measured exchange round trip)."""
-    fac_ms = (tim["panel"]["ms"] + tim["panel_tail"]["ms"] + tim["trailing"]["ms"]) / max(efacs, 1)
+    fac_ms = factor_ms_of(tim, efacs)
     factor_tfs = (N ** 3 / 3.0) / (fac_ms / 1e3) / 1e12
     npan = tim["panel"]["launches"] + tim["panel_tail"]["launches"]
     w = N / max(npan / max(efacs, 1), 1)
     trl = tim["trailing"]
+    near = tim.get("near", {"ms": 0.0, "launches": 0})
+    la = near["launches"] > 0
     nl = max(trl["launches"], 1)
-    avg_s = trl["ms"] / 1e3 / nl
+    # with look-ahead one update is the near strip (reserved units) plus the
+    # rest (the other units, beside the next panel)
+    avg_s = (trl["ms"] + near["ms"]) / 1e3 / nl
     per_launch = trailing_bytes_per_launch(N, w)
-    meas = MEASURED_TRAFFIC.get(("k_bk_trailing", N))
-    trailing = dict(kernel="k_bk_trailing_ps", bound="hbm", achieved=per_launch / avg_s / 1e9,
+    meas = MEASURED_TRAFFIC.get(("k_bk_trailing_la" if la else "k_bk_trailing", N))
+    trailing = dict(kernel="k_bk_trailing_ps" + (" (near strip + rest)" if la else ""),
+                    bound="hbm", achieved=per_launch / avg_s / 1e9,
                     peak=HBM_PEAK_GBS, unit="GB/s", frac=per_launch / avg_s / 1e9 / HBM_PEAK_GBS,
                     traffic=meas[0] if meas else None, bytes_per_launch=per_launch,
                     flops_per_launch=trailing_flops_per_launch(N, w),
-                    avg_launch_us=avg_s * 1e6, launches=nl, ms_per_factorization=trl["ms"] / max(efacs, 1))
+                    avg_launch_us=avg_s * 1e6, launches=nl,
+                    ms_per_factorization=(trl["ms"] + near["ms"]) / max(efacs, 1))
+    if la:
+        trailing["near_ms_per_factorization"] = near["ms"] / max(efacs, 1)
     if meas and meas[0] is not None:
         trailing["traffic_source"] = meas[1]
         trailing["traffic_over_algorithmic"] = meas[0] / per_launch
     return dict(bound="mfma", kernel="factorization (k_bk_panel_coop, k_bk_panel_reg tail, "
-                                     "k_bk_trailing_ps)",
+                                     "k_bk_trailing_ps" + (", look-ahead" if la else "") + ")",
                 achieved=factor_tfs, peak=FP64_MFMA_PEAK_TFS, unit="TFLOP/s",
                 frac=factor_tfs / FP64_MFMA_PEAK_TFS, traffic=None,
                 flops_per_launch=N ** 3 / 3.0, avg_launch_us=fac_ms * 1e3, launches=efacs,
@@ -276,12 +295,12 @@ def precision_sweep(prob, st, N, reps=2, precs=("fp64", "fp32", "bf16x3", "bf16"
         once()
         tim = S.get_timings()
         S.set_timing(False)
-        fac_ms = tim["panel"]["ms"] + tim["panel_tail"]["ms"] + tim["trailing"]["ms"]
+        fac_ms = factor_ms_of(tim, 1)
         x = torch.cat(sol).cpu().numpy()
         if x64 is None:
             x64 = x
         rec = dict(ms_condense_factor_refine=dt * 1e3, ms_factor=fac_ms,
-                   ms_trailing=tim["trailing"]["ms"],
+                   ms_trailing=tim["trailing"]["ms"] + tim["near"]["ms"],
                    ms_panel=tim["panel"]["ms"] + tim["panel_tail"]["ms"],
                    tflops_nominal=(N ** 3 / 3.0 + 2.0 * N ** 2) / dt / 1e12,
                    refine_iterations=info["steps"], eta=info["eta"],
@@ -345,7 +364,7 @@ def opf_section(steps=10, warmup=2):
     xfloor = dict(P=P, first_exchange_us=S.probe_exchange(P, 2000, 69),
                   second_exchange_us=S.probe_exchange(P, 2000, 16),
                   words=dict(first=69, second=16), rounds=2000)
-    fac_ms = (tim["panel"]["ms"] + tim["panel_tail"]["ms"] + tim["trailing"]["ms"]) / max(efacs, 1)
+    fac_ms = factor_ms_of(tim, efacs)
     # whole IPM
     r = S.ipm_solve()
     torch.cuda.synchronize()
@@ -762,7 +781,7 @@ def main():
     h, prob, st = kkt_step_section(args)
     N, nb = h["N"], h["info"]["nb"]
     tim, efacs = h["tim"], h["efacs"]
-    fac_ms = (tim["panel"]["ms"] + tim["panel_tail"]["ms"] + tim["trailing"]["ms"]) / max(efacs, 1)
+    fac_ms = factor_ms_of(tim, efacs)
     factor_tfs = (N ** 3 / 3.0) / (fac_ms / 1e3) / 1e12
     out = {
         "metric": METRIC, "value": h["value"], "unit": "TFLOP/s", "n_gpus": 1,
@@ -773,7 +792,8 @@ def main():
                                f"m=12288 (N={N}), J_s 8 nnz/row, Sigma_d and D_s log-uniform "
                                "1e-8..1e8, FP64 refinement to backward error 1e-14, "
                                "seeded synthetic", "N": N, "nb": nb,
-                   "panel": h["info"]["panel"], "precision": "fp64"},
+                   "panel": h["info"]["panel"], "precision": "fp64",
+                   "lookahead_cus": h["info"]["lookahead_cus"]},
         "roofline": roofline_of(tim, efacs, N, nb, h.get("pstats"), h.get("xfloor")),
         "factor": {"ms_per_factorization": fac_ms, "tflops": factor_tfs,
                    "bound": "mfma", "peak_tflops": FP64_MFMA_PEAK_TFS,

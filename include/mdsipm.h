@@ -133,7 +133,23 @@ typedef struct {
                           this many sparse variables (mds_set_sparse_blocks)
                           and the transformed Jacobian they induce (up to
                           sblk_max * nnz_s entries)                          */
-  int32_t reserved[2];
+  int32_t lookahead;   /* cooperative FP64 factorization: 0 automatic (on for
+                          N >= 8192), 1 on, 2 off.  With look-ahead, panel
+                          b + 1 and the update of the 64-column strip ahead
+                          of it run on a few reserved compute units (4 per
+                          XCD, at least the panel's workgroups) while the
+                          rest of panel b's trailing update runs on the
+                          others (two CU-masked streams the handle creates;
+                          the handle's stream waits for both).  Panel b + 1
+                          computes the entries it needs outside the strip
+                          from panel b's input and multipliers, so its
+                          pivots are those of the sequential order (up to
+                          the rounding of those entries).  Off, or not
+                          applicable (mixed precision, another panel, a
+                          device whose CUs are not 8 equal XCDs): the
+                          launches of one factorization are sequential on
+                          the handle's stream.                              */
+  int32_t reserved[1];
 } mds_options;
 
 /* Problem data, all device pointers, caller-owned, must stay valid and
@@ -223,13 +239,17 @@ typedef struct {       /* one IPM iteration (host) */
 } mds_step_info;
 
 /* Per-kernel-class device time, accumulated while timing is enabled
- * (hipEvents recorded around each launch on the handle's stream).  PERMUTE is
- * the conversion of a new factor to standard form before its first solve;
+ * (hipEvents recorded around each launch on the stream it runs on).  PERMUTE
+ * is the conversion of a new factor to standard form before its first solve;
  * SOLVE is one triangular-solve sequence (permute, L, D, L', permute);
  * PANEL_TAIL holds the register-panel launches that finish a cooperative
- * factorization (PANEL then holds only the cooperative ones). */
+ * factorization (PANEL then holds only the cooperative ones).  FACTOR is
+ * each whole factorization on the handle's stream (with look-ahead its
+ * classes overlap, so their sum exceeds it); NEAR the look-ahead's strip
+ * updates (TRAILING then holds the rest of each trailing update). */
 enum { MDS_T_CONDENSE = 0, MDS_T_PANEL = 1, MDS_T_TRAILING = 2, MDS_T_SOLVE = 3,
-       MDS_T_PERMUTE = 4, MDS_T_PANEL_TAIL = 5, MDS_T_CLASSES = 6 };
+       MDS_T_PERMUTE = 4, MDS_T_PANEL_TAIL = 5, MDS_T_FACTOR = 6, MDS_T_NEAR = 7,
+       MDS_T_CLASSES = 8 };
 typedef struct {
   double ms[MDS_T_CLASSES];     /* summed kernel time per class            */
   int64_t launches[MDS_T_CLASSES];
@@ -495,7 +515,8 @@ typedef struct {
                            3: whole M in one workgroup's LDS                 */
   int32_t precision;    /* MDS_FP64, MDS_FP32, MDS_BF16 or MDS_BF16X3          */
   int32_t panel_threads; /* workgroup size of the panel kernel                */
-  int32_t pad;
+  int32_t lookahead_cus; /* look-ahead: compute units reserved for the panel
+                            and the near update (0: no look-ahead)           */
   int64_t workspace_bytes;
 } mds_info;
 int mds_get_info(const mds_handle *h, mds_info *out_host);

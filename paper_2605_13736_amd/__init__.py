@@ -41,7 +41,7 @@ class Dims(C.Structure):
 class Options(C.Structure):
     _fields_ = [("nb", C.c_int32), ("panel", C.c_int32), ("precision", C.c_int32),
                 ("panel_threads", C.c_int32), ("nlp", C.c_int32), ("sblk_max", C.c_int32),
-                ("reserved", C.c_int32 * 2)]
+                ("lookahead", C.c_int32), ("reserved", C.c_int32 * 1)]
 
 
 # panel kernels: automatic choice, panel in device memory, register-resident
@@ -49,6 +49,9 @@ class Options(C.Structure):
 # whole matrix in one workgroup's LDS (unblocked, N <= 199)
 PANELS = {"auto": 0, "mem": 1, "reg": 2, "coop": 3, "lds": 4}
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2, "bf16x3": 3}
+# look-ahead of the cooperative FP64 factorization (next panel beside the
+# trailing update): automatic (N >= 8192), on, off
+LOOKAHEAD = {"auto": 0, "on": 1, "off": 2}
 
 
 class Problem(C.Structure):
@@ -118,13 +121,13 @@ class Fallbacks(C.Structure):
     _fields_ = [("coop_aborts", C.c_int64), ("fp64_refactors", C.c_int64)]
 
 
-T_CLASSES = ("condense", "panel", "trailing", "solve", "permute", "panel_tail")
+T_CLASSES = ("condense", "panel", "trailing", "solve", "permute", "panel_tail", "factor", "near")
 
 
 class Info(C.Structure):
     _fields_ = [("nb", C.c_int32), ("min_width", C.c_int32), ("panel", C.c_int32),
-                ("precision", C.c_int32), ("panel_threads", C.c_int32), ("pad", C.c_int32),
-                ("workspace_bytes", C.c_int64)]
+                ("precision", C.c_int32), ("panel_threads", C.c_int32),
+                ("lookahead_cus", C.c_int32), ("workspace_bytes", C.c_int64)]
 
 
 class BatchProblem(C.Structure):
@@ -276,7 +279,7 @@ class Solver:
     def __init__(self, n_d: int, n_s: int, m: int, nnz_s: int, nb: int = 0,
                  device: str = "cuda:0", stream=None, panel: str = "auto",
                  precision: str = "fp64", panel_threads: int = 0, m_I: int = 0,
-                 sblk_max: int = 0, nlp: bool = False):
+                 sblk_max: int = 0, nlp: bool = False, lookahead: str = "auto"):
         torch = _torch()
         if not torch.cuda.is_available():
             raise MdsError("no ROCm GPU visible: the mdsipm library has no CPU path")
@@ -288,8 +291,11 @@ class Solver:
         self.precision = precision
         if panel not in PANELS:
             raise MdsError("panel must be one of " + ", ".join(PANELS))
+        if lookahead not in LOOKAHEAD:
+            raise MdsError("lookahead must be one of " + ", ".join(LOOKAHEAD))
         self.opts = Options(nb, PANELS[panel], PRECISIONS[precision],
-                            int(panel_threads), int(bool(nlp)), int(sblk_max))
+                            int(panel_threads), int(bool(nlp)), int(sblk_max),
+                            LOOKAHEAD[lookahead])
         self.n_d, self.n_s, self.m, self.m_I = n_d, n_s, m, m_I
         self.N, self.n = n_d + m, n_d + n_s
         self.nx = self.n + m_I  # IPM primal vector: variables, then inequality slacks
@@ -572,7 +578,7 @@ class Solver:
         prec = {v: k for k, v in PRECISIONS.items()}[i.precision]
         return dict(nb=i.nb, min_width=i.min_width, panel=("reg", "mem", "coop", "lds")[i.panel],
                     precision=prec, panel_threads=i.panel_threads,
-                    workspace_bytes=i.workspace_bytes)
+                    lookahead_cus=i.lookahead_cus, workspace_bytes=i.workspace_bytes)
 
     def panel_stats(self):
         """Pivot statistics of the last factorization (mds_get_panel_stats)."""
@@ -669,14 +675,15 @@ def _step_dict(s):
 
 
 def solver_for(prob: dict, nb: int = 0, device: str = "cuda:0", panel: str = "auto",
-               precision: str = "fp64", panel_threads: int = 0, nlp: bool = False) -> Solver:
+               precision: str = "fp64", panel_threads: int = 0, nlp: bool = False,
+               lookahead: str = "auto") -> Solver:
     """Create a Solver sized for a problem dict and attach the problem (and
     its coupling blocks of the sparse Hessian when it has them)."""
     bp = prob.get("bp")
     smax = int(np.max(np.diff(bp))) if bp is not None and len(bp) > 1 else 0
     s = Solver(prob["n_d"], prob["n_s"], prob["m"], len(prob["v"]), nb=nb, device=device,
                panel=panel, precision=precision, panel_threads=panel_threads,
-               m_I=int(prob.get("m_I", 0)), sblk_max=smax, nlp=nlp)
+               m_I=int(prob.get("m_I", 0)), sblk_max=smax, nlp=nlp, lookahead=lookahead)
     s.set_problem(prob)
     if smax:
         s.set_sparse_blocks(bp, prob["Wb"])

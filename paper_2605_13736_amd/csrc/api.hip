@@ -41,27 +41,32 @@ int set_err(mds_handle *h, int code, const char *fmt, ...) {
   } while (0)
 
 // ---- per-launch timing ---------------------------------------------------
+// Next free pair of the event pool (timers may nest: a pair is taken when
+// a timer starts, its mark added when it stops).
 int ev_take(mds_handle *h) {
-  const size_t used = 2 * h->ev_marks.size();
+  const size_t used = h->ev_used;
   while (h->ev_pool.size() < used + 2) {
     hipEvent_t e;
     if (hipEventCreate(&e) != hipSuccess) return -1;
     h->ev_pool.push_back(e);
   }
+  h->ev_used += 2;
   return (int)used;
 }
 
 struct TimedLaunch {
   mds_handle *h;
   int cls, idx;
-  TimedLaunch(mds_handle *h_, int c) : h(h_), cls(c), idx(-1) {
+  hipStream_t s;
+  TimedLaunch(mds_handle *h_, int c, hipStream_t s_ = nullptr)
+      : h(h_), cls(c), idx(-1), s(s_ ? s_ : h_->stream) {
     if (!h->timing) return;
     idx = ev_take(h);
-    if (idx >= 0) (void)hipEventRecord(h->ev_pool[idx], h->stream);
+    if (idx >= 0) (void)hipEventRecord(h->ev_pool[idx], s);
   }
   ~TimedLaunch() {
     if (idx < 0) return;
-    (void)hipEventRecord(h->ev_pool[idx + 1], h->stream);
+    (void)hipEventRecord(h->ev_pool[idx + 1], s);
     h->ev_marks.push_back({cls, {idx, idx + 1}});
   }
 };
@@ -78,6 +83,7 @@ int resolve_timings(mds_handle *h) {
     }
   }
   h->ev_marks.clear();
+  h->ev_used = 0;
   return MDS_OK;
 }
 
@@ -89,7 +95,7 @@ enum Slot {
   S_GZ, S_GRHS, S_GX, S_GW, S_GPART, S_GCOEF, S_XCH, S_XLE, S_XUE, S_DCV, S_RY2,
   S_BBP, S_BOFF, S_BKB, S_BL, S_HRP, S_HCI, S_HSRC, S_HVAL, S_HCPTR, S_HCROW, S_HCMAP, S_HCVAL,
   S_BT1, S_BT2, S_NH, S_NJD, S_NV, S_NW, S_NZERO, S_NCX0, S_NCSOC, S_NYR, S_NXS, S_NDXS, S_NDYS,
-  S_NXR, S_NDR, S_NCMAP, S_COUNT
+  S_NXR, S_NDR, S_NCMAP, S_SRC2, S_W2, S_LST, S_COUNT
 };
 
 struct Layout {
@@ -132,6 +138,10 @@ Layout make_layout(const mds_dims &d, int nb, bool pingpong, int precision, int 
   bytes[S_XCH] = 8 * 2 * (size_t)kCoopMaxP * kCoopSlotWords;
   bytes[S_SRC] = 4 * N;
   bytes[S_W] = 8 * N * (size_t)(nb + 2);
+  // look-ahead (ping-pong layout): second map and W, two staging buffers
+  bytes[S_SRC2] = pingpong ? 4 * N : 0;
+  bytes[S_W2] = pingpong ? 8 * N * (size_t)(nb + 2) : 0;
+  bytes[S_LST] = pingpong ? 2 * 8 * N * (size_t)(nb + 2) : 0;
   bytes[S_DD] = bytes[S_DS] = 8 * N;
   bytes[S_IPIV] = bytes[S_BLK] = 4 * N;
   bytes[S_PK0] = 4 * (maxp + 2);
@@ -328,11 +338,17 @@ void launch_reg_panel(mds_handle *h, hipStream_t s, int b, const TX *X, double *
                         h->w.dd, h->w.ds, h->w.ipiv, h->w.blk, h->w.fst, h->w.panel_k0);
 }
 
+void factor_launches_la(mds_handle *h, hipStream_t s);
+
 // Blocked Bunch-Kaufman of the current M; reads back the inertia.
 // The launches of one factorization, on stream s.  Their number depends only
 // on N and the panel's least width, so the sequence is fixed per handle.
 void factor_launches(mds_handle *h, hipStream_t s) {
   const int N = h->N;
+  if (h->la_cus > 0) {
+    factor_launches_la(h, s);
+    return;
+  }
   launch_fac_reset(s, h->w.fst, h->w.panel_k0);
   const int slots = (N + h->adv - 1) / h->adv;
   if (h->panel_lds) {
@@ -381,6 +397,128 @@ void factor_launches(mds_handle *h, hipStream_t s) {
                          h->panel_reg ? h->w.src : nullptr, h->w.fst, h->w.panel_k0);
     }
   }
+}
+
+// Look-ahead form of the cooperative FP64 factorization.  Stream A (the
+// reserved compute units) runs every panel and the near update of its
+// trailing matrix (the 64-column strip the next panel reads); stream B (the
+// other units) copies the panel's staged multipliers into their place and
+// runs the rest of the update, while A goes on with the next panel.  Before
+// the near update of slot b, A waits for B's update of slot b - 1: that
+// update writes the strip and reads the buffer the near update writes.
+// Buffers of slot b: input buf[b % 2], output buf[(b + 1) % 2], map, W and
+// staged multipliers of parity b % 2 (the next panel still reads slot b's
+// while it writes its own).  Register-panel tail slots run in order on A.
+void factor_launches_la(mds_handle *h, hipStream_t s) {
+  const int N = h->N, nb = h->nb, adv = h->adv;
+  hipStream_t A = h->la_a, B = h->la_b;
+  hipEvent_t ev_fork = h->la_ev[0], ev_near = h->la_ev[1], ev_far = h->la_ev[2],
+             ev_join = h->la_ev[3];
+  Work &w = h->w;
+  double *buf[2] = {w.M, w.M2};
+  int32_t *src[2] = {w.src, w.src2};
+  double *Wb[2] = {w.W, w.W2};
+  (void)hipEventRecord(ev_fork, s);
+  (void)hipStreamWaitEvent(A, ev_fork, 0);
+  (void)hipStreamWaitEvent(B, ev_fork, 0);
+  launch_fac_reset(A, w.fst, w.panel_k0);
+  const int slots = (N + adv - 1) / adv;
+  bool far_pending = false;  // B holds an update A has not waited for
+  auto wait_far = [&]() {
+    if (far_pending) (void)hipStreamWaitEvent(A, ev_far, 0);
+    far_pending = false;
+  };
+  for (int b = 0; b < slots; ++b) {
+    const int p = b & 1, q = (b + 1) & 1;
+    double *X = buf[p], *Y = buf[q];
+    const long left = (long)N - (long)b * adv;
+    const bool more = (long)N - (long)(b + 1) * adv > 0;
+    if (!is_tail_slot(h, b)) {
+      PanelPrev pv{};
+      if (b > 0) pv = PanelPrev{buf[q], src[q], Wb[q], w.lst[q]};
+      {
+        TimedLaunch t(h, MDS_T_PANEL, A);
+        launch_bk_panel_coop_la(A, (int)left, N, nb, h->alpha_bk, X, pv, w.lst[p], src[p], Wb[p],
+                                w.dd, w.ds, w.ipiv, w.blk, w.fst, w.panel_k0, w.xch);
+      }
+      wait_far();
+      if (more) {
+        {
+          TimedLaunch t(h, MDS_T_NEAR, A);
+          launch_bk_trailing_part(A, N, nb, adv, b, 1, 2 * h->la_cus, Wb[p], X, Y, w.lst[p],
+                                  src[p], w.fst, w.panel_k0);
+        }
+        (void)hipEventRecord(ev_near, A);
+        (void)hipStreamWaitEvent(B, ev_near, 0);
+        launch_lstage_copy(B, N, adv, b, w.lst[p], Y, w.fst, w.panel_k0);
+        {
+          TimedLaunch t(h, MDS_T_TRAILING, B);
+          launch_bk_trailing_part(B, N, nb, adv, b, 2, h->la_grid, Wb[p], X, Y, w.lst[p], src[p],
+                                  w.fst, w.panel_k0);
+        }
+        (void)hipEventRecord(ev_far, B);
+        far_pending = true;
+      } else {
+        launch_lstage_copy(A, N, adv, b, w.lst[p], Y, w.fst, w.panel_k0);
+      }
+    } else {
+      wait_far();
+      {
+        TimedLaunch t(h, MDS_T_PANEL_TAIL, A);
+        launch_bk_panel_reg_tail(A, (int)left, N, nb, h->alpha_bk, (const double *)X, Y, w.src,
+                                 w.W, w.dd, w.ds, w.ipiv, w.blk, w.fst, w.panel_k0);
+      }
+      if (more) {
+        TimedLaunch t(h, MDS_T_TRAILING, A);
+        launch_bk_trailing(A, N, nb, adv, b, w.W, X, Y, Y, w.src, w.fst, w.panel_k0);
+      }
+    }
+  }
+  wait_far();
+  (void)hipEventRecord(ev_join, A);
+  (void)hipStreamWaitEvent(s, ev_join, 0);
+}
+
+// CU-masked streams of the look-ahead: A on `reserve` compute units (the same
+// count on every XCD: unit x + 8 j of XCD x, which is also XCD x when the
+// mask's bits are dealt to the XCDs in turn), B on the others.  Leaves the
+// look-ahead off when the device does not have 8 equal XCDs or a stream
+// cannot be made.
+void setup_lookahead(mds_handle *h) {
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device) != hipSuccess) {
+    (void)hipGetLastError();
+    return;
+  }
+  if (cus < 64 || cus % 8 != 0) return;
+  const int r = bk_coop_la_reserve(h->N, cus);
+  const int per = cus / 8, m = r / 8;
+  if (r == 0 || r % 8 != 0 || 7 + 8 * (m - 1) >= per) return;
+  std::vector<uint32_t> ma((cus + 31) / 32, 0u), mb((cus + 31) / 32, 0u);
+  for (int x = 0; x < 8; ++x)
+    for (int j = 0; j < m; ++j) {
+      const int bit = per * x + x + 8 * j;
+      ma[bit / 32] |= 1u << (bit % 32);
+    }
+  for (int bit = 0; bit < cus; ++bit)
+    if (!(ma[bit / 32] >> (bit % 32) & 1u)) mb[bit / 32] |= 1u << (bit % 32);
+  bool ok = hipExtStreamCreateWithCUMask(&h->la_a, (uint32_t)ma.size(), ma.data()) == hipSuccess &&
+            hipExtStreamCreateWithCUMask(&h->la_b, (uint32_t)mb.size(), mb.data()) == hipSuccess;
+  for (int i = 0; ok && i < 4; ++i)
+    ok = hipEventCreateWithFlags(&h->la_ev[i], hipEventDisableTiming) == hipSuccess;
+  if (!ok) {
+    (void)hipGetLastError();
+    if (h->la_a) (void)hipStreamDestroy(h->la_a);
+    if (h->la_b) (void)hipStreamDestroy(h->la_b);
+    for (hipEvent_t &e : h->la_ev)
+      if (e) (void)hipEventDestroy(e);
+    h->la_a = h->la_b = nullptr;
+    for (hipEvent_t &e : h->la_ev) e = nullptr;
+    (void)hipGetLastError();
+    return;
+  }
+  h->la_cus = r;
+  h->la_grid = 2 * (cus - r);  // two trailing workgroups per compute unit
 }
 
 // Without per-launch timing, the factorization's launches are captured once
@@ -442,10 +580,17 @@ int factor_impl(mds_handle *h, mds_inertia *out) {
   FacState st{};
   bool mem = h->coop_off;
   if (!mem) {
-    const bool graph = !h->timing && !h->panel_lds && !h->fac_graph_off && !h->force64;
+    // the look-ahead's CU masks belong to its streams, which a graph would
+    // not keep: its launches go out one by one
+    const bool graph = !h->timing && !h->panel_lds && !h->fac_graph_off && !h->force64 &&
+                       h->la_cus == 0;
     if (graph && !h->fac_exec) capture_factor(h);
-    if (graph && h->fac_exec) HIPCHK(hipGraphLaunch(h->fac_exec, S(h)));
-    else factor_launches(h, S(h));
+    if (graph && h->fac_exec) {
+      HIPCHK(hipGraphLaunch(h->fac_exec, S(h)));
+    } else {
+      TimedLaunch t(h, MDS_T_FACTOR);
+      factor_launches(h, S(h));
+    }
     TRY(read_fac_state(h, &st));
     if (st.xerr && h->panel_coop) {
       // an exchange wait of the cooperative panel expired (its workgroups
@@ -1030,6 +1175,8 @@ int mds_create(mds_handle **out, const mds_dims *dims, const mds_options *opts, 
   const int sbm = opts ? opts->sblk_max : 0;
   if (sbm < 0 || sbm > kSBlkMax) return MDS_EINVAL;
   const bool nlp = opts && opts->nlp != 0;
+  const int la_opt = opts ? opts->lookahead : 0;
+  if (la_opt < 0 || la_opt > 2) return MDS_EINVAL;
   const Layout L = make_layout(*dims, nb, panel_of(*dims, opts).reg, prec, sbm, nlp);
   const PanelChoice pc = panel_of(*dims, opts);
   // every workgroup of the cooperative panel must be resident at once; if
@@ -1088,6 +1235,10 @@ int mds_create(mds_handle **out, const mds_dims *dims, const mds_options *opts, 
   w.gcoef = D(S_GCOEF);
   w.src = I(S_SRC);
   w.W = D(S_W);
+  w.src2 = I(S_SRC2);
+  w.W2 = D(S_W2);
+  w.lst[0] = D(S_LST);
+  w.lst[1] = w.lst[0] + (size_t)h->N * (size_t)(h->nb + 2);
   w.dd = D(S_DD);
   w.ds = D(S_DS);
   w.ipiv = I(S_IPIV);
@@ -1174,6 +1325,10 @@ int mds_create(mds_handle **out, const mds_dims *dims, const mds_options *opts, 
     delete h;
     return MDS_EHIP;
   }
+  // look-ahead: automatic from N = 8192 (below, the candidate columns it
+  // computes on the fly cost about what the overlap saves)
+  if (pc.coop && !coop_off && prec == MDS_FP64 && la_opt != 2 && (la_opt == 1 || h->N >= 8192))
+    setup_lookahead(h);
   *out = h;
   return MDS_OK;
 }
@@ -1183,6 +1338,10 @@ void mds_destroy(mds_handle *h) {
   for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
   if (h->fac_exec) (void)hipGraphExecDestroy(h->fac_exec);
   if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
+  if (h->la_a) (void)hipStreamDestroy(h->la_a);
+  if (h->la_b) (void)hipStreamDestroy(h->la_b);
+  for (hipEvent_t e : h->la_ev)
+    if (e) (void)hipEventDestroy(e);
   delete h;
 }
 
@@ -2068,6 +2227,7 @@ int mds_get_info(const mds_handle *h, mds_info *out) {
   out->panel = h->panel_lds ? 3 : h->panel_coop ? 2 : h->panel_reg ? 0 : 1;
   out->precision = h->precision;
   out->panel_threads = (h->panel_reg || h->panel_lds) ? h->panel_threads : 1024;
+  out->lookahead_cus = h->la_cus;
   out->workspace_bytes = (int64_t)h->ws_bytes;
   return MDS_OK;
 }

@@ -311,6 +311,7 @@ __global__ __launch_bounds__(NT) void k_bk_panel(int N, int nb, double alpha,
 // l holds A[l%16][l/16], operand B lane l holds B[l/16][l%16], and result
 // register r of lane l holds D[l/16 + 4r][l%16].
 constexpr int TT = 64;
+static_assert(TT == kNearCols, "the near strip is one tile column");
 constexpr int TS = 36;        // panel columns staged in LDS per chunk (multiple of 4)
 constexpr int TS1 = TS + 1;   // odd row stride of the staged panels
 constexpr int TSTAGE = TT * TS / 256;  // staged entries per thread and panel
@@ -442,7 +443,7 @@ __global__ __launch_bounds__(256) void k_bk_trailing(int N, int nb, const double
 // loads of its next tile (the entries it updates and the panel rows it
 // stages) are already in flight.  Per entry the arithmetic is the one of
 // k_bk_trailing, in the same order.
-__device__ inline void tr_load(int i0, int c0, bool diag, int N, int kend, int k0, int jw,
+__device__ inline void tr_load(int i0, int c0, bool diag, int N, int kend, int lk0, int jw,
                                const double *__restrict__ W, const double *X,
                                const double *Lsrc, const int32_t *__restrict__ src,
                                double (&xv)[2][2][4], double (&vw)[TSTAGE],
@@ -482,8 +483,31 @@ __device__ inline void tr_load(int i0, int c0, bool diag, int N, int kend, int k
     const int e = tid + 256 * u, r = e & (TT - 1), t = e >> 6;
     const int c = c0 + r, i = i0 + r;
     vw[u] = (t < jw && c >= kend && c < N) ? W[(size_t)c + (size_t)t * ld] : 0.0;
-    vl[u] = (t < jw && i >= kend && i < N) ? Lsrc[(size_t)i + (size_t)(k0 + t) * ld] : 0.0;
+    vl[u] = (t < jw && i >= kend && i < N) ? Lsrc[(size_t)i + (size_t)(lk0 + t) * ld] : 0.0;
   }
+}
+
+// Tiles of one launch: part 0 every lower tile (in the order of
+// tile_order.hpp), part 1 the first tile column (the near strip of the
+// look-ahead), part 2 the tiles right of it (ti >= tj >= 1).
+__device__ inline long part_slots(int part, int nt, bool xcd) {
+  if (part == 1) return nt;
+  if (part == 2) return (long)(nt - 1) * nt / 2;
+  return tile_slots(nt, xcd);
+}
+__device__ inline bool part_tile(int part, long x, int nt, bool xcd, int &ti, int &tj) {
+  if (part == 1) {
+    ti = (int)x;
+    tj = 0;
+    return ti < nt;
+  }
+  if (part == 2) {
+    tri_of(x, ti, tj);
+    ++ti;
+    ++tj;
+    return ti < nt;
+  }
+  return tile_of(x, nt, xcd, ti, tj);
 }
 
 __global__ __launch_bounds__(256) void k_bk_trailing_ps(int N, int nb,
@@ -493,30 +517,32 @@ __global__ __launch_bounds__(256) void k_bk_trailing_ps(int N, int nb,
                                                         const int32_t *__restrict__ src,
                                                         const FacState *__restrict__ st,
                                                         const int32_t *__restrict__ panel_k0,
-                                                        int slot) {
+                                                        int slot, int part) {
   __shared__ double s_buf[2 * TT * TS1];
   double *s_w = s_buf, *s_l = s_buf + TT * TS1;
   if (slot >= st->npanel) return;
   const int k0 = panel_k0[slot], kend = panel_k0[slot + 1];
   if (kend >= N || kend <= k0 || kend - k0 > nb + 1 || kend - k0 > TS) return;
   const int jw = kend - k0;
+  // the look-ahead parts read the panel's multipliers from its staging buffer
+  const int lk0 = (part == 0) ? k0 : 0;
   const int a0 = kend & ~15;
   const int nt = (N - a0 + TT - 1) / TT;
   // plain row-major order: measured at N = 16384, the super-tile order of
   // tile_order.hpp cut this kernel's fetched bytes by 17% but made it 3.5%
   // slower (188.8 against 182.4 us per launch); the FP32 update keeps it
   const bool xcd = false;
-  const long nslots = tile_slots(nt, xcd);
+  const long nslots = part_slots(part, nt, xcd);
   const size_t ld = (size_t)N;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int l16 = lane & 15, l4 = lane >> 4;
   // first slot of this workgroup that holds a tile
   long x = blockIdx.x;
   int ti = 0, tj = 0;
-  while (x < nslots && !tile_of(x, nt, xcd, ti, tj)) x += gridDim.x;
+  while (x < nslots && !part_tile(part, x, nt, xcd, ti, tj)) x += gridDim.x;
   if (x >= nslots) return;
   double xn[2][2][4], vwn[TSTAGE], vln[TSTAGE];
-  tr_load(a0 + ti * TT, a0 + tj * TT, ti == tj, N, kend, k0, jw, W, X, Lsrc, src, xn, vwn, vln);
+  tr_load(a0 + ti * TT, a0 + tj * TT, ti == tj, N, kend, lk0, jw, W, X, Lsrc, src, xn, vwn, vln);
   while (x < nslots) {
     const int i0 = a0 + ti * TT, c0 = a0 + tj * TT;
     const bool diag = (ti == tj);
@@ -539,9 +565,9 @@ __global__ __launch_bounds__(256) void k_bk_trailing_ps(int N, int nb,
     // the next slot that holds a tile, its loads in flight during this one
     long xnext = x + gridDim.x;
     int tin = 0, tjn = 0;
-    while (xnext < nslots && !tile_of(xnext, nt, xcd, tin, tjn)) xnext += gridDim.x;
+    while (xnext < nslots && !part_tile(part, xnext, nt, xcd, tin, tjn)) xnext += gridDim.x;
     if (xnext < nslots)
-      tr_load(a0 + tin * TT, a0 + tjn * TT, tin == tjn, N, kend, k0, jw, W, X, Lsrc, src, xn, vwn,
+      tr_load(a0 + tin * TT, a0 + tjn * TT, tin == tjn, N, kend, lk0, jw, W, X, Lsrc, src, xn, vwn,
               vln);
     d4 acc[2][2];
 #pragma unroll
@@ -578,6 +604,22 @@ __global__ __launch_bounds__(256) void k_bk_trailing_ps(int N, int nb,
   }
 }
 
+// Staged multipliers of a look-ahead panel into their column of the factor:
+// column t of Lst (rows below the diagonal) -> column k0 + t of Lout.
+__global__ __launch_bounds__(256) void k_lstage_copy(int N, const double *__restrict__ Lst,
+                                                     double *__restrict__ Lout,
+                                                     const FacState *__restrict__ st,
+                                                     const int32_t *__restrict__ panel_k0,
+                                                     int slot) {
+  if (slot >= st->npanel) return;
+  const int k0 = panel_k0[slot], kend = panel_k0[slot + 1];
+  const int t = blockIdx.y;
+  if (t >= kend - k0) return;
+  const size_t ld = (size_t)N;
+  for (int i = k0 + t + 1 + blockIdx.x * 256 + threadIdx.x; i < N; i += gridDim.x * 256)
+    Lout[(size_t)i + (size_t)(k0 + t) * ld] = Lst[(size_t)i + (size_t)t * ld];
+}
+
 }  // namespace
 
 void launch_fac_reset(hipStream_t s, FacState *st, int32_t *panel_k0) {
@@ -604,10 +646,31 @@ void launch_bk_trailing(hipStream_t s, int N, int nb, int adv, int slot, const d
     // persistent: a few workgroups per compute unit walk the tiles
     const long grid = std::min(tiles, (long)kTrailingGrid);
     k_bk_trailing_ps<<<(unsigned)grid, 256, 0, s>>>(N, nb, W, X, Y, Lsrc, src, st, panel_k0,
-                                                     slot);
+                                                     slot, 0);
   } else {
     k_bk_trailing<<<(unsigned)tiles, 256, 0, s>>>(N, nb, W, X, Y, Lsrc, src, st, panel_k0, slot);
   }
+}
+
+void launch_bk_trailing_part(hipStream_t s, int N, int nb, int adv, int slot, int part, int grid,
+                             const double *W, const double *X, double *Y, const double *Lsrc,
+                             const int32_t *src, const FacState *st, const int32_t *panel_k0) {
+  const long rem = (long)N - (long)(slot + 1) * adv;
+  if (rem <= 0 || nb + 1 > TS) return;
+  const long nt = (rem + 15 + TT - 1) / TT;
+  const long tiles = (part == 1) ? nt : (nt - 1) * nt / 2;
+  if (tiles <= 0) return;
+  const long g = std::min(tiles, (long)std::max(grid, 1));
+  k_bk_trailing_ps<<<(unsigned)g, 256, 0, s>>>(N, nb, W, X, Y, Lsrc, src, st, panel_k0, slot,
+                                                part);
+}
+
+void launch_lstage_copy(hipStream_t s, int N, int adv, int slot, const double *Lst, double *Lout,
+                        const FacState *st, const int32_t *panel_k0) {
+  const long rows = (long)N - (long)slot * adv;  // rows at the panel's start, at most
+  if (rows <= 0) return;
+  const unsigned gx = (unsigned)std::min<long>((rows + 1023) / 1024, 64);
+  k_lstage_copy<<<dim3(gx, (unsigned)(TS + 1)), 256, 0, s>>>(N, Lst, Lout, st, panel_k0, slot);
 }
 
 }  // namespace mds

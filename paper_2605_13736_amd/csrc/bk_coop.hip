@@ -65,9 +65,51 @@ __device__ inline double as_f64(uint64_t hi, uint64_t lo) {
   return __longlong_as_double((long long)(((hi & 0xffffffffull) << 32) | (lo & 0xffffffffull)));
 }
 
-template <int T, int R, int NB, int PMAX, typename TX>
+// Look-ahead: entry (hi, lo) of the panel's input, hi and lo the larger and
+// smaller of (rho, c), where the near update has not written it:
+// X_prev[src(hi), src(lo)] - sum_t W(lo, t) L(hi, t).  The row's own L row
+// (rho > c) or W row (rho <= c) meets the candidate c's W or L row, which
+// the caller put in LDS (pw, pl: zero past jw, 40 entries).  Two rows per
+// call (rows with on = false give 0), their loads in flight together.  Not
+// inlined: its loads then take registers only while it runs, not in the
+// pivot loop.
+__device__ __attribute__((noinline)) double2 pending_entries(const double *pX,
+                                                             const int32_t *psrc,
+                                                             const double *pW, const double *pL,
+                                                             int rho0, int rho1, bool on0, bool on1,
+                                                             int c, int jw, int ld,
+                                                             const double *pw, const double *pl) {
+  const int rho[2] = {rho0, rho1};
+  const bool on[2] = {on0, on1};
+  double x[2], acc[2];
+  const double *row[2], *bc[2];
+#pragma unroll
+  for (int r = 0; r < 2; ++r) {
+    const int hi = max(rho[r], c), lo = min(rho[r], c);
+    const int a = on[r] ? psrc[hi] : 0, b = on[r] ? psrc[lo] : 0;
+    x[r] = on[r] ? pX[(a >= b) ? a + b * ld : b + a * ld] : 0.0;
+    row[r] = (rho[r] > c) ? pL : pW;
+    bc[r] = (rho[r] > c) ? pw : pl;
+    acc[r] = 0.0;
+  }
+  for (int t0 = 0; t0 < jw; t0 += 8) {
+    double v[2][8];
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[r][u] = (on[r] && t0 + u < jw) ? row[r][rho[r] + (t0 + u) * ld] : 0.0;
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc[r] = fma(v[r][u], bc[r][t0 + u], acc[r]);
+  }
+  return double2{x[0] - acc[0], x[1] - acc[1]};
+}
+
+template <int T, int R, int NB, int PMAX, typename TX, bool LA>
 __global__ __launch_bounds__(T) void k_bk_panel_coop(int N, int nb, double alpha, int Pmax,
                                                      const TX *__restrict__ X,
+                                                     const PanelPrev pv,
                                                      double *__restrict__ Lout,
                                                      int32_t *__restrict__ src_out,
                                                      double *__restrict__ W,
@@ -76,7 +118,7 @@ __global__ __launch_bounds__(T) void k_bk_panel_coop(int N, int nb, double alpha
                                                      int32_t *__restrict__ ipiv,
                                                      int32_t *__restrict__ blk, FacState *st,
                                                      int32_t *__restrict__ panel_k0,
-                                                     uint64_t *__restrict__ xch) {
+                                                     uint64_t *__restrict__ xch, int lstage) {
   constexpr int NWV = T / 64;
   constexpr int RW = T * R;
   constexpr int NR = NB + 1;          // row record: value + L row
@@ -107,6 +149,8 @@ __global__ __launch_bounds__(T) void k_bk_panel_coop(int N, int nb, double alpha
   __shared__ uint32_t s_tag0;
   __shared__ double s_pdd[NB], s_pds[NB];  // the panel's D and pivot records (written at its end)
   __shared__ int s_pip[NB], s_pbk[NB];
+  __shared__ double s_pw[40], s_pl[40];  // look-ahead: W and L rows of the candidate
+  __shared__ int s_jwp;                  // ... and the previous panel's width
 
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int g = blockIdx.x;
@@ -115,6 +159,8 @@ __global__ __launch_bounds__(T) void k_bk_panel_coop(int N, int nb, double alpha
     s_tag0 = st->xtag;
     s_abort = st->xerr;
     s_force = st->xforce;
+    const int np = st->npanel;
+    s_jwp = (pv.X != nullptr && np > 0) ? min(s_k0 - panel_k0[np - 1], NB + 1) : 0;
   }
   if (tid < NB) {
     s_wk[tid] = 0.0;
@@ -135,6 +181,10 @@ __global__ __launch_bounds__(T) void k_bk_panel_coop(int N, int nb, double alpha
   if (g >= P) return;
   const int ld = N;  // N <= 20480: every offset fits in 32 bits
   const int gbase = k0 + g * RW;
+  // look-ahead: columns below kstrip are up to date in X; the previous
+  // panel factored jwp columns
+  const int kstrip = (k0 & ~15) + kNearCols, jwp = s_jwp;
+  const bool la = LA && pv.X != nullptr && jwp > 0;
   const uint32_t tagb = ((s_tag0 % 0xffffffu) + 1u) << 8;
   auto slot = [&](int par, int wg) { return xch + (size_t)(par * kCoopMaxP + wg) * kCoopSlotWords; };
   auto owner = [&](int phys) { return (phys - k0) / RW; };
@@ -401,15 +451,36 @@ __global__ __launch_bounds__(T) void k_bk_panel_coop(int N, int nb, double alpha
     } else {
       const int src_i = s_map[imax - k0];
       const int src_k2 = (k + 2 < N) ? s_map[k + 2 - k0] : 0;
+      // look-ahead with the candidate past the strip: its entries in rows
+      // past the strip still lack the previous panel's update (the column of
+      // position k + 2 lies in the strip: every position up to k0 + nb holds
+      // a physical row of the strip)
+      const bool fly = la && src_i >= kstrip;
+      if constexpr (LA) if (fly) {
+        if (tid < 40) s_pw[tid] = (tid < jwp) ? pv.W[src_i + tid * ld] : 0.0;
+        else if (tid >= 64 && tid < 104)
+          s_pl[tid - 64] = (tid - 64 < jwp) ? pv.L[src_i + (tid - 64) * ld] : 0.0;
+        __syncthreads();
+      }
       double wic[R];
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         const int rho = gbase + tid + T * r;
         wic[r] = 0.0;
         if (pos[r] >= k) {
-          wic[r] = (double)sym_at(X, rho, src_i, ld);
+          if (!fly || rho < kstrip) wic[r] = (double)sym_at(X, rho, src_i, ld);
           if (k + 2 < N) pre2[r] = sym_at(X, rho, src_k2, ld);
         }
+      }
+      if constexpr (LA) if (fly) {
+        keep_branch();
+        static_assert(R == 2, "two rows per call");
+        const int rho0 = gbase + tid, rho1 = gbase + tid + T;
+        const bool on0 = pos[0] >= k && rho0 >= kstrip, on1 = pos[1] >= k && rho1 >= kstrip;
+        const double2 e = pending_entries(pv.X, pv.src, pv.W, pv.L, rho0, rho1, on0, on1, src_i,
+                                          jwp, ld, s_pw, s_pl);
+        if (on0) wic[0] = e.x;
+        if (on1) wic[1] = e.y;
       }
 #pragma unroll
       for (int t0 = 0; t0 < NB; t0 += 8) {
@@ -657,6 +728,7 @@ __global__ __launch_bounds__(T) void k_bk_panel_coop(int N, int nb, double alpha
 
   // ---- write the panel's multipliers and W = L D for the trailing rows ---------
   const int kend = k, jend = j;
+  const int lcol = lstage ? 0 : k0;  // staged multipliers: column t at t N
   if (tid == 0 && pj >= 0) {
     s_cA[pj] = pA0;
     s_cB[pj] = pB0;
@@ -681,7 +753,7 @@ __global__ __launch_bounds__(T) void k_bk_panel_coop(int N, int nb, double alpha
     const int rho = gbase + tid + T * r;
 #pragma unroll
     for (int t = 0; t < NB; ++t)
-      if (t < jend && pr > k0 + t) Lout[pr + (k0 + t) * ld] = Lr[r][t];
+      if (t < jend && pr > k0 + t) Lout[pr + (lcol + t) * ld] = Lr[r][t];
     if (pr >= kend) {
 #pragma unroll
       for (int t = 0; t < NB; ++t) {
@@ -806,16 +878,16 @@ bool bk_coop_resident(int N) {
   hipError_t e;
   if (P <= 4)
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &per, k_bk_panel_coop<kCoopT, kCoopR, kCoopNB, 4, double>, kCoopT, 0);
+        &per, k_bk_panel_coop<kCoopT, kCoopR, kCoopNB, 4, double, false>, kCoopT, 0);
   else if (P <= 8)
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &per, k_bk_panel_coop<kCoopT, kCoopR, kCoopNB, 8, double>, kCoopT, 0);
+        &per, k_bk_panel_coop<kCoopT, kCoopR, kCoopNB, 8, double, false>, kCoopT, 0);
   else if (P <= 12)
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &per, k_bk_panel_coop<kCoopT, kCoopR, kCoopNB, 12, double>, kCoopT, 0);
+        &per, k_bk_panel_coop<kCoopT, kCoopR, kCoopNB, 12, double, false>, kCoopT, 0);
   else
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &per, k_bk_panel_coop<kCoopT, kCoopR, kCoopNB, kCoopP, double>, kCoopT, 0);
+        &per, k_bk_panel_coop<kCoopT, kCoopR, kCoopNB, kCoopP, double, false>, kCoopT, 0);
   if (e != hipSuccess) {
     (void)hipGetLastError();
     return false;
@@ -830,15 +902,15 @@ int bk_coop_wgs(int N) { return (N + kCoopT * kCoopR - 1) / (kCoopT * kCoopR); }
 // picks the smallest instantiation that covers the panel: `rows` bounds the
 // rows left at the panel's start (every earlier panel factored at least
 // nb - 1 columns), and with them its workgroups.
-template <typename TX>
+template <typename TX, bool LA>
 static void panel_coop(hipStream_t s, int rows, int N, int nb, double alpha, const TX *X,
-                       double *Lout, int32_t *src_out, double *W, double *dd, double *ds,
-                       int32_t *ipiv, int32_t *blk, FacState *st, int32_t *panel_k0,
-                       uint64_t *xch) {
+                       const PanelPrev &pv, double *Lout, int lstage, int32_t *src_out, double *W,
+                       double *dd, double *ds, int32_t *ipiv, int32_t *blk, FacState *st,
+                       int32_t *panel_k0, uint64_t *xch) {
   const int P = std::max(1, std::min(bk_coop_wgs(N), bk_coop_wgs(rows)));
 #define MDS_COOP(PM_)                                                                  \
-  k_bk_panel_coop<kCoopT, kCoopR, kCoopNB, PM_, TX><<<P, kCoopT, 0, s>>>(              \
-      N, nb, alpha, P, X, Lout, src_out, W, dd, ds, ipiv, blk, st, panel_k0, xch)
+  k_bk_panel_coop<kCoopT, kCoopR, kCoopNB, PM_, TX, LA><<<P, kCoopT, 0, s>>>(          \
+      N, nb, alpha, P, X, pv, Lout, src_out, W, dd, ds, ipiv, blk, st, panel_k0, xch, lstage)
   if (P <= 4) MDS_COOP(4);
   else if (P <= 8) MDS_COOP(8);
   else if (P <= 12) MDS_COOP(12);
@@ -860,14 +932,34 @@ void launch_bk_panel_coop(hipStream_t s, int rows, int N, int nb, double alpha, 
                           double *Lout, int32_t *src_out, double *W, double *dd, double *ds,
                           int32_t *ipiv, int32_t *blk, FacState *st, int32_t *panel_k0,
                           uint64_t *xch) {
-  panel_coop(s, rows, N, nb, alpha, X, Lout, src_out, W, dd, ds, ipiv, blk, st, panel_k0, xch);
+  panel_coop<double, false>(s, rows, N, nb, alpha, X, PanelPrev{}, Lout, 0, src_out, W, dd, ds,
+                            ipiv, blk, st, panel_k0, xch);
 }
 
 void launch_bk_panel_coop(hipStream_t s, int rows, int N, int nb, double alpha, const float *X,
                           double *Lout, int32_t *src_out, double *W, double *dd, double *ds,
                           int32_t *ipiv, int32_t *blk, FacState *st, int32_t *panel_k0,
                           uint64_t *xch) {
-  panel_coop(s, rows, N, nb, alpha, X, Lout, src_out, W, dd, ds, ipiv, blk, st, panel_k0, xch);
+  panel_coop<float, false>(s, rows, N, nb, alpha, X, PanelPrev{}, Lout, 0, src_out, W, dd, ds,
+                           ipiv, blk, st, panel_k0, xch);
+}
+
+void launch_bk_panel_coop_la(hipStream_t s, int rows, int N, int nb, double alpha, const double *X,
+                             const PanelPrev &pv, double *Lst, int32_t *src_out, double *W,
+                             double *dd, double *ds, int32_t *ipiv, int32_t *blk, FacState *st,
+                             int32_t *panel_k0, uint64_t *xch) {
+  panel_coop<double, true>(s, rows, N, nb, alpha, X, pv, Lst, 1, src_out, W, dd, ds, ipiv, blk, st,
+                           panel_k0, xch);
+}
+
+// One panel workgroup per compute unit (each takes the whole register file),
+// so the reserved units must number at least the first panel's workgroups;
+// at least 32 (4 per XCD), since the near update runs on them too, and a
+// multiple of the XCD count so that every XCD keeps the same share.
+int bk_coop_la_reserve(int N, int cus) {
+  const int P = bk_coop_wgs(N);
+  const int r = std::max(32, (P + 7) / 8 * 8);
+  return (r <= cus / 4) ? r : 0;
 }
 
 }  // namespace mds

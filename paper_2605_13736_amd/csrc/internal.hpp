@@ -52,6 +52,21 @@ struct FacState {
   int32_t cx3;    // ... of which took the second exchange (the candidate column)
 };
 
+// Look-ahead of the cooperative factorization: while the trailing update of
+// panel b runs on part of the device, panel b + 1 factors its columns, which
+// a near update (the 64-column strip at the trailing matrix's start) has
+// already brought up to date.  Entries it reads outside that strip (the
+// candidate column of a failed first Bunch-Kaufman test) it computes itself
+// from panel b's input and multipliers: entry (i, c), i >= c, of its input is
+// X[src(i), src(c)] - sum_t W[c, t] L[i, t] (lower triangle of X).
+constexpr int kNearCols = 64;  // columns of the near update past the 16-aligned start
+struct PanelPrev {
+  const double *X;      // panel b's input, physical indices (null: no look-ahead)
+  const int32_t *src;   // panel b's map: its output's row -> physical row of X
+  const double *W;      // panel b's W = L D: W[c + t N]
+  const double *L;      // panel b's multipliers, staged: L[i + t N]
+};
+
 // Pointers into the caller's workspace.
 struct Work {
   double *M;          // N x N, full symmetric, column-major; L after factoring
@@ -60,6 +75,11 @@ struct Work {
   double *eq;         // mixed precision: equilibration S (N)
   int32_t *src;       // N: logical -> physical index map of the last panel
   double *W;          // N x (nb + 2) panel workspace (updated columns)
+  // look-ahead: the second map and W (panels alternate), and two staging
+  // buffers of a panel's multipliers (N x (nb + 2) each)
+  int32_t *src2;
+  double *W2;
+  double *lst[2];
   double *dd, *ds;    // D diagonal / sub-diagonal (N)
   int32_t *ipiv;      // LAPACK-style pivots (N)
   int32_t *blk;       // 1: 1x1 pivot, 2: first of a 2x2, 3: second of a 2x2
@@ -132,6 +152,12 @@ struct mds_handle {
   bool fac_lowprec = false; // current factor is of the equilibrated FP32 matrix
   bool fac_pingpong = false;// current factor's L is spread over M and M2
   int64_t n_coop_abort = 0, n_fp64_refactor = 0;
+  // look-ahead of the cooperative factorization: compute units reserved for
+  // the panel and the near update (0: off), the far update's persistent
+  // grid, the two CU-masked streams and the events between them
+  int la_cus = 0, la_grid = 0;
+  hipStream_t la_a = nullptr, la_b = nullptr;
+  hipEvent_t la_ev[4] = {};
   // captured launch sequence of one factorization (replayed without timing)
   hipGraphExec_t fac_exec = nullptr;
   hipStream_t cap_stream = nullptr;
@@ -156,6 +182,7 @@ struct mds_handle {
   bool timing = false;
   int64_t nsolves = 0;  // LDL' solves performed (statistics)
   std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;  // events of the pool taken since the last resolution
   std::vector<std::pair<int, std::pair<int, int>>> ev_marks;  // class, (start, stop)
   double t_ms[MDS_T_CLASSES] = {};
   int64_t t_n[MDS_T_CLASSES] = {};
@@ -219,6 +246,17 @@ void launch_bk_panel(hipStream_t s, int N, int nb, double alpha, double *M, doub
 void launch_bk_trailing(hipStream_t s, int N, int nb, int adv, int slot, const double *W,
                         const double *X, double *Y, const double *Lsrc, const int32_t *src,
                         const FacState *st, const int32_t *panel_k0);
+// look-ahead parts of the trailing update of slot `slot` (nb + 1 <= 36):
+// part 1 the near strip (the first 64-column tile column), part 2 the rest;
+// both persistent over at most `grid` workgroups; Lsrc holds the
+// panel's multipliers staged (row i, column t at Lsrc[i + t N])
+void launch_bk_trailing_part(hipStream_t s, int N, int nb, int adv, int slot, int part, int grid,
+                             const double *W, const double *X, double *Y, const double *Lsrc,
+                             const int32_t *src, const FacState *st, const int32_t *panel_k0);
+// staged multipliers of slot `slot` into their place in Lout (columns
+// k0 .. kend - 1, rows below the diagonal)
+void launch_lstage_copy(hipStream_t s, int N, int adv, int slot, const double *Lst, double *Lout,
+                        const FacState *st, const int32_t *panel_k0);
 
 // bk_reg.hip: register-resident panel for N <= 4096 (X in FP64 or FP32),
 // workgroup of `threads` = 512 or 1024
@@ -259,6 +297,17 @@ void launch_bk_panel_coop(hipStream_t s, int rows, int N, int nb, double alpha, 
                           double *Lout, int32_t *src_out, double *W, double *dd, double *ds,
                           int32_t *ipiv, int32_t *blk, FacState *st, int32_t *panel_k0,
                           uint64_t *xch);
+// look-ahead form (FP64): X is valid in the near strip only, pv names the
+// previous panel's pending update, and the multipliers go to the staging
+// buffer Lst (row i, column t at Lst[i + t N])
+void launch_bk_panel_coop_la(hipStream_t s, int rows, int N, int nb, double alpha, const double *X,
+                             const PanelPrev &pv, double *Lst, int32_t *src_out, double *W,
+                             double *dd, double *ds, int32_t *ipiv, int32_t *blk, FacState *st,
+                             int32_t *panel_k0, uint64_t *xch);
+// the CU count the look-ahead keeps free of the far trailing update for a
+// cooperative panel of order N (its workgroups, rounded up to a multiple of
+// the XCD count); 0 when the panel would not fit beside it
+int bk_coop_la_reserve(int N, int cus);
 void launch_bk_panel_coop(hipStream_t s, int rows, int N, int nb, double alpha, const float *X,
                           double *Lout, int32_t *src_out, double *W, double *dd, double *ds,
                           int32_t *ipiv, int32_t *blk, FacState *st, int32_t *panel_k0,
