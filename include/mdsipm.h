@@ -133,7 +133,7 @@ typedef struct {
                           this many sparse variables (mds_set_sparse_blocks)
                           and the transformed Jacobian they induce (up to
                           sblk_max * nnz_s entries)                          */
-  int32_t lookahead;   /* cooperative FP64 factorization: 0 automatic (on for
+  int32_t lookahead;   /* cooperative factorization: 0 automatic (on for
                           N >= 8192), 1 on, 2 off.  With look-ahead, panel
                           b + 1 and the update of the 64-column strip ahead
                           of it run on a few reserved compute units (4 per
@@ -144,8 +144,9 @@ typedef struct {
                           computes the entries it needs outside the strip
                           from panel b's input and multipliers, so its
                           pivots are those of the sequential order (up to
-                          the rounding of those entries).  Off, or not
-                          applicable (mixed precision, another panel, a
+                          the rounding of those entries).  It applies to
+                          every precision mode.  Off, or not applicable
+                          (another panel, the memory-panel fallback, a
                           device whose CUs are not 8 equal XCDs): the
                           launches of one factorization are sequential on
                           the handle's stream.                              */

@@ -49,7 +49,7 @@ class Options(C.Structure):
 # whole matrix in one workgroup's LDS (unblocked, N <= 199)
 PANELS = {"auto": 0, "mem": 1, "reg": 2, "coop": 3, "lds": 4}
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2, "bf16x3": 3}
-# look-ahead of the cooperative FP64 factorization (next panel beside the
+# look-ahead of the cooperative factorization (next panel beside the
 # trailing update): automatic (N >= 8192), on, off
 LOOKAHEAD = {"auto": 0, "on": 1, "off": 2}
 

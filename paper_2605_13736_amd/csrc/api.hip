@@ -399,25 +399,35 @@ void factor_launches(mds_handle *h, hipStream_t s) {
   }
 }
 
-// Look-ahead form of the cooperative FP64 factorization.  Stream A (the
+// Look-ahead form of the cooperative factorization.  Stream A (the
 // reserved compute units) runs every panel and the near update of its
 // trailing matrix (the 64-column strip the next panel reads); stream B (the
-// other units) copies the panel's staged multipliers into their place and
-// runs the rest of the update, while A goes on with the next panel.  Before
-// the near update of slot b, A waits for B's update of slot b - 1: that
-// update writes the strip and reads the buffer the near update writes.
-// Buffers of slot b: input buf[b % 2], output buf[(b + 1) % 2], map, W and
-// staged multipliers of parity b % 2 (the next panel still reads slot b's
-// while it writes its own).  Register-panel tail slots run in order on A.
+// other units) runs the rest of the update, while A goes on with the next
+// panel.  Before the near update of slot b, A waits for B's update of slot
+// b - 1: that update writes the strip and reads the buffer the near update
+// writes.  Buffers of slot b: input buf[b % 2], output buf[(b + 1) % 2], map
+// and W of parity b % 2 (the next panel still reads slot b's while it
+// writes its own).  FP64 storage: the panel's multipliers go to a staging
+// buffer of parity b % 2, which B copies into place before the rest of the
+// update (the next panel's output buffer is the one that update reads).
+// FP32 storage: they go straight to M, which no trailing update writes.
+// Register-panel tail slots run in order on A.
 void factor_launches_la(mds_handle *h, hipStream_t s) {
   const int N = h->N, nb = h->nb, adv = h->adv;
+  const bool lowp = h->precision != MDS_FP64 && !h->force64;
   hipStream_t A = h->la_a, B = h->la_b;
   hipEvent_t ev_fork = h->la_ev[0], ev_near = h->la_ev[1], ev_far = h->la_ev[2],
              ev_join = h->la_ev[3];
   Work &w = h->w;
   double *buf[2] = {w.M, w.M2};
+  float *buf32[2] = {w.X32[0], w.X32[1]};
   int32_t *src[2] = {w.src, w.src2};
   double *Wb[2] = {w.W, w.W2};
+  if (lowp) {
+    // on the handle's stream, which has every compute unit
+    TimedLaunch t(h, MDS_T_CONDENSE, s);
+    launch_equilibrate_f32(s, N, w.M, w.eq, buf32[0]);
+  }
   (void)hipEventRecord(ev_fork, s);
   (void)hipStreamWaitEvent(A, ev_fork, 0);
   (void)hipStreamWaitEvent(B, ev_fork, 0);
@@ -431,46 +441,72 @@ void factor_launches_la(mds_handle *h, hipStream_t s) {
   for (int b = 0; b < slots; ++b) {
     const int p = b & 1, q = (b + 1) & 1;
     double *X = buf[p], *Y = buf[q];
+    float *X32 = buf32[p], *Y32 = buf32[q];
     const long left = (long)N - (long)b * adv;
     const bool more = (long)N - (long)(b + 1) * adv > 0;
     if (!is_tail_slot(h, b)) {
-      PanelPrev pv{};
-      if (b > 0) pv = PanelPrev{buf[q], src[q], Wb[q], w.lst[q]};
       {
         TimedLaunch t(h, MDS_T_PANEL, A);
-        launch_bk_panel_coop_la(A, (int)left, N, nb, h->alpha_bk, X, pv, w.lst[p], src[p], Wb[p],
-                                w.dd, w.ds, w.ipiv, w.blk, w.fst, w.panel_k0, w.xch);
+        if (lowp) {
+          PanelPrev pv{};
+          if (b > 0) pv = PanelPrev{nullptr, buf32[q], src[q], Wb[q], w.M, 1, -1};
+          launch_bk_panel_coop_la(A, (int)left, N, nb, h->alpha_bk, (const float *)X32, pv, w.M,
+                                  src[p], Wb[p], w.dd, w.ds, w.ipiv, w.blk, w.fst, w.panel_k0,
+                                  w.xch);
+        } else {
+          PanelPrev pv{};
+          if (b > 0) pv = PanelPrev{buf[q], nullptr, src[q], Wb[q], w.lst[q], 0, ~15};
+          launch_bk_panel_coop_la(A, (int)left, N, nb, h->alpha_bk, (const double *)X, pv,
+                                  w.lst[p], src[p], Wb[p], w.dd, w.ds, w.ipiv, w.blk, w.fst,
+                                  w.panel_k0, w.xch);
+        }
       }
       wait_far();
       if (more) {
         {
           TimedLaunch t(h, MDS_T_NEAR, A);
-          launch_bk_trailing_part(A, N, nb, adv, b, 1, 2 * h->la_cus, Wb[p], X, Y, w.lst[p],
-                                  src[p], w.fst, w.panel_k0);
+          if (lowp)
+            launch_trailing_lp_part(A, h->precision, N, nb, adv, b, 1, 2 * h->la_cus, Wb[p], X32,
+                                    Y32, w.M, src[p], w.fst, w.panel_k0);
+          else
+            launch_bk_trailing_part(A, N, nb, adv, b, 1, 2 * h->la_cus, Wb[p], X, Y, w.lst[p],
+                                    src[p], w.fst, w.panel_k0);
         }
         (void)hipEventRecord(ev_near, A);
         (void)hipStreamWaitEvent(B, ev_near, 0);
-        launch_lstage_copy(B, N, adv, b, w.lst[p], Y, w.fst, w.panel_k0);
+        if (!lowp) launch_lstage_copy(B, N, adv, b, w.lst[p], Y, w.fst, w.panel_k0);
         {
           TimedLaunch t(h, MDS_T_TRAILING, B);
-          launch_bk_trailing_part(B, N, nb, adv, b, 2, h->la_grid, Wb[p], X, Y, w.lst[p], src[p],
-                                  w.fst, w.panel_k0);
+          if (lowp)
+            launch_trailing_lp_part(B, h->precision, N, nb, adv, b, 2, h->la_grid, Wb[p], X32,
+                                    Y32, w.M, src[p], w.fst, w.panel_k0);
+          else
+            launch_bk_trailing_part(B, N, nb, adv, b, 2, h->la_grid, Wb[p], X, Y, w.lst[p],
+                                    src[p], w.fst, w.panel_k0);
         }
         (void)hipEventRecord(ev_far, B);
         far_pending = true;
-      } else {
+      } else if (!lowp) {
         launch_lstage_copy(A, N, adv, b, w.lst[p], Y, w.fst, w.panel_k0);
       }
     } else {
       wait_far();
       {
         TimedLaunch t(h, MDS_T_PANEL_TAIL, A);
-        launch_bk_panel_reg_tail(A, (int)left, N, nb, h->alpha_bk, (const double *)X, Y, w.src,
-                                 w.W, w.dd, w.ds, w.ipiv, w.blk, w.fst, w.panel_k0);
+        if (lowp)
+          launch_bk_panel_reg_tail(A, (int)left, N, nb, h->alpha_bk, (const float *)X32, w.M,
+                                   w.src, w.W, w.dd, w.ds, w.ipiv, w.blk, w.fst, w.panel_k0);
+        else
+          launch_bk_panel_reg_tail(A, (int)left, N, nb, h->alpha_bk, (const double *)X, Y, w.src,
+                                   w.W, w.dd, w.ds, w.ipiv, w.blk, w.fst, w.panel_k0);
       }
       if (more) {
         TimedLaunch t(h, MDS_T_TRAILING, A);
-        launch_bk_trailing(A, N, nb, adv, b, w.W, X, Y, Y, w.src, w.fst, w.panel_k0);
+        if (lowp)
+          launch_trailing_lp(A, h->precision, N, nb, adv, b, w.W, X32, Y32, w.M, w.src, w.fst,
+                             w.panel_k0);
+        else
+          launch_bk_trailing(A, N, nb, adv, b, w.W, X, Y, Y, w.src, w.fst, w.panel_k0);
       }
     }
   }
@@ -1327,8 +1363,7 @@ int mds_create(mds_handle **out, const mds_dims *dims, const mds_options *opts, 
   }
   // look-ahead: automatic from N = 8192 (below, the candidate columns it
   // computes on the fly cost about what the overlap saves)
-  if (pc.coop && !coop_off && prec == MDS_FP64 && la_opt != 2 && (la_opt == 1 || h->N >= 8192))
-    setup_lookahead(h);
+  if (pc.coop && !coop_off && la_opt != 2 && (la_opt == 1 || h->N >= 8192)) setup_lookahead(h);
   *out = h;
   return MDS_OK;
 }

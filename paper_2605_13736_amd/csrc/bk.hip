@@ -487,28 +487,6 @@ __device__ inline void tr_load(int i0, int c0, bool diag, int N, int kend, int l
   }
 }
 
-// Tiles of one launch: part 0 every lower tile (in the order of
-// tile_order.hpp), part 1 the first tile column (the near strip of the
-// look-ahead), part 2 the tiles right of it (ti >= tj >= 1).
-__device__ inline long part_slots(int part, int nt, bool xcd) {
-  if (part == 1) return nt;
-  if (part == 2) return (long)(nt - 1) * nt / 2;
-  return tile_slots(nt, xcd);
-}
-__device__ inline bool part_tile(int part, long x, int nt, bool xcd, int &ti, int &tj) {
-  if (part == 1) {
-    ti = (int)x;
-    tj = 0;
-    return ti < nt;
-  }
-  if (part == 2) {
-    tri_of(x, ti, tj);
-    ++ti;
-    ++tj;
-    return ti < nt;
-  }
-  return tile_of(x, nt, xcd, ti, tj);
-}
 
 __global__ __launch_bounds__(256) void k_bk_trailing_ps(int N, int nb,
                                                         const double *__restrict__ W,

@@ -67,14 +67,15 @@ __device__ inline double as_f64(uint64_t hi, uint64_t lo) {
 
 // Look-ahead: entry (hi, lo) of the panel's input, hi and lo the larger and
 // smaller of (rho, c), where the near update has not written it:
-// X_prev[src(hi), src(lo)] - sum_t W(lo, t) L(hi, t).  The row's own L row
-// (rho > c) or W row (rho <= c) meets the candidate c's W or L row, which
-// the caller put in LDS (pw, pl: zero past jw, 40 entries).  Two rows per
-// call (rows with on = false give 0), their loads in flight together.  Not
-// inlined: its loads then take registers only while it runs, not in the
-// pivot loop.
-__device__ __attribute__((noinline)) double2 pending_entries(const double *pX,
-                                                             const int32_t *psrc,
+// X_prev[src(hi), src(lo)] - sum_t W(lo, t) L(hi, t), X_prev in the storage
+// type TX (in FP32 the result is rounded to FP32, as the trailing update
+// stores it).  The row's own L row (rho > c) or W row (rho <= c) meets the
+// candidate c's W or L row, which the caller put in LDS (pw, pl: zero past
+// jw, 40 entries).  Two rows per call (rows with on = false give 0), their
+// loads in flight together.  Not inlined: its loads then take registers only
+// while it runs, not in the pivot loop.
+template <typename TX>
+__device__ __attribute__((noinline)) double2 pending_entries(const TX *pX, const int32_t *psrc,
                                                              const double *pW, const double *pL,
                                                              int rho0, int rho1, bool on0, bool on1,
                                                              int c, int jw, int ld,
@@ -87,7 +88,8 @@ __device__ __attribute__((noinline)) double2 pending_entries(const double *pX,
   for (int r = 0; r < 2; ++r) {
     const int hi = max(rho[r], c), lo = min(rho[r], c);
     const int a = on[r] ? psrc[hi] : 0, b = on[r] ? psrc[lo] : 0;
-    x[r] = on[r] ? pX[(a >= b) ? a + b * ld : b + a * ld] : 0.0;
+    const int q = (a >= b) ? a + b * ld : b + a * ld;
+    x[r] = on[r] ? (double)pX[q] : 0.0;
     row[r] = (rho[r] > c) ? pL : pW;
     bc[r] = (rho[r] > c) ? pw : pl;
     acc[r] = 0.0;
@@ -103,7 +105,7 @@ __device__ __attribute__((noinline)) double2 pending_entries(const double *pX,
 #pragma unroll
       for (int u = 0; u < 8; ++u) acc[r] = fma(v[r][u], bc[r][t0 + u], acc[r]);
   }
-  return double2{x[0] - acc[0], x[1] - acc[1]};
+  return double2{(double)(TX)(x[0] - acc[0]), (double)(TX)(x[1] - acc[1])};
 }
 
 template <int T, int R, int NB, int PMAX, typename TX, bool LA>
@@ -150,7 +152,7 @@ __global__ __launch_bounds__(T) void k_bk_panel_coop(int N, int nb, double alpha
   __shared__ double s_pdd[NB], s_pds[NB];  // the panel's D and pivot records (written at its end)
   __shared__ int s_pip[NB], s_pbk[NB];
   __shared__ double s_pw[40], s_pl[40];  // look-ahead: W and L rows of the candidate
-  __shared__ int s_jwp;                  // ... and the previous panel's width
+  __shared__ int s_jwp, s_kprev;         // ... and the previous panel's width and start
 
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int g = blockIdx.x;
@@ -160,7 +162,9 @@ __global__ __launch_bounds__(T) void k_bk_panel_coop(int N, int nb, double alpha
     s_abort = st->xerr;
     s_force = st->xforce;
     const int np = st->npanel;
-    s_jwp = (pv.X != nullptr && np > 0) ? min(s_k0 - panel_k0[np - 1], NB + 1) : 0;
+    const bool pvon = pv.X != nullptr || pv.Xf != nullptr;
+    s_kprev = (pvon && np > 0) ? panel_k0[np - 1] : 0;
+    s_jwp = (pvon && np > 0) ? min(s_k0 - s_kprev, NB + 1) : 0;
   }
   if (tid < NB) {
     s_wk[tid] = 0.0;
@@ -183,8 +187,8 @@ __global__ __launch_bounds__(T) void k_bk_panel_coop(int N, int nb, double alpha
   const int gbase = k0 + g * RW;
   // look-ahead: columns below kstrip are up to date in X; the previous
   // panel factored jwp columns
-  const int kstrip = (k0 & ~15) + kNearCols, jwp = s_jwp;
-  const bool la = LA && pv.X != nullptr && jwp > 0;
+  const int kstrip = (k0 & pv.amask) + kNearCols, jwp = s_jwp;
+  const bool la = LA && (pv.X != nullptr || pv.Xf != nullptr) && jwp > 0;
   const uint32_t tagb = ((s_tag0 % 0xffffffu) + 1u) << 8;
   auto slot = [&](int par, int wg) { return xch + (size_t)(par * kCoopMaxP + wg) * kCoopSlotWords; };
   auto owner = [&](int phys) { return (phys - k0) / RW; };
@@ -456,10 +460,13 @@ __global__ __launch_bounds__(T) void k_bk_panel_coop(int N, int nb, double alpha
       // position k + 2 lies in the strip: every position up to k0 + nb holds
       // a physical row of the strip)
       const bool fly = la && src_i >= kstrip;
+      // the previous panel's multipliers from column 0 (computed here, not
+      // kept live through the pivot loop)
+      const double *pL = pv.L + (pv.labs ? (size_t)s_kprev * (size_t)N : 0);
       if constexpr (LA) if (fly) {
         if (tid < 40) s_pw[tid] = (tid < jwp) ? pv.W[src_i + tid * ld] : 0.0;
         else if (tid >= 64 && tid < 104)
-          s_pl[tid - 64] = (tid - 64 < jwp) ? pv.L[src_i + (tid - 64) * ld] : 0.0;
+          s_pl[tid - 64] = (tid - 64 < jwp) ? pL[src_i + (tid - 64) * ld] : 0.0;
         __syncthreads();
       }
       double wic[R];
@@ -477,8 +484,11 @@ __global__ __launch_bounds__(T) void k_bk_panel_coop(int N, int nb, double alpha
         static_assert(R == 2, "two rows per call");
         const int rho0 = gbase + tid, rho1 = gbase + tid + T;
         const bool on0 = pos[0] >= k && rho0 >= kstrip, on1 = pos[1] >= k && rho1 >= kstrip;
-        const double2 e = pending_entries(pv.X, pv.src, pv.W, pv.L, rho0, rho1, on0, on1, src_i,
-                                          jwp, ld, s_pw, s_pl);
+        const TX *pX;
+        if constexpr (sizeof(TX) == 8) pX = pv.X;
+        else pX = pv.Xf;
+        const double2 e = pending_entries<TX>(pX, pv.src, pv.W, pL, rho0, rho1, on0, on1, src_i,
+                                              jwp, ld, s_pw, s_pl);
         if (on0) wic[0] = e.x;
         if (on1) wic[1] = e.y;
       }
@@ -950,6 +960,14 @@ void launch_bk_panel_coop_la(hipStream_t s, int rows, int N, int nb, double alph
                              int32_t *panel_k0, uint64_t *xch) {
   panel_coop<double, true>(s, rows, N, nb, alpha, X, pv, Lst, 1, src_out, W, dd, ds, ipiv, blk, st,
                            panel_k0, xch);
+}
+
+void launch_bk_panel_coop_la(hipStream_t s, int rows, int N, int nb, double alpha, const float *X,
+                             const PanelPrev &pv, double *Lout, int32_t *src_out, double *W,
+                             double *dd, double *ds, int32_t *ipiv, int32_t *blk, FacState *st,
+                             int32_t *panel_k0, uint64_t *xch) {
+  panel_coop<float, true>(s, rows, N, nb, alpha, X, pv, Lout, 0, src_out, W, dd, ds, ipiv, blk, st,
+                          panel_k0, xch);
 }
 
 // One panel workgroup per compute unit (each takes the whole register file),

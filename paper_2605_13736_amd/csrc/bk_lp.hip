@@ -28,6 +28,7 @@ constexpr int TSL1 = TSL + 1;  // odd row stride of the staged panels
 constexpr int TSTL = TT * TSL / 256;  // staged entries per thread and panel
 constexpr int kTrailingLpGrid = kTileGrid;  // persistent form: 512 workgroups (2 per CU at <= 196 VGPRs)
 static_assert(TT * TSL % 256 == 0, "staging");
+static_assert(TT == kNearCols, "the near strip is one tile column");
 
 // round-to-nearest-even FP32 -> BF16 (finite inputs)
 __device__ inline short to_bf16(float x) {
@@ -265,7 +266,7 @@ __global__ __launch_bounds__(256) void k_trailing_lp_ps(int N, int nb,
                                                         const int32_t *__restrict__ src,
                                                         const FacState *__restrict__ st,
                                                         const int32_t *__restrict__ panel_k0,
-                                                        int slot) {
+                                                        int slot, int part) {
   __shared__ float s_buf[2 * TT * TSL1];
   float *s_w = s_buf, *s_l = s_buf + TT * TSL1;
   if (slot >= st->npanel) return;
@@ -273,15 +274,17 @@ __global__ __launch_bounds__(256) void k_trailing_lp_ps(int N, int nb,
   if (kend >= N || kend <= k0 || kend - k0 > nb + 1 || kend - k0 > TSL) return;
   const int jw = kend - k0;
   const int nt = (N - kend + TT - 1) / TT;
-  const bool xcd = gridDim.x == (unsigned)kTileGrid;
-  const long nslots = tile_slots(nt, xcd);
+  // the super-tile order needs its full grid; the look-ahead parts (part 1:
+  // the first tile column, part 2: the rest) walk row-major
+  const bool xcd = part == 0 && gridDim.x == (unsigned)kTileGrid;
+  const long nslots = part_slots(part, nt, xcd);
   const size_t ld = (size_t)N;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int l16 = lane & 15, l4 = lane >> 4;
   // first slot of this workgroup that holds a tile (order of tile_order.hpp)
   long x = blockIdx.x;
   int ti = 0, tj = 0;
-  while (x < nslots && !tile_of(x, nt, xcd, ti, tj)) x += gridDim.x;
+  while (x < nslots && !part_tile(part, x, nt, xcd, ti, tj)) x += gridDim.x;
   if (x >= nslots) return;
   float xn[2][2][4];
   double vwn[TSTL], vln[TSTL];
@@ -308,7 +311,7 @@ __global__ __launch_bounds__(256) void k_trailing_lp_ps(int N, int nb,
     // the next slot that holds a tile, its loads in flight during this one
     long xnext = x + gridDim.x;
     int tin = 0, tjn = 0;
-    while (xnext < nslots && !tile_of(xnext, nt, xcd, tin, tjn)) xnext += gridDim.x;
+    while (xnext < nslots && !part_tile(part, xnext, nt, xcd, tin, tjn)) xnext += gridDim.x;
     if (xnext < nslots)
       lp_load(kend + tin * TT, kend + tjn * TT, tin == tjn, N, kend, k0, jw, W, X, Lsrc, src, xn,
               vwn, vln);
@@ -444,11 +447,11 @@ void launch_trailing_lp(hipStream_t s, int mode, int N, int nb, int adv, int slo
     // persistent: a few workgroups per compute unit walk the tiles
     const unsigned g = (unsigned)std::min(tiles, (long)kTrailingLpGrid);
     if (mode == 2)
-      k_trailing_lp_ps<2><<<g, 256, 0, s>>>(N, nb, W, X, Y, Lsrc, src, st, panel_k0, slot);
+      k_trailing_lp_ps<2><<<g, 256, 0, s>>>(N, nb, W, X, Y, Lsrc, src, st, panel_k0, slot, 0);
     else if (mode == 3)
-      k_trailing_lp_ps<3><<<g, 256, 0, s>>>(N, nb, W, X, Y, Lsrc, src, st, panel_k0, slot);
+      k_trailing_lp_ps<3><<<g, 256, 0, s>>>(N, nb, W, X, Y, Lsrc, src, st, panel_k0, slot, 0);
     else
-      k_trailing_lp_ps<1><<<g, 256, 0, s>>>(N, nb, W, X, Y, Lsrc, src, st, panel_k0, slot);
+      k_trailing_lp_ps<1><<<g, 256, 0, s>>>(N, nb, W, X, Y, Lsrc, src, st, panel_k0, slot, 0);
     return;
   }
   if (mode == 2)
@@ -457,6 +460,24 @@ void launch_trailing_lp(hipStream_t s, int mode, int N, int nb, int adv, int slo
     k_trailing_lp<3><<<(unsigned)tiles, 256, 0, s>>>(N, nb, W, X, Y, Lsrc, src, st, panel_k0, slot);
   else
     k_trailing_lp<1><<<(unsigned)tiles, 256, 0, s>>>(N, nb, W, X, Y, Lsrc, src, st, panel_k0, slot);
+}
+
+void launch_trailing_lp_part(hipStream_t s, int mode, int N, int nb, int adv, int slot, int part,
+                             int grid, const double *W, const float *X, float *Y,
+                             const double *Lsrc, const int32_t *src, const FacState *st,
+                             const int32_t *panel_k0) {
+  const long rem = (long)N - (long)(slot + 1) * adv;
+  if (rem <= 0 || nb + 1 > TSL) return;
+  const long nt = (rem + TT - 1) / TT;
+  const long tiles = (part == 1) ? nt : (nt - 1) * nt / 2;
+  if (tiles <= 0) return;
+  const unsigned g = (unsigned)std::min(tiles, (long)std::max(grid, 1));
+  if (mode == 2)
+    k_trailing_lp_ps<2><<<g, 256, 0, s>>>(N, nb, W, X, Y, Lsrc, src, st, panel_k0, slot, part);
+  else if (mode == 3)
+    k_trailing_lp_ps<3><<<g, 256, 0, s>>>(N, nb, W, X, Y, Lsrc, src, st, panel_k0, slot, part);
+  else
+    k_trailing_lp_ps<1><<<g, 256, 0, s>>>(N, nb, W, X, Y, Lsrc, src, st, panel_k0, slot, part);
 }
 
 void launch_equilibrate_f32(hipStream_t s, int N, const double *M, double *scale, float *b) {

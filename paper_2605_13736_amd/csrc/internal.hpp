@@ -59,12 +59,15 @@ struct FacState {
 // candidate column of a failed first Bunch-Kaufman test) it computes itself
 // from panel b's input and multipliers: entry (i, c), i >= c, of its input is
 // X[src(i), src(c)] - sum_t W[c, t] L[i, t] (lower triangle of X).
-constexpr int kNearCols = 64;  // columns of the near update past the 16-aligned start
+constexpr int kNearCols = 64;  // columns of the near update past its start
 struct PanelPrev {
-  const double *X;      // panel b's input, physical indices (null: no look-ahead)
+  const double *X;      // panel b's input, physical indices (FP64 storage), or
+  const float *Xf;      // ... in FP32 storage (null both: no look-ahead)
   const int32_t *src;   // panel b's map: its output's row -> physical row of X
   const double *W;      // panel b's W = L D: W[c + t N]
-  const double *L;      // panel b's multipliers, staged: L[i + t N]
+  const double *L;      // panel b's multipliers: staged, L[i + t N], or in
+  int labs;             // place (labs = 1), L[i + (k0_b + t) N]
+  int amask;            // the strip starts at (k0 & amask): ~15 (FP64 tiles), -1 (FP32)
 };
 
 // Pointers into the caller's workspace.
@@ -304,6 +307,11 @@ void launch_bk_panel_coop_la(hipStream_t s, int rows, int N, int nb, double alph
                              const PanelPrev &pv, double *Lst, int32_t *src_out, double *W,
                              double *dd, double *ds, int32_t *ipiv, int32_t *blk, FacState *st,
                              int32_t *panel_k0, uint64_t *xch);
+// ... FP32 storage: the multipliers go to their place in Lout (FP64)
+void launch_bk_panel_coop_la(hipStream_t s, int rows, int N, int nb, double alpha, const float *X,
+                             const PanelPrev &pv, double *Lout, int32_t *src_out, double *W,
+                             double *dd, double *ds, int32_t *ipiv, int32_t *blk, FacState *st,
+                             int32_t *panel_k0, uint64_t *xch);
 // the CU count the look-ahead keeps free of the far trailing update for a
 // cooperative panel of order N (its workgroups, rounded up to a multiple of
 // the XCD count); 0 when the panel would not fit beside it
@@ -327,6 +335,11 @@ void launch_bk_lds(hipStream_t s, int threads, int N, double alpha, double *M, d
 void launch_trailing_lp(hipStream_t s, int mode, int N, int nb, int adv, int slot,
                         const double *W, const float *X, float *Y, const double *Lsrc,
                         const int32_t *src, const FacState *st, const int32_t *panel_k0);
+// look-ahead parts (as launch_bk_trailing_part; Lsrc in place, not staged)
+void launch_trailing_lp_part(hipStream_t s, int mode, int N, int nb, int adv, int slot, int part,
+                             int grid, const double *W, const float *X, float *Y,
+                             const double *Lsrc, const int32_t *src, const FacState *st,
+                             const int32_t *panel_k0);
 // scale = 1/sqrt(row max |M|), b = FP32(S M S); v = scale .* v
 void launch_equilibrate_f32(hipStream_t s, int N, const double *M, double *scale, float *b);
 void launch_vscale(hipStream_t s, int n, const double *scale, double *v);

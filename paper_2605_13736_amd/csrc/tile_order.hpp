@@ -57,4 +57,27 @@ __device__ inline bool tile_of(long x, int nt, bool xcd, int &ti, int &tj) {
   return ti < nt && tj <= ti;
 }
 
+// Tiles of one launch: part 0 every lower tile (in the order above),
+// part 1 the first tile column (the near strip of the look-ahead), part 2
+// the tiles right of it (ti >= tj >= 1, row-major).
+__device__ inline long part_slots(int part, int nt, bool xcd) {
+  if (part == 1) return nt;
+  if (part == 2) return (long)(nt - 1) * nt / 2;
+  return tile_slots(nt, xcd);
+}
+__device__ inline bool part_tile(int part, long x, int nt, bool xcd, int &ti, int &tj) {
+  if (part == 1) {
+    ti = (int)x;
+    tj = 0;
+    return ti < nt;
+  }
+  if (part == 2) {
+    tri_of(x, ti, tj);
+    ++ti;
+    ++tj;
+    return ti < nt;
+  }
+  return tile_of(x, nt, xcd, ti, tj);
+}
+
 }  // namespace mds

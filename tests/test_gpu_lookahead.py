@@ -94,11 +94,39 @@ def test_lookahead_whole_ipm_matches_sequential():
     assert np.abs(out["on"][2] - x0).max() <= 1e-8 * max(1.0, np.abs(x0).max())
 
 
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_lookahead_fp32_storage_matches_sequential(precision):
+    """FP32 storage of the trailing matrix: the look-ahead panel computes its
+    candidate entries from the previous FP32 buffer and rounds them to FP32;
+    inertia and the refined solution match the sequential order's."""
+    prob = synth.config_problem(synth.OPF_N4096)
+    st = synth.kkt_state(prob, 2)
+    res = {}
+    for la in ("off", "on"):
+        say(f"KKT N=4096 {precision} lookahead={la}")
+        S = mds.solver_for(prob, precision=precision, lookahead=la)
+        assert (S.info()["lookahead_cus"] > 0) == (la == "on")
+        S.condense(st["sigma_d"], st["dsbase"], 0.0, 0.0)
+        _, inn, _ = S.factor_inertia(1e-8)
+        sol, ri = S.refine(st["r_d"], st["r_s"], st["r_y"], 10, 1e-14)
+        assert ri["eta"] <= 1e-14
+        res[la] = (S.get_pivots(), inn, np.concatenate([t.cpu().numpy() for t in sol]))
+        del S
+    (p0, i0, x0), (p1, i1, x1) = res["off"], res["on"]
+    assert i0 == i1
+    assert np.mean(p0 == p1) > 0.999
+    # two different FP32 factors, each refined to backward error 1e-14: they
+    # agree to this system's conditioning (an FP32 factor's refined solution
+    # lies ~1e-8 from the FP64 one here), the bar of the mixed IPM tests
+    assert np.abs(x1 - x0).max() <= 1e-7 * np.abs(x0).max()
+
+
 def test_lookahead_automatic_choice_and_bounds():
     prob = synth.config_problem(synth.OPF_N4096)
     say("look-ahead automatic choice")
     assert mds.solver_for(prob).info()["lookahead_cus"] == 0          # N = 4096 < 8192
-    # mixed precision keeps the sequential order
-    assert mds.solver_for(prob, precision="fp32", lookahead="on").info()["lookahead_cus"] == 0
+    assert mds.solver_for(prob, precision="fp32").info()["lookahead_cus"] == 0
+    # only the cooperative panel has a look-ahead form
+    assert mds.solver_for(prob, panel="mem", lookahead="on").info()["lookahead_cus"] == 0
     with pytest.raises(mds.MdsError):
         mds.Solver(8, 10, 4, 10, lookahead="sometimes")
