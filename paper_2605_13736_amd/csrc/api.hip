@@ -118,7 +118,9 @@ Layout make_layout(const mds_dims &d, int nb, bool pingpong, int precision, int 
   const size_t nd = d.n_d, ns = d.n_s, m = d.m, N = nd + m, n = nd + ns;
   const size_t nx = n + (size_t)d.m_I;
   const size_t nnz = (size_t)d.nnz_s;
-  const size_t maxp = N / (size_t)std::max(nb - 1, 1) + 2;
+  // panels: at least nb - 1 columns each, the register tail's 16-column
+  // tile over the last 2048 rows adds at most 40 (see make_plan)
+  const size_t maxp = N / (size_t)std::max(nb - 1, 1) + 42;
   size_t bytes[S_COUNT] = {};
   bytes[S_M] = 8 * N * N;
   const bool mixed = precision != MDS_FP64;
@@ -316,22 +318,36 @@ int condense_impl(mds_handle *h, double dw, double dc) {
   return MDS_OK;
 }
 
-// Panel of slot b on the ping-pong layout: the cooperative panel, or the
-// register panel over its last rows (every panel before slot b factored at
-// least adv columns, so at most N - b * adv rows remain).
-bool is_tail_slot(const mds_handle *h, int b) {
-  return h->panel_coop && h->panel_tail && (long)h->N - (long)b * h->adv <= bk_reg_tail_rows();
+// Slot plan of a factorization (fixed per handle): the handle's panel until
+// at most bk_reg_tail_rows() rows can remain (cooperative panel with the
+// automatic tail), then the register tail, whose tile is 16 columns wide
+// above 1024 rows and 32 below.
+void make_plan(mds_handle *h) {
+  h->plan.clear();
+  long rows = h->N;
+  while (rows > 0) {
+    SlotPlan sp{0, rows, 0};
+    if (h->panel_coop && h->panel_tail && rows <= bk_reg_tail_rows())
+      sp.tail_nb = std::min(bk_reg_tail_nb((int)rows), h->nb);
+    sp.rows_after = rows - (sp.tail_nb ? std::max(sp.tail_nb - 1, 1) : h->adv);
+    h->plan.push_back(sp);
+    rows = sp.rows_after;
+  }
 }
 
+bool is_tail_slot(const mds_handle *h, int b) { return h->plan[b].tail_nb != 0; }
+
+// Panel of slot b on the ping-pong layout: the cooperative panel, the
+// register tail over its last rows, or the one-workgroup register panel.
 template <typename TX>
 void launch_reg_panel(mds_handle *h, hipStream_t s, int b, const TX *X, double *Y) {
   const int N = h->N;
-  const long left = (long)N - (long)b * h->adv;
-  if (h->panel_coop && !is_tail_slot(h, b))
-    launch_bk_panel_coop(s, (int)left, N, h->nb, h->alpha_bk, X, Y, h->w.src, h->w.W, h->w.dd,
+  const SlotPlan &sp = h->plan[b];
+  if (h->panel_coop && !sp.tail_nb)
+    launch_bk_panel_coop(s, (int)sp.rows, N, h->nb, h->alpha_bk, X, Y, h->w.src, h->w.W, h->w.dd,
                          h->w.ds, h->w.ipiv, h->w.blk, h->w.fst, h->w.panel_k0, h->w.xch);
   else if (h->panel_coop)
-    launch_bk_panel_reg_tail(s, (int)left, N, h->nb, h->alpha_bk, X, Y, h->w.src, h->w.W,
+    launch_bk_panel_reg_tail(s, (int)sp.rows, N, h->nb, h->alpha_bk, X, Y, h->w.src, h->w.W,
                              h->w.dd, h->w.ds, h->w.ipiv, h->w.blk, h->w.fst, h->w.panel_k0);
   else
     launch_bk_panel_reg(s, h->panel_threads, N, h->nb, h->alpha_bk, X, Y, h->w.src, h->w.W,
@@ -350,7 +366,7 @@ void factor_launches(mds_handle *h, hipStream_t s) {
     return;
   }
   launch_fac_reset(s, h->w.fst, h->w.panel_k0);
-  const int slots = (N + h->adv - 1) / h->adv;
+  const int slots = (int)h->plan.size();
   if (h->panel_lds) {
     TimedLaunch t(h, MDS_T_PANEL);
     launch_bk_lds(s, h->panel_threads, N, h->alpha_bk, h->w.M, h->w.dd, h->w.ds, h->w.ipiv,
@@ -369,10 +385,10 @@ void factor_launches(mds_handle *h, hipStream_t s) {
         TimedLaunch t(h, is_tail_slot(h, b) ? MDS_T_PANEL_TAIL : MDS_T_PANEL);
         launch_reg_panel(h, s, b, X, h->w.M);
       }
-      if ((long)N - (long)(b + 1) * h->adv > 0) {
+      if (h->plan[b].rows_after > 0) {
         TimedLaunch t(h, MDS_T_TRAILING);
-        launch_trailing_lp(s, h->precision, N, h->nb, h->adv, b, h->w.W, X, Y, h->w.M,
-                           h->w.src, h->w.fst, h->w.panel_k0);
+        launch_trailing_lp(s, h->precision, N, h->nb, h->plan[b].rows_after, b, h->w.W, X, Y,
+                           h->w.M, h->w.src, h->w.fst, h->w.panel_k0);
       }
     }
   }
@@ -391,9 +407,9 @@ void factor_launches(mds_handle *h, hipStream_t s) {
         launch_bk_panel(s, N, h->nb, h->alpha_bk, h->w.M, h->w.W, h->w.dd, h->w.ds,
                         h->w.ipiv, h->w.blk, h->w.fst, h->w.panel_k0);
     }
-    if ((long)N - (long)(b + 1) * h->adv > 0) {
+    if (h->plan[b].rows_after > 0) {
       TimedLaunch t(h, MDS_T_TRAILING);
-      launch_bk_trailing(s, N, h->nb, h->adv, b, h->w.W, X, Y, Y,
+      launch_bk_trailing(s, N, h->nb, h->plan[b].rows_after, b, h->w.W, X, Y, Y,
                          h->panel_reg ? h->w.src : nullptr, h->w.fst, h->w.panel_k0);
     }
   }
@@ -413,7 +429,7 @@ void factor_launches(mds_handle *h, hipStream_t s) {
 // FP32 storage: they go straight to M, which no trailing update writes.
 // Register-panel tail slots run in order on A.
 void factor_launches_la(mds_handle *h, hipStream_t s) {
-  const int N = h->N, nb = h->nb, adv = h->adv;
+  const int N = h->N, nb = h->nb;
   const bool lowp = h->precision != MDS_FP64 && !h->force64;
   hipStream_t A = h->la_a, B = h->la_b;
   hipEvent_t ev_fork = h->la_ev[0], ev_near = h->la_ev[1], ev_far = h->la_ev[2],
@@ -432,7 +448,7 @@ void factor_launches_la(mds_handle *h, hipStream_t s) {
   (void)hipStreamWaitEvent(A, ev_fork, 0);
   (void)hipStreamWaitEvent(B, ev_fork, 0);
   launch_fac_reset(A, w.fst, w.panel_k0);
-  const int slots = (N + adv - 1) / adv;
+  const int slots = (int)h->plan.size();
   bool far_pending = false;  // B holds an update A has not waited for
   auto wait_far = [&]() {
     if (far_pending) (void)hipStreamWaitEvent(A, ev_far, 0);
@@ -442,8 +458,8 @@ void factor_launches_la(mds_handle *h, hipStream_t s) {
     const int p = b & 1, q = (b + 1) & 1;
     double *X = buf[p], *Y = buf[q];
     float *X32 = buf32[p], *Y32 = buf32[q];
-    const long left = (long)N - (long)b * adv;
-    const bool more = (long)N - (long)(b + 1) * adv > 0;
+    const long left = h->plan[b].rows, rem = h->plan[b].rows_after;
+    const bool more = rem > 0;
     if (!is_tail_slot(h, b)) {
       {
         TimedLaunch t(h, MDS_T_PANEL, A);
@@ -466,28 +482,28 @@ void factor_launches_la(mds_handle *h, hipStream_t s) {
         {
           TimedLaunch t(h, MDS_T_NEAR, A);
           if (lowp)
-            launch_trailing_lp_part(A, h->precision, N, nb, adv, b, 1, 2 * h->la_cus, Wb[p], X32,
+            launch_trailing_lp_part(A, h->precision, N, nb, rem, b, 1, 2 * h->la_cus, Wb[p], X32,
                                     Y32, w.M, src[p], w.fst, w.panel_k0);
           else
-            launch_bk_trailing_part(A, N, nb, adv, b, 1, 2 * h->la_cus, Wb[p], X, Y, w.lst[p],
+            launch_bk_trailing_part(A, N, nb, rem, b, 1, 2 * h->la_cus, Wb[p], X, Y, w.lst[p],
                                     src[p], w.fst, w.panel_k0);
         }
         (void)hipEventRecord(ev_near, A);
         (void)hipStreamWaitEvent(B, ev_near, 0);
-        if (!lowp) launch_lstage_copy(B, N, adv, b, w.lst[p], Y, w.fst, w.panel_k0);
+        if (!lowp) launch_lstage_copy(B, N, left, b, w.lst[p], Y, w.fst, w.panel_k0);
         {
           TimedLaunch t(h, MDS_T_TRAILING, B);
           if (lowp)
-            launch_trailing_lp_part(B, h->precision, N, nb, adv, b, 2, h->la_grid, Wb[p], X32,
+            launch_trailing_lp_part(B, h->precision, N, nb, rem, b, 2, h->la_grid, Wb[p], X32,
                                     Y32, w.M, src[p], w.fst, w.panel_k0);
           else
-            launch_bk_trailing_part(B, N, nb, adv, b, 2, h->la_grid, Wb[p], X, Y, w.lst[p],
+            launch_bk_trailing_part(B, N, nb, rem, b, 2, h->la_grid, Wb[p], X, Y, w.lst[p],
                                     src[p], w.fst, w.panel_k0);
         }
         (void)hipEventRecord(ev_far, B);
         far_pending = true;
       } else if (!lowp) {
-        launch_lstage_copy(A, N, adv, b, w.lst[p], Y, w.fst, w.panel_k0);
+        launch_lstage_copy(A, N, left, b, w.lst[p], Y, w.fst, w.panel_k0);
       }
     } else {
       wait_far();
@@ -503,10 +519,10 @@ void factor_launches_la(mds_handle *h, hipStream_t s) {
       if (more) {
         TimedLaunch t(h, MDS_T_TRAILING, A);
         if (lowp)
-          launch_trailing_lp(A, h->precision, N, nb, adv, b, w.W, X32, Y32, w.M, w.src, w.fst,
+          launch_trailing_lp(A, h->precision, N, nb, rem, b, w.W, X32, Y32, w.M, w.src, w.fst,
                              w.panel_k0);
         else
-          launch_bk_trailing(A, N, nb, adv, b, w.W, X, Y, Y, w.src, w.fst, w.panel_k0);
+          launch_bk_trailing(A, N, nb, rem, b, w.W, X, Y, Y, w.src, w.fst, w.panel_k0);
       }
     }
   }
@@ -598,8 +614,8 @@ void factor_launches_mem(mds_handle *h, hipStream_t s) {
     }
     if ((long)N - (long)(b + 1) * nb > 0) {
       TimedLaunch t(h, MDS_T_TRAILING);
-      launch_bk_trailing(s, N, nb, nb, b, h->w.W, h->w.M, h->w.M, h->w.M, nullptr, h->w.fst,
-                         h->w.panel_k0);
+      launch_bk_trailing(s, N, nb, (long)N - (long)(b + 1) * nb, b, h->w.W, h->w.M, h->w.M,
+                         h->w.M, nullptr, h->w.fst, h->w.panel_k0);
     }
   }
 }
@@ -1247,6 +1263,7 @@ int mds_create(mds_handle **out, const mds_dims *dims, const mds_options *opts, 
   h->precision = prec;
   h->adv = pc.adv;
   h->max_panels = h->N / pc.adv + 2;
+  make_plan(h);
   h->ws_bytes = workspace_bytes;
   h->alpha_bk = (1.0 + std::sqrt(17.0)) / 8.0;
   char *base = (char *)workspace;
@@ -2258,7 +2275,12 @@ int mds_get_inv_ds(mds_handle *h, double *inv_d_host) {
 int mds_get_info(const mds_handle *h, mds_info *out) {
   if (!h || !out) return MDS_ENULL;
   out->nb = h->nb;
-  out->min_width = h->adv;
+  // fewest columns a panel factors, the last panel aside (the register
+  // tail's 16-column tile factors 15)
+  int mw = h->adv;
+  for (size_t b = 0; b + 1 < h->plan.size(); ++b)
+    mw = (int)std::min<long>(mw, h->plan[b].rows - h->plan[b].rows_after);
+  out->min_width = mw;
   out->panel = h->panel_lds ? 3 : h->panel_coop ? 2 : h->panel_reg ? 0 : 1;
   out->precision = h->precision;
   out->panel_threads = (h->panel_reg || h->panel_lds) ? h->panel_threads : 1024;

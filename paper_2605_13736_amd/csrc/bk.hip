@@ -610,13 +610,11 @@ void launch_bk_panel(hipStream_t s, int N, int nb, double alpha, double *M, doub
   k_bk_panel<<<1, NT, 0, s>>>(N, nb, alpha, M, W, dd, ds, ipiv, blk, st, panel_k0);
 }
 
-void launch_bk_trailing(hipStream_t s, int N, int nb, int adv, int slot, const double *W,
+void launch_bk_trailing(hipStream_t s, int N, int nb, long rem, int slot, const double *W,
                         const double *X, double *Y, const double *Lsrc, const int32_t *src,
                         const FacState *st, const int32_t *panel_k0) {
-  // every panel before this slot has at least adv columns, so the trailing
-  // matrix after slot `slot` has at most N - (slot+1)*adv rows; the kernel's
-  // tiles start up to 15 rows earlier (at a 16-row boundary)
-  const long rem = (long)N - (long)(slot + 1) * adv;
+  // rem bounds the rows of the trailing matrix after slot `slot`; the
+  // kernel's tiles start up to 15 rows earlier (at a 16-row boundary)
   if (rem <= 0) return;
   const long nt = (rem + 15 + TT - 1) / TT;
   const long tiles = nt * (nt + 1) / 2;
@@ -630,10 +628,9 @@ void launch_bk_trailing(hipStream_t s, int N, int nb, int adv, int slot, const d
   }
 }
 
-void launch_bk_trailing_part(hipStream_t s, int N, int nb, int adv, int slot, int part, int grid,
+void launch_bk_trailing_part(hipStream_t s, int N, int nb, long rem, int slot, int part, int grid,
                              const double *W, const double *X, double *Y, const double *Lsrc,
                              const int32_t *src, const FacState *st, const int32_t *panel_k0) {
-  const long rem = (long)N - (long)(slot + 1) * adv;
   if (rem <= 0 || nb + 1 > TS) return;
   const long nt = (rem + 15 + TT - 1) / TT;
   const long tiles = (part == 1) ? nt : (nt - 1) * nt / 2;
@@ -643,9 +640,9 @@ void launch_bk_trailing_part(hipStream_t s, int N, int nb, int adv, int slot, in
                                                 part);
 }
 
-void launch_lstage_copy(hipStream_t s, int N, int adv, int slot, const double *Lst, double *Lout,
+void launch_lstage_copy(hipStream_t s, int N, long rows, int slot, const double *Lst, double *Lout,
                         const FacState *st, const int32_t *panel_k0) {
-  const long rows = (long)N - (long)slot * adv;  // rows at the panel's start, at most
+  // rows: the rows at the panel's start, at most
   if (rows <= 0) return;
   const unsigned gx = (unsigned)std::min<long>((rows + 1023) / 1024, 64);
   k_lstage_copy<<<dim3(gx, (unsigned)(TS + 1)), 256, 0, s>>>(N, Lst, Lout, st, panel_k0, slot);

@@ -436,10 +436,9 @@ __global__ void k_vscale(int n, const double *__restrict__ s, double *__restrict
 
 }  // namespace
 
-void launch_trailing_lp(hipStream_t s, int mode, int N, int nb, int adv, int slot,
+void launch_trailing_lp(hipStream_t s, int mode, int N, int nb, long rem, int slot,
                         const double *W, const float *X, float *Y, const double *Lsrc,
                         const int32_t *src, const FacState *st, const int32_t *panel_k0) {
-  const long rem = (long)N - (long)(slot + 1) * adv;
   if (rem <= 0) return;
   const long nt = (rem + TT - 1) / TT;
   const long tiles = nt * (nt + 1) / 2;
@@ -462,11 +461,10 @@ void launch_trailing_lp(hipStream_t s, int mode, int N, int nb, int adv, int slo
     k_trailing_lp<1><<<(unsigned)tiles, 256, 0, s>>>(N, nb, W, X, Y, Lsrc, src, st, panel_k0, slot);
 }
 
-void launch_trailing_lp_part(hipStream_t s, int mode, int N, int nb, int adv, int slot, int part,
+void launch_trailing_lp_part(hipStream_t s, int mode, int N, int nb, long rem, int slot, int part,
                              int grid, const double *W, const float *X, float *Y,
                              const double *Lsrc, const int32_t *src, const FacState *st,
                              const int32_t *panel_k0) {
-  const long rem = (long)N - (long)(slot + 1) * adv;
   if (rem <= 0 || nb + 1 > TSL) return;
   const long nt = (rem + TT - 1) / TT;
   const long tiles = (part == 1) ? nt : (nt - 1) * nt / 2;

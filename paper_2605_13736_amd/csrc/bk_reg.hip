@@ -1,5 +1,7 @@
 // Register-resident Bunch-Kaufman panel kernel (Sec. 2.3): N <= 4096, or the
 // last rows of a cooperative factorization; the body is panel::panel_reg_dev.
+#include <algorithm>
+
 #include "panel_reg.hpp"
 
 namespace mds {
@@ -88,26 +90,34 @@ static void panel_reg(hipStream_t s, int threads, int N, int nb, double alpha, c
 #undef MDS_PANEL_REG
 }
 
-// Tail of a cooperative factorization: once at most 2 * 512 rows remain, one
-// workgroup of 512 threads holds them in its registers at the cooperative
-// panel's tile width (32), and a pivot step needs no grid-wide exchange.
-// rows bounds N - k0 from above (the host knows k0 >= panels * (nb - 1)).
-int bk_reg_tail_rows() { return 2 * TMAX; }
+// Tail of a cooperative factorization: once at most 2048 rows remain, one
+// workgroup of 512 threads holds them in its registers and a pivot step
+// needs no grid-wide exchange.  Measured on KKT systems of the tail's sizes
+// (factorization time): 2048 rows, 512 threads x 4 rows with a 16-column
+// tile 8.5 ms against 12.6 ms for the cooperative panel (two workgroups)
+// and its tail; 1024 rows, 512 x 2 with the 32-column tile 3.4 ms against
+// 4.0 for 1024 x 1; 512 rows, 512 x 1 1.55 ms against 1.66 for 256 x 2.
+// rows bounds N - k0 from above (the host's slot plan).
+int bk_reg_tail_rows() { return 4 * TMAX; }
+int bk_reg_tail_nb(int rows) { return (rows > 2 * TMAX) ? 16 : 32; }
 
 template <typename TX>
 static void panel_reg_tail(hipStream_t s, int rows, int N, int nb, double alpha, const TX *X,
                            double *Lout, int32_t *src_out, double *W, double *dd, double *ds,
                            int32_t *ipiv, int32_t *blk, FacState *st, int32_t *panel_k0) {
-  // up to 512 rows: 256 threads (fewer waves wait at each barrier of a step)
+  const int tnb = std::min(nb, bk_reg_tail_nb(rows));
   if (rows <= 256)
-    k_bk_panel_reg<256, 1, 32, TX><<<1, 256, 0, s>>>(N, nb, alpha, X, Lout, src_out, W, dd, ds,
+    k_bk_panel_reg<256, 1, 32, TX><<<1, 256, 0, s>>>(N, tnb, alpha, X, Lout, src_out, W, dd, ds,
                                                      ipiv, blk, st, panel_k0);
-  else if (rows <= 512)
-    k_bk_panel_reg<256, 2, 32, TX><<<1, 256, 0, s>>>(N, nb, alpha, X, Lout, src_out, W, dd, ds,
-                                                     ipiv, blk, st, panel_k0);
-  else  // rows beyond 1024 would break the caller's bound: the kernel's guard flags them
-    k_bk_panel_reg<TMAX, 2, 32, TX><<<1, TMAX, 0, s>>>(N, nb, alpha, X, Lout, src_out, W, dd, ds,
-                                                       ipiv, blk, st, panel_k0);
+  else if (rows <= TMAX)
+    k_bk_panel_reg<TMAX, 1, 32, TX><<<1, TMAX, 0, s>>>(N, tnb, alpha, X, Lout, src_out, W, dd,
+                                                       ds, ipiv, blk, st, panel_k0);
+  else if (rows <= 2 * TMAX)
+    k_bk_panel_reg<TMAX, 2, 32, TX><<<1, TMAX, 0, s>>>(N, tnb, alpha, X, Lout, src_out, W, dd,
+                                                       ds, ipiv, blk, st, panel_k0);
+  else  // rows beyond 2048 would break the caller's bound: the kernel's guard flags them
+    k_bk_panel_reg<TMAX, 4, 16, TX><<<1, TMAX, 0, s>>>(N, tnb, alpha, X, Lout, src_out, W, dd,
+                                                       ds, ipiv, blk, st, panel_k0);
 }
 
 void launch_bk_panel_reg_tail(hipStream_t s, int rows, int N, int nb, double alpha,

@@ -70,6 +70,17 @@ struct PanelPrev {
   int amask;            // the strip starts at (k0 & amask): ~15 (FP64 tiles), -1 (FP32)
 };
 
+// One slot of a factorization's launch sequence (one panel launch and its
+// trailing update): tail_nb 0 for the handle's panel kernel, else the tile
+// width of the register tail; rows bounds the rows left at the slot's start
+// and rows_after those left for its trailing update (the device's progress
+// is not known to the host; every panel factors at least its tile width - 1
+// columns unless the matrix ends).
+struct SlotPlan {
+  int tail_nb;
+  long rows, rows_after;
+};
+
 // Pointers into the caller's workspace.
 struct Work {
   double *M;          // N x N, full symmetric, column-major; L after factoring
@@ -168,6 +179,7 @@ struct mds_handle {
   int panel_threads = 512; // its workgroup size
   int precision = MDS_FP64;
   int adv = 16;            // least number of columns a panel factors
+  std::vector<mds::SlotPlan> plan;  // slots of a factorization (register and memory panels)
   mds::Work w{};
   size_t ws_bytes = 0;
   mds_problem P{};
@@ -246,19 +258,21 @@ void launch_fac_reset(hipStream_t s, FacState *st, int32_t *panel_k0);
 void launch_bk_panel(hipStream_t s, int N, int nb, double alpha, double *M, double *W,
                      double *dd, double *ds, int32_t *ipiv, int32_t *blk, FacState *st,
                      int32_t *panel_k0);
-void launch_bk_trailing(hipStream_t s, int N, int nb, int adv, int slot, const double *W,
+// rem: an upper bound of the rows of the trailing matrix after the panel of
+// slot `slot` (sizes the grid; 0 or less: nothing to update)
+void launch_bk_trailing(hipStream_t s, int N, int nb, long rem, int slot, const double *W,
                         const double *X, double *Y, const double *Lsrc, const int32_t *src,
                         const FacState *st, const int32_t *panel_k0);
 // look-ahead parts of the trailing update of slot `slot` (nb + 1 <= 36):
 // part 1 the near strip (the first 64-column tile column), part 2 the rest;
 // both persistent over at most `grid` workgroups; Lsrc holds the
 // panel's multipliers staged (row i, column t at Lsrc[i + t N])
-void launch_bk_trailing_part(hipStream_t s, int N, int nb, int adv, int slot, int part, int grid,
+void launch_bk_trailing_part(hipStream_t s, int N, int nb, long rem, int slot, int part, int grid,
                              const double *W, const double *X, double *Y, const double *Lsrc,
                              const int32_t *src, const FacState *st, const int32_t *panel_k0);
 // staged multipliers of slot `slot` into their place in Lout (columns
 // k0 .. kend - 1, rows below the diagonal)
-void launch_lstage_copy(hipStream_t s, int N, int adv, int slot, const double *Lst, double *Lout,
+void launch_lstage_copy(hipStream_t s, int N, long rows, int slot, const double *Lst, double *Lout,
                         const FacState *st, const int32_t *panel_k0);
 
 // bk_reg.hip: register-resident panel for N <= 4096 (X in FP64 or FP32),
@@ -266,8 +280,10 @@ void launch_lstage_copy(hipStream_t s, int N, int adv, int slot, const double *L
 int bk_reg_rows(int N, int threads);
 int bk_reg_nb(int N, int threads);
 // register panel over the last rows of a cooperative factorization (rows >=
-// N - k0, rows <= bk_reg_tail_rows(), nb <= 32)
+// N - k0, rows <= bk_reg_tail_rows(), nb <= 32); it factors at least
+// bk_reg_tail_nb(rows) - 1 columns per launch (unless the matrix ends)
 int bk_reg_tail_rows();
+int bk_reg_tail_nb(int rows);
 void launch_bk_panel_reg_tail(hipStream_t s, int rows, int N, int nb, double alpha,
                               const double *X, double *Lout, int32_t *src_out, double *W,
                               double *dd, double *ds, int32_t *ipiv, int32_t *blk, FacState *st,
@@ -332,11 +348,11 @@ void launch_bk_lds(hipStream_t s, int threads, int N, double alpha, double *M, d
                    double *ds, int32_t *ipiv, int32_t *blk, int32_t *perm, FacState *st);
 
 // bk_lp.hip: FP32-storage trailing update (mode MDS_FP32 or MDS_BF16 products)
-void launch_trailing_lp(hipStream_t s, int mode, int N, int nb, int adv, int slot,
+void launch_trailing_lp(hipStream_t s, int mode, int N, int nb, long rem, int slot,
                         const double *W, const float *X, float *Y, const double *Lsrc,
                         const int32_t *src, const FacState *st, const int32_t *panel_k0);
 // look-ahead parts (as launch_bk_trailing_part; Lsrc in place, not staged)
-void launch_trailing_lp_part(hipStream_t s, int mode, int N, int nb, int adv, int slot, int part,
+void launch_trailing_lp_part(hipStream_t s, int mode, int N, int nb, long rem, int slot, int part,
                              int grid, const double *W, const float *X, float *Y,
                              const double *Lsrc, const int32_t *src, const FacState *st,
                              const int32_t *panel_k0);
