@@ -508,7 +508,9 @@ __global__ __launch_bounds__(256) void k_bk_trailing_ps(int N, int nb,
   const int nt = (N - a0 + TT - 1) / TT;
   // plain row-major order: measured at N = 16384, the super-tile order of
   // tile_order.hpp cut this kernel's fetched bytes by 17% but made it 3.5%
-  // slower (188.8 against 182.4 us per launch); the FP32 update keeps it
+  // slower (188.8 against 182.4 us per launch), and as the look-ahead's rest
+  // of the update 4% slower (113.0 against 108.5 ms per factorization); the
+  // FP32 update keeps it
   const bool xcd = false;
   const long nslots = part_slots(part, nt, xcd);
   const size_t ld = (size_t)N;

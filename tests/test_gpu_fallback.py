@@ -24,13 +24,15 @@ def say(msg):
     print(f"[gpu-case] {msg}", flush=True)
 
 
-def test_cooperative_abort_refactors_with_memory_panel():
+@pytest.mark.parametrize("lookahead", ["off", "on"])
+def test_cooperative_abort_refactors_with_memory_panel(lookahead):
     N = 2200
     prob = synth.make_problem(550, 8000, N - 550, 4, cfg=350)
     st = synth.kkt_state(prob, 0, (-2.0, 2.0))
-    say(f"cooperative abort fallback N={N}")
-    S = mds.solver_for(prob)
+    say(f"cooperative abort fallback N={N} lookahead={lookahead}")
+    S = mds.solver_for(prob, lookahead=lookahead)
     assert S.info()["panel"] == "coop"
+    assert (S.info()["lookahead_cus"] > 0) == (lookahead == "on")
     S.condense(st["sigma_d"], st["dsbase"])
     _, inn0, _ = S.factor_inertia()
     ipiv0 = S.get_pivots()
