@@ -44,9 +44,9 @@ FP32_MFMA_PEAK_TFS = 157.3
 # the counters of a 256 MiB copy (the profile file gives the commands and the
 # factors); valid for the kernel source and workload as profiled.
 MEASURED_TRAFFIC = {
-    ("k_bk_trailing_la", 16384): (860338328.5, "profiles/bk_trailing_kkt_n16384.md"),
-    ("k_bk_trailing", 4096): (52698050.0, "profiles/bk_trailing_ipm_newton_step_n4096.md"),
-    ("k_bk_panel_coop", 4096): (3669981.0, "profiles/bk_panel_coop_ipm_newton_step_n4096.md"),
+    ("k_bk_trailing_la", 16384): (807296431.2, "profiles/bk_trailing_kkt_n16384.md"),
+    ("k_bk_trailing", 4096): (45959473.4, "profiles/bk_trailing_ipm_newton_step_n4096.md"),
+    ("k_bk_panel_coop", 4096): (4594730.0, "profiles/bk_panel_coop_ipm_newton_step_n4096.md"),
 }
 KERNEL_OF_CLASS = {"panel_tail": "k_bk_panel_reg", "trailing": "k_bk_trailing",
                    "solve": "k_trsv_fwd+k_trsv_bwd", "condense": "k_condense_dense",
@@ -77,6 +77,52 @@ def trailing_bytes_per_launch(N, w, elem=8.0):
     while k0 + w < N:
         n = N - (k0 + w)
         total += (n * (n + 1) / 2) * elem * 2 + 2.0 * n * w * 8.0
+        cnt += 1
+        k0 += w
+    return total / max(cnt, 1)
+
+
+def slot_widths(N, nb=32, tail_rows=2048):
+    """Columns each panel launch factors at least, in the library's slot plan
+    for the automatic cooperative factorization: nb - 1 while more than
+    tail_rows rows remain, then the register tail (16-column tile above 1024
+    rows, the 32-column one below).  Panels end on these widths except where
+    a 2x2 pivot closes a panel one column later."""
+    rows, ws = N, []
+    while rows > 0:
+        if rows <= tail_rows:
+            a = min(16 if rows > 1024 else 32, nb) - 1
+        else:
+            a = nb - 1
+        ws.append(a)
+        rows -= a
+    return ws
+
+
+def trailing_bytes_plan(N, nb=32, elem=8.0):
+    """Algorithmic bytes of one trailing update averaged over the slot plan's
+    updates (per update as trailing_bytes_per_launch, at each panel's own
+    width); returns (bytes per update, updates per factorization)."""
+    total, cnt, k0 = 0.0, 0, 0
+    for w in slot_widths(N, nb):
+        n = N - (k0 + w)
+        if n <= 0:
+            break
+        total += (n * (n + 1) / 2) * elem * 2 + 2.0 * n * w * 8.0
+        cnt += 1
+        k0 += w
+    return total / max(cnt, 1), cnt
+
+
+def trailing_flops_plan(N, nb=32):
+    """Flops of one trailing update (2 w per lower entry) averaged over the
+    slot plan's updates."""
+    total, cnt, k0 = 0.0, 0, 0
+    for w in slot_widths(N, nb):
+        n = N - (k0 + w)
+        if n <= 0:
+            break
+        total += (n * (n + 1) / 2) * 2.0 * w
         cnt += 1
         k0 += w
     return total / max(cnt, 1)
@@ -196,8 +242,6 @@ def roofline_of(tim, efacs, N, nb, pstats=None, xfloor=None):
     measured exchange round trip)."""
     fac_ms = factor_ms_of(tim, efacs)
     factor_tfs = (N ** 3 / 3.0) / (fac_ms / 1e3) / 1e12
-    npan = tim["panel"]["launches"] + tim["panel_tail"]["launches"]
-    w = N / max(npan / max(efacs, 1), 1)
     trl = tim["trailing"]
     near = tim.get("near", {"ms": 0.0, "launches": 0})
     la = near["launches"] > 0
@@ -205,13 +249,14 @@ def roofline_of(tim, efacs, N, nb, pstats=None, xfloor=None):
     # with look-ahead one update is the near strip (reserved units) plus the
     # rest (the other units, beside the next panel)
     avg_s = (trl["ms"] + near["ms"]) / 1e3 / nl
-    per_launch = trailing_bytes_per_launch(N, w)
+    # the slot plan's widths (cooperative panels, then the register tail)
+    per_launch, _ = trailing_bytes_plan(N, nb)
     meas = MEASURED_TRAFFIC.get(("k_bk_trailing_la" if la else "k_bk_trailing", N))
     trailing = dict(kernel="k_bk_trailing_ps" + (" (near strip + rest)" if la else ""),
                     bound="hbm", achieved=per_launch / avg_s / 1e9,
                     peak=HBM_PEAK_GBS, unit="GB/s", frac=per_launch / avg_s / 1e9 / HBM_PEAK_GBS,
                     traffic=meas[0] if meas else None, bytes_per_launch=per_launch,
-                    flops_per_launch=trailing_flops_per_launch(N, w),
+                    flops_per_launch=trailing_flops_plan(N, nb),
                     avg_launch_us=avg_s * 1e6, launches=nl,
                     ms_per_factorization=(trl["ms"] + near["ms"]) / max(efacs, 1))
     if la:

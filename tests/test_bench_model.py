@@ -37,3 +37,23 @@ def test_trailing_bytes_small_case():
     got32 = bench.trailing_bytes_per_launch(10, 4, elem=4.0)
     tot32 = sum(8.0 * n * (n + 1) / 2 + 2 * 8.0 * n * 4 for n in (6, 2))
     assert got32 == pytest.approx(tot32 / 2)
+
+
+@pytest.mark.parametrize("N", [4096, 16384, 2049, 1000])
+def test_slot_plan_widths(N):
+    # the widths cover the matrix; above 2048 rows every panel is nb - 1
+    # wide, then 15 down to 1024 rows and 31 below (the library's plan)
+    ws = bench.slot_widths(N)
+    assert sum(ws) >= N and sum(ws[:-1]) < N
+    rows = N
+    for w in ws:
+        assert w == (31 if rows > 2048 or rows <= 1024 else 15)
+        rows -= w
+
+
+def test_trailing_bytes_plan_reduces_to_uniform_width():
+    # without a tail region (N <= 1024 rows: every panel 31 wide) the plan's
+    # average equals the uniform-width model
+    got, cnt = bench.trailing_bytes_plan(1000)
+    assert got == pytest.approx(bench.trailing_bytes_per_launch(1000, 31))
+    assert cnt == (1000 - 1) // 31
