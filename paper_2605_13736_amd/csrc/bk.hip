@@ -326,7 +326,7 @@ __global__ __launch_bounds__(256) void k_bk_trailing(int N, int nb, const double
                                                      const int32_t *__restrict__ src,
                                                      const FacState *__restrict__ st,
                                                      const int32_t *__restrict__ panel_k0,
-                                                     int slot) {
+                                                     int slot, int part) {
   // the staged panels: W rows c0.., L rows i0..
   __shared__ double s_buf[2 * TT * TS1];
   double *s_w = s_buf, *s_l = s_buf + TT * TS1;
@@ -340,12 +340,18 @@ __global__ __launch_bounds__(256) void k_bk_trailing(int N, int nb, const double
   // N is a multiple of 16); rows and columns below kend are masked
   const int a0 = kend & ~15;
   const int nt = (N - a0 + TT - 1) / TT;
-  // triangular tile index -> (ti >= tj)
+  // look-ahead's near strip (part 1): tile (blockIdx.x, 0), the multipliers
+  // staged; otherwise triangular tile index -> (ti >= tj)
+  const int lk0 = (part == 1) ? 0 : k0;
   const int x = blockIdx.x;
   int ti = (int)((sqrt(8.0 * (double)x + 1.0) - 1.0) * 0.5);
   while ((ti + 1) * (ti + 2) / 2 <= x) ++ti;
   while (ti * (ti + 1) / 2 > x) --ti;
-  const int tj = x - ti * (ti + 1) / 2;
+  int tj = x - ti * (ti + 1) / 2;
+  if (part == 1) {
+    ti = x;
+    tj = 0;
+  }
   if (ti >= nt) return;
   const int i0 = a0 + ti * TT, c0 = a0 + tj * TT;
   const size_t ld = (size_t)N;
@@ -401,7 +407,7 @@ __global__ __launch_bounds__(256) void k_bk_trailing(int N, int nb, const double
       const int e = tid + 256 * u, r = e & (TT - 1), t = e >> 6;
       const int c = c0 + r, i = i0 + r;
       vw[u] = (t < tw && c >= kend && c < N) ? W[(size_t)c + (size_t)(tb + t) * ld] : 0.0;
-      vl[u] = (t < tw && i >= kend && i < N) ? Lsrc[(size_t)i + (size_t)(k0 + tb + t) * ld] : 0.0;
+      vl[u] = (t < tw && i >= kend && i < N) ? Lsrc[(size_t)i + (size_t)(lk0 + tb + t) * ld] : 0.0;
     }
 #pragma unroll
     for (int u = 0; u < TSTAGE; ++u) {
@@ -626,7 +632,8 @@ void launch_bk_trailing(hipStream_t s, int N, int nb, long rem, int slot, const 
     k_bk_trailing_ps<<<(unsigned)grid, 256, 0, s>>>(N, nb, W, X, Y, Lsrc, src, st, panel_k0,
                                                      slot, 0);
   } else {
-    k_bk_trailing<<<(unsigned)tiles, 256, 0, s>>>(N, nb, W, X, Y, Lsrc, src, st, panel_k0, slot);
+    k_bk_trailing<<<(unsigned)tiles, 256, 0, s>>>(N, nb, W, X, Y, Lsrc, src, st, panel_k0, slot,
+                                                  0);
   }
 }
 
@@ -637,6 +644,12 @@ void launch_bk_trailing_part(hipStream_t s, int N, int nb, long rem, int slot, i
   const long nt = (rem + 15 + TT - 1) / TT;
   const long tiles = (part == 1) ? nt : (nt - 1) * nt / 2;
   if (tiles <= 0) return;
+  if (part == 1) {
+    // one tile per workgroup (104 VGPRs: more workgroups per compute unit
+    // than the persistent form's two)
+    k_bk_trailing<<<(unsigned)nt, 256, 0, s>>>(N, nb, W, X, Y, Lsrc, src, st, panel_k0, slot, 1);
+    return;
+  }
   const long g = std::min(tiles, (long)std::max(grid, 1));
   k_bk_trailing_ps<<<(unsigned)g, 256, 0, s>>>(N, nb, W, X, Y, Lsrc, src, st, panel_k0, slot,
                                                 part);
