@@ -178,7 +178,17 @@ __global__ __launch_bounds__(TB) void k_trsv_fwd(int N, const double *__restrict
     const int rr = e & 63, cc = e >> 6;
     s_d[rr][cc] = (rr > cc && r0 + rr < N) ? L[(size_t)(r0 + rr) + (size_t)(r0 + cc) * ld] : 0.0;
   }
+  // this row's right-hand side: only this workgroup writes it, at its end
+  const double zrow = live ? z[row] : 0.0;
   double acc = 0.0;
+  // L of the next dependency block does not depend on the flags: it is
+  // loaded before the wait, so that the last link of the chain (block i - 1)
+  // finds it in registers
+  double pf[16];
+  if (i > 0) {
+#pragma unroll
+    for (int t = 0; t < 16; ++t) pf[t] = live ? L[(size_t)row + (size_t)(g * 16 + t) * ld] : 0.0;
+  }
   for (int j = 0; j < i;) {
     if (tid == 0) s_nr = wait_ready(flags, j, i, 1, epoch, err);
     __syncthreads();
@@ -192,8 +202,15 @@ __global__ __launch_bounds__(TB) void k_trsv_fwd(int N, const double *__restrict
         const int c0 = (j + u) * BS + g * 16;
         yv[u] = (r < 16) ? ld_sol(&z[c0 + r]) : 0.0;
 #pragma unroll
-        for (int t = 0; t < 16; ++t) lv[u][t] = live ? L[(size_t)row + (size_t)(c0 + t) * ld] : 0.0;
+        for (int t = 0; t < 16; ++t)
+          lv[u][t] = (u == 0) ? pf[t] : (live ? L[(size_t)row + (size_t)(c0 + t) * ld] : 0.0);
       }
+    }
+    j += nr;
+    if (j < i) {
+#pragma unroll
+      for (int t = 0; t < 16; ++t)
+        pf[t] = live ? L[(size_t)row + (size_t)(j * BS + g * 16 + t) * ld] : 0.0;
     }
 #pragma unroll
     for (int u = 0; u < NR; ++u) {
@@ -202,12 +219,11 @@ __global__ __launch_bounds__(TB) void k_trsv_fwd(int N, const double *__restrict
         for (int t = 0; t < 16; ++t) acc = fma(-lv[u][t], wave::lane_read(yv[u], t), acc);
       }
     }
-    j += nr;
   }
   s_part[g][r] = acc;
   __syncthreads();
   if (g == 0) {
-    double v = live ? z[row] : 0.0;
+    double v = zrow;
     v += (s_part[0][r] + s_part[1][r]) + (s_part[2][r] + s_part[3][r]);
     for (int c = 0; c < BS - 1; ++c) {
       const double yc = wave::lane_read(v, c);
@@ -238,32 +254,58 @@ __global__ __launch_bounds__(TB) void k_trsv_bwd(int N, int nblk, const double *
     s_d[rr][cc] = (rr > cc && r0 + rr < N) ? L[(size_t)(r0 + rr) + (size_t)(r0 + cc) * ld] : 0.0;
   }
   const int cbase = r0 + g * 16;  // this wave's 16 columns of the block
+  // this row's right-hand side: only this workgroup writes it, at its end
+  const double zrow = (r0 + r < N) ? z[r0 + r] : 0.0;
   double acc[16];
 #pragma unroll
   for (int t = 0; t < 16; ++t) acc[t] = 0.0;
+  // L of the next dependency block (row q of it, this wave's 16 columns) is
+  // loaded before the wait, as in the forward solve
+  double pf[16];
+  if (nblk - 1 > i) {
+    const int q = (nblk - 1) * BS + r;
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+      const int c = cbase + t;
+      pf[t] = (q < N && c < N) ? L[(size_t)q + (size_t)c * ld] : 0.0;
+    }
+  }
   for (int j = nblk - 1; j > i;) {
     if (tid == 0) s_nr = wait_ready(flags, j, i, -1, epoch, err);
     __syncthreads();
     const int nr = s_nr;
     __syncthreads();
     if (nr == 0) return;
+    double xv[NR], lv[NR][16];
 #pragma unroll
     for (int u = 0; u < NR; ++u) {
       if (u < nr) {
         const int q = (j - u) * BS + r;
         const bool ok = q < N;
-        const double xq = ok ? ld_sol(&z[q]) : 0.0;
-        double lv[16];
+        xv[u] = ok ? ld_sol(&z[q]) : 0.0;
 #pragma unroll
         for (int t = 0; t < 16; ++t) {
           const int c = cbase + t;
-          lv[t] = (ok && c < N) ? L[(size_t)q + (size_t)c * ld] : 0.0;
+          lv[u][t] = (u == 0) ? pf[t] : ((ok && c < N) ? L[(size_t)q + (size_t)c * ld] : 0.0);
         }
-#pragma unroll
-        for (int t = 0; t < 16; ++t) acc[t] = fma(-lv[t], xq, acc[t]);
       }
     }
     j -= nr;
+    if (j > i) {
+      const int q = j * BS + r;
+#pragma unroll
+      for (int t = 0; t < 16; ++t) {
+        const int c = cbase + t;
+        pf[t] = (q < N && c < N) ? L[(size_t)q + (size_t)c * ld] : 0.0;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < NR; ++u) {
+      if (u < nr) {
+#pragma unroll
+        for (int t = 0; t < 16; ++t) acc[t] = fma(-lv[u][t], xv[u], acc[t]);
+      }
+    }
   }
 #pragma unroll
   for (int t = 0; t < 16; ++t) s_red[g * 16 + t][r] = acc[t];
@@ -273,7 +315,7 @@ __global__ __launch_bounds__(TB) void k_trsv_bwd(int N, int nblk, const double *
     const bool live = row < N;
     double s = 0.0;
     for (int k = 0; k < BS; ++k) s += s_red[r][k];
-    double v = (live ? z[row] : 0.0) + s;
+    double v = (live ? zrow : 0.0) + s;
     // unit upper L11': last row first
     for (int c = BS - 1; c > 0; --c) {
       const double xc = wave::lane_read(v, c);
