@@ -43,12 +43,31 @@ __global__ __launch_bounds__(SW) void k_std_sweep(int N, const int32_t *__restri
                                                   int32_t *__restrict__ colpanel) {
   extern __shared__ int s_h[];
   __shared__ int s_p[kMaxNb + 2], s_q[kMaxNb + 2];
+  static_assert(kMaxNb + 1 <= 128, "a panel's pivot entries fit two per lane of one wave");
   const int tid = threadIdx.x;
   const int np = st->npanel;
   for (int x = tid; x < N; x += SW) s_h[x] = x;
+  // panel b's bounds and pivot entries are loaded one panel ahead, so that
+  // their memory latency overlaps the previous panel's work
+  int k1 = 0, k0 = 0, bk = 0, iv = 0;
+  if (np > 0) {
+    k1 = panel_k0[np];
+    k0 = panel_k0[np - 1];
+    if (tid < k1 - k0) {
+      bk = blk[k0 + tid];
+      iv = ipiv[k0 + tid];
+    }
+  }
   __syncthreads();
   for (int b = np - 1; b >= 0; --b) {
-    const int k0 = panel_k0[b], k1 = panel_k0[b + 1];
+    int k0n = 0, bkn = 0, ivn = 0;
+    if (b > 0) {
+      k0n = panel_k0[b - 1];
+      if (tid < k0 - k0n) {
+        bkn = blk[k0n + tid];
+        ivn = ipiv[k0n + tid];
+      }
+    }
     int32_t *hb = hmap + (size_t)b * N;
     for (int x = k1 + tid; x < N; x += SW) hb[x] = s_h[x];
     for (int c = k0 + tid; c < k1; c += SW) colpanel[c] = b;
@@ -56,22 +75,53 @@ __global__ __launch_bounds__(SW) void k_std_sweep(int N, const int32_t *__restri
     // gives (k, q) for a 1x1 pivot, (k + 1, q) for the first row of a 2x2
     // one and nothing for its second row
     if (tid < k1 - k0) {
-      const int k = k0 + tid, bk = blk[k], iv = ipiv[k];
+      const int k = k0 + tid;
       s_p[tid] = (bk == 1) ? k : (bk == 2) ? k + 1 : -1;
       s_q[tid] = (bk == 1) ? iv - 1 : -iv - 1;
     }
     __syncthreads();
-    if (tid == 0) {
-      for (int e = k1 - k0 - 1; e >= 0; --e) {
-        const int p = s_p[e], q = s_q[e];
-        if (p >= 0 && p != q) {
-          const int t = s_h[p];
-          s_h[p] = s_h[q];
-          s_h[q] = t;
+    // wave 0 holds entries e and e + 64 in lane e and applies only those that
+    // move a row, in reverse pivot order, taking their positions from the
+    // lanes that hold them (one LDS read per lane instead of two per entry)
+    if (tid < 64) {
+      const int w = k1 - k0;
+      int p0 = -1, q0 = 0, p1 = -1, q1 = 0;
+      if (tid < w) {
+        p0 = s_p[tid];
+        q0 = s_q[tid];
+      }
+      if (tid + 64 < w) {
+        p1 = s_p[tid + 64];
+        q1 = s_q[tid + 64];
+      }
+      unsigned long long m = __ballot(p1 >= 0 && p1 != q1);
+      while (m) {
+        const int e = 63 - __clzll((long long)m);
+        m &= ~(1ull << e);
+        const int pe = wave::lane_read(p1, e), qe = wave::lane_read(q1, e);
+        if (tid == 0) {
+          const int x = s_h[pe];
+          s_h[pe] = s_h[qe];
+          s_h[qe] = x;
+        }
+      }
+      m = __ballot(p0 >= 0 && p0 != q0);
+      while (m) {
+        const int e = 63 - __clzll((long long)m);
+        m &= ~(1ull << e);
+        const int pe = wave::lane_read(p0, e), qe = wave::lane_read(q0, e);
+        if (tid == 0) {
+          const int x = s_h[pe];
+          s_h[pe] = s_h[qe];
+          s_h[qe] = x;
         }
       }
     }
     __syncthreads();
+    k1 = k0;
+    k0 = k0n;
+    bk = bkn;
+    iv = ivn;
   }
   for (int x = tid; x < N; x += SW) perm[x] = s_h[x];
 }
