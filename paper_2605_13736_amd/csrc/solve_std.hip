@@ -29,6 +29,7 @@ namespace mds {
 namespace {
 
 constexpr int SW = 1024;  // sweep workgroup
+constexpr int AT = 1024;  // standard-form copy workgroup (one column)
 constexpr int BS = 64;    // triangular-solve block (one wave's rows)
 constexpr int TB = 256;   // triangular-solve workgroup: 4 waves
 constexpr int NR = 4;     // dependency blocks consumed per batch
@@ -129,7 +130,7 @@ __global__ __launch_bounds__(SW) void k_std_sweep(int N, const int32_t *__restri
 // Column c: rows c+1 .. k1-1 (inside its panel) stay, rows x >= k1 go to
 // hb[x].  Reads column c from the buffer its panel wrote and writes column c
 // of Lstd; no other workgroup touches column c of either buffer.
-__global__ __launch_bounds__(256) void k_std_apply(int N, const double *M0, const double *M1,
+__global__ __launch_bounds__(AT) void k_std_apply(int N, const double *M0, const double *M1,
                                                    int pingpong,
                                                    const int32_t *__restrict__ panel_k0,
                                                    const int32_t *__restrict__ colpanel,
@@ -142,13 +143,32 @@ __global__ __launch_bounds__(256) void k_std_apply(int N, const double *M0, cons
   const double *src = (pingpong && (b & 1) == 0) ? M1 : M0;
   const size_t co = (size_t)c * (size_t)N;
   const int32_t *hb = hmap + (size_t)b * N;
-  for (int x = k1 + tid; x < N; x += 256) s_col[hb[x] - k1] = src[co + x];
+  // a column takes up to N * 8 B of LDS, so one workgroup may hold a whole
+  // compute unit: 1024 threads with four loads each in flight keep enough
+  // reads outstanding for the copy to run at memory speed
+  for (int x = k1 + tid; x < N; x += 4 * AT) {
+    double v[4];
+    int h[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int y = x + u * AT;
+      if (y < N) {
+        v[u] = src[co + y];
+        h[u] = hb[y];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int y = x + u * AT;
+      if (y < N) s_col[h[u] - k1] = v[u];
+    }
+  }
   // rows inside the panel: fewer than kMaxNb of them
   const int x0 = c + 1 + tid;
   const double vin = (tid < kMaxNb && x0 < k1) ? src[co + x0] : 0.0;
   __syncthreads();
   if (tid < kMaxNb && x0 < k1) Lstd[co + x0] = vin;
-  for (int y = k1 + tid; y < N; y += 256) Lstd[co + y] = s_col[y - k1];
+  for (int y = k1 + tid; y < N; y += AT) Lstd[co + y] = s_col[y - k1];
 }
 
 // z[h(x)] = v[x]; also advances the solve epoch
@@ -399,7 +419,7 @@ void launch_std_form(hipStream_t s, int N, const double *M0, const double *M1, i
   if (N <= 0) return;
   k_std_sweep<<<1, SW, sizeof(int32_t) * (size_t)N, s>>>(N, ipiv, blk, panel_k0, st, hmap, perm,
                                                          colpanel);
-  k_std_apply<<<(unsigned)N, 256, sizeof(double) * (size_t)N, s>>>(N, M0, M1, pingpong, panel_k0,
+  k_std_apply<<<(unsigned)N, AT, sizeof(double) * (size_t)N, s>>>(N, M0, M1, pingpong, panel_k0,
                                                                     colpanel, hmap, Lstd);
 }
 
