@@ -159,7 +159,7 @@ Layout make_layout(const mds_dims &d, int nb, bool pingpong, int precision, int 
   bytes[S_Z] = bytes[S_Z2] = 8 * N;
   bytes[S_HMAP] = 4 * maxp * N;
   bytes[S_PERM] = bytes[S_COLP] = 4 * N;
-  bytes[S_TRSV] = 4 * (4 + 2 * (size_t)std_solve_blocks((int)N));
+  bytes[S_TRSV] = std_trsv_bytes((int)N);
   bytes[S_SIG] = bytes[S_RX] = 8 * nx;
   bytes[S_RY] = 8 * m;
   bytes[S_DSB] = 8 * ns;
@@ -1369,7 +1369,7 @@ int mds_create(mds_handle **out, const mds_dims *dims, const mds_options *opts, 
     B.tmp2 = D(S_BT2);
   }
   if (std_prepare() != hipSuccess || bk_lds_prepare() != hipSuccess ||
-      hipMemsetAsync(w.trsv, 0, 4 * (4 + 2 * (size_t)std_solve_blocks(h->N)), h->stream) !=
+      hipMemsetAsync(w.trsv, 0, std_trsv_bytes(h->N), h->stream) !=
           hipSuccess ||
       hipMemsetAsync(w.xch, 0, 8 * 2 * (size_t)kCoopMaxP * kCoopSlotWords, h->stream) !=
           hipSuccess ||

@@ -374,13 +374,15 @@ void launch_scale(hipStream_t s, int64_t n, double alpha, const double *w, doubl
 // multi-workgroup solve
 int std_max_n();
 int std_solve_blocks(int N);
+size_t std_trsv_bytes(int N);  // the solve's control words (trsv below)
 hipError_t std_prepare();
 void launch_std_form(hipStream_t s, int N, const double *M0, const double *M1, int pingpong,
                      const int32_t *ipiv, const int32_t *blk, const int32_t *panel_k0,
                      const FacState *st, int32_t *hmap, int32_t *perm, int32_t *colpanel,
                      double *Lstd);
-// out = M^{-1} v through P, L, D; z is scratch (N); trsv: epoch, error word,
-// pad, 2 * std_solve_blocks(N) flags
+// out = M^{-1} v through P, L, D; z is scratch (N); trsv (std_trsv_bytes(N),
+// 8-byte aligned, zeroed once when the handle is made): epoch, error word,
+// pad, then the tagged solution words of the triangular solves
 void launch_std_solve(hipStream_t s, int N, const double *Lstd, const double *dd,
                       const double *ds, const int32_t *blk, const int32_t *perm, const double *v,
                       double *z, double *out, int32_t *trsv);

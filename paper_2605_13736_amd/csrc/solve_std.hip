@@ -32,7 +32,6 @@ constexpr int SW = 1024;  // sweep workgroup
 constexpr int AT = 1024;  // standard-form copy workgroup (one column)
 constexpr int BS = 64;    // triangular-solve block (one wave's rows)
 constexpr int TB = 256;   // triangular-solve workgroup: 4 waves
-constexpr int NR = 4;     // dependency blocks consumed per batch
 constexpr unsigned long long kWaitTicks = 1ull << 26;  // ~0.7 s of the 100 MHz clock
 
 __global__ __launch_bounds__(SW) void k_std_sweep(int N, const int32_t *__restrict__ ipiv,
@@ -204,94 +203,102 @@ __global__ void k_diag_solve(int N, const double *__restrict__ dd, const double 
   }
 }
 
-__device__ inline int ld_flag(const int32_t *f) {
-  return __hip_atomic_load(f, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+// Solved values are published as tagged words: the double of row x goes
+// out as two 64-bit words (its low and its high half, each with the phase's
+// tag in the upper 32 bits), stored with relaxed single-copy-atomic stores.
+// A consumer polls the words themselves: matching tags mean the payload is
+// this phase's value, so no flag, fence or second round trip is needed.  The
+// tag is 2 epoch + phase (0 forward, 1 backward) and the epoch grows with
+// every solve, so words left by an earlier phase or solve never match.
+__device__ inline void pub_sol(uint64_t *tw, int x, double v, uint32_t tag) {
+  const uint64_t b = (uint64_t)__double_as_longlong(v), hi = (uint64_t)tag << 32;
+  __hip_atomic_store(&tw[2 * (size_t)x], hi | (b & 0xffffffffull), __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(&tw[2 * (size_t)x + 1], hi | (b >> 32), __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__device__ inline double ld_sol(const double *p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+__device__ inline bool try_sol(const uint64_t *tw, int x, uint32_t tag, double &v) {
+  const uint64_t w0 = __hip_atomic_load(&tw[2 * (size_t)x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const uint64_t w1 =
+      __hip_atomic_load(&tw[2 * (size_t)x + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  v = __longlong_as_double((long long)((w1 << 32) | (w0 & 0xffffffffull)));
+  return (uint32_t)(w0 >> 32) == tag && (uint32_t)(w1 >> 32) == tag;
 }
 
-// Thread 0: wait for flag[j] (dependencies are consumed in direction dir),
-// then count how many of the following blocks are also ready (NR at most,
-// stopping before jend).  Returns 0 on timeout.
-__device__ int wait_ready(const int32_t *flags, int j, int jend, int dir, int epoch,
-                          int32_t *err) {
+// Called by every lane of a wave: each lane with need waits for the value of
+// row x.  Bounded by the wall clock: on expiry the error word is set and
+// false returned (the caller then ends without publishing, so its consumers
+// expire too and the grid drains).
+__device__ bool wait_sol(const uint64_t *tw, int x, bool need, uint32_t tag, double &v,
+                         int32_t *err) {
+  bool ok = need ? try_sol(tw, x, tag, v) : true;
+  if (__ballot(!ok) == 0) return true;
   const unsigned long long t0 = wall_clock64();
-  while (ld_flag(&flags[j]) != epoch) {
+  for (;;) {
+    __builtin_amdgcn_s_sleep(1);
+    if (!ok) ok = try_sol(tw, x, tag, v);
+    if (__ballot(!ok) == 0) return true;
     if (wall_clock64() - t0 > kWaitTicks) {
       __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      return 0;
+      return false;
     }
-    __builtin_amdgcn_s_sleep(2);
   }
-  int nr = 1;
-  while (nr < NR && j + dir * nr != jend && ld_flag(&flags[j + dir * nr]) == epoch) ++nr;
-  return nr;
 }
 
 // Forward L y = z (unit lower triangular, standard form), in place on z.
 // Workgroup i owns rows [64 i, 64 i + 64): lane r its row, wave g a quarter
-// of each dependency block's 64 columns.
+// of each dependency block's 64 columns (lanes 0..15 wait for those 16
+// solved values).  Each wave walks the dependency blocks on its own; the
+// L of the next block does not depend on the solved values and is loaded
+// before the wait, so the last link of the chain (block i - 1) finds it in
+// registers.
 __global__ __launch_bounds__(TB) void k_trsv_fwd(int N, const double *__restrict__ L, double *z,
-                                                 int32_t *flags, const int32_t *epoch_p,
+                                                 uint64_t *tw, const int32_t *epoch_p,
                                                  int32_t *err) {
   __shared__ double s_part[4][BS];
   __shared__ double s_d[BS][BS + 1];
-  __shared__ int s_nr;
+  __shared__ int s_bad;
   const int i = blockIdx.x, tid = threadIdx.x, r = tid & 63, g = tid >> 6;
   const int r0 = i * BS, row = r0 + r;
   const bool live = row < N;
   const size_t ld = (size_t)N;
-  const int epoch = *epoch_p;
+  const uint32_t tag = 2u * (uint32_t)*epoch_p;
+  if (tid == 0) s_bad = 0;
   for (int e = tid; e < BS * BS; e += TB) {
     const int rr = e & 63, cc = e >> 6;
     s_d[rr][cc] = (rr > cc && r0 + rr < N) ? L[(size_t)(r0 + rr) + (size_t)(r0 + cc) * ld] : 0.0;
   }
   // this row's right-hand side: only this workgroup writes it, at its end
   const double zrow = live ? z[row] : 0.0;
-  double acc = 0.0;
-  // L of the next dependency block does not depend on the flags: it is
-  // loaded before the wait, so that the last link of the chain (block i - 1)
-  // finds it in registers
-  double pf[16];
+  double acc = 0.0, pf[16];
+  bool bad = false;
   if (i > 0) {
 #pragma unroll
     for (int t = 0; t < 16; ++t) pf[t] = live ? L[(size_t)row + (size_t)(g * 16 + t) * ld] : 0.0;
   }
-  for (int j = 0; j < i;) {
-    if (tid == 0) s_nr = wait_ready(flags, j, i, 1, epoch, err);
-    __syncthreads();
-    const int nr = s_nr;
-    __syncthreads();
-    if (nr == 0) return;
-    double lv[NR][16], yv[NR];
-#pragma unroll
-    for (int u = 0; u < NR; ++u) {
-      if (u < nr) {
-        const int c0 = (j + u) * BS + g * 16;
-        yv[u] = (r < 16) ? ld_sol(&z[c0 + r]) : 0.0;
-#pragma unroll
-        for (int t = 0; t < 16; ++t)
-          lv[u][t] = (u == 0) ? pf[t] : (live ? L[(size_t)row + (size_t)(c0 + t) * ld] : 0.0);
-      }
+  for (int j = 0; j < i; ++j) {
+    double yv = 0.0;
+    if (!wait_sol(tw, j * BS + g * 16 + r, r < 16, tag, yv, err)) {
+      bad = true;
+      break;
     }
-    j += nr;
-    if (j < i) {
+    double lv[16];
+#pragma unroll
+    for (int t = 0; t < 16; ++t) lv[t] = pf[t];
+    if (j + 1 < i) {
 #pragma unroll
       for (int t = 0; t < 16; ++t)
-        pf[t] = live ? L[(size_t)row + (size_t)(j * BS + g * 16 + t) * ld] : 0.0;
+        pf[t] = live ? L[(size_t)row + (size_t)((j + 1) * BS + g * 16 + t) * ld] : 0.0;
     }
 #pragma unroll
-    for (int u = 0; u < NR; ++u) {
-      if (u < nr) {
-#pragma unroll
-        for (int t = 0; t < 16; ++t) acc = fma(-lv[u][t], wave::lane_read(yv[u], t), acc);
-      }
-    }
+    for (int t = 0; t < 16; ++t) acc = fma(-lv[t], wave::lane_read(yv, t), acc);
   }
   s_part[g][r] = acc;
+  __syncthreads();  // s_bad was cleared before the loop
+  if (bad && r == 0) s_bad = 1;
   __syncthreads();
+  if (s_bad) return;
   if (g == 0) {
     double v = zrow;
     v += (s_part[0][r] + s_part[1][r]) + (s_part[2][r] + s_part[3][r]);
@@ -299,26 +306,29 @@ __global__ __launch_bounds__(TB) void k_trsv_fwd(int N, const double *__restrict
       const double yc = wave::lane_read(v, c);
       if (r > c) v = fma(-s_d[r][c], yc, v);
     }
-    if (live) __hip_atomic_store(&z[row], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __threadfence();
-    if (r == 0) __hip_atomic_store(&flags[i], epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    if (live) {
+      z[row] = v;
+      pub_sol(tw, row, v, tag);
+    }
   }
 }
 
 // Backward L' x = z, in place.  Launch index b handles block i = nblk-1-b.
 // Lane r takes row q0 + r of a dependency block (contiguous in a column of
-// L), wave g the 16 columns r0 + 16 g + t of this block; the 64 lane partial
-// sums of every column are reduced through LDS at the end.
+// L) and waits for its solved value, wave g the 16 columns r0 + 16 g + t of
+// this block; the 64 lane partial sums of every column are reduced through
+// LDS at the end.
 __global__ __launch_bounds__(TB) void k_trsv_bwd(int N, int nblk, const double *__restrict__ L,
-                                                 double *z, int32_t *flags,
+                                                 double *z, uint64_t *tw,
                                                  const int32_t *epoch_p, int32_t *err) {
   __shared__ double s_red[BS][BS + 1];
   __shared__ double s_d[BS][BS + 1];
-  __shared__ int s_nr;
+  __shared__ int s_bad;
   const int i = nblk - 1 - (int)blockIdx.x, tid = threadIdx.x, r = tid & 63, g = tid >> 6;
   const int r0 = i * BS;
   const size_t ld = (size_t)N;
-  const int epoch = *epoch_p;
+  const uint32_t tag = 2u * (uint32_t)*epoch_p + 1u;
+  if (tid == 0) s_bad = 0;
   for (int e = tid; e < BS * BS; e += TB) {
     const int rr = e & 63, cc = e >> 6;
     s_d[rr][cc] = (rr > cc && r0 + rr < N) ? L[(size_t)(r0 + rr) + (size_t)(r0 + cc) * ld] : 0.0;
@@ -326,12 +336,10 @@ __global__ __launch_bounds__(TB) void k_trsv_bwd(int N, int nblk, const double *
   const int cbase = r0 + g * 16;  // this wave's 16 columns of the block
   // this row's right-hand side: only this workgroup writes it, at its end
   const double zrow = (r0 + r < N) ? z[r0 + r] : 0.0;
-  double acc[16];
+  double acc[16], pf[16];
 #pragma unroll
   for (int t = 0; t < 16; ++t) acc[t] = 0.0;
-  // L of the next dependency block (row q of it, this wave's 16 columns) is
-  // loaded before the wait, as in the forward solve
-  double pf[16];
+  bool bad = false;
   if (nblk - 1 > i) {
     const int q = (nblk - 1) * BS + r;
 #pragma unroll
@@ -340,46 +348,33 @@ __global__ __launch_bounds__(TB) void k_trsv_bwd(int N, int nblk, const double *
       pf[t] = (q < N && c < N) ? L[(size_t)q + (size_t)c * ld] : 0.0;
     }
   }
-  for (int j = nblk - 1; j > i;) {
-    if (tid == 0) s_nr = wait_ready(flags, j, i, -1, epoch, err);
-    __syncthreads();
-    const int nr = s_nr;
-    __syncthreads();
-    if (nr == 0) return;
-    double xv[NR], lv[NR][16];
-#pragma unroll
-    for (int u = 0; u < NR; ++u) {
-      if (u < nr) {
-        const int q = (j - u) * BS + r;
-        const bool ok = q < N;
-        xv[u] = ok ? ld_sol(&z[q]) : 0.0;
-#pragma unroll
-        for (int t = 0; t < 16; ++t) {
-          const int c = cbase + t;
-          lv[u][t] = (u == 0) ? pf[t] : ((ok && c < N) ? L[(size_t)q + (size_t)c * ld] : 0.0);
-        }
-      }
+  for (int j = nblk - 1; j > i; --j) {
+    const int q = j * BS + r;
+    double xq = 0.0;
+    if (!wait_sol(tw, q, q < N, tag, xq, err)) {
+      bad = true;
+      break;
     }
-    j -= nr;
-    if (j > i) {
-      const int q = j * BS + r;
+    double lv[16];
+#pragma unroll
+    for (int t = 0; t < 16; ++t) lv[t] = pf[t];
+    if (j - 1 > i) {
+      const int qn = (j - 1) * BS + r;
 #pragma unroll
       for (int t = 0; t < 16; ++t) {
         const int c = cbase + t;
-        pf[t] = (q < N && c < N) ? L[(size_t)q + (size_t)c * ld] : 0.0;
+        pf[t] = (qn < N && c < N) ? L[(size_t)qn + (size_t)c * ld] : 0.0;
       }
     }
 #pragma unroll
-    for (int u = 0; u < NR; ++u) {
-      if (u < nr) {
-#pragma unroll
-        for (int t = 0; t < 16; ++t) acc[t] = fma(-lv[u][t], xv[u], acc[t]);
-      }
-    }
+    for (int t = 0; t < 16; ++t) acc[t] = fma(-lv[t], xq, acc[t]);
   }
 #pragma unroll
   for (int t = 0; t < 16; ++t) s_red[g * 16 + t][r] = acc[t];
+  __syncthreads();  // s_bad was cleared before the loop
+  if (bad && r == 0) s_bad = 1;
   __syncthreads();
+  if (s_bad) return;
   if (g == 0) {
     const int row = r0 + r;
     const bool live = row < N;
@@ -391,9 +386,10 @@ __global__ __launch_bounds__(TB) void k_trsv_bwd(int N, int nblk, const double *
       const double xc = wave::lane_read(v, c);
       if (r < c) v = fma(-s_d[c][r], xc, v);
     }
-    if (live) __hip_atomic_store(&z[row], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __threadfence();
-    if (r == 0) __hip_atomic_store(&flags[i], epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    if (live) {
+      z[row] = v;
+      pub_sol(tw, row, v, tag);
+    }
   }
 }
 
@@ -403,6 +399,8 @@ inline unsigned grid1(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs);
 
 int std_max_n() { return 160 * 1024 / 8; }
 int std_solve_blocks(int N) { return (N + BS - 1) / BS; }
+// epoch, error word, two pad words, then two tagged words per row
+size_t std_trsv_bytes(int N) { return 16 + 16 * (size_t)(N > 0 ? N : 0); }
 
 hipError_t std_prepare() {
   hipError_t e = hipFuncSetAttribute((const void *)k_std_apply,
@@ -428,11 +426,12 @@ void launch_std_solve(hipStream_t s, int N, const double *Lstd, const double *dd
                       double *z, double *out, int32_t *trsv) {
   if (N <= 0) return;
   const int nblk = std_solve_blocks(N);
-  int32_t *epoch = trsv, *err = trsv + 1, *ff = trsv + 4, *fb = trsv + 4 + nblk;
+  int32_t *epoch = trsv, *err = trsv + 1;
+  uint64_t *tw = reinterpret_cast<uint64_t *>(trsv + 4);
   k_perm_scatter<<<grid1(N, 256), 256, 0, s>>>(N, perm, v, z, epoch);
-  k_trsv_fwd<<<(unsigned)nblk, TB, 0, s>>>(N, Lstd, z, ff, epoch, err);
+  k_trsv_fwd<<<(unsigned)nblk, TB, 0, s>>>(N, Lstd, z, tw, epoch, err);
   k_diag_solve<<<grid1(N, 256), 256, 0, s>>>(N, dd, ds, blk, z);
-  k_trsv_bwd<<<(unsigned)nblk, TB, 0, s>>>(N, nblk, Lstd, z, fb, epoch, err);
+  k_trsv_bwd<<<(unsigned)nblk, TB, 0, s>>>(N, nblk, Lstd, z, tw, epoch, err);
   k_perm_gather<<<grid1(N, 256), 256, 0, s>>>(N, perm, z, out);
 }
 
