@@ -17,8 +17,8 @@
 // The solve is then P -> L^{-1} -> D^{-1} -> L^{-T} -> P'.  Each triangular
 // solve runs one workgroup per 64-row block: block i accumulates the products
 // of its rows of L with the solutions of the blocks it depends on, as their
-// per-block flags (stamped with a per-solve epoch kept in device memory)
-// appear, then solves its diagonal block and publishes its own flag.  A
+// tagged solution words (stamped with a per-solve epoch kept in device
+// memory) appear, then solves its diagonal block and publishes its own.  A
 // block's dependencies all have smaller launch indices, so every awaited
 // block has been dispatched before its dependants; waits are bounded by a
 // wall-clock limit and set an error word instead of hanging.
