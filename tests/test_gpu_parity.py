@@ -154,6 +154,46 @@ def test_factor_random_symmetric(N, nb, panel):
     assert (inn["npos"], inn["nzero"], inn["nneg"]) == ino
 
 
+def _panel_widths(ipiv, N, nb):
+    """Column counts of the memory panel's panels: a panel ends once nb
+    columns are done, so a 2x2 pivot on its last column makes it nb + 1 wide."""
+    out, k = [], 0
+    while k < N:
+        k0, j = k, 0
+        while j < nb and k < N:
+            s = 2 if ipiv[k] < 0 else 1
+            k += s
+            j += s
+        out.append(k - k0)
+    return out
+
+
+@pytest.mark.parametrize("N,seed", [(400, 102), (700, 100)])
+def test_solve_widest_panels(N, seed):
+    """Memory panel with nb = 64 on random symmetric matrices whose pivot
+    sequence ends several panels with a 2x2 pivot (65 columns, more pivot
+    entries than one wave has lanes in the standard form's sweep): the
+    solution equals the oracle's."""
+    rng = np.random.default_rng(seed)
+    A = rng.standard_normal((N, N))
+    A = A + A.T
+    say(f"widest panels N={N} seed={seed}")
+    prob = _dense_problem(A)
+    S = mds.solver_for(prob, nb=64, panel="mem")
+    S.condense(np.zeros(N), np.zeros(0), 0.0, 0.0)
+    S.factor_inertia()
+    _factor_check(S, A)
+    _, _, _, ipiv = S.get_factor()
+    assert 65 in _panel_widths(ipiv, N, 64)
+    r = rng.standard_normal(N)
+    dx = _np(S.solve(r, np.zeros(0), np.zeros(0))[0])
+    F = oracle.Factor(oracle.Problem(prob)).once(np.zeros(N), np.zeros(0), 0.0, 0.0)
+    od = F.solve(r, np.zeros(0), np.zeros(0))[0]
+    # both solves use the same pivots; their factors agree to rounding, so the
+    # solutions agree to about cond(A) times that
+    assert np.abs(dx - od).max() <= 1e-13 * np.linalg.cond(A) * np.abs(od).max()
+
+
 @pytest.mark.parametrize("idx", [0, 1, 2, 3, 4, 5, 6])
 def test_solve_and_refine(idx):
     prob, st, nb = _case(idx, seed=2)
