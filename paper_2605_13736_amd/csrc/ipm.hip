@@ -583,20 +583,26 @@ __global__ void k_abs_jdcol(int m, int nd, const double *__restrict__ Jd,
 
 // Row sums of |[J_d J_s]|: 64 rows per block of 256 threads, the four waves
 // take every fourth column, partials combined in wave order.
-__global__ __launch_bounds__(256) void k_abs_yrow(int m, int nd, const double *__restrict__ Jd,
-                                                  const int32_t *__restrict__ rp,
-                                                  const double *__restrict__ v,
-                                                  double *__restrict__ out) {
-  __shared__ double sh[4][64];
+// 64 rows per workgroup, 16 waves, wave g summing the columns j = g mod 16
+// (enough loads in flight for the row sums to stream J_d at memory speed),
+// then the 16 partial sums combined in a fixed tree order
+__global__ __launch_bounds__(1024) void k_abs_yrow(int m, int nd, const double *__restrict__ Jd,
+                                                   const int32_t *__restrict__ rp,
+                                                   const double *__restrict__ v,
+                                                   double *__restrict__ out) {
+  __shared__ double sh[16][64];
   const int lane = threadIdx.x & 63, g = threadIdx.x >> 6;
   const int i = blockIdx.x * 64 + lane;
   double t = 0.0;
   if (i < m)
-    for (int j = g; j < nd; j += 4) t += fabs(Jd[(size_t)i + (size_t)j * m]);
+    for (int j = g; j < nd; j += 16) t += fabs(Jd[(size_t)i + (size_t)j * m]);
   sh[g][lane] = t;
   __syncthreads();
   if (g == 0 && i < m) {
-    double u = (sh[0][lane] + sh[1][lane]) + (sh[2][lane] + sh[3][lane]);
+    double q[8];
+#pragma unroll
+    for (int a = 0; a < 8; ++a) q[a] = sh[2 * a][lane] + sh[2 * a + 1][lane];
+    double u = ((q[0] + q[1]) + (q[2] + q[3])) + ((q[4] + q[5]) + (q[6] + q[7]));
     for (int a = rp[i]; a < rp[i + 1]; ++a) u += fabs(v[a]);
     out[i] = u;
   }
@@ -839,7 +845,7 @@ void kkt_norm_parts(hipStream_t s, int nd, int ns, int m, const double *H, const
     k_abs_hrow<<<grid1(nd, 4), 256, 0, s>>>(nd, H, sig, dw, hrow);
     k_abs_jdcol<<<grid1(nd, 4), 256, 0, s>>>(m, nd, Jd, jdcol);
   }
-  if (m > 0) k_abs_yrow<<<grid1(m, 64), 256, 0, s>>>(m, nd, Jd, rp, v, yrow);
+  if (m > 0) k_abs_yrow<<<grid1(m, 64), 1024, 0, s>>>(m, nd, Jd, rp, v, yrow);
   if (ns > 0) k_abs_jscol<<<grid1(ns, 256), 256, 0, s>>>(ns, cptr, cval, jscol);
   if (sb && sb->nblk > 0 && ns > 0) {
     // coupling blocks: their off-diagonal row sums join J_s's column sums,
