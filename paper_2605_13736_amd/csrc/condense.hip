@@ -45,21 +45,29 @@ __global__ __launch_bounds__(256) void k_condense_dense(int nd, int m, int N,
     }
     __syncthreads();
   }
-  for (int jj = ty; jj < kTile; jj += 4) {
-    const int i = I0 + tx, j = J0 + jj;
-    if (i >= N || j >= N) continue;
-    double v;
-    if (i < nd && j < nd) {
-      v = H[(size_t)i + (size_t)j * nd];
-      if (i == j) v = (v + sig[i]) + dw;
-    } else if (j < nd) {
-      v = Jd[(size_t)(i - nd) + (size_t)j * m];
-    } else if (i < nd) {
-      v = t[jj][tx];
-    } else {
-      v = 0.0;
+  // every entry of this thread's column strip is loaded before the first
+  // store, so that the loads of one thread overlap
+  double vals[kTile / 4];
+#pragma unroll
+  for (int u = 0; u < kTile / 4; ++u) {
+    const int jj = ty + 4 * u, i = I0 + tx, j = J0 + jj;
+    double v = 0.0;
+    if (i < N && j < N) {
+      if (i < nd && j < nd) {
+        v = H[(size_t)i + (size_t)j * nd];
+        if (i == j) v = (v + sig[i]) + dw;
+      } else if (j < nd) {
+        v = Jd[(size_t)(i - nd) + (size_t)j * m];
+      } else if (i < nd) {
+        v = t[jj][tx];
+      }
     }
-    M[(size_t)i + (size_t)j * N] = v;
+    vals[u] = v;
+  }
+#pragma unroll
+  for (int u = 0; u < kTile / 4; ++u) {
+    const int i = I0 + tx, j = J0 + ty + 4 * u;
+    if (i < N && j < N) M[(size_t)i + (size_t)j * N] = vals[u];
   }
 }
 
